@@ -1,0 +1,202 @@
+/*
+ * lspr.h -- C ABI of the MI355X quasistatic LSPR boundary-element library.
+ *
+ * Method: Clementi, Cooper & Barba, "Computational nanoplasmonics in the quasistatic limit for
+ * biosensing applications" (arXiv 1812.10722).  A metal nanoparticle (surface 0) and optional
+ * dielectric analytes (surfaces 1..S-1) sit in a host medium under a uniform field E.  The
+ * scattered potential solves the boundary integral equations of Eqs. integral_eq_lspr /
+ * integral_eq_lspr_system, discretised with flat triangles, piecewise-constant unknowns and
+ * centroid collocation (Eqs. layers_disc, matrix_lspr, matrix_multi).  The dense matrix-vector
+ * product is replaced by a treecode (section "Acceleration strategies") and the complex
+ * systems are solved by GMRES; the outputs are the surface potential and normal derivative,
+ * the dipole moment (section "Boundary integral expression of the dipole moment") and the
+ * extinction cross-section (Eq. cext_fwa).
+ *
+ * Units: lengths in nm, wavelengths in nm, permittivities relative (dimensionless).
+ *
+ * Conventions for every entry point:
+ *   - Return value: an lspr_status code.  Nothing aborts; on error the outputs are unspecified
+ *     (except LSPR_E_NOCONV, see lspr_solve) and lspr_last_error() holds a message for the
+ *     calling thread.
+ *   - Ownership: the caller owns every buffer it passes.  lspr_geometry_create copies what it
+ *     needs; a geometry handle owns its own device memory (trees, lists, near-field tables,
+ *     Krylov workspace) and frees it in lspr_geometry_destroy.
+ *   - "device" pointers are HIP device addresses on the current device (for instance
+ *     torch.Tensor.data_ptr() of a cuda tensor); "host" pointers are ordinary memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are synchronous with respect
+ *     to the host: they return after their work on `stream` has finished.
+ *   - Calls on one geometry handle must not overlap (a handle holds one Krylov workspace).
+ */
+#ifndef LSPR_H
+#define LSPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } lspr_c64;
+
+typedef struct lspr_geometry lspr_geometry;
+
+enum lspr_status {
+    LSPR_OK = 0,
+    LSPR_E_INVALID = 1,   /* bad argument (NULL pointer, size or parameter out of range) */
+    LSPR_E_MESH = 2,      /* mesh rejected: index out of range, degenerate, open or inverted */
+    LSPR_E_NOMEM = 3,     /* device allocation failed */
+    LSPR_E_DEVICE = 4,    /* a HIP call failed */
+    LSPR_E_NOCONV = 5,    /* GMRES hit max_iter; outputs hold the last iterate */
+    LSPR_E_BUSY = 6       /* (serving) request not finished yet */
+};
+
+enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
+enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1 };
+
+/* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
+ * counter-clockwise seen from outside (outward right-hand normal, as the paper's dipole
+ * section requires).  Device pointers in lspr_geometry_create; host pointers in
+ * lspr_mesh_validate. */
+typedef struct {
+    int32_t n_vert;
+    const double* vert;
+    int32_t n_tri;
+    const int32_t* tri;
+} lspr_surface;
+
+/* Discretisation and treecode parameters (section "Integral evaluation", Tables 1, 2, 4, 5;
+ * section "Acceleration strategies").
+ *   k_far     points of the far-panel rule: 1, 3, 4 or 7 (the paper uses 4)
+ *   k_fine    points of the near-singular rule: 19 or 25 (the paper lists 19, 25, 37)
+ *   n_k       Gauss nodes per edge of the semi-analytic singular rule, 1..64 (paper: 9)
+ *   threshold a source panel j is near-singular for collocation point x_i when
+ *             |x_i - c_j| <= L_j / threshold, L = sqrt(2 Area) (paper: 0.5, i.e. 2L)
+ *   method    LSPR_DENSE (every far pair summed directly) or LSPR_TREECODE
+ *   p         Taylor expansion order of the treecode: 2, 4, 6, 8 or 10 (paper: 6 or 15)
+ *   theta     multipole acceptance parameter, 0 < theta < 1 (paper: 0.5)
+ *   ncrit     maximum panels per octree leaf; 0 selects the library default
+ *   precision LSPR_FP64 or LSPR_FP32 for the far-field sums (P2P, P2M, M2P).  Singular and
+ *             near-singular corrections, the GMRES and the post-processing are always FP64.
+ *   m2p_min_panels  a box that passes the MAC is expanded only if it holds at least this many
+ *             panels, otherwise it is summed directly (cheaper for small boxes); 0 selects the
+ *             library default (the number of expansion terms).  Accuracy is unaffected: a
+ *             direct sum is exact to the quadrature. */
+typedef struct {
+    int32_t k_far;
+    int32_t k_fine;
+    int32_t n_k;
+    double threshold;
+    int32_t method;
+    int32_t p;
+    double theta;
+    int32_t ncrit;
+    int32_t precision;
+    int32_t m2p_min_panels;
+} lspr_op_params;
+
+/* GMRES parameters (the paper gives only tolerances, Tables 2 and 5).
+ *   tol       stop a wavelength when ||b - A x||_2 <= tol ||b||_2 (complex 2-norm over all
+ *             2N unknowns)
+ *   restart   Krylov dimension before restart, 1..512
+ *   max_iter  total iteration cap per wavelength
+ *   precond   0 = none, 1 = right block-Jacobi with the 2x2 self-panel blocks (does not
+ *             change the solution, only the iteration count) */
+typedef struct {
+    double tol;
+    int32_t restart;
+    int32_t max_iter;
+    int32_t precond;
+} lspr_gmres_params;
+
+/* Sizes of a built geometry (host struct filled by lspr_geometry_info). */
+typedef struct {
+    int64_t n_panels;        /* N, all surfaces */
+    int64_t n_surfaces;
+    int64_t n_nodes;         /* N * k_far treecode sources */
+    int64_t n_boxes;         /* octree boxes, all surfaces */
+    int64_t n_leaves;
+    int64_t n_target_chunks; /* groups of consecutive targets sharing interaction lists */
+    int64_t n_m2p;           /* (target chunk, box) expansion interactions */
+    int64_t n_p2p_ranges;    /* (target chunk, source range) direct interactions */
+    int64_t p2p_pairs;       /* target-panel x source-panel pairs summed directly */
+    int64_t m2p_pairs;       /* target x box pairs evaluated by expansion */
+    int64_t n_near;          /* near-singular (target, source) pairs with fine-rule corrections */
+    int64_t device_bytes;    /* device memory held by the handle (without Krylov workspace) */
+    int32_t n_terms;         /* expansion terms per box and column */
+    int32_t ncrit;           /* leaf capacity actually used */
+    int32_t target_chunk;    /* targets per chunk */
+    int32_t max_depth;
+} lspr_geometry_stats;
+
+/* Checks host-side surfaces before upload: indices in range, non-degenerate panels, every
+ * edge shared by exactly two panels with opposite orientation (closed, consistently oriented
+ * 2-manifold) and positive enclosed volume (outward normals).  Returns LSPR_OK or
+ * LSPR_E_MESH / LSPR_E_INVALID with a message. */
+int lspr_mesh_validate(const lspr_surface* surfaces, int32_t n_surf);
+
+/* Builds everything that depends on geometry only (section "Integral evaluation",
+ * section "Acceleration strategies"): panel areas, normals, centroids and quadrature nodes,
+ * Morton order and octree, interaction lists under the MAC, singular self-terms,
+ * near-singular correction table and the geometry part of the right-hand side.
+ * surfaces: host array of n_surf descriptors whose vert/tri point to DEVICE memory.
+ * Surface 0 is the sensor.  Device-side checks reject out-of-range indices and zero-area
+ * panels (LSPR_E_MESH); topology is checked by lspr_mesh_validate.  *out receives the
+ * handle. */
+int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf,
+                         const lspr_op_params* op, void* stream, lspr_geometry** out);
+
+int lspr_geometry_destroy(lspr_geometry* g);
+
+int lspr_geometry_info(const lspr_geometry* g, lspr_geometry_stats* out);
+
+/* Solves n_lambda independent wavelengths in one batch (Eq. matrix_multi per wavelength),
+ * sharing every matrix-vector product launch.
+ *   lambda_nm    host [n_lambda]
+ *   eps_medium   host [n_lambda]            host-medium permittivity
+ *   eps_surface  host [n_lambda][n_surf]    interior permittivity of each surface
+ *   e_field      host [3]                   real incident field E (C_ext does not depend on
+ *                                           its magnitude or sign)
+ *   gm           host                       GMRES parameters
+ *   phi, dphi    device [n_lambda][N] or NULL: interior-side potential and normal derivative
+ *                per panel, in the caller's panel order (surfaces concatenated)
+ *   p_sensor     host [n_lambda][3] or NULL: dipole moment p = eps_m * q of surface 0 alone
+ *   p_total      host [n_lambda][3] or NULL: dipole moment of all surfaces
+ *   cext_sensor  host [n_lambda] or NULL: extinction cross-section (nm^2) from p_sensor
+ *   cext_total   host [n_lambda] or NULL: extinction cross-section from p_total
+ *   iters        host [n_lambda] or NULL: GMRES iterations per wavelength
+ *   rel_resid    host [n_lambda] or NULL: final ||b - A x|| / ||b|| per wavelength
+ * Returns LSPR_E_NOCONV (with all outputs filled from the last iterate) when some wavelength
+ * did not reach tol within max_iter. */
+int lspr_solve(lspr_geometry* g, int32_t n_lambda, const double* lambda_nm,
+               const lspr_c64* eps_medium, const lspr_c64* eps_surface, const double* e_field,
+               const lspr_gmres_params* gm, void* stream, lspr_c64* phi, lspr_c64* dphi,
+               lspr_c64* p_sensor, lspr_c64* p_total, double* cext_sensor, double* cext_total,
+               int32_t* iters, double* rel_resid);
+
+/* One block matrix-vector product y = A x of the system of Eq. matrix_multi for n_cols
+ * independent permittivity sets (no preconditioner).
+ *   eps_medium host [n_cols], eps_surface host [n_cols][n_surf]
+ *   x, y       device [n_cols][2N] complex: per column all phi (caller's panel order), then
+ *              all dphi/dn; y rows: all interior rows, then all exterior rows. */
+int lspr_apply(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,
+               const lspr_c64* eps_surface, const lspr_c64* x, lspr_c64* y, void* stream);
+
+/* Right-hand side of Eq. matrix_multi for n_cols permittivity sets: b device [n_cols][2N]
+ * (interior rows zero; exterior rows sum_s ((eps_m - eps_s)/eps_m) V_s g_s, g = -E . n). */
+int lspr_rhs(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,
+             const lspr_c64* eps_surface, const double* e_field, lspr_c64* b, void* stream);
+
+/* The library's own triangle rule with n points (bary host [n][3], w host [n], weights sum to
+ * 1) and its Gauss-Legendre rule (t host [n], w host [n] on [-1, 1]).  For verification. */
+int lspr_triangle_rule(int32_t n, double* bary, double* w);
+int lspr_gauss_legendre(int32_t n, double* t, double* w);
+
+const char* lspr_status_string(int code);
+const char* lspr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSPR_H */

@@ -1,0 +1,361 @@
+// C ABI of the library (declared in include/lspr.h): argument checks, error translation and
+// orchestration of the set-up and solve steps.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <set>
+#include <utility>
+
+#include "operator.hpp"
+#include "system.hpp"
+
+struct lspr_geometry {
+    lspr::Geometry g;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const lspr::Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return LSPR_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return LSPR_E_INVALID;
+    }
+}
+
+constexpr int MAX_BATCH = 64;  // wavelengths per block matrix-vector product
+
+lspr::EpsSet make_eps(int B, int S, const lspr_c64* em, const lspr_c64* es) {
+    lspr::EpsSet e;
+    for (int b = 0; b < B; ++b) {
+        e.em_re.push_back(em[b].re);
+        e.em_im.push_back(em[b].im);
+        for (int k = 0; k < S; ++k) {
+            e.es_re.push_back(es[b * S + k].re);
+            e.es_im.push_back(es[b * S + k].im);
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
+size_t lspr::Geometry::device_bytes() const {
+    return tri.bytes() + cen.bytes() + nrm.bytes() + area.bytes() + surf.bytes() + perm.bytes() +
+           iperm.bytes() + morton.bytes() + src.bytes() + boxes.bytes() + far_rule.bytes() +
+           mom_boxes_d.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
+           m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
+           near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
+           vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes();
+}
+
+extern "C" {
+
+const char* lspr_status_string(int code) {
+    switch (code) {
+        case LSPR_OK: return "ok";
+        case LSPR_E_INVALID: return "invalid argument";
+        case LSPR_E_MESH: return "invalid mesh";
+        case LSPR_E_NOMEM: return "out of memory";
+        case LSPR_E_DEVICE: return "device error";
+        case LSPR_E_NOCONV: return "GMRES did not converge";
+        case LSPR_E_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+const char* lspr_last_error(void) { return g_last_error.c_str(); }
+
+int lspr_triangle_rule(int32_t n, double* bary, double* w) {
+    return guarded([&] {
+        LSPR_REQUIRE(bary && w, LSPR_E_INVALID, "null output");
+        std::vector<double> b, ww;
+        LSPR_REQUIRE(lspr::triangle_rule(n, b, ww), LSPR_E_INVALID, "no rule with that many points");
+        std::copy(b.begin(), b.end(), bary);
+        std::copy(ww.begin(), ww.end(), w);
+        return LSPR_OK;
+    });
+}
+
+int lspr_gauss_legendre(int32_t n, double* t, double* w) {
+    return guarded([&] {
+        LSPR_REQUIRE(t && w && n >= 1 && n <= 256, LSPR_E_INVALID, "bad Gauss-Legendre request");
+        std::vector<double> a, b;
+        lspr::gauss_legendre(n, a, b);
+        std::copy(a.begin(), a.end(), t);
+        std::copy(b.begin(), b.end(), w);
+        return LSPR_OK;
+    });
+}
+
+int lspr_mesh_validate(const lspr_surface* surfaces, int32_t n_surf) {
+    return guarded([&] {
+        LSPR_REQUIRE(surfaces && n_surf >= 1, LSPR_E_INVALID, "need at least one surface");
+        for (int s = 0; s < n_surf; ++s) {
+            const lspr_surface& f = surfaces[s];
+            const std::string tag = "surface " + std::to_string(s) + ": ";
+            LSPR_REQUIRE(f.vert && f.tri && f.n_vert >= 3 && f.n_tri >= 4, LSPR_E_INVALID,
+                         tag + "empty or null arrays");
+            std::map<std::pair<int, int>, int> edges;
+            double vol = 0.0;
+            for (int t = 0; t < f.n_tri; ++t) {
+                int v[3];
+                for (int k = 0; k < 3; ++k) {
+                    v[k] = f.tri[3 * t + k];
+                    LSPR_REQUIRE(v[k] >= 0 && v[k] < f.n_vert, LSPR_E_MESH,
+                                 tag + "vertex index out of range in triangle " + std::to_string(t));
+                }
+                LSPR_REQUIRE(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], LSPR_E_MESH,
+                             tag + "repeated vertex in triangle " + std::to_string(t));
+                const double* a = f.vert + 3 * v[0];
+                const double* b = f.vert + 3 * v[1];
+                const double* c = f.vert + 3 * v[2];
+                const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+                const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                                     u[0] * w[1] - u[1] * w[0]};
+                const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                const double sc = std::max(u[0] * u[0] + u[1] * u[1] + u[2] * u[2],
+                                           w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+                LSPR_REQUIRE(nn > 1e-14 * sc, LSPR_E_MESH,
+                             tag + "degenerate triangle " + std::to_string(t));
+                vol += (a[0] * n[0] + a[1] * n[1] + a[2] * n[2]) / 6.0;
+                for (int k = 0; k < 3; ++k) {
+                    const auto key = std::make_pair(v[k], v[(k + 1) % 3]);
+                    LSPR_REQUIRE(++edges[key] == 1, LSPR_E_MESH,
+                                 tag + "edge used twice in the same direction (orientation or "
+                                       "non-manifold)");
+                }
+            }
+            for (const auto& e : edges)
+                LSPR_REQUIRE(edges.count(std::make_pair(e.first.second, e.first.first)) == 1,
+                             LSPR_E_MESH, tag + "open surface (edge without its reverse)");
+            LSPR_REQUIRE(vol > 0.0, LSPR_E_MESH,
+                         tag + "negative enclosed volume (normals point inwards)");
+        }
+        return LSPR_OK;
+    });
+}
+
+int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lspr_op_params* op,
+                         void* stream, lspr_geometry** out) {
+    return guarded([&] {
+        LSPR_REQUIRE(surfaces && op && out && n_surf >= 1 && n_surf <= 4096, LSPR_E_INVALID,
+                     "bad arguments");
+        *out = nullptr;
+        int64_t N = 0;
+        for (int s = 0; s < n_surf; ++s) {
+            LSPR_REQUIRE(surfaces[s].vert && surfaces[s].tri && surfaces[s].n_tri > 0 &&
+                             surfaces[s].n_vert > 0,
+                         LSPR_E_INVALID, "empty surface");
+            N += surfaces[s].n_tri;
+        }
+        LSPR_REQUIRE(N < (1ll << 28), LSPR_E_INVALID, "too many panels");
+        std::vector<double> b, w;
+        LSPR_REQUIRE(lspr::triangle_rule(op->k_far, b, w) && op->k_far <= 8, LSPR_E_INVALID,
+                     "k_far must be 1, 3, 4 or 7");
+        LSPR_REQUIRE(lspr::triangle_rule(op->k_fine, b, w), LSPR_E_INVALID,
+                     "k_fine must be one of 1, 3, 4, 7, 19, 25");
+        LSPR_REQUIRE(op->n_k >= 1 && op->n_k <= 64, LSPR_E_INVALID, "n_k must be in 1..64");
+        LSPR_REQUIRE(op->threshold > 0.0, LSPR_E_INVALID, "threshold must be positive");
+        LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
+                     "unknown method");
+        LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64, LSPR_E_INVALID,
+                     "unknown precision");
+        if (op->method == LSPR_TREECODE) {
+            LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,
+                         LSPR_E_INVALID, "p must be 2, 4, 6, 8 or 10");
+            LSPR_REQUIRE(op->theta > 0.0 && op->theta < 1.0, LSPR_E_INVALID,
+                         "theta must be in (0, 1)");
+        }
+        LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
+                     "ncrit and m2p_min_panels must be >= 0");
+        auto h = std::make_unique<lspr_geometry>();
+        lspr::Geometry& g = h->g;
+        g.stream = static_cast<hipStream_t>(stream);
+        g.K = op->k_far;
+        g.Kf = op->k_fine;
+        g.Nk = op->n_k;
+        g.threshold = op->threshold;
+        g.method = op->method;
+        g.P = op->method == LSPR_TREECODE ? op->p : 4;
+        g.theta = op->theta;
+        g.ncrit = op->ncrit > 0 ? op->ncrit : 16;
+        g.precision = op->precision;
+        g.n_terms = lspr::expansion_terms(g.P);
+        g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
+        lspr::build_geometry(g, surfaces, n_surf);
+        lspr::build_tree(g);
+        lspr::build_lists(g);
+        // boxes whose moments are needed
+        std::vector<int32_t> mb(static_cast<size_t>(g.n_m2p));
+        if (g.n_m2p > 0)
+            LSPR_HIP(hipMemcpy(mb.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost));
+        std::set<int32_t> uniq(mb.begin(), mb.end());
+        g.mom_boxes.assign(uniq.begin(), uniq.end());
+        if (!g.mom_boxes.empty()) {
+            g.mom_boxes_d.alloc(g.mom_boxes.size());
+            LSPR_HIP(hipMemcpy(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size() * 4,
+                               hipMemcpyHostToDevice));
+        }
+        lspr::build_near_table(g);
+        lspr::precompute_rhs(g);
+        *out = h.release();
+        return LSPR_OK;
+    });
+}
+
+int lspr_geometry_destroy(lspr_geometry* g) {
+    return guarded([&] {
+        if (g) {
+            (void)hipStreamSynchronize(g->g.stream);
+            delete g;
+        }
+        return LSPR_OK;
+    });
+}
+
+int lspr_geometry_info(const lspr_geometry* h, lspr_geometry_stats* o) {
+    return guarded([&] {
+        LSPR_REQUIRE(h && o, LSPR_E_INVALID, "null argument");
+        const lspr::Geometry& g = h->g;
+        o->n_panels = g.N;
+        o->n_surfaces = g.S;
+        o->n_nodes = static_cast<int64_t>(g.N) * g.K;
+        o->n_boxes = g.n_boxes;
+        o->n_leaves = g.n_leaves;
+        o->n_target_chunks = g.n_chunks;
+        o->n_m2p = g.n_m2p;
+        o->n_p2p_ranges = g.n_p2p;
+        o->p2p_pairs = g.p2p_pairs;
+        o->m2p_pairs = g.m2p_pairs;
+        o->n_near = g.n_near;
+        o->device_bytes = static_cast<int64_t>(g.device_bytes());
+        o->n_terms = g.n_terms;
+        o->ncrit = g.ncrit;
+        o->target_chunk = g.tchunk;
+        o->max_depth = g.max_depth;
+        return LSPR_OK;
+    });
+}
+
+int lspr_apply(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
+               const lspr_c64* eps_surface, const lspr_c64* x, lspr_c64* y, void* stream) {
+    return guarded([&] {
+        LSPR_REQUIRE(h && eps_medium && eps_surface && x && y && n_cols >= 1, LSPR_E_INVALID,
+                     "bad arguments");
+        lspr::Geometry& g = h->g;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t nvec = 2 * static_cast<int64_t>(g.N);
+        for (int b0 = 0; b0 < n_cols; b0 += MAX_BATCH) {
+            const int B = std::min(MAX_BATCH, n_cols - b0);
+            const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
+            lspr::DevBuf<double2> ratio, xs(B * nvec), ys(B * nvec);
+            lspr::upload_ratios(g, e, B, ratio, s);
+            lspr::to_sorted(g, B, reinterpret_cast<const double2*>(x) + b0 * nvec, xs.p, s);
+            lspr::system_apply(g, B, ratio.p, xs.p, nvec, ys.p, nvec, nullptr, s);
+            lspr::from_sorted(g, B, ys.p, reinterpret_cast<double2*>(y) + b0 * nvec, s);
+            LSPR_HIP(hipStreamSynchronize(s));
+        }
+        return LSPR_OK;
+    });
+}
+
+int lspr_rhs(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
+             const lspr_c64* eps_surface, const double* e_field, lspr_c64* b, void* stream) {
+    return guarded([&] {
+        LSPR_REQUIRE(h && eps_medium && eps_surface && e_field && b && n_cols >= 1,
+                     LSPR_E_INVALID, "bad arguments");
+        lspr::Geometry& g = h->g;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t nvec = 2 * static_cast<int64_t>(g.N);
+        for (int b0 = 0; b0 < n_cols; b0 += MAX_BATCH) {
+            const int B = std::min(MAX_BATCH, n_cols - b0);
+            const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
+            lspr::DevBuf<double2> ratio, bs(B * nvec);
+            lspr::upload_ratios(g, e, B, ratio, s);
+            lspr::system_rhs(g, B, ratio.p, e_field, bs.p, nvec, s);
+            lspr::from_sorted(g, B, bs.p, reinterpret_cast<double2*>(b) + b0 * nvec, s);
+            LSPR_HIP(hipStreamSynchronize(s));
+        }
+        return LSPR_OK;
+    });
+}
+
+int lspr_solve(lspr_geometry* h, int32_t n_lambda, const double* lambda_nm,
+               const lspr_c64* eps_medium, const lspr_c64* eps_surface, const double* e_field,
+               const lspr_gmres_params* gm, void* stream, lspr_c64* phi, lspr_c64* dphi,
+               lspr_c64* p_sensor, lspr_c64* p_total, double* cext_sensor, double* cext_total,
+               int32_t* iters, double* rel_resid) {
+    return guarded([&] {
+        LSPR_REQUIRE(h && lambda_nm && eps_medium && eps_surface && e_field && gm && n_lambda >= 1,
+                     LSPR_E_INVALID, "bad arguments");
+        LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1,
+                     LSPR_E_INVALID, "bad GMRES parameters");
+        const double e2 = e_field[0] * e_field[0] + e_field[1] * e_field[1] + e_field[2] * e_field[2];
+        LSPR_REQUIRE(e2 > 0.0, LSPR_E_INVALID, "zero incident field");
+        for (int k = 0; k < n_lambda; ++k)
+            LSPR_REQUIRE(lambda_nm[k] > 0.0, LSPR_E_INVALID, "wavelengths must be positive");
+        lspr::Geometry& g = h->g;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t nvec = 2 * static_cast<int64_t>(g.N);
+        bool all_ok = true;
+        for (int b0 = 0; b0 < n_lambda; b0 += MAX_BATCH) {
+            const int B = std::min(MAX_BATCH, n_lambda - b0);
+            const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
+            lspr::DevBuf<double2> ratio, xs(B * nvec);
+            lspr::upload_ratios(g, e, B, ratio, s);
+            const lspr::SolveResult r = lspr::gmres_solve(g, B, ratio.p, e_field, *gm, xs.p, s);
+            all_ok = all_ok && r.all_converged;
+            std::vector<double> q;
+            lspr::dipole_moments(g, B, ratio.p, e_field, xs.p, q, s);
+            for (int b = 0; b < B; ++b) {
+                const int k = b0 + b;
+                const std::complex<double> em(eps_medium[k].re, eps_medium[k].im);
+                const std::complex<double> kw = 2.0 * M_PI * std::sqrt(em) / lambda_nm[k];
+                for (int which = 0; which < 2; ++which) {
+                    std::complex<double> qv[3];
+                    for (int d = 0; d < 3; ++d)
+                        qv[d] = std::complex<double>(q[b * 12 + 6 * which + 2 * d],
+                                                     q[b * 12 + 6 * which + 2 * d + 1]);
+                    const std::complex<double> eq = e_field[0] * qv[0] + e_field[1] * qv[1] +
+                                                    e_field[2] * qv[2];
+                    const double cext = std::imag(kw * kw * eq) / (kw.real() * e2);
+                    lspr_c64* pp = which == 0 ? p_sensor : p_total;
+                    double* cc = which == 0 ? cext_sensor : cext_total;
+                    if (pp)
+                        for (int d = 0; d < 3; ++d) {
+                            const std::complex<double> p = em * qv[d];
+                            pp[3 * k + d] = lspr_c64{p.real(), p.imag()};
+                        }
+                    if (cc) cc[k] = cext;
+                }
+                if (iters) iters[k] = r.iters[b];
+                if (rel_resid) rel_resid[k] = r.rel_resid[b];
+            }
+            if (phi || dphi)
+                lspr::unpermute(g, B, xs.p, phi ? reinterpret_cast<double2*>(phi) + b0 * g.N : nullptr,
+                                dphi ? reinterpret_cast<double2*>(dphi) + b0 * g.N : nullptr, s);
+            LSPR_HIP(hipStreamSynchronize(s));
+        }
+        if (!all_ok) {
+            g_last_error = "some wavelengths reached max_iter before tol";
+            return static_cast<int>(LSPR_E_NOCONV);
+        }
+        return static_cast<int>(LSPR_OK);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Internal declarations of the LSPR library: error handling, device buffers, the geometry
+// handle and the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "lspr.h"
+
+namespace lspr {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define LSPR_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t err_ = (call);                                                           \
+        if (err_ != hipSuccess)                                                             \
+            throw ::lspr::Error(err_ == hipErrorOutOfMemory ? LSPR_E_NOMEM : LSPR_E_DEVICE, \
+                                std::string(#call) + ": " + hipGetErrorString(err_));       \
+    } while (0)
+
+#define LSPR_REQUIRE(cond, code, msg)                                  \
+    do {                                                               \
+        if (!(cond)) throw ::lspr::Error((code), std::string(msg));    \
+    } while (0)
+
+// Owning device allocation (hipMalloc / hipFree).  Moves, never copies.
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        LSPR_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+        n = count;
+    }
+    // grow-only reallocation for workspaces
+    void reserve(size_t count) { if (count > n) alloc(count); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    T* get() const { return p; }
+};
+
+// Octree box, one per node of every surface's tree.  Boxes of one surface are stored level by
+// level; the children of a box are contiguous.
+struct Box {
+    double cx, cy, cz;  // expansion centre: centre of the bounding box of the box's nodes
+    double rb;          // max |node - centre| over its quadrature nodes (MAC radius)
+    double rv;          // max |vertex - centre| over its panels (near-singular guard radius)
+    double lmax;        // max representative length L = sqrt(2 A) of its panels
+    int32_t start, end; // panel range [start, end) in sorted order
+    int32_t child, nchild;
+    int32_t level, surf;
+};
+
+// Group of consecutive targets (panel centroids of one surface, sorted order) that share
+// interaction lists.
+struct Chunk {
+    double cx, cy, cz;  // centre of the bounding box of its centroids
+    double r;           // max |centroid - centre|
+    int32_t start, end;
+    int32_t surf, pad;
+};
+
+// One entry of a chunk's direct-sum list: source panels [start, end) of one surface.
+struct Range {
+    int32_t start, end;
+};
+
+struct Geometry {
+    // parameters
+    int S = 0, N = 0;
+    int K = 4, Kf = 19, Nk = 9;
+    double threshold = 0.5;
+    int method = LSPR_TREECODE, P = 6, ncrit = 16, precision = LSPR_FP32;
+    double theta = 0.5;
+    int tchunk = 64;
+    int n_terms = 0;   // expansion terms per column (Taylor terms kept after folding)
+    int max_depth = 0;
+    std::vector<int> surf_start;  // S+1 offsets of each surface's panels in sorted order
+    std::vector<int> surf_root;   // root box of each surface's tree
+    double origin[3] = {0, 0, 0}; // centre of the global bounding cube
+    double half = 1.0;            // half side of the global bounding cube
+
+    // per panel, sorted order
+    DevBuf<double> tri;     // [N][9] vertex coordinates
+    DevBuf<double> cen;     // [N][3] centroid
+    DevBuf<double> nrm;     // [N][3] unit outward normal
+    DevBuf<double> area;    // [N]
+    DevBuf<int32_t> surf;   // [N] surface id
+    DevBuf<int32_t> perm;   // [N] sorted index -> caller's panel index
+    DevBuf<int32_t> iperm;  // [N] caller's panel index -> sorted index
+    DevBuf<uint64_t> morton; // [N] sorted keys: surface id << 48 | 48-bit Morton code
+    // far-field source record per panel in the compute precision (geometry.hip, k_permute):
+    // (n_x, n_y, n_z, A) then (y_g - c, w_g) for each far-rule node g
+    DevBuf<uint8_t> src;
+    int m2p_min_panels = 0;  // boxes with fewer panels are summed directly (cost criterion)
+    // tree and lists
+    int n_boxes = 0, n_leaves = 0;
+    DevBuf<Box> boxes;
+    DevBuf<double> far_rule;   // [K][4] barycentric coordinates and weight of the far rule
+    std::vector<int32_t> mom_boxes;  // boxes that appear in some expansion list
+    DevBuf<int32_t> mom_boxes_d;
+    int n_chunks = 0;
+    DevBuf<Chunk> chunks;
+    std::vector<int> chunk_h_surf;
+    DevBuf<int32_t> m2p_off;   // [n_chunks + 1]
+    DevBuf<int32_t> m2p_box;   // [n_m2p]
+    DevBuf<int32_t> m2p_self;  // [n_chunks] entries of the own surface come first: count
+    DevBuf<int32_t> p2p_off;   // [n_chunks + 1]
+    DevBuf<Range> p2p_rng;     // [n_p2p]
+    DevBuf<int32_t> p2p_self;  // [n_chunks]
+    int64_t n_m2p = 0, n_p2p = 0, p2p_pairs = 0, m2p_pairs = 0;
+    // near-singular corrections (CSR over targets, sorted order) and singular self terms
+    DevBuf<int64_t> near_off64; // [N + 1]
+    DevBuf<int32_t> near_col;  // [n_near]
+    DevBuf<double> near_dv;    // [n_near] fine - coarse single-layer entry
+    DevBuf<double> near_dk;    // [n_near] fine - coarse double-layer entry
+    DevBuf<double> vself;      // [N] semi-analytic V_ii
+    int64_t n_near = 0;
+    // geometry part of the right-hand side: u[s][d][i] = sum_{j in s} V_ij (-n_j,d)
+    DevBuf<double> rhs_u;      // [S][3][N]
+    // workspaces reused by the operator
+    DevBuf<uint8_t> ws_dens, ws_mom, ws_out;
+    hipStream_t stream = nullptr;
+
+    size_t device_bytes() const;
+};
+
+// Column layout of one block matrix-vector product.  The real operators act on 2*ncol real
+// columns: ncol "K columns" (real and imaginary parts of phi) and ncol "V columns" (of
+// sigma = (eps_s / eps_m) psi).  Every column count is padded to a multiple of cpt.
+struct Cols {
+    int ncol = 0;  // real columns per operator (2 * wavelengths)
+    int cpt = 0;   // columns per thread per operator
+    int pad = 0;   // ncol rounded up to cpt
+};
+
+// ---------------------------------------------------------------- quadrature (quadrature.cpp)
+// Returns false when no rule with n points exists.
+bool triangle_rule(int n, std::vector<double>& bary, std::vector<double>& w);
+void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w);
+
+// ---------------------------------------------------------------- geometry (geometry.hip)
+void build_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf);
+
+// ---------------------------------------------------------------- tree (tree.hip)
+void build_tree(Geometry& g);
+void build_lists(Geometry& g);
+void build_near_table(Geometry& g);
+
+// ---------------------------------------------------------------- operator (operator.hip)
+// Raw layer sums for a packed density: dens [N][2*pad] in the compute precision (K columns
+// then V columns, sorted panel order).  out_self/out_all [N][2*pad] FP64 receive, per target,
+// the K and V sums over its own surface and over all surfaces, including the near-singular
+// and singular corrections, without the 1/(4 pi) factor.
+void apply_raw(Geometry& g, const Cols& c, const void* dens, double* out_self, double* out_all,
+               hipStream_t s);
+void precompute_rhs(Geometry& g);
+
+}  // namespace lspr

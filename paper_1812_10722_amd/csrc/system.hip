@@ -1,0 +1,207 @@
+// The complex block systems of Eq. matrix_lspr / Eq. matrix_multi on top of the real layer
+// operators, their right-hand side, a batched complex GMRES with the Arnoldi process on the
+// device (section "Code modifications and added features": GMRES for complex numbers), and
+// the dipole moment / extinction cross-section post-processing.
+//
+// Unknowns per wavelength, in sorted panel order: phi (N values) then psi = dphi/dn on the
+// interior side (N values).  For target panel i of surface t and eps ratios r_s = eps_s/eps_m:
+//   interior row:  phi_i/2 + sum_{j in t} K_ij phi_j - sum_{j in t} V_ij psi_j = 0
+//   exterior row:  phi_i/2 - sum_j K_ij phi_j + sum_j r_s(j) V_ij psi_j
+//                      = sum_j (1 - r_s(j)) V_ij g_j,     g = dphi_inc/dn = -E . n.
+// The V columns carry sigma_j = r_s(j) psi_j, so the own-surface V sum divided by r_t gives
+// the interior row's V psi term.
+#include <cmath>
+#include <cstdio>
+
+#include "operator.hpp"
+#include "system.hpp"
+
+namespace lspr {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr double INV_4PI = 0.07957747154594767;  // 1 / (4 pi)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// x (complex, [col][2N] sorted order) -> packed real columns dens [N][2 pad]:
+// K columns 2s, 2s+1 = Re, Im phi; V columns pad + 2s, pad + 2s + 1 = Re, Im sigma.
+template <class T>
+__global__ void k_pack(const double2* __restrict__ x, int64_t x_stride,
+                       const int32_t* __restrict__ cols, int nslot, int N,
+                       const double2* __restrict__ ratio, int S,
+                       const int32_t* __restrict__ surf, int pad, T* __restrict__ dens) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * pad) return;
+    const int i = static_cast<int>(t / pad), c = static_cast<int>(t % pad);
+    const int slot = c >> 1;
+    T* row = dens + static_cast<size_t>(i) * 2 * pad;
+    if (slot >= nslot) {
+        row[c] = T(0);
+        row[pad + c] = T(0);
+        return;
+    }
+    const int col = cols ? cols[slot] : slot;
+    const double2* xc = x + col * x_stride;
+    const double2 phi = xc[i];
+    const double2 sig = cmul(ratio[col * S + surf[i]], xc[N + i]);
+    row[c] = static_cast<T>((c & 1) ? phi.y : phi.x);
+    row[pad + c] = static_cast<T>((c & 1) ? sig.y : sig.x);
+}
+
+// Rows of Eq. matrix_multi from the raw sums (no 1/4pi yet).
+__global__ void k_combine(const double2* __restrict__ x, int64_t x_stride,
+                          double2* __restrict__ y, int64_t y_stride,
+                          const int32_t* __restrict__ cols, int nslot, int N,
+                          const double2* __restrict__ ratio, int S,
+                          const int32_t* __restrict__ surf, int pad,
+                          const double* __restrict__ out_self, const double* __restrict__ out_all) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * nslot) return;
+    const int slot = static_cast<int>(t / N), i = static_cast<int>(t % N);
+    const int col = cols ? cols[slot] : slot;
+    const double2 phi = x[col * x_stride + i];
+    const double* ra = out_all + static_cast<size_t>(i) * 2 * pad;
+    const double* rs = (out_self ? out_self : out_all) + static_cast<size_t>(i) * 2 * pad;
+    const double2 k_all = make_double2(ra[2 * slot] * INV_4PI, ra[2 * slot + 1] * INV_4PI);
+    const double2 v_all = make_double2(ra[pad + 2 * slot] * INV_4PI, ra[pad + 2 * slot + 1] * INV_4PI);
+    const double2 k_own = make_double2(rs[2 * slot] * INV_4PI, rs[2 * slot + 1] * INV_4PI);
+    const double2 v_own = make_double2(rs[pad + 2 * slot] * INV_4PI, rs[pad + 2 * slot + 1] * INV_4PI);
+    const double2 r = ratio[col * S + surf[i]];
+    const double den = r.x * r.x + r.y * r.y;
+    const double2 rinv = make_double2(r.x / den, -r.y / den);
+    const double2 vpsi = cmul(rinv, v_own);
+    double2* yc = y + col * y_stride;
+    yc[i] = make_double2(0.5 * phi.x + k_own.x - vpsi.x, 0.5 * phi.y + k_own.y - vpsi.y);
+    yc[N + i] = make_double2(0.5 * phi.x - k_all.x + v_all.x, 0.5 * phi.y - k_all.y + v_all.y);
+}
+
+// b = [0; sum_s (1 - r_s) sum_d E_d u[s][d]] / 4pi per column
+__global__ void k_rhs(const double* __restrict__ u, int S, int N, int ncolumn,
+                      const double2* __restrict__ ratio, double e0, double e1, double e2,
+                      double2* __restrict__ b, int64_t b_stride) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * ncolumn) return;
+    const int col = static_cast<int>(t / N), i = static_cast<int>(t % N);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < S; ++s) {
+        const double us = (e0 * u[(3 * s) * N + i] + e1 * u[(3 * s + 1) * N + i] +
+                           e2 * u[(3 * s + 2) * N + i]) * INV_4PI;
+        const double2 r = ratio[col * S + s];
+        acc.x += (1.0 - r.x) * us;
+        acc.y += -r.y * us;
+    }
+    b[col * b_stride + i] = make_double2(0.0, 0.0);
+    b[col * b_stride + N + i] = acc;
+}
+
+// RHS geometry columns: V column 3s + d holds -n_d on surface s, zero elsewhere.
+template <class T>
+__global__ void k_rhs_dens(const double* __restrict__ nrm, const int32_t* __restrict__ surf,
+                           int N, int S, int pad, T* __restrict__ dens) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * 2 * pad) return;
+    const int i = static_cast<int>(t / (2 * pad)), c = static_cast<int>(t % (2 * pad));
+    T v = T(0);
+    if (c >= pad && c - pad < 3 * S) {
+        const int s = (c - pad) / 3, d = (c - pad) % 3;
+        if (surf[i] == s) v = static_cast<T>(-nrm[3 * i + d]);
+    }
+    dens[t] = v;
+}
+
+__global__ void k_rhs_extract(const double* __restrict__ out, int N, int S, int pad,
+                              double* __restrict__ u) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * 3 * S) return;
+    const int k = static_cast<int>(t / N), i = static_cast<int>(t % N);
+    u[t] = out[static_cast<size_t>(i) * 2 * pad + pad + k];
+}
+
+}  // namespace
+
+void precompute_rhs(Geometry& g) {
+    hipStream_t s = g.stream;
+    const Cols c = make_cols(3 * g.S);
+    const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
+    const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
+    DevBuf<uint8_t> dens(nd * esz);
+    DevBuf<double> oa(nd), os(g.S > 1 ? nd : 0);
+    const int64_t tot = static_cast<int64_t>(nd);
+    if (g.precision == LSPR_FP32)
+        hipLaunchKernelGGL(k_rhs_dens<float>, dim3((tot + TPB - 1) / TPB), dim3(TPB), 0, s,
+                           g.nrm.p, g.surf.p, g.N, g.S, c.pad, reinterpret_cast<float*>(dens.p));
+    else
+        hipLaunchKernelGGL(k_rhs_dens<double>, dim3((tot + TPB - 1) / TPB), dim3(TPB), 0, s,
+                           g.nrm.p, g.surf.p, g.N, g.S, c.pad, reinterpret_cast<double*>(dens.p));
+    LSPR_HIP(hipGetLastError());
+    apply_raw(g, c, dens.p, os.p, oa.p, s);
+    g.rhs_u.alloc(static_cast<size_t>(3) * g.S * g.N);
+    const int64_t nu = static_cast<int64_t>(3) * g.S * g.N;
+    hipLaunchKernelGGL(k_rhs_extract, dim3((nu + TPB - 1) / TPB), dim3(TPB), 0, s, oa.p, g.N,
+                       g.S, c.pad, g.rhs_u.p);
+    LSPR_HIP(hipGetLastError());
+    LSPR_HIP(hipStreamSynchronize(s));
+}
+
+void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s) {
+    std::vector<double2> h(static_cast<size_t>(B) * g.S);
+    for (int b = 0; b < B; ++b) {
+        const double mr = eps.em_re[b], mi = eps.em_im[b];
+        const double den = mr * mr + mi * mi;
+        LSPR_REQUIRE(den > 0.0, LSPR_E_INVALID, "eps_medium must be nonzero");
+        for (int k = 0; k < g.S; ++k) {
+            const double sr = eps.es_re[b * g.S + k], si = eps.es_im[b * g.S + k];
+            LSPR_REQUIRE(sr * sr + si * si > 1e-24 * den, LSPR_E_INVALID,
+                         "eps_surface must be nonzero");
+            h[b * g.S + k] = make_double2((sr * mr + si * mi) / den, (si * mr - sr * mi) / den);
+        }
+    }
+    d.reserve(h.size());
+    LSPR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    LSPR_HIP(hipStreamSynchronize(s));  // h is local
+}
+
+// y[col] = A(eps[col]) x[col] for the nslot columns listed in d_cols (or 0..nslot-1).
+void system_apply(Geometry& g, int nslot, const double2* ratio_d, const double2* x,
+                  int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
+                  hipStream_t s) {
+    const Cols c = make_cols(2 * nslot);
+    const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
+    const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
+    g.ws_dens.reserve(nd * esz);
+    g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
+    double* oa = reinterpret_cast<double*>(g.ws_out.p);
+    double* os = g.S > 1 ? oa + nd : nullptr;
+    const int64_t tp = static_cast<int64_t>(g.N) * c.pad;
+    if (g.precision == LSPR_FP32)
+        hipLaunchKernelGGL(k_pack<float>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
+                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad,
+                           reinterpret_cast<float*>(g.ws_dens.p));
+    else
+        hipLaunchKernelGGL(k_pack<double>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
+                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad,
+                           reinterpret_cast<double*>(g.ws_dens.p));
+    LSPR_HIP(hipGetLastError());
+    apply_raw(g, c, g.ws_dens.p, os, oa, s);
+    const int64_t tc = static_cast<int64_t>(g.N) * nslot;
+    hipLaunchKernelGGL(k_combine, dim3((tc + TPB - 1) / TPB), dim3(TPB), 0, s, x, x_stride, y,
+                       y_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad, os, oa);
+    LSPR_HIP(hipGetLastError());
+}
+
+void system_rhs(Geometry& g, int ncolumn, const double2* ratio_d, const double* e_field,
+                double2* b, int64_t b_stride, hipStream_t s) {
+    const int64_t t = static_cast<int64_t>(g.N) * ncolumn;
+    hipLaunchKernelGGL(k_rhs, dim3((t + TPB - 1) / TPB), dim3(TPB), 0, s, g.rhs_u.p, g.S, g.N,
+                       ncolumn, ratio_d, e_field[0], e_field[1], e_field[2], b, b_stride);
+    LSPR_HIP(hipGetLastError());
+}
+
+}  // namespace lspr

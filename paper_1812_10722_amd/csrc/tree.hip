@@ -1,0 +1,558 @@
+// Octree, interaction lists, near-singular correction table and singular self-terms
+// (set-up, once per mesh and parameter set).
+//
+// Section "Acceleration strategies": sources are grouped in the boxes of an octree whose
+// leaves hold at most N_crit sources; a target uses a box's Taylor expansion when the box is
+// far enough (MAC theta > r_b / r, r measured from the box centre), opens it otherwise, and
+// sums a leaf that is still too close directly.  Here the targets of a group of consecutive
+// panels (a "chunk") share their lists: a box is accepted for the whole chunk when
+// r_b < theta (d - r_T) (d the centre distance, r_T the chunk radius), which implies the
+// paper's per-target criterion for every target of the chunk.  Section "Integral evaluation":
+// near-singular pairs (|x_i - c_j| <= L_j / threshold) and the singular self pair use other
+// rules; the table built here holds, per such pair, the fine-rule value minus the far-rule
+// value that the direct sum adds, so that the far-field kernels can treat all pairs alike.
+#include <cmath>
+
+#include "primitives.hpp"
+
+namespace lspr {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAX_LEVEL = 16;   // 16 Morton bits per axis
+constexpr int STACK = 160;
+
+// For each box to split (start, end, level) the lower bounds of its 8 octants; out[9*b + 8] =
+// end.  The octant bits follow the box's common prefix, so they are sorted inside the box.
+__global__ void k_split(const uint64_t* __restrict__ keys, const int32_t* __restrict__ se,
+                        const int32_t* __restrict__ level, int nb, int32_t* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * 9) return;
+    const int b = t / 9, o = t % 9;
+    const int start = se[2 * b], end = se[2 * b + 1];
+    if (o == 8) {
+        out[t] = end;
+        return;
+    }
+    const int shift = 45 - 3 * level[b];
+    int lo = start, hi = end;  // first index with octant >= o
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int oct = static_cast<int>((keys[mid] >> shift) & 7);
+        if (oct < o) lo = mid + 1;
+        else hi = mid;
+    }
+    out[t] = lo;
+}
+
+__device__ inline void node_pos(const double* v, const double* rule, int g, double* y) {
+    const double b0 = rule[4 * g], b1 = rule[4 * g + 1], b2 = rule[4 * g + 2];
+    for (int d = 0; d < 3; ++d) y[d] = b0 * v[d] + b1 * v[3 + d] + b2 * v[6 + d];
+}
+
+template <class Op>
+__device__ inline double block_reduce(double v, double* sh, Op op) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+struct MinOp { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct MaxOp { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+
+// One block per box: centre of the nodes' bounding box, node radius, vertex radius, max L.
+__global__ void __launch_bounds__(TPB) k_box_stats(Box* __restrict__ boxes,
+                                                   const double* __restrict__ tri,
+                                                   const double* __restrict__ area,
+                                                   const double* __restrict__ rule, int K) {
+    __shared__ double sh[TPB];
+    Box& b = boxes[blockIdx.x];
+    const int start = b.start, end = b.end;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int p = start + threadIdx.x; p < end; p += TPB) {
+        const double* v = tri + 9 * static_cast<size_t>(p);
+        for (int gq = 0; gq < K; ++gq) {
+            double y[3];
+            node_pos(v, rule, gq, y);
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = fmin(lo[d], y[d]);
+                hi[d] = fmax(hi[d], y[d]);
+            }
+        }
+    }
+    double c[3];
+    for (int d = 0; d < 3; ++d)
+        c[d] = 0.5 * (block_reduce(lo[d], sh, MinOp()) + block_reduce(hi[d], sh, MaxOp()));
+    double rb = 0.0, rv = 0.0, lm = 0.0;
+    for (int p = start + threadIdx.x; p < end; p += TPB) {
+        const double* v = tri + 9 * static_cast<size_t>(p);
+        for (int gq = 0; gq < K; ++gq) {
+            double y[3];
+            node_pos(v, rule, gq, y);
+            const double dx = y[0] - c[0], dy = y[1] - c[1], dz = y[2] - c[2];
+            rb = fmax(rb, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double dx = v[3 * k] - c[0], dy = v[3 * k + 1] - c[1], dz = v[3 * k + 2] - c[2];
+            rv = fmax(rv, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        lm = fmax(lm, sqrt(2.0 * area[p]));
+    }
+    rb = block_reduce(rb, sh, MaxOp());
+    rv = block_reduce(rv, sh, MaxOp());
+    lm = block_reduce(lm, sh, MaxOp());
+    if (threadIdx.x == 0) {
+        b.cx = c[0];
+        b.cy = c[1];
+        b.cz = c[2];
+        b.rb = rb;
+        b.rv = rv;
+        b.lmax = lm;
+    }
+}
+
+// One block per chunk: centre of the centroids' bounding box and radius.
+__global__ void __launch_bounds__(TPB) k_chunk_stats(Chunk* __restrict__ ch,
+                                                     const double* __restrict__ cen) {
+    __shared__ double sh[TPB];
+    Chunk& c = ch[blockIdx.x];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int p = c.start + threadIdx.x; p < c.end; p += TPB)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], cen[3 * p + d]);
+            hi[d] = fmax(hi[d], cen[3 * p + d]);
+        }
+    double m[3];
+    for (int d = 0; d < 3; ++d)
+        m[d] = 0.5 * (block_reduce(lo[d], sh, MinOp()) + block_reduce(hi[d], sh, MaxOp()));
+    double r = 0.0;
+    for (int p = c.start + threadIdx.x; p < c.end; p += TPB) {
+        const double dx = cen[3 * p] - m[0], dy = cen[3 * p + 1] - m[1], dz = cen[3 * p + 2] - m[2];
+        r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    r = block_reduce(r, sh, MaxOp());
+    if (threadIdx.x == 0) {
+        c.cx = m[0];
+        c.cy = m[1];
+        c.cz = m[2];
+        c.r = r;
+    }
+}
+
+struct ListParams {
+    double theta, inv_thr;
+    int min_panels;
+    int S;
+    const int32_t* roots;  // [S]
+};
+
+// Interaction lists of one chunk against every surface's tree, own surface first.  With
+// fill == false only counts are produced.  A box is expanded (M2P) when the MAC holds for the
+// whole chunk, no target of the chunk can be near-singular to any of its panels
+// (d - r_T - r_v > L_max / threshold), and it holds enough panels for the expansion to be
+// cheaper than the direct sum; otherwise a leaf, or a box that passes the MAC but is small,
+// is summed directly.  Direct ranges that touch are merged.
+__global__ void k_lists(const Box* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                        int n_chunks, ListParams lp, bool fill, int32_t* __restrict__ m2p_cnt,
+                        int32_t* __restrict__ p2p_cnt, int32_t* __restrict__ m2p_selfc,
+                        int32_t* __restrict__ p2p_selfc, const int64_t* __restrict__ m2p_off,
+                        const int64_t* __restrict__ p2p_off, int32_t* __restrict__ m2p_box,
+                        Range* __restrict__ p2p_rng, int64_t* __restrict__ pairs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const Chunk T = chunks[c];
+    const int nt = T.end - T.start;
+    int stack[STACK];
+    int nm = 0, np = 0, nm_self = 0, np_self = 0;
+    int64_t pp = 0, mp = 0;
+    int64_t mo = fill ? m2p_off[c] : 0, po = fill ? p2p_off[c] : 0;
+    for (int pass = 0; pass < lp.S; ++pass) {
+        const int s = pass == 0 ? T.surf : (pass <= T.surf ? pass - 1 : pass);
+        int top = 0;
+        stack[top++] = lp.roots[s];
+        int last_end = -1;
+        while (top > 0) {
+            const int bi = stack[--top];
+            const Box B = boxes[bi];
+            const double dx = T.cx - B.cx, dy = T.cy - B.cy, dz = T.cz - B.cz;
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            const bool ok = d > T.r && B.rb < lp.theta * (d - T.r) &&
+                            (d - T.r - B.rv) > B.lmax * lp.inv_thr;
+            const int npan = B.end - B.start;
+            if (ok && npan >= lp.min_panels) {
+                if (fill) m2p_box[mo + nm] = bi;
+                ++nm;
+                mp += nt;
+            } else if (ok || B.nchild == 0) {
+                if (B.start == last_end) {
+                    if (fill) p2p_rng[po + np - 1].end = B.end;
+                } else {
+                    if (fill) p2p_rng[po + np] = Range{B.start, B.end};
+                    ++np;
+                }
+                last_end = B.end;
+                pp += static_cast<int64_t>(nt) * npan;
+            } else {
+                if (top + B.nchild > STACK) {  // cannot happen for depth <= 16; stay safe
+                    continue;
+                }
+                for (int k = B.nchild - 1; k >= 0; --k) stack[top++] = B.child + k;
+            }
+        }
+        if (pass == 0) {
+            nm_self = nm;
+            np_self = np;
+        }
+    }
+    if (!fill) {
+        m2p_cnt[c] = nm;
+        p2p_cnt[c] = np;
+        m2p_selfc[c] = nm_self;
+        p2p_selfc[c] = np_self;
+        pairs[2 * c] = pp;
+        pairs[2 * c + 1] = mp;
+    }
+}
+
+struct NearParams {
+    double inv_thr;
+    int S;
+    const int32_t* roots;
+};
+
+// Near-singular source panels of every target panel, all surfaces, ascending index order.
+__global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__ cen,
+                       const double* __restrict__ area, int N, NearParams np, bool fill,
+                       int64_t* __restrict__ cnt, const int64_t* __restrict__ off,
+                       int32_t* __restrict__ col) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double x = cen[3 * i], y = cen[3 * i + 1], z = cen[3 * i + 2];
+    int stack[STACK];
+    int64_t k = fill ? off[i] : 0;
+    int n = 0;
+    for (int s = 0; s < np.S; ++s) {
+        int top = 0;
+        stack[top++] = np.roots[s];
+        while (top > 0) {
+            const int bi = stack[--top];
+            const Box B = boxes[bi];
+            const double dx = x - B.cx, dy = y - B.cy, dz = z - B.cz;
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d - B.rv > B.lmax * np.inv_thr * (1.0 + 1e-9) + 1e-12) continue;
+            if (B.nchild == 0) {
+                for (int j = B.start; j < B.end; ++j) {
+                    if (j == i) continue;
+                    const double ex = x - cen[3 * j], ey = y - cen[3 * j + 1], ez = z - cen[3 * j + 2];
+                    const double dj = sqrt(ex * ex + ey * ey + ez * ez);
+                    if (dj <= sqrt(2.0 * area[j]) * np.inv_thr) {
+                        if (fill) col[k + n] = j;
+                        ++n;
+                    }
+                }
+            } else {
+                if (top + B.nchild > STACK) continue;
+                for (int q = B.nchild - 1; q >= 0; --q) stack[top++] = B.child + q;
+            }
+        }
+    }
+    if (!fill) cnt[i] = n;
+}
+
+// Rule sums of one panel at point x (no 1/4pi): V = sum w/r, K = sum w n.(x - y)/r^3.
+__device__ inline void rule_sums(const double* v, const double* nrm, double A, const double* x,
+                                 const double* rule, int K, double& sv, double& sk) {
+    sv = 0.0;
+    sk = 0.0;
+    for (int gq = 0; gq < K; ++gq) {
+        double y[3];
+        node_pos(v, rule, gq, y);
+        const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = sqrt(r2);
+        const double w = A * rule[4 * gq + 3];
+        sv += w / r;
+        sk += w * (nrm[0] * dx + nrm[1] * dy + nrm[2] * dz) / (r2 * r);
+    }
+}
+
+// Fine-rule minus far-rule values for every near-singular pair.
+__global__ void k_near_values(const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
+                              int64_t nnz, const double* __restrict__ tri,
+                              const double* __restrict__ cen, const double* __restrict__ nrm,
+                              const double* __restrict__ area, const double* __restrict__ far_rule,
+                              int K, const double* __restrict__ fine_rule, int Kf,
+                              double* __restrict__ dv, double* __restrict__ dk) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int i = row_of[e], j = col[e];
+    const double* v = tri + 9 * static_cast<size_t>(j);
+    double fv, fk, cv, ck;
+    rule_sums(v, nrm + 3 * j, area[j], cen + 3 * i, fine_rule, Kf, fv, fk);
+    rule_sums(v, nrm + 3 * j, area[j], cen + 3 * i, far_rule, K, cv, ck);
+    dv[e] = fv - cv;
+    dk[e] = fk - ck;
+}
+
+__global__ void k_row_of(const int64_t* __restrict__ off, int N, int32_t* __restrict__ row_of) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) row_of[e] = i;
+}
+
+// Singular self term (section "Integral evaluation"): the panel is split at its centroid into
+// three sub-triangles (centroid, edge); for an edge at perpendicular distance h the radial
+// integral is exact (the ray at angle a from the perpendicular meets the edge at h / cos a)
+// and the angle integral takes n_k Gauss-Legendre nodes.  Result without 1/4pi.
+__global__ void k_vself(const double* __restrict__ tri, const double* __restrict__ cen,
+                        const double* __restrict__ nrm, int N, const double* __restrict__ gl_t,
+                        const double* __restrict__ gl_w, int nk, double* __restrict__ vself) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double* v = tri + 9 * static_cast<size_t>(i);
+    const double* n = nrm + 3 * i;
+    const double* x = cen + 3 * i;
+    double total = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        const double* a = v + 3 * e;
+        const double* b = v + 3 * ((e + 1) % 3);
+        const double ex = b[0] - a[0], ey = b[1] - a[1], ez = b[2] - a[2];
+        const double len = sqrt(ex * ex + ey * ey + ez * ez);
+        const double ux = ex / len, uy = ey / len, uz = ez / len;
+        // in-plane direction away from the panel: edge x normal
+        const double ox = uy * n[2] - uz * n[1], oy = uz * n[0] - ux * n[2], oz = ux * n[1] - uy * n[0];
+        const double ax = a[0] - x[0], ay = a[1] - x[1], az = a[2] - x[2];
+        const double bx = b[0] - x[0], by = b[1] - x[1], bz = b[2] - x[2];
+        const double h = ax * ox + ay * oy + az * oz;
+        const double al = atan2(ax * ux + ay * uy + az * uz, h);
+        const double be = atan2(bx * ux + by * uy + bz * uz, h);
+        const double half = 0.5 * (be - al), mid = 0.5 * (be + al);
+        double s = 0.0;
+        for (int k = 0; k < nk; ++k) s += gl_w[k] / cos(mid + half * gl_t[k]);
+        total += half * h * s;
+    }
+    vself[i] = total;
+}
+
+// Copies a host vector to a new device buffer; waits for the copy, so temporaries may be passed.
+DevBuf<double> upload(const std::vector<double>& h, hipStream_t s) {
+    DevBuf<double> d(h.size());
+    LSPR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    LSPR_HIP(hipStreamSynchronize(s));
+    return d;
+}
+
+std::vector<double> rule_rows(int n) {
+    std::vector<double> bary, w;
+    LSPR_REQUIRE(triangle_rule(n, bary, w), LSPR_E_INVALID, "unsupported triangle rule");
+    std::vector<double> r(4 * n);
+    for (int q = 0; q < n; ++q) {
+        r[4 * q] = bary[3 * q];
+        r[4 * q + 1] = bary[3 * q + 1];
+        r[4 * q + 2] = bary[3 * q + 2];
+        r[4 * q + 3] = w[q];
+    }
+    return r;
+}
+
+}  // namespace
+
+void build_tree(Geometry& g) {
+    hipStream_t s = g.stream;
+    std::vector<Box> bx;
+    g.surf_root.assign(g.S, 0);
+    g.max_depth = 0;
+    DevBuf<int32_t> se_d, lv_d, out_d;
+    for (int sf = 0; sf < g.S; ++sf) {
+        Box root{};
+        root.start = g.surf_start[sf];
+        root.end = g.surf_start[sf + 1];
+        root.child = -1;
+        root.nchild = 0;
+        root.level = 0;
+        root.surf = sf;
+        g.surf_root[sf] = static_cast<int>(bx.size());
+        bx.push_back(root);
+        std::vector<int> frontier = {g.surf_root[sf]};
+        for (int level = 0; level < MAX_LEVEL && !frontier.empty(); ++level) {
+            std::vector<int> split;
+            for (int b : frontier)
+                if (bx[b].end - bx[b].start > g.ncrit) split.push_back(b);
+            if (split.empty()) break;
+            const int nb = static_cast<int>(split.size());
+            std::vector<int32_t> se(2 * nb), lv(nb), out(9 * nb);
+            for (int k = 0; k < nb; ++k) {
+                se[2 * k] = bx[split[k]].start;
+                se[2 * k + 1] = bx[split[k]].end;
+                lv[k] = bx[split[k]].level;
+            }
+            se_d.reserve(se.size());
+            lv_d.reserve(lv.size());
+            out_d.reserve(out.size());
+            LSPR_HIP(hipMemcpyAsync(se_d.p, se.data(), se.size() * 4, hipMemcpyHostToDevice, s));
+            LSPR_HIP(hipMemcpyAsync(lv_d.p, lv.data(), lv.size() * 4, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_split, dim3((9 * nb + TPB - 1) / TPB), dim3(TPB), 0, s,
+                               g.morton.p, se_d.p, lv_d.p, nb, out_d.p);
+            LSPR_HIP(hipGetLastError());
+            LSPR_HIP(hipMemcpyAsync(out.data(), out_d.p, out.size() * 4, hipMemcpyDeviceToHost, s));
+            LSPR_HIP(hipStreamSynchronize(s));
+            std::vector<int> next;
+            for (int k = 0; k < nb; ++k) {
+                const int b = split[k];
+                bx[b].child = static_cast<int>(bx.size());
+                int nc = 0;
+                for (int o = 0; o < 8; ++o) {
+                    if (out[9 * k + o] < out[9 * k + o + 1]) {
+                        Box c{};
+                        c.start = out[9 * k + o];
+                        c.end = out[9 * k + o + 1];
+                        c.child = -1;
+                        c.nchild = 0;
+                        c.level = level + 1;
+                        c.surf = sf;
+                        next.push_back(static_cast<int>(bx.size()));
+                        bx.push_back(c);
+                        ++nc;
+                    }
+                }
+                bx[b].nchild = nc;
+                g.max_depth = std::max(g.max_depth, level + 1);
+            }
+            frontier.swap(next);
+        }
+    }
+    g.n_boxes = static_cast<int>(bx.size());
+    g.n_leaves = 0;
+    for (const Box& b : bx) g.n_leaves += b.nchild == 0;
+    g.boxes.alloc(bx.size());
+    LSPR_HIP(hipMemcpyAsync(g.boxes.p, bx.data(), bx.size() * sizeof(Box), hipMemcpyHostToDevice, s));
+    g.far_rule = upload(rule_rows(g.K), s);
+    hipLaunchKernelGGL(k_box_stats, dim3(g.n_boxes), dim3(TPB), 0, s, g.boxes.p, g.tri.p,
+                       g.area.p, g.far_rule.p, g.K);
+    LSPR_HIP(hipGetLastError());
+    // target chunks: consecutive panels of one surface
+    std::vector<Chunk> ch;
+    for (int sf = 0; sf < g.S; ++sf)
+        for (int a = g.surf_start[sf]; a < g.surf_start[sf + 1]; a += g.tchunk) {
+            Chunk c{};
+            c.start = a;
+            c.end = std::min(a + g.tchunk, g.surf_start[sf + 1]);
+            c.surf = sf;
+            ch.push_back(c);
+        }
+    g.n_chunks = static_cast<int>(ch.size());
+    g.chunks.alloc(ch.size());
+    LSPR_HIP(hipMemcpyAsync(g.chunks.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_chunk_stats, dim3(g.n_chunks), dim3(TPB), 0, s, g.chunks.p, g.cen.p);
+    LSPR_HIP(hipGetLastError());
+    LSPR_HIP(hipStreamSynchronize(s));
+}
+
+void build_lists(Geometry& g) {
+    hipStream_t s = g.stream;
+    const int nc = g.n_chunks;
+    DevBuf<int32_t> roots(g.S);
+    LSPR_HIP(hipMemcpyAsync(roots.p, g.surf_root.data(), g.S * 4, hipMemcpyHostToDevice, s));
+    ListParams lp{g.method == LSPR_DENSE ? 0.0 : g.theta, 1.0 / g.threshold, g.m2p_min_panels,
+                  g.S, roots.p};
+    DevBuf<int32_t> mc(nc), pc(nc);
+    g.m2p_self.alloc(nc);
+    g.p2p_self.alloc(nc);
+    DevBuf<int64_t> pairs(2 * nc);
+    const dim3 grid((nc + 63) / 64), blk(64);
+    hipLaunchKernelGGL(k_lists, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, false, mc.p,
+                       pc.p, g.m2p_self.p, g.p2p_self.p, nullptr, nullptr, nullptr, nullptr,
+                       pairs.p);
+    LSPR_HIP(hipGetLastError());
+    std::vector<int32_t> mh(nc), ph(nc);
+    std::vector<int64_t> prh(2 * nc);
+    LSPR_HIP(hipMemcpyAsync(mh.data(), mc.p, nc * 4, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipMemcpyAsync(ph.data(), pc.p, nc * 4, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipMemcpyAsync(prh.data(), pairs.p, 2 * nc * 8, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> mo(nc + 1, 0), po(nc + 1, 0);
+    g.p2p_pairs = 0;
+    g.m2p_pairs = 0;
+    for (int c = 0; c < nc; ++c) {
+        mo[c + 1] = mo[c] + mh[c];
+        po[c + 1] = po[c] + ph[c];
+        g.p2p_pairs += prh[2 * c];
+        g.m2p_pairs += prh[2 * c + 1];
+    }
+    g.n_m2p = mo[nc];
+    g.n_p2p = po[nc];
+    LSPR_REQUIRE(g.n_m2p < (1ll << 31) && g.n_p2p < (1ll << 31), LSPR_E_INVALID,
+                 "interaction lists too long");
+    DevBuf<int64_t> mo_d(nc + 1), po_d(nc + 1);
+    LSPR_HIP(hipMemcpyAsync(mo_d.p, mo.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s));
+    LSPR_HIP(hipMemcpyAsync(po_d.p, po.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s));
+    g.m2p_box.alloc(std::max<int64_t>(g.n_m2p, 1));
+    g.p2p_rng.alloc(std::max<int64_t>(g.n_p2p, 1));
+    hipLaunchKernelGGL(k_lists, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, true, mc.p,
+                       pc.p, g.m2p_self.p, g.p2p_self.p, mo_d.p, po_d.p, g.m2p_box.p,
+                       g.p2p_rng.p, pairs.p);
+    LSPR_HIP(hipGetLastError());
+    std::vector<int32_t> mo32(nc + 1), po32(nc + 1);
+    for (int c = 0; c <= nc; ++c) {
+        mo32[c] = static_cast<int32_t>(mo[c]);
+        po32[c] = static_cast<int32_t>(po[c]);
+    }
+    g.m2p_off.alloc(nc + 1);
+    g.p2p_off.alloc(nc + 1);
+    LSPR_HIP(hipMemcpyAsync(g.m2p_off.p, mo32.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    LSPR_HIP(hipMemcpyAsync(g.p2p_off.p, po32.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    LSPR_HIP(hipStreamSynchronize(s));
+}
+
+void build_near_table(Geometry& g) {
+    hipStream_t s = g.stream;
+    const int N = g.N;
+    DevBuf<int32_t> roots(g.S);
+    LSPR_HIP(hipMemcpyAsync(roots.p, g.surf_root.data(), g.S * 4, hipMemcpyHostToDevice, s));
+    NearParams np{1.0 / g.threshold, g.S, roots.p};
+    DevBuf<int64_t> cnt(N + 1);
+    const dim3 grid((N + TPB - 1) / TPB), blk(TPB);
+    hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, false,
+                       cnt.p, nullptr, nullptr);
+    LSPR_HIP(hipGetLastError());
+    scan_exclusive(cnt.p, cnt.p, N, s);
+    int64_t nnz = 0;
+    LSPR_HIP(hipMemcpyAsync(&nnz, cnt.p + N, 8, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipStreamSynchronize(s));
+    LSPR_REQUIRE(nnz < (1ll << 31), LSPR_E_INVALID, "near-singular table too large");
+    g.n_near = nnz;
+    g.near_col.alloc(std::max<int64_t>(nnz, 1));
+    g.near_dv.alloc(std::max<int64_t>(nnz, 1));
+    g.near_dk.alloc(std::max<int64_t>(nnz, 1));
+    hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, true,
+                       nullptr, cnt.p, g.near_col.p);
+    LSPR_HIP(hipGetLastError());
+    g.near_off64 = std::move(cnt);
+    DevBuf<int32_t> row_of(std::max<int64_t>(nnz, 1));
+    hipLaunchKernelGGL(k_row_of, grid, blk, 0, s, g.near_off64.p, N, row_of.p);
+    LSPR_HIP(hipGetLastError());
+    DevBuf<double> fine = upload(rule_rows(g.Kf), s);
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_near_values, dim3((nnz + TPB - 1) / TPB), dim3(TPB), 0, s, row_of.p,
+                           g.near_col.p, nnz, g.tri.p, g.cen.p, g.nrm.p, g.area.p, g.far_rule.p,
+                           g.K, fine.p, g.Kf, g.near_dv.p, g.near_dk.p);
+        LSPR_HIP(hipGetLastError());
+    }
+    std::vector<double> t, w;
+    gauss_legendre(g.Nk, t, w);
+    DevBuf<double> t_d = upload(t, s), w_d = upload(w, s);
+    g.vself.alloc(N);
+    hipLaunchKernelGGL(k_vself, grid, blk, 0, s, g.tri.p, g.cen.p, g.nrm.p, N, t_d.p, w_d.p,
+                       g.Nk, g.vself.p);
+    LSPR_HIP(hipGetLastError());
+    LSPR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace lspr

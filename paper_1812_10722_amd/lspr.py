@@ -1,0 +1,253 @@
+"""Thin ctypes binding of liblspr.so (the C ABI declared in include/lspr.h).
+
+Argument marshalling only: every step of the method runs inside the HIP library.  PyTorch is
+used for device memory and streams (tensor.data_ptr(), torch.cuda.current_stream()).  The
+library must have been built (paper_1812_10722_amd/build.py); importing this module without it
+raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblspr.so")
+
+LSPR_OK, LSPR_E_INVALID, LSPR_E_MESH, LSPR_E_NOMEM, LSPR_E_DEVICE, LSPR_E_NOCONV, LSPR_E_BUSY = range(7)
+LSPR_DENSE, LSPR_TREECODE = 0, 1
+LSPR_FP64, LSPR_FP32 = 0, 1
+
+
+class lspr_c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class lspr_surface(C.Structure):
+    _fields_ = [("n_vert", C.c_int32), ("vert", C.c_void_p), ("n_tri", C.c_int32),
+                ("tri", C.c_void_p)]
+
+
+class lspr_op_params(C.Structure):
+    _fields_ = [("k_far", C.c_int32), ("k_fine", C.c_int32), ("n_k", C.c_int32),
+                ("threshold", C.c_double), ("method", C.c_int32), ("p", C.c_int32),
+                ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
+                ("m2p_min_panels", C.c_int32)]
+
+
+class lspr_gmres_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("precond", C.c_int32)]
+
+
+class lspr_geometry_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_panels", "n_surfaces", "n_nodes", "n_boxes", "n_leaves", "n_target_chunks", "n_m2p",
+        "n_p2p_ranges", "p2p_pairs", "m2p_pairs", "n_near", "device_bytes")] + \
+        [(n, C.c_int32) for n in ("n_terms", "ncrit", "target_chunk", "max_depth")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1812_10722_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    P = C.POINTER
+    sig = {
+        "lspr_mesh_validate": (C.c_int, [P(lspr_surface), i32]),
+        "lspr_geometry_create": (C.c_int, [P(lspr_surface), i32, P(lspr_op_params), vp, P(vp)]),
+        "lspr_geometry_destroy": (C.c_int, [vp]),
+        "lspr_geometry_info": (C.c_int, [vp, P(lspr_geometry_stats)]),
+        "lspr_solve": (C.c_int, [vp, i32, P(dbl), P(lspr_c64), P(lspr_c64), P(dbl),
+                                 P(lspr_gmres_params), vp, vp, vp, P(lspr_c64), P(lspr_c64),
+                                 P(dbl), P(dbl), P(i32), P(dbl)]),
+        "lspr_apply": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), vp, vp, vp]),
+        "lspr_rhs": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), P(dbl), vp, vp]),
+        "lspr_triangle_rule": (C.c_int, [i32, P(dbl), P(dbl)]),
+        "lspr_gauss_legendre": (C.c_int, [i32, P(dbl), P(dbl)]),
+        "lspr_status_string": (C.c_char_p, [C.c_int]),
+        "lspr_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class LsprError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = _lib.lspr_last_error().decode()
+        super().__init__(f"{where}: {_lib.lspr_status_string(code).decode()} ({code}): {msg}")
+
+
+def _check(code, where, allow=()):
+    if code != LSPR_OK and code not in allow:
+        raise LsprError(code, where)
+    return code
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64_array(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return z, z.ctypes.data_as(C.POINTER(lspr_c64))
+
+
+# ------------------------------------------------------------------ functions with the C names
+def lspr_triangle_rule(n: int):
+    bary = np.zeros((n, 3))
+    w = np.zeros(n)
+    _check(_lib.lspr_triangle_rule(n, _dptr(bary), _dptr(w)), "lspr_triangle_rule")
+    return bary, w
+
+
+def lspr_gauss_legendre(n: int):
+    t = np.zeros(n)
+    w = np.zeros(n)
+    _check(_lib.lspr_gauss_legendre(n, _dptr(t), _dptr(w)), "lspr_gauss_legendre")
+    return t, w
+
+
+def lspr_mesh_validate(surfaces):
+    """surfaces: list of (verts [n,3] float64, tris [m,3] int32) host arrays."""
+    keep = []
+    arr = (lspr_surface * len(surfaces))()
+    for k, (v, t) in enumerate(surfaces):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        keep += [v, t]
+        arr[k] = lspr_surface(len(v), v.ctypes.data, len(t), t.ctypes.data)
+    return _lib.lspr_mesh_validate(arr, len(surfaces))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, theta=0.5,
+              ncrit=0, precision="fp32", m2p_min_panels=0):
+    return lspr_op_params(k_far, k_fine, n_k, threshold,
+                          LSPR_TREECODE if method == "treecode" else LSPR_DENSE, p, theta, ncrit,
+                          LSPR_FP32 if precision == "fp32" else LSPR_FP64, m2p_min_panels)
+
+
+def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1):
+    return lspr_gmres_params(tol, restart, max_iter, precond)
+
+
+class Geometry:
+    """A geometry handle (lspr_geometry_create / lspr_geometry_destroy).
+
+    surfaces: list of (verts, tris); numpy arrays are validated on the host with
+    lspr_mesh_validate and uploaded as torch cuda tensors; cuda tensors are used as they are.
+    """
+
+    def __init__(self, surfaces, op=None, stream=None, validate=True, **op_kw):
+        import torch
+        self.op = op if op is not None else op_params(**op_kw)
+        dev = []
+        host = []
+        for v, t in surfaces:
+            if isinstance(v, torch.Tensor):
+                dv = v.to(dtype=torch.float64).contiguous()
+                dt = t.to(dtype=torch.int32).contiguous()
+            else:
+                host.append((v, t))
+                dv = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+                dt = torch.as_tensor(np.ascontiguousarray(t, dtype=np.int32)).cuda()
+            dev.append((dv, dt))
+        if validate and host and len(host) == len(surfaces):
+            _check(lspr_mesh_validate(host), "lspr_mesh_validate")
+        arr = (lspr_surface * len(dev))()
+        for k, (dv, dt) in enumerate(dev):
+            arr[k] = lspr_surface(dv.shape[0], dv.data_ptr(), dt.shape[0], dt.data_ptr())
+        self._dev = dev
+        self.n_surf = len(dev)
+        self.n_panels = int(sum(dt.shape[0] for _, dt in dev))
+        h = C.c_void_p()
+        _check(_lib.lspr_geometry_create(arr, len(dev), C.byref(self.op), _stream_ptr(stream),
+                                         C.byref(h)), "lspr_geometry_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lspr_geometry_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        st = lspr_geometry_stats()
+        _check(_lib.lspr_geometry_info(self.handle, C.byref(st)), "lspr_geometry_info")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def solve(self, lambdas, eps_medium, eps_surface, e_field=(0.0, 0.0, 1.0), gmres=None,
+              stream=None, want_fields=False, allow_noconv=False, **gm_kw):
+        """Batched solve; returns a dict of numpy arrays (phi/dphi as torch cuda tensors)."""
+        import torch
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64).reshape(-1)
+        nl = len(lam)
+        em, em_p = _c64_array(np.broadcast_to(np.asarray(eps_medium), (nl,)))
+        es, es_p = _c64_array(np.asarray(eps_surface).reshape(nl, self.n_surf))
+        ef = np.ascontiguousarray(e_field, dtype=np.float64)
+        gm = gmres if gmres is not None else gmres_params(**gm_kw)
+        phi = dphi = None
+        if want_fields:
+            phi = torch.zeros((nl, self.n_panels), dtype=torch.complex128, device="cuda")
+            dphi = torch.zeros_like(phi)
+        ps = np.zeros((nl, 3), np.complex128)
+        pt = np.zeros((nl, 3), np.complex128)
+        cs = np.zeros(nl)
+        ct = np.zeros(nl)
+        it = np.zeros(nl, np.int32)
+        rr = np.zeros(nl)
+        code = _lib.lspr_solve(self.handle, nl, _dptr(lam), em_p, es_p, _dptr(ef), C.byref(gm),
+                               _stream_ptr(stream),
+                               C.c_void_p(phi.data_ptr() if phi is not None else None),
+                               C.c_void_p(dphi.data_ptr() if dphi is not None else None),
+                               ps.ctypes.data_as(C.POINTER(lspr_c64)),
+                               pt.ctypes.data_as(C.POINTER(lspr_c64)), _dptr(cs), _dptr(ct),
+                               it.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(rr))
+        _check(code, "lspr_solve", allow=(LSPR_E_NOCONV,) if allow_noconv else ())
+        return {"p_sensor": ps, "p_total": pt, "cext_sensor": cs, "cext_total": ct,
+                "iters": it, "rel_resid": rr, "phi": phi, "dphi": dphi,
+                "converged": code == LSPR_OK}
+
+    def apply(self, x, eps_medium, eps_surface, stream=None):
+        """y = A x for x a complex128 cuda tensor [n_cols, 2N] (caller's panel order)."""
+        import torch
+        x = x.to(torch.complex128).contiguous()
+        nc = x.shape[0]
+        em, em_p = _c64_array(np.broadcast_to(np.asarray(eps_medium), (nc,)))
+        es, es_p = _c64_array(np.asarray(eps_surface).reshape(nc, self.n_surf))
+        y = torch.empty_like(x)
+        _check(_lib.lspr_apply(self.handle, nc, em_p, es_p, C.c_void_p(x.data_ptr()),
+                               C.c_void_p(y.data_ptr()), _stream_ptr(stream)), "lspr_apply")
+        return y
+
+    def rhs(self, eps_medium, eps_surface, e_field=(0.0, 0.0, 1.0), stream=None):
+        import torch
+        es_arr = np.asarray(eps_surface).reshape(-1, self.n_surf)
+        nc = es_arr.shape[0]
+        em, em_p = _c64_array(np.broadcast_to(np.asarray(eps_medium), (nc,)))
+        es, es_p = _c64_array(es_arr)
+        ef = np.ascontiguousarray(e_field, dtype=np.float64)
+        b = torch.empty((nc, 2 * self.n_panels), dtype=torch.complex128, device="cuda")
+        _check(_lib.lspr_rhs(self.handle, nc, em_p, es_p, _dptr(ef), C.c_void_p(b.data_ptr()),
+                             _stream_ptr(stream)), "lspr_rhs")
+        return b

@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports every function
+declared in include/lspr.h, and its host-only entry points behave."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from lspr_inputs import octasphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lspr.h")
+LIB = os.path.join(ROOT, "paper_1812_10722_amd", "liblspr.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="liblspr.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(lspr_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_wraps_every_declared_symbol():
+    from paper_1812_10722_amd import lspr
+    for n in declared_functions():
+        assert hasattr(lspr._lib, n)
+
+
+@pytest.mark.parametrize("n,deg", [(1, 1), (3, 2), (4, 3), (7, 5), (19, 9), (25, 10)])
+def test_library_triangle_rules_are_exact(n, deg):
+    """The library's own tables (independent of the oracle's) integrate monomials exactly."""
+    from paper_1812_10722_amd.lspr import lspr_triangle_rule
+    bary, w = lspr_triangle_rule(n)
+    assert abs(w.sum() - 1) < 1e-14 and np.allclose(bary.sum(1), 1)
+    x, y = bary[:, 1], bary[:, 2]
+    for d in range(deg + 1):
+        for a in range(d + 1):
+            b = d - a
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            assert abs(0.5 * np.sum(w * x ** a * y ** b) / exact - 1) < 1e-13
+
+
+def test_library_gauss_legendre():
+    from paper_1812_10722_amd.lspr import lspr_gauss_legendre
+    for n in (1, 2, 9, 20):
+        t, w = lspr_gauss_legendre(n)
+        for k in range(2 * n):
+            exact = 0.0 if k % 2 else 2.0 / (k + 1)
+            assert abs(np.sum(w * t ** k) - exact) < 1e-13
+
+
+def test_mesh_validation():
+    from paper_1812_10722_amd import lspr
+    v, t = octasphere(4, 1.0)
+    assert lspr.lspr_mesh_validate([(v, t)]) == lspr.LSPR_OK
+    assert lspr.lspr_mesh_validate([(v, t[:, ::-1].copy())]) == lspr.LSPR_E_MESH  # inverted
+    assert lspr.lspr_mesh_validate([(v, t[1:])]) == lspr.LSPR_E_MESH              # open
+    bad = t.copy()
+    bad[0, 0] = len(v) + 5
+    assert lspr.lspr_mesh_validate([(v, bad)]) == lspr.LSPR_E_MESH                # index
+    assert "surface 0" in lspr._lib.lspr_last_error().decode()
+    deg = v.copy()
+    deg[t[0, 1]] = deg[t[0, 0]]
+    assert lspr.lspr_mesh_validate([(deg, t)]) == lspr.LSPR_E_MESH               # degenerate
+    assert lspr.lspr_mesh_validate([]) == lspr.LSPR_E_INVALID
+
+
+def test_status_strings():
+    from paper_1812_10722_amd import lspr
+    for code in range(7):
+        assert lspr._lib.lspr_status_string(code)
