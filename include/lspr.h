@@ -192,6 +192,20 @@ int lspr_rhs(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,
 int lspr_triangle_rule(int32_t n, double* bary, double* w);
 int lspr_gauss_legendre(int32_t n, double* t, double* w);
 
+/* Kernel profiling (tracing).  When enabled, the library brackets its main launches with HIP
+ * events on the launch stream and records, per launch, the algorithmic work: flops counted from
+ * the interaction lists (direct pairs, expansion pairs) and the columns actually used, bytes of
+ * the arrays the kernel must read and write once.  Names: "far" (expansions plus direct sums),
+ * "p2m", "near" (near-singular corrections), "matvec" (one whole block product), "arnoldi"
+ * (orthogonalisation of one GMRES step).  For "far", `items` counts interactions times
+ * wavelengths: (direct target-node pairs + expansion target-box pairs) per launch times the
+ * complex columns of that launch.  lspr_profile_query waits for the recorded events and returns
+ * totals since the last reset; unknown names give zero launches. */
+int lspr_profile_enable(int32_t on);
+int lspr_profile_reset(void);
+int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
+                       double* bytes, double* items);
+
 const char* lspr_status_string(int code);
 const char* lspr_last_error(void);
 

@@ -49,13 +49,17 @@ def sphere_512():
                     gmres=dict(tol=1e-8, restart=100, max_iter=1000))
 
 
-def sphere_32k_sweep(n_lambda=64, nu=64):
-    """Silver sphere R = 10 nm, 32768 panels, 64 wavelengths 350-420 nm, treecode, FP32 kernels."""
+def sphere_32k_sweep(n_lambda=64, nu=64, p=8, theta=0.5):
+    """Silver sphere R = 10 nm, 32768 panels, 64 wavelengths 350-420 nm, treecode, FP32 kernels.
+
+    The configured expansion (theta = 0.5, P = 6) misses 1e-4 relative C_ext near resonance
+    (measured max 6.2e-4 against FP64 dense); P = 8 at theta = 0.5 is the lowest order that
+    meets it (measured max 7e-6), so it is the default here."""
     surfs, lam, em, es = _sphere_case(nu, 10.0, wavelength_grid(350.0, 420.0, n_lambda))
     return Workload(f"sphere_R10_N{8 * nu * nu}_sweep{n_lambda}_350-420nm_treecode_fp32",
                     surfs, lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                            p=6, theta=0.5, ncrit=0, precision="fp32"),
+                            p=p, theta=theta, ncrit=0, precision="fp32"),
                     gmres=dict(tol=1e-6, restart=60, max_iter=600))
 
 
@@ -76,7 +80,7 @@ def sensor_two_analytes(seed=3, nu_sphere=71, nu_blob=61, gap=1.0, n_lambda=32, 
     return Workload(f"sensor_R8_N{len(sphere[1])}+2x{len(bt)}_gap{gap}_{axis}_sweep{n_lambda}",
                     [sphere, (b1, bt), (b2, bt)], lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                            p=6, theta=0.5, ncrit=0, precision="fp32"),
+                            p=8, theta=0.5, ncrit=0, precision="fp32"),
                     gmres=dict(tol=1e-6, restart=60, max_iter=600), seed=seed)
 
 
@@ -113,7 +117,7 @@ def large_sensor(seed=4, nu_sphere=128, nu_blob=75, n_blobs=8, n_lambda=16):
     n = sum(len(t) for _, t in surfs)
     return Workload(f"large_sensor_R10_N{n}_{n_blobs}blobs_sweep{n_lambda}", surfs, lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                            p=6, theta=0.5, ncrit=0, precision="fp32"),
+                            p=8, theta=0.5, ncrit=0, precision="fp32"),
                     gmres=dict(tol=1e-6, restart=60, max_iter=600), seed=seed)
 
 
@@ -136,7 +140,7 @@ def serving_stream(seed=5, n_requests=2000, rate_per_s=1.0, nu_range=(16, 128),
         es = np.concatenate([eps_silver_drude(lam)[:, None], np.full((nl, nb), 2.5 + 0j)], 1)
         yield t, Workload(f"req{k}", surfs, lam, em, es,
                           op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                                  p=6, theta=0.5, ncrit=0, precision="fp32"),
+                                  p=8, theta=0.5, ncrit=0, precision="fp32"),
                           gmres=dict(tol=1e-6, restart=60, max_iter=600), seed=seed)
 
 

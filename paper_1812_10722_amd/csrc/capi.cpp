@@ -58,7 +58,8 @@ size_t lspr::Geometry::device_bytes() const {
            mom_boxes_d.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
-           vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes();
+           vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
+           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes();
 }
 
 extern "C" {
@@ -206,6 +207,39 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
         std::set<int32_t> uniq(mb.begin(), mb.end());
         g.mom_boxes.assign(uniq.begin(), uniq.end());
         if (!g.mom_boxes.empty()) {
+            std::vector<lspr::Box> bh(g.n_boxes);
+            LSPR_HIP(hipMemcpy(bh.data(), g.boxes.p, bh.size() * sizeof(lspr::Box),
+                               hipMemcpyDeviceToHost));
+            g.mom_panels = 0;
+            for (int32_t b : g.mom_boxes) g.mom_panels += bh[b].end - bh[b].start;
+            // P2M work items: segments of at most 128 panels per expanded box
+            constexpr int SEG = 128;
+            std::vector<lspr::P2MSeg> segs;
+            std::vector<lspr::P2MRed> reds;
+            int slots = 0;
+            for (int32_t b : g.mom_boxes) {
+                const int n = bh[b].end - bh[b].start;
+                const int ns = (n + SEG - 1) / SEG;
+                const int slot0 = ns > 1 ? slots : -1;
+                for (int k = 0; k < ns; ++k)
+                    segs.push_back({b, bh[b].start + k * SEG, std::min(bh[b].end, bh[b].start + (k + 1) * SEG),
+                                    ns > 1 ? slots + k : -1});
+                if (ns > 1) {
+                    reds.push_back({b, slot0, slot0 + ns, 0});
+                    slots += ns;
+                }
+            }
+            g.n_seg = static_cast<int>(segs.size());
+            g.n_slots = slots;
+            g.n_red = static_cast<int>(reds.size());
+            g.p2m_seg.alloc(segs.size());
+            LSPR_HIP(hipMemcpy(g.p2m_seg.p, segs.data(), segs.size() * sizeof(lspr::P2MSeg),
+                               hipMemcpyHostToDevice));
+            if (!reds.empty()) {
+                g.p2m_red.alloc(reds.size());
+                LSPR_HIP(hipMemcpy(g.p2m_red.p, reds.data(), reds.size() * sizeof(lspr::P2MRed),
+                                   hipMemcpyHostToDevice));
+            }
             g.mom_boxes_d.alloc(g.mom_boxes.size());
             LSPR_HIP(hipMemcpy(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size() * 4,
                                hipMemcpyHostToDevice));

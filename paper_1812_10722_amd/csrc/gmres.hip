@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "profile.hpp"
 #include "system.hpp"
 
 namespace lspr {
@@ -423,16 +424,20 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
                 vin_stride = nvec;
             }
             system_apply(g, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_dots, dim3(nblk, ns), dim3(GT),
-                                   (GT / 64) * (j + 1) * sizeof(double2), s, V.p, m1, nvec, j,
-                                   w.p, cols_d.p, part.p, nblk);
-                const int nt = ns * (j + 1);
-                hipLaunchKernelGGL(k_dots_final, dim3((nt + 255) / 256), dim3(256), 0, s, part.p,
-                                   nblk, m1, j, cols_d.p, ns, hpass.p, hcol.p, pass);
-                hipLaunchKernelGGL(k_update, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, j,
-                                   w.p, cols_d.p, hpass.p);
-                LSPR_HIP(hipGetLastError());
+            {
+                // two sweeps reading j+1 basis vectors twice each (dots, update) plus w
+                prof::Scope sc("arnoldi", s, 2.0 * 16.0 * (j + 1) * double(nvec) * ns,
+                               (4.0 * (j + 1) + 8.0) * 16.0 * double(nvec) * ns);
+                for (int pass = 0; pass < 2; ++pass) {
+                    hipLaunchKernelGGL(k_dots, dim3(nblk, ns), dim3(GT),
+                                       (GT / 64) * (j + 1) * sizeof(double2), s, V.p, m1, nvec, j,
+                                       w.p, cols_d.p, part.p, nblk);
+                    const int nt = ns * (j + 1);
+                    hipLaunchKernelGGL(k_dots_final, dim3((nt + 255) / 256), dim3(256), 0, s, part.p,
+                                       nblk, m1, j, cols_d.p, ns, hpass.p, hcol.p, pass);
+                    hipLaunchKernelGGL(k_update, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, j,
+                                       w.p, cols_d.p, hpass.p);
+                    LSPR_HIP(hipGetLastError());
             }
             hipLaunchKernelGGL(k_norm_part, dim3(nblk, ns), dim3(GT), 0, s, w.p, nvec, nvec,
                                cols_d.p, part2.p, nblk);
@@ -442,6 +447,7 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
             hipLaunchKernelGGL(k_scale, dim3(nblk, ns), dim3(GT), 0, s, w.p, nvec,
                                V.p + (j + 1) * nvec, m1 * nvec, nvec, cols_d.p, inv.p);
             LSPR_HIP(hipGetLastError());
+            }
             LSPR_HIP(hipMemcpyAsync(est_h.data(), est.p, B * 8, hipMemcpyDeviceToHost, s));
             LSPR_HIP(hipStreamSynchronize(s));
             std::vector<int32_t> still;

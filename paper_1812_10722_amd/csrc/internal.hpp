@@ -86,6 +86,16 @@ struct Chunk {
     int32_t surf, pad;
 };
 
+// A P2M work item: panels [start, end) of expanded box `box`; slot < 0 writes the box's
+// moments directly, otherwise partial moments go to scratch slot `slot`.
+struct P2MSeg {
+    int32_t box, start, end, slot;
+};
+// Boxes assembled from several segments: moments = sum of scratch slots [slot0, slot1).
+struct P2MRed {
+    int32_t box, slot0, slot1, pad;
+};
+
 // One entry of a chunk's direct-sum list: source panels [start, end) of one surface.
 struct Range {
     int32_t start, end;
@@ -124,6 +134,10 @@ struct Geometry {
     DevBuf<Box> boxes;
     DevBuf<double> far_rule;   // [K][4] barycentric coordinates and weight of the far rule
     std::vector<int32_t> mom_boxes;  // boxes that appear in some expansion list
+    int64_t mom_panels = 0;          // panels summed over those boxes
+    int n_seg = 0, n_slots = 0, n_red = 0;
+    DevBuf<P2MSeg> p2m_seg;
+    DevBuf<P2MRed> p2m_red;
     DevBuf<int32_t> mom_boxes_d;
     int n_chunks = 0;
     DevBuf<Chunk> chunks;
@@ -145,7 +159,7 @@ struct Geometry {
     // geometry part of the right-hand side: u[s][d][i] = sum_{j in s} V_ij (-n_j,d)
     DevBuf<double> rhs_u;      // [S][3][N]
     // workspaces reused by the operator
-    DevBuf<uint8_t> ws_dens, ws_mom, ws_out;
+    DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
 
     size_t device_bytes() const;

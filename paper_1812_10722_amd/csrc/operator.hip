@@ -16,6 +16,7 @@
 
 #include "expansion.hpp"
 #include "operator.hpp"
+#include "profile.hpp"
 
 namespace lspr {
 
@@ -41,10 +42,13 @@ __device__ __forceinline__ void two_sum_add(T& hi, T& lo, T part) {
 }
 
 // ------------------------------------------------------------------------------- P2M
-// Moments of box b about its centre c, for every real column:
+// Moments of an expanded box about its centre c, for every real column:
 //   K columns: M_k = sum_j phi_j sum_g w_g n_j . grad (y_g - c)^k
 //   V columns: M_k = sum_j sigma_j sum_g w_g (y_g - c)^k
-// then folded to the (P+1)^2 terms with kz <= 1.  Block = 256 columns of one box; the
+// then folded to the (P+1)^2 terms with kz <= 1.  Work items are segments of at most
+// P2M_SEG consecutive panels of one box, so that large boxes spread over many workgroups;
+// a box made of one segment writes its moments directly, the others write partial moments
+// that k_p2m_reduce adds in segment order (deterministic).  Block = 256 columns; the
 // per-panel polynomial sums of a tile of panels are staged in LDS and shared by all columns.
 constexpr int P2M_THREADS = 256;
 template <class T, int P> constexpr int p2m_tile() {
@@ -57,17 +61,17 @@ template <class T, int P> constexpr int p2m_tile() {
 
 template <class T, int P>
 __global__ void __launch_bounds__(P2M_THREADS)
-k_p2m(const Box* __restrict__ boxes, const int32_t* __restrict__ box_list,
+k_p2m(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
       const double* __restrict__ cen, const T* __restrict__ src, int K,
-      const T* __restrict__ dens, int pad, T* __restrict__ mom) {
+      const T* __restrict__ dens, int pad, T* __restrict__ mom, T* __restrict__ part) {
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF;
     constexpr int P2M_TILE = p2m_tile<T, P>();
     __shared__ T pw[P2M_TILE][8][3][P + 1];      // powers of (y_g - c) per node (K <= 8)
     __shared__ T poly[P2M_TILE][2][NF];           // [0]: V polynomial, [1]: K polynomial
-    const int bi = box_list[blockIdx.x];
-    const Box B = boxes[bi];
+    const P2MSeg sg = segs[blockIdx.x];
+    const Box B = boxes[sg.box];
     const int col = blockIdx.y * P2M_THREADS + threadIdx.x;
     const int ncols = 2 * pad;
     const bool kcol = col < pad;
@@ -75,8 +79,8 @@ k_p2m(const Box* __restrict__ boxes, const int32_t* __restrict__ box_list,
 #pragma unroll
     for (int t = 0; t < NF; ++t) acc[t] = T(0);
     const int rs = 4 + 4 * K;
-    for (int p0 = B.start; p0 < B.end; p0 += P2M_TILE) {
-        const int np = min(P2M_TILE, B.end - p0);
+    for (int p0 = sg.start; p0 < sg.end; p0 += P2M_TILE) {
+        const int np = min(P2M_TILE, sg.end - p0);
         // powers of node offsets from the box centre
         for (int e = threadIdx.x; e < np * K; e += P2M_THREADS) {
             const int pp = e / K, gq = e % K;
@@ -132,9 +136,25 @@ k_p2m(const Box* __restrict__ boxes, const int32_t* __restrict__ box_list,
         acc[ex.fdx[f]] += T(ex.fcx[f]) * acc[ex.fsrc[f]];
         acc[ex.fdy[f]] += T(ex.fcy[f]) * acc[ex.fsrc[f]];
     }
-    T* out = mom + static_cast<size_t>(bi) * E::NR * ncols;
+    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * E::NR * ncols
+                         : part + static_cast<size_t>(sg.slot) * E::NR * ncols;
 #pragma unroll
     for (int q = 0; q < E::NR; ++q) out[static_cast<size_t>(q) * ncols + col] = acc[ex.rfull[q]];
+}
+
+// mom[box] = sum of its segments' partial moments, in segment order.
+template <class T>
+__global__ void k_p2m_reduce(const P2MRed* __restrict__ red, int n_red, int nr, int ncols,
+                             const T* __restrict__ part, T* __restrict__ mom) {
+    const int64_t per = static_cast<int64_t>(nr) * ncols;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= per * n_red) return;
+    const int r = static_cast<int>(t / per);
+    const int64_t e = t % per;
+    const P2MRed R = red[r];
+    T s = T(0);
+    for (int k = R.slot0; k < R.slot1; ++k) s += part[static_cast<int64_t>(k) * per + e];
+    mom[static_cast<int64_t>(R.box) * per + e] = s;
 }
 
 // ------------------------------------------------------------------------------- far field
@@ -318,12 +338,24 @@ void launch_far_p(Geometry& g, int pad, const T* dens, const T* mom, double* os,
 
 template <class T, int P>
 void launch_p2m_p(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
-    const int nb = static_cast<int>(g.mom_boxes.size());
-    if (nb == 0) return;
-    const dim3 grid(nb, (2 * pad + P2M_THREADS - 1) / P2M_THREADS);
-    hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(P2M_THREADS), 0, s, g.boxes.p, g.mom_boxes_d.p,
-                       g.cen.p, reinterpret_cast<const T*>(g.src.p), g.K, dens, pad, mom);
+    if (g.n_seg == 0) return;
+    const int ncols = 2 * pad;
+    const int nr = Expansion<P>::NR;
+    T* part = nullptr;
+    if (g.n_slots > 0) {
+        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * nr * ncols * sizeof(T));
+        part = reinterpret_cast<T*>(g.ws_part.p);
+    }
+    const dim3 grid(g.n_seg, (ncols + P2M_THREADS - 1) / P2M_THREADS);
+    hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(P2M_THREADS), 0, s, g.boxes.p, g.p2m_seg.p,
+                       g.cen.p, reinterpret_cast<const T*>(g.src.p), g.K, dens, pad, mom, part);
     LSPR_HIP(hipGetLastError());
+    if (g.n_red > 0) {
+        const int64_t tot = static_cast<int64_t>(g.n_red) * nr * ncols;
+        hipLaunchKernelGGL(k_p2m_reduce<T>, dim3((tot + 255) / 256), dim3(256), 0, s,
+                           g.p2m_red.p, g.n_red, nr, ncols, part, mom);
+        LSPR_HIP(hipGetLastError());
+    }
 }
 
 template <class T, int CPT>
@@ -342,11 +374,21 @@ void launch_far_cpt(Geometry& g, int pad, const T* dens, const T* mom, double* o
 template <class T>
 void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* oa,
                  hipStream_t s) {
+    const double nc = c.ncol;                     // used real columns per operator
+    const double esz = sizeof(T);
+    const double dens_bytes = double(g.N) * 2 * c.pad * esz;
+    const double out_bytes = double(g.N) * 2 * c.pad * 8 * (os ? 2 : 1);
+    const int NF = (g.P + 1) * (g.P + 2) * (g.P + 3) / 6;
+    const double mom_bytes = double(g.mom_boxes.size()) * g.n_terms * 2 * c.pad * esz;
     T* mom = nullptr;
     if (!g.mom_boxes.empty()) {
         const size_t need = static_cast<size_t>(g.n_boxes) * g.n_terms * 2 * c.pad * sizeof(T);
         g.ws_mom.reserve(need);
         mom = reinterpret_cast<T*>(g.ws_mom.p);
+        // per panel of an expanded box: node polynomials (V and K) and the contraction with
+        // every used column
+        prof::Scope sc("p2m", s, double(g.mom_panels) * (8.0 * g.K * NF + 2.0 * NF * 2 * nc),
+                       double(g.mom_panels) * 2 * c.pad * esz + mom_bytes);
         switch (g.P) {
             case 2: launch_p2m_p<T, 2>(g, c.pad, dens, mom, s); break;
             case 4: launch_p2m_p<T, 4>(g, c.pad, dens, mom, s); break;
@@ -356,13 +398,25 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
             default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
         }
     }
-    switch (c.cpt) {
-        case 2: launch_far_cpt<T, 2>(g, c.pad, dens, mom, os, oa, s); break;
-        case 4: launch_far_cpt<T, 4>(g, c.pad, dens, mom, os, oa, s); break;
-        case 16: launch_far_cpt<T, 16>(g, c.pad, dens, mom, os, oa, s); break;
-        default: throw Error(LSPR_E_INVALID, "unsupported column blocking");
+    {
+        // direct pairs: per node 15 flops (difference, r^2, rsqrt, two weighted sums), 9 per
+        // pair (centroid difference, plane height, product), then 2 flops per used column of
+        // each operator; expansion pairs: about 10 flops per coefficient of the recurrence and
+        // 2 per coefficient and used column of each operator
+        const double f = double(g.p2p_pairs) * (15.0 * g.K + 9.0 + 4.0 * nc) +
+                         double(g.m2p_pairs) * (10.0 * g.n_terms + 4.0 * nc * g.n_terms);
+        prof::Scope sc("far", s, f, dens_bytes + mom_bytes + out_bytes,
+                       (double(g.p2p_pairs) * g.K + double(g.m2p_pairs)) * (nc / 2));
+        switch (c.cpt) {
+            case 2: launch_far_cpt<T, 2>(g, c.pad, dens, mom, os, oa, s); break;
+            case 4: launch_far_cpt<T, 4>(g, c.pad, dens, mom, os, oa, s); break;
+            case 16: launch_far_cpt<T, 16>(g, c.pad, dens, mom, os, oa, s); break;
+            default: throw Error(LSPR_E_INVALID, "unsupported column blocking");
+        }
     }
     const int64_t tot = static_cast<int64_t>(g.N) * 2 * c.pad;
+    prof::Scope sc("near", s, double(g.n_near + g.N) * 2.0 * 2 * nc,
+                   double(g.n_near) * 20 + dens_bytes + 2 * out_bytes);
     hipLaunchKernelGGL(k_near_corr<T>, dim3((tot + 255) / 256), dim3(256), 0, s,
                        g.near_off64.p, g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p,
                        g.surf.p, g.N, dens, c.pad, os, oa);

@@ -1,0 +1,99 @@
+// Event-based kernel profiling: HIP events recorded on the launch stream around a launch, plus
+// the algorithmic flops and bytes of that launch.  Events are kept until the next reset.
+#include "profile.hpp"
+
+#include <map>
+#include <mutex>
+
+namespace lspr {
+namespace prof {
+
+namespace {
+
+struct Rec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+    double flops = 0, bytes = 0, items = 0;
+    bool done = false;
+};
+
+std::mutex mu;
+bool on = false;
+std::vector<Rec> recs;
+
+void clear_locked() {
+    for (Rec& r : recs) {
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+}
+
+}  // namespace
+
+bool enabled() { return on; }
+
+int start(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu);
+    Rec r;
+    r.name = name;
+    LSPR_HIP(hipEventCreate(&r.a));
+    LSPR_HIP(hipEventCreate(&r.b));
+    LSPR_HIP(hipEventRecord(r.a, s));
+    recs.push_back(r);
+    return static_cast<int>(recs.size()) - 1;
+}
+
+void stop(int token, hipStream_t s, double flops, double bytes, double items) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (token < 0 || token >= static_cast<int>(recs.size())) return;
+    Rec& r = recs[token];
+    (void)hipEventRecord(r.b, s);
+    r.flops = flops;
+    r.bytes = bytes;
+    r.items = items;
+    r.done = true;
+}
+
+}  // namespace prof
+}  // namespace lspr
+
+extern "C" {
+
+int lspr_profile_enable(int32_t enable) {
+    lspr::prof::on = enable != 0;
+    return LSPR_OK;
+}
+
+int lspr_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(lspr::prof::mu);
+    lspr::prof::clear_locked();
+    return LSPR_OK;
+}
+
+int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
+                       double* bytes, double* items) {
+    if (!name || !total_ms || !launches || !flops || !bytes || !items) return LSPR_E_INVALID;
+    std::lock_guard<std::mutex> lk(lspr::prof::mu);
+    double ms = 0, f = 0, by = 0, it = 0;
+    int64_t n = 0;
+    for (auto& r : lspr::prof::recs) {
+        if (!r.done || r.name != name) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return LSPR_E_DEVICE;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return LSPR_E_DEVICE;
+        ms += t;
+        f += r.flops;
+        by += r.bytes;
+        it += r.items;
+        ++n;
+    }
+    *total_ms = ms;
+    *launches = n;
+    *flops = f;
+    *bytes = by;
+    *items = it;
+    return LSPR_OK;
+}
+
+}  // extern "C"

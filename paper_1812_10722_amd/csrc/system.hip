@@ -14,6 +14,7 @@
 #include <cstdio>
 
 #include "operator.hpp"
+#include "profile.hpp"
 #include "system.hpp"
 
 namespace lspr {
@@ -175,6 +176,7 @@ void system_apply(Geometry& g, int nslot, const double2* ratio_d, const double2*
     const Cols c = make_cols(2 * nslot);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
     const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
+    prof::Scope sc("matvec", s, 0.0, 0.0);
     g.ws_dens.reserve(nd * esz);
     g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
     double* oa = reinterpret_cast<double*>(g.ws_out.p);

@@ -251,3 +251,31 @@ class Geometry:
         _check(_lib.lspr_rhs(self.handle, nc, em_p, es_p, _dptr(ef), C.c_void_p(b.data_ptr()),
                              _stream_ptr(stream)), "lspr_rhs")
         return b
+
+
+# ------------------------------------------------------------------ profiling
+_lib.lspr_profile_enable.restype = C.c_int
+_lib.lspr_profile_enable.argtypes = [C.c_int32]
+_lib.lspr_profile_reset.restype = C.c_int
+_lib.lspr_profile_reset.argtypes = []
+_lib.lspr_profile_query.restype = C.c_int
+_lib.lspr_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
+
+
+def lspr_profile_enable(on: bool):
+    _check(_lib.lspr_profile_enable(1 if on else 0), "lspr_profile_enable")
+
+
+def lspr_profile_reset():
+    _check(_lib.lspr_profile_reset(), "lspr_profile_reset")
+
+
+def lspr_profile_query(name: str) -> dict:
+    ms, fl, by, it = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    n = C.c_int64()
+    _check(_lib.lspr_profile_query(name.encode(), C.byref(ms), C.byref(n), C.byref(fl),
+                                   C.byref(by), C.byref(it)), "lspr_profile_query")
+    return {"total_ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value,
+            "items": it.value}
