@@ -53,6 +53,7 @@ enum lspr_status {
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
 enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1 };
+enum lspr_flags { LSPR_NO_MATRIX_CORES = 1 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
  * counter-clockwise seen from outside (outward right-hand normal, as the paper's dipole
@@ -81,7 +82,12 @@ typedef struct {
  *   m2p_min_panels  a box that passes the MAC is expanded only if it holds at least this many
  *             panels, otherwise it is summed directly (cheaper for small boxes); 0 selects the
  *             library default (the number of expansion terms).  Accuracy is unaffected: a
- *             direct sum is exact to the quadrature. */
+ *             direct sum is exact to the quadrature.
+ *   flags     bit 0: never use the matrix-core far-field kernel.  By default FP32 geometries
+ *             precompute the geometry-only factors of every expansion and direct tile (about
+ *             1.7 GB at 32768 panels, P = 8) and run all products on matrix cores; above
+ *             64 GB of tiles the geometry falls back to the vector-ALU kernel, which computes
+ *             the same sums on the fly. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;
@@ -93,6 +99,7 @@ typedef struct {
     int32_t ncrit;
     int32_t precision;
     int32_t m2p_min_panels;
+    int32_t flags;
 } lspr_op_params;
 
 /* GMRES parameters (the paper gives only tolerances, Tables 2 and 5).

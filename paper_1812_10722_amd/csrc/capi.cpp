@@ -59,7 +59,8 @@ size_t lspr::Geometry::device_bytes() const {
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
-           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes();
+           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + tiles.bytes() + tile_off.bytes() +
+           tile_self.bytes() + tileA.bytes();
 }
 
 extern "C" {
@@ -197,6 +198,7 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
         g.precision = op->precision;
         g.n_terms = lspr::expansion_terms(g.P);
         g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
+        g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
         lspr::build_geometry(g, surfaces, n_surf);
         lspr::build_tree(g);
         lspr::build_lists(g);
@@ -245,6 +247,7 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
                                hipMemcpyHostToDevice));
         }
         lspr::build_near_table(g);
+        if (g.precision == LSPR_FP32 && g.allow_mfma) lspr::build_tiles(g);
         lspr::precompute_rhs(g);
         *out = h.release();
         return LSPR_OK;

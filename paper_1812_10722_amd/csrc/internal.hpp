@@ -96,6 +96,16 @@ struct P2MRed {
     int32_t box, slot0, slot1, pad;
 };
 
+// One left factor of the matrix-core far-field product, stored in MFMA operand order.
+// kind 0: expansion (Taylor coefficients; B rows = moments rows b_row0 .. b_row0 + b_rows);
+// kind 1: direct tile (double-layer then single-layer kernel values; B rows = density rows of
+// panels b_row0 .. b_row0 + b_rows).  nstep K-steps of 4 rows; a_off indexes the float store.
+struct TileDesc {
+    int32_t kind, nstep;
+    int64_t a_off;
+    int32_t b_row0, b_rows;
+};
+
 // One entry of a chunk's direct-sum list: source panels [start, end) of one surface.
 struct Range {
     int32_t start, end;
@@ -136,6 +146,11 @@ struct Geometry {
     std::vector<int32_t> mom_boxes;  // boxes that appear in some expansion list
     int64_t mom_panels = 0;          // panels summed over those boxes
     int n_seg = 0, n_slots = 0, n_red = 0;
+    // matrix-core tiles (FP32 geometries)
+    int64_t n_tiles = 0;
+    DevBuf<TileDesc> tiles;
+    DevBuf<int32_t> tile_off, tile_self;
+    DevBuf<float> tileA;
     DevBuf<P2MSeg> p2m_seg;
     DevBuf<P2MRed> p2m_red;
     DevBuf<int32_t> mom_boxes_d;
@@ -161,6 +176,8 @@ struct Geometry {
     // workspaces reused by the operator
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
+    bool allow_mfma = true;  // FP32 products use matrix cores (precomputed tiles)
+    double tile_budget_bytes = 64e9;  // largest tile store kept per geometry
 
     size_t device_bytes() const;
 };
@@ -172,6 +189,7 @@ struct Cols {
     int ncol = 0;  // real columns per operator (2 * wavelengths)
     int cpt = 0;   // columns per thread per operator
     int pad = 0;   // ncol rounded up to cpt
+    bool mfma = false;  // FP32 matrix-core far-field kernel
 };
 
 // ---------------------------------------------------------------- quadrature (quadrature.cpp)
@@ -195,5 +213,7 @@ void build_near_table(Geometry& g);
 void apply_raw(Geometry& g, const Cols& c, const void* dens, double* out_self, double* out_all,
                hipStream_t s);
 void precompute_rhs(Geometry& g);
+// Geometry-only left factors of the matrix-core far-field product (FP32 geometries).
+void build_tiles(Geometry& g);
 
 }  // namespace lspr

@@ -12,6 +12,7 @@
 //   k_near  fine-rule minus far-rule corrections of near-singular pairs and the singular
 //           self-term, in FP64.
 // Sums are raw: no 1/(4 pi) factor.
+#include <algorithm>
 #include <cmath>
 
 #include "expansion.hpp"
@@ -298,6 +299,267 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
     }
 }
 
+// ------------------------------------------------------------------------------- far field, MFMA
+// FP32 far-field sums on matrix cores.  For a chunk of 64 targets every interaction is a small
+// dense product: an expansion is (64 x terms) . (terms x columns) of Taylor coefficients and
+// box moments, a direct tile is (64 x 32 panels) . (32 panels x columns) of far-rule kernel
+// values and densities.  The left factors depend on geometry only; build_tiles stores them once
+// per geometry, in the operand order of v_mfma_f32_16x16x4f32 (lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and holds D[4 (l / 16) + i][l % 16]): for K-step s and lane l, the four
+// target tiles' values are one float4.  The product then streams those tiles from HBM and
+// spends its time in matrix-core instructions.  Each tile's product is accumulated in FP32 by
+// the matrix cores and then added to an FP64 running sum per output, so rounding does not grow
+// with the number of tiles.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Workgroup = one chunk; waves [0, nwc) each own 16 K columns and the same 16 V columns
+// (4 target tiles x 2 column tiles of 16 x 16); extra waves (up to 4 in all) only help to
+// stage the left factors.  The left factor of tile e + 1 is fetched into registers while tile
+// e is multiplied out of LDS, then stored to the other LDS buffer (double buffering).
+// Consecutive chunks are spatially close and share moments and densities, so workgroups are
+// mapped to chunks XCD by XCD: the hardware deals workgroups round-robin over the 8 XCDs, and
+// workgroup b handles chunk (b % 8) * ceil(n / 8) + b / 8, which gives every XCD's L2 one
+// contiguous run of chunks.
+// One tile: NST K-steps of 4 rows; all B operands of the tile are requested before the first
+// matrix-core instruction so that their latency overlaps the products.
+template <int NST>
+__device__ __forceinline__ void tile_product(const float4* __restrict__ ak4,
+                                             const float4* __restrict__ av4,
+                                             const float* __restrict__ B, int rows, int ncols,
+                                             int colk, int colv, int lane, int grp,
+                                             v4f (&acc)[4][2]) {
+    float bk[NST], bv[NST];
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int row = 4 * st + grp;
+        const bool ok = row < rows;
+        const float* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
+        bk[st] = ok ? br[colk] : 0.f;
+        bv[st] = ok ? br[colv] : 0.f;
+    }
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const float4 ak = ak4[st * 64 + lane];
+        const float4 av = av4[st * 64 + lane];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.x, bk[st], acc[0][0], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.y, bk[st], acc[1][0], 0, 0, 0);
+        acc[2][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.z, bk[st], acc[2][0], 0, 0, 0);
+        acc[3][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.w, bk[st], acc[3][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[st], acc[0][1], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[st], acc[1][1], 0, 0, 0);
+        acc[2][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[st], acc[2][1], 0, 0, 0);
+        acc[3][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[st], acc[3][1], 0, 0, 0);
+    }
+}
+
+template <int PF, int NSM>
+__global__ void __launch_bounds__(512)
+k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __restrict__ tile_off,
+            const int32_t* __restrict__ tile_self, const TileDesc* __restrict__ tiles,
+            const float* __restrict__ tileA, const float* __restrict__ dens,
+            const float* __restrict__ mom, int pad, int nwc, int abuf_floats,
+            double* __restrict__ out_self, double* __restrict__ out_all) {
+    extern __shared__ float4 abuf4[];  // [2][abuf_floats / 4]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthr = blockDim.x;
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int ncols = 2 * pad;
+    const int per_xcd = (n_chunks + 7) / 8;
+    const int chunk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (chunk >= n_chunks) return;
+    const Chunk C = chunks[chunk];
+    const int ntg = C.end - C.start;
+    const bool mma = wave < nwc;
+    const int colk = 16 * wave + c16;        // K column of this lane
+    const int colv = pad + 16 * wave + c16;  // V column of this lane
+    v4f acc[4][2];
+    double run[4][2][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) run[a][b][q] = 0.0;
+        }
+    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
+    const int t_mid = t_beg + tile_self[chunk];
+    const int buf4 = abuf_floats / 4;
+    // stage the first left factor
+    if (t_beg < t_end) {
+        const TileDesc T = tiles[t_beg];
+        const int n4 = (T.kind == 0 ? 64 : 128) * T.nstep;
+        const float4* src4 = reinterpret_cast<const float4*>(tileA + T.a_off);
+        for (int k = tid; k < n4; k += nthr) abuf4[k] = src4[k];
+    }
+    __syncthreads();
+    for (int e = t_beg; e < t_end; ++e) {
+        const int cur = (e - t_beg) & 1;
+        // fetch the next left factor into registers
+        float4 pf[PF];
+        int n4n = 0;
+        const float4* src4n = reinterpret_cast<const float4*>(tileA);
+        if (e + 1 < t_end) {
+            const TileDesc Tn = tiles[e + 1];
+            n4n = (Tn.kind == 0 ? 64 : 128) * Tn.nstep;
+            src4n = reinterpret_cast<const float4*>(tileA + Tn.a_off);
+        }
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int k = tid + r * nthr;
+            pf[r] = k < n4n ? src4n[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const TileDesc T = tiles[e];
+        if (mma) {
+            const float4* ak4 = abuf4 + cur * buf4;
+            if (T.kind == 0)
+                tile_product<NSM>(ak4, ak4, mom + static_cast<size_t>(T.b_row0) * ncols, T.b_rows,
+                                  ncols, colk, colv, lane, grp, acc);
+            else
+                tile_product<8>(ak4, ak4 + 64 * 8, dens + static_cast<size_t>(T.b_row0) * ncols,
+                                T.b_rows, ncols, colk, colv, lane, grp, acc);
+            // the tile's FP32 partial joins an FP64 running sum
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) run[a][b][q] += static_cast<double>(acc[a][b][q]);
+                    acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        {
+            float4* dst = abuf4 + (cur ^ 1) * buf4;
+#pragma unroll
+            for (int r = 0; r < PF; ++r) {
+                const int k = tid + r * nthr;
+                if (k < n4n) dst[k] = pf[r];
+            }
+        }
+        // own-surface sums are complete after the last own-surface tile
+        if (e + 1 == t_mid && out_self != nullptr && mma) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = 16 * mt + 4 * grp + q;
+                    if (t < ntg) {
+                        double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
+                        rowp[colk] = run[mt][0][q];
+                        rowp[colv] = run[mt][1][q];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    if (!mma) return;
+    if (t_mid == t_beg && out_self != nullptr) {  // no own-surface tiles
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + 4 * grp + q;
+                if (t < ntg) {
+                    double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
+                    rowp[colk] = 0.0;
+                    rowp[colv] = 0.0;
+                }
+            }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = 16 * mt + 4 * grp + q;
+            if (t < ntg) {
+                double* rowp = out_all + static_cast<size_t>(C.start + t) * ncols;
+                rowp[colk] = run[mt][0][q];
+                rowp[colv] = run[mt][1][q];
+            }
+        }
+}
+
+// ---- geometry-only tiles for k_far_tiles (built once per geometry)
+// Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
+template <int P>
+__global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
+                                  const TileDesc* __restrict__ tiles,
+                                  const int32_t* __restrict__ m2p_tile,
+                                  const int32_t* __restrict__ m2p_chunk,
+                                  const int32_t* __restrict__ m2p_box, int n,
+                                  const double* __restrict__ cen, float* __restrict__ tileA) {
+    using E = Expansion<P>;
+    constexpr int NR = E::NR;
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    const int t = threadIdx.x;  // target within the chunk
+    const Chunk C = chunks[m2p_chunk[e]];
+    const Box B = boxes[m2p_box[e]];
+    const TileDesc T = tiles[m2p_tile[e]];
+    float* A = tileA + T.a_off;
+    const int i = C.start + t;
+    float F[NR];
+    if (i < C.end) {
+        taylor_coefficients<float, P>(static_cast<float>(B.cx - cen[3 * i]),
+                                      static_cast<float>(B.cy - cen[3 * i + 1]),
+                                      static_cast<float>(B.cz - cen[3 * i + 2]), F);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) F[q] = 0.f;
+    }
+    const int mt = t >> 4, r16 = t & 15;
+    constexpr int NRP = (NR + 3) / 4 * 4;  // equals 4 * T.nstep
+#pragma unroll
+    for (int q = 0; q < NRP; ++q) {
+        const int st = q >> 2, g = q & 3;
+        A[(static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt] = q < NR ? F[q] : 0.f;
+    }
+}
+
+// Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
+// up to 32 consecutive source panels (zero for the target's own panel and past the range).
+__global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
+                                  const int32_t* __restrict__ p2p_tile,
+                                  const int32_t* __restrict__ p2p_chunk, int n,
+                                  const double* __restrict__ cen, const float* __restrict__ src,
+                                  int K, float* __restrict__ tileA) {
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    const TileDesc T = tiles[p2p_tile[e]];
+    const Chunk C = chunks[p2p_chunk[e]];
+    float* AK = tileA + T.a_off;
+    float* AV = AK + static_cast<size_t>(T.nstep) * 256;
+    const int rs = 4 + 4 * K;
+    for (int pr = threadIdx.x; pr < 64 * 4 * T.nstep; pr += blockDim.x) {
+        const int t = pr & 63, p = pr >> 6;  // target, panel within the tile
+        const int i = C.start + t, j = T.b_row0 + p;
+        float kv = 0.f, kk = 0.f;
+        if (i < C.end && p < T.b_rows && j != i) {
+            const float* r = src + static_cast<size_t>(j) * rs;
+            const float dx = static_cast<float>(cen[3 * i] - cen[3 * j]);
+            const float dy = static_cast<float>(cen[3 * i + 1] - cen[3 * j + 1]);
+            const float dz = static_cast<float>(cen[3 * i + 2] - cen[3 * j + 2]);
+            const float sh = r[0] * dx + r[1] * dy + r[2] * dz;
+            float sv = 0.f, sk = 0.f;
+            for (int gq = 0; gq < K; ++gq) {
+                const float ex_ = dx - r[4 + 4 * gq];
+                const float ey_ = dy - r[5 + 4 * gq];
+                const float ez_ = dz - r[6 + 4 * gq];
+                const float w = r[7 + 4 * gq];
+                const float ri = rsqrtf(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                sv += w * ri;
+                sk += w * ri * ri * ri;
+            }
+            kv = sv;
+            kk = sh * sk;
+        }
+        const int st = p >> 2, g = p & 3, mt = t >> 4, r16 = t & 15;
+        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
+        AK[idx] = kk;
+        AV[idx] = kv;
+    }
+}
+
 // ------------------------------------------------------------------------------- near field
 // out[i][c] += sum over near-singular pairs (fine - far) * density, plus the singular V_ii,
 // split into own-surface and all-surface sums.  Thread = (target, column), FP64.
@@ -358,6 +620,41 @@ void launch_p2m_p(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
     }
 }
 
+template <int PF, int NSM>
+void launch_far_tiles_pf(Geometry& g, int pad, int threads, int nwc, int abuf, const float* dens,
+                         const float* mom, double* os, double* oa, hipStream_t s) {
+    const int nblk = (g.n_chunks + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_far_tiles<PF, NSM>), dim3(nblk), dim3(threads),
+                       2 * abuf * sizeof(float), s, g.chunks.p, g.n_chunks, g.tile_off.p,
+                       g.tile_self.p, g.tiles.p, g.tileA.p, dens, mom, pad, nwc, abuf, os, oa);
+    LSPR_HIP(hipGetLastError());
+}
+
+void launch_far_tiles(Geometry& g, int pad, const float* dens, const float* mom, double* os,
+                      double* oa, hipStream_t s) {
+    const int nwc = pad / 16;                 // waves that own columns
+    const int threads = 64 * std::max(4, nwc);
+    const int nsm = (g.n_terms + 3) / 4;
+    const int abuf = std::max(nsm * 256, 2 * 8 * 256);  // floats of the largest left factor
+    const int pf = (abuf / 4 + threads - 1) / threads;   // float4 per thread to stage it
+    LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the matrix-core kernel");
+#define LSPR_FAR_TILES(NSM_)                                                                   \
+    case NSM_:                                                                                 \
+        if (pf <= 2) launch_far_tiles_pf<2, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+        else if (pf <= 4) launch_far_tiles_pf<4, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+        else launch_far_tiles_pf<8, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s);   \
+        break;
+    switch (nsm) {  // (P + 1)^2 / 4 rounded up for P = 2, 4, 6, 8, 10
+        LSPR_FAR_TILES(3)
+        LSPR_FAR_TILES(7)
+        LSPR_FAR_TILES(13)
+        LSPR_FAR_TILES(21)
+        LSPR_FAR_TILES(31)
+        default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
+    }
+#undef LSPR_FAR_TILES
+}
+
 template <class T, int CPT>
 void launch_far_cpt(Geometry& g, int pad, const T* dens, const T* mom, double* os, double* oa,
                     hipStream_t s) {
@@ -407,11 +704,21 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
                          double(g.m2p_pairs) * (10.0 * g.n_terms + 4.0 * nc * g.n_terms);
         prof::Scope sc("far", s, f, dens_bytes + mom_bytes + out_bytes,
                        (double(g.p2p_pairs) * g.K + double(g.m2p_pairs)) * (nc / 2));
-        switch (c.cpt) {
-            case 2: launch_far_cpt<T, 2>(g, c.pad, dens, mom, os, oa, s); break;
-            case 4: launch_far_cpt<T, 4>(g, c.pad, dens, mom, os, oa, s); break;
-            case 16: launch_far_cpt<T, 16>(g, c.pad, dens, mom, os, oa, s); break;
-            default: throw Error(LSPR_E_INVALID, "unsupported column blocking");
+        if (c.mfma) {
+            if constexpr (sizeof(T) == 4) {
+                LSPR_REQUIRE(g.n_tiles > 0 || (g.n_m2p == 0 && g.n_p2p == 0), LSPR_E_INVALID,
+                             "matrix-core tiles were not built");
+                launch_far_tiles(g, c.pad, dens, mom, os, oa, s);
+            } else {
+                throw Error(LSPR_E_INVALID, "matrix-core path is FP32 only");
+            }
+        } else {
+            switch (c.cpt) {
+                case 2: launch_far_cpt<T, 2>(g, c.pad, dens, mom, os, oa, s); break;
+                case 4: launch_far_cpt<T, 4>(g, c.pad, dens, mom, os, oa, s); break;
+                case 16: launch_far_cpt<T, 16>(g, c.pad, dens, mom, os, oa, s); break;
+                default: throw Error(LSPR_E_INVALID, "unsupported column blocking");
+            }
         }
     }
     const int64_t tot = static_cast<int64_t>(g.N) * 2 * c.pad;
@@ -423,11 +730,112 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
     LSPR_HIP(hipGetLastError());
 }
 
+template <int P>
+void launch_build_m2p(Geometry& g, const TileDesc* tiles, const int32_t* mt, const int32_t* mc,
+                      int n, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_m2p_tiles<P>), dim3(n), dim3(64), 0, s, g.chunks.p, g.boxes.p,
+                       tiles, mt, mc, g.m2p_box.p, n, g.cen.p, g.tileA.p);
+    LSPR_HIP(hipGetLastError());
+}
+
 }  // namespace
 
-Cols make_cols(int ncol) {
+void build_tiles(Geometry& g) {
+    hipStream_t s = g.stream;
+    const int nc = g.n_chunks;
+    std::vector<int32_t> mo(nc + 1), po(nc + 1), ms(nc), ps(nc);
+    LSPR_HIP(hipMemcpy(mo.data(), g.m2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
+    LSPR_HIP(hipMemcpy(po.data(), g.p2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
+    LSPR_HIP(hipMemcpy(ms.data(), g.m2p_self.p, nc * 4, hipMemcpyDeviceToHost));
+    LSPR_HIP(hipMemcpy(ps.data(), g.p2p_self.p, nc * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> mbox(std::max<int64_t>(g.n_m2p, 1));
+    std::vector<Range> rng(std::max<int64_t>(g.n_p2p, 1));
+    if (g.n_m2p) LSPR_HIP(hipMemcpy(mbox.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost));
+    if (g.n_p2p)
+        LSPR_HIP(hipMemcpy(rng.data(), g.p2p_rng.p, g.n_p2p * sizeof(Range), hipMemcpyDeviceToHost));
+    const int nsm = (g.n_terms + 3) / 4;  // K-steps of an expansion tile
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> toff(nc + 1, 0), tself(nc, 0);
+    std::vector<int32_t> m2p_tile(std::max<int64_t>(g.n_m2p, 1)), m2p_chunk(std::max<int64_t>(g.n_m2p, 1));
+    std::vector<int32_t> p2p_tile, p2p_chunk;
+    int64_t aoff = 0;
+    for (int c = 0; c < nc; ++c) {
+        toff[c] = static_cast<int32_t>(tiles.size());
+        for (int phase = 0; phase < 2; ++phase) {
+            const int ma = phase == 0 ? mo[c] : mo[c] + ms[c], mb = phase == 0 ? mo[c] + ms[c] : mo[c + 1];
+            const int pa = phase == 0 ? po[c] : po[c] + ps[c], pb = phase == 0 ? po[c] + ps[c] : po[c + 1];
+            for (int e = ma; e < mb; ++e) {
+                m2p_tile[e] = static_cast<int32_t>(tiles.size());
+                m2p_chunk[e] = c;
+                tiles.push_back(TileDesc{0, nsm, aoff, mbox[e] * g.n_terms, g.n_terms});
+                aoff += static_cast<int64_t>(nsm) * 256;
+            }
+            for (int e = pa; e < pb; ++e)
+                for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 32) {
+                    p2p_tile.push_back(static_cast<int32_t>(tiles.size()));
+                    p2p_chunk.push_back(c);
+                    tiles.push_back(TileDesc{1, 8, aoff, p0, std::min(32, rng[e].end - p0)});
+                    aoff += 2 * 8 * 256;
+                }
+            if (phase == 0) tself[c] = static_cast<int32_t>(tiles.size()) - toff[c];
+        }
+    }
+    toff[nc] = static_cast<int32_t>(tiles.size());
+    if (static_cast<double>(aoff) * sizeof(float) > g.tile_budget_bytes) {
+        // too large to keep (e.g. a dense product on a big mesh): keep the on-the-fly kernel
+        g.allow_mfma = false;
+        g.n_tiles = 0;
+        return;
+    }
+    g.n_tiles = static_cast<int64_t>(tiles.size());
+    g.tileA.alloc(std::max<int64_t>(aoff, 1));
+    g.tiles.alloc(std::max<int64_t>(g.n_tiles, 1));
+    g.tile_off.alloc(nc + 1);
+    g.tile_self.alloc(nc);
+    LSPR_HIP(hipMemcpy(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+    LSPR_HIP(hipMemcpy(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
+    LSPR_HIP(hipMemcpy(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice));
+    if (g.n_m2p > 0) {
+        DevBuf<int32_t> mt(g.n_m2p), mc(g.n_m2p);
+        LSPR_HIP(hipMemcpy(mt.p, m2p_tile.data(), g.n_m2p * 4, hipMemcpyHostToDevice));
+        LSPR_HIP(hipMemcpy(mc.p, m2p_chunk.data(), g.n_m2p * 4, hipMemcpyHostToDevice));
+        const int n = static_cast<int>(g.n_m2p);
+        switch (g.P) {
+            case 2: launch_build_m2p<2>(g, g.tiles.p, mt.p, mc.p, n, s); break;
+            case 4: launch_build_m2p<4>(g, g.tiles.p, mt.p, mc.p, n, s); break;
+            case 6: launch_build_m2p<6>(g, g.tiles.p, mt.p, mc.p, n, s); break;
+            case 8: launch_build_m2p<8>(g, g.tiles.p, mt.p, mc.p, n, s); break;
+            case 10: launch_build_m2p<10>(g, g.tiles.p, mt.p, mc.p, n, s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        }
+        LSPR_HIP(hipStreamSynchronize(s));
+    }
+    if (!p2p_tile.empty()) {
+        const int n = static_cast<int>(p2p_tile.size());
+        DevBuf<int32_t> pt(n), pc(n);
+        LSPR_HIP(hipMemcpy(pt.p, p2p_tile.data(), n * 4, hipMemcpyHostToDevice));
+        LSPR_HIP(hipMemcpy(pc.p, p2p_chunk.data(), n * 4, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_build_p2p_tiles, dim3(n), dim3(256), 0, s, g.chunks.p, g.tiles.p,
+                           pt.p, pc.p, n, g.cen.p, reinterpret_cast<const float*>(g.src.p), g.K,
+                           g.tileA.p);
+        LSPR_HIP(hipGetLastError());
+        LSPR_HIP(hipStreamSynchronize(s));
+    }
+}
+
+Cols make_cols(int ncol, int precision, bool allow_mfma) {
     Cols c;
     c.ncol = ncol;
+    if (precision == LSPR_FP32 && allow_mfma) {
+        // matrix cores from precomputed tiles: 16 K columns (and 16 V columns) per wavefront;
+        // the tile stream dominates, so even a single wavelength is cheapest this way
+        c.mfma = true;
+        c.cpt = 16;
+        c.pad = (ncol + 15) / 16 * 16;
+        LSPR_REQUIRE(c.pad / 16 * 64 <= 512, LSPR_E_INVALID,
+                     "too many columns in one product (at most 64 wavelengths)");
+        return c;
+    }
     c.cpt = ncol <= 2 ? 2 : (ncol <= 4 ? 4 : 16);
     c.pad = (ncol + c.cpt - 1) / c.cpt * c.cpt;
     LSPR_REQUIRE(c.pad / c.cpt * NT <= 1024, LSPR_E_INVALID,

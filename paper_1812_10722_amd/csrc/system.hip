@@ -129,7 +129,7 @@ __global__ void k_rhs_extract(const double* __restrict__ out, int N, int S, int 
 
 void precompute_rhs(Geometry& g) {
     hipStream_t s = g.stream;
-    const Cols c = make_cols(3 * g.S);
+    const Cols c = make_cols(3 * g.S, g.precision, g.allow_mfma);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
     const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
     DevBuf<uint8_t> dens(nd * esz);
@@ -173,7 +173,7 @@ void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hi
 void system_apply(Geometry& g, int nslot, const double2* ratio_d, const double2* x,
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
                   hipStream_t s) {
-    const Cols c = make_cols(2 * nslot);
+    const Cols c = make_cols(2 * nslot, g.precision, g.allow_mfma);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
     const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
     prof::Scope sc("matvec", s, 0.0, 0.0);

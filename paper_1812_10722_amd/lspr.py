@@ -33,7 +33,7 @@ class lspr_op_params(C.Structure):
     _fields_ = [("k_far", C.c_int32), ("k_fine", C.c_int32), ("n_k", C.c_int32),
                 ("threshold", C.c_double), ("method", C.c_int32), ("p", C.c_int32),
                 ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
-                ("m2p_min_panels", C.c_int32)]
+                ("m2p_min_panels", C.c_int32), ("flags", C.c_int32)]
 
 
 class lspr_gmres_params(C.Structure):
@@ -135,11 +135,15 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+LSPR_NO_MATRIX_CORES = 1
+
+
 def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, theta=0.5,
-              ncrit=0, precision="fp32", m2p_min_panels=0):
+              ncrit=0, precision="fp32", m2p_min_panels=0, matrix_cores=True):
     return lspr_op_params(k_far, k_fine, n_k, threshold,
                           LSPR_TREECODE if method == "treecode" else LSPR_DENSE, p, theta, ncrit,
-                          LSPR_FP32 if precision == "fp32" else LSPR_FP64, m2p_min_panels)
+                          LSPR_FP32 if precision == "fp32" else LSPR_FP64, m2p_min_panels,
+                          0 if matrix_cores else LSPR_NO_MATRIX_CORES)
 
 
 def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1):

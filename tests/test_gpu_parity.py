@@ -99,6 +99,31 @@ def test_treecode_error_falls_with_order(lib, precision):
     assert errs[2] < 2e-4 and errs[-1] < max(1e-5, floor), errs  # P = 6 and P = 10
 
 
+@pytest.mark.parametrize("method,ncol", [("treecode", 20), ("dense", 9), ("treecode", 64)])
+def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol):
+    """FP32 products with >= 8 wavelengths run on matrix cores from precomputed tiles; they must
+    equal the vector-ALU kernel (same sums, different order) and the oracle's dense product
+    (treecode: to its truncation error at P = 8)."""
+    surfs = sensor_and_blob(10, 7)
+    v, t, sid, V, K, g = _dense_system(surfs, None, None)
+    rng = np.random.default_rng(11)
+    eps_m = np.full(ncol, 1.7733) + 0.01j * rng.standard_normal(ncol)
+    eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(ncol), 2.5 + 0.1j * rng.random(ncol)], 1)
+    x = _rand_x(rng, ncol, len(t))
+    xt = torch.as_tensor(x).cuda()
+    kw = dict(method=method, precision="fp32", p=8, theta=0.5)
+    mc = lib.Geometry(surfs, **kw)
+    vc = lib.Geometry(surfs, matrix_cores=False, **kw)
+    y_mc = mc.apply(xt, eps_m, eps_s).cpu().numpy()
+    y_vc = vc.apply(xt, eps_m, eps_s).cpu().numpy()
+    for c in (0, ncol // 2, ncol - 1):
+        A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m[c], eps_s[c], [0, 0, 1.0])
+        ref = A @ x[c]
+        scale = np.abs(ref).max()
+        assert np.abs(y_mc[c] - y_vc[c]).max() / scale < 3e-6
+        assert np.abs(y_mc[c] - ref).max() / scale < (3e-6 if method == "dense" else 1e-4)
+
+
 # ----------------------------------------------------------------------------- full solves
 def test_sphere_512_dense_fp64_matches_oracle(lib):
     """The 512-panel silver sphere (lambda = 380 nm) solved by the GPU dense FP64 path equals the
