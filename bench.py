@@ -91,7 +91,7 @@ def cpu_baseline(w, n_rows=768, seed=0):
 
 def traffic_entry(kernel_file, name):
     """HBM bytes per launch from rocprofv3 counter runs, valid only for the same kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")  # written from rocprofv3 --pmc runs
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference solve and the one-at-a-time FP64 comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device-to-device copy of 256 MiB (a kernel of known "
+                         "traffic, used to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the build targets a "
@@ -136,6 +139,13 @@ def main():
         g.close()
         return out, info
 
+    if args.copy_calibration:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)  # elementwise kernel: reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del a, b
     assert lspr.lspr_mesh_validate(w.surfaces) == lspr.LSPR_OK
     log(f"[bench] workload {w.name}: N={w.n_panels}, {len(lam)} wavelengths")
     for k in range(args.warmup):
@@ -156,7 +166,8 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     lspr.lspr_profile_enable(False)
-    prof = {n: lspr.lspr_profile_query(n) for n in ("far", "p2m", "near", "matvec", "arnoldi")}
+    prof = {n: lspr.lspr_profile_query(n)
+            for n in ("far", "p2m", "near", "matvec", "arnoldi", "setup")}
     n_matvec = prof["matvec"]["launches"]
 
     # accuracy against the FP64 reference (dense direct FP64 on the GPU, validated against the

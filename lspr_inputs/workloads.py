@@ -49,18 +49,20 @@ def sphere_512():
                     gmres=dict(tol=1e-8, restart=100, max_iter=1000))
 
 
-def sphere_32k_sweep(n_lambda=64, nu=64, p=8, theta=0.5):
+def sphere_32k_sweep(n_lambda=64, nu=64, p=8, theta=0.5, tol=1e-5):
     """Silver sphere R = 10 nm, 32768 panels, 64 wavelengths 350-420 nm, treecode, FP32 kernels.
 
     The configured expansion (theta = 0.5, P = 6) misses 1e-4 relative C_ext near resonance
     (measured max 6.2e-4 against FP64 dense); P = 8 at theta = 0.5 is the lowest order that
-    meets it (measured max 7e-6), so it is the default here."""
+    meets it (measured max 7e-6), so it is the default here.  GMRES stops at a relative
+    residual of 1e-5, which keeps every C_ext within 1e-5 of the FP64 value (measured max
+    9.5e-6), a tenfold margin under the 1e-4 target."""
     surfs, lam, em, es = _sphere_case(nu, 10.0, wavelength_grid(350.0, 420.0, n_lambda))
     return Workload(f"sphere_R10_N{8 * nu * nu}_sweep{n_lambda}_350-420nm_treecode_fp32",
                     surfs, lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
                             p=p, theta=theta, ncrit=0, precision="fp32"),
-                    gmres=dict(tol=1e-6, restart=60, max_iter=600))
+                    gmres=dict(tol=tol, restart=60, max_iter=600))
 
 
 def sensor_two_analytes(seed=3, nu_sphere=71, nu_blob=61, gap=1.0, n_lambda=32, axis="z"):

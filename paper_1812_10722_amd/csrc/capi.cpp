@@ -8,6 +8,7 @@
 #include <utility>
 
 #include "operator.hpp"
+#include "profile.hpp"
 #include "system.hpp"
 
 struct lspr_geometry {
@@ -199,6 +200,7 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
         g.n_terms = lspr::expansion_terms(g.P);
         g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
         g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
+        lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
         lspr::build_geometry(g, surfaces, n_surf);
         lspr::build_tree(g);
         lspr::build_lists(g);
