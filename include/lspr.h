@@ -213,6 +213,82 @@ int lspr_profile_reset(void);
 int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
                        double* bytes, double* items);
 
+/* ------------------------------------------------------------------ request server
+ * Continuous batching of independent solve requests (mixed meshes, wavelength sets and
+ * analyte placements) on one GPU.  Each request is one lspr_geometry_create + lspr_solve with
+ * its own stream; up to max_slots requests are on the device at once, their kernels overlap,
+ * and a queued request is admitted, in arrival order, as soon as a slot is free and its
+ * footprint estimate (lspr_request_footprint) fits into the device-memory budget beside the
+ * requests already admitted.  All device memory of a request comes from a memory pool owned by
+ * the server and is released stream-ordered, so no request synchronises the whole device.
+ * Trees, interaction lists, tiles and Krylov state stay on the device for the life of the
+ * request.  A request's results do not depend on what else is running (every kernel sums in
+ * a fixed order). */
+typedef struct lspr_server lspr_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device bytes admitted requests may hold; 0 = 85 % of the free
+                                 device memory when the server is created */
+    int32_t max_slots;        /* requests on the device at once, 1..16 */
+    int32_t pad;
+} lspr_server_params;
+
+typedef struct {
+    int32_t status;      /* LSPR_OK, LSPR_E_NOCONV (outputs from the last iterate) or the error
+                            that ended the request */
+    int32_t n_lambda;
+    int64_t n_panels;
+    double t_submit;     /* seconds since the server was created */
+    double t_admit;      /* admission: slot and memory granted */
+    double t_done;       /* results ready; latency = t_done - t_submit */
+    int64_t est_bytes;   /* admission estimate */
+    int64_t peak_bytes;  /* measured peak of the request's device allocations */
+    char error[256];     /* error text when status != LSPR_OK (truncated), else empty */
+} lspr_request_info;
+
+typedef struct {
+    int64_t submitted, completed, queued, active;
+    int64_t max_active;           /* most requests on the device at once so far */
+    int64_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+    int64_t estimate_violations;  /* requests whose measured peak exceeded their estimate */
+} lspr_server_stats;
+
+/* Creates a server on the current device (worker threads, one non-blocking stream per slot at
+ * the default priority, and a device memory pool). */
+int lspr_server_create(const lspr_server_params* params, lspr_server** out);
+
+/* Queues one request.  All pointers are HOST pointers and are copied before return, so the
+ * caller may free them at once: surfaces (as lspr_geometry_create), op, lambda_nm [n_lambda],
+ * eps_medium [n_lambda], eps_surface [n_lambda][n_surf], e_field [3], gm.  The mesh topology is
+ * checked as by lspr_mesh_validate when the request runs.  Returns LSPR_E_NOMEM at once when
+ * the request's footprint exceeds the whole budget, LSPR_E_INVALID for bad parameters;
+ * *ticket identifies the request. */
+int lspr_server_submit(lspr_server* sv, const lspr_surface* surfaces, int32_t n_surf,
+                       const lspr_op_params* op, int32_t n_lambda, const double* lambda_nm,
+                       const lspr_c64* eps_medium, const lspr_c64* eps_surface,
+                       const double* e_field, const lspr_gmres_params* gm, uint64_t* ticket);
+
+/* Result of a request.  wait = 0 returns LSPR_E_BUSY while the request is queued or running;
+ * wait != 0 blocks until it is done.  On LSPR_OK the results are copied (host arrays of
+ * n_lambda entries, [n_lambda][3] for the dipoles; any may be NULL), *info is filled and the
+ * ticket is released.  The request's own status is info->status; unknown tickets give
+ * LSPR_E_INVALID. */
+int lspr_server_poll(lspr_server* sv, uint64_t ticket, int32_t wait, lspr_request_info* info,
+                     double* cext_sensor, double* cext_total, lspr_c64* p_sensor,
+                     lspr_c64* p_total, int32_t* iters, double* rel_resid);
+
+int lspr_server_stats_get(lspr_server* sv, lspr_server_stats* out);
+
+/* Waits for the running requests, cancels the queued ones and frees everything. */
+int lspr_server_destroy(lspr_server* sv);
+
+/* Admission estimate: an upper bound of the device bytes one request with N panels on n_surf
+ * surfaces and n_lambda wavelengths holds at its peak (set-up, matrix-core tiles up to their
+ * cap, GMRES state for one batch of at most 64 wavelengths). */
+int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
+                           const lspr_op_params* op, const lspr_gmres_params* gm,
+                           int64_t* bytes);
+
 const char* lspr_status_string(int code);
 const char* lspr_last_error(void);
 

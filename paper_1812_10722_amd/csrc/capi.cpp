@@ -3,10 +3,10 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
-#include <map>
 #include <set>
 #include <utility>
 
+#include "driver.hpp"
 #include "operator.hpp"
 #include "profile.hpp"
 #include "system.hpp"
@@ -17,26 +17,8 @@ struct lspr_geometry {
 
 namespace {
 
-thread_local std::string g_last_error;
-
-template <class F>
-int guarded(F&& f) {
-    try {
-        g_last_error.clear();
-        return f();
-    } catch (const lspr::Error& e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return LSPR_E_NOMEM;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return LSPR_E_INVALID;
-    }
-}
-
-constexpr int MAX_BATCH = 64;  // wavelengths per block matrix-vector product
+using lspr::guarded;
+using lspr::MAX_BATCH;
 
 lspr::EpsSet make_eps(int B, int S, const lspr_c64* em, const lspr_c64* es) {
     lspr::EpsSet e;
@@ -52,6 +34,267 @@ lspr::EpsSet make_eps(int B, int S, const lspr_c64* em, const lspr_c64* es) {
 }
 
 }  // namespace
+
+namespace lspr {
+
+std::string& last_error() {
+    thread_local std::string text;
+    return text;
+}
+
+AllocCtx& alloc_ctx() {
+    thread_local AllocCtx ctx;
+    return ctx;
+}
+
+void validate_mesh_host(const lspr_surface* surfaces, int n_surf) {
+    LSPR_REQUIRE(surfaces && n_surf >= 1, LSPR_E_INVALID, "need at least one surface");
+    for (int s = 0; s < n_surf; ++s) {
+        const lspr_surface& f = surfaces[s];
+        const std::string tag = "surface " + std::to_string(s) + ": ";
+        LSPR_REQUIRE(f.vert && f.tri && f.n_vert >= 3 && f.n_tri >= 4, LSPR_E_INVALID,
+                     tag + "empty or null arrays");
+        // directed edges (a, b) as 64-bit keys; closed + consistently oriented + edge-manifold
+        // means every directed edge occurs once and its reverse occurs once
+        std::vector<uint64_t> edges;
+        edges.reserve(3 * static_cast<size_t>(f.n_tri));
+        double vol = 0.0;
+        for (int t = 0; t < f.n_tri; ++t) {
+            int v[3];
+            for (int k = 0; k < 3; ++k) {
+                v[k] = f.tri[3 * t + k];
+                LSPR_REQUIRE(v[k] >= 0 && v[k] < f.n_vert, LSPR_E_MESH,
+                             tag + "vertex index out of range in triangle " + std::to_string(t));
+            }
+            LSPR_REQUIRE(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], LSPR_E_MESH,
+                         tag + "repeated vertex in triangle " + std::to_string(t));
+            const double* a = f.vert + 3 * v[0];
+            const double* b = f.vert + 3 * v[1];
+            const double* c = f.vert + 3 * v[2];
+            const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+            const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+            const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                                 u[0] * w[1] - u[1] * w[0]};
+            const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            const double sc = std::max(u[0] * u[0] + u[1] * u[1] + u[2] * u[2],
+                                       w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            LSPR_REQUIRE(nn > 1e-14 * sc, LSPR_E_MESH,
+                         tag + "degenerate triangle " + std::to_string(t));
+            vol += (a[0] * n[0] + a[1] * n[1] + a[2] * n[2]) / 6.0;
+            for (int k = 0; k < 3; ++k)
+                edges.push_back(static_cast<uint64_t>(v[k]) << 32 |
+                                static_cast<uint32_t>(v[(k + 1) % 3]));
+        }
+        std::sort(edges.begin(), edges.end());
+        for (size_t k = 1; k < edges.size(); ++k)
+            LSPR_REQUIRE(edges[k] != edges[k - 1], LSPR_E_MESH,
+                         tag + "edge used twice in the same direction (orientation or "
+                               "non-manifold)");
+        for (uint64_t e : edges) {
+            const uint64_t r = (e & 0xffffffffull) << 32 | (e >> 32);
+            LSPR_REQUIRE(std::binary_search(edges.begin(), edges.end(), r), LSPR_E_MESH,
+                         tag + "open surface (edge without its reverse)");
+        }
+        LSPR_REQUIRE(vol > 0.0, LSPR_E_MESH,
+                     tag + "negative enclosed volume (normals point inwards)");
+    }
+}
+
+void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params* op) {
+    int64_t N = 0;
+    for (int s = 0; s < n_surf; ++s) {
+        LSPR_REQUIRE(surfaces[s].vert && surfaces[s].tri && surfaces[s].n_tri > 0 &&
+                 surfaces[s].n_vert > 0,
+             LSPR_E_INVALID, "empty surface");
+        N += surfaces[s].n_tri;
+    }
+    LSPR_REQUIRE(N < (1ll << 28), LSPR_E_INVALID, "too many panels");
+    std::vector<double> b, w;
+    LSPR_REQUIRE(lspr::triangle_rule(op->k_far, b, w) && op->k_far <= 8, LSPR_E_INVALID,
+             "k_far must be 1, 3, 4 or 7");
+    LSPR_REQUIRE(lspr::triangle_rule(op->k_fine, b, w), LSPR_E_INVALID,
+             "k_fine must be one of 1, 3, 4, 7, 19, 25");
+    LSPR_REQUIRE(op->n_k >= 1 && op->n_k <= 64, LSPR_E_INVALID, "n_k must be in 1..64");
+    LSPR_REQUIRE(op->threshold > 0.0, LSPR_E_INVALID, "threshold must be positive");
+    LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
+             "unknown method");
+    LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64, LSPR_E_INVALID,
+             "unknown precision");
+    if (op->method == LSPR_TREECODE) {
+        LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,
+             LSPR_E_INVALID, "p must be 2, 4, 6, 8 or 10");
+        LSPR_REQUIRE(op->theta > 0.0 && op->theta < 1.0, LSPR_E_INVALID,
+             "theta must be in (0, 1)");
+    }
+    LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
+             "ncrit and m2p_min_panels must be >= 0");
+}
+
+void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
+                     const lspr_op_params& opr, hipStream_t stream) {
+    const lspr_op_params* op = &opr;
+    validate_op(surfaces, n_surf, op);
+    g.stream = static_cast<hipStream_t>(stream);
+    g.K = op->k_far;
+    g.Kf = op->k_fine;
+    g.Nk = op->n_k;
+    g.threshold = op->threshold;
+    g.method = op->method;
+    g.P = op->method == LSPR_TREECODE ? op->p : 4;
+    g.theta = op->theta;
+    g.ncrit = op->ncrit > 0 ? op->ncrit : 16;
+    g.precision = op->precision;
+    g.n_terms = lspr::expansion_terms(g.P);
+    g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
+    g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
+    lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
+    lspr::build_geometry(g, surfaces, n_surf);
+    lspr::build_tree(g);
+    lspr::build_lists(g);
+    // boxes whose moments are needed
+    std::vector<int32_t> mb(static_cast<size_t>(g.n_m2p));
+    if (g.n_m2p > 0)
+        lspr::copy_sync(mb.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost, g.stream);
+    std::set<int32_t> uniq(mb.begin(), mb.end());
+    g.mom_boxes.assign(uniq.begin(), uniq.end());
+    if (!g.mom_boxes.empty()) {
+        std::vector<lspr::Box> bh(g.n_boxes);
+        lspr::copy_sync(bh.data(), g.boxes.p, bh.size() * sizeof(lspr::Box),
+                           hipMemcpyDeviceToHost, g.stream);
+        g.mom_panels = 0;
+        for (int32_t b : g.mom_boxes) g.mom_panels += bh[b].end - bh[b].start;
+        // P2M work items: segments of at most 128 panels per expanded box
+        constexpr int SEG = 128;
+        std::vector<lspr::P2MSeg> segs;
+        std::vector<lspr::P2MRed> reds;
+        int slots = 0;
+        for (int32_t b : g.mom_boxes) {
+            const int n = bh[b].end - bh[b].start;
+            const int ns = (n + SEG - 1) / SEG;
+            const int slot0 = ns > 1 ? slots : -1;
+            for (int k = 0; k < ns; ++k)
+                segs.push_back({b, bh[b].start + k * SEG, std::min(bh[b].end, bh[b].start + (k + 1) * SEG),
+                                ns > 1 ? slots + k : -1});
+            if (ns > 1) {
+                reds.push_back({b, slot0, slot0 + ns, 0});
+                slots += ns;
+            }
+        }
+        g.n_seg = static_cast<int>(segs.size());
+        g.n_slots = slots;
+        g.n_red = static_cast<int>(reds.size());
+        g.p2m_seg.alloc(segs.size());
+        lspr::copy_sync(g.p2m_seg.p, segs.data(), segs.size() * sizeof(lspr::P2MSeg),
+                           hipMemcpyHostToDevice, g.stream);
+        if (!reds.empty()) {
+            g.p2m_red.alloc(reds.size());
+            lspr::copy_sync(g.p2m_red.p, reds.data(), reds.size() * sizeof(lspr::P2MRed),
+                               hipMemcpyHostToDevice, g.stream);
+        }
+        g.mom_boxes_d.alloc(g.mom_boxes.size());
+        lspr::copy_sync(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size() * 4,
+                           hipMemcpyHostToDevice, g.stream);
+    }
+    lspr::build_near_table(g);
+    if (g.precision == LSPR_FP32 && g.allow_mfma) lspr::build_tiles(g);
+    lspr::precompute_rhs(g);
+}
+
+bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
+                    const lspr_c64* eps_medium, const lspr_c64* eps_surface,
+                    const double* e_field, const lspr_gmres_params& gmr, hipStream_t stream,
+                    lspr_c64* phi, lspr_c64* dphi, lspr_c64* p_sensor, lspr_c64* p_total,
+                    double* cext_sensor, double* cext_total, int32_t* iters, double* rel_resid) {
+    const lspr_gmres_params* gm = &gmr;
+    LSPR_REQUIRE(lambda_nm && eps_medium && eps_surface && e_field && gm && n_lambda >= 1,
+                 LSPR_E_INVALID, "bad arguments");
+    LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1,
+                 LSPR_E_INVALID, "bad GMRES parameters");
+    const double e2 = e_field[0] * e_field[0] + e_field[1] * e_field[1] + e_field[2] * e_field[2];
+    LSPR_REQUIRE(e2 > 0.0, LSPR_E_INVALID, "zero incident field");
+    for (int k = 0; k < n_lambda; ++k)
+        LSPR_REQUIRE(lambda_nm[k] > 0.0, LSPR_E_INVALID, "wavelengths must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nvec = 2 * static_cast<int64_t>(g.N);
+    bool all_ok = true;
+    for (int b0 = 0; b0 < n_lambda; b0 += MAX_BATCH) {
+        const int B = std::min(MAX_BATCH, n_lambda - b0);
+        const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
+        lspr::DevBuf<double2> ratio, xs(B * nvec);
+        lspr::upload_ratios(g, e, B, ratio, s);
+        const lspr::SolveResult r = lspr::gmres_solve(g, B, ratio.p, e_field, *gm, xs.p, s);
+        all_ok = all_ok && r.all_converged;
+        std::vector<double> q;
+        lspr::dipole_moments(g, B, ratio.p, e_field, xs.p, q, s);
+        for (int b = 0; b < B; ++b) {
+            const int k = b0 + b;
+            const std::complex<double> em(eps_medium[k].re, eps_medium[k].im);
+            const std::complex<double> kw = 2.0 * M_PI * std::sqrt(em) / lambda_nm[k];
+            for (int which = 0; which < 2; ++which) {
+                std::complex<double> qv[3];
+                for (int d = 0; d < 3; ++d)
+                    qv[d] = std::complex<double>(q[b * 12 + 6 * which + 2 * d],
+                                                 q[b * 12 + 6 * which + 2 * d + 1]);
+                const std::complex<double> eq = e_field[0] * qv[0] + e_field[1] * qv[1] +
+                                                e_field[2] * qv[2];
+                const double cext = std::imag(kw * kw * eq) / (kw.real() * e2);
+                lspr_c64* pp = which == 0 ? p_sensor : p_total;
+                double* cc = which == 0 ? cext_sensor : cext_total;
+                if (pp)
+                    for (int d = 0; d < 3; ++d) {
+                        const std::complex<double> p = em * qv[d];
+                        pp[3 * k + d] = lspr_c64{p.real(), p.imag()};
+                    }
+                if (cc) cc[k] = cext;
+            }
+            if (iters) iters[k] = r.iters[b];
+            if (rel_resid) rel_resid[k] = r.rel_resid[b];
+        }
+        if (phi || dphi)
+            lspr::unpermute(g, B, xs.p, phi ? reinterpret_cast<double2*>(phi) + b0 * g.N : nullptr,
+                            dphi ? reinterpret_cast<double2*>(dphi) + b0 * g.N : nullptr, s);
+        LSPR_HIP(hipStreamSynchronize(s));
+    }
+    return all_ok;
+}
+
+int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
+                    const lspr_gmres_params& gm) {
+    const int64_t nvec = 2 * N, m1 = gm.restart + 1;
+    const int64_t esz = op.precision == LSPR_FP32 ? 4 : 8;
+    const int64_t pad = (2 * B + 15) / 16 * 16;
+    const int64_t nblk = (nvec + 2047) / 2048 + 1;
+    int64_t b = 0;
+    b += static_cast<int64_t>(B) * m1 * nvec * 16;                 // Krylov basis
+    b += static_cast<int64_t>(B) * nvec * 16 * (gm.precond ? 4 : 3);  // x, w, b (, z)
+    b += static_cast<int64_t>(B) * m1 * nblk * 16 + 64 * B * m1 * 16;  // partial dots, H
+    b += N * 2 * pad * esz;                                        // packed densities
+    b += N * 2 * pad * 8 * (S > 1 ? 2 : 1);                        // raw layer sums
+    // moments and P2M partial sums: expanded boxes hold at most N panels per tree level
+    const int64_t terms = static_cast<int64_t>(op.p + 1) * (op.p + 1);
+    int levels = 2;
+    for (int64_t n = N; n > terms; n /= 4) ++levels;
+    const int64_t rows = levels * (N / std::max<int64_t>(terms, 1) + S) * terms;
+    b += 2 * rows * 2 * pad * esz;
+    return b;
+}
+
+int64_t tile_cap_bytes(int64_t N) { return N * 96 * 1024; }
+
+int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& op,
+                          const lspr_gmres_params& gm) {
+    const int B = std::min(n_lambda, MAX_BATCH);
+    const int64_t esz = op.precision == LSPR_FP32 ? 4 : 8;
+    // mesh upload, sorted panel data, tree, lists and near-singular table (up to 96 pairs per
+    // target), the set-up temporaries, and the right-hand-side columns
+    int64_t b = N * (1024 + 24 * S + (4 + 4 * op.k_far) * esz + 96 * 20) + (64 << 20);
+    b += N * 32 * (esz + 16);
+    if (op.precision == LSPR_FP32 && (op.flags & LSPR_NO_MATRIX_CORES) == 0)
+        b += tile_cap_bytes(N);
+    return b + solve_bytes(N, S, B, op, gm);
+}
+
+}  // namespace lspr
 
 size_t lspr::Geometry::device_bytes() const {
     return tri.bytes() + cen.bytes() + nrm.bytes() + area.bytes() + surf.bytes() + perm.bytes() +
@@ -79,7 +322,7 @@ const char* lspr_status_string(int code) {
     }
 }
 
-const char* lspr_last_error(void) { return g_last_error.c_str(); }
+const char* lspr_last_error(void) { return lspr::last_error().c_str(); }
 
 int lspr_triangle_rule(int32_t n, double* bary, double* w) {
     return guarded([&] {
@@ -105,49 +348,7 @@ int lspr_gauss_legendre(int32_t n, double* t, double* w) {
 
 int lspr_mesh_validate(const lspr_surface* surfaces, int32_t n_surf) {
     return guarded([&] {
-        LSPR_REQUIRE(surfaces && n_surf >= 1, LSPR_E_INVALID, "need at least one surface");
-        for (int s = 0; s < n_surf; ++s) {
-            const lspr_surface& f = surfaces[s];
-            const std::string tag = "surface " + std::to_string(s) + ": ";
-            LSPR_REQUIRE(f.vert && f.tri && f.n_vert >= 3 && f.n_tri >= 4, LSPR_E_INVALID,
-                         tag + "empty or null arrays");
-            std::map<std::pair<int, int>, int> edges;
-            double vol = 0.0;
-            for (int t = 0; t < f.n_tri; ++t) {
-                int v[3];
-                for (int k = 0; k < 3; ++k) {
-                    v[k] = f.tri[3 * t + k];
-                    LSPR_REQUIRE(v[k] >= 0 && v[k] < f.n_vert, LSPR_E_MESH,
-                                 tag + "vertex index out of range in triangle " + std::to_string(t));
-                }
-                LSPR_REQUIRE(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], LSPR_E_MESH,
-                             tag + "repeated vertex in triangle " + std::to_string(t));
-                const double* a = f.vert + 3 * v[0];
-                const double* b = f.vert + 3 * v[1];
-                const double* c = f.vert + 3 * v[2];
-                const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-                const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-                const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
-                                     u[0] * w[1] - u[1] * w[0]};
-                const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-                const double sc = std::max(u[0] * u[0] + u[1] * u[1] + u[2] * u[2],
-                                           w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-                LSPR_REQUIRE(nn > 1e-14 * sc, LSPR_E_MESH,
-                             tag + "degenerate triangle " + std::to_string(t));
-                vol += (a[0] * n[0] + a[1] * n[1] + a[2] * n[2]) / 6.0;
-                for (int k = 0; k < 3; ++k) {
-                    const auto key = std::make_pair(v[k], v[(k + 1) % 3]);
-                    LSPR_REQUIRE(++edges[key] == 1, LSPR_E_MESH,
-                                 tag + "edge used twice in the same direction (orientation or "
-                                       "non-manifold)");
-                }
-            }
-            for (const auto& e : edges)
-                LSPR_REQUIRE(edges.count(std::make_pair(e.first.second, e.first.first)) == 1,
-                             LSPR_E_MESH, tag + "open surface (edge without its reverse)");
-            LSPR_REQUIRE(vol > 0.0, LSPR_E_MESH,
-                         tag + "negative enclosed volume (normals point inwards)");
-        }
+        lspr::validate_mesh_host(surfaces, n_surf);
         return LSPR_OK;
     });
 }
@@ -158,99 +359,8 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
         LSPR_REQUIRE(surfaces && op && out && n_surf >= 1 && n_surf <= 4096, LSPR_E_INVALID,
                      "bad arguments");
         *out = nullptr;
-        int64_t N = 0;
-        for (int s = 0; s < n_surf; ++s) {
-            LSPR_REQUIRE(surfaces[s].vert && surfaces[s].tri && surfaces[s].n_tri > 0 &&
-                             surfaces[s].n_vert > 0,
-                         LSPR_E_INVALID, "empty surface");
-            N += surfaces[s].n_tri;
-        }
-        LSPR_REQUIRE(N < (1ll << 28), LSPR_E_INVALID, "too many panels");
-        std::vector<double> b, w;
-        LSPR_REQUIRE(lspr::triangle_rule(op->k_far, b, w) && op->k_far <= 8, LSPR_E_INVALID,
-                     "k_far must be 1, 3, 4 or 7");
-        LSPR_REQUIRE(lspr::triangle_rule(op->k_fine, b, w), LSPR_E_INVALID,
-                     "k_fine must be one of 1, 3, 4, 7, 19, 25");
-        LSPR_REQUIRE(op->n_k >= 1 && op->n_k <= 64, LSPR_E_INVALID, "n_k must be in 1..64");
-        LSPR_REQUIRE(op->threshold > 0.0, LSPR_E_INVALID, "threshold must be positive");
-        LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
-                     "unknown method");
-        LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64, LSPR_E_INVALID,
-                     "unknown precision");
-        if (op->method == LSPR_TREECODE) {
-            LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,
-                         LSPR_E_INVALID, "p must be 2, 4, 6, 8 or 10");
-            LSPR_REQUIRE(op->theta > 0.0 && op->theta < 1.0, LSPR_E_INVALID,
-                         "theta must be in (0, 1)");
-        }
-        LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
-                     "ncrit and m2p_min_panels must be >= 0");
         auto h = std::make_unique<lspr_geometry>();
-        lspr::Geometry& g = h->g;
-        g.stream = static_cast<hipStream_t>(stream);
-        g.K = op->k_far;
-        g.Kf = op->k_fine;
-        g.Nk = op->n_k;
-        g.threshold = op->threshold;
-        g.method = op->method;
-        g.P = op->method == LSPR_TREECODE ? op->p : 4;
-        g.theta = op->theta;
-        g.ncrit = op->ncrit > 0 ? op->ncrit : 16;
-        g.precision = op->precision;
-        g.n_terms = lspr::expansion_terms(g.P);
-        g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
-        g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
-        lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
-        lspr::build_geometry(g, surfaces, n_surf);
-        lspr::build_tree(g);
-        lspr::build_lists(g);
-        // boxes whose moments are needed
-        std::vector<int32_t> mb(static_cast<size_t>(g.n_m2p));
-        if (g.n_m2p > 0)
-            LSPR_HIP(hipMemcpy(mb.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost));
-        std::set<int32_t> uniq(mb.begin(), mb.end());
-        g.mom_boxes.assign(uniq.begin(), uniq.end());
-        if (!g.mom_boxes.empty()) {
-            std::vector<lspr::Box> bh(g.n_boxes);
-            LSPR_HIP(hipMemcpy(bh.data(), g.boxes.p, bh.size() * sizeof(lspr::Box),
-                               hipMemcpyDeviceToHost));
-            g.mom_panels = 0;
-            for (int32_t b : g.mom_boxes) g.mom_panels += bh[b].end - bh[b].start;
-            // P2M work items: segments of at most 128 panels per expanded box
-            constexpr int SEG = 128;
-            std::vector<lspr::P2MSeg> segs;
-            std::vector<lspr::P2MRed> reds;
-            int slots = 0;
-            for (int32_t b : g.mom_boxes) {
-                const int n = bh[b].end - bh[b].start;
-                const int ns = (n + SEG - 1) / SEG;
-                const int slot0 = ns > 1 ? slots : -1;
-                for (int k = 0; k < ns; ++k)
-                    segs.push_back({b, bh[b].start + k * SEG, std::min(bh[b].end, bh[b].start + (k + 1) * SEG),
-                                    ns > 1 ? slots + k : -1});
-                if (ns > 1) {
-                    reds.push_back({b, slot0, slot0 + ns, 0});
-                    slots += ns;
-                }
-            }
-            g.n_seg = static_cast<int>(segs.size());
-            g.n_slots = slots;
-            g.n_red = static_cast<int>(reds.size());
-            g.p2m_seg.alloc(segs.size());
-            LSPR_HIP(hipMemcpy(g.p2m_seg.p, segs.data(), segs.size() * sizeof(lspr::P2MSeg),
-                               hipMemcpyHostToDevice));
-            if (!reds.empty()) {
-                g.p2m_red.alloc(reds.size());
-                LSPR_HIP(hipMemcpy(g.p2m_red.p, reds.data(), reds.size() * sizeof(lspr::P2MRed),
-                                   hipMemcpyHostToDevice));
-            }
-            g.mom_boxes_d.alloc(g.mom_boxes.size());
-            LSPR_HIP(hipMemcpy(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size() * 4,
-                               hipMemcpyHostToDevice));
-        }
-        lspr::build_near_table(g);
-        if (g.precision == LSPR_FP32 && g.allow_mfma) lspr::build_tiles(g);
-        lspr::precompute_rhs(g);
+        lspr::create_geometry(h->g, surfaces, n_surf, *op, static_cast<hipStream_t>(stream));
         *out = h.release();
         return LSPR_OK;
     });
@@ -339,58 +449,13 @@ int lspr_solve(lspr_geometry* h, int32_t n_lambda, const double* lambda_nm,
                lspr_c64* p_sensor, lspr_c64* p_total, double* cext_sensor, double* cext_total,
                int32_t* iters, double* rel_resid) {
     return guarded([&] {
-        LSPR_REQUIRE(h && lambda_nm && eps_medium && eps_surface && e_field && gm && n_lambda >= 1,
-                     LSPR_E_INVALID, "bad arguments");
-        LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1,
-                     LSPR_E_INVALID, "bad GMRES parameters");
-        const double e2 = e_field[0] * e_field[0] + e_field[1] * e_field[1] + e_field[2] * e_field[2];
-        LSPR_REQUIRE(e2 > 0.0, LSPR_E_INVALID, "zero incident field");
-        for (int k = 0; k < n_lambda; ++k)
-            LSPR_REQUIRE(lambda_nm[k] > 0.0, LSPR_E_INVALID, "wavelengths must be positive");
-        lspr::Geometry& g = h->g;
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        const int64_t nvec = 2 * static_cast<int64_t>(g.N);
-        bool all_ok = true;
-        for (int b0 = 0; b0 < n_lambda; b0 += MAX_BATCH) {
-            const int B = std::min(MAX_BATCH, n_lambda - b0);
-            const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
-            lspr::DevBuf<double2> ratio, xs(B * nvec);
-            lspr::upload_ratios(g, e, B, ratio, s);
-            const lspr::SolveResult r = lspr::gmres_solve(g, B, ratio.p, e_field, *gm, xs.p, s);
-            all_ok = all_ok && r.all_converged;
-            std::vector<double> q;
-            lspr::dipole_moments(g, B, ratio.p, e_field, xs.p, q, s);
-            for (int b = 0; b < B; ++b) {
-                const int k = b0 + b;
-                const std::complex<double> em(eps_medium[k].re, eps_medium[k].im);
-                const std::complex<double> kw = 2.0 * M_PI * std::sqrt(em) / lambda_nm[k];
-                for (int which = 0; which < 2; ++which) {
-                    std::complex<double> qv[3];
-                    for (int d = 0; d < 3; ++d)
-                        qv[d] = std::complex<double>(q[b * 12 + 6 * which + 2 * d],
-                                                     q[b * 12 + 6 * which + 2 * d + 1]);
-                    const std::complex<double> eq = e_field[0] * qv[0] + e_field[1] * qv[1] +
-                                                    e_field[2] * qv[2];
-                    const double cext = std::imag(kw * kw * eq) / (kw.real() * e2);
-                    lspr_c64* pp = which == 0 ? p_sensor : p_total;
-                    double* cc = which == 0 ? cext_sensor : cext_total;
-                    if (pp)
-                        for (int d = 0; d < 3; ++d) {
-                            const std::complex<double> p = em * qv[d];
-                            pp[3 * k + d] = lspr_c64{p.real(), p.imag()};
-                        }
-                    if (cc) cc[k] = cext;
-                }
-                if (iters) iters[k] = r.iters[b];
-                if (rel_resid) rel_resid[k] = r.rel_resid[b];
-            }
-            if (phi || dphi)
-                lspr::unpermute(g, B, xs.p, phi ? reinterpret_cast<double2*>(phi) + b0 * g.N : nullptr,
-                                dphi ? reinterpret_cast<double2*>(dphi) + b0 * g.N : nullptr, s);
-            LSPR_HIP(hipStreamSynchronize(s));
-        }
-        if (!all_ok) {
-            g_last_error = "some wavelengths reached max_iter before tol";
+        LSPR_REQUIRE(h && gm, LSPR_E_INVALID, "bad arguments");
+        const bool ok = lspr::solve_geometry(h->g, n_lambda, lambda_nm, eps_medium, eps_surface,
+                                             e_field, *gm, static_cast<hipStream_t>(stream), phi,
+                                             dphi, p_sensor, p_total, cext_sensor, cext_total,
+                                             iters, rel_resid);
+        if (!ok) {
+            lspr::last_error() = "some wavelengths reached max_iter before tol";
             return static_cast<int>(LSPR_E_NOCONV);
         }
         return static_cast<int>(LSPR_OK);

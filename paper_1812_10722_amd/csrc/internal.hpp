@@ -33,37 +33,81 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::lspr::Error((code), std::string(msg));    \
     } while (0)
 
-// Owning device allocation (hipMalloc / hipFree).  Moves, never copies.
+// Allocation context of the calling thread.  By default DevBuf allocates with hipMalloc and
+// frees with hipFree.  A thread that installs a memory pool allocates stream-ordered from it on
+// `stream` and frees stream-ordered on the same stream, so that requests sharing the device do
+// not synchronise the whole device on every free (the request server does this per worker).
+// live / peak count the bytes held by DevBufs allocated on this thread.
+struct AllocCtx {
+    hipMemPool_t pool = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t live = 0, peak = 0;
+};
+AllocCtx& alloc_ctx();
+
+// Owning device allocation.  Moves, never copies.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    hipStream_t free_stream = nullptr;
+    bool pooled = false;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf&& o) noexcept { take(o); }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); take(o); }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        LSPR_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+        AllocCtx& c = alloc_ctx();
+        const size_t b = count * sizeof(T);
+        if (c.pool) {
+            LSPR_HIP(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), b, c.pool, c.stream));
+            free_stream = c.stream;
+            pooled = true;
+        } else {
+            LSPR_HIP(hipMalloc(reinterpret_cast<void**>(&p), b));
+            pooled = false;
+        }
         n = count;
+        c.live += static_cast<int64_t>(b);
+        if (c.live > c.peak) c.peak = c.live;
     }
     // grow-only reallocation for workspaces
     void reserve(size_t count) { if (count > n) alloc(count); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pooled) (void)hipFreeAsync(p, free_stream);
+            else (void)hipFree(p);
+            alloc_ctx().live -= static_cast<int64_t>(bytes());
+        }
         p = nullptr;
         n = 0;
+        pooled = false;
     }
     size_t bytes() const { return n * sizeof(T); }
     T* get() const { return p; }
+
+  private:
+    void take(DevBuf& o) {
+        p = o.p; n = o.n; free_stream = o.free_stream; pooled = o.pooled;
+        o.p = nullptr; o.n = 0; o.pooled = false;
+    }
 };
+
+// Stream-ordered copy that returns when it has completed (host buffers may be temporaries).
+inline void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind,
+                      hipStream_t s) {
+    if (bytes == 0) return;
+    LSPR_HIP(hipMemcpyAsync(dst, src, bytes, kind, s));
+    LSPR_HIP(hipStreamSynchronize(s));
+}
 
 // Octree box, one per node of every surface's tree.  Boxes of one surface are stored level by
 // level; the children of a box are contiguous.

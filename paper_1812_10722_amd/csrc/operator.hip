@@ -744,15 +744,15 @@ void build_tiles(Geometry& g) {
     hipStream_t s = g.stream;
     const int nc = g.n_chunks;
     std::vector<int32_t> mo(nc + 1), po(nc + 1), ms(nc), ps(nc);
-    LSPR_HIP(hipMemcpy(mo.data(), g.m2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
-    LSPR_HIP(hipMemcpy(po.data(), g.p2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
-    LSPR_HIP(hipMemcpy(ms.data(), g.m2p_self.p, nc * 4, hipMemcpyDeviceToHost));
-    LSPR_HIP(hipMemcpy(ps.data(), g.p2p_self.p, nc * 4, hipMemcpyDeviceToHost));
+    copy_sync(mo.data(), g.m2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost, s);
+    copy_sync(po.data(), g.p2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost, s);
+    copy_sync(ms.data(), g.m2p_self.p, nc * 4, hipMemcpyDeviceToHost, s);
+    copy_sync(ps.data(), g.p2p_self.p, nc * 4, hipMemcpyDeviceToHost, s);
     std::vector<int32_t> mbox(std::max<int64_t>(g.n_m2p, 1));
     std::vector<Range> rng(std::max<int64_t>(g.n_p2p, 1));
-    if (g.n_m2p) LSPR_HIP(hipMemcpy(mbox.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost));
+    if (g.n_m2p) copy_sync(mbox.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost, s);
     if (g.n_p2p)
-        LSPR_HIP(hipMemcpy(rng.data(), g.p2p_rng.p, g.n_p2p * sizeof(Range), hipMemcpyDeviceToHost));
+        copy_sync(rng.data(), g.p2p_rng.p, g.n_p2p * sizeof(Range), hipMemcpyDeviceToHost, s);
     const int nsm = (g.n_terms + 3) / 4;  // K-steps of an expansion tile
     std::vector<TileDesc> tiles;
     std::vector<int32_t> toff(nc + 1, 0), tself(nc, 0);
@@ -792,13 +792,13 @@ void build_tiles(Geometry& g) {
     g.tiles.alloc(std::max<int64_t>(g.n_tiles, 1));
     g.tile_off.alloc(nc + 1);
     g.tile_self.alloc(nc);
-    LSPR_HIP(hipMemcpy(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
-    LSPR_HIP(hipMemcpy(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
-    LSPR_HIP(hipMemcpy(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice));
+    copy_sync(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
+    copy_sync(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s);
+    copy_sync(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice, s);
     if (g.n_m2p > 0) {
         DevBuf<int32_t> mt(g.n_m2p), mc(g.n_m2p);
-        LSPR_HIP(hipMemcpy(mt.p, m2p_tile.data(), g.n_m2p * 4, hipMemcpyHostToDevice));
-        LSPR_HIP(hipMemcpy(mc.p, m2p_chunk.data(), g.n_m2p * 4, hipMemcpyHostToDevice));
+        copy_sync(mt.p, m2p_tile.data(), g.n_m2p * 4, hipMemcpyHostToDevice, s);
+        copy_sync(mc.p, m2p_chunk.data(), g.n_m2p * 4, hipMemcpyHostToDevice, s);
         const int n = static_cast<int>(g.n_m2p);
         switch (g.P) {
             case 2: launch_build_m2p<2>(g, g.tiles.p, mt.p, mc.p, n, s); break;
@@ -813,8 +813,8 @@ void build_tiles(Geometry& g) {
     if (!p2p_tile.empty()) {
         const int n = static_cast<int>(p2p_tile.size());
         DevBuf<int32_t> pt(n), pc(n);
-        LSPR_HIP(hipMemcpy(pt.p, p2p_tile.data(), n * 4, hipMemcpyHostToDevice));
-        LSPR_HIP(hipMemcpy(pc.p, p2p_chunk.data(), n * 4, hipMemcpyHostToDevice));
+        copy_sync(pt.p, p2p_tile.data(), n * 4, hipMemcpyHostToDevice, s);
+        copy_sync(pc.p, p2p_chunk.data(), n * 4, hipMemcpyHostToDevice, s);
         hipLaunchKernelGGL(k_build_p2p_tiles, dim3(n), dim3(256), 0, s, g.chunks.p, g.tiles.p,
                            pt.p, pc.p, n, g.cen.p, reinterpret_cast<const float*>(g.src.p), g.K,
                            g.tileA.p);

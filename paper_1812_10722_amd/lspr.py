@@ -283,3 +283,121 @@ def lspr_profile_query(name: str) -> dict:
                                    C.byref(by), C.byref(it)), "lspr_profile_query")
     return {"total_ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value,
             "items": it.value}
+
+
+# ------------------------------------------------------------------ request server
+class lspr_server_params(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("pad", C.c_int32)]
+
+
+class lspr_request_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_lambda", C.c_int32), ("n_panels", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("est_bytes", C.c_int64), ("peak_bytes", C.c_int64), ("error", C.c_char * 256)]
+
+
+class lspr_server_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "submitted", "completed", "queued", "active", "max_active", "budget_bytes",
+        "reserved_bytes", "peak_reserved_bytes", "estimate_violations")]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+
+
+_P = C.POINTER
+_sig("lspr_server_create", C.c_int, [_P(lspr_server_params), _P(C.c_void_p)])
+_sig("lspr_server_submit", C.c_int, [C.c_void_p, _P(lspr_surface), C.c_int32, _P(lspr_op_params),
+                                     C.c_int32, _P(C.c_double), _P(lspr_c64), _P(lspr_c64),
+                                     _P(C.c_double), _P(lspr_gmres_params), _P(C.c_uint64)])
+_sig("lspr_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, _P(lspr_request_info),
+                                   _P(C.c_double), _P(C.c_double), _P(lspr_c64), _P(lspr_c64),
+                                   _P(C.c_int32), _P(C.c_double)])
+_sig("lspr_server_stats_get", C.c_int, [C.c_void_p, _P(lspr_server_stats)])
+_sig("lspr_server_destroy", C.c_int, [C.c_void_p])
+_sig("lspr_request_footprint", C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P(lspr_op_params),
+                                         _P(lspr_gmres_params), _P(C.c_int64)])
+
+
+def lspr_request_footprint(n_panels, n_surf, n_lambda, op, gm) -> int:
+    out = C.c_int64()
+    _check(_lib.lspr_request_footprint(n_panels, n_surf, n_lambda, C.byref(op), C.byref(gm),
+                                       C.byref(out)), "lspr_request_footprint")
+    return out.value
+
+
+class Server:
+    """Request server (lspr_server_*): continuous batching of solve requests on the current
+    device.  Meshes are host arrays; submit() copies them and returns a ticket at once."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=4):
+        h = C.c_void_p()
+        prm = lspr_server_params(int(hbm_budget_bytes), int(max_slots), 0)
+        _check(_lib.lspr_server_create(C.byref(prm), C.byref(h)), "lspr_server_create")
+        self.handle = h
+        self._nl = {}
+
+    def submit(self, surfaces, lambdas, eps_medium, eps_surface, e_field=(0.0, 0.0, 1.0),
+               op=None, gmres=None) -> int:
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64).reshape(-1)
+        nl = len(lam)
+        ns = len(surfaces)
+        em, em_p = _c64_array(np.broadcast_to(np.asarray(eps_medium), (nl,)))
+        es, es_p = _c64_array(np.asarray(eps_surface).reshape(nl, ns))
+        ef = np.ascontiguousarray(e_field, dtype=np.float64)
+        keep = []
+        arr = (lspr_surface * ns)()
+        for k, (v, t) in enumerate(surfaces):
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            t = np.ascontiguousarray(t, dtype=np.int32)
+            keep += [v, t]
+            arr[k] = lspr_surface(len(v), v.ctypes.data, len(t), t.ctypes.data)
+        op = op if op is not None else op_params()
+        gm = gmres if gmres is not None else gmres_params()
+        tk = C.c_uint64()
+        _check(_lib.lspr_server_submit(self.handle, arr, ns, C.byref(op), nl, _dptr(lam), em_p,
+                                       es_p, _dptr(ef), C.byref(gm), C.byref(tk)),
+               "lspr_server_submit")
+        self._nl[tk.value] = nl
+        return tk.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """None while the request runs (wait=False); else a dict with its results."""
+        nl = self._nl.get(ticket, 0)  # unknown tickets are reported by the library
+        info = lspr_request_info()
+        cs, ct, rr = np.zeros(nl), np.zeros(nl), np.zeros(nl)
+        ps = np.zeros((nl, 3), np.complex128)
+        pt = np.zeros((nl, 3), np.complex128)
+        it = np.zeros(nl, np.int32)
+        code = _lib.lspr_server_poll(self.handle, ticket, 1 if wait else 0, C.byref(info),
+                                     _dptr(cs), _dptr(ct), ps.ctypes.data_as(_P(lspr_c64)),
+                                     pt.ctypes.data_as(_P(lspr_c64)),
+                                     it.ctypes.data_as(_P(C.c_int32)), _dptr(rr))
+        if code == LSPR_E_BUSY:
+            return None
+        _check(code, "lspr_server_poll")
+        self._nl.pop(ticket, None)
+        out = {name: getattr(info, name) for name, _ in info._fields_}
+        out["error"] = info.error.decode(errors="replace")
+        out.update(cext_sensor=cs, cext_total=ct, p_sensor=ps, p_total=pt, iters=it,
+                   rel_resid=rr, latency_s=info.t_done - info.t_submit)
+        return out
+
+    def stats(self) -> dict:
+        st = lspr_server_stats()
+        _check(_lib.lspr_server_stats_get(self.handle, C.byref(st)), "lspr_server_stats_get")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(_lib.lspr_server_destroy(self.handle), "lspr_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
