@@ -52,7 +52,7 @@ enum lspr_status {
 };
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
-enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1 };
+enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2 };
 enum lspr_flags { LSPR_NO_MATRIX_CORES = 1 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
@@ -79,15 +79,19 @@ typedef struct {
  *   ncrit     maximum panels per octree leaf; 0 selects the library default
  *   precision LSPR_FP64 or LSPR_FP32 for the far-field sums (P2P, P2M, M2P).  Singular and
  *             near-singular corrections, the GMRES and the post-processing are always FP64.
+ *             LSPR_FP32_REFINE64: mixed-precision iterative refinement; GMRES with FP32 products
+ *             solves for corrections, and the residual b - A x of each outer step is formed
+ *             with FP64 products; tol then applies to that FP64 residual, and lspr_apply uses
+ *             the FP64 products.
  *   m2p_min_panels  a box that passes the MAC is expanded only if it holds at least this many
  *             panels, otherwise it is summed directly (cheaper for small boxes); 0 selects the
  *             library default (the number of expansion terms).  Accuracy is unaffected: a
  *             direct sum is exact to the quadrature.
- *   flags     bit 0: never use the matrix-core far-field kernel.  By default FP32 geometries
- *             precompute the geometry-only factors of every expansion and direct tile (about
- *             1.7 GB at 32768 panels, P = 8) and run all products on matrix cores; above
- *             64 GB of tiles the geometry falls back to the vector-ALU kernel, which computes
- *             the same sums on the fly. */
+ *   flags     bit 0: never use the matrix-core far-field kernel.  By default a geometry
+ *             precomputes the geometry-only factors of every expansion and direct tile in the
+ *             precision(s) it computes in (about 1.7 GB at 32768 panels, P = 8, in FP32; twice
+ *             that in FP64) and runs all products on matrix cores; above 64 GB of tiles it falls
+ *             back to the vector-ALU kernel, which computes the same sums on the fly. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;
@@ -108,12 +112,16 @@ typedef struct {
  *   restart   Krylov dimension before restart, 1..512
  *   max_iter  total iteration cap per wavelength
  *   precond   0 = none, 1 = right block-Jacobi with the 2x2 self-panel blocks (does not
- *             change the solution, only the iteration count) */
+ *             change the solution, only the iteration count)
+ *   inner_tol LSPR_FP32_REFINE64 only: relative tolerance of each inner FP32 solve
+ *             (0 selects 1e-4); max_iter then caps the inner iterations summed over the
+ *             outer steps */
 typedef struct {
     double tol;
     int32_t restart;
     int32_t max_iter;
     int32_t precond;
+    double inner_tol;
 } lspr_gmres_params;
 
 /* Sizes of a built geometry (host struct filled by lspr_geometry_info). */

@@ -118,8 +118,9 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     LSPR_REQUIRE(op->threshold > 0.0, LSPR_E_INVALID, "threshold must be positive");
     LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
              "unknown method");
-    LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64, LSPR_E_INVALID,
-             "unknown precision");
+    LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64 ||
+                     op->precision == LSPR_FP32_REFINE64,
+                 LSPR_E_INVALID, "unknown precision");
     if (op->method == LSPR_TREECODE) {
         LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,
              LSPR_E_INVALID, "p must be 2, 4, 6, 8 or 10");
@@ -144,6 +145,8 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.theta = op->theta;
     g.ncrit = op->ncrit > 0 ? op->ncrit : 16;
     g.precision = op->precision;
+    g.need32 = op->precision != LSPR_FP64;
+    g.need64 = op->precision != LSPR_FP32;
     g.n_terms = lspr::expansion_terms(g.P);
     g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
     g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
@@ -196,7 +199,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
                            hipMemcpyHostToDevice, g.stream);
     }
     lspr::build_near_table(g);
-    if (g.precision == LSPR_FP32 && g.allow_mfma) lspr::build_tiles(g);
+    if (g.allow_mfma) lspr::build_tiles(g);
     lspr::precompute_rhs(g);
 }
 
@@ -208,7 +211,8 @@ bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
     const lspr_gmres_params* gm = &gmr;
     LSPR_REQUIRE(lambda_nm && eps_medium && eps_surface && e_field && gm && n_lambda >= 1,
                  LSPR_E_INVALID, "bad arguments");
-    LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1,
+    LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1 &&
+                     gm->inner_tol >= 0.0 && gm->inner_tol < 1.0,
                  LSPR_E_INVALID, "bad GMRES parameters");
     const double e2 = e_field[0] * e_field[0] + e_field[1] * e_field[1] + e_field[2] * e_field[2];
     LSPR_REQUIRE(e2 > 0.0, LSPR_E_INVALID, "zero incident field");
@@ -222,7 +226,10 @@ bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
         const lspr::EpsSet e = make_eps(B, g.S, eps_medium + b0, eps_surface + b0 * g.S);
         lspr::DevBuf<double2> ratio, xs(B * nvec);
         lspr::upload_ratios(g, e, B, ratio, s);
-        const lspr::SolveResult r = lspr::gmres_solve(g, B, ratio.p, e_field, *gm, xs.p, s);
+        const lspr::SolveResult r =
+            g.precision == LSPR_FP32_REFINE64
+                ? lspr::refine_solve(g, B, ratio.p, e_field, *gm, xs.p, s)
+                : lspr::gmres_solve(g, g.precision, B, ratio.p, e_field, *gm, nullptr, xs.p, s);
         all_ok = all_ok && r.all_converged;
         std::vector<double> q;
         lspr::dipole_moments(g, B, ratio.p, e_field, xs.p, q, s);
@@ -261,13 +268,15 @@ bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
 int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
                     const lspr_gmres_params& gm) {
     const int64_t nvec = 2 * N, m1 = gm.restart + 1;
-    const int64_t esz = op.precision == LSPR_FP32 ? 4 : 8;
+    const int64_t esz = op.precision == LSPR_FP32 ? 4 : 8;  // largest product precision
     const int64_t pad = (2 * B + 15) / 16 * 16;
     const int64_t nblk = (nvec + 2047) / 2048 + 1;
     int64_t b = 0;
     b += static_cast<int64_t>(B) * m1 * nvec * 16;                 // Krylov basis
     b += static_cast<int64_t>(B) * nvec * 16 * (gm.precond ? 4 : 3);  // x, w, b (, z)
     b += static_cast<int64_t>(B) * m1 * nblk * 16 + 64 * B * m1 * 16;  // partial dots, H
+    if (op.precision == LSPR_FP32_REFINE64)
+        b += static_cast<int64_t>(B) * nvec * 16 * 4;              // refinement b, r, d, w
     b += N * 2 * pad * esz;                                        // packed densities
     b += N * 2 * pad * 8 * (S > 1 ? 2 : 1);                        // raw layer sums
     // moments and P2M partial sums: expanded boxes hold at most N panels per tree level
@@ -279,7 +288,10 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
     return b;
 }
 
-int64_t tile_cap_bytes(int64_t N) { return N * 96 * 1024; }
+int64_t tile_cap_bytes(int64_t N, int precision) {
+    const int64_t per_elem = (precision != LSPR_FP64 ? 4 : 0) + (precision != LSPR_FP32 ? 8 : 0);
+    return N * 24 * 1024 * per_elem;  // 24 K elements per panel (measured: 13-18 K)
+}
 
 int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& op,
                           const lspr_gmres_params& gm) {
@@ -289,8 +301,8 @@ int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& 
     // target), the set-up temporaries, and the right-hand-side columns
     int64_t b = N * (1024 + 24 * S + (4 + 4 * op.k_far) * esz + 96 * 20) + (64 << 20);
     b += N * 32 * (esz + 16);
-    if (op.precision == LSPR_FP32 && (op.flags & LSPR_NO_MATRIX_CORES) == 0)
-        b += tile_cap_bytes(N);
+    if ((op.flags & LSPR_NO_MATRIX_CORES) == 0)
+        b += tile_cap_bytes(N, op.precision);
     return b + solve_bytes(N, S, B, op, gm);
 }
 
@@ -298,13 +310,13 @@ int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& 
 
 size_t lspr::Geometry::device_bytes() const {
     return tri.bytes() + cen.bytes() + nrm.bytes() + area.bytes() + surf.bytes() + perm.bytes() +
-           iperm.bytes() + morton.bytes() + src.bytes() + boxes.bytes() + far_rule.bytes() +
+           iperm.bytes() + morton.bytes() + boxes.bytes() + far_rule.bytes() +
            mom_boxes_d.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
            ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + tiles.bytes() + tile_off.bytes() +
-           tile_self.bytes() + tileA.bytes();
+           tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 
 extern "C" {
@@ -414,7 +426,8 @@ int lspr_apply(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
             lspr::DevBuf<double2> ratio, xs(B * nvec), ys(B * nvec);
             lspr::upload_ratios(g, e, B, ratio, s);
             lspr::to_sorted(g, B, reinterpret_cast<const double2*>(x) + b0 * nvec, xs.p, s);
-            lspr::system_apply(g, B, ratio.p, xs.p, nvec, ys.p, nvec, nullptr, s);
+            lspr::system_apply(g, g.need64 ? LSPR_FP64 : LSPR_FP32, B, ratio.p, xs.p, nvec, ys.p,
+                               nvec, nullptr, s);
             lspr::from_sorted(g, B, ys.p, reinterpret_cast<double2*>(y) + b0 * nvec, s);
             LSPR_HIP(hipStreamSynchronize(s));
         }

@@ -50,9 +50,9 @@ bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
 // B wavelengths on a geometry of N panels and S surfaces.
 int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
                     const lspr_gmres_params& gm);
-// Upper bound of the matrix-core tile store kept for a geometry of N panels (larger stores fall
-// back to the on-the-fly kernel).
-int64_t tile_cap_bytes(int64_t N);
+// Upper bound of the matrix-core tile store kept for a geometry of N panels in the given
+// precision mode (larger stores fall back to the on-the-fly kernel).
+int64_t tile_cap_bytes(int64_t N, int precision);
 // Upper bound of the device bytes one request holds at its peak (set-up, tiles, solve).
 int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& op,
                           const lspr_gmres_params& gm);

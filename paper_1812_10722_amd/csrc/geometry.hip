@@ -233,18 +233,18 @@ void build_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf) {
     g.surf.alloc(N);
     g.iperm.alloc(N);
     const size_t rs = static_cast<size_t>(N) * (4 + 4 * g.K);
-    if (g.precision == LSPR_FP32) {
-        g.src.alloc(rs * sizeof(float));
+    if (g.need32) {
+        g.src32.alloc(rs);
         hipLaunchKernelGGL(k_permute<float>, dim3((N + TPB - 1) / TPB), dim3(TPB), 0, s,
                            tri_in.p, surf_in.p, g.perm.p, N, rule_d.p, g.K, g.tri.p, g.cen.p,
-                           g.nrm.p, g.area.p, g.surf.p, g.iperm.p,
-                           reinterpret_cast<float*>(g.src.p));
-    } else {
-        g.src.alloc(rs * sizeof(double));
+                           g.nrm.p, g.area.p, g.surf.p, g.iperm.p, g.src32.p);
+        LSPR_HIP(hipGetLastError());
+    }
+    if (g.need64) {
+        g.src64.alloc(rs);
         hipLaunchKernelGGL(k_permute<double>, dim3((N + TPB - 1) / TPB), dim3(TPB), 0, s,
                            tri_in.p, surf_in.p, g.perm.p, N, rule_d.p, g.K, g.tri.p, g.cen.p,
-                           g.nrm.p, g.area.p, g.surf.p, g.iperm.p,
-                           reinterpret_cast<double*>(g.src.p));
+                           g.nrm.p, g.area.p, g.surf.p, g.iperm.p, g.src64.p);
     }
     LSPR_HIP(hipGetLastError());
     g.surf_start = offs;

@@ -348,8 +348,9 @@ int blocks_for(int64_t nvec) { return static_cast<int>((nvec + GSLICE - 1) / GSL
 
 }  // namespace
 
-SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double* e_field,
-                        const lspr_gmres_params& gm, double2* x, hipStream_t s) {
+SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
+                        const double* e_field, const lspr_gmres_params& gm, const double2* b_in,
+                        double2* x, hipStream_t s) {
     const int m = gm.restart, m1 = m + 1;
     const int64_t nvec = 2 * static_cast<int64_t>(g.N);
     const int nblk = blocks_for(nvec);
@@ -385,7 +386,10 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
     };
 
     // b, ||b||; r0 = b goes to V_0 after scaling
-    system_rhs(g, B, ratio_d, e_field, bvec.p, nvec, s);
+    if (b_in != nullptr)
+        LSPR_HIP(hipMemcpyAsync(bvec.p, b_in, B * nvec * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    else
+        system_rhs(g, B, ratio_d, e_field, bvec.p, nvec, s);
     std::vector<int32_t> active(B);
     for (int b = 0; b < B; ++b) active[b] = b;
     norms(bvec.p, nvec, active);
@@ -423,7 +427,7 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
                 vin = z.p;
                 vin_stride = nvec;
             }
-            system_apply(g, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+            system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
             {
                 // two sweeps reading j+1 basis vectors twice each (dots, update) plus w
                 prof::Scope sc("arnoldi", s, 2.0 * 16.0 * (j + 1) * double(nvec) * ns,
@@ -476,7 +480,7 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
             hipLaunchKernelGGL(k_axpy, dim3(nblk, ns), dim3(GT), 0, s, w.p, x, nvec, cols_d.p);
         }
         LSPR_HIP(hipGetLastError());
-        system_apply(g, ns, ratio_d, x, nvec, w.p, nvec, cols_d.p, s);
+        system_apply(g, prec, ns, ratio_d, x, nvec, w.p, nvec, cols_d.p, s);
         hipLaunchKernelGGL(k_resid, dim3(nblk, ns), dim3(GT), 0, s, bvec.p, w.p, V.p, m1 * nvec,
                            nvec, cols_d.p);
         LSPR_HIP(hipGetLastError());
@@ -501,6 +505,88 @@ SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double
                                cols_d.p, ns2, nrm.p);
             LSPR_HIP(hipGetLastError());
         }
+    }
+    LSPR_HIP(hipStreamSynchronize(s));
+    return res;
+}
+
+// Mixed-precision iterative refinement: x_{k+1} = x_k + d_k, where d_k solves A d = r_k by
+// GMRES with FP32 far-field products to the relative tolerance inner_tol, and the residual
+// r_k = b - A x_k is formed with FP64 products.  A column stops when ||r_k|| <= tol ||b|| or its
+// total inner iterations reach max_iter.
+SolveResult refine_solve(Geometry& g, int B, const double2* ratio_d, const double* e_field,
+                         const lspr_gmres_params& gm, double2* x, hipStream_t s) {
+    const int64_t nvec = 2 * static_cast<int64_t>(g.N);
+    const int nblk = blocks_for(nvec);
+    DevBuf<double2> b(B * nvec), r(B * nvec), d(B * nvec), w(B * nvec);
+    DevBuf<double> part2(static_cast<size_t>(B) * nblk), nrm(B), inv(B);
+    DevBuf<int32_t> cols_d(B);
+    std::vector<double> nrm_h(B);
+    LSPR_HIP(hipMemsetAsync(x, 0, B * nvec * sizeof(double2), s));
+    auto norms = [&](const double2* vec, const std::vector<int32_t>& c) {
+        LSPR_HIP(hipMemcpyAsync(cols_d.p, c.data(), c.size() * 4, hipMemcpyHostToDevice, s));
+        const int ns = static_cast<int>(c.size());
+        hipLaunchKernelGGL(k_norm_part, dim3(nblk, ns), dim3(GT), 0, s, vec, nvec, nvec,
+                           cols_d.p, part2.p, nblk);
+        hipLaunchKernelGGL(k_norm_final, dim3((ns + 63) / 64), dim3(64), 0, s, part2.p, nblk,
+                           cols_d.p, ns, nrm.p, inv.p);
+        LSPR_HIP(hipGetLastError());
+        LSPR_HIP(hipMemcpyAsync(nrm_h.data(), nrm.p, B * 8, hipMemcpyDeviceToHost, s));
+        LSPR_HIP(hipStreamSynchronize(s));
+    };
+    system_rhs(g, B, ratio_d, e_field, b.p, nvec, s);
+    LSPR_HIP(hipMemcpyAsync(r.p, b.p, B * nvec * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    std::vector<int32_t> active(B);
+    for (int c = 0; c < B; ++c) active[c] = c;
+    norms(b.p, active);
+    const std::vector<double> bnorm = nrm_h;
+    SolveResult res;
+    res.iters.assign(B, 0);
+    res.rel_resid.assign(B, 0.0);
+    auto retire = [&](int c) {  // a zero residual column is skipped by the inner solves
+        LSPR_HIP(hipMemsetAsync(r.p + c * nvec, 0, nvec * sizeof(double2), s));
+    };
+    {
+        std::vector<int32_t> keep;
+        for (int c : active) {
+            if (bnorm[c] > 0.0) keep.push_back(c);
+            else retire(c);
+        }
+        active.swap(keep);
+    }
+    lspr_gmres_params gi = gm;
+    gi.tol = gm.inner_tol > 0.0 ? gm.inner_tol : 1e-4;
+    for (int outer = 0; !active.empty(); ++outer) {
+        int used = 0;
+        for (int c : active) used = std::max(used, res.iters[c]);
+        gi.max_iter = std::max(1, gm.max_iter - used);
+        const SolveResult ri = gmres_solve(g, LSPR_FP32, B, ratio_d, e_field, gi, r.p, d.p, s);
+        for (int c : active) res.iters[c] += ri.iters[c];
+        LSPR_HIP(hipMemcpyAsync(cols_d.p, active.data(), active.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        const int ns = static_cast<int>(active.size());
+        hipLaunchKernelGGL(k_axpy, dim3(nblk, ns), dim3(GT), 0, s, d.p, x, nvec, cols_d.p);
+        LSPR_HIP(hipGetLastError());
+        system_apply(g, LSPR_FP64, ns, ratio_d, x, nvec, w.p, nvec, cols_d.p, s);
+        hipLaunchKernelGGL(k_resid, dim3(nblk, ns), dim3(GT), 0, s, b.p, w.p, r.p, nvec, nvec,
+                           cols_d.p);
+        LSPR_HIP(hipGetLastError());
+        norms(r.p, active);
+        std::vector<int32_t> cont;
+        for (int c : active) {
+            res.rel_resid[c] = nrm_h[c] / bnorm[c];
+            if (res.rel_resid[c] <= gm.tol) {
+                retire(c);
+                continue;
+            }
+            if (res.iters[c] >= gm.max_iter || outer >= 50) {
+                res.all_converged = false;
+                retire(c);
+                continue;
+            }
+            cont.push_back(c);
+        }
+        active.swap(cont);
     }
     LSPR_HIP(hipStreamSynchronize(s));
     return res;

@@ -179,9 +179,11 @@ struct Geometry {
     DevBuf<int32_t> perm;   // [N] sorted index -> caller's panel index
     DevBuf<int32_t> iperm;  // [N] caller's panel index -> sorted index
     DevBuf<uint64_t> morton; // [N] sorted keys: surface id << 48 | 48-bit Morton code
-    // far-field source record per panel in the compute precision (geometry.hip, k_permute):
-    // (n_x, n_y, n_z, A) then (y_g - c, w_g) for each far-rule node g
-    DevBuf<uint8_t> src;
+    // far-field source record per panel (geometry.hip, k_permute), in FP32 and/or FP64 as the
+    // geometry's precision needs: (n_x, n_y, n_z, A) then (y_g - c, w_g) per far-rule node g
+    DevBuf<float> src32;
+    DevBuf<double> src64;
+    bool need32 = true, need64 = false;  // precisions of the products this geometry runs
     int m2p_min_panels = 0;  // boxes with fewer panels are summed directly (cost criterion)
     // tree and lists
     int n_boxes = 0, n_leaves = 0;
@@ -194,7 +196,8 @@ struct Geometry {
     int64_t n_tiles = 0;
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
-    DevBuf<float> tileA;
+    DevBuf<float> tileA;      // FP32 left factors (need32)
+    DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
     DevBuf<P2MRed> p2m_red;
     DevBuf<int32_t> mom_boxes_d;
@@ -220,7 +223,7 @@ struct Geometry {
     // workspaces reused by the operator
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
-    bool allow_mfma = true;  // FP32 products use matrix cores (precomputed tiles)
+    bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
     double tile_budget_bytes = 64e9;  // largest tile store kept per geometry
 
     size_t device_bytes() const;
@@ -233,7 +236,8 @@ struct Cols {
     int ncol = 0;  // real columns per operator (2 * wavelengths)
     int cpt = 0;   // columns per thread per operator
     int pad = 0;   // ncol rounded up to cpt
-    bool mfma = false;  // FP32 matrix-core far-field kernel
+    bool mfma = false;  // matrix-core far-field kernel
+    int prec = LSPR_FP32;  // LSPR_FP32 or LSPR_FP64 products
 };
 
 // ---------------------------------------------------------------- quadrature (quadrature.cpp)
@@ -250,14 +254,14 @@ void build_lists(Geometry& g);
 void build_near_table(Geometry& g);
 
 // ---------------------------------------------------------------- operator (operator.hip)
-// Raw layer sums for a packed density: dens [N][2*pad] in the compute precision (K columns
+// Raw layer sums for a packed density: dens [N][2*pad] in the precision c.prec (K columns
 // then V columns, sorted panel order).  out_self/out_all [N][2*pad] FP64 receive, per target,
 // the K and V sums over its own surface and over all surfaces, including the near-singular
 // and singular corrections, without the 1/(4 pi) factor.
 void apply_raw(Geometry& g, const Cols& c, const void* dens, double* out_self, double* out_all,
                hipStream_t s);
 void precompute_rhs(Geometry& g);
-// Geometry-only left factors of the matrix-core far-field product (FP32 geometries).
+// Geometry-only left factors of the matrix-core far-field product, in each needed precision.
 void build_tiles(Geometry& g);
 
 }  // namespace lspr

@@ -300,66 +300,134 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
 }
 
 // ------------------------------------------------------------------------------- far field, MFMA
-// FP32 far-field sums on matrix cores.  For a chunk of 64 targets every interaction is a small
-// dense product: an expansion is (64 x terms) . (terms x columns) of Taylor coefficients and
-// box moments, a direct tile is (64 x 32 panels) . (32 panels x columns) of far-rule kernel
-// values and densities.  The left factors depend on geometry only; build_tiles stores them once
-// per geometry, in the operand order of v_mfma_f32_16x16x4f32 (lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16] and holds D[4 (l / 16) + i][l % 16]): for K-step s and lane l, the four
-// target tiles' values are one float4.  The product then streams those tiles from HBM and
-// spends its time in matrix-core instructions.  Each tile's product is accumulated in FP32 by
-// the matrix cores and then added to an FP64 running sum per output, so rounding does not grow
-// with the number of tiles.
+// Far-field sums on matrix cores, FP32 or FP64.  For a chunk of 64 targets every interaction is
+// a small dense product: an expansion is (64 x terms) . (terms x columns) of Taylor
+// coefficients and box moments, a direct tile is (64 x 32 panels) . (32 panels x columns) of
+// far-rule kernel values and densities.  The left factors depend on geometry only; build_tiles
+// stores them once per geometry, in the operand order of v_mfma_{f32,f64}_16x16x4 (lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; see out_row for the result rows): for
+// K-step s and lane l, the four target tiles' values are four consecutive elements.  The product
+// then streams those tiles from HBM and spends its time in matrix-core instructions.  In FP32
+// each tile's product is accumulated by the matrix cores and then added to an FP64 running sum
+// per output, so rounding does not grow with the number of tiles; in FP64 the matrix cores
+// accumulate every tile directly.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct alignas(4 * sizeof(T)) Quad {
+    T x, y, z, w;
+};
+
+template <class T>
+struct Mma;
+template <>
+struct Mma<float> {
+    using acc = v4f;
+    static __device__ __forceinline__ v4f op(float a, float b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mma<double> {
+    using acc = v4d;
+    static __device__ __forceinline__ v4d op(double a, double b, v4d c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
 
 // Workgroup = one chunk; waves [0, nwc) each own 16 K columns and the same 16 V columns
-// (4 target tiles x 2 column tiles of 16 x 16); extra waves (up to 4 in all) only help to
-// stage the left factors.  The left factor of tile e + 1 is fetched into registers while tile
-// e is multiplied out of LDS, then stored to the other LDS buffer (double buffering).
+// (4 target tiles x 2 column tiles of 16 x 16); extra waves only help to stage the left
+// factors.  The left factor of tile e + 1 is fetched into registers while tile e is multiplied
+// out of LDS, then stored to the other LDS buffer (double buffering).
 // Consecutive chunks are spatially close and share moments and densities, so workgroups are
 // mapped to chunks XCD by XCD: the hardware deals workgroups round-robin over the 8 XCDs, and
 // workgroup b handles chunk (b % 8) * ceil(n / 8) + b / 8, which gives every XCD's L2 one
 // contiguous run of chunks.
-// One tile: NST K-steps of 4 rows; all B operands of the tile are requested before the first
-// matrix-core instruction so that their latency overlaps the products.
-template <int NST>
-__device__ __forceinline__ void tile_product(const float4* __restrict__ ak4,
-                                             const float4* __restrict__ av4,
-                                             const float* __restrict__ B, int rows, int ncols,
+// One tile: NST K-steps of 4 rows.  FP32: the B operands of the whole tile are requested
+// before the first matrix-core instruction so that their latency overlaps the products.
+// FP64 operands take twice the registers: the tile goes in groups of 2 K-steps.
+#define LSPR_MMA_STEP(AK, AV, BK, BV)                         \
+    acc[0][0] = Mma<T>::op((AK).x, (BK), acc[0][0]);          \
+    acc[1][0] = Mma<T>::op((AK).y, (BK), acc[1][0]);          \
+    acc[2][0] = Mma<T>::op((AK).z, (BK), acc[2][0]);          \
+    acc[3][0] = Mma<T>::op((AK).w, (BK), acc[3][0]);          \
+    acc[0][1] = Mma<T>::op((AV).x, (BV), acc[0][1]);          \
+    acc[1][1] = Mma<T>::op((AV).y, (BV), acc[1][1]);          \
+    acc[2][1] = Mma<T>::op((AV).z, (BV), acc[2][1]);          \
+    acc[3][1] = Mma<T>::op((AV).w, (BV), acc[3][1]);
+
+template <class T, int NST>
+__device__ __forceinline__ void tile_product(const Quad<T>* __restrict__ ak4,
+                                             const Quad<T>* __restrict__ av4,
+                                             const T* __restrict__ B, int rows, int ncols,
                                              int colk, int colv, int lane, int grp,
-                                             v4f (&acc)[4][2]) {
-    float bk[NST], bv[NST];
+                                             typename Mma<T>::acc (&acc)[4][2]) {
+    if constexpr (sizeof(T) == 4) {
+        T bk[NST], bv[NST];
 #pragma unroll
-    for (int st = 0; st < NST; ++st) {
-        const int row = 4 * st + grp;
-        const bool ok = row < rows;
-        const float* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
-        bk[st] = ok ? br[colk] : 0.f;
-        bv[st] = ok ? br[colv] : 0.f;
-    }
+        for (int st = 0; st < NST; ++st) {
+            const int row = 4 * st + grp;
+            const bool ok = row < rows;
+            const T* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
+            bk[st] = ok ? br[colk] : T(0);
+            bv[st] = ok ? br[colv] : T(0);
+        }
 #pragma unroll
-    for (int st = 0; st < NST; ++st) {
-        const float4 ak = ak4[st * 64 + lane];
-        const float4 av = av4[st * 64 + lane];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.x, bk[st], acc[0][0], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.y, bk[st], acc[1][0], 0, 0, 0);
-        acc[2][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.z, bk[st], acc[2][0], 0, 0, 0);
-        acc[3][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak.w, bk[st], acc[3][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[st], acc[0][1], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[st], acc[1][1], 0, 0, 0);
-        acc[2][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[st], acc[2][1], 0, 0, 0);
-        acc[3][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[st], acc[3][1], 0, 0, 0);
+        for (int st = 0; st < NST; ++st) {
+            const Quad<T> ak = ak4[st * 64 + lane];
+            const Quad<T> av = av4[st * 64 + lane];
+            LSPR_MMA_STEP(ak, av, bk[st], bv[st])
+        }
+    } else {
+        constexpr int G = 2;
+#pragma unroll 1
+        for (int g0 = 0; g0 < NST; g0 += G) {
+            T bk[G], bv[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int row = 4 * (g0 + k) + grp;
+                const bool ok = g0 + k < NST && row < rows;
+                const T* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
+                bk[k] = ok ? br[colk] : T(0);
+                bv[k] = ok ? br[colv] : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (g0 + k < NST) {
+                    const Quad<T> ak = ak4[(g0 + k) * 64 + lane];
+                    const Quad<T> av = av4[(g0 + k) * 64 + lane];
+                    LSPR_MMA_STEP(ak, av, bk[k], bv[k])
+                }
+            }
+        }
     }
 }
+#undef LSPR_MMA_STEP
 
-template <int PF, int NSM>
+// Row within a 16 x 16 result tile of accumulator element q of lane group grp = lane / 16:
+// v_mfma_f32_16x16x4f32 holds rows 4 grp + q, v_mfma_f64_16x16x4f64 rows grp + 4 q.
+template <class T>
+__device__ __forceinline__ int out_row(int grp, int q) {
+    return sizeof(T) == 4 ? 4 * grp + q : grp + 4 * q;
+}
+
+// Elements of a tile's left factor: expansion tiles nstep * 256, direct tiles two factors
+// (double layer, then single layer) of nstep * 256.
+__device__ __forceinline__ int tile_elems(const TileDesc& T) {
+    return (T.kind == 0 ? 256 : 512) * T.nstep;
+}
+
+template <class T, int PF, int NSM>
 __global__ void __launch_bounds__(512)
 k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __restrict__ tile_off,
             const int32_t* __restrict__ tile_self, const TileDesc* __restrict__ tiles,
-            const float* __restrict__ tileA, const float* __restrict__ dens,
-            const float* __restrict__ mom, int pad, int nwc, int abuf_floats,
-            double* __restrict__ out_self, double* __restrict__ out_all) {
-    extern __shared__ float4 abuf4[];  // [2][abuf_floats / 4]
+            const T* __restrict__ tileA, const T* __restrict__ dens, const T* __restrict__ mom,
+            int pad, int nwc, int abuf_elems, double* __restrict__ out_self,
+            double* __restrict__ out_all) {
+    using Acc = typename Mma<T>::acc;
+    constexpr int PER16 = 16 / sizeof(T);  // elements per 16-byte staging chunk
+    extern __shared__ float4 abuf16[];    // [2][abuf_elems / PER16]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nthr = blockDim.x;
     const int c16 = lane & 15, grp = lane >> 4;
@@ -372,68 +440,74 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
     const bool mma = wave < nwc;
     const int colk = 16 * wave + c16;        // K column of this lane
     const int colv = pad + 16 * wave + c16;  // V column of this lane
-    v4f acc[4][2];
-    double run[4][2][4];
+    Acc acc[4][2];
+    double run[4][2][4];  // FP32 only: FP64 running sums of the tiles' partials
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+            acc[a][b] = Acc{0, 0, 0, 0};
 #pragma unroll
             for (int q = 0; q < 4; ++q) run[a][b][q] = 0.0;
         }
     const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
     const int t_mid = t_beg + tile_self[chunk];
-    const int buf4 = abuf_floats / 4;
+    const int buf16 = abuf_elems / PER16;
+    auto result = [&](int mt, int b, int q) -> double {
+        if constexpr (sizeof(T) == 4) return run[mt][b][q];
+        else return acc[mt][b][q];
+    };
     // stage the first left factor
     if (t_beg < t_end) {
-        const TileDesc T = tiles[t_beg];
-        const int n4 = (T.kind == 0 ? 64 : 128) * T.nstep;
-        const float4* src4 = reinterpret_cast<const float4*>(tileA + T.a_off);
-        for (int k = tid; k < n4; k += nthr) abuf4[k] = src4[k];
+        const TileDesc Tf = tiles[t_beg];
+        const int n16 = tile_elems(Tf) / PER16;
+        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off);
+        for (int k = tid; k < n16; k += nthr) abuf16[k] = src[k];
     }
     __syncthreads();
     for (int e = t_beg; e < t_end; ++e) {
         const int cur = (e - t_beg) & 1;
         // fetch the next left factor into registers
         float4 pf[PF];
-        int n4n = 0;
-        const float4* src4n = reinterpret_cast<const float4*>(tileA);
+        int n16n = 0;
+        const float4* srcn = reinterpret_cast<const float4*>(tileA);
         if (e + 1 < t_end) {
             const TileDesc Tn = tiles[e + 1];
-            n4n = (Tn.kind == 0 ? 64 : 128) * Tn.nstep;
-            src4n = reinterpret_cast<const float4*>(tileA + Tn.a_off);
+            n16n = tile_elems(Tn) / PER16;
+            srcn = reinterpret_cast<const float4*>(tileA + Tn.a_off);
         }
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const int k = tid + r * nthr;
-            pf[r] = k < n4n ? src4n[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            pf[r] = k < n16n ? srcn[k] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const TileDesc T = tiles[e];
+        const TileDesc Te = tiles[e];
         if (mma) {
-            const float4* ak4 = abuf4 + cur * buf4;
-            if (T.kind == 0)
-                tile_product<NSM>(ak4, ak4, mom + static_cast<size_t>(T.b_row0) * ncols, T.b_rows,
-                                  ncols, colk, colv, lane, grp, acc);
+            const Quad<T>* ak4 = reinterpret_cast<const Quad<T>*>(abuf16 + cur * buf16);
+            if (Te.kind == 0)
+                tile_product<T, NSM>(ak4, ak4, mom + static_cast<size_t>(Te.b_row0) * ncols,
+                                     Te.b_rows, ncols, colk, colv, lane, grp, acc);
             else
-                tile_product<8>(ak4, ak4 + 64 * 8, dens + static_cast<size_t>(T.b_row0) * ncols,
-                                T.b_rows, ncols, colk, colv, lane, grp, acc);
-            // the tile's FP32 partial joins an FP64 running sum
+                tile_product<T, 8>(ak4, ak4 + 64 * 8, dens + static_cast<size_t>(Te.b_row0) * ncols,
+                                   Te.b_rows, ncols, colk, colv, lane, grp, acc);
+            if constexpr (sizeof(T) == 4) {
+                // the tile's FP32 partial joins an FP64 running sum
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+                    for (int b = 0; b < 2; ++b) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) run[a][b][q] += static_cast<double>(acc[a][b][q]);
-                    acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-                }
+                        for (int q = 0; q < 4; ++q) run[a][b][q] += static_cast<double>(acc[a][b][q]);
+                        acc[a][b] = Acc{0, 0, 0, 0};
+                    }
+            }
         }
         {
-            float4* dst = abuf4 + (cur ^ 1) * buf4;
+            float4* dst = abuf16 + (cur ^ 1) * buf16;
 #pragma unroll
             for (int r = 0; r < PF; ++r) {
                 const int k = tid + r * nthr;
-                if (k < n4n) dst[k] = pf[r];
+                if (k < n16n) dst[k] = pf[r];
             }
         }
         // own-surface sums are complete after the last own-surface tile
@@ -442,11 +516,11 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int t = 16 * mt + 4 * grp + q;
+                    const int t = 16 * mt + out_row<T>(grp, q);
                     if (t < ntg) {
                         double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
-                        rowp[colk] = run[mt][0][q];
-                        rowp[colv] = run[mt][1][q];
+                        rowp[colk] = result(mt, 0, q);
+                        rowp[colv] = result(mt, 1, q);
                     }
                 }
         }
@@ -458,7 +532,7 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int t = 16 * mt + 4 * grp + q;
+                const int t = 16 * mt + out_row<T>(grp, q);
                 if (t < ntg) {
                     double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
                     rowp[colk] = 0.0;
@@ -470,24 +544,24 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int t = 16 * mt + 4 * grp + q;
+            const int t = 16 * mt + out_row<T>(grp, q);
             if (t < ntg) {
                 double* rowp = out_all + static_cast<size_t>(C.start + t) * ncols;
-                rowp[colk] = run[mt][0][q];
-                rowp[colv] = run[mt][1][q];
+                rowp[colk] = result(mt, 0, q);
+                rowp[colv] = result(mt, 1, q);
             }
         }
 }
 
 // ---- geometry-only tiles for k_far_tiles (built once per geometry)
 // Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
-template <int P>
+template <class T, int P>
 __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
                                   const TileDesc* __restrict__ tiles,
                                   const int32_t* __restrict__ m2p_tile,
                                   const int32_t* __restrict__ m2p_chunk,
                                   const int32_t* __restrict__ m2p_box, int n,
-                                  const double* __restrict__ cen, float* __restrict__ tileA) {
+                                  const double* __restrict__ cen, T* __restrict__ tileA) {
     using E = Expansion<P>;
     constexpr int NR = E::NR;
     const int e = blockIdx.x;
@@ -495,58 +569,62 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
     const int t = threadIdx.x;  // target within the chunk
     const Chunk C = chunks[m2p_chunk[e]];
     const Box B = boxes[m2p_box[e]];
-    const TileDesc T = tiles[m2p_tile[e]];
-    float* A = tileA + T.a_off;
+    const TileDesc TD = tiles[m2p_tile[e]];
+    T* A = tileA + TD.a_off;
     const int i = C.start + t;
-    float F[NR];
+    T F[NR];
     if (i < C.end) {
-        taylor_coefficients<float, P>(static_cast<float>(B.cx - cen[3 * i]),
-                                      static_cast<float>(B.cy - cen[3 * i + 1]),
-                                      static_cast<float>(B.cz - cen[3 * i + 2]), F);
+        taylor_coefficients<T, P>(static_cast<T>(B.cx - cen[3 * i]),
+                                  static_cast<T>(B.cy - cen[3 * i + 1]),
+                                  static_cast<T>(B.cz - cen[3 * i + 2]), F);
     } else {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) F[q] = 0.f;
+        for (int q = 0; q < NR; ++q) F[q] = T(0);
     }
     const int mt = t >> 4, r16 = t & 15;
-    constexpr int NRP = (NR + 3) / 4 * 4;  // equals 4 * T.nstep
+    constexpr int NRP = (NR + 3) / 4 * 4;  // equals 4 * TD.nstep
 #pragma unroll
     for (int q = 0; q < NRP; ++q) {
         const int st = q >> 2, g = q & 3;
-        A[(static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt] = q < NR ? F[q] : 0.f;
+        A[(static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt] = q < NR ? F[q] : T(0);
     }
 }
 
+__device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
 // Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
 // up to 32 consecutive source panels (zero for the target's own panel and past the range).
+template <class T>
 __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
                                   const int32_t* __restrict__ p2p_tile,
                                   const int32_t* __restrict__ p2p_chunk, int n,
-                                  const double* __restrict__ cen, const float* __restrict__ src,
-                                  int K, float* __restrict__ tileA) {
+                                  const double* __restrict__ cen, const T* __restrict__ src,
+                                  int K, T* __restrict__ tileA) {
     const int e = blockIdx.x;
     if (e >= n) return;
-    const TileDesc T = tiles[p2p_tile[e]];
+    const TileDesc TD = tiles[p2p_tile[e]];
     const Chunk C = chunks[p2p_chunk[e]];
-    float* AK = tileA + T.a_off;
-    float* AV = AK + static_cast<size_t>(T.nstep) * 256;
+    T* AK = tileA + TD.a_off;
+    T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
     const int rs = 4 + 4 * K;
-    for (int pr = threadIdx.x; pr < 64 * 4 * T.nstep; pr += blockDim.x) {
+    for (int pr = threadIdx.x; pr < 64 * 4 * TD.nstep; pr += blockDim.x) {
         const int t = pr & 63, p = pr >> 6;  // target, panel within the tile
-        const int i = C.start + t, j = T.b_row0 + p;
-        float kv = 0.f, kk = 0.f;
-        if (i < C.end && p < T.b_rows && j != i) {
-            const float* r = src + static_cast<size_t>(j) * rs;
-            const float dx = static_cast<float>(cen[3 * i] - cen[3 * j]);
-            const float dy = static_cast<float>(cen[3 * i + 1] - cen[3 * j + 1]);
-            const float dz = static_cast<float>(cen[3 * i + 2] - cen[3 * j + 2]);
-            const float sh = r[0] * dx + r[1] * dy + r[2] * dz;
-            float sv = 0.f, sk = 0.f;
+        const int i = C.start + t, j = TD.b_row0 + p;
+        T kv = 0, kk = 0;
+        if (i < C.end && p < TD.b_rows && j != i) {
+            const T* r = src + static_cast<size_t>(j) * rs;
+            const T dx = static_cast<T>(cen[3 * i] - cen[3 * j]);
+            const T dy = static_cast<T>(cen[3 * i + 1] - cen[3 * j + 1]);
+            const T dz = static_cast<T>(cen[3 * i + 2] - cen[3 * j + 2]);
+            const T sh = r[0] * dx + r[1] * dy + r[2] * dz;
+            T sv = 0, sk = 0;
             for (int gq = 0; gq < K; ++gq) {
-                const float ex_ = dx - r[4 + 4 * gq];
-                const float ey_ = dy - r[5 + 4 * gq];
-                const float ez_ = dz - r[6 + 4 * gq];
-                const float w = r[7 + 4 * gq];
-                const float ri = rsqrtf(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                const T ex_ = dx - r[4 + 4 * gq];
+                const T ey_ = dy - r[5 + 4 * gq];
+                const T ez_ = dz - r[6 + 4 * gq];
+                const T w = r[7 + 4 * gq];
+                const T ri = inv_sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
                 sv += w * ri;
                 sk += w * ri * ri * ri;
             }
@@ -587,14 +665,21 @@ __global__ void k_near_corr(const int64_t* __restrict__ off, const int32_t* __re
     if (out_self != nullptr) out_self[t] += own;
 }
 
+template <class T>
+const T* src_of(const Geometry& g);
+template <>
+const float* src_of<float>(const Geometry& g) { return g.src32.p; }
+template <>
+const double* src_of<double>(const Geometry& g) { return g.src64.p; }
+
 template <class T, int P, int CPT>
 void launch_far_p(Geometry& g, int pad, const T* dens, const T* mom, double* os, double* oa,
                   hipStream_t s) {
     const int threads = NT * (pad / CPT);
     hipLaunchKernelGGL((k_far<T, P, CPT>), dim3(g.n_chunks), dim3(threads), 0, s, g.chunks.p,
                        g.boxes.p, g.m2p_off.p, g.m2p_box.p, g.m2p_self.p, g.p2p_off.p,
-                       g.p2p_rng.p, g.p2p_self.p, g.cen.p, reinterpret_cast<const T*>(g.src.p),
-                       g.K, dens, mom, pad, os, oa);
+                       g.p2p_rng.p, g.p2p_self.p, g.cen.p, src_of<T>(g), g.K, dens, mom, pad, os,
+                       oa);
     LSPR_HIP(hipGetLastError());
 }
 
@@ -610,7 +695,7 @@ void launch_p2m_p(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
     }
     const dim3 grid(g.n_seg, (ncols + P2M_THREADS - 1) / P2M_THREADS);
     hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(P2M_THREADS), 0, s, g.boxes.p, g.p2m_seg.p,
-                       g.cen.p, reinterpret_cast<const T*>(g.src.p), g.K, dens, pad, mom, part);
+                       g.cen.p, src_of<T>(g), g.K, dens, pad, mom, part);
     LSPR_HIP(hipGetLastError());
     if (g.n_red > 0) {
         const int64_t tot = static_cast<int64_t>(g.n_red) * nr * ncols;
@@ -620,29 +705,49 @@ void launch_p2m_p(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
     }
 }
 
-template <int PF, int NSM>
-void launch_far_tiles_pf(Geometry& g, int pad, int threads, int nwc, int abuf, const float* dens,
-                         const float* mom, double* os, double* oa, hipStream_t s) {
+template <class T>
+const T* tiles_of(const Geometry& g);
+template <>
+const float* tiles_of<float>(const Geometry& g) { return g.tileA.p; }
+template <>
+const double* tiles_of<double>(const Geometry& g) { return g.tileA64.p; }
+
+template <class T, int PF, int NSM>
+void launch_far_tiles_pf(Geometry& g, int pad, int threads, int nwc, int abuf, const T* dens,
+                         const T* mom, double* os, double* oa, hipStream_t s) {
     const int nblk = (g.n_chunks + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_far_tiles<PF, NSM>), dim3(nblk), dim3(threads),
-                       2 * abuf * sizeof(float), s, g.chunks.p, g.n_chunks, g.tile_off.p,
-                       g.tile_self.p, g.tiles.p, g.tileA.p, dens, mom, pad, nwc, abuf, os, oa);
+    const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(T);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles<T, PF, NSM>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(lds));
+    hipLaunchKernelGGL((k_far_tiles<T, PF, NSM>), dim3(nblk), dim3(threads), lds, s, g.chunks.p,
+                       g.n_chunks, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g), dens,
+                       mom, pad, nwc, abuf, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
-void launch_far_tiles(Geometry& g, int pad, const float* dens, const float* mom, double* os,
+template <class T>
+void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
-    const int nwc = pad / 16;                 // waves that own columns
-    const int threads = 64 * std::max(4, nwc);
+    const int nwc = pad / 16;  // waves that own columns
+    // 8 waves always: the ones that own no columns still stage left factors
+    const int threads = 512;
     const int nsm = (g.n_terms + 3) / 4;
-    const int abuf = std::max(nsm * 256, 2 * 8 * 256);  // floats of the largest left factor
-    const int pf = (abuf / 4 + threads - 1) / threads;   // float4 per thread to stage it
+    const int abuf = std::max(nsm * 256, 2 * 8 * 256);  // elements of the largest left factor
+    const int per16 = 16 / static_cast<int>(sizeof(T));
+    const int pf = (abuf / per16 + threads - 1) / threads;  // 16-byte chunks per thread
     LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the matrix-core kernel");
-#define LSPR_FAR_TILES(NSM_)                                                                   \
-    case NSM_:                                                                                 \
-        if (pf <= 2) launch_far_tiles_pf<2, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
-        else if (pf <= 4) launch_far_tiles_pf<4, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
-        else launch_far_tiles_pf<8, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s);   \
+#define LSPR_FAR_TILES(NSM_)                                                                  \
+    case NSM_:                                                                                \
+        if (pf <= 2)                                                                          \
+            launch_far_tiles_pf<T, 2, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+        else if (pf <= 4)                                                                     \
+            launch_far_tiles_pf<T, 4, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+        else if (pf <= 6)                                                                     \
+            launch_far_tiles_pf<T, 6, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+        else                                                                                  \
+            launch_far_tiles_pf<T, 8, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
         break;
     switch (nsm) {  // (P + 1)^2 / 4 rounded up for P = 2, 4, 6, 8, 10
         LSPR_FAR_TILES(3)
@@ -671,12 +776,15 @@ void launch_far_cpt(Geometry& g, int pad, const T* dens, const T* mom, double* o
 template <class T>
 void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* oa,
                  hipStream_t s) {
+    LSPR_REQUIRE(src_of<T>(g) != nullptr, LSPR_E_INVALID,
+                 "the geometry was not built for products in this precision");
     const double nc = c.ncol;                     // used real columns per operator
     const double esz = sizeof(T);
     const double dens_bytes = double(g.N) * 2 * c.pad * esz;
     const double out_bytes = double(g.N) * 2 * c.pad * 8 * (os ? 2 : 1);
     const int NF = (g.P + 1) * (g.P + 2) * (g.P + 3) / 6;
     const double mom_bytes = double(g.mom_boxes.size()) * g.n_terms * 2 * c.pad * esz;
+    const bool fp64 = sizeof(T) == 8;
     T* mom = nullptr;
     if (!g.mom_boxes.empty()) {
         const size_t need = static_cast<size_t>(g.n_boxes) * g.n_terms * 2 * c.pad * sizeof(T);
@@ -684,7 +792,8 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
         mom = reinterpret_cast<T*>(g.ws_mom.p);
         // per panel of an expanded box: node polynomials (V and K) and the contraction with
         // every used column
-        prof::Scope sc("p2m", s, double(g.mom_panels) * (8.0 * g.K * NF + 2.0 * NF * 2 * nc),
+        prof::Scope sc(fp64 ? "p2m64" : "p2m", s,
+                       double(g.mom_panels) * (8.0 * g.K * NF + 2.0 * NF * 2 * nc),
                        double(g.mom_panels) * 2 * c.pad * esz + mom_bytes);
         switch (g.P) {
             case 2: launch_p2m_p<T, 2>(g, c.pad, dens, mom, s); break;
@@ -702,16 +811,12 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
         // 2 per coefficient and used column of each operator
         const double f = double(g.p2p_pairs) * (15.0 * g.K + 9.0 + 4.0 * nc) +
                          double(g.m2p_pairs) * (10.0 * g.n_terms + 4.0 * nc * g.n_terms);
-        prof::Scope sc("far", s, f, dens_bytes + mom_bytes + out_bytes,
+        prof::Scope sc(fp64 ? "far64" : "far", s, f, dens_bytes + mom_bytes + out_bytes,
                        (double(g.p2p_pairs) * g.K + double(g.m2p_pairs)) * (nc / 2));
         if (c.mfma) {
-            if constexpr (sizeof(T) == 4) {
-                LSPR_REQUIRE(g.n_tiles > 0 || (g.n_m2p == 0 && g.n_p2p == 0), LSPR_E_INVALID,
-                             "matrix-core tiles were not built");
-                launch_far_tiles(g, c.pad, dens, mom, os, oa, s);
-            } else {
-                throw Error(LSPR_E_INVALID, "matrix-core path is FP32 only");
-            }
+            LSPR_REQUIRE(tiles_of<T>(g) != nullptr || (g.n_m2p == 0 && g.n_p2p == 0),
+                         LSPR_E_INVALID, "matrix-core tiles were not built");
+            launch_far_tiles<T>(g, c.pad, dens, mom, os, oa, s);
         } else {
             switch (c.cpt) {
                 case 2: launch_far_cpt<T, 2>(g, c.pad, dens, mom, os, oa, s); break;
@@ -730,12 +835,32 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
     LSPR_HIP(hipGetLastError());
 }
 
-template <int P>
-void launch_build_m2p(Geometry& g, const TileDesc* tiles, const int32_t* mt, const int32_t* mc,
-                      int n, hipStream_t s) {
-    hipLaunchKernelGGL((k_build_m2p_tiles<P>), dim3(n), dim3(64), 0, s, g.chunks.p, g.boxes.p,
-                       tiles, mt, mc, g.m2p_box.p, n, g.cen.p, g.tileA.p);
+template <class T, int P>
+void launch_build_m2p(Geometry& g, T* A, const TileDesc* tiles, const int32_t* mt,
+                      const int32_t* mc, int n, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_m2p_tiles<T, P>), dim3(n), dim3(64), 0, s, g.chunks.p,
+                       g.boxes.p, tiles, mt, mc, g.m2p_box.p, n, g.cen.p, A);
     LSPR_HIP(hipGetLastError());
+}
+
+template <class T>
+void build_tiles_t(Geometry& g, T* A, const int32_t* mt, const int32_t* mc, int n_m2p,
+                   const int32_t* pt, const int32_t* pc, int n_p2p, hipStream_t s) {
+    if (n_m2p > 0) {
+        switch (g.P) {
+            case 2: launch_build_m2p<T, 2>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 4: launch_build_m2p<T, 4>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 6: launch_build_m2p<T, 6>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 8: launch_build_m2p<T, 8>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 10: launch_build_m2p<T, 10>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        }
+    }
+    if (n_p2p > 0) {
+        hipLaunchKernelGGL(k_build_p2p_tiles<T>, dim3(n_p2p), dim3(256), 0, s, g.chunks.p,
+                           g.tiles.p, pt, pc, n_p2p, g.cen.p, src_of<T>(g), g.K, A);
+        LSPR_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace
@@ -781,52 +906,43 @@ void build_tiles(Geometry& g) {
         }
     }
     toff[nc] = static_cast<int32_t>(tiles.size());
-    if (static_cast<double>(aoff) * sizeof(float) > g.tile_budget_bytes) {
+    const double esz = (g.need32 ? 4.0 : 0.0) + (g.need64 ? 8.0 : 0.0);
+    if (static_cast<double>(aoff) * esz > g.tile_budget_bytes) {
         // too large to keep (e.g. a dense product on a big mesh): keep the on-the-fly kernel
         g.allow_mfma = false;
         g.n_tiles = 0;
         return;
     }
     g.n_tiles = static_cast<int64_t>(tiles.size());
-    g.tileA.alloc(std::max<int64_t>(aoff, 1));
     g.tiles.alloc(std::max<int64_t>(g.n_tiles, 1));
     g.tile_off.alloc(nc + 1);
     g.tile_self.alloc(nc);
     copy_sync(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
     copy_sync(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s);
     copy_sync(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice, s);
-    if (g.n_m2p > 0) {
-        DevBuf<int32_t> mt(g.n_m2p), mc(g.n_m2p);
-        copy_sync(mt.p, m2p_tile.data(), g.n_m2p * 4, hipMemcpyHostToDevice, s);
-        copy_sync(mc.p, m2p_chunk.data(), g.n_m2p * 4, hipMemcpyHostToDevice, s);
-        const int n = static_cast<int>(g.n_m2p);
-        switch (g.P) {
-            case 2: launch_build_m2p<2>(g, g.tiles.p, mt.p, mc.p, n, s); break;
-            case 4: launch_build_m2p<4>(g, g.tiles.p, mt.p, mc.p, n, s); break;
-            case 6: launch_build_m2p<6>(g, g.tiles.p, mt.p, mc.p, n, s); break;
-            case 8: launch_build_m2p<8>(g, g.tiles.p, mt.p, mc.p, n, s); break;
-            case 10: launch_build_m2p<10>(g, g.tiles.p, mt.p, mc.p, n, s); break;
-            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
-        }
-        LSPR_HIP(hipStreamSynchronize(s));
+    const int n_m2p = static_cast<int>(g.n_m2p), n_p2p = static_cast<int>(p2p_tile.size());
+    DevBuf<int32_t> mt(n_m2p), mc(n_m2p), pt(n_p2p), pc(n_p2p);
+    copy_sync(mt.p, m2p_tile.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
+    copy_sync(mc.p, m2p_chunk.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
+    copy_sync(pt.p, p2p_tile.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
+    copy_sync(pc.p, p2p_chunk.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
+    if (g.need32) {
+        g.tileA.alloc(std::max<int64_t>(aoff, 1));
+        build_tiles_t<float>(g, g.tileA.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
     }
-    if (!p2p_tile.empty()) {
-        const int n = static_cast<int>(p2p_tile.size());
-        DevBuf<int32_t> pt(n), pc(n);
-        copy_sync(pt.p, p2p_tile.data(), n * 4, hipMemcpyHostToDevice, s);
-        copy_sync(pc.p, p2p_chunk.data(), n * 4, hipMemcpyHostToDevice, s);
-        hipLaunchKernelGGL(k_build_p2p_tiles, dim3(n), dim3(256), 0, s, g.chunks.p, g.tiles.p,
-                           pt.p, pc.p, n, g.cen.p, reinterpret_cast<const float*>(g.src.p), g.K,
-                           g.tileA.p);
-        LSPR_HIP(hipGetLastError());
-        LSPR_HIP(hipStreamSynchronize(s));
+    if (g.need64) {
+        g.tileA64.alloc(std::max<int64_t>(aoff, 1));
+        build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
     }
+    LSPR_HIP(hipStreamSynchronize(s));
 }
 
-Cols make_cols(int ncol, int precision, bool allow_mfma) {
+Cols make_cols(const Geometry& g, int ncol, int prec) {
     Cols c;
     c.ncol = ncol;
-    if (precision == LSPR_FP32 && allow_mfma) {
+    c.prec = prec;
+    const bool tiles = prec == LSPR_FP32 ? g.tileA.p != nullptr : g.tileA64.p != nullptr;
+    if (g.allow_mfma && (tiles || g.n_chunks == 0)) {
         // matrix cores from precomputed tiles: 16 K columns (and 16 V columns) per wavefront;
         // the tile stream dominates, so even a single wavelength is cheapest this way
         c.mfma = true;
@@ -848,7 +964,7 @@ int expansion_terms(int P) { return (P + 1) * (P + 1); }
 void apply_raw(Geometry& g, const Cols& c, const void* dens, double* out_self, double* out_all,
                hipStream_t s) {
     double* os = g.S > 1 ? out_self : nullptr;
-    if (g.precision == LSPR_FP32)
+    if (c.prec == LSPR_FP32)
         apply_far_t<float>(g, c, static_cast<const float*>(dens), os, out_all, s);
     else
         apply_far_t<double>(g, c, static_cast<const double*>(dens), os, out_all, s);

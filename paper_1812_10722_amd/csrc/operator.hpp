@@ -5,9 +5,10 @@
 
 namespace lspr {
 
-// Column blocking for ncol real columns per operator; FP32 products with at least 16 columns
-// use the matrix-core kernel unless allow_mfma is false.
-Cols make_cols(int ncol, int precision, bool allow_mfma = true);
+// Column blocking for ncol real columns per operator and products in precision prec
+// (LSPR_FP32 or LSPR_FP64); the matrix-core kernel is used when the geometry holds tiles of
+// that precision.
+Cols make_cols(const Geometry& g, int ncol, int prec);
 // Expansion terms per box and column for order P (after folding).
 int expansion_terms(int P);
 

@@ -85,7 +85,8 @@ void lspr_server::run(Request& r, hipStream_t s) {
                                    static_cast<int32_t>(r.tri[k].size() / 3), r.tri[k].data()};
         lspr::validate_mesh_host(host.data(), r.S);
         lspr::Geometry g;
-        g.tile_budget_bytes = static_cast<double>(lspr::tile_cap_bytes(r.n_panels));
+        g.tile_budget_bytes =
+            static_cast<double>(lspr::tile_cap_bytes(r.n_panels, r.op.precision));
         {
             std::vector<lspr::DevBuf<double>> vd(r.S);
             std::vector<lspr::DevBuf<int32_t>> td(r.S);
@@ -239,7 +240,8 @@ int lspr_server_submit(lspr_server* sv, const lspr_surface* surfaces, int32_t n_
                          gm && ticket && n_surf >= 1 && n_surf <= 4096 && n_lambda >= 1,
                      LSPR_E_INVALID, "bad arguments");
         lspr::validate_op(surfaces, n_surf, op);
-        LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1,
+        LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1 &&
+                     gm->inner_tol >= 0.0 && gm->inner_tol < 1.0,
                      LSPR_E_INVALID, "bad GMRES parameters");
         auto r = std::make_shared<Request>();
         r->S = n_surf;

@@ -129,13 +129,14 @@ __global__ void k_rhs_extract(const double* __restrict__ out, int N, int S, int 
 
 void precompute_rhs(Geometry& g) {
     hipStream_t s = g.stream;
-    const Cols c = make_cols(3 * g.S, g.precision, g.allow_mfma);
+    // in FP64 whenever the geometry runs FP64 products
+    const Cols c = make_cols(g, 3 * g.S, g.need64 ? LSPR_FP64 : LSPR_FP32);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
-    const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
+    const size_t esz = c.prec == LSPR_FP32 ? 4 : 8;
     DevBuf<uint8_t> dens(nd * esz);
     DevBuf<double> oa(nd), os(g.S > 1 ? nd : 0);
     const int64_t tot = static_cast<int64_t>(nd);
-    if (g.precision == LSPR_FP32)
+    if (c.prec == LSPR_FP32)
         hipLaunchKernelGGL(k_rhs_dens<float>, dim3((tot + TPB - 1) / TPB), dim3(TPB), 0, s,
                            g.nrm.p, g.surf.p, g.N, g.S, c.pad, reinterpret_cast<float*>(dens.p));
     else
@@ -170,19 +171,19 @@ void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hi
 }
 
 // y[col] = A(eps[col]) x[col] for the nslot columns listed in d_cols (or 0..nslot-1).
-void system_apply(Geometry& g, int nslot, const double2* ratio_d, const double2* x,
+void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, const double2* x,
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
                   hipStream_t s) {
-    const Cols c = make_cols(2 * nslot, g.precision, g.allow_mfma);
+    const Cols c = make_cols(g, 2 * nslot, prec);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
-    const size_t esz = g.precision == LSPR_FP32 ? 4 : 8;
+    const size_t esz = c.prec == LSPR_FP32 ? 4 : 8;
     prof::Scope sc("matvec", s, 0.0, 0.0);
     g.ws_dens.reserve(nd * esz);
     g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
     double* oa = reinterpret_cast<double*>(g.ws_out.p);
     double* os = g.S > 1 ? oa + nd : nullptr;
     const int64_t tp = static_cast<int64_t>(g.N) * c.pad;
-    if (g.precision == LSPR_FP32)
+    if (c.prec == LSPR_FP32)
         hipLaunchKernelGGL(k_pack<float>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
                            x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad,
                            reinterpret_cast<float*>(g.ws_dens.p));

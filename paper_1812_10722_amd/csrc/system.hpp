@@ -13,9 +13,10 @@ struct EpsSet {
 // ratio[b][s] = eps_surface[b][s] / eps_medium[b] on the device (grow-only buffer).
 void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s);
 
-// y[col] = A(col) x[col] for nslot columns; col = d_cols[slot] (or slot when d_cols is null).
+// y[col] = A(col) x[col] for nslot columns; col = d_cols[slot] (or slot when d_cols is null),
+// with far-field products in precision prec (LSPR_FP32 or LSPR_FP64).
 // Vectors are complex [*][2N] in sorted panel order with the given strides (in elements).
-void system_apply(Geometry& g, int nslot, const double2* ratio_d, const double2* x,
+void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, const double2* x,
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
                   hipStream_t s);
 
@@ -29,9 +30,16 @@ struct SolveResult {
     bool all_converged = true;
 };
 
-// Batched GMRES for columns 0..B-1; x_out receives the solutions [B][2N] (sorted order).
-SolveResult gmres_solve(Geometry& g, int B, const double2* ratio_d, const double* e_field,
-                        const lspr_gmres_params& gm, double2* x_out, hipStream_t s);
+// Batched GMRES for columns 0..B-1 with far-field products in precision prec; b_in holds the
+// right-hand sides [B][2N] (sorted order), or is null for the system's own (e_field);
+// x_out receives the solutions [B][2N] (sorted order).
+SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
+                        const double* e_field, const lspr_gmres_params& gm, const double2* b_in,
+                        double2* x_out, hipStream_t s);
+
+// Iterative refinement with FP32 inner solves and FP64 residuals (LSPR_FP32_REFINE64).
+SolveResult refine_solve(Geometry& g, int B, const double2* ratio_d, const double* e_field,
+                         const lspr_gmres_params& gm, double2* x_out, hipStream_t s);
 
 // Dipole moments q = p / eps_m (sensor only and total) for each column: host [B][2][3] complex.
 void dipole_moments(Geometry& g, int B, const double2* ratio_d, const double* e_field,

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "liblspr.so")
 
 LSPR_OK, LSPR_E_INVALID, LSPR_E_MESH, LSPR_E_NOMEM, LSPR_E_DEVICE, LSPR_E_NOCONV, LSPR_E_BUSY = range(7)
 LSPR_DENSE, LSPR_TREECODE = 0, 1
-LSPR_FP64, LSPR_FP32 = 0, 1
+LSPR_FP64, LSPR_FP32, LSPR_FP32_REFINE64 = 0, 1, 2
+_PRECISION = {"fp64": LSPR_FP64, "fp32": LSPR_FP32, "fp32_refine64": LSPR_FP32_REFINE64}
 
 
 class lspr_c64(C.Structure):
@@ -38,7 +39,7 @@ class lspr_op_params(C.Structure):
 
 class lspr_gmres_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class lspr_geometry_stats(C.Structure):
@@ -142,12 +143,12 @@ def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, 
               ncrit=0, precision="fp32", m2p_min_panels=0, matrix_cores=True):
     return lspr_op_params(k_far, k_fine, n_k, threshold,
                           LSPR_TREECODE if method == "treecode" else LSPR_DENSE, p, theta, ncrit,
-                          LSPR_FP32 if precision == "fp32" else LSPR_FP64, m2p_min_panels,
+                          _PRECISION[precision], m2p_min_panels,
                           0 if matrix_cores else LSPR_NO_MATRIX_CORES)
 
 
-def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1):
-    return lspr_gmres_params(tol, restart, max_iter, precond)
+def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1, inner_tol=0.0):
+    return lspr_gmres_params(tol, restart, max_iter, precond, inner_tol)
 
 
 class Geometry:

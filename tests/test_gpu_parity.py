@@ -99,11 +99,13 @@ def test_treecode_error_falls_with_order(lib, precision):
     assert errs[2] < 2e-4 and errs[-1] < max(1e-5, floor), errs  # P = 6 and P = 10
 
 
-@pytest.mark.parametrize("method,ncol", [("treecode", 20), ("dense", 9), ("treecode", 64)])
-def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol):
-    """FP32 products with >= 8 wavelengths run on matrix cores from precomputed tiles; they must
-    equal the vector-ALU kernel (same sums, different order) and the oracle's dense product
-    (treecode: to its truncation error at P = 8)."""
+@pytest.mark.parametrize("method,ncol,precision", [("treecode", 20, "fp32"), ("dense", 9, "fp32"),
+                                                   ("treecode", 64, "fp32"),
+                                                   ("treecode", 20, "fp64"), ("dense", 9, "fp64")])
+def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol, precision):
+    """Products run on matrix cores from precomputed tiles (FP32 or FP64); they must equal the
+    vector-ALU kernel (same sums, different order: FP32 3e-6, FP64 1e-12 of the largest
+    entry) and the oracle's dense product (treecode: to its truncation error at P = 8)."""
     surfs = sensor_and_blob(10, 7)
     v, t, sid, V, K, g = _dense_system(surfs, None, None)
     rng = np.random.default_rng(11)
@@ -111,17 +113,18 @@ def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol):
     eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(ncol), 2.5 + 0.1j * rng.random(ncol)], 1)
     x = _rand_x(rng, ncol, len(t))
     xt = torch.as_tensor(x).cuda()
-    kw = dict(method=method, precision="fp32", p=8, theta=0.5)
+    kw = dict(method=method, precision=precision, p=8, theta=0.5)
     mc = lib.Geometry(surfs, **kw)
     vc = lib.Geometry(surfs, matrix_cores=False, **kw)
     y_mc = mc.apply(xt, eps_m, eps_s).cpu().numpy()
     y_vc = vc.apply(xt, eps_m, eps_s).cpu().numpy()
+    same = 3e-6 if precision == "fp32" else 1e-12
     for c in (0, ncol // 2, ncol - 1):
         A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m[c], eps_s[c], [0, 0, 1.0])
         ref = A @ x[c]
         scale = np.abs(ref).max()
-        assert np.abs(y_mc[c] - y_vc[c]).max() / scale < 3e-6
-        assert np.abs(y_mc[c] - ref).max() / scale < (3e-6 if method == "dense" else 1e-4)
+        assert np.abs(y_mc[c] - y_vc[c]).max() / scale < same
+        assert np.abs(y_mc[c] - ref).max() / scale < (same if method == "dense" else 1e-4)
 
 
 # ----------------------------------------------------------------------------- full solves
@@ -158,7 +161,9 @@ def test_preconditioner_keeps_solution(lib):
 
 @pytest.mark.parametrize("method,precision,tol", [("dense", "fp64", 1e-6), ("dense", "fp32", 1e-4),
                                                   ("treecode", "fp64", 1e-4),
-                                                  ("treecode", "fp32", 1e-4)])
+                                                  ("treecode", "fp32", 1e-4),
+                                                  ("dense", "fp32_refine64", 1e-6),
+                                                  ("treecode", "fp32_refine64", 1e-4)])
 def test_spectrum_matches_oracle(lib, method, precision, tol):
     """A spectrum across the Drude resonance (8 wavelengths, 2048-panel sphere, E along x):
     every wavelength's C_ext within the path's bar of the oracle's LU value."""
@@ -169,13 +174,14 @@ def test_spectrum_matches_oracle(lib, method, precision, tol):
     e = [1.0, 0.0, 0.0]
     ref = oracle.solve(v, t, np.zeros(len(t), int), lam, em, es, e, k_far=4, k_fine=19)
     geo = lib.Geometry([(v, t)], method=method, precision=precision, p=8, theta=0.5)
-    out = geo.solve(lam, em, es, e, tol=1e-9 if precision == "fp64" else 1e-6, restart=80,
+    out = geo.solve(lam, em, es, e, tol=1e-6 if precision == "fp32" else 1e-9, restart=80,
                     max_iter=800)
+    assert out["converged"]
     rel = np.abs(out["cext_sensor"] / ref["cext_sensor"] - 1)
     assert rel.max() < tol, rel
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-4), ("fp32_refine64", 1e-6)])
 def test_sensor_with_analyte_matches_oracle(lib, precision, tol):
     """Two surfaces (Eq. matrix_multi): sensor and total cross-sections and dipoles."""
     surfs = sensor_and_blob(8, 6)
@@ -185,8 +191,9 @@ def test_sensor_with_analyte_matches_oracle(lib, precision, tol):
     es = np.stack([eps_silver_drude(lam), np.full(3, 2.5 + 0.1j)], 1)
     ref = oracle.solve(v, t, sid, lam, em, es, [0, 0, 1.0], k_far=4, k_fine=19)
     geo = lib.Geometry(surfs, method="dense", precision=precision)
-    out = geo.solve(lam, em, es, [0, 0, 1.0], tol=1e-10 if precision == "fp64" else 1e-6,
+    out = geo.solve(lam, em, es, [0, 0, 1.0], tol=1e-6 if precision == "fp32" else 1e-10,
                     restart=100, max_iter=1000)
+    assert out["converged"]
     for key in ("cext_sensor", "cext_total"):
         rel = np.abs(out[key] / ref[key] - 1)
         assert rel.max() < tol, (key, rel)
@@ -231,3 +238,21 @@ def test_bad_inputs_are_rejected(lib):
     geo = lib.Geometry([(v, t)], method="dense", precision="fp64")
     with pytest.raises(lib.LsprError):
         geo.solve([380.0], [1.7733], [[0.0]])  # eps_surface = 0
+
+
+def test_refinement_reaches_fp64_solution(lib):
+    """FP32 inner solves with FP64 residuals converge to the FP64 treecode solution: the final
+    residual is an FP64 one, and C_ext equals the FP64 solve's to the tolerance."""
+    surfs = sensor_and_blob(12, 8)
+    lam = np.array([350.0, 384.0, 420.0])
+    em = np.full(3, EPS_WATER + 0j)
+    es = np.stack([eps_silver_drude(lam), np.full(3, 2.5 + 0j)], 1)
+    kw = dict(method="treecode", p=8, theta=0.5)
+    ref = lib.Geometry(surfs, precision="fp64", **kw).solve(lam, em, es, tol=1e-10, restart=100,
+                                                            max_iter=2000)
+    geo = lib.Geometry(surfs, precision="fp32_refine64", **kw)
+    for inner in (1e-2, 1e-4):
+        out = geo.solve(lam, em, es, tol=1e-9, restart=60, max_iter=3000, inner_tol=inner)
+        assert out["converged"] and (out["rel_resid"] <= 1e-9).all(), out["rel_resid"]
+        rel = np.abs(out["cext_total"] / ref["cext_total"] - 1)
+        assert rel.max() < 1e-7, (inner, rel)
