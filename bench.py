@@ -107,6 +107,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere_32k_sweep")
+    ap.add_argument("--precision", choices=("fp32", "fp64", "fp32_refine64"),
+                    help="override the workload's product precision")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="inner tolerance of fp32_refine64 (default: the library's)")
+    ap.add_argument("--tol", type=float, default=None, help="override the GMRES tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference solve and the one-at-a-time FP64 comparison")
@@ -128,6 +133,12 @@ def main():
     w = workload(args.workload)
     op = dict(w.op)
     gm = dict(w.gmres)
+    if args.precision:
+        op["precision"] = args.precision
+    if args.inner_tol is not None:
+        gm["inner_tol"] = args.inner_tol
+    if args.tol is not None:
+        gm["tol"] = args.tol
     lam, em, es, ef = w.lambdas, w.eps_medium, w.eps_surface, w.e_field
     dev = [(torch.as_tensor(v).cuda(), torch.as_tensor(t).cuda()) for v, t in w.surfaces]
     stream = torch.cuda.current_stream()
@@ -167,7 +178,7 @@ def main():
     total = time.perf_counter() - t_start
     lspr.lspr_profile_enable(False)
     prof = {n: lspr.lspr_profile_query(n)
-            for n in ("far", "p2m", "near", "matvec", "arnoldi", "setup")}
+            for n in ("far", "far64", "p2m", "p2m64", "near", "matvec", "arnoldi", "setup")}
     n_matvec = prof["matvec"]["launches"]
 
     # accuracy against the FP64 reference (dense direct FP64 on the GPU, validated against the

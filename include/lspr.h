@@ -142,6 +142,9 @@ typedef struct {
     int32_t ncrit;           /* leaf capacity actually used */
     int32_t target_chunk;    /* targets per chunk */
     int32_t max_depth;
+    int64_t n_tiles;         /* matrix-core tiles (0 when the on-the-fly kernel is used) */
+    int64_t tile_steps;      /* K-steps over all tiles (matrix-core work per column tile) */
+    int64_t max_chunk_steps; /* K-steps of the most loaded target chunk */
 } lspr_geometry_stats;
 
 /* Checks host-side surfaces before upload: indices in range, non-degenerate panels, every

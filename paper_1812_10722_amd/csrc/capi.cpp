@@ -315,7 +315,7 @@ size_t lspr::Geometry::device_bytes() const {
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
-           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + tiles.bytes() + tile_off.bytes() +
+           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 
@@ -408,6 +408,9 @@ int lspr_geometry_info(const lspr_geometry* h, lspr_geometry_stats* o) {
         o->ncrit = g.ncrit;
         o->target_chunk = g.tchunk;
         o->max_depth = g.max_depth;
+        o->n_tiles = g.n_tiles;
+        o->tile_steps = g.tile_steps;
+        o->max_chunk_steps = g.max_chunk_steps;
         return LSPR_OK;
     });
 }

@@ -194,8 +194,10 @@ struct Geometry {
     int n_seg = 0, n_slots = 0, n_red = 0;
     // matrix-core tiles (FP32 geometries)
     int64_t n_tiles = 0;
+    int64_t tile_steps = 0, max_chunk_steps = 0;  // K-steps in all, and of the busiest chunk
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
+    DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)
     DevBuf<float> tileA;      // FP32 left factors (need32)
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;

@@ -342,8 +342,10 @@ struct Mma<double> {
 // out of LDS, then stored to the other LDS buffer (double buffering).
 // Consecutive chunks are spatially close and share moments and densities, so workgroups are
 // mapped to chunks XCD by XCD: the hardware deals workgroups round-robin over the 8 XCDs, and
-// workgroup b handles chunk (b % 8) * ceil(n / 8) + b / 8, which gives every XCD's L2 one
-// contiguous run of chunks.
+// workgroup b handles a chunk of run b % 8 of ceil(n / 8) consecutive chunks, which gives every
+// XCD's L2 one contiguous run.  Within a run, workgroups take the chunks in decreasing order of
+// work (chunk_order, built with the tiles), so the longest chunks start first and the short
+// ones fill in behind them.
 // One tile: NST K-steps of 4 rows.  FP32: the B operands of the whole tile are requested
 // before the first matrix-core instruction so that their latency overlaps the products.
 // FP64 operands take twice the registers: the tile goes in groups of 2 K-steps.
@@ -418,9 +420,10 @@ __device__ __forceinline__ int tile_elems(const TileDesc& T) {
     return (T.kind == 0 ? 256 : 512) * T.nstep;
 }
 
-template <class T, int PF, int NSM>
-__global__ void __launch_bounds__(512)
-k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __restrict__ tile_off,
+template <class T, int PF, int NSM, int NTHR>
+__global__ void __launch_bounds__(NTHR, 2)
+k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order, int halves,
+            const int32_t* __restrict__ tile_off,
             const int32_t* __restrict__ tile_self, const TileDesc* __restrict__ tiles,
             const T* __restrict__ tileA, const T* __restrict__ dens, const T* __restrict__ mom,
             int pad, int nwc, int abuf_elems, double* __restrict__ out_self,
@@ -429,17 +432,21 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
     constexpr int PER16 = 16 / sizeof(T);  // elements per 16-byte staging chunk
     extern __shared__ float4 abuf16[];    // [2][abuf_elems / PER16]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nthr = blockDim.x;
+    constexpr int nthr = NTHR;
     const int c16 = lane & 15, grp = lane >> 4;
     const int ncols = 2 * pad;
-    const int per_xcd = (n_chunks + 7) / 8;
-    const int chunk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (chunk >= n_chunks) return;
+    // halves == 2: the chunk's column groups are split over two workgroups (b and b + 8,
+    // which land on the same XCD), so that two independent workgroups share each CU
+    const int b = blockIdx.x;
+    const int half = halves == 2 ? (b >> 3) & 1 : 0;
+    const int chunk = chunk_order[halves == 2 ? ((b >> 4) << 3) + (b & 7) : b];
+    if (chunk < 0) return;
     const Chunk C = chunks[chunk];
     const int ntg = C.end - C.start;
-    const bool mma = wave < nwc;
-    const int colk = 16 * wave + c16;        // K column of this lane
-    const int colv = pad + 16 * wave + c16;  // V column of this lane
+    const int wg = wave + half * (NTHR / 64);  // column group of this wave
+    const bool mma = wg < nwc;
+    const int colk = 16 * wg + c16;        // K column of this lane
+    const int colv = pad + 16 * wg + c16;  // V column of this lane
     Acc acc[4][2];
     double run[4][2][4];  // FP32 only: FP64 running sums of the tiles' partials
 #pragma unroll
@@ -465,23 +472,26 @@ k_far_tiles(const Chunk* __restrict__ chunks, int n_chunks, const int32_t* __res
         for (int k = tid; k < n16; k += nthr) abuf16[k] = src[k];
     }
     __syncthreads();
+    // the next tile's descriptor is read one tile ahead, so that the B operands of a tile
+    // can be requested as soon as the tile starts
+    TileDesc Tnext = tiles[t_beg < t_end ? t_beg : 0];
     for (int e = t_beg; e < t_end; ++e) {
         const int cur = (e - t_beg) & 1;
+        const TileDesc Te = Tnext;
+        if (e + 1 < t_end) Tnext = tiles[e + 1];
         // fetch the next left factor into registers
         float4 pf[PF];
         int n16n = 0;
         const float4* srcn = reinterpret_cast<const float4*>(tileA);
         if (e + 1 < t_end) {
-            const TileDesc Tn = tiles[e + 1];
-            n16n = tile_elems(Tn) / PER16;
-            srcn = reinterpret_cast<const float4*>(tileA + Tn.a_off);
+            n16n = tile_elems(Tnext) / PER16;
+            srcn = reinterpret_cast<const float4*>(tileA + Tnext.a_off);
         }
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const int k = tid + r * nthr;
             pf[r] = k < n16n ? srcn[k] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const TileDesc Te = tiles[e];
         if (mma) {
             const Quad<T>* ak4 = reinterpret_cast<const Quad<T>*>(abuf16 + cur * buf16);
             if (Te.kind == 0)
@@ -712,42 +722,44 @@ const float* tiles_of<float>(const Geometry& g) { return g.tileA.p; }
 template <>
 const double* tiles_of<double>(const Geometry& g) { return g.tileA64.p; }
 
-template <class T, int PF, int NSM>
-void launch_far_tiles_pf(Geometry& g, int pad, int threads, int nwc, int abuf, const T* dens,
+template <class T, int PF, int NSM, int NTHR>
+void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, const T* dens,
                          const T* mom, double* os, double* oa, hipStream_t s) {
-    const int nblk = (g.n_chunks + 7) / 8 * 8;
+    const int nblk = (g.n_chunks + 7) / 8 * 8 * halves;
     const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(T);
     if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles<T, PF, NSM>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles<T, PF, NSM, NTHR>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(lds));
-    hipLaunchKernelGGL((k_far_tiles<T, PF, NSM>), dim3(nblk), dim3(threads), lds, s, g.chunks.p,
-                       g.n_chunks, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g), dens,
-                       mom, pad, nwc, abuf, os, oa);
+    hipLaunchKernelGGL((k_far_tiles<T, PF, NSM, NTHR>), dim3(nblk), dim3(NTHR), lds, s,
+                       g.chunks.p, g.chunk_order.p, halves, g.tile_off.p, g.tile_self.p,
+                       g.tiles.p, tiles_of<T>(g), dens, mom, pad, nwc, abuf, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
-    const int nwc = pad / 16;  // waves that own columns
-    // 8 waves always: the ones that own no columns still stage left factors
-    const int threads = 512;
+    const int nwc = pad / 16;  // column groups (16 K and 16 V columns each)
+    // FP32: 4-wave workgroups, two per CU (a chunk with more than 4 column groups is split
+    // over two workgroups); FP64 left factors fill a CU's LDS, so one 8-wave workgroup per CU
+    constexpr int NTHR = sizeof(T) == 4 ? 256 : 512;
+    const int halves = nwc > NTHR / 64 ? 2 : 1;
     const int nsm = (g.n_terms + 3) / 4;
     const int abuf = std::max(nsm * 256, 2 * 8 * 256);  // elements of the largest left factor
     const int per16 = 16 / static_cast<int>(sizeof(T));
-    const int pf = (abuf / per16 + threads - 1) / threads;  // 16-byte chunks per thread
+    const int pf = (abuf / per16 + NTHR - 1) / NTHR;  // 16-byte chunks per thread
     LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the matrix-core kernel");
-#define LSPR_FAR_TILES(NSM_)                                                                  \
-    case NSM_:                                                                                \
-        if (pf <= 2)                                                                          \
-            launch_far_tiles_pf<T, 2, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
-        else if (pf <= 4)                                                                     \
-            launch_far_tiles_pf<T, 4, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
-        else if (pf <= 6)                                                                     \
-            launch_far_tiles_pf<T, 6, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
-        else                                                                                  \
-            launch_far_tiles_pf<T, 8, NSM_>(g, pad, threads, nwc, abuf, dens, mom, os, oa, s); \
+#define LSPR_FAR_TILES(NSM_)                                                                    \
+    case NSM_:                                                                                  \
+        if (pf <= 2)                                                                            \
+            launch_far_tiles_pf<T, 2, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
+        else if (pf <= 4)                                                                       \
+            launch_far_tiles_pf<T, 4, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
+        else if (pf <= 6)                                                                       \
+            launch_far_tiles_pf<T, 6, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
+        else                                                                                    \
+            launch_far_tiles_pf<T, 8, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
         break;
     switch (nsm) {  // (P + 1)^2 / 4 rounded up for P = 2, 4, 6, 8, 10
         LSPR_FAR_TILES(3)
@@ -906,6 +918,24 @@ void build_tiles(Geometry& g) {
         }
     }
     toff[nc] = static_cast<int32_t>(tiles.size());
+    g.tile_steps = 0;
+    g.max_chunk_steps = 0;
+    std::vector<int64_t> csteps(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+        for (int t = toff[c]; t < toff[c + 1]; ++t) csteps[c] += tiles[t].nstep;
+        g.tile_steps += csteps[c];
+        g.max_chunk_steps = std::max(g.max_chunk_steps, csteps[c]);
+    }
+    // workgroup order: run x = b % 8 of consecutive chunks, heaviest first within the run
+    const int per_xcd = (nc + 7) / 8;
+    std::vector<int32_t> order(static_cast<size_t>(per_xcd) * 8, -1);
+    for (int x = 0; x < 8; ++x) {
+        std::vector<int32_t> run;
+        for (int c = x * per_xcd; c < std::min(nc, (x + 1) * per_xcd); ++c) run.push_back(c);
+        std::stable_sort(run.begin(), run.end(),
+                         [&](int32_t a, int32_t b) { return csteps[a] > csteps[b]; });
+        for (size_t i = 0; i < run.size(); ++i) order[i * 8 + x] = run[i];
+    }
     const double esz = (g.need32 ? 4.0 : 0.0) + (g.need64 ? 8.0 : 0.0);
     if (static_cast<double>(aoff) * esz > g.tile_budget_bytes) {
         // too large to keep (e.g. a dense product on a big mesh): keep the on-the-fly kernel
@@ -917,6 +947,8 @@ void build_tiles(Geometry& g) {
     g.tiles.alloc(std::max<int64_t>(g.n_tiles, 1));
     g.tile_off.alloc(nc + 1);
     g.tile_self.alloc(nc);
+    g.chunk_order.alloc(order.size());
+    copy_sync(g.chunk_order.p, order.data(), order.size() * 4, hipMemcpyHostToDevice, s);
     copy_sync(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
     copy_sync(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s);
     copy_sync(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice, s);

@@ -46,7 +46,8 @@ class lspr_geometry_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n_panels", "n_surfaces", "n_nodes", "n_boxes", "n_leaves", "n_target_chunks", "n_m2p",
         "n_p2p_ranges", "p2p_pairs", "m2p_pairs", "n_near", "device_bytes")] + \
-        [(n, C.c_int32) for n in ("n_terms", "ncrit", "target_chunk", "max_depth")]
+        [(n, C.c_int32) for n in ("n_terms", "ncrit", "target_chunk", "max_depth")] + \
+        [(n, C.c_int64) for n in ("n_tiles", "tile_steps", "max_chunk_steps")]
 
 
 def _load():
