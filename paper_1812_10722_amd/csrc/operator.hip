@@ -314,6 +314,11 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// K-steps of a direct tile: 4 * DSTEPS source panels per tile, summed in FP32 by the matrix
+// cores before the tile joins the FP64 running sum (longer tiles measured no faster and add
+// FP32 rounding that GMRES feels near resonance).
+constexpr int DSTEPS = 8;
+
 template <class T>
 struct alignas(4 * sizeof(T)) Quad {
     T x, y, z, w;
@@ -498,7 +503,7 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
                 tile_product<T, NSM>(ak4, ak4, mom + static_cast<size_t>(Te.b_row0) * ncols,
                                      Te.b_rows, ncols, colk, colv, lane, grp, acc);
             else
-                tile_product<T, 8>(ak4, ak4 + 64 * 8, dens + static_cast<size_t>(Te.b_row0) * ncols,
+                tile_product<T, DSTEPS>(ak4, ak4 + 64 * DSTEPS, dens + static_cast<size_t>(Te.b_row0) * ncols,
                                    Te.b_rows, ncols, colk, colv, lane, grp, acc);
             if constexpr (sizeof(T) == 4) {
                 // the tile's FP32 partial joins an FP64 running sum
@@ -563,6 +568,143 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
         }
 }
 
+// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, b + 16, b + 24 handle one
+// chunk (all on the same XCD, so the later ones read the chunk's left factors from L2): the
+// double-layer (K) and single-layer (V) columns, each in two halves of 4 column groups of 16,
+// one group per wave.  Per wave this needs far fewer registers than a K-and-V wave, so three
+// independent workgroups share each CU and hide each other's latencies.
+// Expansion tiles share one left factor between the operators; direct tiles hold the K factor
+// and then the V factor.
+// Buffer resource over [p, p + bytes) for raw buffer loads: out-of-range offsets read zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
+}
+
+template <int PF, int NSM>
+__global__ void __launch_bounds__(256, 3)
+k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
+               const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
+               const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
+               const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
+               int abuf_elems, double* __restrict__ out_self, double* __restrict__ out_all) {
+    constexpr int NTHR = 256;
+    extern __shared__ float4 abuf16[];  // [2][abuf_elems / 4]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int ncols = 2 * pad;
+    const int b = blockIdx.x;
+    const int j = (b >> 3) & 3;
+    const int opr = j & 1;                  // 0: K columns, 1: V columns
+    const int wg = wave + 4 * (j >> 1);     // column group of this wave
+    const int chunk = chunk_order[((b >> 5) << 3) + (b & 7)];
+    if (chunk < 0) return;
+    const Chunk C = chunks[chunk];
+    const int ntg = C.end - C.start;
+    const bool mma = wg < nwc;
+    const int col = opr * pad + 16 * wg + c16;  // this lane's column
+    // B operand of K-step st: row 4 st + grp of the tile, column col, i.e. byte offset
+    // boff + st * bstep from the tile's first row (rows past the tile read zero)
+    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * 4u;
+    const uint32_t bstep = 16u * static_cast<uint32_t>(ncols);
+    v4f acc[4];
+    double run[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[a][q] = 0.0;
+    }
+    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
+    const int t_mid = t_beg + tile_self[chunk];
+    const int buf16 = abuf_elems / 4;
+    auto write_sums = [&](double* out) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + 4 * grp + q;
+                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = run[mt][q];
+            }
+    };
+    if (t_beg < t_end) {
+        const TileDesc Tf = tiles[t_beg];
+        const int n16 = tile_elems(Tf) / 4;
+        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off);
+        for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
+    }
+    __syncthreads();
+    for (int e = t_beg; e < t_end; ++e) {
+        const int cur = (e - t_beg) & 1;
+        // the next left factor into registers (chunks past it read zero and are not stored)
+        float4 pf[PF];
+        int n16n = 0;
+        {
+            const TileDesc Tn = tiles[e + 1 < t_end ? e + 1 : e];
+            n16n = e + 1 < t_end ? tile_elems(Tn) / 4 : 0;
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + Tn.a_off, n16n * 16u);
+#pragma unroll
+            for (int r = 0; r < PF; ++r) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, (tid + r * NTHR) * 16, 0, 0);
+                pf[r] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
+                                    __uint_as_float(v[2]), __uint_as_float(v[3]));
+            }
+        }
+        const TileDesc Te = tiles[e];
+        if (mma) {
+            const float4* ab = abuf16 + cur * buf16;
+#define LSPR_OP_TILE(NS, BSRC, AOFF)                                                       \
+    {                                                                                      \
+        const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(                                     \
+            (BSRC) + static_cast<size_t>(Te.b_row0) * ncols,                               \
+            static_cast<uint32_t>(Te.b_rows) * static_cast<uint32_t>(ncols) * 4u);          \
+        float bb[NS];                                                                      \
+        _Pragma("unroll") for (int st = 0; st < (NS); ++st)                                \
+            bb[st] = __uint_as_float(                                                      \
+                __builtin_amdgcn_raw_buffer_load_b32(rb, boff + st * bstep, 0, 0));        \
+        const float4* a4 = ab + (AOFF);                                                    \
+        _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
+            const float4 a = a4[st * 64 + lane];                                           \
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb[st], acc[0], 0, 0, 0);   \
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb[st], acc[1], 0, 0, 0);   \
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bb[st], acc[2], 0, 0, 0);   \
+            acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bb[st], acc[3], 0, 0, 0);   \
+        }                                                                                  \
+    }
+            if (Te.kind == 0) LSPR_OP_TILE(NSM, mom, 0)
+            else LSPR_OP_TILE(DSTEPS, dens, opr * 64 * DSTEPS)
+#undef LSPR_OP_TILE
+            // the tile's FP32 partial joins an FP64 running sum
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
+                acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+            if (e + 1 == t_mid && out_self != nullptr) write_sums(out_self);
+        }
+        {
+            float4* dst = abuf16 + (cur ^ 1) * buf16;
+#pragma unroll
+            for (int r = 0; r < PF; ++r) {
+                const int k = tid + r * NTHR;
+                if (k < n16n) dst[k] = pf[r];
+            }
+        }
+        __syncthreads();
+    }
+    if (!mma) return;
+    if (t_mid == t_beg && out_self != nullptr) {  // no own-surface tiles
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + 4 * grp + q;
+                if (t < ntg) out_self[static_cast<size_t>(C.start + t) * ncols + col] = 0.0;
+            }
+    }
+    write_sums(out_all);
+}
+
 // ---- geometry-only tiles for k_far_tiles (built once per geometry)
 // Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
 template <class T, int P>
@@ -604,7 +746,7 @@ __device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
 
 // Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
-// up to 32 consecutive source panels (zero for the target's own panel and past the range).
+// up to 4 * DSTEPS consecutive source panels (zero for the target's own panel and past the range).
 template <class T>
 __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
                                   const int32_t* __restrict__ p2p_tile,
@@ -737,16 +879,50 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
+template <int PF, int NSM>
+void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
+                         double* os, double* oa, hipStream_t s) {
+    const int nblk = (g.n_chunks + 7) / 8 * 8 * 4;
+    const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(float);
+    hipLaunchKernelGGL((k_far_tiles_op<PF, NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
+                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
+                       mom, pad, pad / 16, abuf, os, oa);
+    LSPR_HIP(hipGetLastError());
+}
+
 template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (pad >= 16 * 8) {  // 8 column groups per operator: one operator per workgroup
+            const int nsm = (g.n_terms + 3) / 4;
+            const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);
+            const int pf = (abuf / 4 + 255) / 256;
+            LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the kernel");
+#define LSPR_FAR_OP(NSM_)                                                                    \
+    case NSM_:                                                                               \
+        if (pf <= 4) launch_far_tiles_op<4, NSM_>(g, pad, abuf, dens, mom, os, oa, s);       \
+        else if (pf <= 6) launch_far_tiles_op<6, NSM_>(g, pad, abuf, dens, mom, os, oa, s);  \
+        else launch_far_tiles_op<8, NSM_>(g, pad, abuf, dens, mom, os, oa, s);               \
+        return;
+            switch (nsm) {
+                LSPR_FAR_OP(3)
+                LSPR_FAR_OP(7)
+                LSPR_FAR_OP(13)
+                LSPR_FAR_OP(21)
+                LSPR_FAR_OP(31)
+                default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
+            }
+#undef LSPR_FAR_OP
+        }
+    }
     const int nwc = pad / 16;  // column groups (16 K and 16 V columns each)
     // FP32: 4-wave workgroups, two per CU (a chunk with more than 4 column groups is split
     // over two workgroups); FP64 left factors fill a CU's LDS, so one 8-wave workgroup per CU
     constexpr int NTHR = sizeof(T) == 4 ? 256 : 512;
     const int halves = nwc > NTHR / 64 ? 2 : 1;
     const int nsm = (g.n_terms + 3) / 4;
-    const int abuf = std::max(nsm * 256, 2 * 8 * 256);  // elements of the largest left factor
+    const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);  // elements of the largest left factor
     const int per16 = 16 / static_cast<int>(sizeof(T));
     const int pf = (abuf / per16 + NTHR - 1) / NTHR;  // 16-byte chunks per thread
     LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the matrix-core kernel");
@@ -908,11 +1084,12 @@ void build_tiles(Geometry& g) {
                 aoff += static_cast<int64_t>(nsm) * 256;
             }
             for (int e = pa; e < pb; ++e)
-                for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 32) {
+                for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 4 * DSTEPS) {
                     p2p_tile.push_back(static_cast<int32_t>(tiles.size()));
                     p2p_chunk.push_back(c);
-                    tiles.push_back(TileDesc{1, 8, aoff, p0, std::min(32, rng[e].end - p0)});
-                    aoff += 2 * 8 * 256;
+                    tiles.push_back(
+                        TileDesc{1, DSTEPS, aoff, p0, std::min(4 * DSTEPS, rng[e].end - p0)});
+                    aoff += 2 * DSTEPS * 256;
                 }
             if (phase == 0) tself[c] = static_cast<int32_t>(tiles.size()) - toff[c];
         }
