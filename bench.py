@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("treecode matvec Gpair/s; wavelength-solves/s at 1e-4 rel err vs FP64; p50/p99")
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X datasheet (packed FP32 FMA)
+PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X datasheet, dense FP32 matrix cores (measured sustained: 155)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -89,6 +89,60 @@ def cpu_baseline(w, n_rows=768, seed=0):
     }
 
 
+def serving_leg(lspr, n_requests, seed=5, max_slots=4, load=0.8):
+    """Request-serving leg: the first n_requests of the seeded Poisson stream (spheres of
+    2048-131072 panels with 0-4 analytes at 0.5-3 nm, 1-64 wavelengths each) through the
+    request server.  A burst (all submitted at once) gives the saturated throughput; then the
+    same requests arrive with the stream's own exponential gaps rescaled to `load` times that
+    rate, and the latency (completion - arrival) of each is recorded."""
+    from lspr_inputs import serving_stream
+    reqs = [w for _, w in serving_stream(seed=seed, n_requests=n_requests)]
+    gaps = np.diff([t for t, _ in serving_stream(seed=seed, n_requests=n_requests)], prepend=0.0)
+    sv = lspr.Server(max_slots=max_slots)
+
+    def submit(w):
+        return sv.submit(w.surfaces, w.lambdas, w.eps_medium, w.eps_surface, w.e_field,
+                         op=lspr.op_params(**w.op), gmres=lspr.gmres_params(**w.gmres))
+
+    try:
+        t0 = time.perf_counter()
+        burst = [sv.poll(t, wait=True) for t in [submit(w) for w in reqs]]
+        burst_s = time.perf_counter() - t0
+        burst_stats = sv.stats()
+        rate = load * len(reqs) / burst_s
+        arrive = np.cumsum(gaps) - gaps[0]
+        arrive *= (1.0 / rate) / max(np.mean(gaps), 1e-12)
+        start = time.perf_counter()
+        tickets = []
+        for k, w in enumerate(reqs):
+            while time.perf_counter() - start < arrive[k]:
+                time.sleep(0.0005)
+            tickets.append(submit(w))
+        paced = [sv.poll(t, wait=True) for t in tickets]
+        paced_stats = sv.stats()
+    finally:
+        sv.close()
+    lat = np.array([r["latency_s"] for r in paced])
+    ok = [r["status"] == lspr.LSPR_OK for r in burst]
+    n_ok_lambda = int(sum(r["n_lambda"] for r, good in zip(burst, ok) if good))
+    return {
+        "requests": len(reqs), "max_slots": max_slots,
+        "panels": {"min": int(min(r["n_panels"] for r in burst)),
+                   "max": int(max(r["n_panels"] for r in burst))},
+        "wavelengths": int(sum(r["n_lambda"] for r in burst)),
+        "converged": int(sum(ok)),
+        "burst_s": burst_s, "burst_requests_per_s": len(reqs) / burst_s,
+        "burst_wavelength_solves_per_s": n_ok_lambda / burst_s,
+        "max_concurrent": int(burst_stats["max_active"]),
+        "paced_rate_requests_per_s": rate,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "estimate_violations": int(paced_stats["estimate_violations"]),
+        "precision": reqs[0].op["precision"],
+    }
+
+
 def traffic_entry(kernel_file, name):
     """HBM bytes per launch from rocprofv3 counter runs, valid only for the same kernel source."""
     path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")  # written from rocprofv3 --pmc runs
@@ -113,6 +167,8 @@ def main():
                     help="inner tolerance of fp32_refine64 (default: the library's)")
     ap.add_argument("--tol", type=float, default=None, help="override the GMRES tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=16,
+                    help="requests of the serving leg (0 skips it)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference solve and the one-at-a-time FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -217,9 +273,10 @@ def main():
     far = prof["far"]
     achieved = far["flops"] / (far["total_ms"] * 1e-3) / 1e12 if far["total_ms"] > 0 else 0.0
     trec = traffic_entry(os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"), "far")
-    roofline = {"kernel": "k_far (expansions + direct far-rule sums, FP32)", "bound": "alu",
-                "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+    roofline = {"kernel": "k_far_tiles_op (FP32 matrix-core far field: expansion and direct "
+                          "far-rule tiles)", "bound": "mfma",
+                "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
                 "traffic": (trec["bytes_per_launch"] if trec else None),
                 "launches": far["launches"],
                 "avg_launch_ms": far["total_ms"] / max(far["launches"], 1),
@@ -233,15 +290,16 @@ def main():
         "config": {"workload": w.name, "panels": w.n_panels, "wavelengths": int(len(lam)),
                    "method": op["method"], "p": op["p"], "theta": op["theta"],
                    "k_far": op["k_far"], "k_fine": op["k_fine"], "n_k": op["n_k"],
-                   "threshold": op["threshold"], "kernels": "fp32", "gmres": "fp64",
+                   "threshold": op["threshold"], "kernels": op["precision"], "gmres": "fp64",
                    "gmres_tol": gm["tol"], "parallelism": "single GPU"},
         # (direct target-node pairs + expansion target-box pairs) x wavelengths per second of
         # the far-field kernel
         "matvec_gpair_per_s": far["items"] / (far["total_ms"] * 1e-3) / 1e9
         if far["total_ms"] > 0 else None,
         "matvec_launches_per_step": n_matvec / args.steps,
-        "latency_p50_s": float(np.percentile(times_s, 50)),
-        "latency_p99_s": float(np.percentile(times_s, 99)),
+        "step_latency_p50_s": float(np.percentile(times_s, 50)),
+        "step_latency_p99_s": float(np.percentile(times_s, 99)),
+        "latency_p50_s": None, "latency_p99_s": None, "serving": None,
         "roofline": roofline,
         "cpu_baseline": None,
         "accuracy": accuracy,
@@ -254,6 +312,15 @@ def main():
         "lists": {k: int(info[k]) for k in ("n_boxes", "n_m2p", "n_p2p_ranges", "p2p_pairs",
                                             "m2p_pairs", "n_near", "n_terms", "ncrit")},
     }
+    if args.serving_requests > 0:
+        log(f"[bench] serving leg: {args.serving_requests} requests ...")
+        srv = serving_leg(lspr, args.serving_requests)
+        line["serving"] = srv
+        line["latency_p50_s"] = srv["latency_p50_s"]
+        line["latency_p99_s"] = srv["latency_p99_s"]
+        log(f"[bench] serving: burst {srv['burst_requests_per_s']:.2f} req/s, p50 "
+            f"{srv['latency_p50_s']:.2f} s, p99 {srv['latency_p99_s']:.2f} s at "
+            f"{srv['paced_rate_requests_per_s']:.2f} req/s")
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(w)

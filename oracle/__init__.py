@@ -27,13 +27,13 @@ from .quadrature import triangle_rule, gauss_legendre, RULE_DEGREE
 from .geometry import panel_geometry, quadrature_nodes
 from .operators import (singular_v_semianalytic, singular_v_closed_form, operator_rows,
                         dense_operators, near_singular_mask)
-from .system import assemble_system, solve_lu, gmres, solve
+from .system import assemble_system, system_rows, solve_lu, gmres, solve
 from .dipole import exterior_traces, dipole_moment, extinction_cross_section
 from .analytic import cext_sphere_analytic
 
 __all__ = [
     "triangle_rule", "gauss_legendre", "RULE_DEGREE", "panel_geometry", "quadrature_nodes",
     "singular_v_semianalytic", "singular_v_closed_form", "operator_rows", "dense_operators",
-    "near_singular_mask", "assemble_system", "solve_lu", "gmres", "solve", "exterior_traces",
-    "dipole_moment", "extinction_cross_section", "cext_sphere_analytic",
+    "near_singular_mask", "assemble_system", "system_rows", "solve_lu", "gmres", "solve",
+    "exterior_traces", "dipole_moment", "extinction_cross_section", "cext_sphere_analytic",
 ]

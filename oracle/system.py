@@ -41,6 +41,27 @@ def assemble_system(V, K, surf_id, normals, eps_m, eps_surf, e_field):
     return A, b
 
 
+def system_rows(V_rows, K_rows, rows, surf_id, eps_m, eps_surf):
+    """Rows of A (Eq. matrix_multi) for the targets `rows`: interior rows [M, 2N] and exterior
+    rows [M, 2N], from the same rows of V and K ([M, N] each).  The same entries as
+    assemble_system, for targets of a mesh too large to assemble densely."""
+    surf_id = np.asarray(surf_id)
+    rows = np.asarray(rows)
+    N = len(surf_id)
+    M = len(rows)
+    same = surf_id[rows][:, None] == surf_id[None, :]
+    eps_panel = np.asarray(eps_surf)[surf_id]
+    unit = np.zeros((M, N))
+    unit[np.arange(M), rows] = 1.0
+    interior = np.zeros((M, 2 * N), dtype=np.complex128)
+    interior[:, :N] = np.where(same, 0.5 * unit + K_rows, 0.0)
+    interior[:, N:] = np.where(same, -V_rows, 0.0)
+    exterior = np.zeros((M, 2 * N), dtype=np.complex128)
+    exterior[:, :N] = 0.5 * unit - K_rows
+    exterior[:, N:] = V_rows * (eps_panel / eps_m)[None, :]
+    return interior, exterior
+
+
 def solve_lu(A, b):
     """Direct solve by LU with partial pivoting (LAPACK through numpy)."""
     return np.linalg.solve(A, b)

@@ -309,3 +309,21 @@ def test_index_matched_analyte_is_nearly_invisible():
     matched = _solve_one(v, t, sid, [0, 0, 1.0], [-3.38 + 0.2j, em])["cext_sensor"][0]
     loaded = _solve_one(v, t, sid, [0, 0, 1.0], [-3.38 + 0.2j, 2.5 + 0j])["cext_sensor"][0]
     assert abs(matched / iso - 1) < 0.2 * abs(loaded / iso - 1)
+
+
+def test_system_rows_are_rows_of_the_assembled_system():
+    """The row-subset form of Eq. matrix_multi used for sampled parity at full size equals the
+    dense assembly (itself pinned by the solves above) on a two-surface mesh."""
+    rng = np.random.default_rng(4)
+    s = octasphere(4, 8.0)
+    bv, bt = octasphere(3, 3.0)
+    surfs = [s, (bv + np.array([0.0, 0.0, 12.0]), bt)]
+    v, t, sid = merge_surfaces(surfs)
+    V, K = oracle.dense_operators(v, t, 4, 19, 9, 0.5)
+    g = oracle.panel_geometry(v, t)
+    eps_m, eps_s = 1.7733 + 0.01j, np.array([-3.4 + 0.2j, 2.5 + 0.1j])
+    A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m, eps_s, [0, 0, 1.0])
+    rows = rng.choice(len(t), 17, replace=False)
+    inner, outer = oracle.system_rows(V[rows], K[rows], rows, sid, eps_m, eps_s)
+    N = len(t)
+    assert np.array_equal(inner, A[rows]) and np.array_equal(outer, A[N + rows])
