@@ -90,8 +90,10 @@ typedef struct {
  *   flags     bit 0: never use the matrix-core far-field kernel.  By default a geometry
  *             precomputes the geometry-only factors of every expansion and direct tile in the
  *             precision(s) it computes in (about 1.7 GB at 32768 panels, P = 8, in FP32; twice
- *             that in FP64) and runs all products on matrix cores; above 64 GB of tiles it falls
- *             back to the vector-ALU kernel, which computes the same sums on the fly. */
+ *             that in FP64) and runs all products on matrix cores.  Tiles are kept while they
+ *             fit in 40 % of the free device memory (FP32 first, then FP64); a precision whose
+ *             tiles do not fit uses the vector-ALU kernel, which computes the same sums on the
+ *             fly. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;

@@ -199,6 +199,11 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
                            hipMemcpyHostToDevice, g.stream);
     }
     lspr::build_near_table(g);
+    if (g.tile_budget_bytes <= 0.0) {
+        size_t free_b = 0, total_b = 0;
+        LSPR_HIP(hipMemGetInfo(&free_b, &total_b));
+        g.tile_budget_bytes = 0.4 * static_cast<double>(free_b);
+    }
     if (g.allow_mfma) lspr::build_tiles(g);
     lspr::precompute_rhs(g);
 }

@@ -226,7 +226,7 @@ struct Geometry {
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
-    double tile_budget_bytes = 64e9;  // largest tile store kept per geometry
+    double tile_budget_bytes = 0.0;  // largest tile store kept (0: 40 % of free device memory)
 
     size_t device_bytes() const;
 };

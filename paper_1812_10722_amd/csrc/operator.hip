@@ -1113,10 +1113,14 @@ void build_tiles(Geometry& g) {
                          [&](int32_t a, int32_t b) { return csteps[a] > csteps[b]; });
         for (size_t i = 0; i < run.size(); ++i) order[i * 8 + x] = run[i];
     }
-    const double esz = (g.need32 ? 4.0 : 0.0) + (g.need64 ? 8.0 : 0.0);
-    if (static_cast<double>(aoff) * esz > g.tile_budget_bytes) {
-        // too large to keep (e.g. a dense product on a big mesh): keep the on-the-fly kernel
-        g.allow_mfma = false;
+    // Tile stores within the budget: FP32 first (the GMRES products of the FP32 and refinement
+    // modes), then FP64 with what is left.  A precision without tiles keeps the on-the-fly
+    // vector-ALU kernel (e.g. a dense product on a big mesh).
+    double left = g.tile_budget_bytes;
+    const bool keep32 = g.need32 && static_cast<double>(aoff) * 4.0 <= left;
+    if (keep32) left -= static_cast<double>(aoff) * 4.0;
+    const bool keep64 = g.need64 && static_cast<double>(aoff) * 8.0 <= left;
+    if (!keep32 && !keep64) {
         g.n_tiles = 0;
         return;
     }
@@ -1135,11 +1139,11 @@ void build_tiles(Geometry& g) {
     copy_sync(mc.p, m2p_chunk.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
     copy_sync(pt.p, p2p_tile.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
     copy_sync(pc.p, p2p_chunk.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
-    if (g.need32) {
+    if (keep32) {
         g.tileA.alloc(std::max<int64_t>(aoff, 1));
         build_tiles_t<float>(g, g.tileA.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
     }
-    if (g.need64) {
+    if (keep64) {
         g.tileA64.alloc(std::max<int64_t>(aoff, 1));
         build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
     }
