@@ -53,7 +53,7 @@ enum lspr_status {
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
 enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2 };
-enum lspr_flags { LSPR_NO_MATRIX_CORES = 1 };
+enum lspr_flags { LSPR_NO_MATRIX_CORES = 1, LSPR_NO_SPLIT_OPERATORS = 2 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
  * counter-clockwise seen from outside (outward right-hand normal, as the paper's dipole
@@ -93,7 +93,9 @@ typedef struct {
  *             that in FP64) and runs all products on matrix cores.  Tiles are kept while they
  *             fit in 40 % of the free device memory (FP32 first, then FP64); a precision whose
  *             tiles do not fit uses the vector-ALU kernel, which computes the same sums on the
- *             fly. */
+ *             fly.
+ *             bit 1: FP32 matrix-core products keep both operators in one workgroup instead of
+ *             one workgroup per operator (same sums; a tuning alternative). */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;

@@ -150,6 +150,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.n_terms = lspr::expansion_terms(g.P);
     g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
     g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
+    if (op->flags & LSPR_NO_SPLIT_OPERATORS) g.far_op_min_pad = 0;
     lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);

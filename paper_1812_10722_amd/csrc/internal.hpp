@@ -226,6 +226,8 @@ struct Geometry {
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
+    int far_op_min_pad = 16;  // FP32 products with at least this many columns per operator run
+                              // one operator per workgroup (0: never)
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 40 % of free device memory)
 
     size_t device_bytes() const;

@@ -568,10 +568,10 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
         }
 }
 
-// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, b + 16, b + 24 handle one
-// chunk (all on the same XCD, so the later ones read the chunk's left factors from L2): the
-// double-layer (K) and single-layer (V) columns, each in two halves of 4 column groups of 16,
-// one group per wave.  Per wave this needs far fewer registers than a K-and-V wave, so three
+// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, ... handle one chunk (all on
+// the same XCD, so the later ones read the chunk's left factors from L2): the double-layer (K)
+// and single-layer (V) columns, each in 1 or 2 halves of 4 column groups of 16, one group per
+// wave.  Per wave this needs far fewer registers than a K-and-V wave, so three
 // independent workgroups share each CU and hide each other's latencies.
 // Expansion tiles share one left factor between the operators; direct tiles hold the K factor
 // and then the V factor.
@@ -586,17 +586,20 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
                const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
-               int abuf_elems, double* __restrict__ out_self, double* __restrict__ out_all) {
+               int halves, int abuf_elems, double* __restrict__ out_self,
+               double* __restrict__ out_all) {
     constexpr int NTHR = 256;
     extern __shared__ float4 abuf16[];  // [2][abuf_elems / 4]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, grp = lane >> 4;
     const int ncols = 2 * pad;
+    // 2 * halves workgroups per chunk, at b, b + 8, ...: operator j & 1, column half j >> 1
     const int b = blockIdx.x;
-    const int j = (b >> 3) & 3;
+    const int per = 2 * halves;
+    const int j = (b >> 3) % per;
     const int opr = j & 1;                  // 0: K columns, 1: V columns
     const int wg = wave + 4 * (j >> 1);     // column group of this wave
-    const int chunk = chunk_order[((b >> 5) << 3) + (b & 7)];
+    const int chunk = chunk_order[(b >> 3) / per * 8 + (b & 7)];
     if (chunk < 0) return;
     const Chunk C = chunks[chunk];
     const int ntg = C.end - C.start;
@@ -882,11 +885,12 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
 template <int PF, int NSM>
 void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
                          double* os, double* oa, hipStream_t s) {
-    const int nblk = (g.n_chunks + 7) / 8 * 8 * 4;
+    const int halves = pad > 64 ? 2 : 1;
+    const int nblk = (g.n_chunks + 7) / 8 * 8 * 2 * halves;
     const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(float);
     hipLaunchKernelGGL((k_far_tiles_op<PF, NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
                        g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
-                       mom, pad, pad / 16, abuf, os, oa);
+                       mom, pad, pad / 16, halves, abuf, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
@@ -894,7 +898,7 @@ template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
-        if (pad >= 16 * 8) {  // 8 column groups per operator: one operator per workgroup
+        if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
             const int nsm = (g.n_terms + 3) / 4;
             const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);
             const int pf = (abuf / 4 + 255) / 256;
