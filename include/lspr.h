@@ -304,6 +304,16 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
                            const lspr_op_params* op, const lspr_gmres_params* gm,
                            int64_t* bytes);
 
+/* Resonance peak of a sampled extinction spectrum (the quantity a plasmonic sensor reads: the
+ * peak position and its shift when analytes bind, section "Results", sensing experiments).
+ * lambda host [n] strictly increasing, cext host [n], n >= 3.  The peak is the vertex of the
+ * parabola through the largest sample and its two neighbours (exact for a parabola; on a
+ * non-uniform grid the parabola is fitted exactly through the three points).  A maximum at
+ * either end of the grid returns that end point.  *peak_lambda and *peak_cext receive the
+ * vertex.  LSPR_E_INVALID for n < 3, null pointers or a grid that is not increasing. */
+int lspr_resonance_peak(int32_t n, const double* lambda, const double* cext,
+                        double* peak_lambda, double* peak_cext);
+
 const char* lspr_status_string(int code);
 const char* lspr_last_error(void);
 

@@ -321,7 +321,7 @@ size_t lspr::Geometry::device_bytes() const {
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
-           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
+           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 
@@ -360,6 +360,41 @@ int lspr_gauss_legendre(int32_t n, double* t, double* w) {
         lspr::gauss_legendre(n, a, b);
         std::copy(a.begin(), a.end(), t);
         std::copy(b.begin(), b.end(), w);
+        return LSPR_OK;
+    });
+}
+
+int lspr_resonance_peak(int32_t n, const double* lambda, const double* cext,
+                        double* peak_lambda, double* peak_cext) {
+    return guarded([&] {
+        LSPR_REQUIRE(n >= 3 && lambda && cext && peak_lambda && peak_cext, LSPR_E_INVALID,
+                     "need at least three samples and non-null pointers");
+        for (int k = 1; k < n; ++k)
+            LSPR_REQUIRE(lambda[k] > lambda[k - 1], LSPR_E_INVALID,
+                         "wavelengths must be strictly increasing");
+        int m = 0;
+        for (int k = 1; k < n; ++k)
+            if (cext[k] > cext[m]) m = k;
+        if (m == 0 || m == n - 1) {
+            *peak_lambda = lambda[m];
+            *peak_cext = cext[m];
+            return LSPR_OK;
+        }
+        // parabola c(x) = y1 + a (x - x1) + b (x - x1)^2 through (x0, y0), (x1, y1), (x2, y2)
+        const double x0 = lambda[m - 1], x1 = lambda[m], x2 = lambda[m + 1];
+        const double y0 = cext[m - 1], y1 = cext[m], y2 = cext[m + 1];
+        const double h0 = x0 - x1, h2 = x2 - x1;
+        const double s0 = (y0 - y1) / h0, s2 = (y2 - y1) / h2;  // secant slopes
+        const double b = (s2 - s0) / (h2 - h0);
+        const double a = s0 - b * h0;
+        if (!(b < 0.0)) {  // flat or convex around the sample: keep the sample
+            *peak_lambda = x1;
+            *peak_cext = y1;
+            return LSPR_OK;
+        }
+        const double dx = -a / (2.0 * b);
+        *peak_lambda = x1 + dx;
+        *peak_cext = y1 + a * dx + b * dx * dx;
         return LSPR_OK;
     });
 }

@@ -708,6 +708,111 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     write_sums(out_all);
 }
 
+// ------------------------------------------------------------------------------- P2M, MFMA
+// The folded moments of an expanded box are linear in the densities of its panels with
+// geometry-only weights: M[term][col] = sum_j A[term][j] dens[j][col], A[term][j] the folded
+// node polynomial of panel j (V polynomial for the V columns, K polynomial for the K columns).
+// k_build_p2m_tiles stores A once per geometry, segment by segment (P2MSeg: at most 128 panels
+// of one box), as [step][row tile][lane] with step = 4 panels and lane l holding
+// A[16 rt + l % 16][4 step + l / 16] (the v_mfma_f32_16x16x4f32 operand order); the K block of a
+// segment follows its V block.  k_p2m_mfma then forms each segment's moments on matrix cores.
+template <int P>
+constexpr int p2m_row_tiles() { return (Expansion<P>::NR + 15) / 16; }
+
+template <int P>
+__global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
+                                  const int64_t* __restrict__ aoff, const double* __restrict__ cen,
+                                  const float* __restrict__ src, int K, float* __restrict__ A) {
+    using E = Expansion<P>;
+    constexpr E ex{};
+    constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
+    const P2MSeg sg = segs[blockIdx.x];
+    const int j = sg.start + static_cast<int>(threadIdx.x);
+    if (j >= sg.end) return;
+    const Box B = boxes[sg.box];
+    const int rs = 4 + 4 * K;
+    const float* r = src + static_cast<size_t>(j) * rs;
+    double pv[NF], pk[NF];
+    for (int t = 0; t < NF; ++t) pv[t] = pk[t] = 0.0;
+    for (int gq = 0; gq < K; ++gq) {
+        const double d[3] = {cen[3 * j] - B.cx + r[4 + 4 * gq], cen[3 * j + 1] - B.cy + r[5 + 4 * gq],
+                             cen[3 * j + 2] - B.cz + r[6 + 4 * gq]};
+        const double w = r[7 + 4 * gq];
+        double pw[3][P + 1];
+        for (int a = 0; a < 3; ++a) {
+            pw[a][0] = 1.0;
+            for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
+        }
+        for (int t = 0; t < NF; ++t) {
+            const int kx = ex.fx[t], ky = ex.fy[t], kz = ex.fz[t];
+            const double X = pw[0][kx], Y = pw[1][ky], Z = pw[2][kz];
+            pv[t] += w * X * Y * Z;
+            double gs = 0.0;
+            if (kx > 0) gs += r[0] * kx * pw[0][kx - 1] * Y * Z;
+            if (ky > 0) gs += r[1] * ky * X * pw[1][ky - 1] * Z;
+            if (kz > 0) gs += r[2] * kz * X * Y * pw[2][kz - 1];
+            pk[t] += w * gs;
+        }
+    }
+    // fold the kz >= 2 terms onto kz <= 1, as the moments themselves are folded
+    for (int f = 0; f < E::NFOLD; ++f) {
+        pv[ex.fdx[f]] += ex.fcx[f] * pv[ex.fsrc[f]];
+        pv[ex.fdy[f]] += ex.fcy[f] * pv[ex.fsrc[f]];
+        pk[ex.fdx[f]] += ex.fcx[f] * pk[ex.fsrc[f]];
+        pk[ex.fdy[f]] += ex.fcy[f] * pk[ex.fsrc[f]];
+    }
+    const int p = j - sg.start, st = p >> 2, kk = p & 3;
+    const int steps = (sg.end - sg.start + 3) / 4;
+    float* AV = A + aoff[blockIdx.x];
+    float* AK = AV + static_cast<size_t>(steps) * RT * 64;
+    for (int q = 0; q < NR; ++q) {
+        const int rt = q >> 4, lane = (q & 15) + 16 * kk;
+        const size_t idx = (static_cast<size_t>(st) * RT + rt) * 64 + lane;
+        AV[idx] = static_cast<float>(pv[ex.rfull[q]]);
+        AK[idx] = static_cast<float>(pk[ex.rfull[q]]);
+    }
+}
+
+// Workgroup = (segment, operator, column half): 4 waves, each 16 columns of one operator.
+template <int RT, int NR>
+__global__ void __launch_bounds__(256)
+k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
+           const float* __restrict__ A, const float* __restrict__ dens, int pad, int nwc,
+           float* __restrict__ mom, float* __restrict__ part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int opr = blockIdx.y & 1, wg = wave + 4 * (blockIdx.y >> 1);
+    if (wg >= nwc) return;
+    const int ncols = 2 * pad;
+    const int col = opr * pad + 16 * wg + c16;
+    const P2MSeg sg = segs[blockIdx.x];
+    const int np = sg.end - sg.start, steps = (np + 3) / 4;
+    const float* Ab = A + aoff[blockIdx.x] + (opr == 0 ? static_cast<size_t>(steps) * RT * 64 : 0);
+    const float* Db = dens + static_cast<size_t>(sg.start) * ncols + col;
+    v4f acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int st = 0; st < steps; ++st) {
+        const int p = 4 * st + grp;
+        const float b = Db[static_cast<size_t>(p < np ? p : 0) * ncols];
+        const float bb = p < np ? b : 0.f;
+        const float* a = Ab + static_cast<size_t>(st) * RT * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t * 64], bb, acc[t], 0, 0, 0);
+    }
+    float* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * NR * ncols
+                             : part + static_cast<size_t>(sg.slot) * NR * ncols;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = 16 * t + 4 * grp + i;
+            if (q < NR) out[static_cast<size_t>(q) * ncols + col] = acc[t][i];
+        }
+}
+
 // ---- geometry-only tiles for k_far_tiles (built once per geometry)
 // Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
 template <class T, int P>
@@ -952,6 +1057,67 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
 #undef LSPR_FAR_TILES
 }
 
+template <int P>
+void launch_p2m_mfma(Geometry& g, int pad, const float* dens, float* mom, hipStream_t s) {
+    if (g.n_seg == 0) return;
+    constexpr int NR = Expansion<P>::NR, RT = p2m_row_tiles<P>();
+    const int ncols = 2 * pad;
+    float* part = nullptr;
+    if (g.n_slots > 0) {
+        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * NR * ncols * sizeof(float));
+        part = reinterpret_cast<float*>(g.ws_part.p);
+    }
+    const int halves = pad > 64 ? 2 : 1;
+    hipLaunchKernelGGL((k_p2m_mfma<RT, NR>), dim3(g.n_seg, 2 * halves), dim3(256), 0, s,
+                       g.p2m_seg.p, g.p2m_aoff.p, g.p2mA.p, dens, pad, pad / 16, mom, part);
+    LSPR_HIP(hipGetLastError());
+    if (g.n_red > 0) {
+        const int64_t tot = static_cast<int64_t>(g.n_red) * NR * ncols;
+        hipLaunchKernelGGL(k_p2m_reduce<float>, dim3((tot + 255) / 256), dim3(256), 0, s,
+                           g.p2m_red.p, g.n_red, NR, ncols, part, mom);
+        LSPR_HIP(hipGetLastError());
+    }
+}
+
+// Moments on matrix cores when the geometry holds FP32 polynomial tiles; false otherwise.
+inline bool launch_p2m_tiles(Geometry& g, const Cols& c, const double*, double*, hipStream_t) {
+    return false;
+}
+inline bool launch_p2m_tiles(Geometry& g, const Cols& c, const float* dens, float* mom,
+                             hipStream_t s) {
+    if (!c.mfma || g.p2mA.p == nullptr) return false;
+    switch (g.P) {
+        case 2: launch_p2m_mfma<2>(g, c.pad, dens, mom, s); break;
+        case 4: launch_p2m_mfma<4>(g, c.pad, dens, mom, s); break;
+        case 6: launch_p2m_mfma<6>(g, c.pad, dens, mom, s); break;
+        case 8: launch_p2m_mfma<8>(g, c.pad, dens, mom, s); break;
+        case 10: launch_p2m_mfma<10>(g, c.pad, dens, mom, s); break;
+        default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+    }
+    return true;
+}
+
+template <int P>
+void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
+    constexpr int RT = p2m_row_tiles<P>();
+    std::vector<P2MSeg> segs(g.n_seg);
+    copy_sync(segs.data(), g.p2m_seg.p, segs.size() * sizeof(P2MSeg), hipMemcpyDeviceToHost, s);
+    std::vector<int64_t> off(g.n_seg);
+    int64_t tot = 0;
+    for (int k = 0; k < g.n_seg; ++k) {
+        off[k] = tot;
+        tot += 2ll * ((segs[k].end - segs[k].start + 3) / 4) * RT * 64;
+    }
+    g.p2m_aoff.alloc(g.n_seg);
+    copy_sync(g.p2m_aoff.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    g.p2mA.alloc(std::max<int64_t>(tot, 1));
+    LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s));
+    hipLaunchKernelGGL(k_build_p2m_tiles<P>, dim3(g.n_seg), dim3(128), 0, s, g.boxes.p,
+                       g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K, g.p2mA.p);
+    LSPR_HIP(hipGetLastError());
+    LSPR_HIP(hipStreamSynchronize(s));
+}
+
 template <class T, int CPT>
 void launch_far_cpt(Geometry& g, int pad, const T* dens, const T* mom, double* os, double* oa,
                     hipStream_t s) {
@@ -987,13 +1153,15 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
         prof::Scope sc(fp64 ? "p2m64" : "p2m", s,
                        double(g.mom_panels) * (8.0 * g.K * NF + 2.0 * NF * 2 * nc),
                        double(g.mom_panels) * 2 * c.pad * esz + mom_bytes);
-        switch (g.P) {
-            case 2: launch_p2m_p<T, 2>(g, c.pad, dens, mom, s); break;
-            case 4: launch_p2m_p<T, 4>(g, c.pad, dens, mom, s); break;
-            case 6: launch_p2m_p<T, 6>(g, c.pad, dens, mom, s); break;
-            case 8: launch_p2m_p<T, 8>(g, c.pad, dens, mom, s); break;
-            case 10: launch_p2m_p<T, 10>(g, c.pad, dens, mom, s); break;
-            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        if (!launch_p2m_tiles(g, c, dens, mom, s)) {
+            switch (g.P) {
+                case 2: launch_p2m_p<T, 2>(g, c.pad, dens, mom, s); break;
+                case 4: launch_p2m_p<T, 4>(g, c.pad, dens, mom, s); break;
+                case 6: launch_p2m_p<T, 6>(g, c.pad, dens, mom, s); break;
+                case 8: launch_p2m_p<T, 8>(g, c.pad, dens, mom, s); break;
+                case 10: launch_p2m_p<T, 10>(g, c.pad, dens, mom, s); break;
+                default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+            }
         }
     }
     {
@@ -1152,6 +1320,16 @@ void build_tiles(Geometry& g) {
         build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
     }
     LSPR_HIP(hipStreamSynchronize(s));
+    if (keep32 && g.n_seg > 0) {  // moments on matrix cores as well
+        switch (g.P) {
+            case 2: build_p2m_tiles_p<2>(g, s); break;
+            case 4: build_p2m_tiles_p<4>(g, s); break;
+            case 6: build_p2m_tiles_p<6>(g, s); break;
+            case 8: build_p2m_tiles_p<8>(g, s); break;
+            case 10: build_p2m_tiles_p<10>(g, s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        }
+    }
 }
 
 Cols make_cols(const Geometry& g, int ncol, int prec) {

@@ -68,6 +68,7 @@ def _load():
         "lspr_rhs": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), P(dbl), vp, vp]),
         "lspr_triangle_rule": (C.c_int, [i32, P(dbl), P(dbl)]),
         "lspr_gauss_legendre": (C.c_int, [i32, P(dbl), P(dbl)]),
+        "lspr_resonance_peak": (C.c_int, [i32, P(dbl), P(dbl), P(dbl), P(dbl)]),
         "lspr_status_string": (C.c_char_p, [C.c_int]),
         "lspr_last_error": (C.c_char_p, []),
     }
@@ -116,6 +117,16 @@ def lspr_gauss_legendre(n: int):
     w = np.zeros(n)
     _check(_lib.lspr_gauss_legendre(n, _dptr(t), _dptr(w)), "lspr_gauss_legendre")
     return t, w
+
+
+def lspr_resonance_peak(lambdas, cext):
+    """(peak wavelength, peak C_ext) of a sampled spectrum (parabola through the maximum)."""
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    c = np.ascontiguousarray(cext, dtype=np.float64)
+    pl, pc = C.c_double(), C.c_double()
+    _check(_lib.lspr_resonance_peak(len(lam), _dptr(lam), _dptr(c), C.byref(pl), C.byref(pc)),
+           "lspr_resonance_peak")
+    return pl.value, pc.value
 
 
 def lspr_mesh_validate(surfaces):

@@ -79,3 +79,42 @@ def test_status_strings():
     from paper_1812_10722_amd import lspr
     for code in range(7):
         assert lspr._lib.lspr_status_string(code)
+
+
+# ----------------------------------------------------------------------------- resonance peak
+@pytest.fixture
+def lib():
+    from paper_1812_10722_amd import lspr
+    return lspr
+
+
+def test_resonance_peak_is_exact_for_a_parabola(lib):
+    x = np.array([370.0, 374.5, 377.0, 381.2, 386.0, 392.0])
+    y = 5000.0 - 3.0 * (x - 378.3) ** 2
+    pl, pc = lib.lspr_resonance_peak(x, y)
+    assert abs(pl - 378.3) < 1e-9 and abs(pc - 5000.0) < 1e-6
+
+
+def test_resonance_peak_of_the_analytic_sphere():
+    """On a 2 nm grid the parabola vertex lands within 0.1 nm of the analytic peak (Eq. an_sol
+    evaluated on a 0.001 nm grid); the raw grid maximum can be off by up to 1 nm."""
+    from paper_1812_10722_amd import lspr
+    import oracle
+    from lspr_inputs import eps_silver_drude, EPS_WATER
+    fine = np.arange(370.0, 400.0, 0.001)
+    ref = fine[np.argmax(oracle.cext_sphere_analytic(10.0, fine, eps_silver_drude(fine),
+                                                      EPS_WATER))]
+    grid = np.arange(371.0, 399.0, 2.0)
+    c = oracle.cext_sphere_analytic(10.0, grid, eps_silver_drude(grid), EPS_WATER)
+    pl, _ = lspr.lspr_resonance_peak(grid, c)
+    assert abs(pl - ref) < 0.1, (pl, ref)
+
+
+def test_resonance_peak_edges_and_errors(lib):
+    x = np.array([1.0, 2.0, 3.0, 4.0])
+    assert lib.lspr_resonance_peak(x, np.array([4.0, 3.0, 2.0, 1.0])) == (1.0, 4.0)
+    assert lib.lspr_resonance_peak(x, np.array([1.0, 2.0, 3.0, 5.0])) == (4.0, 5.0)
+    with pytest.raises(lib.LsprError):
+        lib.lspr_resonance_peak(x[::-1], np.ones(4))
+    with pytest.raises(lib.LsprError):
+        lib.lspr_resonance_peak(x[:2], np.ones(2))
