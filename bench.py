@@ -155,6 +155,66 @@ def traffic_entry(kernel_file, name):
     return rec
 
 
+def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
+    """Turn two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, each over a run with
+    --copy-calibration) into the traffic record of the far-field kernel.  The counters are in KiB
+    per dispatch; each is scaled by what it reads for a kernel of known traffic in the same run
+    (the 256 MiB fill writes 256 MiB; the 256 MiB elementwise multiply reads 256 MiB)."""
+    import collections
+    import csv
+
+    def load(path, counter):
+        rows = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                rows[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return rows
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    known_kib = 256.0 * 1024.0
+
+    def only(rows, tag):
+        hits = [v for k, v in rows.items() if tag in k]
+        if len(hits) != 1 or len(hits[0]) != 1:
+            raise SystemExit(f"calibration kernel {tag!r} not found exactly once")
+        return hits[0][0]
+
+    fetch_scale = known_kib / only(fetch, "AUnaryFunctor")
+    write_scale = known_kib / only(write, "FillFunctor")
+    per, total_b, total_n = {}, 0.0, 0
+    for k in sorted(fetch):
+        if "k_far_tiles" not in k:
+            continue
+        f, wr = fetch[k], write.get(k, [])
+        if len(f) != len(wr):
+            raise SystemExit(f"dispatch counts differ between the passes for {k}")
+        b = [fv * 1024 * fetch_scale + wv * 1024 * write_scale for fv, wv in zip(f, wr)]
+        short = k.split("::")[-1].split("(")[0]
+        per[short] = {"dispatches": len(f), "fetch_kib_raw_mean": float(np.mean(f)),
+                      "write_kib_raw_mean": float(np.mean(wr)),
+                      "bytes_scaled_mean": float(np.mean(b))}
+        total_b += sum(b)
+        total_n += len(b)
+    if not total_n:
+        raise SystemExit("no far-field dispatches in the counter files")
+    rec = {"kernel": "k_far_tiles_op", "workload": workload,
+           "source_sha256": hashlib.sha256(open(kernel_file, "rb").read()).hexdigest(),
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "bytes_per_launch": total_b / total_n, "per_instance": per}
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"FETCH_SIZE x {fetch_scale:.3f}, WRITE_SIZE x {write_scale:.3f}")
+    print("| instance | dispatches | FETCH_SIZE KiB (raw mean) | WRITE_SIZE KiB (raw mean) | "
+          "scaled bytes per launch |")
+    print("|---|---:|---:|---:|---:|")
+    for k, v in per.items():
+        print(f"| `{k}` | {v['dispatches']} | {v['fetch_kib_raw_mean']:.0f} | "
+              f"{v['write_kib_raw_mean']:.0f} | {v['bytes_scaled_mean'] / 1e9:.3f} GB |")
+    print(f"Average over all far-field launches: {rec['bytes_per_launch'] / 1e9:.3f} GB; "
+          f"written {path}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,7 +234,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device-to-device copy of 256 MiB (a kernel of known "
                          "traffic, used to scale hardware byte counters)")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: write the far-field traffic record from two rocprofv3 "
+                         "counter files (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        from lspr_inputs import workload
+        record_traffic(*args.traffic_record,
+                       os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"), "far",
+                       workload(args.workload).name)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the build targets a "
               "single MI355X; a multi-GPU split by wavelength is described in DESIGN.md but not "

@@ -280,7 +280,9 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
     int64_t b = 0;
     b += static_cast<int64_t>(B) * m1 * nvec * 16;                 // Krylov basis
     b += static_cast<int64_t>(B) * nvec * 16 * (gm.precond ? 4 : 3);  // x, w, b (, z)
-    b += static_cast<int64_t>(B) * m1 * nblk * 16 + 64 * B * m1 * 16;  // partial dots, H
+    // partial inner products (one per wave of each block), Hessenberg matrices, coefficients
+    b += static_cast<int64_t>(B) * (2 * m1 + 3) * 4 * nblk * 16;
+    b += 2 * static_cast<int64_t>(B) * m1 * m1 * 16 + static_cast<int64_t>(B) * (8 * m1 + 64) * 16;
     if (op.precision == LSPR_FP32_REFINE64)
         b += static_cast<int64_t>(B) * nvec * 16 * 4;              // refinement b, r, d, w
     b += N * 2 * pad * esz;                                        // packed densities

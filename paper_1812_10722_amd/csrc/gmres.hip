@@ -2,13 +2,28 @@
 // the solver accepts complex numbers; the paper fixes only tolerances, Tables 2 and 5).
 //
 // Every wavelength has its own Krylov space; all running wavelengths share each block
-// matrix-vector product.  The Arnoldi process runs on the device: classical Gram-Schmidt with
-// one re-orthogonalisation pass (two dot/update sweeps), the norm, the Givens rotations and
-// the residual estimate |g_{j+1}|.  The host only launches kernels and reads one residual
-// estimate per wavelength per iteration to retire converged wavelengths, which then leave the
-// matrix-vector product.  x0 = 0; a wavelength stops when ||b - A x|| <= tol ||b||, checked
-// on the true residual at each restart.  Optional right block-Jacobi preconditioning with the
-// 2x2 self-panel blocks (K_ii = 0 on flat panels) does not change the solution.
+// matrix-vector product.  The Arnoldi process runs on the device as classical Gram-Schmidt with
+// delayed re-orthogonalisation (the low-synchronisation "DCGS2" scheme of Swirydowicz et al.,
+// 2020, and Bielich et al., 2022), written out below from its defining relations.  Step j
+// multiplies the provisional vector p (slot j: projected once against q_0..q_{j-1} and
+// normalised) and then needs one pass over the basis for all inner products
+//     s = Q^H p,  alpha = p^H p,  z = Q^H w,  beta = p^H w,  gamma = w^H w   (w = A p)
+// and one pass that writes the final q_j = (p - Q s) / r, r = sqrt(alpha - |s|^2), and the next
+// provisional vector.  With p = Q s + r q_j the relations
+//     A q_j = (w - Q_{0..j} H s) / r,      u_j = (w - Q (z - s t) - p t) / r,
+//     t = (beta - s^H z) / r^2,             |u_j|^2 = (gamma - |z|^2 - r^2 |t|^2) / r^2
+// give Hessenberg column j (provisional until its subdiagonal norm is corrected one step
+// later: column j-1 becomes final as h_{:,j-1} += |u_{j-1}| s, h_{j,j-1} = |u_{j-1}| r).  So each
+// step reads the basis twice instead of four times (classical Gram-Schmidt with a second pass),
+// with the same orthogonality.  Givens rotations turn each final column; the residual estimate
+// of the next dimension is predicted from the provisional column, and when it meets the
+// tolerance (or the cycle or the iteration budget ends) the column is finalised with an inner
+// product pass alone, so no matrix-vector product is wasted.  The host only launches kernels
+// and reads two residual estimates per wavelength per step to retire converged wavelengths,
+// which then leave the matrix-vector product.  x0 = 0; a wavelength stops when
+// ||b - A x|| <= tol ||b||, checked on the true residual at each restart.  Optional right
+// block-Jacobi preconditioning with the 2x2 self-panel blocks (K_ii = 0 on flat panels) does not
+// change the solution.
 #include <algorithm>
 #include <cmath>
 
@@ -39,91 +54,276 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// part[(slot * m1 + i) * nblk + blk] = sum over the block's slice of conj(V_i) . w, i <= j
-__global__ void __launch_bounds__(GT) k_dots(const double2* __restrict__ V, int m1,
-                                             int64_t nvec, int j, const double2* __restrict__ w,
-                                             const int32_t* __restrict__ cols,
-                                             double2* __restrict__ part, int nblk) {
-    extern __shared__ double2 red[];  // [GT/64][j+1]
+// Inner products of one Arnoldi step.  nq final basis vectors Q = V_0..V_{nq-1}, the provisional
+// vector p = V_nq and (with_w) the product w.  Per wave and block slice, partial sums of
+//   k < nq: q_k^H p;  k = nq: p^H p;  (with_w) nq + 1 + k: q_k^H w;  2 nq + 1: p^H w;  2 nq + 2: w^H w
+// go to part[(slot * kmax + k) * nparts + 4 blk + wave].
+__global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, int m1,
+                                                 int64_t nvec, int nq, int with_w,
+                                                 const double2* __restrict__ w,
+                                                 const int32_t* __restrict__ cols,
+                                                 double2* __restrict__ part, int kmax,
+                                                 int nparts) {
     const int slot = blockIdx.y, col = cols[slot];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * GSLICE;
+    const double2* Vc = V + static_cast<int64_t>(col) * m1 * nvec;
     const double2* wc = w + col * nvec;
-    double2 wl[GE];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double2* out = part + static_cast<int64_t>(slot) * kmax * nparts + 4 * blockIdx.x + wave;
+    auto put = [&](int k, double re, double im) {
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) out[static_cast<int64_t>(k) * nparts] = make_double2(re, im);
+    };
+    double2 pl[GE], wl[GE];
 #pragma unroll
     for (int e = 0; e < GE; ++e) {
         const int64_t n = base + e * GT + threadIdx.x;
-        wl[e] = n < nvec ? wc[n] : make_double2(0.0, 0.0);
+        const bool in = n < nvec;
+        pl[e] = in ? Vc[nq * nvec + n] : make_double2(0.0, 0.0);
+        wl[e] = in && with_w ? wc[n] : make_double2(0.0, 0.0);
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = 0; i <= j; ++i) {
-        const double2* vi = V + (static_cast<int64_t>(col) * m1 + i) * nvec;
-        double ar = 0.0, ai = 0.0;
+    for (int k = 0; k < nq; ++k) {
+        const double2* qk = Vc + k * nvec;
+        double sr = 0.0, si = 0.0, zr = 0.0, zi = 0.0;
 #pragma unroll
         for (int e = 0; e < GE; ++e) {
             const int64_t n = base + e * GT + threadIdx.x;
             if (n < nvec) {
-                const double2 p = cconjmul(vi[n], wl[e]);
-                ar += p.x;
-                ai += p.y;
+                const double2 q = qk[n];
+                const double2 a = cconjmul(q, pl[e]), c = cconjmul(q, wl[e]);
+                sr += a.x;
+                si += a.y;
+                zr += c.x;
+                zi += c.y;
             }
         }
-        ar = wave_sum(ar);
-        ai = wave_sum(ai);
-        if (lane == 0) red[wave * (j + 1) + i] = make_double2(ar, ai);
+        put(k, sr, si);
+        if (with_w) put(nq + 1 + k, zr, zi);
+    }
+    double al = 0.0, br = 0.0, bi = 0.0, ga = 0.0;
+#pragma unroll
+    for (int e = 0; e < GE; ++e) {
+        al += pl[e].x * pl[e].x + pl[e].y * pl[e].y;
+        const double2 c = cconjmul(pl[e], wl[e]);
+        br += c.x;
+        bi += c.y;
+        ga += wl[e].x * wl[e].x + wl[e].y * wl[e].y;
+    }
+    put(nq, al, 0.0);
+    if (with_w) {
+        put(2 * nq + 1, br, bi);
+        put(2 * nq + 2, ga, 0.0);
+    }
+}
+
+// red[col * kmax + k] = sum over the parts, in a fixed order
+__global__ void k_dcgs_red_final(const double2* __restrict__ part, int nparts, int nk, int kmax,
+                                 const int32_t* __restrict__ cols, int nslot,
+                                 double2* __restrict__ red) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslot * nk) return;
+    const int slot = t / nk, k = t % nk;
+    const double2* p = part + (static_cast<int64_t>(slot) * kmax + k) * nparts;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nparts; ++b) {
+        acc.x += p[b].x;
+        acc.y += p[b].y;
+    }
+    red[cols[slot] * kmax + k] = acc;
+}
+
+// Per-wavelength state of the Arnoldi process (all arrays indexed by column col):
+//   Hr [m][m1]  final Hessenberg columns as the Arnoldi relation has them (not rotated)
+//   H  [m][m1]  the same columns after the Givens rotations (upper triangle for the back solve)
+//   hp [m1 + 1] the provisional column, nu its provisional subdiagonal |u|
+//   cs, sn [m]  rotations; gv [m1] rotated right-hand side |r0| e_0
+//   coef [kmax] update coefficients: s (m1), z - s t (m1), then 1/r, t, 1/(r nu)
+struct ArnoldiState {
+    double2 *Hr, *H, *hp, *cs, *sn, *gv, *coef;
+    double *nu, *est_fin, *est_prov, *r_fin;
+    int32_t* fin;
+    int m, kmax;
+};
+
+// Applies the stored rotations 0..c-1 to column h (entries 0..c+1) and returns the rotation that
+// zeroes h[c + 1] (h[c] becomes its norm).
+__device__ void rotate_column(double2* h, int c, const double2* cs, const double2* sn,
+                              double2& cc, double2& ss) {
+    for (int i = 0; i < c; ++i) {  // [x, y] -> [conj(c) x + conj(s) y, -s x + c y]
+        const double2 hi = h[i], hn = h[i + 1];
+        const double2 a = cconjmul(cs[i], hi), bq = cconjmul(sn[i], hn);
+        const double2 d = cmul(sn[i], hi), e = cmul(cs[i], hn);
+        h[i] = make_double2(a.x + bq.x, a.y + bq.y);
+        h[i + 1] = make_double2(e.x - d.x, e.y - d.y);
+    }
+    const double2 a = h[c], bq = h[c + 1];
+    const double den = sqrt(a.x * a.x + a.y * a.y + bq.x * bq.x + bq.y * bq.y);
+    cc = make_double2(1.0, 0.0);
+    ss = make_double2(0.0, 0.0);
+    if (den > 0.0) {
+        cc = make_double2(a.x / den, a.y / den);
+        ss = make_double2(bq.x / den, bq.y / den);
+    }
+    h[c] = make_double2(den, 0.0);
+    h[c + 1] = make_double2(0.0, 0.0);
+}
+
+// Finalises column c from its provisional form: h_{i,c} = hp_i + nu s_i (i <= c),
+// h_{c+1,c} = nu r; stores it raw and rotated, updates the rotated right-hand side and the
+// final residual estimate.  Thread 0 only.
+__device__ void finalize_column(ArnoldiState& A, int col, int c, const double2* s, double r,
+                                double2* tmp) {
+    const int m1 = A.m + 1;
+    const double nu = A.nu[col];
+    const double2* hp = A.hp + static_cast<int64_t>(col) * (m1 + 1);
+    double2* hr = A.Hr + (static_cast<int64_t>(col) * A.m + c) * m1;
+    for (int i = 0; i <= c; ++i) {
+        tmp[i] = make_double2(hp[i].x + nu * s[i].x, hp[i].y + nu * s[i].y);
+        hr[i] = tmp[i];
+    }
+    tmp[c + 1] = make_double2(nu * r, 0.0);
+    hr[c + 1] = tmp[c + 1];
+    double2* cs = A.cs + col * A.m;
+    double2* sn = A.sn + col * A.m;
+    double2 cc, ss;
+    rotate_column(tmp, c, cs, sn, cc, ss);
+    cs[c] = cc;
+    sn[c] = ss;
+    double2* H = A.H + (static_cast<int64_t>(col) * A.m + c) * m1;
+    for (int i = 0; i <= c + 1; ++i) H[i] = tmp[i];
+    double2* g = A.gv + col * m1;
+    const double2 gc = g[c];
+    const double2 t = cmul(ss, gc);
+    g[c + 1] = make_double2(-t.x, -t.y);
+    g[c] = cconjmul(cc, gc);
+    A.est_fin[col] = sqrt(g[c + 1].x * g[c + 1].x + g[c + 1].y * g[c + 1].y);
+    A.fin[col] = c;
+    A.r_fin[col] = r;
+}
+
+// One block of 64 threads per running column.
+// mode 0, step j (nq = j): finalise column j - 1 (unless a finalising pass already did), form
+//   provisional column j, the update coefficients and the predicted estimate of dimension j + 1.
+// mode 1, step j (nq = j + 1): finalise column j only.
+__global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ red,
+                                                    const int32_t* __restrict__ cols, int mode,
+                                                    int j, ArnoldiState A) {
+    extern __shared__ double2 sh[];  // s [m1], z [m1], g [m1 + 1], tmp [m1 + 1]
+    const int col = cols[blockIdx.x];
+    const int m1 = A.m + 1;
+    double2* s = sh;
+    double2* z = s + m1;
+    double2* g = z + m1;
+    double2* tmp = g + m1 + 1;
+    const double2* rd = red + col * A.kmax;
+    const int nq = mode == 0 ? j : j + 1;
+    for (int i = threadIdx.x; i < nq; i += 64) {
+        s[i] = rd[i];
+        if (mode == 0) z[i] = rd[nq + 1 + i];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += GT) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int q = 0; q < GT / 64; ++q) {
-            s.x += red[q * (j + 1) + i].x;
-            s.y += red[q * (j + 1) + i].y;
+    __shared__ double r_sh;
+    if (threadIdx.x == 0) {
+        double ss = 0.0;
+        for (int i = 0; i < nq; ++i) ss += s[i].x * s[i].x + s[i].y * s[i].y;
+        const double r = sqrt(fmax(rd[nq].x - ss, 0.0));
+        r_sh = r;
+        if (mode == 1) {
+            finalize_column(A, col, j, s, r, tmp);
+            A.est_prov[col] = A.est_fin[col];
+        } else if (j >= 1 && A.fin[col] != j - 1) {
+            finalize_column(A, col, j - 1, s, r, tmp);
         }
-        part[(static_cast<int64_t>(slot) * m1 + i) * nblk + blockIdx.x] = s;
     }
+    __syncthreads();
+    if (mode == 1) return;
+    const double r = r_sh;
+    // g = Hr[0..j][0..j-1] s (column k of Hr has entries 0..k+1)
+    const double2* hr = A.Hr + static_cast<int64_t>(col) * A.m * m1;
+    for (int i = threadIdx.x; i <= j; i += 64) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) {
+            const double2 p = cmul(hr[k * m1 + i], s[k]);
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+        g[i] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double2* coef = A.coef + col * A.kmax;
+    double2* hp = A.hp + static_cast<int64_t>(col) * (m1 + 1);
+    if (!(r > 0.0)) {  // p lies in the span of Q: the space is invariant (breakdown)
+        for (int i = 0; i < j; ++i) coef[i] = coef[m1 + i] = make_double2(0.0, 0.0);
+        coef[2 * m1] = coef[2 * m1 + 1] = coef[2 * m1 + 2] = make_double2(0.0, 0.0);
+        A.est_prov[col] = 0.0;
+        return;
+    }
+    const double beta_r = rd[2 * nq + 1].x, beta_i = rd[2 * nq + 1].y, gamma = rd[2 * nq + 2].x;
+    double2 sz = make_double2(0.0, 0.0);
+    double zz = 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double2 c = cconjmul(s[i], z[i]);
+        sz.x += c.x;
+        sz.y += c.y;
+        zz += z[i].x * z[i].x + z[i].y * z[i].y;
+    }
+    const double inv_r = 1.0 / r;
+    const double2 qw = make_double2((beta_r - sz.x) * inv_r, (beta_i - sz.y) * inv_r);  // q_j^H w
+    const double2 t = make_double2(qw.x * inv_r, qw.y * inv_r);
+    for (int i = 0; i < j; ++i) {
+        hp[i] = make_double2((z[i].x - g[i].x) * inv_r, (z[i].y - g[i].y) * inv_r);
+        const double2 st = cmul(s[i], t);
+        coef[i] = s[i];
+        coef[m1 + i] = make_double2(z[i].x - st.x, z[i].y - st.y);
+    }
+    hp[j] = make_double2((qw.x - g[j].x) * inv_r, (qw.y - g[j].y) * inv_r);
+    const double nu2 = gamma - zz - (qw.x * qw.x + qw.y * qw.y);
+    const double nu = sqrt(fmax(nu2, 1e-30 * gamma)) * inv_r;
+    hp[j + 1] = make_double2(nu, 0.0);
+    A.nu[col] = nu;
+    coef[2 * m1] = make_double2(inv_r, 0.0);
+    coef[2 * m1 + 1] = t;
+    coef[2 * m1 + 2] = make_double2(nu > 0.0 ? inv_r / nu : 0.0, 0.0);
+    // predicted estimate of dimension j + 1 from the provisional column
+    for (int i = 0; i <= j + 1; ++i) tmp[i] = hp[i];
+    double2 cc, ssr;
+    rotate_column(tmp, j, A.cs + col * A.m, A.sn + col * A.m, cc, ssr);
+    const double2 gj = A.gv[col * m1 + j];
+    A.est_prov[col] = sqrt(ssr.x * ssr.x + ssr.y * ssr.y) * sqrt(gj.x * gj.x + gj.y * gj.y);
 }
 
-// hpass[col][i] = sum_blk part; hcol[col][i] (+)= hpass
-__global__ void k_dots_final(const double2* __restrict__ part, int nblk, int m1, int j,
-                             const int32_t* __restrict__ cols, int nslot,
-                             double2* __restrict__ hpass, double2* __restrict__ hcol, int accum) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nslot * (j + 1)) return;
-    const int slot = t / (j + 1), i = t % (j + 1);
-    const int col = cols[slot];
-    double2 s = make_double2(0.0, 0.0);
-    const double2* p = part + (static_cast<int64_t>(slot) * m1 + i) * nblk;
-    for (int b = 0; b < nblk; ++b) {
-        s.x += p[b].x;
-        s.y += p[b].y;
-    }
-    hpass[col * m1 + i] = s;
-    if (accum) {
-        hcol[col * m1 + i].x += s.x;
-        hcol[col * m1 + i].y += s.y;
-    } else {
-        hcol[col * m1 + i] = s;
-    }
-}
-
-// w -= sum_{i <= j} V_i hpass_i
-__global__ void __launch_bounds__(GT) k_update(const double2* __restrict__ V, int m1,
-                                               int64_t nvec, int j, double2* __restrict__ w,
-                                               const int32_t* __restrict__ cols,
-                                               const double2* __restrict__ hpass) {
+// Second pass of step j: q_j = (p - Q s) / r into slot j and the next provisional vector
+// (w - Q (z - s t) - p t) / (r nu) into slot j + 1, reading each basis vector once.
+__global__ void __launch_bounds__(GT) k_dcgs_update(double2* __restrict__ V, int m1, int64_t nvec,
+                                                    int j, const double2* __restrict__ w,
+                                                    const int32_t* __restrict__ cols,
+                                                    const double2* __restrict__ coef, int kmax) {
     const int col = cols[blockIdx.y];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * GSLICE;
-    double2* wc = w + col * nvec;
+    double2* Vc = V + static_cast<int64_t>(col) * m1 * nvec;
+    const double2* cf = coef + col * kmax;
+    const double qs = cf[2 * m1].x, ws = cf[2 * m1 + 2].x;
+    const double2 t = cf[2 * m1 + 1];
 #pragma unroll
     for (int e = 0; e < GE; ++e) {
         const int64_t n = base + e * GT + threadIdx.x;
         if (n >= nvec) continue;
-        double2 a = wc[n];
-        for (int i = 0; i <= j; ++i) {
-            const double2 p = cmul(V[(static_cast<int64_t>(col) * m1 + i) * nvec + n], hpass[col * m1 + i]);
-            a.x -= p.x;
-            a.y -= p.y;
+        const double2 p = Vc[j * nvec + n];
+        const double2 pt = cmul(t, p);
+        double2 aq = p;
+        double2 aw = make_double2(w[col * nvec + n].x - pt.x, w[col * nvec + n].y - pt.y);
+        for (int i = 0; i < j; ++i) {
+            const double2 q = Vc[i * nvec + n];
+            const double2 a = cmul(cf[i], q), c = cmul(cf[m1 + i], q);
+            aq.x -= a.x;
+            aq.y -= a.y;
+            aw.x -= c.x;
+            aw.y -= c.y;
         }
-        wc[n] = a;
+        Vc[j * nvec + n] = make_double2(aq.x * qs, aq.y * qs);
+        Vc[(j + 1) * nvec + n] = make_double2(aw.x * ws, aw.y * ws);
     }
 }
 
@@ -149,53 +349,6 @@ __global__ void __launch_bounds__(GT) k_norm_part(const double2* __restrict__ w,
         for (int q = 0; q < GT / 64; ++q) t += red[q];
         part2[static_cast<int64_t>(blockIdx.y) * nblk + blockIdx.x] = t;
     }
-}
-
-// Finishes Arnoldi step j for each running column: h_{j+1,j} = ||w||, previous rotations on
-// column j, new rotation zeroing h_{j+1,j}, g update, residual estimate, 1/||w||.
-__global__ void k_arnoldi_finish(const double* __restrict__ part2, int nblk,
-                                 const int32_t* __restrict__ cols, int nslot, int m, int j,
-                                 double2* __restrict__ hcol, double2* __restrict__ H,
-                                 double2* __restrict__ cs, double2* __restrict__ sn,
-                                 double2* __restrict__ gv, double* __restrict__ est,
-                                 double* __restrict__ inv_norm) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= nslot) return;
-    const int col = cols[slot];
-    const int m1 = m + 1;
-    double ss = 0.0;
-    for (int b = 0; b < nblk; ++b) ss += part2[static_cast<int64_t>(slot) * nblk + b];
-    const double nrm = sqrt(ss);
-    double2* h = hcol + col * m1;
-    h[j + 1] = make_double2(nrm, 0.0);
-    double2* c = cs + col * m;
-    double2* s = sn + col * m;
-    for (int i = 0; i < j; ++i) {  // [x, y] -> [conj(c) x + conj(s) y, -s x + c y]
-        const double2 hi = h[i], hn = h[i + 1];
-        const double2 a = cconjmul(c[i], hi), bq = cconjmul(s[i], hn);
-        const double2 d = cmul(s[i], hi), e = cmul(c[i], hn);
-        h[i] = make_double2(a.x + bq.x, a.y + bq.y);
-        h[i + 1] = make_double2(e.x - d.x, e.y - d.y);
-    }
-    const double2 a = h[j], bq = h[j + 1];
-    const double den = sqrt(a.x * a.x + a.y * a.y + bq.x * bq.x + bq.y * bq.y);
-    double2 cj = make_double2(1.0, 0.0), sj = make_double2(0.0, 0.0);
-    if (den > 0.0) {
-        cj = make_double2(a.x / den, a.y / den);
-        sj = make_double2(bq.x / den, bq.y / den);
-    }
-    c[j] = cj;
-    s[j] = sj;
-    h[j] = make_double2(den, 0.0);
-    h[j + 1] = make_double2(0.0, 0.0);
-    double2* g = gv + col * m1;
-    const double2 gj = g[j];
-    const double2 t = cmul(sj, gj);
-    g[j + 1] = make_double2(-t.x, -t.y);
-    g[j] = cconjmul(cj, gj);
-    for (int i = 0; i <= j + 1; ++i) H[(static_cast<int64_t>(col) * m + j) * m1 + i] = h[i];
-    est[col] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-    inv_norm[col] = nrm > 0.0 ? 1.0 / nrm : 0.0;
 }
 
 // dst_col = src_col * scale[col]
@@ -357,18 +510,24 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     const bool pre = gm.precond != 0;
     DevBuf<double2> V(static_cast<size_t>(B) * m1 * nvec), w(B * nvec), bvec(B * nvec);
     DevBuf<double2> z(pre ? B * nvec : 0);
-    DevBuf<double2> hcol(B * m1), hpass(B * m1), H(static_cast<size_t>(B) * m * m1);
-    DevBuf<double2> cs(B * m), sn(B * m), gv(B * m1), y(B * m);
-    DevBuf<double2> part(static_cast<size_t>(B) * m1 * nblk);
-    DevBuf<double> part2(static_cast<size_t>(B) * nblk), est(B), inv(B), nrm(B);
-    DevBuf<int32_t> cols_d(B), jn_d(B);
+    const int kmax = 2 * m1 + 3;
+    const int nparts = 4 * nblk;  // one partial sum per wave of each block
+    DevBuf<double2> Hr(static_cast<size_t>(B) * m * m1), H(static_cast<size_t>(B) * m * m1);
+    DevBuf<double2> hp(B * (m1 + 1)), cs(B * m), sn(B * m), gv(B * m1), y(B * m);
+    DevBuf<double2> red(B * kmax), coef(B * kmax);
+    DevBuf<double2> part(static_cast<size_t>(B) * kmax * nparts);
+    DevBuf<double> part2(static_cast<size_t>(B) * nblk), inv(B), nrm(B);
+    DevBuf<double> nu(B), est_fin(B), est_prov(B), r_fin(B);
+    DevBuf<int32_t> cols_d(B), jn_d(B), fin(B);
+    ArnoldiState AS{Hr.p, H.p, hp.p, cs.p, sn.p, gv.p, coef.p, nu.p, est_fin.p, est_prov.p,
+                    r_fin.p, fin.p, m, kmax};
     LSPR_HIP(hipMemsetAsync(x, 0, B * nvec * sizeof(double2), s));
 
     SolveResult res;
     res.iters.assign(B, 0);
     res.rel_resid.assign(B, 0.0);
     std::vector<int32_t> jn(B, 0);
-    std::vector<double> bnorm(B), est_h(B), nrm_h(B);
+    std::vector<double> bnorm(B), ef_h(B), ep_h(B), nrm_h(B);
 
     auto upload_cols = [&](const std::vector<int32_t>& c) {
         LSPR_HIP(hipMemcpyAsync(cols_d.p, c.data(), c.size() * 4, hipMemcpyHostToDevice, s));
@@ -409,10 +568,23 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
                            cols_d.p, ns, nrm.p);
         LSPR_HIP(hipGetLastError());
     }
+    // inner products of step j (nq final vectors, provisional vector in slot nq) for the columns
+    // in cols_d, then the per-column finishing kernel
+    auto reduce_finish = [&](int ns, int nq, int with_w, int mode, int j) {
+        const int nk = with_w ? 2 * nq + 3 : nq + 1;
+        hipLaunchKernelGGL(k_dcgs_red, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq, with_w,
+                           w.p, cols_d.p, part.p, kmax, nparts);
+        hipLaunchKernelGGL(k_dcgs_red_final, dim3((ns * nk + 255) / 256), dim3(256), 0, s, part.p,
+                           nparts, nk, kmax, cols_d.p, ns, red.p);
+        hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(64), (4 * m1 + 2) * sizeof(double2), s,
+                           red.p, cols_d.p, mode, j, AS);
+        LSPR_HIP(hipGetLastError());
+    };
     while (!active.empty()) {
         // ---------------- one restart cycle over the active columns
         std::vector<int32_t> running = active;
         for (int b : active) jn[b] = 0;
+        LSPR_HIP(hipMemsetAsync(fin.p, 0xff, B * sizeof(int32_t), s));  // no final column yet
         for (int j = 0; j < m && !running.empty(); ++j) {
             upload_cols(running);
             const int ns = static_cast<int>(running.size());
@@ -429,37 +601,46 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
             }
             system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
             {
-                // two sweeps reading j+1 basis vectors twice each (dots, update) plus w
-                prof::Scope sc("arnoldi", s, 2.0 * 16.0 * (j + 1) * double(nvec) * ns,
-                               (4.0 * (j + 1) + 8.0) * 16.0 * double(nvec) * ns);
-                for (int pass = 0; pass < 2; ++pass) {
-                    hipLaunchKernelGGL(k_dots, dim3(nblk, ns), dim3(GT),
-                                       (GT / 64) * (j + 1) * sizeof(double2), s, V.p, m1, nvec, j,
-                                       w.p, cols_d.p, part.p, nblk);
-                    const int nt = ns * (j + 1);
-                    hipLaunchKernelGGL(k_dots_final, dim3((nt + 255) / 256), dim3(256), 0, s, part.p,
-                                       nblk, m1, j, cols_d.p, ns, hpass.p, hcol.p, pass);
-                    hipLaunchKernelGGL(k_update, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, j,
-                                       w.p, cols_d.p, hpass.p);
-                    LSPR_HIP(hipGetLastError());
+                // one pass reading j basis vectors, p and w; one reading them again and writing
+                // two vectors
+                prof::Scope sc("arnoldi", s, 32.0 * (j + 1) * double(nvec) * ns,
+                               (2.0 * j + 8.0) * 16.0 * double(nvec) * ns);
+                reduce_finish(ns, j, 1, 0, j);
+                hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, j,
+                                   w.p, cols_d.p, coef.p, kmax);
+                LSPR_HIP(hipGetLastError());
             }
-            hipLaunchKernelGGL(k_norm_part, dim3(nblk, ns), dim3(GT), 0, s, w.p, nvec, nvec,
-                               cols_d.p, part2.p, nblk);
-            hipLaunchKernelGGL(k_arnoldi_finish, dim3((ns + 63) / 64), dim3(64), 0, s, part2.p,
-                               nblk, cols_d.p, ns, m, j, hcol.p, H.p, cs.p, sn.p, gv.p, est.p,
-                               inv.p);
-            hipLaunchKernelGGL(k_scale, dim3(nblk, ns), dim3(GT), 0, s, w.p, nvec,
-                               V.p + (j + 1) * nvec, m1 * nvec, nvec, cols_d.p, inv.p);
-            LSPR_HIP(hipGetLastError());
-            }
-            LSPR_HIP(hipMemcpyAsync(est_h.data(), est.p, B * 8, hipMemcpyDeviceToHost, s));
+            LSPR_HIP(hipMemcpyAsync(ef_h.data(), est_fin.p, B * 8, hipMemcpyDeviceToHost, s));
+            LSPR_HIP(hipMemcpyAsync(ep_h.data(), est_prov.p, B * 8, hipMemcpyDeviceToHost, s));
             LSPR_HIP(hipStreamSynchronize(s));
-            std::vector<int32_t> still;
+            std::vector<int32_t> still, cand;
             for (int b : running) {
-                jn[b] = j + 1;
                 res.iters[b] += 1;
-                const bool done = est_h[b] <= gm.tol * bnorm[b] || res.iters[b] >= gm.max_iter;
-                if (!done) still.push_back(b);
+                if (j >= 1 && ef_h[b] <= gm.tol * bnorm[b]) {
+                    jn[b] = j;  // dimension j already meets the tolerance
+                    continue;
+                }
+                const bool last = res.iters[b] >= gm.max_iter || j + 1 == m;
+                if (last || ep_h[b] <= gm.tol * bnorm[b]) cand.push_back(b);
+                else still.push_back(b);
+            }
+            if (!cand.empty()) {
+                // finalise column j of the candidates: inner products of slot j + 1 alone
+                upload_cols(cand);
+                const int nc = static_cast<int>(cand.size());
+                {
+                    prof::Scope sc("arnoldi", s, 8.0 * (j + 1) * double(nvec) * nc,
+                                   (j + 2.0) * 16.0 * double(nvec) * nc);
+                    reduce_finish(nc, j + 1, 0, 1, j);
+                }
+                LSPR_HIP(hipMemcpyAsync(ef_h.data(), est_fin.p, B * 8, hipMemcpyDeviceToHost, s));
+                LSPR_HIP(hipStreamSynchronize(s));
+                for (int b : cand) {
+                    jn[b] = j + 1;
+                    const bool last = res.iters[b] >= gm.max_iter || j + 1 == m;
+                    if (!last && ef_h[b] > gm.tol * bnorm[b]) still.push_back(b);
+                }
+                std::sort(still.begin(), still.end());
             }
             running.swap(still);
         }

@@ -143,12 +143,16 @@ struct P2MRed {
 // One left factor of the matrix-core far-field product, stored in MFMA operand order.
 // kind 0: expansion (Taylor coefficients; B rows = moments rows b_row0 .. b_row0 + b_rows);
 // kind 1: direct tile (double-layer then single-layer kernel values; B rows = density rows of
-// panels b_row0 .. b_row0 + b_rows).  nstep K-steps of 4 rows; a_off indexes the float store.
+// panels b_row0 .. b_row0 + b_rows).  nstep K-steps of 4 rows; the left factor starts at
+// element 256 a_blk of the tile store (every tile is a multiple of 256 elements).  16 bytes, so
+// a kernel fetches a descriptor with one 128-bit load.
 struct TileDesc {
-    int32_t kind, nstep;
-    int64_t a_off;
+    int16_t kind, nstep;
+    int32_t a_blk;
     int32_t b_row0, b_rows;
+    __host__ __device__ int64_t a_off() const { return static_cast<int64_t>(a_blk) * 256; }
 };
+static_assert(sizeof(TileDesc) == 16, "tile descriptors are fetched as one 128-bit load");
 
 // One entry of a chunk's direct-sum list: source panels [start, end) of one surface.
 struct Range {

@@ -312,6 +312,7 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
 // per output, so rounding does not grow with the number of tiles; in FP64 the matrix cores
 // accumulate every tile directly.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // K-steps of a direct tile: 4 * DSTEPS source panels per tile, summed in FP32 by the matrix
@@ -473,7 +474,7 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
     if (t_beg < t_end) {
         const TileDesc Tf = tiles[t_beg];
         const int n16 = tile_elems(Tf) / PER16;
-        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off);
+        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off());
         for (int k = tid; k < n16; k += nthr) abuf16[k] = src[k];
     }
     __syncthreads();
@@ -490,7 +491,7 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
         const float4* srcn = reinterpret_cast<const float4*>(tileA);
         if (e + 1 < t_end) {
             n16n = tile_elems(Tnext) / PER16;
-            srcn = reinterpret_cast<const float4*>(tileA + Tnext.a_off);
+            srcn = reinterpret_cast<const float4*>(tileA + Tnext.a_off());
         }
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
@@ -568,28 +569,39 @@ k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_
         }
 }
 
-// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, ... handle one chunk (all on
-// the same XCD, so the later ones read the chunk's left factors from L2): the double-layer (K)
-// and single-layer (V) columns, each in 1 or 2 halves of 4 column groups of 16, one group per
-// wave.  Per wave this needs far fewer registers than a K-and-V wave, so three
-// independent workgroups share each CU and hide each other's latencies.
-// Expansion tiles share one left factor between the operators; direct tiles hold the K factor
-// and then the V factor.
+// Scalar offset of the next K-step's B operand.  The empty asm makes each step's offset opaque,
+// so that the compiler forms it with one scalar add instead of keeping every step's offset in
+// its own scalar register across the tile loop.
+__device__ __forceinline__ uint32_t next_step(uint32_t so, uint32_t step) {
+    so += step;
+    asm volatile("" : "+s"(so));
+    return so;
+}
+
 // Buffer resource over [p, p + bytes) for raw buffer loads: out-of-range offsets read zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
 }
 
-template <int PF, int NSM>
-__global__ void __launch_bounds__(256, 3)
+// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, ... handle one chunk (all on
+// the same XCD, so the later ones read the chunk's left factors from L2): the double-layer (K)
+// and single-layer (V) columns, each in 1 or 2 halves of 4 column groups of 16, one group per
+// wave.  Expansion tiles share one left factor between the operators; direct tiles hold the K
+// factor and then the V factor.
+// Latency hiding, per tile: the next tile's left factor is fetched into registers and stored to
+// the single LDS buffer between two barriers at the end of the tile; each B operand of the next
+// tile is requested into its register right after the current tile's step has used it; the
+// descriptor two tiles ahead comes with the vector loads.  No scalar load and no register spill
+// remains in the loop, 127 VGPRs and 21.5 KB of LDS: four workgroups (16 waves) per CU.
+template <int NSM>
+__global__ void __launch_bounds__(256, 4)
 k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
                const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
-               int halves, int abuf_elems, double* __restrict__ out_self,
-               double* __restrict__ out_all) {
+               int halves, double* __restrict__ out_self, double* __restrict__ out_all) {
     constexpr int NTHR = 256;
-    extern __shared__ float4 abuf16[];  // [2][abuf_elems / 4]
+    extern __shared__ float4 abuf16[];  // the current tile's left factor
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, grp = lane >> 4;
     const int ncols = 2 * pad;
@@ -619,7 +631,6 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     }
     const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
     const int t_mid = t_beg + tile_self[chunk];
-    const int buf16 = abuf_elems / 4;
     auto write_sums = [&](double* out) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
@@ -629,52 +640,101 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                 if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = run[mt][q];
             }
     };
+    // B operands: NB values per lane whatever the tile's kind (steps past a tile's rows read
+    // zero without touching memory).  Operand st of the next tile is requested into the same
+    // register as soon as step st of the current tile has been issued, so the loads of a tile's
+    // operands overlap the whole previous tile with one register per step.
+    constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
+    auto b_rsrc = [&](const TileDesc& T, uint32_t rows) {
+        const float* bsrc = T.kind == 0 ? mom : dens;
+        return buffer_rsrc(bsrc + static_cast<size_t>(T.b_row0) * ncols,
+                           rows * static_cast<uint32_t>(ncols) * 4u);
+    };
+    auto load_b_at = [&](__amdgpu_buffer_rsrc_t rb, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, boff, so, 0));
+    };
+    auto load_b = [&](__amdgpu_buffer_rsrc_t rb, int st) {
+        // the per-step offset is uniform: it goes in the scalar offset, not in a VGPR
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, boff, st * bstep, 0));
+    };
+    // Tile descriptors: the current and next in scalar registers, the one after that
+    // requested with the vector prefetch of each tile (one 128-bit load, zero past the chunk's
+    // last tile), so no scalar load waits inside the loop.
+    const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(tiles + t_beg, static_cast<uint32_t>(t_end - t_beg) * 16u);
+    auto to_desc = [](const v4u& w) {
+        const uint32_t w0 = __builtin_amdgcn_readfirstlane(w[0]);
+        TileDesc T;
+        T.kind = static_cast<int16_t>(w0 & 0xffffu);
+        T.nstep = static_cast<int16_t>(w0 >> 16);
+        T.a_blk = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[1]));
+        T.b_row0 = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[2]));
+        T.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
+        return T;
+    };
+    TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
+    TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
+    float bc[NB];
     if (t_beg < t_end) {
-        const TileDesc Tf = tiles[t_beg];
-        const int n16 = tile_elems(Tf) / 4;
-        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off);
+        const int n16 = tile_elems(Te) / 4;
+        const float4* src = reinterpret_cast<const float4*>(tileA + Te.a_off());
         for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
+        const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
+#pragma unroll
+        for (int st = 0; st < NB; ++st) bc[st] = load_b(rb, st);
     }
     __syncthreads();
-    for (int e = t_beg; e < t_end; ++e) {
-        const int cur = (e - t_beg) & 1;
-        // the next left factor into registers (chunks past it read zero and are not stored)
-        float4 pf[PF];
-        int n16n = 0;
+    // a left factor is NA floats per thread: NA / 4 float4 at float4 index tid + 256 r, then
+    // NA % 4 floats at float index 1024 (NA / 4) + tid + 256 r
+    constexpr int NA = NSM > 2 * DSTEPS ? NSM : 2 * DSTEPS;
+    constexpr int QA = NA / 4, RA = NA % 4;
+    // one tile: prefetches for the next, products of this one (all waves of the workgroup run
+    // it together: it ends with a barrier)
+    auto tile = [&](int e) {
+        // the descriptor two tiles ahead, the next left factor into registers (past the last
+        // tile it reads zero and is not stored), and the descriptor of the next B operands
+        // (empty past the last tile)
+        const v4u dn = __builtin_amdgcn_raw_buffer_load_b128(
+            rt, 0, static_cast<uint32_t>(e + 2 - t_beg) * 16u, 0);
+        float4 pf[QA];
+        float pr[RA > 0 ? RA : 1];
+        const bool more = e + 1 < t_end;
+        const int n16n = more ? tile_elems(Tn) / 4 : 0;
         {
-            const TileDesc Tn = tiles[e + 1 < t_end ? e + 1 : e];
-            n16n = e + 1 < t_end ? tile_elems(Tn) / 4 : 0;
-            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + Tn.a_off, n16n * 16u);
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + Tn.a_off(), n16n * 16u);
 #pragma unroll
-            for (int r = 0; r < PF; ++r) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, (tid + r * NTHR) * 16, 0, 0);
+            for (int r = 0; r < QA; ++r) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, r * NTHR * 16, 0);
                 pf[r] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
                                     __uint_as_float(v[2]), __uint_as_float(v[3]));
             }
+#pragma unroll
+            for (int r = 0; r < RA; ++r)
+                pr[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    ra, tid * 4, (QA * 1024 + r * NTHR) * 4, 0));
         }
-        const TileDesc Te = tiles[e];
+        const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
         if (mma) {
-            const float4* ab = abuf16 + cur * buf16;
-#define LSPR_OP_TILE(NS, BSRC, AOFF)                                                       \
+            const float4* ab = abuf16;
+#define LSPR_OP_TILE(NS, AOFF)                                                             \
     {                                                                                      \
-        const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(                                     \
-            (BSRC) + static_cast<size_t>(Te.b_row0) * ncols,                               \
-            static_cast<uint32_t>(Te.b_rows) * static_cast<uint32_t>(ncols) * 4u);          \
-        float bb[NS];                                                                      \
-        _Pragma("unroll") for (int st = 0; st < (NS); ++st)                                \
-            bb[st] = __uint_as_float(                                                      \
-                __builtin_amdgcn_raw_buffer_load_b32(rb, boff + st * bstep, 0, 0));        \
         const float4* a4 = ab + (AOFF);                                                    \
+        uint32_t so = 0;                                                                   \
         _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
             const float4 a = a4[st * 64 + lane];                                           \
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb[st], acc[0], 0, 0, 0);   \
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb[st], acc[1], 0, 0, 0);   \
-            acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bb[st], acc[2], 0, 0, 0);   \
-            acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bb[st], acc[3], 0, 0, 0);   \
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bc[st], acc[0], 0, 0, 0);   \
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bc[st], acc[1], 0, 0, 0);   \
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bc[st], acc[2], 0, 0, 0);   \
+            acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bc[st], acc[3], 0, 0, 0);   \
+            bc[st] = load_b_at(rbn, so);                                                   \
+            so = next_step(so, bstep);                                                     \
+        }                                                                                  \
+        _Pragma("unroll") for (int st = (NS); st < NB; ++st) {                             \
+            bc[st] = load_b_at(rbn, so);                                                   \
+            so = next_step(so, bstep);                                                     \
         }                                                                                  \
     }
-            if (Te.kind == 0) LSPR_OP_TILE(NSM, mom, 0)
-            else LSPR_OP_TILE(DSTEPS, dens, opr * 64 * DSTEPS)
+            if (Te.kind == 0) LSPR_OP_TILE(NSM, 0)
+            else LSPR_OP_TILE(DSTEPS, opr * 64 * DSTEPS)
 #undef LSPR_OP_TILE
             // the tile's FP32 partial joins an FP64 running sum
 #pragma unroll
@@ -683,29 +743,32 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                 for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
                 acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
             }
-            if (e + 1 == t_mid && out_self != nullptr) write_sums(out_self);
         }
+        __syncthreads();  // every wave is done with this tile's left factor
         {
-            float4* dst = abuf16 + (cur ^ 1) * buf16;
+            float4* dst = abuf16;
 #pragma unroll
-            for (int r = 0; r < PF; ++r) {
+            for (int r = 0; r < QA; ++r) {
                 const int k = tid + r * NTHR;
                 if (k < n16n) dst[k] = pf[r];
             }
-        }
-        __syncthreads();
-    }
-    if (!mma) return;
-    if (t_mid == t_beg && out_self != nullptr) {  // no own-surface tiles
+            float* dst1 = reinterpret_cast<float*>(dst);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = 16 * mt + 4 * grp + q;
-                if (t < ntg) out_self[static_cast<size_t>(C.start + t) * ncols + col] = 0.0;
+            for (int r = 0; r < RA; ++r) {
+                const int k = QA * 1024 + tid + r * NTHR;
+                if (k < 4 * n16n) dst1[k] = pr[r];
             }
-    }
-    write_sums(out_all);
+        }
+        Te = Tn;
+        Tn = to_desc(dn);
+        __syncthreads();
+    };
+    // own-surface tiles first: their sums are the own-surface result (written between the two
+    // loops, so that no output address is kept in registers across the tile loop)
+    for (int e = t_beg; e < t_mid; ++e) tile(e);
+    if (mma && out_self != nullptr) write_sums(out_self);
+    for (int e = t_mid; e < t_end; ++e) tile(e);
+    if (mma) write_sums(out_all);
 }
 
 // ------------------------------------------------------------------------------- P2M, MFMA
@@ -830,7 +893,7 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
     const Chunk C = chunks[m2p_chunk[e]];
     const Box B = boxes[m2p_box[e]];
     const TileDesc TD = tiles[m2p_tile[e]];
-    T* A = tileA + TD.a_off;
+    T* A = tileA + TD.a_off();
     const int i = C.start + t;
     T F[NR];
     if (i < C.end) {
@@ -865,7 +928,7 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
     if (e >= n) return;
     const TileDesc TD = tiles[p2p_tile[e]];
     const Chunk C = chunks[p2p_chunk[e]];
-    T* AK = tileA + TD.a_off;
+    T* AK = tileA + TD.a_off();
     T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
     const int rs = 4 + 4 * K;
     for (int pr = threadIdx.x; pr < 64 * 4 * TD.nstep; pr += blockDim.x) {
@@ -987,15 +1050,15 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
-template <int PF, int NSM>
+template <int NSM>
 void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
                          double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
     const int nblk = (g.n_chunks + 7) / 8 * 8 * 2 * halves;
-    const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(float);
-    hipLaunchKernelGGL((k_far_tiles_op<PF, NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
+    const size_t lds = static_cast<size_t>(abuf) * sizeof(float);
+    hipLaunchKernelGGL((k_far_tiles_op<NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
                        g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
-                       mom, pad, pad / 16, halves, abuf, os, oa);
+                       mom, pad, pad / 16, halves, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
@@ -1006,13 +1069,9 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
         if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
             const int nsm = (g.n_terms + 3) / 4;
             const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);
-            const int pf = (abuf / 4 + 255) / 256;
-            LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the kernel");
 #define LSPR_FAR_OP(NSM_)                                                                    \
     case NSM_:                                                                               \
-        if (pf <= 4) launch_far_tiles_op<4, NSM_>(g, pad, abuf, dens, mom, os, oa, s);       \
-        else if (pf <= 6) launch_far_tiles_op<6, NSM_>(g, pad, abuf, dens, mom, os, oa, s);  \
-        else launch_far_tiles_op<8, NSM_>(g, pad, abuf, dens, mom, os, oa, s);               \
+        launch_far_tiles_op<NSM_>(g, pad, abuf, dens, mom, os, oa, s);                       \
         return;
             switch (nsm) {
                 LSPR_FAR_OP(3)
@@ -1239,6 +1298,17 @@ void build_tiles(Geometry& g) {
     if (g.n_p2p)
         copy_sync(rng.data(), g.p2p_rng.p, g.n_p2p * sizeof(Range), hipMemcpyDeviceToHost, s);
     const int nsm = (g.n_terms + 3) / 4;  // K-steps of an expansion tile
+    auto make_tile = [](int kind, int nstep, int64_t aoff, int r0, int rows) {
+        LSPR_REQUIRE(aoff % 256 == 0 && aoff / 256 < INT32_MAX, LSPR_E_INVALID,
+                     "tile store offset out of range");
+        TileDesc T;
+        T.kind = static_cast<int16_t>(kind);
+        T.nstep = static_cast<int16_t>(nstep);
+        T.a_blk = static_cast<int32_t>(aoff / 256);
+        T.b_row0 = r0;
+        T.b_rows = rows;
+        return T;
+    };
     std::vector<TileDesc> tiles;
     std::vector<int32_t> toff(nc + 1, 0), tself(nc, 0);
     std::vector<int32_t> m2p_tile(std::max<int64_t>(g.n_m2p, 1)), m2p_chunk(std::max<int64_t>(g.n_m2p, 1));
@@ -1252,7 +1322,7 @@ void build_tiles(Geometry& g) {
             for (int e = ma; e < mb; ++e) {
                 m2p_tile[e] = static_cast<int32_t>(tiles.size());
                 m2p_chunk[e] = c;
-                tiles.push_back(TileDesc{0, nsm, aoff, mbox[e] * g.n_terms, g.n_terms});
+                tiles.push_back(make_tile(0, nsm, aoff, mbox[e] * g.n_terms, g.n_terms));
                 aoff += static_cast<int64_t>(nsm) * 256;
             }
             for (int e = pa; e < pb; ++e)
@@ -1260,7 +1330,7 @@ void build_tiles(Geometry& g) {
                     p2p_tile.push_back(static_cast<int32_t>(tiles.size()));
                     p2p_chunk.push_back(c);
                     tiles.push_back(
-                        TileDesc{1, DSTEPS, aoff, p0, std::min(4 * DSTEPS, rng[e].end - p0)});
+                        make_tile(1, DSTEPS, aoff, p0, std::min(4 * DSTEPS, rng[e].end - p0)));
                     aoff += 2 * DSTEPS * 256;
                 }
             if (phase == 0) tself[c] = static_cast<int32_t>(tiles.size()) - toff[c];
