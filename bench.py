@@ -378,6 +378,12 @@ def main():
                         "converged": bool(out["converged"]),
                         "max_rel_resid": float(out["rel_resid"].max())},
         "kernel_ms_per_step": {n: p["total_ms"] / args.steps for n, p in prof.items()},
+        # algorithmic bytes / event time of the HBM-bound passes (Arnoldi: the basis vectors,
+        # p and w read, q and the next vector written; near: table, densities and sums)
+        "hbm_passes": {n: {"GB/s": prof[n]["bytes"] / (prof[n]["total_ms"] * 1e-3) / 1e9,
+                           "frac": prof[n]["bytes"] / (prof[n]["total_ms"] * 1e-3) / 1e9
+                           / PEAK_HBM_GBS}
+                       for n in ("arnoldi", "near") if prof[n]["total_ms"] > 0},
         "lists": {k: int(info[k]) for k in ("n_boxes", "n_m2p", "n_p2p_ranges", "p2p_pairs",
                                             "m2p_pairs", "n_near", "n_terms", "ncrit")},
     }

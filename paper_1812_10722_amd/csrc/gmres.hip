@@ -55,51 +55,88 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Inner products of one Arnoldi step.  nq final basis vectors Q = V_0..V_{nq-1}, the provisional
-// vector p = V_nq and (with_w) the product w.  Per wave and block slice, partial sums of
-//   k < nq: q_k^H p;  k = nq: p^H p;  (with_w) nq + 1 + k: q_k^H w;  2 nq + 1: p^H w;  2 nq + 2: w^H w
-// go to part[(slot * kmax + k) * nparts + 4 blk + wave].
+// vector p = V_nq and (WITH_W) the product w.  Per wave and block slice, partial sums of
+//   k < nq: q_k^H p;  k = nq: p^H p;  (WITH_W) nq + 1 + k: q_k^H w;  2 nq + 1: p^H w;  2 nq + 2: w^H w
+// go to part[(slot * kmax + k) * nparts + 4 blk + wave].  The basis is taken KB vectors at a
+// time, and the wave reductions of their 4 KB partial sums are interleaved, so that the
+// cross-lane exchanges overlap instead of waiting on each other.
+template <int WITH_W>
 __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, int m1,
-                                                 int64_t nvec, int nq, int with_w,
+                                                 int64_t nvec, int nq,
                                                  const double2* __restrict__ w,
                                                  const int32_t* __restrict__ cols,
                                                  double2* __restrict__ part, int kmax,
                                                  int nparts) {
+    constexpr int KB = 4, NV = WITH_W ? 4 : 2;  // values per basis vector: s (re, im) [, z]
     const int slot = blockIdx.y, col = cols[slot];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * GSLICE;
     const double2* Vc = V + static_cast<int64_t>(col) * m1 * nvec;
     const double2* wc = w + col * nvec;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double2* out = part + static_cast<int64_t>(slot) * kmax * nparts + 4 * blockIdx.x + wave;
-    auto put = [&](int k, double re, double im) {
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) out[static_cast<int64_t>(k) * nparts] = make_double2(re, im);
-    };
+    // element indices clamped into the vector and out-of-range values zeroed by a select, so
+    // that loads carry no branch and all of a step's loads are in flight together
+    int64_t nn[GE];
+    bool in[GE];
     double2 pl[GE], wl[GE];
 #pragma unroll
     for (int e = 0; e < GE; ++e) {
         const int64_t n = base + e * GT + threadIdx.x;
-        const bool in = n < nvec;
-        pl[e] = in ? Vc[nq * nvec + n] : make_double2(0.0, 0.0);
-        wl[e] = in && with_w ? wc[n] : make_double2(0.0, 0.0);
+        in[e] = n < nvec;
+        nn[e] = in[e] ? n : nvec - 1;
     }
-    for (int k = 0; k < nq; ++k) {
-        const double2* qk = Vc + k * nvec;
-        double sr = 0.0, si = 0.0, zr = 0.0, zi = 0.0;
 #pragma unroll
-        for (int e = 0; e < GE; ++e) {
-            const int64_t n = base + e * GT + threadIdx.x;
-            if (n < nvec) {
-                const double2 q = qk[n];
-                const double2 a = cconjmul(q, pl[e]), c = cconjmul(q, wl[e]);
-                sr += a.x;
-                si += a.y;
-                zr += c.x;
-                zi += c.y;
+    for (int e = 0; e < GE; ++e) {
+        const double2 a = Vc[nq * nvec + nn[e]];
+        pl[e] = in[e] ? a : make_double2(0.0, 0.0);
+        if (WITH_W) {
+            const double2 c = wc[nn[e]];
+            wl[e] = in[e] ? c : make_double2(0.0, 0.0);
+        } else {
+            wl[e] = make_double2(0.0, 0.0);
+        }
+    }
+    for (int k0 = 0; k0 < nq; k0 += KB) {
+        double v[KB][NV];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+#pragma unroll
+            for (int c = 0; c < NV; ++c) v[kk][c] = 0.0;
+            // past the last basis vector the products read vector nq - 1 again and are dropped
+            const int k = k0 + kk < nq ? k0 + kk : nq - 1;
+            const double2* qk = Vc + k * nvec;
+            double2 q[GE];
+#pragma unroll
+            for (int e = 0; e < GE; ++e) q[e] = qk[nn[e]];  // pl, wl are zero out of range
+#pragma unroll
+            for (int e = 0; e < GE; ++e) {
+                const double2 a = cconjmul(q[e], pl[e]);
+                v[kk][0] += a.x;
+                v[kk][1] += a.y;
+                if (WITH_W) {
+                    const double2 c = cconjmul(q[e], wl[e]);
+                    v[kk][2] += c.x;
+                    v[kk][3] += c.y;
+                }
             }
         }
-        put(k, sr, si);
-        if (with_w) put(nq + 1 + k, zr, zi);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) v[kk][c] += __shfl_xor(v[kk][c], off, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) {
+                const int k = k0 + kk;
+                if (k < nq) {
+                    out[static_cast<int64_t>(k) * nparts] = make_double2(v[kk][0], v[kk][1]);
+                    if (WITH_W)
+                        out[static_cast<int64_t>(nq + 1 + k) * nparts] = make_double2(v[kk][2], v[kk][3]);
+                }
+            }
+        }
     }
     double al = 0.0, br = 0.0, bi = 0.0, ga = 0.0;
 #pragma unroll
@@ -110,10 +147,18 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
         bi += c.y;
         ga += wl[e].x * wl[e].x + wl[e].y * wl[e].y;
     }
-    put(nq, al, 0.0);
-    if (with_w) {
-        put(2 * nq + 1, br, bi);
-        put(2 * nq + 2, ga, 0.0);
+    al = wave_sum(al);
+    if (WITH_W) {
+        br = wave_sum(br);
+        bi = wave_sum(bi);
+        ga = wave_sum(ga);
+    }
+    if (lane == 0) {
+        out[static_cast<int64_t>(nq) * nparts] = make_double2(al, 0.0);
+        if (WITH_W) {
+            out[static_cast<int64_t>(2 * nq + 1) * nparts] = make_double2(br, bi);
+            out[static_cast<int64_t>(2 * nq + 2) * nparts] = make_double2(ga, 0.0);
+        }
     }
 }
 
@@ -300,30 +345,59 @@ __global__ void __launch_bounds__(GT) k_dcgs_update(double2* __restrict__ V, int
                                                     int j, const double2* __restrict__ w,
                                                     const int32_t* __restrict__ cols,
                                                     const double2* __restrict__ coef, int kmax) {
+    extern __shared__ double2 cfs[];  // [2 j]: s, then z - s t
     const int col = cols[blockIdx.y];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * GSLICE;
     double2* Vc = V + static_cast<int64_t>(col) * m1 * nvec;
     const double2* cf = coef + col * kmax;
+    for (int i = threadIdx.x; i < j; i += GT) {
+        cfs[i] = cf[i];
+        cfs[j + i] = cf[m1 + i];
+    }
+    __syncthreads();
     const double qs = cf[2 * m1].x, ws = cf[2 * m1 + 2].x;
     const double2 t = cf[2 * m1 + 1];
+    // basis vector by basis vector, GE elements per thread, so that GE loads are in flight
+    // clamped indices: loads without branches (out-of-range lanes compute values never stored)
+    int64_t nn[GE];
 #pragma unroll
     for (int e = 0; e < GE; ++e) {
         const int64_t n = base + e * GT + threadIdx.x;
-        if (n >= nvec) continue;
-        const double2 p = Vc[j * nvec + n];
+        nn[e] = n < nvec ? n : nvec - 1;
+    }
+    double2 aq[GE], aw[GE];
+#pragma unroll
+    for (int e = 0; e < GE; ++e) {
+        const double2 p = Vc[j * nvec + nn[e]];
+        const double2 wv = w[col * nvec + nn[e]];
         const double2 pt = cmul(t, p);
-        double2 aq = p;
-        double2 aw = make_double2(w[col * nvec + n].x - pt.x, w[col * nvec + n].y - pt.y);
-        for (int i = 0; i < j; ++i) {
-            const double2 q = Vc[i * nvec + n];
-            const double2 a = cmul(cf[i], q), c = cmul(cf[m1 + i], q);
-            aq.x -= a.x;
-            aq.y -= a.y;
-            aw.x -= c.x;
-            aw.y -= c.y;
+        aq[e] = p;
+        aw[e] = make_double2(wv.x - pt.x, wv.y - pt.y);
+    }
+#pragma unroll 2
+    for (int i = 0; i < j; ++i) {
+        const double2* qi = Vc + i * nvec;
+        const double2 cq = cfs[i], cw = cfs[j + i];
+        double2 qv[GE];
+#pragma unroll
+        for (int e = 0; e < GE; ++e) qv[e] = qi[nn[e]];
+#pragma unroll
+        for (int e = 0; e < GE; ++e) {
+            const double2 q = qv[e];
+            const double2 a = cmul(cq, q), c = cmul(cw, q);
+            aq[e].x -= a.x;
+            aq[e].y -= a.y;
+            aw[e].x -= c.x;
+            aw[e].y -= c.y;
         }
-        Vc[j * nvec + n] = make_double2(aq.x * qs, aq.y * qs);
-        Vc[(j + 1) * nvec + n] = make_double2(aw.x * ws, aw.y * ws);
+    }
+#pragma unroll
+    for (int e = 0; e < GE; ++e) {
+        const int64_t n = base + e * GT + threadIdx.x;
+        if (n < nvec) {
+            Vc[j * nvec + n] = make_double2(aq[e].x * qs, aq[e].y * qs);
+            Vc[(j + 1) * nvec + n] = make_double2(aw[e].x * ws, aw[e].y * ws);
+        }
     }
 }
 
@@ -499,6 +573,18 @@ __global__ void k_norm_final(const double* __restrict__ part2, int nblk,
 
 int blocks_for(int64_t nvec) { return static_cast<int>((nvec + GSLICE - 1) / GSLICE); }
 
+// Pinned host memory for the residual estimates, one block per host thread, allocated once and
+// kept for the life of the process (freeing pinned memory can wait for the whole device, which
+// would stall concurrent requests).
+double* pinned_estimates(int n) {
+    constexpr int CAP = 4 * 64;
+    LSPR_REQUIRE(n <= CAP, LSPR_E_INVALID, "too many columns for the estimate buffer");
+    thread_local double* p = nullptr;
+    if (p == nullptr)
+        LSPR_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), CAP * sizeof(double), hipHostMallocDefault));
+    return p;
+}
+
 }  // namespace
 
 SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
@@ -517,9 +603,9 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     DevBuf<double2> red(B * kmax), coef(B * kmax);
     DevBuf<double2> part(static_cast<size_t>(B) * kmax * nparts);
     DevBuf<double> part2(static_cast<size_t>(B) * nblk), inv(B), nrm(B);
-    DevBuf<double> nu(B), est_fin(B), est_prov(B), r_fin(B);
+    DevBuf<double> nu(B), est(2 * B), r_fin(B);  // est: final estimates, then predicted ones
     DevBuf<int32_t> cols_d(B), jn_d(B), fin(B);
-    ArnoldiState AS{Hr.p, H.p, hp.p, cs.p, sn.p, gv.p, coef.p, nu.p, est_fin.p, est_prov.p,
+    ArnoldiState AS{Hr.p, H.p, hp.p, cs.p, sn.p, gv.p, coef.p, nu.p, est.p, est.p + B,
                     r_fin.p, fin.p, m, kmax};
     LSPR_HIP(hipMemsetAsync(x, 0, B * nvec * sizeof(double2), s));
 
@@ -527,10 +613,17 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     res.iters.assign(B, 0);
     res.rel_resid.assign(B, 0.0);
     std::vector<int32_t> jn(B, 0);
-    std::vector<double> bnorm(B), ef_h(B), ep_h(B), nrm_h(B);
+    std::vector<double> bnorm(B), nrm_h(B);
+    // the two estimates of every column come back through pinned memory in one copy per step
+    double* est_h = pinned_estimates(2 * B);
+    const double* ef_h = est_h;
+    const double* ep_h = est_h + B;
 
+    std::vector<int32_t> cols_now;  // the list cols_d holds
     auto upload_cols = [&](const std::vector<int32_t>& c) {
+        if (c == cols_now) return;
         LSPR_HIP(hipMemcpyAsync(cols_d.p, c.data(), c.size() * 4, hipMemcpyHostToDevice, s));
+        cols_now = c;
     };
     auto norms = [&](const double2* vec, int64_t stride, const std::vector<int32_t>& c) {
         upload_cols(c);
@@ -572,8 +665,12 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     // in cols_d, then the per-column finishing kernel
     auto reduce_finish = [&](int ns, int nq, int with_w, int mode, int j) {
         const int nk = with_w ? 2 * nq + 3 : nq + 1;
-        hipLaunchKernelGGL(k_dcgs_red, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq, with_w,
-                           w.p, cols_d.p, part.p, kmax, nparts);
+        if (with_w)
+            hipLaunchKernelGGL(k_dcgs_red<1>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
+                               w.p, cols_d.p, part.p, kmax, nparts);
+        else
+            hipLaunchKernelGGL(k_dcgs_red<0>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
+                               w.p, cols_d.p, part.p, kmax, nparts);
         hipLaunchKernelGGL(k_dcgs_red_final, dim3((ns * nk + 255) / 256), dim3(256), 0, s, part.p,
                            nparts, nk, kmax, cols_d.p, ns, red.p);
         hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(64), (4 * m1 + 2) * sizeof(double2), s,
@@ -606,12 +703,12 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
                 prof::Scope sc("arnoldi", s, 32.0 * (j + 1) * double(nvec) * ns,
                                (2.0 * j + 8.0) * 16.0 * double(nvec) * ns);
                 reduce_finish(ns, j, 1, 0, j);
-                hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, j,
-                                   w.p, cols_d.p, coef.p, kmax);
+                hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ns), dim3(GT),
+                                   2 * j * sizeof(double2), s, V.p, m1, nvec, j, w.p, cols_d.p,
+                                   coef.p, kmax);
                 LSPR_HIP(hipGetLastError());
             }
-            LSPR_HIP(hipMemcpyAsync(ef_h.data(), est_fin.p, B * 8, hipMemcpyDeviceToHost, s));
-            LSPR_HIP(hipMemcpyAsync(ep_h.data(), est_prov.p, B * 8, hipMemcpyDeviceToHost, s));
+            LSPR_HIP(hipMemcpyAsync(est_h, est.p, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
             LSPR_HIP(hipStreamSynchronize(s));
             std::vector<int32_t> still, cand;
             for (int b : running) {
@@ -633,7 +730,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
                                    (j + 2.0) * 16.0 * double(nvec) * nc);
                     reduce_finish(nc, j + 1, 0, 1, j);
                 }
-                LSPR_HIP(hipMemcpyAsync(ef_h.data(), est_fin.p, B * 8, hipMemcpyDeviceToHost, s));
+                LSPR_HIP(hipMemcpyAsync(est_h, est.p, B * sizeof(double), hipMemcpyDeviceToHost, s));
                 LSPR_HIP(hipStreamSynchronize(s));
                 for (int b : cand) {
                     jn[b] = j + 1;

@@ -202,6 +202,7 @@ struct Geometry {
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
     DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)
+    int n_order = 0;              // entries of chunk_order (a multiple of 8)
     DevBuf<float> tileA;      // FP32 left factors (need32)
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
@@ -235,6 +236,9 @@ struct Geometry {
     int far_op_min_pad = 16;  // FP32 products with at least this many columns per operator run
                               // one operator per workgroup (0: never)
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 40 % of free device memory)
+    // near-singular corrections and V_ii folded into the direct tiles of that precision (the
+    // matrix-core products then need no separate near-field pass)
+    bool near_in_tiles32 = false, near_in_tiles64 = false;
 
     size_t device_bytes() const;
 };

@@ -13,6 +13,7 @@
 //           self-term, in FP64.
 // Sums are raw: no 1/(4 pi) factor.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 
 #include "expansion.hpp"
@@ -961,6 +962,58 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
     }
 }
 
+// Near-singular pairs and the singular self-term folded into the direct tiles: the far-rule
+// value of a near pair (i, j) plus its fine-minus-far correction is its fine-rule value
+// (section "Integral evaluation"), and V_ii joins the otherwise empty self pair.  Every near
+// pair lies in a direct tile of its target's chunk (a box is never expanded for targets that
+// could be near-singular to it), so the tiles then carry the whole operator.  Thread = target;
+// each thread writes its own tile row, so no two threads touch one entry; pairs without a tile
+// are counted (the caller then rebuilds the tiles without folding).
+template <class T>
+__global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
+                            const int32_t* __restrict__ dt_off, const int32_t* __restrict__ dt_row0,
+                            const int32_t* __restrict__ dt_tile,
+                            const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
+                            const int32_t* __restrict__ col, const double* __restrict__ dv,
+                            const double* __restrict__ dk, const double* __restrict__ vself,
+                            int N, T* __restrict__ tileA, int32_t* __restrict__ missing) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int lo = 0, hi = n_chunks - 1;  // the chunk holding target i (chunks are in target order)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (chunks[mid].start <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int t = i - chunks[lo].start;
+    const int d0 = dt_off[lo], d1 = dt_off[lo + 1];
+    // the chunk's direct tiles sorted by first source panel: the last one starting at or
+    // before j holds j if j is inside its range
+    auto place = [&](int j, double add_k, double add_v) {
+        int a = d0, b = d1 - 1;
+        if (b < a || dt_row0[a] > j) return false;
+        while (a < b) {
+            const int mid = (a + b + 1) / 2;
+            if (dt_row0[mid] <= j) a = mid;
+            else b = mid - 1;
+        }
+        const TileDesc TD = tiles[dt_tile[a]];
+        const int p = j - TD.b_row0;
+        if (p >= TD.b_rows) return false;
+        T* AK = tileA + TD.a_off();
+        T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
+        const int st = p >> 2, gq = p & 3, mt = t >> 4, r16 = t & 15;
+        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * gq + r16) * 4 + mt;
+        AK[idx] = static_cast<T>(static_cast<double>(AK[idx]) + add_k);
+        AV[idx] = static_cast<T>(static_cast<double>(AV[idx]) + add_v);
+        return true;
+    };
+    int miss = 0;
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) miss += !place(col[e], dk[e], dv[e]);
+    miss += !place(i, 0.0, vself[i]);
+    if (miss) atomicAdd(missing, miss);
+}
+
 // ------------------------------------------------------------------------------- near field
 // out[i][c] += sum over near-singular pairs (fine - far) * density, plus the singular V_ii,
 // split into own-surface and all-surface sums.  Thread = (target, column), FP64.
@@ -1038,7 +1091,7 @@ const double* tiles_of<double>(const Geometry& g) { return g.tileA64.p; }
 template <class T, int PF, int NSM, int NTHR>
 void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, const T* dens,
                          const T* mom, double* os, double* oa, hipStream_t s) {
-    const int nblk = (g.n_chunks + 7) / 8 * 8 * halves;
+    const int nblk = g.n_order * halves;
     const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(T);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles<T, PF, NSM, NTHR>),
@@ -1054,7 +1107,7 @@ template <int NSM>
 void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
                          double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
-    const int nblk = (g.n_chunks + 7) / 8 * 8 * 2 * halves;
+    const int nblk = g.n_order * 2 * halves;
     const size_t lds = static_cast<size_t>(abuf) * sizeof(float);
     hipLaunchKernelGGL((k_far_tiles_op<NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
                        g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
@@ -1245,6 +1298,7 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
             }
         }
     }
+    if (c.mfma && (fp64 ? g.near_in_tiles64 : g.near_in_tiles32)) return;
     const int64_t tot = static_cast<int64_t>(g.N) * 2 * c.pad;
     prof::Scope sc("near", s, double(g.n_near + g.N) * 2.0 * 2 * nc,
                    double(g.n_near) * 20 + dens_bytes + 2 * out_bytes);
@@ -1283,6 +1337,26 @@ void build_tiles_t(Geometry& g, T* A, const int32_t* mt, const int32_t* mc, int 
 }
 
 }  // namespace
+
+// Folds the near-field terms into freshly built direct tiles; false (and the tiles rebuilt
+// without them, so the separate near pass applies) if some pair had no tile.
+template <class T>
+bool fold_near(Geometry& g, T* A, const int32_t* dt_off, const int32_t* dt_row0,
+               const int32_t* dt_tile, hipStream_t s,
+               const std::function<void()>& rebuild) {
+    if (g.N == 0 || g.n_chunks == 0) return false;
+    DevBuf<int32_t> miss(1);
+    LSPR_HIP(hipMemsetAsync(miss.p, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_fold_near<T>, dim3((g.N + 255) / 256), dim3(256), 0, s, g.chunks.p,
+                       g.n_chunks, dt_off, dt_row0, dt_tile, g.tiles.p, g.near_off64.p,
+                       g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p, g.N, A, miss.p);
+    LSPR_HIP(hipGetLastError());
+    int32_t h = 0;
+    copy_sync(&h, miss.p, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (h == 0) return true;
+    rebuild();
+    return false;
+}
 
 void build_tiles(Geometry& g) {
     hipStream_t s = g.stream;
@@ -1345,16 +1419,39 @@ void build_tiles(Geometry& g) {
         g.tile_steps += csteps[c];
         g.max_chunk_steps = std::max(g.max_chunk_steps, csteps[c]);
     }
-    // workgroup order: run x = b % 8 of consecutive chunks, heaviest first within the run
-    const int per_xcd = (nc + 7) / 8;
-    std::vector<int32_t> order(static_cast<size_t>(per_xcd) * 8, -1);
-    for (int x = 0; x < 8; ++x) {
-        std::vector<int32_t> run;
-        for (int c = x * per_xcd; c < std::min(nc, (x + 1) * per_xcd); ++c) run.push_back(c);
-        std::stable_sort(run.begin(), run.end(),
-                         [&](int32_t a, int32_t b) { return csteps[a] > csteps[b]; });
-        for (size_t i = 0; i < run.size(); ++i) order[i * 8 + x] = run[i];
+    // Workgroup order: run x = b % 8 of consecutive chunks (the workgroups of one XCD), the runs
+    // cut at equal shares of the estimated work (K-steps plus 4 per tile for its fixed costs),
+    // heaviest chunk first within each run.
+    std::vector<double> ccost(nc);
+    double total = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        ccost[c] = static_cast<double>(csteps[c]) + 4.0 * (toff[c + 1] - toff[c]);
+        total += ccost[c];
     }
+    std::vector<std::vector<int32_t>> runs(8);
+    {
+        double acc = 0.0;
+        int x = 0;
+        for (int c = 0; c < nc; ++c) {
+            // move on to the next run once this one holds its share (every run gets a chunk
+            // while enough remain)
+            while (x < 7 && !runs[x].empty() &&
+                   (acc + 0.5 * ccost[c] > (x + 1) * total / 8.0 || nc - c <= 7 - x))
+                ++x;
+            runs[x].push_back(c);
+            acc += ccost[c];
+        }
+    }
+    size_t per_xcd = 0;
+    for (auto& run : runs) {
+        std::stable_sort(run.begin(), run.end(),
+                         [&](int32_t a, int32_t b) { return ccost[a] > ccost[b]; });
+        per_xcd = std::max(per_xcd, run.size());
+    }
+    std::vector<int32_t> order(std::max<size_t>(per_xcd, 1) * 8, -1);
+    for (int x = 0; x < 8; ++x)
+        for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
+    g.n_order = static_cast<int>(order.size());
     // Tile stores within the budget: FP32 first (the GMRES products of the FP32 and refinement
     // modes), then FP64 with what is left.  A precision without tiles keeps the on-the-fly
     // vector-ALU kernel (e.g. a dense product on a big mesh).
@@ -1381,13 +1478,37 @@ void build_tiles(Geometry& g) {
     copy_sync(mc.p, m2p_chunk.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
     copy_sync(pt.p, p2p_tile.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
     copy_sync(pc.p, p2p_chunk.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
+    // each chunk's direct tiles sorted by first source panel, for the near-field fold
+    std::vector<int32_t> dto(nc + 1, 0), dtr, dti;
+    for (int c = 0; c < nc; ++c) {
+        dto[c] = static_cast<int32_t>(dti.size());
+        std::vector<std::pair<int32_t, int32_t>> d;
+        for (int t = toff[c]; t < toff[c + 1]; ++t)
+            if (tiles[t].kind == 1) d.emplace_back(tiles[t].b_row0, t);
+        std::sort(d.begin(), d.end());
+        for (auto& e : d) {
+            dtr.push_back(e.first);
+            dti.push_back(e.second);
+        }
+    }
+    dto[nc] = static_cast<int32_t>(dti.size());
+    DevBuf<int32_t> dto_d(nc + 1), dtr_d(std::max<size_t>(dtr.size(), 1)), dti_d(std::max<size_t>(dti.size(), 1));
+    copy_sync(dto_d.p, dto.data(), dto.size() * 4, hipMemcpyHostToDevice, s);
+    if (!dti.empty()) {
+        copy_sync(dtr_d.p, dtr.data(), dtr.size() * 4, hipMemcpyHostToDevice, s);
+        copy_sync(dti_d.p, dti.data(), dti.size() * 4, hipMemcpyHostToDevice, s);
+    }
     if (keep32) {
         g.tileA.alloc(std::max<int64_t>(aoff, 1));
-        build_tiles_t<float>(g, g.tileA.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
+        auto build = [&] { build_tiles_t<float>(g, g.tileA.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
+        build();
+        g.near_in_tiles32 = fold_near(g, g.tileA.p, dto_d.p, dtr_d.p, dti_d.p, s, build);
     }
     if (keep64) {
         g.tileA64.alloc(std::max<int64_t>(aoff, 1));
-        build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s);
+        auto build = [&] { build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
+        build();
+        g.near_in_tiles64 = fold_near(g, g.tileA64.p, dto_d.p, dtr_d.p, dti_d.p, s, build);
     }
     LSPR_HIP(hipStreamSynchronize(s));
     if (keep32 && g.n_seg > 0) {  // moments on matrix cores as well

@@ -13,6 +13,7 @@ namespace {
 struct Rec {
     std::string name;
     hipEvent_t a = nullptr, b = nullptr;
+    int dev = 0;
     double flops = 0, bytes = 0, items = 0;
     bool done = false;
 };
@@ -20,11 +21,25 @@ struct Rec {
 std::mutex mu;
 bool on = false;
 std::vector<Rec> recs;
+// events of earlier records, per device, reused (creating one costs microseconds)
+std::map<int, std::vector<hipEvent_t>> spare;
+
+hipEvent_t take_event(int dev) {
+    std::vector<hipEvent_t>& pool = spare[dev];
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    LSPR_HIP(hipEventCreate(&e));
+    return e;
+}
 
 void clear_locked() {
     for (Rec& r : recs) {
-        if (r.a) (void)hipEventDestroy(r.a);
-        if (r.b) (void)hipEventDestroy(r.b);
+        if (r.a) spare[r.dev].push_back(r.a);
+        if (r.b) spare[r.dev].push_back(r.b);
     }
     recs.clear();
 }
@@ -37,8 +52,9 @@ int start(const char* name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(mu);
     Rec r;
     r.name = name;
-    LSPR_HIP(hipEventCreate(&r.a));
-    LSPR_HIP(hipEventCreate(&r.b));
+    LSPR_HIP(hipGetDevice(&r.dev));
+    r.a = take_event(r.dev);
+    r.b = take_event(r.dev);
     LSPR_HIP(hipEventRecord(r.a, s));
     recs.push_back(r);
     return static_cast<int>(recs.size()) - 1;

@@ -159,6 +159,29 @@ def test_preconditioner_keeps_solution(lib):
     assert b["iters"][0] <= a["iters"][0]
 
 
+@pytest.fixture(scope="module")
+def sphere_512_ref():
+    w = workload("sphere_512")
+    v, t = w.surfaces[0]
+    return w, oracle.solve(v, t, np.zeros(len(t), int), w.lambdas, w.eps_medium, w.eps_surface,
+                           w.e_field, k_far=4, k_fine=25, n_k=9, threshold=0.5)
+
+
+@pytest.mark.parametrize("restart", [7, 13])
+def test_short_restart_cycles(lib, sphere_512_ref, restart):
+    """Cycles of 7 and 13 Arnoldi steps end on a column that is finalised by an inner-product
+    pass alone; the restarted solves still meet the tolerance on the true residual and equal
+    the oracle's LU solution.  (Cycles of 1 to 5 steps stagnate on this system, as plain
+    restarted GMRES does.)"""
+    w, ref = sphere_512_ref
+    geo = lib.Geometry(w.surfaces, method="dense", precision="fp64", k_far=4, k_fine=25, n_k=9)
+    out = geo.solve(w.lambdas, w.eps_medium, w.eps_surface, w.e_field, tol=1e-9,
+                    restart=restart, max_iter=4000, precond=1)
+    assert out["converged"] and out["rel_resid"][0] <= 1e-9, (out["iters"], out["rel_resid"])
+    rel = abs(out["cext_sensor"][0] / ref["cext_sensor"][0] - 1)
+    assert rel < 1e-7, rel
+
+
 @pytest.mark.parametrize("method,precision,tol", [("dense", "fp64", 1e-6), ("dense", "fp32", 1e-4),
                                                   ("treecode", "fp64", 1e-4),
                                                   ("treecode", "fp32", 1e-4),
