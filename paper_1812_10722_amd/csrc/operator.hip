@@ -593,9 +593,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
 // the single LDS buffer between two barriers at the end of the tile; each B operand of the next
 // tile is requested into its register right after the current tile's step has used it; the
 // descriptor two tiles ahead comes with the vector loads.  No scalar load and no register spill
-// remains in the loop, 127 VGPRs and 21.5 KB of LDS: four workgroups (16 waves) per CU.
+// remains in the loop; at P = 8, 128 VGPRs and 21.5 KB of LDS: four workgroups (16 waves) per CU
+// (three at P = 10).
 template <int NSM>
-__global__ void __launch_bounds__(256, 4)
+__global__ void __launch_bounds__(256, NSM > 21 ? 3 : 4)
 k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
@@ -672,12 +673,18 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         T.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
         return T;
     };
+    // the part of a left factor this workgroup uses: all of an expansion tile, the factor of its
+    // own operator of a direct tile (its first element, count)
+    auto own_off = [&](const TileDesc& T) {
+        return T.a_off() + (T.kind == 1 ? static_cast<int64_t>(opr) * T.nstep * 256 : 0);
+    };
+    auto own_elems = [](const TileDesc& T) { return 256 * T.nstep; };
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
     float bc[NB];
     if (t_beg < t_end) {
-        const int n16 = tile_elems(Te) / 4;
-        const float4* src = reinterpret_cast<const float4*>(tileA + Te.a_off());
+        const int n16 = own_elems(Te) / 4;
+        const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
         for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
@@ -686,7 +693,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     __syncthreads();
     // a left factor is NA floats per thread: NA / 4 float4 at float4 index tid + 256 r, then
     // NA % 4 floats at float index 1024 (NA / 4) + tid + 256 r
-    constexpr int NA = NSM > 2 * DSTEPS ? NSM : 2 * DSTEPS;
+    constexpr int NA = NSM > DSTEPS ? NSM : DSTEPS;
     constexpr int QA = NA / 4, RA = NA % 4;
     // one tile: prefetches for the next, products of this one (all waves of the workgroup run
     // it together: it ends with a barrier)
@@ -699,9 +706,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         float4 pf[QA];
         float pr[RA > 0 ? RA : 1];
         const bool more = e + 1 < t_end;
-        const int n16n = more ? tile_elems(Tn) / 4 : 0;
+        const int n16n = more ? own_elems(Tn) / 4 : 0;
         {
-            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + Tn.a_off(), n16n * 16u);
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + own_off(Tn), n16n * 16u);
 #pragma unroll
             for (int r = 0; r < QA; ++r) {
                 const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, r * NTHR * 16, 0);
@@ -735,7 +742,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         }                                                                                  \
     }
             if (Te.kind == 0) LSPR_OP_TILE(NSM, 0)
-            else LSPR_OP_TILE(DSTEPS, opr * 64 * DSTEPS)
+            else LSPR_OP_TILE(DSTEPS, 0)
 #undef LSPR_OP_TILE
             // the tile's FP32 partial joins an FP64 running sum
 #pragma unroll
@@ -1121,7 +1128,7 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
     if constexpr (sizeof(T) == 4) {
         if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
             const int nsm = (g.n_terms + 3) / 4;
-            const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);
+            const int abuf = std::max(nsm, DSTEPS) * 256;  // largest part a workgroup stages
 #define LSPR_FAR_OP(NSM_)                                                                    \
     case NSM_:                                                                               \
         launch_far_tiles_op<NSM_>(g, pad, abuf, dens, mom, os, oa, s);                       \
