@@ -162,6 +162,7 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
     (the 256 MiB fill writes 256 MiB; the 256 MiB elementwise multiply reads 256 MiB)."""
     import collections
     import csv
+    import re
 
     def load(path, counter):
         rows = collections.defaultdict(list)
@@ -189,7 +190,8 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
         if len(f) != len(wr):
             raise SystemExit(f"dispatch counts differ between the passes for {k}")
         b = [fv * 1024 * fetch_scale + wv * 1024 * write_scale for fv, wv in zip(f, wr)]
-        short = k.split("::")[-1].split("(")[0]
+        m = re.search(r"(k_\w+(?:<[^()]*>)?)\(", k)
+        short = m.group(1) if m else k
         per[short] = {"dispatches": len(f), "fetch_kib_raw_mean": float(np.mean(f)),
                       "write_kib_raw_mean": float(np.mean(wr)),
                       "bytes_scaled_mean": float(np.mean(b))}
