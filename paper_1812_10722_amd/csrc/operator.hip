@@ -595,8 +595,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
 // descriptor two tiles ahead comes with the vector loads.  No scalar load and no register spill
 // remains in the loop; at P = 8, 128 VGPRs and 21.5 KB of LDS: four workgroups (16 waves) per CU
 // (three at P = 10).
-template <int NSM>
-__global__ void __launch_bounds__(256, NSM > 21 ? 3 : 4)
+// Narrow products (one or two column groups per operator) split the K-steps instead: S = 4 / G
+// waves share each of the G column groups, wave k taking steps k, k + S, ...; at the end their
+// FP64 sums are added in wave order through LDS.  S = 1 is the wide kernel.
+template <int NSM, int S>
+__global__ void __launch_bounds__(256, (S == 2 || NSM > 21) ? 3 : 4)
 k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
@@ -612,7 +615,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     const int per = 2 * halves;
     const int j = (b >> 3) % per;
     const int opr = j & 1;                  // 0: K columns, 1: V columns
-    const int wg = wave + 4 * (j >> 1);     // column group of this wave
+    constexpr int G = 4 / S;                // column groups per workgroup
+    const int kpart = wave % S;             // this wave's share of the K-steps
+    const int wg = wave / S + G * (j >> 1); // column group of this wave
     const int chunk = chunk_order[(b >> 3) / per * 8 + (b & 7)];
     if (chunk < 0) return;
     const Chunk C = chunks[chunk];
@@ -633,13 +638,40 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     }
     const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
     const int t_mid = t_beg + tile_self[chunk];
+    // Writes the sums (with S > 1 the first wave of each column group adds the others' sums, in
+    // wave order, from LDS after the left-factor buffer; all waves call it).
     auto write_sums = [&](double* out) {
+        double sum[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[mt][q] = run[mt][q];
+        if constexpr (S > 1) {
+            // one 8 KB slot per column group, passed from wave to wave
+            constexpr int NAB = NSM > DSTEPS ? NSM : DSTEPS;  // float4 per lane of the buffer
+            double* red = reinterpret_cast<double*>(abuf16 + NAB * 64) + (wave / S) * 16 * 64;
+            for (int k = 1; k < S; ++k) {
+                if (kpart == k)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) red[(4 * mt + q) * 64 + lane] = run[mt][q];
+                __syncthreads();
+                if (kpart == 0)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) sum[mt][q] += red[(4 * mt + q) * 64 + lane];
+                __syncthreads();
+            }
+        }
+        if (!mma || kpart != 0) return;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = 16 * mt + 4 * grp + q;
-                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = run[mt][q];
+                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = sum[mt][q];
             }
     };
     // B operands: NB values per lane whatever the tile's kind (steps past a tile's rows read
@@ -647,6 +679,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     // register as soon as step st of the current tile has been issued, so the loads of a tile's
     // operands overlap the whole previous tile with one register per step.
     constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
+    constexpr int NBS = (NB + S - 1) / S;  // operand registers per wave
     auto b_rsrc = [&](const TileDesc& T, uint32_t rows) {
         const float* bsrc = T.kind == 0 ? mom : dens;
         return buffer_rsrc(bsrc + static_cast<size_t>(T.b_row0) * ncols,
@@ -681,14 +714,14 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     auto own_elems = [](const TileDesc& T) { return 256 * T.nstep; };
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
-    float bc[NB];
+    float bc[NBS];
     if (t_beg < t_end) {
         const int n16 = own_elems(Te) / 4;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
         for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
-        for (int st = 0; st < NB; ++st) bc[st] = load_b(rb, st);
+        for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
     }
     __syncthreads();
     // a left factor is NA floats per thread: NA / 4 float4 at float4 index tid + 256 r, then
@@ -724,7 +757,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         if (mma) {
             const float4* ab = abuf16;
 #define LSPR_OP_TILE(NS, AOFF)                                                             \
-    {                                                                                      \
+    if constexpr (S == 1) {                                                                \
         const float4* a4 = ab + (AOFF);                                                    \
         uint32_t so = 0;                                                                   \
         _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
@@ -739,6 +772,19 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         _Pragma("unroll") for (int st = (NS); st < NB; ++st) {                             \
             bc[st] = load_b_at(rbn, so);                                                   \
             so = next_step(so, bstep);                                                     \
+        }                                                                                  \
+    } else {                                                                               \
+        const float4* a4 = ab + (AOFF);                                                    \
+        _Pragma("unroll") for (int i = 0; i < NBS; ++i) {                                  \
+            const int st = kpart + S * i;                                                  \
+            if (st < (NS)) {                                                               \
+                const float4 a = a4[st * 64 + lane];                                       \
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bc[i], acc[0], 0, 0, 0); \
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bc[i], acc[1], 0, 0, 0); \
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bc[i], acc[2], 0, 0, 0); \
+                acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bc[i], acc[3], 0, 0, 0); \
+            }                                                                              \
+            bc[i] = load_b(rbn, st);                                                       \
         }                                                                                  \
     }
             if (Te.kind == 0) LSPR_OP_TILE(NSM, 0)
@@ -774,9 +820,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     // own-surface tiles first: their sums are the own-surface result (written between the two
     // loops, so that no output address is kept in registers across the tile loop)
     for (int e = t_beg; e < t_mid; ++e) tile(e);
-    if (mma && out_self != nullptr) write_sums(out_self);
+    if (out_self != nullptr) write_sums(out_self);
     for (int e = t_mid; e < t_end; ++e) tile(e);
-    if (mma) write_sums(out_all);
+    write_sums(out_all);
 }
 
 // ------------------------------------------------------------------------------- P2M, MFMA
@@ -1110,16 +1156,27 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
-template <int NSM>
-void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
-                         double* os, double* oa, hipStream_t s) {
+template <int NSM, int S>
+void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
+                           double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
     const int nblk = g.n_order * 2 * halves;
-    const size_t lds = static_cast<size_t>(abuf) * sizeof(float);
-    hipLaunchKernelGGL((k_far_tiles_op<NSM>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
+    // the left factor, then (S > 1) one slot of FP64 sums per column group for the final additions
+    const size_t lds = static_cast<size_t>(abuf) * sizeof(float) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
+    hipLaunchKernelGGL((k_far_tiles_op<NSM, S>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
                        g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
                        mom, pad, pad / 16, halves, os, oa);
     LSPR_HIP(hipGetLastError());
+}
+
+// one column group per operator: four waves share it; two: two waves each; more: one each
+template <int NSM>
+void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
+                         double* os, double* oa, hipStream_t s) {
+    const int groups = pad / 16;
+    if (groups == 1) launch_far_tiles_op_s<NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
+    else if (groups == 2) launch_far_tiles_op_s<NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
+    else launch_far_tiles_op_s<NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
 }
 
 template <class T>
