@@ -222,7 +222,8 @@ int lspr_gauss_legendre(int32_t n, double* t, double* w);
  * (orthogonalisation of one GMRES step).  For "far", `items` counts interactions times
  * wavelengths: (direct target-node pairs + expansion target-box pairs) per launch times the
  * complex columns of that launch.  lspr_profile_query waits for the recorded events and returns
- * totals since the last reset; unknown names give zero launches. */
+ * totals since the last reset; unknown names give zero launches.  on: 0 off, 1 all launches,
+ * 2 far-field launches only ("far", "far64"; the fewest events in the timed stream). */
 int lspr_profile_enable(int32_t on);
 int lspr_profile_reset(void);
 int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,

@@ -1,6 +1,8 @@
 // C ABI of the library (declared in include/lspr.h): argument checks, error translation and
 // orchestration of the set-up and solve steps.
 #include <algorithm>
+#include <mutex>
+#include <map>
 #include <cmath>
 #include <complex>
 #include <set>
@@ -45,6 +47,27 @@ std::string& last_error() {
 AllocCtx& alloc_ctx() {
     thread_local AllocCtx ctx;
     return ctx;
+}
+
+hipMemPool_t library_pool() {
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    int dev = 0;
+    LSPR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    LSPR_HIP(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = 16ull << 30;
+    LSPR_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    pools[dev] = pool;
+    return pool;
 }
 
 void validate_mesh_host(const lspr_surface* surfaces, int n_surf) {
@@ -415,6 +438,7 @@ int lspr_geometry_create(const lspr_surface* surfaces, int32_t n_surf, const lsp
                      "bad arguments");
         *out = nullptr;
         auto h = std::make_unique<lspr_geometry>();
+        lspr::PoolScope ps(static_cast<hipStream_t>(stream));
         lspr::create_geometry(h->g, surfaces, n_surf, *op, static_cast<hipStream_t>(stream));
         *out = h.release();
         return LSPR_OK;
@@ -425,6 +449,7 @@ int lspr_geometry_destroy(lspr_geometry* g) {
     return guarded([&] {
         if (g) {
             (void)hipStreamSynchronize(g->g.stream);
+            lspr::PoolScope ps(g->g.stream);  // pooled memory goes back on the geometry's stream
             delete g;
         }
         return LSPR_OK;
@@ -465,6 +490,7 @@ int lspr_apply(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
                      "bad arguments");
         lspr::Geometry& g = h->g;
         hipStream_t s = static_cast<hipStream_t>(stream);
+        lspr::PoolScope ps(s);
         const int64_t nvec = 2 * static_cast<int64_t>(g.N);
         for (int b0 = 0; b0 < n_cols; b0 += MAX_BATCH) {
             const int B = std::min(MAX_BATCH, n_cols - b0);
@@ -488,6 +514,7 @@ int lspr_rhs(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
                      LSPR_E_INVALID, "bad arguments");
         lspr::Geometry& g = h->g;
         hipStream_t s = static_cast<hipStream_t>(stream);
+        lspr::PoolScope ps(s);
         const int64_t nvec = 2 * static_cast<int64_t>(g.N);
         for (int b0 = 0; b0 < n_cols; b0 += MAX_BATCH) {
             const int B = std::min(MAX_BATCH, n_cols - b0);
@@ -509,6 +536,7 @@ int lspr_solve(lspr_geometry* h, int32_t n_lambda, const double* lambda_nm,
                int32_t* iters, double* rel_resid) {
     return guarded([&] {
         LSPR_REQUIRE(h && gm, LSPR_E_INVALID, "bad arguments");
+        lspr::PoolScope ps(static_cast<hipStream_t>(stream));
         const bool ok = lspr::solve_geometry(h->g, n_lambda, lambda_nm, eps_medium, eps_surface,
                                              e_field, *gm, static_cast<hipStream_t>(stream), phi,
                                              dphi, p_sensor, p_total, cext_sensor, cext_total,

@@ -162,22 +162,6 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
     }
 }
 
-// red[col * kmax + k] = sum over the parts, in a fixed order
-__global__ void k_dcgs_red_final(const double2* __restrict__ part, int nparts, int nk, int kmax,
-                                 const int32_t* __restrict__ cols, int nslot,
-                                 double2* __restrict__ red) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nslot * nk) return;
-    const int slot = t / nk, k = t % nk;
-    const double2* p = part + (static_cast<int64_t>(slot) * kmax + k) * nparts;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int b = 0; b < nparts; ++b) {
-        acc.x += p[b].x;
-        acc.y += p[b].y;
-    }
-    red[cols[slot] * kmax + k] = acc;
-}
-
 // Per-wavelength state of the Arnoldi process (all arrays indexed by column col):
 //   Hr [m][m1]  final Hessenberg columns as the Arnoldi relation has them (not rotated)
 //   H  [m][m1]  the same columns after the Givens rotations (upper triangle for the back solve)
@@ -191,8 +175,8 @@ struct ArnoldiState {
     int m, kmax;
 };
 
-// Applies the stored rotations 0..c-1 to column h (entries 0..c+1) and returns the rotation that
-// zeroes h[c + 1] (h[c] becomes its norm).
+// Applies the rotations 0..c-1 (cs, sn) to column h (entries 0..c+1) and returns the rotation
+// that zeroes h[c + 1] (h[c] becomes its norm).
 __device__ void rotate_column(double2* h, int c, const double2* cs, const double2* sn,
                               double2& cc, double2& ss) {
     for (int i = 0; i < c; ++i) {  // [x, y] -> [conj(c) x + conj(s) y, -s x + c y]
@@ -214,79 +198,95 @@ __device__ void rotate_column(double2* h, int c, const double2* cs, const double
     h[c + 1] = make_double2(0.0, 0.0);
 }
 
-// Finalises column c from its provisional form: h_{i,c} = hp_i + nu s_i (i <= c),
-// h_{c+1,c} = nu r; stores it raw and rotated, updates the rotated right-hand side and the
-// final residual estimate.  Thread 0 only.
-__device__ void finalize_column(ArnoldiState& A, int col, int c, const double2* s, double r,
-                                double2* tmp) {
-    const int m1 = A.m + 1;
-    const double nu = A.nu[col];
-    const double2* hp = A.hp + static_cast<int64_t>(col) * (m1 + 1);
-    double2* hr = A.Hr + (static_cast<int64_t>(col) * A.m + c) * m1;
-    for (int i = 0; i <= c; ++i) {
-        tmp[i] = make_double2(hp[i].x + nu * s[i].x, hp[i].y + nu * s[i].y);
-        hr[i] = tmp[i];
-    }
-    tmp[c + 1] = make_double2(nu * r, 0.0);
-    hr[c + 1] = tmp[c + 1];
-    double2* cs = A.cs + col * A.m;
-    double2* sn = A.sn + col * A.m;
-    double2 cc, ss;
-    rotate_column(tmp, c, cs, sn, cc, ss);
-    cs[c] = cc;
-    sn[c] = ss;
-    double2* H = A.H + (static_cast<int64_t>(col) * A.m + c) * m1;
-    for (int i = 0; i <= c + 1; ++i) H[i] = tmp[i];
-    double2* g = A.gv + col * m1;
-    const double2 gc = g[c];
-    const double2 t = cmul(ss, gc);
-    g[c + 1] = make_double2(-t.x, -t.y);
-    g[c] = cconjmul(cc, gc);
-    A.est_fin[col] = sqrt(g[c + 1].x * g[c + 1].x + g[c + 1].y * g[c + 1].y);
-    A.fin[col] = c;
-    A.r_fin[col] = r;
-}
-
-// One block of 64 threads per running column.
+// One block of 64 threads per running column; it first adds the inner products' partial sums
+// (in a fixed order) and stages the column's rotations and provisional Hessenberg column in LDS,
+// so that the sequential part (thread 0) touches LDS only.
 // mode 0, step j (nq = j): finalise column j - 1 (unless a finalising pass already did), form
 //   provisional column j, the update coefficients and the predicted estimate of dimension j + 1.
 // mode 1, step j (nq = j + 1): finalise column j only.
-__global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ red,
+// Finalising column c: h_{i,c} = hp_i + nu s_i (i <= c), h_{c+1,c} = nu r; stored raw and
+// rotated, with the rotated right-hand side and the final residual estimate.
+__global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ part, int nparts,
                                                     const int32_t* __restrict__ cols, int mode,
                                                     int j, ArnoldiState A) {
-    extern __shared__ double2 sh[];  // s [m1], z [m1], g [m1 + 1], tmp [m1 + 1]
-    const int col = cols[blockIdx.x];
-    const int m1 = A.m + 1;
-    double2* s = sh;
-    double2* z = s + m1;
-    double2* g = z + m1;
+    extern __shared__ double2 sh[];  // rd [kmax], g [m1 + 1], tmp [m1 + 1], cs [m], sn [m], hp [m1 + 1]
+    const int slot = blockIdx.x, col = cols[slot];
+    const int m = A.m, m1 = m + 1, tid = threadIdx.x;
+    double2* rd = sh;
+    double2* g = rd + A.kmax;
     double2* tmp = g + m1 + 1;
-    const double2* rd = red + col * A.kmax;
+    double2* csl = tmp + m1 + 1;
+    double2* snl = csl + m;
+    double2* hpl = snl + m;
     const int nq = mode == 0 ? j : j + 1;
-    for (int i = threadIdx.x; i < nq; i += 64) {
-        s[i] = rd[i];
-        if (mode == 0) z[i] = rd[nq + 1 + i];
-    }
-    __syncthreads();
+    const int nk = mode == 0 ? 2 * nq + 3 : nq + 1;
+    const int c = mode == 0 ? j - 1 : j;  // the column to finalise (none when c < 0)
     __shared__ double r_sh;
-    if (threadIdx.x == 0) {
+    __shared__ int fin_sh;
+    // partial sums, in part order
+    for (int k = tid; k < nk; k += 64) {
+        const double2* p = part + (static_cast<int64_t>(slot) * A.kmax + k) * nparts;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int b = 0; b < nparts; ++b) {
+            acc.x += p[b].x;
+            acc.y += p[b].y;
+        }
+        rd[k] = acc;
+    }
+    const int nrot = mode == 0 ? j : j + 1;  // rotations a step may read (0..c, then c)
+    for (int i = tid; i < nrot && i < m; i += 64) {
+        csl[i] = A.cs[col * m + i];
+        snl[i] = A.sn[col * m + i];
+    }
+    for (int i = tid; i <= j + 1 && i <= m1; i += 64) hpl[i] = A.hp[static_cast<int64_t>(col) * (m1 + 1) + i];
+    __syncthreads();
+    const double2* s = rd;                // s_i = q_i^H p, i < nq
+    const double2* z = rd + nq + 1;       // z_i = q_i^H w, i < nq (mode 0)
+    if (tid == 0) {
         double ss = 0.0;
         for (int i = 0; i < nq; ++i) ss += s[i].x * s[i].x + s[i].y * s[i].y;
         const double r = sqrt(fmax(rd[nq].x - ss, 0.0));
         r_sh = r;
-        if (mode == 1) {
-            finalize_column(A, col, j, s, r, tmp);
-            A.est_prov[col] = A.est_fin[col];
-        } else if (j >= 1 && A.fin[col] != j - 1) {
-            finalize_column(A, col, j - 1, s, r, tmp);
+        const bool do_fin = c >= 0 && (mode == 1 || A.fin[col] != c);
+        fin_sh = do_fin;
+        if (do_fin) {
+            const double nu = A.nu[col];
+            for (int i = 0; i <= c; ++i)
+                tmp[i] = make_double2(hpl[i].x + nu * s[i].x, hpl[i].y + nu * s[i].y);
+            tmp[c + 1] = make_double2(nu * r, 0.0);
+            for (int i = 0; i <= c + 1; ++i) g[i] = tmp[i];  // raw copy (g is free until later)
+            double2 cc, sr;
+            rotate_column(tmp, c, csl, snl, cc, sr);
+            csl[c] = cc;
+            snl[c] = sr;
+            A.cs[col * m + c] = cc;
+            A.sn[col * m + c] = sr;
+            double2* gv = A.gv + col * m1;
+            const double2 gc = gv[c];
+            const double2 t = cmul(sr, gc);
+            gv[c + 1] = make_double2(-t.x, -t.y);
+            gv[c] = cconjmul(cc, gc);
+            A.est_fin[col] = sqrt(t.x * t.x + t.y * t.y);
+            A.fin[col] = c;
+            A.r_fin[col] = r;
+            if (mode == 1) A.est_prov[col] = A.est_fin[col];
         }
     }
     __syncthreads();
+    if (fin_sh) {  // column c, raw (in g) and rotated (in tmp)
+        double2* hr = A.Hr + (static_cast<int64_t>(col) * m + c) * m1;
+        double2* H = A.H + (static_cast<int64_t>(col) * m + c) * m1;
+        for (int i = tid; i <= c + 1; i += 64) {
+            hr[i] = g[i];
+            H[i] = tmp[i];
+        }
+    }
     if (mode == 1) return;
+    __syncthreads();  // column j - 1 of Hr is in memory before g reads it
     const double r = r_sh;
     // g = Hr[0..j][0..j-1] s (column k of Hr has entries 0..k+1)
-    const double2* hr = A.Hr + static_cast<int64_t>(col) * A.m * m1;
-    for (int i = threadIdx.x; i <= j; i += 64) {
+    const double2* hr = A.Hr + static_cast<int64_t>(col) * m * m1;
+    for (int i = tid; i <= j; i += 64) {
         double2 acc = make_double2(0.0, 0.0);
         for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) {
             const double2 p = cmul(hr[k * m1 + i], s[k]);
@@ -296,47 +296,56 @@ __global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ 
         g[i] = acc;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
     double2* coef = A.coef + col * A.kmax;
+    __shared__ double2 t_sh;
+    if (tid == 0) {
+        if (!(r > 0.0)) {  // p lies in the span of Q: the space is invariant (breakdown)
+            t_sh = make_double2(0.0, 0.0);
+            coef[2 * m1] = coef[2 * m1 + 1] = coef[2 * m1 + 2] = make_double2(0.0, 0.0);
+            A.est_prov[col] = 0.0;
+        } else {
+            const double beta_r = rd[2 * nq + 1].x, beta_i = rd[2 * nq + 1].y, gamma = rd[2 * nq + 2].x;
+            double2 sz = make_double2(0.0, 0.0);
+            double zz = 0.0;
+            for (int i = 0; i < j; ++i) {
+                const double2 q = cconjmul(s[i], z[i]);
+                sz.x += q.x;
+                sz.y += q.y;
+                zz += z[i].x * z[i].x + z[i].y * z[i].y;
+            }
+            const double inv_r = 1.0 / r;
+            const double2 qw = make_double2((beta_r - sz.x) * inv_r, (beta_i - sz.y) * inv_r);  // q_j^H w
+            const double2 t = make_double2(qw.x * inv_r, qw.y * inv_r);
+            t_sh = t;
+            for (int i = 0; i < j; ++i)
+                hpl[i] = make_double2((z[i].x - g[i].x) * inv_r, (z[i].y - g[i].y) * inv_r);
+            hpl[j] = make_double2((qw.x - g[j].x) * inv_r, (qw.y - g[j].y) * inv_r);
+            const double nu2 = gamma - zz - (qw.x * qw.x + qw.y * qw.y);
+            const double nu = sqrt(fmax(nu2, 1e-30 * gamma)) * inv_r;
+            hpl[j + 1] = make_double2(nu, 0.0);
+            A.nu[col] = nu;
+            coef[2 * m1] = make_double2(inv_r, 0.0);
+            coef[2 * m1 + 1] = t;
+            coef[2 * m1 + 2] = make_double2(nu > 0.0 ? inv_r / nu : 0.0, 0.0);
+            // predicted estimate of dimension j + 1 from the provisional column
+            for (int i = 0; i <= j + 1; ++i) tmp[i] = hpl[i];
+            double2 cc, ssr;
+            rotate_column(tmp, j, csl, snl, cc, ssr);
+            const double2 gj = A.gv[col * m1 + j];
+            A.est_prov[col] = sqrt(ssr.x * ssr.x + ssr.y * ssr.y) * sqrt(gj.x * gj.x + gj.y * gj.y);
+        }
+    }
+    __syncthreads();
+    const bool ok = r > 0.0;
+    const double2 t = t_sh;
     double2* hp = A.hp + static_cast<int64_t>(col) * (m1 + 1);
-    if (!(r > 0.0)) {  // p lies in the span of Q: the space is invariant (breakdown)
-        for (int i = 0; i < j; ++i) coef[i] = coef[m1 + i] = make_double2(0.0, 0.0);
-        coef[2 * m1] = coef[2 * m1 + 1] = coef[2 * m1 + 2] = make_double2(0.0, 0.0);
-        A.est_prov[col] = 0.0;
-        return;
-    }
-    const double beta_r = rd[2 * nq + 1].x, beta_i = rd[2 * nq + 1].y, gamma = rd[2 * nq + 2].x;
-    double2 sz = make_double2(0.0, 0.0);
-    double zz = 0.0;
-    for (int i = 0; i < j; ++i) {
-        const double2 c = cconjmul(s[i], z[i]);
-        sz.x += c.x;
-        sz.y += c.y;
-        zz += z[i].x * z[i].x + z[i].y * z[i].y;
-    }
-    const double inv_r = 1.0 / r;
-    const double2 qw = make_double2((beta_r - sz.x) * inv_r, (beta_i - sz.y) * inv_r);  // q_j^H w
-    const double2 t = make_double2(qw.x * inv_r, qw.y * inv_r);
-    for (int i = 0; i < j; ++i) {
-        hp[i] = make_double2((z[i].x - g[i].x) * inv_r, (z[i].y - g[i].y) * inv_r);
+    for (int i = tid; i < j; i += 64) {
         const double2 st = cmul(s[i], t);
-        coef[i] = s[i];
-        coef[m1 + i] = make_double2(z[i].x - st.x, z[i].y - st.y);
+        coef[i] = ok ? s[i] : make_double2(0.0, 0.0);
+        coef[m1 + i] = ok ? make_double2(z[i].x - st.x, z[i].y - st.y) : make_double2(0.0, 0.0);
     }
-    hp[j] = make_double2((qw.x - g[j].x) * inv_r, (qw.y - g[j].y) * inv_r);
-    const double nu2 = gamma - zz - (qw.x * qw.x + qw.y * qw.y);
-    const double nu = sqrt(fmax(nu2, 1e-30 * gamma)) * inv_r;
-    hp[j + 1] = make_double2(nu, 0.0);
-    A.nu[col] = nu;
-    coef[2 * m1] = make_double2(inv_r, 0.0);
-    coef[2 * m1 + 1] = t;
-    coef[2 * m1 + 2] = make_double2(nu > 0.0 ? inv_r / nu : 0.0, 0.0);
-    // predicted estimate of dimension j + 1 from the provisional column
-    for (int i = 0; i <= j + 1; ++i) tmp[i] = hp[i];
-    double2 cc, ssr;
-    rotate_column(tmp, j, A.cs + col * A.m, A.sn + col * A.m, cc, ssr);
-    const double2 gj = A.gv[col * m1 + j];
-    A.est_prov[col] = sqrt(ssr.x * ssr.x + ssr.y * ssr.y) * sqrt(gj.x * gj.x + gj.y * gj.y);
+    if (ok)
+        for (int i = tid; i <= j + 1; i += 64) hp[i] = hpl[i];
 }
 
 // Second pass of step j: q_j = (p - Q s) / r into slot j and the next provisional vector
@@ -585,6 +594,43 @@ double* pinned_estimates(int n) {
     return p;
 }
 
+// Column lists go to the device through a ring of pinned slots (asynchronous copies); a slot is
+// reused only after the event recorded behind its last copy has completed.  Per host thread,
+// allocated once and kept.
+struct PinnedCols {
+    static constexpr int SLOTS = 8, CAP = 64;
+    int32_t* host = nullptr;
+    hipEvent_t ev[SLOTS] = {};
+    int next = 0, dev = -1;
+    void upload(int32_t* dst, const std::vector<int32_t>& c, hipStream_t s) {
+        LSPR_REQUIRE(static_cast<int>(c.size()) <= CAP, LSPR_E_INVALID, "too many columns");
+        int d = 0;
+        LSPR_HIP(hipGetDevice(&d));
+        if (host != nullptr && d != dev) {  // events belong to one device: plain copy elsewhere
+            LSPR_HIP(hipMemcpyAsync(dst, c.data(), c.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s));
+            return;
+        }
+        if (host == nullptr) {
+            dev = d;
+            LSPR_HIP(hipHostMalloc(reinterpret_cast<void**>(&host), SLOTS * CAP * sizeof(int32_t),
+                                   hipHostMallocDefault));
+            for (hipEvent_t& e : ev) LSPR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        const int k = next;
+        next = (next + 1) % SLOTS;
+        LSPR_HIP(hipEventSynchronize(ev[k]));
+        std::copy(c.begin(), c.end(), host + k * CAP);
+        LSPR_HIP(hipMemcpyAsync(dst, host + k * CAP, c.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+        LSPR_HIP(hipEventRecord(ev[k], s));
+    }
+};
+PinnedCols& pinned_cols() {
+    thread_local PinnedCols pc;
+    return pc;
+}
+
 }  // namespace
 
 SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
@@ -600,7 +646,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     const int nparts = 4 * nblk;  // one partial sum per wave of each block
     DevBuf<double2> Hr(static_cast<size_t>(B) * m * m1), H(static_cast<size_t>(B) * m * m1);
     DevBuf<double2> hp(B * (m1 + 1)), cs(B * m), sn(B * m), gv(B * m1), y(B * m);
-    DevBuf<double2> red(B * kmax), coef(B * kmax);
+    DevBuf<double2> coef(B * kmax);
     DevBuf<double2> part(static_cast<size_t>(B) * kmax * nparts);
     DevBuf<double> part2(static_cast<size_t>(B) * nblk), inv(B), nrm(B);
     DevBuf<double> nu(B), est(2 * B), r_fin(B);  // est: final estimates, then predicted ones
@@ -622,7 +668,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     std::vector<int32_t> cols_now;  // the list cols_d holds
     auto upload_cols = [&](const std::vector<int32_t>& c) {
         if (c == cols_now) return;
-        LSPR_HIP(hipMemcpyAsync(cols_d.p, c.data(), c.size() * 4, hipMemcpyHostToDevice, s));
+        pinned_cols().upload(cols_d.p, c, s);
         cols_now = c;
     };
     auto norms = [&](const double2* vec, int64_t stride, const std::vector<int32_t>& c) {
@@ -664,17 +710,15 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     // inner products of step j (nq final vectors, provisional vector in slot nq) for the columns
     // in cols_d, then the per-column finishing kernel
     auto reduce_finish = [&](int ns, int nq, int with_w, int mode, int j) {
-        const int nk = with_w ? 2 * nq + 3 : nq + 1;
         if (with_w)
             hipLaunchKernelGGL(k_dcgs_red<1>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
                                w.p, cols_d.p, part.p, kmax, nparts);
         else
             hipLaunchKernelGGL(k_dcgs_red<0>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
                                w.p, cols_d.p, part.p, kmax, nparts);
-        hipLaunchKernelGGL(k_dcgs_red_final, dim3((ns * nk + 255) / 256), dim3(256), 0, s, part.p,
-                           nparts, nk, kmax, cols_d.p, ns, red.p);
-        hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(64), (4 * m1 + 2) * sizeof(double2), s,
-                           red.p, cols_d.p, mode, j, AS);
+        hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(64),
+                           (kmax + 2 * (m1 + 1) + 2 * m + (m1 + 1)) * sizeof(double2), s, part.p,
+                           nparts, cols_d.p, mode, j, AS);
         LSPR_HIP(hipGetLastError());
     };
     while (!active.empty()) {

@@ -33,17 +33,52 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::lspr::Error((code), std::string(msg));    \
     } while (0)
 
-// Allocation context of the calling thread.  By default DevBuf allocates with hipMalloc and
+// Allocation context of the calling thread.  Without a pool DevBuf allocates with hipMalloc and
 // frees with hipFree.  A thread that installs a memory pool allocates stream-ordered from it on
 // `stream` and frees stream-ordered on the same stream, so that requests sharing the device do
-// not synchronise the whole device on every free (the request server does this per worker).
+// not synchronise the whole device on every free (the request server does this per worker; the
+// C entry points install the library's own pool for their call, see PoolScope).  While
+// `free_on` is set, pooled frees go to `free_stream` instead (a stream valid for the call).
 // live / peak count the bytes held by DevBufs allocated on this thread.
 struct AllocCtx {
     hipMemPool_t pool = nullptr;
     hipStream_t stream = nullptr;
+    bool free_on = false;
+    hipStream_t free_stream = nullptr;
     int64_t live = 0, peak = 0;
 };
 AllocCtx& alloc_ctx();
+
+// The library's memory pool on the current device (created on first use; keeps up to 16 GiB of
+// freed memory for reuse instead of returning it at every synchronisation).
+hipMemPool_t library_pool();
+
+// Installs the library pool and `stream` for allocations, and `stream` for frees, for the
+// lifetime of the object, unless the thread already has a pool (the request server's).
+struct PoolScope {
+    AllocCtx saved;
+    bool active = false;
+    explicit PoolScope(hipStream_t stream) {
+        AllocCtx& c = alloc_ctx();
+        if (c.pool != nullptr) return;
+        saved = c;
+        c.pool = library_pool();
+        c.stream = stream;
+        c.free_on = true;
+        c.free_stream = stream;
+        active = true;
+    }
+    ~PoolScope() {
+        if (!active) return;
+        AllocCtx& c = alloc_ctx();
+        const int64_t live = c.live, peak = c.peak;
+        c = saved;
+        c.live = live;
+        c.peak = peak;
+    }
+    PoolScope(const PoolScope&) = delete;
+    PoolScope& operator=(const PoolScope&) = delete;
+};
 
 // Owning device allocation.  Moves, never copies.
 template <class T>
@@ -83,7 +118,10 @@ struct DevBuf {
     void reserve(size_t count) { if (count > n) alloc(count); }
     void release() {
         if (p) {
-            if (pooled) (void)hipFreeAsync(p, free_stream);
+            if (pooled) {
+                const AllocCtx& c = alloc_ctx();
+                (void)hipFreeAsync(p, c.free_on ? c.free_stream : free_stream);
+            }
             else (void)hipFree(p);
             alloc_ctx().live -= static_cast<int64_t>(bytes());
         }

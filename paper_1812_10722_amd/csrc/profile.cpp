@@ -2,6 +2,7 @@
 // the algorithmic flops and bytes of that launch.  Events are kept until the next reset.
 #include "profile.hpp"
 
+#include <cstring>
 #include <map>
 #include <mutex>
 
@@ -20,6 +21,7 @@ struct Rec {
 
 std::mutex mu;
 bool on = false;
+int mode = 0;  // 1: every scope, 2: far-field scopes only
 std::vector<Rec> recs;
 // events of earlier records, per device, reused (creating one costs microseconds)
 std::map<int, std::vector<hipEvent_t>> spare;
@@ -47,6 +49,10 @@ void clear_locked() {
 }  // namespace
 
 bool enabled() { return on; }
+
+bool records(const char* name) {
+    return mode != 2 || std::strcmp(name, "far") == 0 || std::strcmp(name, "far64") == 0;
+}
 
 int start(const char* name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(mu);
@@ -77,7 +83,9 @@ void stop(int token, hipStream_t s, double flops, double bytes, double items) {
 extern "C" {
 
 int lspr_profile_enable(int32_t enable) {
+    if (enable < 0 || enable > 2) return LSPR_E_INVALID;
     lspr::prof::on = enable != 0;
+    lspr::prof::mode = enable;
     return LSPR_OK;
 }
 

@@ -7,6 +7,8 @@ namespace lspr {
 namespace prof {
 
 bool enabled();
+// Whether a scope of this name records (all of them, or only the far-field ones in mode 2).
+bool records(const char* name);
 // Records a start event on s; the matching stop() records the end and the work counts.
 int start(const char* name, hipStream_t s);
 void stop(int token, hipStream_t s, double flops, double bytes, double items);
@@ -18,7 +20,7 @@ struct Scope {
     double flops, bytes, items;
     Scope(const char* name, hipStream_t st, double f, double b, double n = 0.0)
         : s(st), flops(f), bytes(b), items(n) {
-        if (enabled()) token = start(name, s);
+        if (enabled() && records(name)) token = start(name, s);
     }
     ~Scope() {
         if (token >= 0) stop(token, s, flops, bytes, items);

@@ -284,8 +284,9 @@ _lib.lspr_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER
                                     C.POINTER(C.c_double)]
 
 
-def lspr_profile_enable(on: bool):
-    _check(_lib.lspr_profile_enable(1 if on else 0), "lspr_profile_enable")
+def lspr_profile_enable(on):
+    """on: False/0 off, True/1 all launches, 2 far-field launches only."""
+    _check(_lib.lspr_profile_enable(int(on)), "lspr_profile_enable")
 
 
 def lspr_profile_reset():
