@@ -167,6 +167,16 @@ void lspr_server::worker(int w) {
             max_active = std::max(max_active, active);
             r->t_admit = now();
         }
+        // Freed memory stays in the pool for the next request; when the device itself no longer
+        // has room for this request's estimate, the pool returns what it holds unused (blocks of
+        // earlier requests that another request's sizes cannot reuse would otherwise crowd the
+        // device out).
+        {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                static_cast<double>(free_b) < 1.1 * static_cast<double>(r->est))
+                (void)hipMemPoolTrimTo(pool, 0);
+        }
         run(*r, streams[w]);
         {
             std::lock_guard<std::mutex> lk(mu);

@@ -192,3 +192,24 @@ def test_small_multi_surface_request_matches_oracle(lib):
     for key in ("cext_sensor", "cext_total"):
         rel = np.abs(r[key] - ref[key]) / np.abs(ref[key])
         assert rel.max() < 1e-4, (key, rel.max())
+
+
+def test_burst_of_large_requests_all_succeed(lib):
+    """The first 12 requests of the seeded serving stream (16400-258080 panels) submitted at
+    once on 4 slots: the reservations come close to the budget, so memory freed by finished
+    requests must be reusable or returned by the pool (a regression: it once ran the device out
+    of memory while the reservations still fitted)."""
+    from lspr_inputs import serving_stream
+    reqs = [w for _, w in serving_stream(seed=5, n_requests=12)]
+    sv = lib.Server(max_slots=4)
+    try:
+        tickets = [sv.submit(w.surfaces, w.lambdas, w.eps_medium, w.eps_surface, w.e_field,
+                             op=lib.op_params(**w.op), gmres=lib.gmres_params(**w.gmres))
+                   for w in reqs]
+        out = [sv.poll(t, wait=True) for t in tickets]
+        st = sv.stats()
+    finally:
+        sv.close()
+    assert all(r["status"] == lib.LSPR_OK for r in out), [(r["status"], r["error"]) for r in out]
+    assert st["estimate_violations"] == 0
+    assert all(0 < r["peak_bytes"] <= r["est_bytes"] for r in out)
