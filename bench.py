@@ -2,8 +2,8 @@
 """Benchmark of the hot path: a batched wavelength sweep of the quasistatic LSPR BEM.
 
 Workload (default): silver sphere R = 10 nm with 32768 panels, 64 wavelengths 350-420 nm
-(Drude silver, water), treecode theta = 0.5, P = 6, K = 4, K_fine = 19, N_k = 9, FP32 far-field
-kernels, FP64 GMRES (tol 1e-6).  One step = the whole path on one batch: geometry set-up
+(Drude silver, water), treecode theta = 0.5, P = 8, K = 4, K_fine = 19, N_k = 9, FP32 far-field
+kernels, FP64 GMRES (tol 1e-5).  One step = the whole path on one batch: geometry set-up
 (panels, Morton sort, octree, lists, near-singular table, right-hand side) from meshes already
 in device memory, the batched GMRES over all 64 wavelengths, dipole moments and extinction
 cross-sections.
@@ -184,7 +184,7 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
     write_scale = known_kib / only(write, "FillFunctor")
     per, total_b, total_n = {}, 0.0, 0
     for k in sorted(fetch):
-        if "k_far_tiles" not in k:
+        if "k_far_tiles_op" not in k:
             continue
         f, wr = fetch[k], write.get(k, [])
         if len(f) != len(wr):
@@ -223,10 +223,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere_32k_sweep")
-    ap.add_argument("--precision", choices=("fp32", "fp64", "fp32_refine64"),
+    ap.add_argument("--precision", choices=("fp32", "fp64", "fp32_refine64", "fp32_lead64"),
                     help="override the workload's product precision")
     ap.add_argument("--inner-tol", type=float, default=None,
-                    help="inner tolerance of fp32_refine64 (default: the library's)")
+                    help="inner tolerance of fp32_refine64, or the FP64-to-FP32 switch level of "
+                         "fp32_lead64 (default: the library's)")
     ap.add_argument("--tol", type=float, default=None, help="override the GMRES tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=16,
@@ -364,7 +365,8 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "wavelength-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "fp32", "fp64": "fp64"}.get(op["precision"], "fp32+fp64"),
         "data": "synthetic (seed-free octahedral sphere mesh, Drude silver in water)",
         "config": {"workload": w.name, "panels": w.n_panels, "wavelengths": int(len(lam)),
                    "method": op["method"], "p": op["p"], "theta": op["theta"],

@@ -52,7 +52,7 @@ enum lspr_status {
 };
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
-enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2 };
+enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2, LSPR_FP32_LEAD64 = 3 };
 enum lspr_flags { LSPR_NO_MATRIX_CORES = 1, LSPR_NO_SPLIT_OPERATORS = 2 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
@@ -83,6 +83,11 @@ typedef struct {
  *             solves for corrections, and the residual b - A x of each outer step is formed
  *             with FP64 products; tol then applies to that FP64 residual, and lspr_apply uses
  *             the FP64 products.
+ *             LSPR_FP32_LEAD64: one GMRES whose product for a wavelength runs in FP64 while
+ *             that wavelength's residual estimate is above inner_tol ||b|| (the leading Krylov
+ *             vectors, whose coefficients in the solution are largest) and in FP32 after;
+ *             the true residual at each restart uses FP32 products, and lspr_apply uses the
+ *             FP64 products.  Needs the tile stores of both precisions.
  *   m2p_min_panels  a box that passes the MAC is expanded only if it holds at least this many
  *             panels, otherwise it is summed directly (cheaper for small boxes); 0 selects the
  *             library default (the number of expansion terms).  Accuracy is unaffected: a
@@ -117,9 +122,10 @@ typedef struct {
  *   max_iter  total iteration cap per wavelength
  *   precond   0 = none, 1 = right block-Jacobi with the 2x2 self-panel blocks (does not
  *             change the solution, only the iteration count)
- *   inner_tol LSPR_FP32_REFINE64 only: relative tolerance of each inner FP32 solve
- *             (0 selects 1e-4); max_iter then caps the inner iterations summed over the
- *             outer steps */
+ *   inner_tol LSPR_FP32_REFINE64: relative tolerance of each inner FP32 solve (0 selects
+ *             1e-4); max_iter then caps the inner iterations summed over the outer steps.
+ *             LSPR_FP32_LEAD64: relative residual level below which a wavelength's products
+ *             switch from FP64 to FP32 (0 selects 0.3).  Ignored otherwise. */
 typedef struct {
     double tol;
     int32_t restart;
@@ -300,7 +306,8 @@ int lspr_server_destroy(lspr_server* sv);
 
 /* Admission estimate: an upper bound of the device bytes one request with N panels on n_surf
  * surfaces and n_lambda wavelengths holds at its peak (set-up, matrix-core tiles up to their
- * cap, GMRES state for one batch of at most 64 wavelengths). */
+ * cap, GMRES state for one batch of at most 64 wavelengths).  Host arithmetic only (no device
+ * call).  LSPR_E_INVALID for null pointers, non-positive sizes or an unknown precision. */
 int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
                            const lspr_op_params* op, const lspr_gmres_params* gm,
                            int64_t* bytes);

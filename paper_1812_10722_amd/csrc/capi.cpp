@@ -142,7 +142,7 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
              "unknown method");
     LSPR_REQUIRE(op->precision == LSPR_FP32 || op->precision == LSPR_FP64 ||
-                     op->precision == LSPR_FP32_REFINE64,
+                     op->precision == LSPR_FP32_REFINE64 || op->precision == LSPR_FP32_LEAD64,
                  LSPR_E_INVALID, "unknown precision");
     if (op->method == LSPR_TREECODE) {
         LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,

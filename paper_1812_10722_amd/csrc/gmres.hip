@@ -20,7 +20,12 @@
 // tolerance (or the cycle or the iteration budget ends) the column is finalised with an inner
 // product pass alone, so no matrix-vector product is wasted.  The host only launches kernels
 // and reads two residual estimates per wavelength per step to retire converged wavelengths,
-// which then leave the matrix-vector product.  x0 = 0; a wavelength stops when
+// which then leave the matrix-vector product.  With LSPR_FP32_LEAD64 a wavelength's product
+// runs in FP64 while its residual estimate is above a level (inner_tol, default 0.3, relative
+// to ||b||) and in FP32 after: the error of the product of basis vector q_j reaches the
+// solution scaled by its coefficient y_j, and these fall with the residual (the relaxation
+// results for inexact Krylov methods: Simoncini and Szyld 2003, van den Eshof and Sleijpen
+// 2004), so only the first few products need FP64.  x0 = 0; a wavelength stops when
 // ||b - A x|| <= tol ||b||, checked on the true residual at each restart.  Optional right
 // block-Jacobi preconditioning with the 2x2 self-panel blocks (K_ii = 0 on flat panels) does not
 // change the solution.
@@ -660,6 +665,9 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     res.rel_resid.assign(B, 0.0);
     std::vector<int32_t> jn(B, 0);
     std::vector<double> bnorm(B), nrm_h(B);
+    const bool lead = prec == LSPR_FP32_LEAD64;
+    const double lead_level = gm.inner_tol > 0.0 ? gm.inner_tol : 0.3;
+    std::vector<double> level(B, 1.0);  // latest relative residual estimate per column
     // the two estimates of every column come back through pinned memory in one copy per step
     double* est_h = pinned_estimates(2 * B);
     const double* ef_h = est_h;
@@ -740,7 +748,20 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
                 vin = z.p;
                 vin_stride = nvec;
             }
-            system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+            if (lead) {
+                std::vector<int32_t> hi, lo;
+                for (int b : running) (level[b] > lead_level ? hi : lo).push_back(b);
+                for (int h = 0; h < 2; ++h) {
+                    const std::vector<int32_t>& c = h == 0 ? hi : lo;
+                    if (c.empty()) continue;
+                    upload_cols(c);
+                    system_apply(g, h == 0 ? LSPR_FP64 : LSPR_FP32, static_cast<int>(c.size()),
+                                 ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+                }
+                upload_cols(running);
+            } else {
+                system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+            }
             {
                 // one pass reading j basis vectors, p and w; one reading them again and writing
                 // two vectors
@@ -757,6 +778,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
             std::vector<int32_t> still, cand;
             for (int b : running) {
                 res.iters[b] += 1;
+                level[b] = (j >= 1 ? std::min(ef_h[b], ep_h[b]) : ep_h[b]) / bnorm[b];
                 if (j >= 1 && ef_h[b] <= gm.tol * bnorm[b]) {
                     jn[b] = j;  // dimension j already meets the tolerance
                     continue;
@@ -802,7 +824,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
             hipLaunchKernelGGL(k_axpy, dim3(nblk, ns), dim3(GT), 0, s, w.p, x, nvec, cols_d.p);
         }
         LSPR_HIP(hipGetLastError());
-        system_apply(g, prec, ns, ratio_d, x, nvec, w.p, nvec, cols_d.p, s);
+        system_apply(g, lead ? LSPR_FP32 : prec, ns, ratio_d, x, nvec, w.p, nvec, cols_d.p, s);
         hipLaunchKernelGGL(k_resid, dim3(nblk, ns), dim3(GT), 0, s, bvec.p, w.p, V.p, m1 * nvec,
                            nvec, cols_d.p);
         LSPR_HIP(hipGetLastError());
@@ -810,6 +832,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
         std::vector<int32_t> cont;
         for (int b : active) {
             res.rel_resid[b] = nrm_h[b] / bnorm[b];
+            level[b] = res.rel_resid[b];
             if (res.rel_resid[b] <= gm.tol) continue;
             if (res.iters[b] >= gm.max_iter) {
                 res.all_converged = false;

@@ -201,6 +201,8 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
     return guarded([&] {
         LSPR_REQUIRE(op && gm && bytes && n_panels > 0 && n_surf >= 1 && n_lambda >= 1,
                      LSPR_E_INVALID, "bad arguments");
+        LSPR_REQUIRE(op->precision >= LSPR_FP64 && op->precision <= LSPR_FP32_LEAD64,
+                     LSPR_E_INVALID, "unknown precision");
         *bytes = lspr::request_footprint(n_panels, n_surf, n_lambda, *op, *gm);
         return LSPR_OK;
     });

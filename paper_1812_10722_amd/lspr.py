@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_HERE, "liblspr.so")
 
 LSPR_OK, LSPR_E_INVALID, LSPR_E_MESH, LSPR_E_NOMEM, LSPR_E_DEVICE, LSPR_E_NOCONV, LSPR_E_BUSY = range(7)
 LSPR_DENSE, LSPR_TREECODE = 0, 1
-LSPR_FP64, LSPR_FP32, LSPR_FP32_REFINE64 = 0, 1, 2
-_PRECISION = {"fp64": LSPR_FP64, "fp32": LSPR_FP32, "fp32_refine64": LSPR_FP32_REFINE64}
+LSPR_FP64, LSPR_FP32, LSPR_FP32_REFINE64, LSPR_FP32_LEAD64 = 0, 1, 2, 3
+_PRECISION = {"fp64": LSPR_FP64, "fp32": LSPR_FP32, "fp32_refine64": LSPR_FP32_REFINE64,
+              "fp32_lead64": LSPR_FP32_LEAD64}
 
 
 class lspr_c64(C.Structure):

@@ -118,3 +118,17 @@ def test_resonance_peak_edges_and_errors(lib):
         lib.lspr_resonance_peak(x[::-1], np.ones(4))
     with pytest.raises(lib.LsprError):
         lib.lspr_resonance_peak(x[:2], np.ones(2))
+
+
+def test_footprint_counts_the_tile_stores_of_each_precision(lib):
+    """Host-only arithmetic: a mode that runs products in both precisions holds both tile
+    stores, so its estimate exceeds either single-precision mode's; the refinement mode adds
+    its four outer vectors on top."""
+    gm = lib.gmres_params(tol=1e-5, restart=60, max_iter=600)
+    est = {p: lib.lspr_request_footprint(32768, 1, 64, lib.op_params(p=8, precision=p), gm)
+           for p in ("fp32", "fp64", "fp32_refine64", "fp32_lead64")}
+    assert est["fp32"] < est["fp64"] < est["fp32_lead64"] < est["fp32_refine64"], est
+    bad = lib.op_params(p=8)
+    bad.precision = 7
+    with pytest.raises(lib.LsprError):
+        lib.lspr_request_footprint(32768, 1, 64, bad, gm)

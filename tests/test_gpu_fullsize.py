@@ -26,14 +26,15 @@ def lib():
     return lspr
 
 
-def _sampled_row_parity(lib, w, n_rows, n_cols, tol, seed=0):
+def _sampled_row_parity(lib, w, n_rows, n_cols, tol, seed=0, precision=None):
     v, t, sid = merge_surfaces(w.surfaces)
     N = len(t)
     rng = np.random.default_rng(seed)
     cols = np.linspace(0, len(w.lambdas) - 1, n_cols).round().astype(int)
     em, es = w.eps_medium[cols], w.eps_surface[cols]
     x = rng.standard_normal((n_cols, 2 * N)) + 1j * rng.standard_normal((n_cols, 2 * N))
-    geo = lib.Geometry(w.surfaces, op=lib.op_params(**w.op))
+    op = dict(w.op, precision=precision) if precision else w.op
+    geo = lib.Geometry(w.surfaces, op=lib.op_params(**op))
     try:
         y = geo.apply(torch.as_tensor(x).cuda(), em, es).cpu().numpy()
     finally:
@@ -56,7 +57,12 @@ def _sampled_row_parity(lib, w, n_rows, n_cols, tol, seed=0):
 
 def test_sweep_workload_sampled_rows(lib):
     """32768-panel sphere, FP32 treecode, all 64 wavelengths in one product (as timed)."""
-    _sampled_row_parity(lib, workload("sphere_32k_sweep"), 48, 64, 1e-4)
+    _sampled_row_parity(lib, workload("sphere_32k_sweep"), 48, 64, 1e-4, precision="fp32")
+
+
+def test_sweep_workload_sampled_rows_fp64(lib):
+    """The same geometry's FP64 product (the leading Krylov vectors of every solve)."""
+    _sampled_row_parity(lib, workload("sphere_32k_sweep"), 32, 16, 3e-5, seed=1)
 
 
 def test_sensor_two_analytes_sampled_rows(lib):

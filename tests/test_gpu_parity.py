@@ -186,7 +186,8 @@ def test_short_restart_cycles(lib, sphere_512_ref, restart):
                                                   ("treecode", "fp64", 1e-4),
                                                   ("treecode", "fp32", 1e-4),
                                                   ("dense", "fp32_refine64", 1e-6),
-                                                  ("treecode", "fp32_refine64", 1e-4)])
+                                                  ("treecode", "fp32_refine64", 1e-4),
+                                                  ("treecode", "fp32_lead64", 1e-4)])
 def test_spectrum_matches_oracle(lib, method, precision, tol):
     """A spectrum across the Drude resonance (8 wavelengths, 2048-panel sphere, E along x):
     every wavelength's C_ext within the path's bar of the oracle's LU value."""
@@ -197,8 +198,8 @@ def test_spectrum_matches_oracle(lib, method, precision, tol):
     e = [1.0, 0.0, 0.0]
     ref = oracle.solve(v, t, np.zeros(len(t), int), lam, em, es, e, k_far=4, k_fine=19)
     geo = lib.Geometry([(v, t)], method=method, precision=precision, p=8, theta=0.5)
-    out = geo.solve(lam, em, es, e, tol=1e-6 if precision == "fp32" else 1e-9, restart=80,
-                    max_iter=800)
+    fp32_resid = precision in ("fp32", "fp32_lead64")  # the residual uses FP32 products
+    out = geo.solve(lam, em, es, e, tol=1e-6 if fp32_resid else 1e-9, restart=80, max_iter=800)
     assert out["converged"]
     rel = np.abs(out["cext_sensor"] / ref["cext_sensor"] - 1)
     assert rel.max() < tol, rel
@@ -279,3 +280,28 @@ def test_refinement_reaches_fp64_solution(lib):
         assert out["converged"] and (out["rel_resid"] <= 1e-9).all(), out["rel_resid"]
         rel = np.abs(out["cext_total"] / ref["cext_total"] - 1)
         assert rel.max() < 1e-7, (inner, rel)
+
+
+def test_leading_fp64_products(lib):
+    """FP64 products for each wavelength's leading Krylov vectors, FP32 after.  With a switch
+    level below every residual all products are FP64 and the solve needs no more iterations
+    than the FP64 mode; at the default level no more than with FP32 products throughout; both
+    give the FP64 solve's C_ext within the tolerance's reach."""
+    v, t = octasphere(16, 10.0)
+    lam = np.array([370.0, 384.0, 400.0])
+    em = np.full(3, EPS_WATER + 0j)
+    es = eps_silver_drude(lam)[:, None]
+    kw = dict(method="treecode", p=8, theta=0.5)
+    gm = dict(tol=1e-6, restart=60, max_iter=600)
+    o64 = lib.Geometry([(v, t)], precision="fp64", **kw).solve(lam, em, es, **gm)
+    o32 = lib.Geometry([(v, t)], precision="fp32", **kw).solve(lam, em, es, **gm)
+    geo = lib.Geometry([(v, t)], precision="fp32_lead64", **kw)
+    lead = geo.solve(lam, em, es, **gm)
+    all64 = geo.solve(lam, em, es, inner_tol=1e-15, **gm)
+    for out in (o64, o32, lead, all64):
+        assert out["converged"] and (out["rel_resid"] <= 1e-6).all(), out["rel_resid"]
+    assert (lead["iters"] <= o32["iters"] + 1).all(), (lead["iters"], o32["iters"])
+    assert (all64["iters"] <= o64["iters"] + 1).all(), (all64["iters"], o64["iters"])
+    for out in (lead, all64):
+        rel = np.abs(out["cext_total"] / o64["cext_total"] - 1)
+        assert rel.max() < 2e-5, rel
