@@ -346,7 +346,7 @@ size_t lspr::Geometry::device_bytes() const {
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
-           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
+           ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2mA64.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 

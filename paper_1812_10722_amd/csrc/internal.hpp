@@ -245,7 +245,8 @@ struct Geometry {
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
     DevBuf<float> p2mA;          // FP32 folded node polynomials per P2M segment (matrix cores)
-    DevBuf<int64_t> p2m_aoff;    // [n_seg] offset of each segment's block in p2mA
+    DevBuf<double> p2mA64;       // FP64 ones, same element offsets
+    DevBuf<int64_t> p2m_aoff;    // [n_seg] offset of each segment's block in p2mA / p2mA64
     DevBuf<P2MRed> p2m_red;
     DevBuf<int32_t> mom_boxes_d;
     int n_chunks = 0;

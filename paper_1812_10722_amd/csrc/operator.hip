@@ -831,15 +831,16 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 // node polynomial of panel j (V polynomial for the V columns, K polynomial for the K columns).
 // k_build_p2m_tiles stores A once per geometry, segment by segment (P2MSeg: at most 128 panels
 // of one box), as [step][row tile][lane] with step = 4 panels and lane l holding
-// A[16 rt + l % 16][4 step + l / 16] (the v_mfma_f32_16x16x4f32 operand order); the K block of a
-// segment follows its V block.  k_p2m_mfma then forms each segment's moments on matrix cores.
+// A[16 rt + l % 16][4 step + l / 16] (the operand order of v_mfma_f32_16x16x4f32 and of
+// v_mfma_f64_16x16x4f64); the K block of a segment follows its V block.  k_p2m_mfma then forms
+// each segment's moments on matrix cores, in the precision of the product.
 template <int P>
 constexpr int p2m_row_tiles() { return (Expansion<P>::NR + 15) / 16; }
 
-template <int P>
+template <class T, int P>
 __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
                                   const int64_t* __restrict__ aoff, const double* __restrict__ cen,
-                                  const float* __restrict__ src, int K, float* __restrict__ A) {
+                                  const T* __restrict__ src, int K, T* __restrict__ A) {
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
@@ -848,7 +849,7 @@ __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* _
     if (j >= sg.end) return;
     const Box B = boxes[sg.box];
     const int rs = 4 + 4 * K;
-    const float* r = src + static_cast<size_t>(j) * rs;
+    const T* r = src + static_cast<size_t>(j) * rs;
     double pv[NF], pk[NF];
     for (int t = 0; t < NF; ++t) pv[t] = pk[t] = 0.0;
     for (int gq = 0; gq < K; ++gq) {
@@ -880,22 +881,22 @@ __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* _
     }
     const int p = j - sg.start, st = p >> 2, kk = p & 3;
     const int steps = (sg.end - sg.start + 3) / 4;
-    float* AV = A + aoff[blockIdx.x];
-    float* AK = AV + static_cast<size_t>(steps) * RT * 64;
+    T* AV = A + aoff[blockIdx.x];
+    T* AK = AV + static_cast<size_t>(steps) * RT * 64;
     for (int q = 0; q < NR; ++q) {
         const int rt = q >> 4, lane = (q & 15) + 16 * kk;
         const size_t idx = (static_cast<size_t>(st) * RT + rt) * 64 + lane;
-        AV[idx] = static_cast<float>(pv[ex.rfull[q]]);
-        AK[idx] = static_cast<float>(pk[ex.rfull[q]]);
+        AV[idx] = static_cast<T>(pv[ex.rfull[q]]);
+        AK[idx] = static_cast<T>(pk[ex.rfull[q]]);
     }
 }
 
 // Workgroup = (segment, operator, column half): 4 waves, each 16 columns of one operator.
-template <int RT, int NR>
+template <class T, int RT, int NR>
 __global__ void __launch_bounds__(256)
 k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
-           const float* __restrict__ A, const float* __restrict__ dens, int pad, int nwc,
-           float* __restrict__ mom, float* __restrict__ part) {
+           const T* __restrict__ A, const T* __restrict__ dens, int pad, int nwc,
+           T* __restrict__ mom, T* __restrict__ part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c16 = lane & 15, grp = lane >> 4;
     const int opr = blockIdx.y & 1, wg = wave + 4 * (blockIdx.y >> 1);
@@ -904,28 +905,27 @@ k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
     const int col = opr * pad + 16 * wg + c16;
     const P2MSeg sg = segs[blockIdx.x];
     const int np = sg.end - sg.start, steps = (np + 3) / 4;
-    const float* Ab = A + aoff[blockIdx.x] + (opr == 0 ? static_cast<size_t>(steps) * RT * 64 : 0);
-    const float* Db = dens + static_cast<size_t>(sg.start) * ncols + col;
-    v4f acc[RT];
+    const T* Ab = A + aoff[blockIdx.x] + (opr == 0 ? static_cast<size_t>(steps) * RT * 64 : 0);
+    const T* Db = dens + static_cast<size_t>(sg.start) * ncols + col;
+    typename Mma<T>::acc acc[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < RT; ++t) acc[t] = typename Mma<T>::acc{0, 0, 0, 0};
 #pragma unroll 2
     for (int st = 0; st < steps; ++st) {
         const int p = 4 * st + grp;
-        const float b = Db[static_cast<size_t>(p < np ? p : 0) * ncols];
-        const float bb = p < np ? b : 0.f;
-        const float* a = Ab + static_cast<size_t>(st) * RT * 64 + lane;
+        const T b = Db[static_cast<size_t>(p < np ? p : 0) * ncols];
+        const T bb = p < np ? b : T(0);
+        const T* a = Ab + static_cast<size_t>(st) * RT * 64 + lane;
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t * 64], bb, acc[t], 0, 0, 0);
+        for (int t = 0; t < RT; ++t) acc[t] = Mma<T>::op(a[t * 64], bb, acc[t]);
     }
-    float* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * NR * ncols
-                             : part + static_cast<size_t>(sg.slot) * NR * ncols;
+    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * NR * ncols
+                         : part + static_cast<size_t>(sg.slot) * NR * ncols;
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int q = 16 * t + 4 * grp + i;
+            const int q = 16 * t + out_row<T>(grp, i);
             if (q < NR) out[static_cast<size_t>(q) * ncols + col] = acc[t][i];
         }
 }
@@ -1233,41 +1233,43 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
 #undef LSPR_FAR_TILES
 }
 
-template <int P>
-void launch_p2m_mfma(Geometry& g, int pad, const float* dens, float* mom, hipStream_t s) {
+inline const float* p2m_tiles_of(const Geometry& g, const float*) { return g.p2mA.p; }
+inline const double* p2m_tiles_of(const Geometry& g, const double*) { return g.p2mA64.p; }
+
+template <class T, int P>
+void launch_p2m_mfma(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
     if (g.n_seg == 0) return;
     constexpr int NR = Expansion<P>::NR, RT = p2m_row_tiles<P>();
     const int ncols = 2 * pad;
-    float* part = nullptr;
+    T* part = nullptr;
     if (g.n_slots > 0) {
-        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * NR * ncols * sizeof(float));
-        part = reinterpret_cast<float*>(g.ws_part.p);
+        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * NR * ncols * sizeof(T));
+        part = reinterpret_cast<T*>(g.ws_part.p);
     }
     const int halves = pad > 64 ? 2 : 1;
-    hipLaunchKernelGGL((k_p2m_mfma<RT, NR>), dim3(g.n_seg, 2 * halves), dim3(256), 0, s,
-                       g.p2m_seg.p, g.p2m_aoff.p, g.p2mA.p, dens, pad, pad / 16, mom, part);
+    hipLaunchKernelGGL((k_p2m_mfma<T, RT, NR>), dim3(g.n_seg, 2 * halves), dim3(256), 0, s,
+                       g.p2m_seg.p, g.p2m_aoff.p, p2m_tiles_of(g, dens), dens, pad, pad / 16,
+                       mom, part);
     LSPR_HIP(hipGetLastError());
     if (g.n_red > 0) {
         const int64_t tot = static_cast<int64_t>(g.n_red) * NR * ncols;
-        hipLaunchKernelGGL(k_p2m_reduce<float>, dim3((tot + 255) / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_p2m_reduce<T>, dim3((tot + 255) / 256), dim3(256), 0, s,
                            g.p2m_red.p, g.n_red, NR, ncols, part, mom);
         LSPR_HIP(hipGetLastError());
     }
 }
 
-// Moments on matrix cores when the geometry holds FP32 polynomial tiles; false otherwise.
-inline bool launch_p2m_tiles(Geometry& g, const Cols& c, const double*, double*, hipStream_t) {
-    return false;
-}
-inline bool launch_p2m_tiles(Geometry& g, const Cols& c, const float* dens, float* mom,
-                             hipStream_t s) {
-    if (!c.mfma || g.p2mA.p == nullptr) return false;
+// Moments on matrix cores when the geometry holds polynomial tiles of the product's
+// precision; false otherwise.
+template <class T>
+bool launch_p2m_tiles(Geometry& g, const Cols& c, const T* dens, T* mom, hipStream_t s) {
+    if (!c.mfma || p2m_tiles_of(g, dens) == nullptr) return false;
     switch (g.P) {
-        case 2: launch_p2m_mfma<2>(g, c.pad, dens, mom, s); break;
-        case 4: launch_p2m_mfma<4>(g, c.pad, dens, mom, s); break;
-        case 6: launch_p2m_mfma<6>(g, c.pad, dens, mom, s); break;
-        case 8: launch_p2m_mfma<8>(g, c.pad, dens, mom, s); break;
-        case 10: launch_p2m_mfma<10>(g, c.pad, dens, mom, s); break;
+        case 2: launch_p2m_mfma<T, 2>(g, c.pad, dens, mom, s); break;
+        case 4: launch_p2m_mfma<T, 4>(g, c.pad, dens, mom, s); break;
+        case 6: launch_p2m_mfma<T, 6>(g, c.pad, dens, mom, s); break;
+        case 8: launch_p2m_mfma<T, 8>(g, c.pad, dens, mom, s); break;
+        case 10: launch_p2m_mfma<T, 10>(g, c.pad, dens, mom, s); break;
         default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
     }
     return true;
@@ -1286,11 +1288,22 @@ void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
     }
     g.p2m_aoff.alloc(g.n_seg);
     copy_sync(g.p2m_aoff.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
-    g.p2mA.alloc(std::max<int64_t>(tot, 1));
-    LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s));
-    hipLaunchKernelGGL(k_build_p2m_tiles<P>, dim3(g.n_seg), dim3(128), 0, s, g.boxes.p,
-                       g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K, g.p2mA.p);
-    LSPR_HIP(hipGetLastError());
+    if (g.tileA.p != nullptr) {
+        g.p2mA.alloc(std::max<int64_t>(tot, 1));
+        LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s));
+        hipLaunchKernelGGL((k_build_p2m_tiles<float, P>), dim3(g.n_seg), dim3(128), 0, s,
+                           g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K,
+                           g.p2mA.p);
+        LSPR_HIP(hipGetLastError());
+    }
+    if (g.tileA64.p != nullptr) {
+        g.p2mA64.alloc(std::max<int64_t>(tot, 1));
+        LSPR_HIP(hipMemsetAsync(g.p2mA64.p, 0, g.p2mA64.bytes(), s));
+        hipLaunchKernelGGL((k_build_p2m_tiles<double, P>), dim3(g.n_seg), dim3(128), 0, s,
+                           g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src64.p, g.K,
+                           g.p2mA64.p);
+        LSPR_HIP(hipGetLastError());
+    }
     LSPR_HIP(hipStreamSynchronize(s));
 }
 
@@ -1575,7 +1588,7 @@ void build_tiles(Geometry& g) {
         g.near_in_tiles64 = fold_near(g, g.tileA64.p, dto_d.p, dtr_d.p, dti_d.p, s, build);
     }
     LSPR_HIP(hipStreamSynchronize(s));
-    if (keep32 && g.n_seg > 0) {  // moments on matrix cores as well
+    if (g.n_seg > 0) {  // moments on matrix cores as well, for each precision with tiles
         switch (g.P) {
             case 2: build_p2m_tiles_p<2>(g, s); break;
             case 4: build_p2m_tiles_p<4>(g, s); break;

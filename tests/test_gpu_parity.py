@@ -101,7 +101,8 @@ def test_treecode_error_falls_with_order(lib, precision):
 
 @pytest.mark.parametrize("method,ncol,precision", [("treecode", 20, "fp32"), ("dense", 9, "fp32"),
                                                    ("treecode", 64, "fp32"),
-                                                   ("treecode", 20, "fp64"), ("dense", 9, "fp64")])
+                                                   ("treecode", 20, "fp64"), ("treecode", 64, "fp64"),
+                                                   ("dense", 9, "fp64")])
 def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol, precision):
     """Products run on matrix cores from precomputed tiles (FP32 or FP64); they must equal the
     vector-ALU kernel (same sums, different order: FP32 3e-6, FP64 1e-12 of the largest
