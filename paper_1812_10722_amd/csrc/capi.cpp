@@ -70,6 +70,75 @@ hipMemPool_t library_pool() {
     return pool;
 }
 
+namespace {
+struct CachedBlock {
+    hipMemPool_t pool;
+    void* p;
+    size_t bytes;
+    hipEvent_t ready;
+};
+std::mutex cache_mu;
+std::vector<CachedBlock> cache;  // every device's pools; blocks are few and large
+constexpr size_t CACHE_CAP = 16ull << 30;
+size_t cached_bytes(hipMemPool_t pool) {
+    size_t t = 0;
+    for (const CachedBlock& b : cache) t += b.pool == pool ? b.bytes : 0;
+    return t;
+}
+}  // namespace
+
+void* big_block_take(hipMemPool_t pool, size_t bytes, hipStream_t s, size_t* got) {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    // the smallest block that holds the request and wastes at most a quarter of it
+    int best = -1;
+    for (size_t i = 0; i < cache.size(); ++i) {
+        const CachedBlock& b = cache[i];
+        if (b.pool != pool || b.bytes < bytes || b.bytes > bytes + bytes / 4) continue;
+        if (best < 0 || b.bytes < cache[best].bytes) best = static_cast<int>(i);
+    }
+    if (best < 0) return nullptr;
+    const CachedBlock b = cache[best];
+    cache.erase(cache.begin() + best);
+    LSPR_HIP(hipStreamWaitEvent(s, b.ready, 0));
+    (void)hipEventDestroy(b.ready);
+    *got = b.bytes;
+    return b.p;
+}
+
+bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    if (cached_bytes(pool) + bytes > CACHE_CAP) return false;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return false;
+    }
+    cache.push_back({pool, p, bytes, ev});
+    return true;
+}
+
+bool big_block_flush(hipMemPool_t pool) {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    bool any = false;
+    for (size_t i = 0; i < cache.size();) {
+        if (cache[i].pool != pool) {
+            ++i;
+            continue;
+        }
+        (void)hipEventSynchronize(cache[i].ready);
+        (void)hipEventDestroy(cache[i].ready);
+        (void)hipFreeAsync(cache[i].p, nullptr);
+        cache.erase(cache.begin() + i);
+        any = true;
+    }
+    if (any) {
+        (void)hipStreamSynchronize(nullptr);
+        (void)hipMemPoolTrimTo(pool, 0);
+    }
+    return any;
+}
+
 void validate_mesh_host(const lspr_surface* surfaces, int n_surf) {
     LSPR_REQUIRE(surfaces && n_surf >= 1, LSPR_E_INVALID, "need at least one surface");
     for (int s = 0; s < n_surf; ++s) {

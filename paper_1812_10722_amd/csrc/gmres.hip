@@ -636,6 +636,14 @@ PinnedCols& pinned_cols() {
     return pc;
 }
 
+struct Event {
+    hipEvent_t e = nullptr;
+    Event() { LSPR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+    ~Event() { (void)hipEventDestroy(e); }
+    Event(const Event&) = delete;
+    Event& operator=(const Event&) = delete;
+};
+
 }  // namespace
 
 SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
@@ -717,6 +725,37 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     }
     // inner products of step j (nq final vectors, provisional vector in slot nq) for the columns
     // in cols_d, then the per-column finishing kernel
+    // w = A M^{-1} V_j for the listed columns; with LSPR_FP32_LEAD64 in FP64 for the columns
+    // whose residual estimate is above the level, in FP32 for the others
+    auto product = [&](int j, const std::vector<int32_t>& c) {
+        upload_cols(c);
+        const int ns = static_cast<int>(c.size());
+        const double2* vin = V.p + j * nvec;
+        int64_t vin_stride = m1 * nvec;
+        if (pre) {
+            const int64_t t = static_cast<int64_t>(g.N) * ns;
+            hipLaunchKernelGGL(k_precond, dim3((t + 255) / 256), dim3(256), 0, s, vin,
+                               vin_stride, z.p, nvec, g.N, cols_d.p, ns, ratio_d, g.S,
+                               g.surf.p, g.vself.p, 0);
+            LSPR_HIP(hipGetLastError());
+            vin = z.p;
+            vin_stride = nvec;
+        }
+        if (!lead) {
+            system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+            return;
+        }
+        std::vector<int32_t> hi, lo;
+        for (int b : c) (level[b] > lead_level ? hi : lo).push_back(b);
+        for (int h = 0; h < 2; ++h) {
+            const std::vector<int32_t>& part_c = h == 0 ? hi : lo;
+            if (part_c.empty()) continue;
+            upload_cols(part_c);
+            system_apply(g, h == 0 ? LSPR_FP64 : LSPR_FP32, static_cast<int>(part_c.size()),
+                         ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+        }
+    };
+    Event est_ready;
     auto reduce_finish = [&](int ns, int nq, int with_w, int mode, int j) {
         if (with_w)
             hipLaunchKernelGGL(k_dcgs_red<1>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
@@ -732,36 +771,13 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     while (!active.empty()) {
         // ---------------- one restart cycle over the active columns
         std::vector<int32_t> running = active;
+        bool queued = false;  // the product of step j is already queued for running's columns
         for (int b : active) jn[b] = 0;
         LSPR_HIP(hipMemsetAsync(fin.p, 0xff, B * sizeof(int32_t), s));  // no final column yet
         for (int j = 0; j < m && !running.empty(); ++j) {
+            if (!queued) product(j, running);
             upload_cols(running);
             const int ns = static_cast<int>(running.size());
-            const double2* vin = V.p + j * nvec;
-            int64_t vin_stride = m1 * nvec;
-            if (pre) {
-                const int64_t t = static_cast<int64_t>(g.N) * ns;
-                hipLaunchKernelGGL(k_precond, dim3((t + 255) / 256), dim3(256), 0, s, vin,
-                                   vin_stride, z.p, nvec, g.N, cols_d.p, ns, ratio_d, g.S,
-                                   g.surf.p, g.vself.p, 0);
-                LSPR_HIP(hipGetLastError());
-                vin = z.p;
-                vin_stride = nvec;
-            }
-            if (lead) {
-                std::vector<int32_t> hi, lo;
-                for (int b : running) (level[b] > lead_level ? hi : lo).push_back(b);
-                for (int h = 0; h < 2; ++h) {
-                    const std::vector<int32_t>& c = h == 0 ? hi : lo;
-                    if (c.empty()) continue;
-                    upload_cols(c);
-                    system_apply(g, h == 0 ? LSPR_FP64 : LSPR_FP32, static_cast<int>(c.size()),
-                                 ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
-                }
-                upload_cols(running);
-            } else {
-                system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
-            }
             {
                 // one pass reading j basis vectors, p and w; one reading them again and writing
                 // two vectors
@@ -774,7 +790,20 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
                 LSPR_HIP(hipGetLastError());
             }
             LSPR_HIP(hipMemcpyAsync(est_h, est.p, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
-            LSPR_HIP(hipStreamSynchronize(s));
+            // The next step's product for the same columns is queued behind the estimates when
+            // its precision cannot change (a column's estimate does not rise within a cycle),
+            // so the device computes it while the host reads the estimates.  Columns that
+            // then finish were multiplied for nothing; the others find w ready.
+            queued = j + 1 < m;
+            if (lead)
+                for (int b : running) queued = queued && level[b] <= lead_level;
+            if (queued) {
+                LSPR_HIP(hipEventRecord(est_ready.e, s));
+                product(j + 1, running);
+                LSPR_HIP(hipEventSynchronize(est_ready.e));
+            } else {
+                LSPR_HIP(hipStreamSynchronize(s));
+            }
             std::vector<int32_t> still, cand;
             for (int b : running) {
                 res.iters[b] += 1;

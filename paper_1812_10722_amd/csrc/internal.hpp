@@ -45,6 +45,7 @@ struct AllocCtx {
     hipStream_t stream = nullptr;
     bool free_on = false;
     hipStream_t free_stream = nullptr;
+    bool keep_big = false;  // large blocks of `pool` go to the block cache when released
     int64_t live = 0, peak = 0;
 };
 AllocCtx& alloc_ctx();
@@ -52,6 +53,20 @@ AllocCtx& alloc_ctx();
 // The library's memory pool on the current device (created on first use; keeps up to 16 GiB of
 // freed memory for reuse instead of returning it at every synchronisation).
 hipMemPool_t library_pool();
+
+// Cache of large released blocks of the library pool.  Returning a pool allocation of several
+// GB costs the host about 1.3 ms per GB, and obtaining it again a few tenths of a ms, so blocks
+// of at least BIG_BLOCK bytes are kept (up to 16 GiB per pool) and handed to the next request
+// of a size they cover.  A kept block is reusable once an event recorded on its last stream
+// has completed; the taker's stream waits for that event.
+constexpr size_t BIG_BLOCK = 32ull << 20;
+// A cached block of `pool` of at least `bytes` (and not much larger), ordered after its last
+// use on `s`; nullptr if none.  *got receives the block's size.
+void* big_block_take(hipMemPool_t pool, size_t bytes, hipStream_t s, size_t* got);
+// Keeps `p` (a block of `bytes` from `pool`, last used on `s`); false if the cache is full.
+bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s);
+// Frees every cached block of `pool` (after their last uses); true if there was any.
+bool big_block_flush(hipMemPool_t pool);
 
 // Installs the library pool and `stream` for allocations, and `stream` for frees, for the
 // lifetime of the object, unless the thread already has a pool (the request server's).
@@ -66,6 +81,7 @@ struct PoolScope {
         c.stream = stream;
         c.free_on = true;
         c.free_stream = stream;
+        c.keep_big = true;
         active = true;
     }
     ~PoolScope() {
@@ -87,6 +103,8 @@ struct DevBuf {
     size_t n = 0;
     hipStream_t free_stream = nullptr;
     bool pooled = false;
+    hipMemPool_t keep_pool = nullptr;  // set: the block goes back to the block cache
+    size_t block = 0;                  // bytes of the underlying block
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
@@ -103,7 +121,23 @@ struct DevBuf {
         AllocCtx& c = alloc_ctx();
         const size_t b = count * sizeof(T);
         if (c.pool) {
-            LSPR_HIP(hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), b, c.pool, c.stream));
+            block = b;
+            void* q = nullptr;
+            if (c.keep_big && b >= BIG_BLOCK) {
+                keep_pool = c.pool;
+                q = big_block_take(c.pool, b, c.stream, &block);
+            }
+            if (q == nullptr) {
+                hipError_t e = hipMallocFromPoolAsync(&q, b, c.pool, c.stream);
+                if (e == hipErrorOutOfMemory && c.keep_big) {
+                    (void)hipGetLastError();  // clear the recorded failure before retrying
+                    if (big_block_flush(c.pool))
+                        e = hipMallocFromPoolAsync(&q, b, c.pool, c.stream);
+                }
+                LSPR_HIP(e);
+                block = b;
+            }
+            p = static_cast<T*>(q);
             free_stream = c.stream;
             pooled = true;
         } else {
@@ -120,7 +154,9 @@ struct DevBuf {
         if (p) {
             if (pooled) {
                 const AllocCtx& c = alloc_ctx();
-                (void)hipFreeAsync(p, c.free_on ? c.free_stream : free_stream);
+                hipStream_t fs = c.free_on ? c.free_stream : free_stream;
+                if (keep_pool == nullptr || !big_block_put(keep_pool, p, block, fs))
+                    (void)hipFreeAsync(p, fs);
             }
             else (void)hipFree(p);
             alloc_ctx().live -= static_cast<int64_t>(bytes());
@@ -128,6 +164,8 @@ struct DevBuf {
         p = nullptr;
         n = 0;
         pooled = false;
+        keep_pool = nullptr;
+        block = 0;
     }
     size_t bytes() const { return n * sizeof(T); }
     T* get() const { return p; }
@@ -135,7 +173,8 @@ struct DevBuf {
   private:
     void take(DevBuf& o) {
         p = o.p; n = o.n; free_stream = o.free_stream; pooled = o.pooled;
-        o.p = nullptr; o.n = 0; o.pooled = false;
+        keep_pool = o.keep_pool; block = o.block;
+        o.p = nullptr; o.n = 0; o.pooled = false; o.keep_pool = nullptr; o.block = 0;
     }
 };
 

@@ -832,15 +832,18 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 // k_build_p2m_tiles stores A once per geometry, segment by segment (P2MSeg: at most 128 panels
 // of one box), as [step][row tile][lane] with step = 4 panels and lane l holding
 // A[16 rt + l % 16][4 step + l / 16] (the operand order of v_mfma_f32_16x16x4f32 and of
-// v_mfma_f64_16x16x4f64); the K block of a segment follows its V block.  k_p2m_mfma then forms
-// each segment's moments on matrix cores, in the precision of the product.
+// v_mfma_f64_16x16x4f64); the K block of a segment follows its V block.  One pass writes the
+// FP32 and / or FP64 copies (null when not kept), from the FP64 panel records when the geometry
+// has them.  k_p2m_mfma then forms each segment's moments on matrix cores, in the precision of
+// the product.
 template <int P>
 constexpr int p2m_row_tiles() { return (Expansion<P>::NR + 15) / 16; }
 
-template <class T, int P>
+template <class S, int P>
 __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
                                   const int64_t* __restrict__ aoff, const double* __restrict__ cen,
-                                  const T* __restrict__ src, int K, T* __restrict__ A) {
+                                  const S* __restrict__ src, int K, float* __restrict__ A32,
+                                  double* __restrict__ A64) {
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
@@ -849,7 +852,7 @@ __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* _
     if (j >= sg.end) return;
     const Box B = boxes[sg.box];
     const int rs = 4 + 4 * K;
-    const T* r = src + static_cast<size_t>(j) * rs;
+    const S* r = src + static_cast<size_t>(j) * rs;
     double pv[NF], pk[NF];
     for (int t = 0; t < NF; ++t) pv[t] = pk[t] = 0.0;
     for (int gq = 0; gq < K; ++gq) {
@@ -881,13 +884,19 @@ __global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* _
     }
     const int p = j - sg.start, st = p >> 2, kk = p & 3;
     const int steps = (sg.end - sg.start + 3) / 4;
-    T* AV = A + aoff[blockIdx.x];
-    T* AK = AV + static_cast<size_t>(steps) * RT * 64;
+    const size_t a0 = aoff[blockIdx.x], kb = static_cast<size_t>(steps) * RT * 64;
     for (int q = 0; q < NR; ++q) {
         const int rt = q >> 4, lane = (q & 15) + 16 * kk;
-        const size_t idx = (static_cast<size_t>(st) * RT + rt) * 64 + lane;
-        AV[idx] = static_cast<T>(pv[ex.rfull[q]]);
-        AK[idx] = static_cast<T>(pk[ex.rfull[q]]);
+        const size_t idx = a0 + (static_cast<size_t>(st) * RT + rt) * 64 + lane;
+        const double v = pv[ex.rfull[q]], k = pk[ex.rfull[q]];
+        if (A32 != nullptr) {
+            A32[idx] = static_cast<float>(v);
+            A32[idx + kb] = static_cast<float>(k);
+        }
+        if (A64 != nullptr) {
+            A64[idx] = v;
+            A64[idx + kb] = k;
+        }
     }
 }
 
@@ -1291,19 +1300,20 @@ void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
     if (g.tileA.p != nullptr) {
         g.p2mA.alloc(std::max<int64_t>(tot, 1));
         LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s));
-        hipLaunchKernelGGL((k_build_p2m_tiles<float, P>), dim3(g.n_seg), dim3(128), 0, s,
-                           g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K,
-                           g.p2mA.p);
-        LSPR_HIP(hipGetLastError());
     }
     if (g.tileA64.p != nullptr) {
         g.p2mA64.alloc(std::max<int64_t>(tot, 1));
         LSPR_HIP(hipMemsetAsync(g.p2mA64.p, 0, g.p2mA64.bytes(), s));
+    }
+    if (g.src64.p != nullptr)
         hipLaunchKernelGGL((k_build_p2m_tiles<double, P>), dim3(g.n_seg), dim3(128), 0, s,
                            g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src64.p, g.K,
-                           g.p2mA64.p);
-        LSPR_HIP(hipGetLastError());
-    }
+                           g.p2mA.p, g.p2mA64.p);
+    else
+        hipLaunchKernelGGL((k_build_p2m_tiles<float, P>), dim3(g.n_seg), dim3(128), 0, s,
+                           g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K,
+                           g.p2mA.p, g.p2mA64.p);
+    LSPR_HIP(hipGetLastError());
     LSPR_HIP(hipStreamSynchronize(s));
 }
 
