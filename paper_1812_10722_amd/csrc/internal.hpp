@@ -311,7 +311,7 @@ struct Geometry {
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
     hipStream_t stream = nullptr;
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
-    int far_op_min_pad = 16;  // FP32 products with at least this many columns per operator run
+    int far_op_min_pad = 16;  // products with at least this many columns per operator run
                               // one operator per workgroup (0: never)
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 40 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the

@@ -584,7 +584,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
 }
 
-// FP32 far field, one operator per workgroup.  Workgroups b, b + 8, ... handle one chunk (all on
+// One element of a raw buffer load (out-of-range offsets read zero).
+template <class T>
+__device__ __forceinline__ T load_elem(__amdgpu_buffer_rsrc_t rb, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float load_elem<float>(__amdgpu_buffer_rsrc_t rb, uint32_t voff,
+                                                  uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double load_elem<double>(__amdgpu_buffer_rsrc_t rb, uint32_t voff,
+                                                    uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, voff, soff, 0));
+}
+
+// Far field on matrix cores, one operator per workgroup (FP32 or FP64 products).  Workgroups b, b + 8, ... handle one chunk (all on
 // the same XCD, so the later ones read the chunk's left factors from L2): the double-layer (K)
 // and single-layer (V) columns, each in 1 or 2 halves of 4 column groups of 16, one group per
 // wave.  Expansion tiles share one left factor between the operators; direct tiles hold the K
@@ -594,18 +608,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
 // tile is requested into its register right after the current tile's step has used it; the
 // descriptor two tiles ahead comes with the vector loads.  No scalar load and no register spill
 // remains in the loop; at P = 8, 128 VGPRs and 21.5 KB of LDS: four workgroups (16 waves) per CU
-// (three at P = 10).
+// (three at P = 10).  FP64: the same scheme on v_mfma_f64_16x16x4f64, whose accumulators are
+// the FP64 sums themselves; the left factor takes twice the LDS, three workgroups per CU.
 // Narrow products (one or two column groups per operator) split the K-steps instead: S = 4 / G
 // waves share each of the G column groups, wave k taking steps k, k + S, ...; at the end their
 // FP64 sums are added in wave order through LDS.  S = 1 is the wide kernel.
-template <int NSM, int S>
-__global__ void __launch_bounds__(256, (S == 2 || NSM > 21) ? 3 : 4)
+template <class T, int NSM, int S>
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4))
 k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
-               const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
-               const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
+               const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
+               const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
                int halves, double* __restrict__ out_self, double* __restrict__ out_all) {
     constexpr int NTHR = 256;
+    constexpr uint32_t ES = sizeof(T);       // bytes per element
+    constexpr int EPU = 16 / sizeof(T);      // elements per 16-byte unit
+    using Acc = typename Mma<T>::acc;
     extern __shared__ float4 abuf16[];  // the current tile's left factor
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, grp = lane >> 4;
@@ -626,16 +644,21 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     const int col = opr * pad + 16 * wg + c16;  // this lane's column
     // B operand of K-step st: row 4 st + grp of the tile, column col, i.e. byte offset
     // boff + st * bstep from the tile's first row (rows past the tile read zero)
-    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * 4u;
-    const uint32_t bstep = 16u * static_cast<uint32_t>(ncols);
-    v4f acc[4];
-    double run[4][4];
+    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * ES;
+    const uint32_t bstep = 4u * ES * static_cast<uint32_t>(ncols);
+    Acc acc[4];
+    double run[4][4];  // FP32: FP64 running sums of the tiles' partials
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
+        acc[a] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) run[a][q] = 0.0;
     }
+    // this wave's sum of target row 16 mt + out_row(grp, q) of its column
+    auto own = [&](int mt, int q) -> double {
+        if constexpr (sizeof(T) == 4) return run[mt][q];
+        else return acc[mt][q];
+    };
     const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
     const int t_mid = t_beg + tile_self[chunk];
     // Writes the sums (with S > 1 the first wave of each column group adds the others' sums, in
@@ -645,17 +668,18 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sum[mt][q] = run[mt][q];
+            for (int q = 0; q < 4; ++q) sum[mt][q] = own(mt, q);
         if constexpr (S > 1) {
             // one 8 KB slot per column group, passed from wave to wave
-            constexpr int NAB = NSM > DSTEPS ? NSM : DSTEPS;  // float4 per lane of the buffer
-            double* red = reinterpret_cast<double*>(abuf16 + NAB * 64) + (wave / S) * 16 * 64;
+            constexpr int NAB = NSM > DSTEPS ? NSM : DSTEPS;  // 16-byte units per lane / EPU
+            double* red = reinterpret_cast<double*>(abuf16 + NAB * 64 * 4 / EPU) +
+                          (wave / S) * 16 * 64;
             for (int k = 1; k < S; ++k) {
                 if (kpart == k)
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) red[(4 * mt + q) * 64 + lane] = run[mt][q];
+                        for (int q = 0; q < 4; ++q) red[(4 * mt + q) * 64 + lane] = own(mt, q);
                 __syncthreads();
                 if (kpart == 0)
 #pragma unroll
@@ -670,7 +694,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int t = 16 * mt + 4 * grp + q;
+                const int t = 16 * mt + out_row<T>(grp, q);
                 if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = sum[mt][q];
             }
     };
@@ -680,17 +704,17 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     // operands overlap the whole previous tile with one register per step.
     constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
     constexpr int NBS = (NB + S - 1) / S;  // operand registers per wave
-    auto b_rsrc = [&](const TileDesc& T, uint32_t rows) {
-        const float* bsrc = T.kind == 0 ? mom : dens;
-        return buffer_rsrc(bsrc + static_cast<size_t>(T.b_row0) * ncols,
-                           rows * static_cast<uint32_t>(ncols) * 4u);
+    auto b_rsrc = [&](const TileDesc& D, uint32_t rows) {
+        const T* bsrc = D.kind == 0 ? mom : dens;
+        return buffer_rsrc(bsrc + static_cast<size_t>(D.b_row0) * ncols,
+                           rows * static_cast<uint32_t>(ncols) * ES);
     };
     auto load_b_at = [&](__amdgpu_buffer_rsrc_t rb, uint32_t so) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, boff, so, 0));
+        return load_elem<T>(rb, boff, so);
     };
     auto load_b = [&](__amdgpu_buffer_rsrc_t rb, int st) {
         // the per-step offset is uniform: it goes in the scalar offset, not in a VGPR
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, boff, st * bstep, 0));
+        return load_elem<T>(rb, boff, st * bstep);
     };
     // Tile descriptors: the current and next in scalar registers, the one after that
     // requested with the vector prefetch of each tile (one 128-bit load, zero past the chunk's
@@ -698,25 +722,25 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(tiles + t_beg, static_cast<uint32_t>(t_end - t_beg) * 16u);
     auto to_desc = [](const v4u& w) {
         const uint32_t w0 = __builtin_amdgcn_readfirstlane(w[0]);
-        TileDesc T;
-        T.kind = static_cast<int16_t>(w0 & 0xffffu);
-        T.nstep = static_cast<int16_t>(w0 >> 16);
-        T.a_blk = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[1]));
-        T.b_row0 = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[2]));
-        T.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
-        return T;
+        TileDesc D;
+        D.kind = static_cast<int16_t>(w0 & 0xffffu);
+        D.nstep = static_cast<int16_t>(w0 >> 16);
+        D.a_blk = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[1]));
+        D.b_row0 = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[2]));
+        D.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
+        return D;
     };
     // the part of a left factor this workgroup uses: all of an expansion tile, the factor of its
     // own operator of a direct tile (its first element, count)
-    auto own_off = [&](const TileDesc& T) {
-        return T.a_off() + (T.kind == 1 ? static_cast<int64_t>(opr) * T.nstep * 256 : 0);
+    auto own_off = [&](const TileDesc& D) {
+        return D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
     };
-    auto own_elems = [](const TileDesc& T) { return 256 * T.nstep; };
+    auto own_elems = [](const TileDesc& D) { return 256 * D.nstep; };
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
-    float bc[NBS];
+    T bc[NBS];
     if (t_beg < t_end) {
-        const int n16 = own_elems(Te) / 4;
+        const int n16 = own_elems(Te) / EPU;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
         for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
@@ -724,10 +748,10 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
     }
     __syncthreads();
-    // a left factor is NA floats per thread: NA / 4 float4 at float4 index tid + 256 r, then
-    // NA % 4 floats at float index 1024 (NA / 4) + tid + 256 r
+    // a left factor is NA elements per thread: NA / EPU 16-byte units at unit index
+    // tid + 256 r, then NA % EPU elements at element index 256 EPU (NA / EPU) + tid + 256 r
     constexpr int NA = NSM > DSTEPS ? NSM : DSTEPS;
-    constexpr int QA = NA / 4, RA = NA % 4;
+    constexpr int QA = NA / EPU, RA = NA % EPU;
     // one tile: prefetches for the next, products of this one (all waves of the workgroup run
     // it together: it ends with a barrier)
     auto tile = [&](int e) {
@@ -737,9 +761,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         const v4u dn = __builtin_amdgcn_raw_buffer_load_b128(
             rt, 0, static_cast<uint32_t>(e + 2 - t_beg) * 16u, 0);
         float4 pf[QA];
-        float pr[RA > 0 ? RA : 1];
+        T pr[RA > 0 ? RA : 1];
         const bool more = e + 1 < t_end;
-        const int n16n = more ? own_elems(Tn) / 4 : 0;
+        const int n16n = more ? own_elems(Tn) / EPU : 0;
         {
             const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + own_off(Tn), n16n * 16u);
 #pragma unroll
@@ -750,22 +774,21 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             }
 #pragma unroll
             for (int r = 0; r < RA; ++r)
-                pr[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                    ra, tid * 4, (QA * 1024 + r * NTHR) * 4, 0));
+                pr[r] = load_elem<T>(ra, tid * ES, (QA * EPU * 256 + r * NTHR) * ES);
         }
         const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
         if (mma) {
             const float4* ab = abuf16;
 #define LSPR_OP_TILE(NS, AOFF)                                                             \
     if constexpr (S == 1) {                                                                \
-        const float4* a4 = ab + (AOFF);                                                    \
+        const Quad<T>* a4 = reinterpret_cast<const Quad<T>*>(ab) + (AOFF);                 \
         uint32_t so = 0;                                                                   \
         _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
-            const float4 a = a4[st * 64 + lane];                                           \
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bc[st], acc[0], 0, 0, 0);   \
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bc[st], acc[1], 0, 0, 0);   \
-            acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bc[st], acc[2], 0, 0, 0);   \
-            acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bc[st], acc[3], 0, 0, 0);   \
+            const Quad<T> a = a4[st * 64 + lane];                                          \
+            acc[0] = Mma<T>::op(a.x, bc[st], acc[0]);                                      \
+            acc[1] = Mma<T>::op(a.y, bc[st], acc[1]);                                      \
+            acc[2] = Mma<T>::op(a.z, bc[st], acc[2]);                                      \
+            acc[3] = Mma<T>::op(a.w, bc[st], acc[3]);                                      \
             bc[st] = load_b_at(rbn, so);                                                   \
             so = next_step(so, bstep);                                                     \
         }                                                                                  \
@@ -774,15 +797,15 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             so = next_step(so, bstep);                                                     \
         }                                                                                  \
     } else {                                                                               \
-        const float4* a4 = ab + (AOFF);                                                    \
+        const Quad<T>* a4 = reinterpret_cast<const Quad<T>*>(ab) + (AOFF);                 \
         _Pragma("unroll") for (int i = 0; i < NBS; ++i) {                                  \
             const int st = kpart + S * i;                                                  \
             if (st < (NS)) {                                                               \
-                const float4 a = a4[st * 64 + lane];                                       \
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bc[i], acc[0], 0, 0, 0); \
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bc[i], acc[1], 0, 0, 0); \
-                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bc[i], acc[2], 0, 0, 0); \
-                acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bc[i], acc[3], 0, 0, 0); \
+                const Quad<T> a = a4[st * 64 + lane];                                      \
+                acc[0] = Mma<T>::op(a.x, bc[i], acc[0]);                                   \
+                acc[1] = Mma<T>::op(a.y, bc[i], acc[1]);                                   \
+                acc[2] = Mma<T>::op(a.z, bc[i], acc[2]);                                   \
+                acc[3] = Mma<T>::op(a.w, bc[i], acc[3]);                                   \
             }                                                                              \
             bc[i] = load_b(rbn, st);                                                       \
         }                                                                                  \
@@ -790,12 +813,14 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             if (Te.kind == 0) LSPR_OP_TILE(NSM, 0)
             else LSPR_OP_TILE(DSTEPS, 0)
 #undef LSPR_OP_TILE
-            // the tile's FP32 partial joins an FP64 running sum
+            // FP32: the tile's partial joins an FP64 running sum
+            if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
+                for (int a = 0; a < 4; ++a) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
-                acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
+                    for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
+                    acc[a] = Acc{0, 0, 0, 0};
+                }
             }
         }
         __syncthreads();  // every wave is done with this tile's left factor
@@ -806,11 +831,11 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                 const int k = tid + r * NTHR;
                 if (k < n16n) dst[k] = pf[r];
             }
-            float* dst1 = reinterpret_cast<float*>(dst);
+            T* dst1 = reinterpret_cast<T*>(dst);
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
-                const int k = QA * 1024 + tid + r * NTHR;
-                if (k < 4 * n16n) dst1[k] = pr[r];
+                const int k = QA * EPU * 256 + tid + r * NTHR;
+                if (k < EPU * n16n) dst1[k] = pr[r];
             }
         }
         Te = Tn;
@@ -1165,50 +1190,52 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
-template <int NSM, int S>
-void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
+template <class T, int NSM, int S>
+void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                            double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
     const int nblk = g.n_order * 2 * halves;
     // the left factor, then (S > 1) one slot of FP64 sums per column group for the final additions
-    const size_t lds = static_cast<size_t>(abuf) * sizeof(float) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
-    hipLaunchKernelGGL((k_far_tiles_op<NSM, S>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
-                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens,
-                       mom, pad, pad / 16, halves, os, oa);
+    const size_t lds = static_cast<size_t>(abuf) * sizeof(T) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles_op<T, NSM, S>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(lds));
+    hipLaunchKernelGGL((k_far_tiles_op<T, NSM, S>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
+                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g),
+                       dens, mom, pad, pad / 16, halves, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
 // one column group per operator: four waves share it; two: two waves each; more: one each
-template <int NSM>
-void launch_far_tiles_op(Geometry& g, int pad, int abuf, const float* dens, const float* mom,
+template <class T, int NSM>
+void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                          double* os, double* oa, hipStream_t s) {
     const int groups = pad / 16;
-    if (groups == 1) launch_far_tiles_op_s<NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
-    else if (groups == 2) launch_far_tiles_op_s<NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
-    else launch_far_tiles_op_s<NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
+    if (groups == 1) launch_far_tiles_op_s<T, NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
+    else if (groups == 2) launch_far_tiles_op_s<T, NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
+    else launch_far_tiles_op_s<T, NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
 }
 
 template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
-    if constexpr (sizeof(T) == 4) {
-        if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
-            const int nsm = (g.n_terms + 3) / 4;
-            const int abuf = std::max(nsm, DSTEPS) * 256;  // largest part a workgroup stages
+    if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
+        const int nsm = (g.n_terms + 3) / 4;
+        const int abuf = std::max(nsm, DSTEPS) * 256;  // largest part a workgroup stages
 #define LSPR_FAR_OP(NSM_)                                                                    \
     case NSM_:                                                                               \
-        launch_far_tiles_op<NSM_>(g, pad, abuf, dens, mom, os, oa, s);                       \
+        launch_far_tiles_op<T, NSM_>(g, pad, abuf, dens, mom, os, oa, s);                    \
         return;
-            switch (nsm) {
-                LSPR_FAR_OP(3)
-                LSPR_FAR_OP(7)
-                LSPR_FAR_OP(13)
-                LSPR_FAR_OP(21)
-                LSPR_FAR_OP(31)
-                default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
-            }
-#undef LSPR_FAR_OP
+        switch (nsm) {
+            LSPR_FAR_OP(3)
+            LSPR_FAR_OP(7)
+            LSPR_FAR_OP(13)
+            LSPR_FAR_OP(21)
+            LSPR_FAR_OP(31)
+            default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
         }
+#undef LSPR_FAR_OP
     }
     const int nwc = pad / 16;  // column groups (16 K and 16 V columns each)
     // FP32: 4-wave workgroups, two per CU (a chunk with more than 4 column groups is split
