@@ -184,7 +184,7 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
     write_scale = known_kib / only(write, "FillFunctor")
     per, total_b, total_n = {}, 0.0, 0
     for k in sorted(fetch):
-        if "k_far_tiles_op" not in k:
+        if "k_far_tiles_op<float" not in k:  # the FP32 instances: the kernel the roofline times
             continue
         f, wr = fetch[k], write.get(k, [])
         if len(f) != len(wr):

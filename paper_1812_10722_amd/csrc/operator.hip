@@ -598,6 +598,30 @@ __device__ __forceinline__ double load_elem<double>(__amdgpu_buffer_rsrc_t rb, u
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, voff, soff, 0));
 }
 
+// Left factors in LDS.  A K-step's operand of one lane is the four target tiles' values (16
+// bytes in FP32, 32 in FP64).  FP32 keeps the order of HBM (one conflict-free 128-bit read per
+// lane and step); FP64 stores the two halves of each lane's 32 bytes in separate planes of 64
+// lanes, so that both 128-bit reads of a step are contiguous across the lanes.
+template <class T>
+__device__ __forceinline__ int lds_unit(int u) {  // LDS position of 16-byte unit u of a factor
+    if constexpr (sizeof(T) == 4) return u;
+    else return (u & ~127) | ((u & 1) << 6) | ((u >> 1) & 63);
+}
+template <class T>
+__device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return reinterpret_cast<const Quad<float>*>(ab)[st * 64 + lane];
+    } else {
+        const float4 lo = ab[2 * st * 64 + lane], hi = ab[(2 * st + 1) * 64 + lane];
+        Quad<double> q;
+        q.x = __builtin_bit_cast(double, make_float2(lo.x, lo.y));
+        q.y = __builtin_bit_cast(double, make_float2(lo.z, lo.w));
+        q.z = __builtin_bit_cast(double, make_float2(hi.x, hi.y));
+        q.w = __builtin_bit_cast(double, make_float2(hi.z, hi.w));
+        return q;
+    }
+}
+
 // Far field on matrix cores, one operator per workgroup (FP32 or FP64 products).  Workgroups b, b + 8, ... handle one chunk (all on
 // the same XCD, so the later ones read the chunk's left factors from L2): the double-layer (K)
 // and single-layer (V) columns, each in 1 or 2 halves of 4 column groups of 16, one group per
@@ -742,7 +766,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     if (t_beg < t_end) {
         const int n16 = own_elems(Te) / EPU;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
-        for (int k = tid; k < n16; k += NTHR) abuf16[k] = src[k];
+        for (int k = tid; k < n16; k += NTHR) abuf16[lds_unit<T>(k)] = src[k];
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
         for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
@@ -779,12 +803,11 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
         if (mma) {
             const float4* ab = abuf16;
-#define LSPR_OP_TILE(NS, AOFF)                                                             \
+#define LSPR_OP_TILE(NS)                                                             \
     if constexpr (S == 1) {                                                                \
-        const Quad<T>* a4 = reinterpret_cast<const Quad<T>*>(ab) + (AOFF);                 \
         uint32_t so = 0;                                                                   \
         _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
-            const Quad<T> a = a4[st * 64 + lane];                                          \
+            const Quad<T> a = lds_quad<T>(ab, st, lane);                                   \
             acc[0] = Mma<T>::op(a.x, bc[st], acc[0]);                                      \
             acc[1] = Mma<T>::op(a.y, bc[st], acc[1]);                                      \
             acc[2] = Mma<T>::op(a.z, bc[st], acc[2]);                                      \
@@ -797,11 +820,10 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             so = next_step(so, bstep);                                                     \
         }                                                                                  \
     } else {                                                                               \
-        const Quad<T>* a4 = reinterpret_cast<const Quad<T>*>(ab) + (AOFF);                 \
         _Pragma("unroll") for (int i = 0; i < NBS; ++i) {                                  \
             const int st = kpart + S * i;                                                  \
             if (st < (NS)) {                                                               \
-                const Quad<T> a = a4[st * 64 + lane];                                      \
+                const Quad<T> a = lds_quad<T>(ab, st, lane);                               \
                 acc[0] = Mma<T>::op(a.x, bc[i], acc[0]);                                   \
                 acc[1] = Mma<T>::op(a.y, bc[i], acc[1]);                                   \
                 acc[2] = Mma<T>::op(a.z, bc[i], acc[2]);                                   \
@@ -810,8 +832,8 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             bc[i] = load_b(rbn, st);                                                       \
         }                                                                                  \
     }
-            if (Te.kind == 0) LSPR_OP_TILE(NSM, 0)
-            else LSPR_OP_TILE(DSTEPS, 0)
+            if (Te.kind == 0) LSPR_OP_TILE(NSM)
+            else LSPR_OP_TILE(DSTEPS)
 #undef LSPR_OP_TILE
             // FP32: the tile's partial joins an FP64 running sum
             if constexpr (sizeof(T) == 4) {
@@ -829,13 +851,16 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 #pragma unroll
             for (int r = 0; r < QA; ++r) {
                 const int k = tid + r * NTHR;
-                if (k < n16n) dst[k] = pf[r];
+                if (k < n16n) dst[lds_unit<T>(k)] = pf[r];
             }
             T* dst1 = reinterpret_cast<T*>(dst);
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
-                const int k = QA * EPU * 256 + tid + r * NTHR;
-                if (k < EPU * n16n) dst1[k] = pr[r];
+                const int k = QA * EPU * 256 + tid + r * NTHR;  // element index
+                if (k < EPU * n16n) {
+                    if constexpr (sizeof(T) == 4) dst1[k] = pr[r];
+                    else dst1[lds_unit<T>(k / EPU) * EPU + k % EPU] = pr[r];
+                }
             }
         }
         Te = Tn;
