@@ -368,7 +368,7 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
     const int64_t nvec = 2 * N, m1 = gm.restart + 1;
     const int64_t esz = op.precision == LSPR_FP32 ? 4 : 8;  // largest product precision
     const int64_t pad = (2 * B + 15) / 16 * 16;
-    const int64_t nblk = (nvec + 2047) / 2048 + 1;
+    const int64_t nblk = (nvec + 4095) / 4096 + 1;  // Arnoldi blocks of 4096 elements
     int64_t b = 0;
     b += static_cast<int64_t>(B) * m1 * nvec * 16;                 // Krylov basis
     b += static_cast<int64_t>(B) * nvec * 16 * (gm.precond ? 4 : 3);  // x, w, b (, z)

@@ -40,7 +40,7 @@ namespace lspr {
 namespace {
 
 constexpr int GT = 256;
-constexpr int GE = 8;
+constexpr int GE = 16;
 constexpr int GSLICE = GT * GE;
 constexpr double INV_4PI = 0.07957747154594767;
 
