@@ -153,72 +153,177 @@ struct ListParams {
     const int32_t* roots;  // [S]
 };
 
-// Interaction lists of one chunk against every surface's tree, own surface first.  With
-// fill == false only counts are produced.  A box is expanded (M2P) when the MAC holds for the
-// whole chunk, no target of the chunk can be near-singular to any of its panels
-// (d - r_T - r_v > L_max / threshold), and it holds enough panels for the expansion to be
-// cheaper than the direct sum; otherwise a leaf, or a box that passes the MAC but is small,
-// is summed directly.  Direct ranges that touch are merged.
-__global__ void k_lists(const Box* __restrict__ boxes, const Chunk* __restrict__ chunks,
-                        int n_chunks, ListParams lp, bool fill, int32_t* __restrict__ m2p_cnt,
-                        int32_t* __restrict__ p2p_cnt, int32_t* __restrict__ m2p_selfc,
-                        int32_t* __restrict__ p2p_selfc, const int64_t* __restrict__ m2p_off,
-                        const int64_t* __restrict__ p2p_off, int32_t* __restrict__ m2p_box,
-                        Range* __restrict__ p2p_rng, int64_t* __restrict__ pairs) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_chunks) return;
-    const Chunk T = chunks[c];
+// Interaction lists of one chunk against every surface's tree, own surface first.  A box is
+// expanded (M2P) when the MAC holds for the whole chunk, no target of the chunk can be
+// near-singular to any of its panels (d - r_T - r_v > L_max / threshold), and it holds enough
+// panels for the expansion to be cheaper than the direct sum; otherwise a leaf, or a box that
+// passes the MAC but is small, is summed directly; any other box is opened.  Direct ranges that
+// touch are merged.  The lists are those of one depth-first walk per (chunk, surface); the walk
+// is split over up to SUBS sub-trees (the boxes two levels below the root, in depth-first
+// order, or a shallower box that is not opened), one thread each: a count pass, a per-chunk pass
+// that places the sub-lists and merges direct ranges across sub-tree boundaries, and a fill pass.
+constexpr int SUBS = 64;
+enum ListAction { LIST_OPEN = 0, LIST_M2P = 1, LIST_P2P = 2 };
+
+__device__ __forceinline__ int list_action(const Chunk& T, const Box& B, const ListParams& lp) {
+    const double dx = T.cx - B.cx, dy = T.cy - B.cy, dz = T.cz - B.cz;
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    const bool ok = d > T.r && B.rb < lp.theta * (d - T.r) &&
+                    (d - T.r - B.rv) > B.lmax * lp.inv_thr;
+    if (ok && B.end - B.start >= lp.min_panels) return LIST_M2P;
+    if (ok || B.nchild == 0) return LIST_P2P;
+    return LIST_OPEN;
+}
+
+// Root of sub-tree k of the walk from `root` for chunk T, or -1.
+__device__ int sub_root(const Box* __restrict__ boxes, const Chunk& T, int root, int k,
+                        const ListParams& lp) {
+    const Box R = boxes[root];
+    if (list_action(T, R, lp) != LIST_OPEN) return k == 0 ? root : -1;
+    int n = 0;
+    for (int i = 0; i < R.nchild; ++i) {
+        const int ci = R.child + i;
+        const Box Cb = boxes[ci];
+        if (list_action(T, Cb, lp) != LIST_OPEN) {
+            if (n == k) return ci;
+            ++n;
+        } else {
+            if (k < n + Cb.nchild) return Cb.child + (k - n);
+            n += Cb.nchild;
+        }
+    }
+    return -1;
+}
+
+// One sub-tree's part of the lists.  flags: 1 its first item is a direct range, 2 its last item
+// is a direct range, 4 it has items.  first_end: end of its first direct range (after merges).
+struct SubList {
+    int32_t nm, np, first_end, flags;
+    int64_t pp, mp;
+};
+// Where a sub-tree writes: offsets within the chunk's lists; skip: its first direct range joins
+// the previous sub-tree's last one; end: new end of its last direct range (-1: unchanged).
+struct SubPlace {
+    int32_t m2p, p2p, skip, end;
+};
+
+template <bool FILL>
+__device__ void walk_sub(const Box* __restrict__ boxes, const Chunk& T, int q,
+                         const ListParams& lp, SubList& L, const SubPlace& pl,
+                         int32_t* __restrict__ m2p_box, Range* __restrict__ p2p_rng) {
     const int nt = T.end - T.start;
     int stack[STACK];
-    int nm = 0, np = 0, nm_self = 0, np_self = 0;
-    int64_t pp = 0, mp = 0;
-    int64_t mo = fill ? m2p_off[c] : 0, po = fill ? p2p_off[c] : 0;
-    for (int pass = 0; pass < lp.S; ++pass) {
-        const int s = pass == 0 ? T.surf : (pass <= T.surf ? pass - 1 : pass);
-        int top = 0;
-        stack[top++] = lp.roots[s];
-        int last_end = -1;
-        while (top > 0) {
-            const int bi = stack[--top];
-            const Box B = boxes[bi];
-            const double dx = T.cx - B.cx, dy = T.cy - B.cy, dz = T.cz - B.cz;
-            const double d = sqrt(dx * dx + dy * dy + dz * dz);
-            const bool ok = d > T.r && B.rb < lp.theta * (d - T.r) &&
-                            (d - T.r - B.rv) > B.lmax * lp.inv_thr;
-            const int npan = B.end - B.start;
-            if (ok && npan >= lp.min_panels) {
-                if (fill) m2p_box[mo + nm] = bi;
-                ++nm;
-                mp += nt;
-            } else if (ok || B.nchild == 0) {
-                if (B.start == last_end) {
-                    if (fill) p2p_rng[po + np - 1].end = B.end;
-                } else {
-                    if (fill) p2p_rng[po + np] = Range{B.start, B.end};
-                    ++np;
-                }
-                last_end = B.end;
-                pp += static_cast<int64_t>(nt) * npan;
+    int top = 0;
+    stack[top++] = q;
+    int last_end = -1, li = -1;  // li: local index of the last direct range
+    auto slot = [&](int i) { return pl.p2p + i - pl.skip; };
+    while (top > 0) {
+        const int bi = stack[--top];
+        const Box B = boxes[bi];
+        const int act = list_action(T, B, lp);
+        if (act == LIST_M2P) {
+            if (FILL) m2p_box[pl.m2p + L.nm] = bi;
+            ++L.nm;
+            L.mp += nt;
+            L.flags = (L.flags & ~2) | 4;
+        } else if (act == LIST_P2P) {
+            if (!(L.flags & 4)) L.flags |= 1;
+            if (B.start == last_end) {
+                if (FILL && !(pl.skip && li == 0)) p2p_rng[slot(li)].end = B.end;
             } else {
-                if (top + B.nchild > STACK) {  // cannot happen for depth <= 16; stay safe
-                    continue;
-                }
-                for (int k = B.nchild - 1; k >= 0; --k) stack[top++] = B.child + k;
+                ++li;
+                ++L.np;
+                if (FILL && !(pl.skip && li == 0)) p2p_rng[slot(li)] = Range{B.start, B.end};
             }
+            if (li == 0) L.first_end = B.end;
+            last_end = B.end;
+            L.pp += static_cast<int64_t>(nt) * (B.end - B.start);
+            L.flags |= 2 | 4;
+        } else {
+            if (top + B.nchild > STACK) continue;  // cannot happen for depth <= 16; stay safe
+            for (int k = B.nchild - 1; k >= 0; --k) stack[top++] = B.child + k;
+        }
+    }
+    if (FILL && pl.end >= 0 && (L.flags & 2) && !(pl.skip && li == 0)) p2p_rng[slot(li)].end = pl.end;
+}
+
+__device__ __forceinline__ void list_task(int t, int n_chunks, const ListParams& lp, int& c,
+                                          int& pass, int& k) {
+    k = t % SUBS;
+    pass = (t / SUBS) % lp.S;
+    c = t / (SUBS * lp.S);
+}
+
+__global__ void k_lists_count(const Box* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                              int n_chunks, ListParams lp, SubList* __restrict__ sub) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n_chunks) * lp.S * SUBS) return;
+    int c, pass, k;
+    list_task(static_cast<int>(t), n_chunks, lp, c, pass, k);
+    const Chunk T = chunks[c];
+    const int s = pass == 0 ? T.surf : (pass <= T.surf ? pass - 1 : pass);
+    SubList L{0, 0, -1, 0, 0, 0};
+    const int q = sub_root(boxes, T, lp.roots[s], k, lp);
+    if (q >= 0) walk_sub<false>(boxes, T, q, lp, L, SubPlace{0, 0, 0, -1}, nullptr, nullptr);
+    sub[t] = L;
+}
+
+// One thread per chunk: sub-list offsets in depth-first order, direct ranges merged across
+// sub-tree boundaries (within a surface), per-chunk counts.
+__global__ void k_lists_place(const SubList* __restrict__ sub, int n_chunks, int S,
+                              SubPlace* __restrict__ place, int32_t* __restrict__ m2p_cnt,
+                              int32_t* __restrict__ p2p_cnt, int32_t* __restrict__ m2p_selfc,
+                              int32_t* __restrict__ p2p_selfc, int64_t* __restrict__ pairs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    int nm = 0, np = 0;
+    int64_t pp = 0, mp = 0;
+    for (int pass = 0; pass < S; ++pass) {
+        int64_t open = -1;  // sub-tree whose last direct range is still open
+        for (int k = 0; k < SUBS; ++k) {
+            const int64_t t = (static_cast<int64_t>(c) * S + pass) * SUBS + k;
+            const SubList L = sub[t];
+            SubPlace P{nm, np, 0, -1};
+            if (L.flags & 4) {
+                const bool join = open >= 0 && (L.flags & 1);
+                if (join) {
+                    P.skip = 1;
+                    place[open].end = L.first_end;
+                }
+                const bool only_range = L.nm == 0 && L.np == 1;
+                if (!(join && only_range)) open = (L.flags & 2) ? t : -1;
+                nm += L.nm;
+                np += L.np - P.skip;
+                pp += L.pp;
+                mp += L.mp;
+            }
+            place[t] = P;
         }
         if (pass == 0) {
-            nm_self = nm;
-            np_self = np;
+            m2p_selfc[c] = nm;
+            p2p_selfc[c] = np;
         }
     }
-    if (!fill) {
-        m2p_cnt[c] = nm;
-        p2p_cnt[c] = np;
-        m2p_selfc[c] = nm_self;
-        p2p_selfc[c] = np_self;
-        pairs[2 * c] = pp;
-        pairs[2 * c + 1] = mp;
-    }
+    m2p_cnt[c] = nm;
+    p2p_cnt[c] = np;
+    pairs[2 * c] = pp;
+    pairs[2 * c + 1] = mp;
+}
+
+__global__ void k_lists_fill(const Box* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                             int n_chunks, ListParams lp, const SubPlace* __restrict__ place,
+                             const int64_t* __restrict__ m2p_off, const int64_t* __restrict__ p2p_off,
+                             int32_t* __restrict__ m2p_box, Range* __restrict__ p2p_rng) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n_chunks) * lp.S * SUBS) return;
+    int c, pass, k;
+    list_task(static_cast<int>(t), n_chunks, lp, c, pass, k);
+    const Chunk T = chunks[c];
+    const int s = pass == 0 ? T.surf : (pass <= T.surf ? pass - 1 : pass);
+    const int q = sub_root(boxes, T, lp.roots[s], k, lp);
+    if (q < 0) return;
+    SubList L{0, 0, -1, 0, 0, 0};
+    walk_sub<true>(boxes, T, q, lp, L, place[t], m2p_box + m2p_off[c], p2p_rng + p2p_off[c]);
 }
 
 struct NearParams {
@@ -466,10 +571,14 @@ void build_lists(Geometry& g) {
     g.m2p_self.alloc(nc);
     g.p2p_self.alloc(nc);
     DevBuf<int64_t> pairs(2 * nc);
-    const dim3 grid((nc + 63) / 64), blk(64);
-    hipLaunchKernelGGL(k_lists, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, false, mc.p,
-                       pc.p, g.m2p_self.p, g.p2p_self.p, nullptr, nullptr, nullptr, nullptr,
-                       pairs.p);
+    const int64_t ntask = static_cast<int64_t>(nc) * g.S * SUBS;
+    LSPR_REQUIRE(ntask < (1ll << 31), LSPR_E_INVALID, "too many list tasks");
+    DevBuf<SubList> sub(ntask);
+    DevBuf<SubPlace> place(ntask);
+    const dim3 grid((ntask + 63) / 64), blk(64);
+    hipLaunchKernelGGL(k_lists_count, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, sub.p);
+    hipLaunchKernelGGL(k_lists_place, dim3((nc + 63) / 64), dim3(64), 0, s, sub.p, nc, g.S,
+                       place.p, mc.p, pc.p, g.m2p_self.p, g.p2p_self.p, pairs.p);
     LSPR_HIP(hipGetLastError());
     std::vector<int32_t> mh(nc), ph(nc);
     std::vector<int64_t> prh(2 * nc);
@@ -495,9 +604,8 @@ void build_lists(Geometry& g) {
     LSPR_HIP(hipMemcpyAsync(po_d.p, po.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s));
     g.m2p_box.alloc(std::max<int64_t>(g.n_m2p, 1));
     g.p2p_rng.alloc(std::max<int64_t>(g.n_p2p, 1));
-    hipLaunchKernelGGL(k_lists, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, true, mc.p,
-                       pc.p, g.m2p_self.p, g.p2p_self.p, mo_d.p, po_d.p, g.m2p_box.p,
-                       g.p2p_rng.p, pairs.p);
+    hipLaunchKernelGGL(k_lists_fill, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, place.p,
+                       mo_d.p, po_d.p, g.m2p_box.p, g.p2p_rng.p);
     LSPR_HIP(hipGetLastError());
     std::vector<int32_t> mo32(nc + 1), po32(nc + 1);
     for (int c = 0; c <= nc; ++c) {
