@@ -371,7 +371,7 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
     const int64_t nblk = (nvec + 4095) / 4096 + 1;  // Arnoldi blocks of 4096 elements
     int64_t b = 0;
     b += static_cast<int64_t>(B) * m1 * nvec * 16;                 // Krylov basis
-    b += static_cast<int64_t>(B) * nvec * 16 * (gm.precond ? 4 : 3);  // x, w, b (, z)
+    b += static_cast<int64_t>(B) * nvec * 16 * 3;                  // x, w, b
     // partial inner products (one per wave of each block), Hessenberg matrices, coefficients
     b += static_cast<int64_t>(B) * (2 * m1 + 3) * 4 * nblk * 16;
     b += 2 * static_cast<int64_t>(B) * m1 * m1 * 16 + static_cast<int64_t>(B) * (8 * m1 + 64) * 16;

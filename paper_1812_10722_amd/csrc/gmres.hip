@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "precond.hpp"
 #include "profile.hpp"
 #include "system.hpp"
 
@@ -515,13 +516,8 @@ __global__ void k_precond(const double2* __restrict__ in, int64_t in_stride,
     const int slot = static_cast<int>(t / N), i = static_cast<int>(t % N);
     const int col = cols[slot];
     const double2 a = in[col * in_stride + i], b = in[col * in_stride + N + i];
-    const double2 r = ratio[col * S + surf[i]];
-    const double v = vself[i] * INV_4PI;
-    const double2 onep = make_double2(1.0 + r.x, r.y);
-    // phi = 2 (r a + b) / (1 + r);  psi = (b - a) / (v (1 + r))
-    const double2 ra = cmul(r, a);
-    double2 phi = cdiv(make_double2(2.0 * (ra.x + b.x), 2.0 * (ra.y + b.y)), onep);
-    double2 psi = cdiv(make_double2((b.x - a.x) / v, (b.y - a.y) / v), onep);
+    double2 phi, psi;
+    block_jacobi(a, b, ratio[col * S + surf[i]], vself[i] * INV_4PI, phi, psi);
     double2* o = out + col * out_stride;
     if (add) {
         o[i].x += phi.x;
@@ -654,7 +650,6 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     const int nblk = blocks_for(nvec);
     const bool pre = gm.precond != 0;
     DevBuf<double2> V(static_cast<size_t>(B) * m1 * nvec), w(B * nvec), bvec(B * nvec);
-    DevBuf<double2> z(pre ? B * nvec : 0);
     const int kmax = 2 * m1 + 3;
     const int nparts = 4 * nblk;  // one partial sum per wave of each block
     DevBuf<double2> Hr(static_cast<size_t>(B) * m * m1), H(static_cast<size_t>(B) * m * m1);
@@ -730,19 +725,11 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
     auto product = [&](int j, const std::vector<int32_t>& c) {
         upload_cols(c);
         const int ns = static_cast<int>(c.size());
+        // the preconditioner is applied inside the product (packing and row combination)
         const double2* vin = V.p + j * nvec;
-        int64_t vin_stride = m1 * nvec;
-        if (pre) {
-            const int64_t t = static_cast<int64_t>(g.N) * ns;
-            hipLaunchKernelGGL(k_precond, dim3((t + 255) / 256), dim3(256), 0, s, vin,
-                               vin_stride, z.p, nvec, g.N, cols_d.p, ns, ratio_d, g.S,
-                               g.surf.p, g.vself.p, 0);
-            LSPR_HIP(hipGetLastError());
-            vin = z.p;
-            vin_stride = nvec;
-        }
+        const int64_t vin_stride = m1 * nvec;
         if (!lead) {
-            system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+            system_apply(g, prec, ns, ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s, pre);
             return;
         }
         std::vector<int32_t> hi, lo;
@@ -752,7 +739,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
             if (part_c.empty()) continue;
             upload_cols(part_c);
             system_apply(g, h == 0 ? LSPR_FP64 : LSPR_FP32, static_cast<int>(part_c.size()),
-                         ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s);
+                         ratio_d, vin, vin_stride, w.p, nvec, cols_d.p, s, pre);
         }
     };
     Event est_ready;

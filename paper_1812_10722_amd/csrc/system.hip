@@ -14,6 +14,7 @@
 #include <cstdio>
 
 #include "operator.hpp"
+#include "precond.hpp"
 #include "profile.hpp"
 #include "system.hpp"
 
@@ -31,13 +32,22 @@ __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) 
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// Unknowns (phi, psi) of panel i of column col: x itself, or M^-1 x when vself is given.
+__device__ __forceinline__ void unknowns(const double2* xc, int N, int i, double2 r,
+                                         const double* vself, double2& phi, double2& psi) {
+    phi = xc[i];
+    psi = xc[N + i];
+    if (vself != nullptr) block_jacobi(phi, psi, r, vself[i] * INV_4PI, phi, psi);
+}
+
 // x (complex, [col][2N] sorted order) -> packed real columns dens [N][2 pad]:
 // K columns 2s, 2s+1 = Re, Im phi; V columns pad + 2s, pad + 2s + 1 = Re, Im sigma.
 template <class T>
 __global__ void k_pack(const double2* __restrict__ x, int64_t x_stride,
                        const int32_t* __restrict__ cols, int nslot, int N,
                        const double2* __restrict__ ratio, int S,
-                       const int32_t* __restrict__ surf, int pad, T* __restrict__ dens) {
+                       const int32_t* __restrict__ surf, const double* __restrict__ vself,
+                       int pad, T* __restrict__ dens) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<int64_t>(N) * pad) return;
     const int i = static_cast<int>(t / pad), c = static_cast<int>(t % pad);
@@ -49,9 +59,10 @@ __global__ void k_pack(const double2* __restrict__ x, int64_t x_stride,
         return;
     }
     const int col = cols ? cols[slot] : slot;
-    const double2* xc = x + col * x_stride;
-    const double2 phi = xc[i];
-    const double2 sig = cmul(ratio[col * S + surf[i]], xc[N + i]);
+    const double2 r = ratio[col * S + surf[i]];
+    double2 phi, psi;
+    unknowns(x + col * x_stride, N, i, r, vself, phi, psi);
+    const double2 sig = cmul(r, psi);
     row[c] = static_cast<T>((c & 1) ? phi.y : phi.x);
     row[pad + c] = static_cast<T>((c & 1) ? sig.y : sig.x);
 }
@@ -61,13 +72,15 @@ __global__ void k_combine(const double2* __restrict__ x, int64_t x_stride,
                           double2* __restrict__ y, int64_t y_stride,
                           const int32_t* __restrict__ cols, int nslot, int N,
                           const double2* __restrict__ ratio, int S,
-                          const int32_t* __restrict__ surf, int pad,
-                          const double* __restrict__ out_self, const double* __restrict__ out_all) {
+                          const int32_t* __restrict__ surf, const double* __restrict__ vself,
+                          int pad, const double* __restrict__ out_self,
+                          const double* __restrict__ out_all) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<int64_t>(N) * nslot) return;
     const int slot = static_cast<int>(t / N), i = static_cast<int>(t % N);
     const int col = cols ? cols[slot] : slot;
-    const double2 phi = x[col * x_stride + i];
+    double2 phi, psi;
+    unknowns(x + col * x_stride, N, i, ratio[col * S + surf[i]], vself, phi, psi);
     const double* ra = out_all + static_cast<size_t>(i) * 2 * pad;
     const double* rs = (out_self ? out_self : out_all) + static_cast<size_t>(i) * 2 * pad;
     const double2 k_all = make_double2(ra[2 * slot] * INV_4PI, ra[2 * slot + 1] * INV_4PI);
@@ -173,7 +186,8 @@ void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hi
 // y[col] = A(eps[col]) x[col] for the nslot columns listed in d_cols (or 0..nslot-1).
 void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, const double2* x,
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
-                  hipStream_t s) {
+                  hipStream_t s, bool precond) {
+    const double* vs = precond ? g.vself.p : nullptr;
     const Cols c = make_cols(g, 2 * nslot, prec);
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
     const size_t esz = c.prec == LSPR_FP32 ? 4 : 8;
@@ -185,17 +199,17 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
     const int64_t tp = static_cast<int64_t>(g.N) * c.pad;
     if (c.prec == LSPR_FP32)
         hipLaunchKernelGGL(k_pack<float>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
-                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad,
+                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad,
                            reinterpret_cast<float*>(g.ws_dens.p));
     else
         hipLaunchKernelGGL(k_pack<double>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
-                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad,
+                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad,
                            reinterpret_cast<double*>(g.ws_dens.p));
     LSPR_HIP(hipGetLastError());
     apply_raw(g, c, g.ws_dens.p, os, oa, s);
     const int64_t tc = static_cast<int64_t>(g.N) * nslot;
     hipLaunchKernelGGL(k_combine, dim3((tc + TPB - 1) / TPB), dim3(TPB), 0, s, x, x_stride, y,
-                       y_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, c.pad, os, oa);
+                       y_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 

@@ -14,11 +14,12 @@ struct EpsSet {
 void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s);
 
 // y[col] = A(col) x[col] for nslot columns; col = d_cols[slot] (or slot when d_cols is null),
-// with far-field products in precision prec (LSPR_FP32 or LSPR_FP64).
+// with far-field products in precision prec (LSPR_FP32 or LSPR_FP64); with precond,
+// y[col] = A(col) M(col)^-1 x[col] (M: the 2x2 self-panel blocks, precond.hpp).
 // Vectors are complex [*][2N] in sorted panel order with the given strides (in elements).
 void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, const double2* x,
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
-                  hipStream_t s);
+                  hipStream_t s, bool precond = false);
 
 // b[col] for columns 0..ncolumn-1 (sorted order, stride b_stride).
 void system_rhs(Geometry& g, int ncolumn, const double2* ratio_d, const double* e_field,
