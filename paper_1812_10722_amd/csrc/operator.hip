@@ -889,64 +889,115 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 template <int P>
 constexpr int p2m_row_tiles() { return (Expansion<P>::NR + 15) / 16; }
 
+// Index of term (x, y, z) in the full list (by degree, then x and y descending).
+__device__ __forceinline__ int full_term(int x, int y, int z) {
+    const int n = x + y + z, a = n - x;
+    return n * (n + 1) * (n + 2) / 6 + a * (a + 1) / 2 + (a - y);
+}
+
+// One block per segment, PB panels at a time with TPP threads each: the node polynomials of a
+// panel go to LDS (each thread a share of the terms, nodes summed in order), the kz >= 2 terms
+// are folded level by level (each destination gathers its two sources in the order of the
+// sequential fold), and the folded terms are stored.
 template <class S, int P>
-__global__ void k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
-                                  const int64_t* __restrict__ aoff, const double* __restrict__ cen,
-                                  const S* __restrict__ src, int K, float* __restrict__ A32,
-                                  double* __restrict__ A64) {
+__global__ void __launch_bounds__(128)
+k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
+                  const int64_t* __restrict__ aoff, const double* __restrict__ cen,
+                  const S* __restrict__ src, int K, float* __restrict__ A32,
+                  double* __restrict__ A64) {
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
+    constexpr int PB = 8, TPP = 16;
+    __shared__ double poly[PB][2][NF];  // V then K polynomial of each panel of the batch
     const P2MSeg sg = segs[blockIdx.x];
-    const int j = sg.start + static_cast<int>(threadIdx.x);
-    if (j >= sg.end) return;
     const Box B = boxes[sg.box];
+    const int lp = threadIdx.x / TPP, lt = threadIdx.x % TPP;
     const int rs = 4 + 4 * K;
-    const S* r = src + static_cast<size_t>(j) * rs;
-    double pv[NF], pk[NF];
-    for (int t = 0; t < NF; ++t) pv[t] = pk[t] = 0.0;
-    for (int gq = 0; gq < K; ++gq) {
-        const double d[3] = {cen[3 * j] - B.cx + r[4 + 4 * gq], cen[3 * j + 1] - B.cy + r[5 + 4 * gq],
-                             cen[3 * j + 2] - B.cz + r[6 + 4 * gq]};
-        const double w = r[7 + 4 * gq];
-        double pw[3][P + 1];
-        for (int a = 0; a < 3; ++a) {
-            pw[a][0] = 1.0;
-            for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
-        }
-        for (int t = 0; t < NF; ++t) {
-            const int kx = ex.fx[t], ky = ex.fy[t], kz = ex.fz[t];
-            const double X = pw[0][kx], Y = pw[1][ky], Z = pw[2][kz];
-            pv[t] += w * X * Y * Z;
-            double gs = 0.0;
-            if (kx > 0) gs += r[0] * kx * pw[0][kx - 1] * Y * Z;
-            if (ky > 0) gs += r[1] * ky * X * pw[1][ky - 1] * Z;
-            if (kz > 0) gs += r[2] * kz * X * Y * pw[2][kz - 1];
-            pk[t] += w * gs;
-        }
-    }
-    // fold the kz >= 2 terms onto kz <= 1, as the moments themselves are folded
-    for (int f = 0; f < E::NFOLD; ++f) {
-        pv[ex.fdx[f]] += ex.fcx[f] * pv[ex.fsrc[f]];
-        pv[ex.fdy[f]] += ex.fcy[f] * pv[ex.fsrc[f]];
-        pk[ex.fdx[f]] += ex.fcx[f] * pk[ex.fsrc[f]];
-        pk[ex.fdy[f]] += ex.fcy[f] * pk[ex.fsrc[f]];
-    }
-    const int p = j - sg.start, st = p >> 2, kk = p & 3;
     const int steps = (sg.end - sg.start + 3) / 4;
     const size_t a0 = aoff[blockIdx.x], kb = static_cast<size_t>(steps) * RT * 64;
-    for (int q = 0; q < NR; ++q) {
-        const int rt = q >> 4, lane = (q & 15) + 16 * kk;
-        const size_t idx = a0 + (static_cast<size_t>(st) * RT + rt) * 64 + lane;
-        const double v = pv[ex.rfull[q]], k = pk[ex.rfull[q]];
-        if (A32 != nullptr) {
-            A32[idx] = static_cast<float>(v);
-            A32[idx + kb] = static_cast<float>(k);
+    double* pv = poly[lp][0];
+    double* pk = poly[lp][1];
+    for (int base = sg.start; base < sg.end; base += PB) {
+        const int j = base + lp;
+        const bool live = j < sg.end;
+        if (live) {
+            const S* r = src + static_cast<size_t>(j) * rs;
+            const double cx = cen[3 * j] - B.cx, cy = cen[3 * j + 1] - B.cy,
+                         cz = cen[3 * j + 2] - B.cz;
+            for (int t = lt; t < NF; t += TPP) {
+                const int kx = ex.fx[t], ky = ex.fy[t], kz = ex.fz[t];
+                double v = 0.0, k = 0.0;
+                for (int gq = 0; gq < K; ++gq) {
+                    const double d0 = cx + r[4 + 4 * gq], d1 = cy + r[5 + 4 * gq],
+                                 d2 = cz + r[6 + 4 * gq];
+                    const double w = r[7 + 4 * gq];
+                    // powers d^k and d^(k - 1), by successive products from 1
+                    double X = 1.0, Y = 1.0, Z = 1.0, Xm = 1.0, Ym = 1.0, Zm = 1.0;
+                    for (int q = 0; q < kx; ++q) { Xm = X; X *= d0; }
+                    for (int q = 0; q < ky; ++q) { Ym = Y; Y *= d1; }
+                    for (int q = 0; q < kz; ++q) { Zm = Z; Z *= d2; }
+                    v += w * X * Y * Z;
+                    double gs = 0.0;
+                    if (kx > 0) gs += r[0] * kx * Xm * Y * Z;
+                    if (ky > 0) gs += r[1] * ky * X * Ym * Z;
+                    if (kz > 0) gs += r[2] * kz * X * Y * Zm;
+                    k += w * gs;
+                }
+                pv[t] = v;
+                pk[t] = k;
+            }
         }
-        if (A64 != nullptr) {
-            A64[idx] = v;
-            A64[idx + kb] = k;
+        __syncthreads();
+        // fold: level z feeds level z - 2, whose term (x, y) receives c_y M(x, y - 2, z) and
+        // then c_x M(x - 2, y, z), c = -(k - 1) k / ((z - 1) z)
+        for (int z = P; z >= 2; --z) {
+            const int L = P - z + 2;  // x + y <= L at level z - 2
+            const double den = double(z - 1) * double(z);
+            for (int u = lt; u < (L + 1) * (L + 2) / 2; u += TPP) {
+                int x = 0, rem = u;
+                while (rem > L - x) {
+                    rem -= L - x + 1;
+                    ++x;
+                }
+                const int y = rem;
+                if (!live) continue;
+                const int dst = full_term(x, y, z - 2);
+                double v = pv[dst], k = pk[dst];
+                if (y >= 2) {
+                    const double c = -double(y - 1) * double(y) / den;
+                    const int sidx = full_term(x, y - 2, z);
+                    v += c * pv[sidx];
+                    k += c * pk[sidx];
+                }
+                if (x >= 2) {
+                    const double c = -double(x - 1) * double(x) / den;
+                    const int sidx = full_term(x - 2, y, z);
+                    v += c * pv[sidx];
+                    k += c * pk[sidx];
+                }
+                pv[dst] = v;
+                pk[dst] = k;
+            }
+            __syncthreads();
         }
+        if (live) {
+            const int p = j - sg.start, st = p >> 2, kk = p & 3;
+            for (int q = lt; q < NR; q += TPP) {
+                const int rt = q >> 4, lane = (q & 15) + 16 * kk;
+                const size_t idx = a0 + (static_cast<size_t>(st) * RT + rt) * 64 + lane;
+                const double v = pv[ex.rfull[q]], k = pk[ex.rfull[q]];
+                if (A32 != nullptr) {
+                    A32[idx] = static_cast<float>(v);
+                    A32[idx + kb] = static_cast<float>(k);
+                }
+                if (A64 != nullptr) {
+                    A64[idx] = v;
+                    A64[idx + kb] = k;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
