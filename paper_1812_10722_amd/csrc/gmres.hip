@@ -460,24 +460,30 @@ __global__ void __launch_bounds__(GT) k_scale(const double2* src, int64_t src_st
 }
 
 // y = R^{-1} g with R the jn x jn upper triangle of the rotated Hessenberg matrix.
-__global__ void k_backsolve(const double2* __restrict__ H, const double2* __restrict__ gv,
-                            const int32_t* __restrict__ jn, const int32_t* __restrict__ cols,
-                            int nslot, int m, double2* __restrict__ y) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= nslot) return;
-    const int col = cols[slot];
+// One 64-thread block per column: column-oriented back substitution, the right-hand side in
+// LDS (y_k from the finished r_k, then r_i -= H_ik y_k for all i < k in parallel).
+__global__ void __launch_bounds__(64) k_backsolve(const double2* __restrict__ H,
+                                                  const double2* __restrict__ gv,
+                                                  const int32_t* __restrict__ jn,
+                                                  const int32_t* __restrict__ cols, int m,
+                                                  double2* __restrict__ y) {
+    extern __shared__ double2 rs[];  // [m + 1]
+    const int col = cols[blockIdx.x], tid = threadIdx.x;
     const int n = jn[col], m1 = m + 1;
     const double2* Hc = H + static_cast<int64_t>(col) * m * m1;  // column k at Hc + k*m1
     double2* yc = y + col * m;
+    for (int i = tid; i < n; i += 64) rs[i] = gv[col * m1 + i];
+    __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
-        double2 r = gv[col * m1 + k];
-        for (int l = k + 1; l < n; ++l) {
-            const double2 p = cmul(Hc[l * m1 + k], yc[l]);
-            r.x -= p.x;
-            r.y -= p.y;
-        }
         const double2 d = Hc[k * m1 + k];
-        yc[k] = (d.x == 0.0 && d.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(r, d);
+        const double2 yk = (d.x == 0.0 && d.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(rs[k], d);
+        if (tid == 0) yc[k] = yk;
+        for (int i = tid; i < k; i += 64) {
+            const double2 p = cmul(Hc[k * m1 + i], yk);
+            rs[i].x -= p.x;
+            rs[i].y -= p.y;
+        }
+        __syncthreads();
     }
 }
 
@@ -781,9 +787,16 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
             // its precision cannot change (a column's estimate does not rise within a cycle),
             // so the device computes it while the host reads the estimates.  Columns that
             // then finish were multiplied for nothing; the others find w ready.
+            // Not queued either when every column is about to finish (estimates within twice the
+            // tolerance): that product would be wasted whole.
             queued = j + 1 < m;
             if (lead)
                 for (int b : running) queued = queued && level[b] <= lead_level;
+            {
+                bool all_near = true;
+                for (int b : running) all_near = all_near && level[b] <= 2.0 * gm.tol;
+                queued = queued && !all_near;
+            }
             if (queued) {
                 LSPR_HIP(hipEventRecord(est_ready.e, s));
                 product(j + 1, running);
@@ -827,8 +840,8 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
         upload_cols(active);
         const int ns = static_cast<int>(active.size());
         LSPR_HIP(hipMemcpyAsync(jn_d.p, jn.data(), B * 4, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_backsolve, dim3((ns + 63) / 64), dim3(64), 0, s, H.p, gv.p, jn_d.p,
-                           cols_d.p, ns, m, y.p);
+        hipLaunchKernelGGL(k_backsolve, dim3(ns), dim3(64), (m + 1) * sizeof(double2), s, H.p,
+                           gv.p, jn_d.p, cols_d.p, m, y.p);
         hipLaunchKernelGGL(k_basis_combine, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, y.p,
                            m, jn_d.p, cols_d.p, w.p);
         LSPR_HIP(hipGetLastError());

@@ -1042,13 +1042,15 @@ k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
 
 // ---- geometry-only tiles for k_far_tiles (built once per geometry)
 // Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
+// tileA32 (FP64 builds, may be null): the same values rounded to FP32, at the same offsets.
 template <class T, int P>
 __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
                                   const TileDesc* __restrict__ tiles,
                                   const int32_t* __restrict__ m2p_tile,
                                   const int32_t* __restrict__ m2p_chunk,
                                   const int32_t* __restrict__ m2p_box, int n,
-                                  const double* __restrict__ cen, T* __restrict__ tileA) {
+                                  const double* __restrict__ cen, T* __restrict__ tileA,
+                                  float* __restrict__ tileA32) {
     using E = Expansion<P>;
     constexpr int NR = E::NR;
     const int e = blockIdx.x;
@@ -1073,7 +1075,10 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
 #pragma unroll
     for (int q = 0; q < NRP; ++q) {
         const int st = q >> 2, g = q & 3;
-        A[(static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt] = q < NR ? F[q] : T(0);
+        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
+        const T v = q < NR ? F[q] : T(0);
+        A[idx] = v;
+        if (tileA32 != nullptr) tileA32[TD.a_off() + idx] = static_cast<float>(v);
     }
 }
 
@@ -1087,13 +1092,14 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
                                   const int32_t* __restrict__ p2p_tile,
                                   const int32_t* __restrict__ p2p_chunk, int n,
                                   const double* __restrict__ cen, const T* __restrict__ src,
-                                  int K, T* __restrict__ tileA) {
+                                  int K, T* __restrict__ tileA, float* __restrict__ tileA32) {
     const int e = blockIdx.x;
     if (e >= n) return;
     const TileDesc TD = tiles[p2p_tile[e]];
     const Chunk C = chunks[p2p_chunk[e]];
     T* AK = tileA + TD.a_off();
     T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
+    float* BK = tileA32 != nullptr ? tileA32 + TD.a_off() : nullptr;
     const int rs = 4 + 4 * K;
     for (int pr = threadIdx.x; pr < 64 * 4 * TD.nstep; pr += blockDim.x) {
         const int t = pr & 63, p = pr >> 6;  // target, panel within the tile
@@ -1122,6 +1128,10 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
         const size_t idx = (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
         AK[idx] = kk;
         AV[idx] = kv;
+        if (BK != nullptr) {
+            BK[idx] = static_cast<float>(kk);
+            BK[static_cast<size_t>(TD.nstep) * 256 + idx] = static_cast<float>(kv);
+        }
     }
 }
 
@@ -1139,7 +1149,8 @@ __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
                             const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
                             const int32_t* __restrict__ col, const double* __restrict__ dv,
                             const double* __restrict__ dk, const double* __restrict__ vself,
-                            int N, T* __restrict__ tileA, int32_t* __restrict__ missing) {
+                            int N, T* __restrict__ tileA, float* __restrict__ tileA32,
+                            int32_t* __restrict__ missing) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int lo = 0, hi = n_chunks - 1;  // the chunk holding target i (chunks are in target order)
@@ -1169,6 +1180,11 @@ __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
         const size_t idx = (static_cast<size_t>(st) * 64 + 16 * gq + r16) * 4 + mt;
         AK[idx] = static_cast<T>(static_cast<double>(AK[idx]) + add_k);
         AV[idx] = static_cast<T>(static_cast<double>(AV[idx]) + add_v);
+        if (tileA32 != nullptr) {  // FP32 copy of FP64 tiles: the folded values, rounded
+            float* BK = tileA32 + TD.a_off();
+            BK[idx] = static_cast<float>(AK[idx]);
+            BK[static_cast<size_t>(TD.nstep) * 256 + idx] = static_cast<float>(AV[idx]);
+        }
         return true;
     };
     int miss = 0;
@@ -1499,29 +1515,31 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
 }
 
 template <class T, int P>
-void launch_build_m2p(Geometry& g, T* A, const TileDesc* tiles, const int32_t* mt,
+void launch_build_m2p(Geometry& g, T* A, float* A32, const TileDesc* tiles, const int32_t* mt,
                       const int32_t* mc, int n, hipStream_t s) {
     hipLaunchKernelGGL((k_build_m2p_tiles<T, P>), dim3(n), dim3(64), 0, s, g.chunks.p,
-                       g.boxes.p, tiles, mt, mc, g.m2p_box.p, n, g.cen.p, A);
+                       g.boxes.p, tiles, mt, mc, g.m2p_box.p, n, g.cen.p, A, A32);
     LSPR_HIP(hipGetLastError());
 }
 
+// Builds the tiles in precision T; A32 (T = double, may be null): the FP32 store, filled with
+// the same values rounded.
 template <class T>
-void build_tiles_t(Geometry& g, T* A, const int32_t* mt, const int32_t* mc, int n_m2p,
-                   const int32_t* pt, const int32_t* pc, int n_p2p, hipStream_t s) {
+void build_tiles_t(Geometry& g, T* A, float* A32, const int32_t* mt, const int32_t* mc,
+                   int n_m2p, const int32_t* pt, const int32_t* pc, int n_p2p, hipStream_t s) {
     if (n_m2p > 0) {
         switch (g.P) {
-            case 2: launch_build_m2p<T, 2>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
-            case 4: launch_build_m2p<T, 4>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
-            case 6: launch_build_m2p<T, 6>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
-            case 8: launch_build_m2p<T, 8>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
-            case 10: launch_build_m2p<T, 10>(g, A, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 2: launch_build_m2p<T, 2>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 4: launch_build_m2p<T, 4>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 6: launch_build_m2p<T, 6>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 8: launch_build_m2p<T, 8>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 10: launch_build_m2p<T, 10>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
             default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
         }
     }
     if (n_p2p > 0) {
         hipLaunchKernelGGL(k_build_p2p_tiles<T>, dim3(n_p2p), dim3(256), 0, s, g.chunks.p,
-                           g.tiles.p, pt, pc, n_p2p, g.cen.p, src_of<T>(g), g.K, A);
+                           g.tiles.p, pt, pc, n_p2p, g.cen.p, src_of<T>(g), g.K, A, A32);
         LSPR_HIP(hipGetLastError());
     }
 }
@@ -1531,7 +1549,7 @@ void build_tiles_t(Geometry& g, T* A, const int32_t* mt, const int32_t* mc, int 
 // Folds the near-field terms into freshly built direct tiles; false (and the tiles rebuilt
 // without them, so the separate near pass applies) if some pair had no tile.
 template <class T>
-bool fold_near(Geometry& g, T* A, const int32_t* dt_off, const int32_t* dt_row0,
+bool fold_near(Geometry& g, T* A, float* A32, const int32_t* dt_off, const int32_t* dt_row0,
                const int32_t* dt_tile, hipStream_t s,
                const std::function<void()>& rebuild) {
     if (g.N == 0 || g.n_chunks == 0) return false;
@@ -1539,7 +1557,7 @@ bool fold_near(Geometry& g, T* A, const int32_t* dt_off, const int32_t* dt_row0,
     LSPR_HIP(hipMemsetAsync(miss.p, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(k_fold_near<T>, dim3((g.N + 255) / 256), dim3(256), 0, s, g.chunks.p,
                        g.n_chunks, dt_off, dt_row0, dt_tile, g.tiles.p, g.near_off64.p,
-                       g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p, g.N, A, miss.p);
+                       g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p, g.N, A, A32, miss.p);
     LSPR_HIP(hipGetLastError());
     int32_t h = 0;
     copy_sync(&h, miss.p, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -1688,17 +1706,19 @@ void build_tiles(Geometry& g) {
         copy_sync(dtr_d.p, dtr.data(), dtr.size() * 4, hipMemcpyHostToDevice, s);
         copy_sync(dti_d.p, dti.data(), dti.size() * 4, hipMemcpyHostToDevice, s);
     }
-    if (keep32) {
-        g.tileA.alloc(std::max<int64_t>(aoff, 1));
-        auto build = [&] { build_tiles_t<float>(g, g.tileA.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
-        build();
-        g.near_in_tiles32 = fold_near(g, g.tileA.p, dto_d.p, dtr_d.p, dti_d.p, s, build);
-    }
+    // with both stores, one FP64 pass fills both (the FP32 tiles are the FP64 values rounded)
+    if (keep32) g.tileA.alloc(std::max<int64_t>(aoff, 1));
     if (keep64) {
         g.tileA64.alloc(std::max<int64_t>(aoff, 1));
-        auto build = [&] { build_tiles_t<double>(g, g.tileA64.p, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
+        float* a32 = keep32 ? g.tileA.p : nullptr;
+        auto build = [&] { build_tiles_t<double>(g, g.tileA64.p, a32, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
         build();
-        g.near_in_tiles64 = fold_near(g, g.tileA64.p, dto_d.p, dtr_d.p, dti_d.p, s, build);
+        g.near_in_tiles64 = fold_near(g, g.tileA64.p, a32, dto_d.p, dtr_d.p, dti_d.p, s, build);
+        if (keep32) g.near_in_tiles32 = g.near_in_tiles64;
+    } else if (keep32) {
+        auto build = [&] { build_tiles_t<float>(g, g.tileA.p, nullptr, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
+        build();
+        g.near_in_tiles32 = fold_near(g, g.tileA.p, nullptr, dto_d.p, dtr_d.p, dti_d.p, s, build);
     }
     LSPR_HIP(hipStreamSynchronize(s));
     if (g.n_seg > 0) {  // moments on matrix cores as well, for each precision with tiles
