@@ -312,6 +312,40 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
                            const lspr_op_params* op, const lspr_gmres_params* gm,
                            int64_t* bytes);
 
+/* Autotuner for the treecode parameters of a mesh (the paper picks P and theta by hand per
+ * experiment, section "Acceleration strategies", Tables treeparams1/2): expansion order
+ * P in {4, 6, 8, 10}, acceptance parameter theta in {0.4, 0.5, 0.6, 0.7} and leaf size N_crit
+ * in {8, 16, 32}.  The truncation error of a candidate is measured apart from rounding: the
+ * relative 2-norm difference between its FP64 product of the system matrix (first
+ * wavelength's permittivities, a fixed pseudo-random complex vector) and a reference product
+ * (the dense FP64 product for N <= 40000 panels, otherwise the treecode at P = 10, theta =
+ * 0.3).  For each (theta, N_crit) the smallest P that meets max_rel_err is timed: n_cols
+ * columns in the product precision of op (FP32 unless op->precision is LSPR_FP64), fastest of
+ * three after one warm-up, HIP events on `stream`.  The fastest candidate that meets the bound
+ * is written to op->p, op->theta, op->ncrit (op->method becomes LSPR_TREECODE; the other
+ * fields are kept and used for every candidate).
+ *   surfaces     device pointers, as lspr_geometry_create
+ *   n_cols       columns of the timed product, 1..64
+ *   eps_medium   host [1]; eps_surface host [n_surf]
+ *   entries      host [max_entries] or null: every candidate tried, in order (ms_per_product
+ *                -1 when it was not timed); *n_entries receives their number (it may exceed
+ *                max_entries, the rest is not stored)
+ * Device memory: the reference (dense FP64 tiles: 16 N^2 bytes) and one candidate geometry at
+ * a time.  LSPR_E_NOCONV when no candidate meets the bound (op then holds the most accurate
+ * one); LSPR_E_INVALID for bad arguments. */
+typedef struct {
+    int32_t p;
+    int32_t ncrit;
+    double theta;
+    double rel_err;         /* FP64 product against the reference */
+    double ms_per_product;  /* n_cols columns in the timed precision, or -1 */
+} lspr_tune_entry;
+
+int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
+                  const lspr_c64* eps_medium, const lspr_c64* eps_surface, double max_rel_err,
+                  lspr_op_params* op, lspr_tune_entry* entries, int32_t max_entries,
+                  int32_t* n_entries, void* stream);
+
 /* Resonance peak of a sampled extinction spectrum (the quantity a plasmonic sensor reads: the
  * peak position and its shift when analytes bind, section "Results", sensing experiments).
  * lambda host [n] strictly increasing, cext host [n], n >= 3.  The peak is the vertex of the

@@ -598,6 +598,145 @@ int lspr_rhs(lspr_geometry* h, int32_t n_cols, const lspr_c64* eps_medium,
     });
 }
 
+int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
+                  const lspr_c64* eps_medium, const lspr_c64* eps_surface, double max_rel_err,
+                  lspr_op_params* op, lspr_tune_entry* entries, int32_t max_entries,
+                  int32_t* n_entries, void* stream) {
+    return guarded([&] {
+        LSPR_REQUIRE(surfaces && op && eps_medium && eps_surface && n_entries && n_surf >= 1 &&
+                         n_cols >= 1 && n_cols <= MAX_BATCH && max_rel_err > 0.0 &&
+                         max_entries >= 0 && (entries != nullptr || max_entries == 0),
+                     LSPR_E_INVALID, "bad arguments");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        lspr::PoolScope ps(s);
+        int64_t N = 0;
+        for (int k = 0; k < n_surf; ++k) N += surfaces[k].n_tri;
+        const int64_t nvec = 2 * N;
+        // probe vector in caller order: a fixed linear congruential sequence in [-1, 1)
+        std::vector<double2> xh(nvec);
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        auto uni = [&] {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            return static_cast<double>(st >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        };
+        for (auto& v : xh) {
+            v.x = uni();
+            v.y = uni();
+        }
+        lspr::DevBuf<double2> x(nvec), y(nvec), yref(nvec);
+        LSPR_HIP(hipMemcpyAsync(x.p, xh.data(), nvec * sizeof(double2), hipMemcpyHostToDevice, s));
+        std::vector<lspr_c64> em(n_cols, eps_medium[0]), es;
+        for (int c = 0; c < n_cols; ++c)
+            for (int k = 0; k < n_surf; ++k) es.push_back(eps_surface[k]);
+        const lspr::EpsSet e1 = make_eps(1, n_surf, em.data(), es.data());
+        const lspr::EpsSet eb = make_eps(n_cols, n_surf, em.data(), es.data());
+        // product of the probe vector in precision prec (caller order)
+        auto product = [&](lspr::Geometry& g, int prec, double2* out) {
+            lspr::DevBuf<double2> ratio, xs(nvec), ys(nvec);
+            lspr::upload_ratios(g, e1, 1, ratio, s);
+            lspr::to_sorted(g, 1, x.p, xs.p, s);
+            lspr::system_apply(g, prec, 1, ratio.p, xs.p, nvec, ys.p, nvec, nullptr, s);
+            lspr::from_sorted(g, 1, ys.p, out, s);
+            LSPR_HIP(hipStreamSynchronize(s));
+        };
+        std::vector<double2> yh(nvec), rh(nvec);
+        {
+            lspr_op_params r = *op;
+            r.precision = LSPR_FP64;
+            if (N <= 40000) {
+                r.method = LSPR_DENSE;
+            } else {
+                r.method = LSPR_TREECODE;
+                r.p = 10;
+                r.theta = 0.3;
+            }
+            lspr::Geometry gr;
+            lspr::create_geometry(gr, surfaces, n_surf, r, s);
+            product(gr, LSPR_FP64, yref.p);
+        }
+        LSPR_HIP(hipMemcpy(rh.data(), yref.p, nvec * sizeof(double2), hipMemcpyDeviceToHost));
+        double rn = 0.0;
+        for (const auto& v : rh) rn += v.x * v.x + v.y * v.y;
+        rn = std::sqrt(rn);
+        LSPR_REQUIRE(rn > 0.0, LSPR_E_INVALID, "zero reference product");
+        const int tprec = op->precision == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32;
+        const int orders[] = {4, 6, 8, 10};
+        const double thetas[] = {0.4, 0.5, 0.6, 0.7};
+        const int leaves[] = {8, 16, 32};
+        hipEvent_t e0 = nullptr, e_1 = nullptr;
+        LSPR_HIP(hipEventCreate(&e0));
+        LSPR_HIP(hipEventCreate(&e_1));
+        int count = 0;
+        lspr_tune_entry best{0, 0, 0.0, 0.0, -1.0}, closest{0, 0, 0.0, 1e300, -1.0};
+        try {
+            for (double th : thetas)
+                for (int nc : leaves)
+                    for (int P : orders) {
+                        lspr_op_params c = *op;
+                        c.method = LSPR_TREECODE;
+                        c.p = P;
+                        c.theta = th;
+                        c.ncrit = nc;
+                        // both tile stores: FP64 for the error, the timed precision for speed
+                        c.precision = tprec == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32_LEAD64;
+                        lspr::Geometry g;
+                        lspr::create_geometry(g, surfaces, n_surf, c, s);
+                        product(g, LSPR_FP64, y.p);
+                        LSPR_HIP(hipMemcpy(yh.data(), y.p, nvec * sizeof(double2),
+                                           hipMemcpyDeviceToHost));
+                        double dn = 0.0;
+                        for (int64_t i = 0; i < nvec; ++i) {
+                            const double dx = yh[i].x - rh[i].x, dy = yh[i].y - rh[i].y;
+                            dn += dx * dx + dy * dy;
+                        }
+                        lspr_tune_entry t{P, nc, th, std::sqrt(dn) / rn, -1.0};
+                        if (t.rel_err <= max_rel_err) {
+                            lspr::DevBuf<double2> ratio, ys(n_cols * nvec), xs(nvec);
+                            lspr::upload_ratios(g, eb, n_cols, ratio, s);
+                            lspr::to_sorted(g, 1, x.p, xs.p, s);
+                            float ms_min = 1e30f;
+                            for (int rep = 0; rep < 4; ++rep) {
+                                LSPR_HIP(hipEventRecord(e0, s));
+                                // every column multiplies the same vector (stride 0)
+                                lspr::system_apply(g, tprec, n_cols, ratio.p, xs.p, 0, ys.p,
+                                                   nvec, nullptr, s);
+                                LSPR_HIP(hipEventRecord(e_1, s));
+                                LSPR_HIP(hipEventSynchronize(e_1));
+                                float ms = 0.0f;
+                                LSPR_HIP(hipEventElapsedTime(&ms, e0, e_1));
+                                if (rep > 0) ms_min = std::min(ms_min, ms);
+                            }
+                            t.ms_per_product = ms_min;
+                            if (best.ms_per_product < 0.0 || t.ms_per_product < best.ms_per_product)
+                                best = t;
+                        }
+                        if (t.rel_err < closest.rel_err) closest = t;
+                        if (count < max_entries) entries[count] = t;
+                        ++count;
+                        LSPR_HIP(hipStreamSynchronize(s));
+                        if (t.rel_err <= max_rel_err) break;  // a higher order only costs more
+                    }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e_1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e_1);
+        *n_entries = count;
+        const lspr_tune_entry& pick = best.ms_per_product >= 0.0 ? best : closest;
+        op->method = LSPR_TREECODE;
+        op->p = pick.p;
+        op->theta = pick.theta;
+        op->ncrit = pick.ncrit;
+        if (best.ms_per_product < 0.0) {
+            lspr::last_error() = "no candidate meets the error bound";
+            return static_cast<int>(LSPR_E_NOCONV);
+        }
+        return static_cast<int>(LSPR_OK);
+    });
+}
+
 int lspr_solve(lspr_geometry* h, int32_t n_lambda, const double* lambda_nm,
                const lspr_c64* eps_medium, const lspr_c64* eps_surface, const double* e_field,
                const lspr_gmres_params* gm, void* stream, lspr_c64* phi, lspr_c64* dphi,

@@ -11,6 +11,9 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: its HIP runtime is then the one this library binds to, whatever the caller
+# imports next (two runtimes in one process do not see the same device)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblspr.so")
@@ -338,6 +341,48 @@ _sig("lspr_server_stats_get", C.c_int, [C.c_void_p, _P(lspr_server_stats)])
 _sig("lspr_server_destroy", C.c_int, [C.c_void_p])
 _sig("lspr_request_footprint", C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P(lspr_op_params),
                                          _P(lspr_gmres_params), _P(C.c_int64)])
+
+
+class lspr_tune_entry(C.Structure):
+    _fields_ = [("p", C.c_int32), ("ncrit", C.c_int32), ("theta", C.c_double),
+                ("rel_err", C.c_double), ("ms_per_product", C.c_double)]
+
+
+_sig("lspr_autotune", C.c_int, [_P(lspr_surface), C.c_int32, C.c_int32, _P(lspr_c64),
+                                 _P(lspr_c64), C.c_double, _P(lspr_op_params),
+                                 _P(lspr_tune_entry), C.c_int32, _P(C.c_int32), C.c_void_p])
+
+
+def lspr_autotune(surfaces, n_cols, eps_medium, eps_surface, max_rel_err=1e-5, op=None,
+                  stream=None, **op_kw):
+    """Treecode parameters for a mesh (lspr_autotune).  surfaces: list of (verts, tris) torch
+    cuda tensors or numpy arrays (uploaded); eps_surface: one value per surface.  Returns
+    (op, entries, ok): op the lspr_op_params with the chosen p, theta, ncrit; entries a list of
+    dicts (every candidate tried); ok False when no candidate met the bound."""
+    import torch
+    op = op if op is not None else op_params(**op_kw)
+    dev = []
+    for v, t in surfaces:
+        if isinstance(v, torch.Tensor):
+            dev.append((v.to(dtype=torch.float64).contiguous(), t.to(dtype=torch.int32).contiguous()))
+        else:
+            dev.append((torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)).cuda(),
+                        torch.as_tensor(np.ascontiguousarray(t, dtype=np.int32)).cuda()))
+    arr = (lspr_surface * len(dev))()
+    for k, (dv, dt) in enumerate(dev):
+        arr[k] = lspr_surface(dv.shape[0], dv.data_ptr(), dt.shape[0], dt.data_ptr())
+    em = (lspr_c64 * 1)(lspr_c64(complex(eps_medium).real, complex(eps_medium).imag))
+    es_list = [complex(e) for e in np.ravel(eps_surface)]
+    es = (lspr_c64 * len(es_list))(*[lspr_c64(e.real, e.imag) for e in es_list])
+    cap = 64
+    ent = (lspr_tune_entry * cap)()
+    n = C.c_int32()
+    code = _lib.lspr_autotune(arr, len(dev), int(n_cols), em, es, float(max_rel_err),
+                              C.byref(op), ent, cap, C.byref(n), _stream_ptr(stream))
+    _check(code, "lspr_autotune", allow=(LSPR_E_NOCONV,))
+    entries = [{name: getattr(ent[k], name) for name, _ in lspr_tune_entry._fields_}
+               for k in range(min(n.value, cap))]
+    return op, entries, code == LSPR_OK
 
 
 def lspr_request_footprint(n_panels, n_surf, n_lambda, op, gm) -> int:

@@ -306,3 +306,35 @@ def test_leading_fp64_products(lib):
     for out in (lead, all64):
         rel = np.abs(out["cext_total"] / o64["cext_total"] - 1)
         assert rel.max() < 2e-5, rel
+
+
+def test_autotune_meets_the_bound_and_picks_the_fastest(lib):
+    """The autotuner's choice meets its error bound, checked again here with another vector
+    against the oracle's dense matrix, and is the fastest timed candidate."""
+    v, t = octasphere(12, 10.0)  # 1152 panels
+    em = EPS_WATER + 0j
+    es = eps_silver_drude(np.array([380.0]))
+    bound = 1e-5
+    op, entries, ok = lib.lspr_autotune([(v, t)], 8, em, es, max_rel_err=bound)
+    assert ok and entries
+    timed = [e for e in entries if e["ms_per_product"] >= 0]
+    assert timed and all(e["rel_err"] <= bound for e in timed)
+    assert all(e["rel_err"] > bound for e in entries if e["ms_per_product"] < 0)
+    fastest = min(timed, key=lambda e: e["ms_per_product"])
+    assert (op.p, op.ncrit) == (fastest["p"], fastest["ncrit"])
+    assert abs(op.theta - fastest["theta"]) < 1e-12 and op.method == lib.LSPR_TREECODE
+    # each (theta, N_crit) stops at its first order that meets the bound, orders ascending
+    for th in {e["theta"] for e in entries}:
+        for nc in {e["ncrit"] for e in entries}:
+            ps = [e["p"] for e in entries if e["theta"] == th and e["ncrit"] == nc]
+            assert ps == sorted(ps)
+    op.precision = lib.LSPR_FP64
+    surfs = [(v, t)]
+    _, _, sid, V, K, g = _dense_system(surfs, None, None)
+    A, _ = oracle.assemble_system(V, K, sid, g["normal"], em, es, [0, 0, 1.0])
+    x = _rand_x(np.random.default_rng(5), 1, len(t))
+    geo = lib.Geometry(surfs, op=op)
+    y = geo.apply(torch.as_tensor(x).cuda(), np.array([em]), es[:, None]).cpu().numpy()
+    geo.close()
+    ref = A @ x[0]
+    assert np.linalg.norm(y[0] - ref) / np.linalg.norm(ref) < 3 * bound
