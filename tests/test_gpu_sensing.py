@@ -73,3 +73,65 @@ def test_shift_decreases_with_analyte_distance(lib):
         else:
             shifts.append(pk - base)
     assert shifts[0] > shifts[1] > shifts[2] > 0.0, shifts
+
+
+def _rotate(surfs, R):
+    return [(v @ R.T, t) for v, t in surfs]
+
+
+def test_rotated_configuration_gives_the_same_spectrum(lib):
+    """Sensor and two analytes along z under a field along z, and the same configuration turned
+    so that z becomes x (a proper rotation), with the field along x: C_ext is the same (treecode
+    FP64: the tree, lists and tiles differ, the result only at truncation level)."""
+    lam = wavelength_grid(378.0, 390.0, 5)
+    surfs = _sensor(16, 5, 1.0)
+    R = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])  # (x, y, z) -> (z, x, y)
+    em, es = _spectrum(surfs, lam)
+    kw = dict(method="treecode", precision="fp64", p=8, theta=0.5)
+    a = studies().spectrum(surfs, lam, em, es, [0, 0, 1.0], gmres=lib.gmres_params(tol=1e-10),
+                           **kw)
+    b = studies().spectrum(_rotate(surfs, R), lam, em, es, [1.0, 0, 0],
+                           gmres=lib.gmres_params(tol=1e-10), **kw)
+    for key in ("cext_sensor", "cext_total"):
+        assert np.abs(a[key] / b[key] - 1).max() < 1e-5, key
+    assert np.abs(a["p_total"][:, 2] - b["p_total"][:, 0]).max() < 1e-5 * np.abs(a["p_total"]).max()
+
+
+def studies():
+    from paper_1812_10722_amd import studies as st
+    return st
+
+
+def test_field_along_the_analytes_shifts_the_peak_most(lib):
+    """Placement and polarisation (the paper's +-x / +-y placements): two analytes at +-z, field
+    along z (the analytes sit where the field of the plasmon is strongest) against the same
+    analytes under a field along x; the first shift is the larger, and both are red shifts."""
+    lam = wavelength_grid(374.0, 394.0, 21)
+    surfs = _sensor(32, 10, 1.0)
+    kw = dict(method="treecode", precision="fp32_lead64", p=8, theta=0.5,
+              gmres=lib.gmres_params(tol=1e-6, restart=60, max_iter=800))
+    es = eps_silver_drude(lam)
+    along = studies().resonance_shift(surfs[0], surfs[1:], lam, EPS_WATER, es, 2.5,
+                                      (0.0, 0.0, 1.0), **kw)
+    across = studies().resonance_shift(surfs[0], surfs[1:], lam, EPS_WATER, es, 2.5,
+                                       (1.0, 0.0, 0.0), **kw)
+    assert along["converged"] and across["converged"]
+    assert along["shift"] > across["shift"] > 0.0, (along, across)
+    assert abs(along["peak_alone"] - across["peak_alone"]) < 1e-3  # the sphere alone: isotropic
+
+
+def test_grid_convergence_and_richardson(lib):
+    """C_ext of the R = 10 nm silver sphere at 370 nm on meshes of 512 to 32768 panels against
+    Eq. an_sol: the error falls with N at an observed order near 1 (the paper's grid study), and
+    the Richardson value of the two finest meshes is closer to the exact one than either."""
+    lam = 370.0
+    es = complex(eps_silver_drude(np.array([lam]))[0])
+    meshes = [octasphere(nu, 10.0) for nu in (8, 16, 32, 64)]
+    out = studies().grid_convergence(meshes, lam, EPS_WATER, es, method="treecode",
+                                     precision="fp64", p=8, theta=0.5,
+                                     gmres=lib.gmres_params(tol=1e-9, restart=100, max_iter=2000))
+    exact = oracle.cext_sphere_analytic(10.0, lam, es, EPS_WATER)
+    err = [abs(c / exact - 1) for c in out["cext"]]
+    assert all(b < a for a, b in zip(err, err[1:])), err
+    assert 0.6 < out["order"] < 1.6, out
+    assert abs(out["richardson"] / exact - 1) < err[-1] / 3, (out, err)
