@@ -13,7 +13,10 @@ integral_eq_lspr_system, written as matrices in Eqs. matrix_lspr and matrix_mult
 
 The incident potential of a uniform field E is phi_inc = -E . r.  Unknown order in the 2N
 vector: all phi (panel order of the caller), then all psi; rows: all interior rows, then all
-exterior rows.  No point charges (the analytes of the synthetic workloads carry none).
+exterior rows.  Point charges q_k at r_k inside surface s (Eq. integral_eq_lspr_system, last row:
+charges of an analyte) put (1 / (4 pi eps_s)) sum_k q_k / |x_i - r_k| on the right of the
+interior rows of the panels i of surface s (eps_s relative, q_k divided by the vacuum
+permittivity, in the units of the potential times length).
 """
 from __future__ import annotations
 
@@ -24,8 +27,24 @@ from .operators import dense_operators
 from .dipole import exterior_traces, dipole_moment, extinction_cross_section
 
 
-def assemble_system(V, K, surf_id, normals, eps_m, eps_surf, e_field):
-    """Dense complex matrix A [2N, 2N] and right-hand side b [2N] for one wavelength."""
+def charge_potential(centroids, surf_id, charges, eps_surf):
+    """Interior right-hand side of the point charges: for each panel i of surface s,
+    (1 / (4 pi eps_s)) sum over the charges of surface s of q_k / |x_i - r_k|.  charges:
+    (positions [Nq, 3], values [Nq], surfaces [Nq])."""
+    pos, q, sq = (np.asarray(a) for a in charges)
+    out = np.zeros(len(surf_id), dtype=np.complex128)
+    for i in range(len(surf_id)):
+        on = sq == surf_id[i]
+        if np.any(on):
+            r = np.linalg.norm(centroids[i][None, :] - pos[on], axis=1)
+            out[i] = np.sum(q[on] / r) / (4.0 * np.pi * eps_surf[surf_id[i]])
+    return out
+
+
+def assemble_system(V, K, surf_id, normals, eps_m, eps_surf, e_field, centroids=None,
+                    charges=None):
+    """Dense complex matrix A [2N, 2N] and right-hand side b [2N] for one wavelength (with
+    point charges: centroids [N, 3] and charges as in charge_potential)."""
     N = len(surf_id)
     same = surf_id[:, None] == surf_id[None, :]
     eps_panel = np.asarray(eps_surf)[surf_id]
@@ -38,6 +57,8 @@ def assemble_system(V, K, surf_id, normals, eps_m, eps_surf, e_field):
     g = -(normals @ np.asarray(e_field, dtype=np.float64))
     b = np.zeros(2 * N, dtype=np.complex128)
     b[N:] = V @ (((eps_m - eps_panel) / eps_m) * g)
+    if charges is not None and len(charges[1]) > 0:
+        b[:N] = charge_potential(centroids, surf_id, charges, np.asarray(eps_surf))
     return A, b
 
 
@@ -126,11 +147,13 @@ def gmres(matvec, b, tol=1e-10, restart=50, max_iter=2000):
 
 
 def solve(verts, tris, surf_id, lambdas, eps_medium, eps_surface, e_field, k_far=4, k_fine=19,
-          n_k=9, threshold=0.5, method="lu", tol=1e-10, restart=50, max_iter=2000):
+          n_k=9, threshold=0.5, method="lu", tol=1e-10, restart=50, max_iter=2000,
+          charges=None):
     """Solve every wavelength densely; returns a dict of per-wavelength results.
 
     eps_medium [n_lambda] and eps_surface [n_lambda, n_surf] are complex relative
     permittivities; e_field is the real incident field vector.  `method` is "lu" or "gmres".
+    charges: optional (positions, values, surfaces), see charge_potential.
     """
     surf_id = np.asarray(surf_id)
     geom = panel_geometry(verts, tris)
@@ -143,7 +166,8 @@ def solve(verts, tris, surf_id, lambdas, eps_medium, eps_surface, e_field, k_far
     for li, lam in enumerate(lambdas):
         em = complex(eps_medium[li])
         es = np.asarray(eps_surface[li], dtype=np.complex128)
-        A, b = assemble_system(V, K, surf_id, geom["normal"], em, es, e_field)
+        A, b = assemble_system(V, K, surf_id, geom["normal"], em, es, e_field,
+                               geom["centroid"], charges)
         if method == "lu":
             x = solve_lu(A, b)
             iters, res = 0, float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))

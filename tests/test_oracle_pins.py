@@ -327,3 +327,32 @@ def test_system_rows_are_rows_of_the_assembled_system():
     inner, outer = oracle.system_rows(V[rows], K[rows], rows, sid, eps_m, eps_s)
     N = len(t)
     assert np.array_equal(inner, A[rows]) and np.array_equal(outer, A[N + rows])
+
+
+def test_point_charge_at_the_centre_of_a_dielectric_sphere():
+    """Closed form (Born's ion): a charge q at the centre of a sphere of radius R and
+    permittivity eps_in in a medium eps_out.  Outside, phi = q / (4 pi eps_out r); inside,
+    phi = q / (4 pi eps_in r) + const, so on the surface phi = q / (4 pi eps_out R) and the
+    interior normal derivative is -q / (4 pi eps_in R^2).  The charge's response is the
+    difference of solves with and without it (the system is linear); the flat-panel error
+    falls at second order in the panel size."""
+    R, eps_in, eps_out, q = 10.0, 2.0 + 0.0j, 1.7733 + 0.0j, 3.0
+    errs = []
+    for nu in (6, 12):
+        v, t = octasphere(nu, R)
+        sid = np.zeros(len(t), int)
+        kw = dict(lambdas=[500.0], eps_medium=[eps_out], eps_surface=[[eps_in]],
+                  e_field=[0.0, 0.0, 1.0])
+        with_q = oracle.solve(v, t, sid, charges=(np.zeros((1, 3)), np.array([q]),
+                                                  np.array([0])), **kw)
+        without = oracle.solve(v, t, sid, **kw)
+        phi = with_q["phi"][0] - without["phi"][0]
+        dphi = with_q["dphi"][0] - without["dphi"][0]
+        area = oracle.panel_geometry(v, t)["area"]
+        phi_avg = np.sum(area * phi) / area.sum()
+        dphi_avg = np.sum(area * dphi) / area.sum()
+        e_phi = abs(phi_avg / (q / (4 * np.pi * eps_out * R)) - 1)
+        e_dphi = abs(dphi_avg / (-q / (4 * np.pi * eps_in * R * R)) - 1)
+        errs.append((e_phi, e_dphi))
+    assert errs[1][0] < 0.01 and errs[1][1] < 0.01, errs
+    assert errs[1][0] < errs[0][0] / 2.5 and errs[1][1] < errs[0][1] / 2.5, errs
