@@ -346,6 +346,18 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
                   lspr_op_params* op, lspr_tune_entry* entries, int32_t max_entries,
                   int32_t* n_entries, void* stream);
 
+/* Point charges inside the surfaces (Eq. integral_eq_lspr_system, last row: the charges of an
+ * analyte put (1 / (4 pi eps_s)) sum_k q_k / |x_i - r_k| on the right of the interior rows of
+ * its panels i, eps_s the surface's relative permittivity at each wavelength).  Host arrays:
+ * pos [n_q][3] (same length unit as the mesh), q [n_q] (charge divided by the vacuum
+ * permittivity, in units of the incident potential times length: one elementary charge is
+ * 18.0951 V nm), surface [n_q] (index of the enclosing surface).  The geometry keeps
+ * sum_k q_k / (4 pi |c_i - r_k|) per panel (FP64, direct sum) for every later lspr_solve and
+ * lspr_rhs; n_q = 0 removes the charges.  The request server does not take charges.
+ * LSPR_E_INVALID for a surface index out of range or non-finite values. */
+int lspr_geometry_set_charges(lspr_geometry* g, int32_t n_q, const double* pos, const double* q,
+                              const int32_t* surface, void* stream);
+
 /* Resonance peak of a sampled extinction spectrum (the quantity a plasmonic sensor reads: the
  * peak position and its shift when analytes bind, section "Results", sensing experiments).
  * lambda host [n] strictly increasing, cext host [n], n >= 3.  The peak is the vertex of the

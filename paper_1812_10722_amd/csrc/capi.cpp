@@ -414,7 +414,7 @@ size_t lspr::Geometry::device_bytes() const {
            mom_boxes_d.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
-           vself.bytes() + rhs_u.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
+           vself.bytes() + rhs_u.bytes() + charge_u.bytes() + ws_inv_eps.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
            ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2mA64.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
@@ -521,6 +521,18 @@ int lspr_geometry_destroy(lspr_geometry* g) {
             lspr::PoolScope ps(g->g.stream);  // pooled memory goes back on the geometry's stream
             delete g;
         }
+        return LSPR_OK;
+    });
+}
+
+int lspr_geometry_set_charges(lspr_geometry* h, int32_t n_q, const double* pos, const double* q,
+                              const int32_t* surface, void* stream) {
+    return guarded([&] {
+        LSPR_REQUIRE(h && n_q >= 0 && (n_q == 0 || (pos && q && surface)), LSPR_E_INVALID,
+                     "bad arguments");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        lspr::PoolScope ps(s);
+        lspr::set_charges(h->g, n_q, pos, q, surface, s);
         return LSPR_OK;
     });
 }

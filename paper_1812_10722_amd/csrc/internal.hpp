@@ -309,6 +309,11 @@ struct Geometry {
     DevBuf<double> rhs_u;      // [S][3][N]
     // workspaces reused by the operator
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
+    // point charges: charge_u[i] = sum over the charges inside panel i's surface of
+    // q_k / (4 pi |c_i - r_k|) (sorted order; empty without charges); ws_inv_eps: 1 / eps_s
+    // [column][surface] of the current batch, filled with the ratios
+    DevBuf<double> charge_u;
+    DevBuf<double2> ws_inv_eps;
     hipStream_t stream = nullptr;
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
     int far_op_min_pad = 16;  // products with at least this many columns per operator run

@@ -96,10 +96,13 @@ __global__ void k_combine(const double2* __restrict__ x, int64_t x_stride,
     yc[N + i] = make_double2(0.5 * phi.x - k_all.x + v_all.x, 0.5 * phi.y - k_all.y + v_all.y);
 }
 
-// b = [0; sum_s (1 - r_s) sum_d E_d u[s][d]] / 4pi per column
+// b = [cu / eps_s; sum_s (1 - r_s) sum_d E_d u[s][d] / 4pi] per column (cu: the point charges'
+// potential times eps_s on the interior rows of their surface, or null)
 __global__ void k_rhs(const double* __restrict__ u, int S, int N, int ncolumn,
                       const double2* __restrict__ ratio, double e0, double e1, double e2,
-                      double2* __restrict__ b, int64_t b_stride) {
+                      const double* __restrict__ cu, const double2* __restrict__ inv_eps,
+                      const int32_t* __restrict__ surf, double2* __restrict__ b,
+                      int64_t b_stride) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<int64_t>(N) * ncolumn) return;
     const int col = static_cast<int>(t / N), i = static_cast<int>(t % N);
@@ -111,8 +114,30 @@ __global__ void k_rhs(const double* __restrict__ u, int S, int N, int ncolumn,
         acc.x += (1.0 - r.x) * us;
         acc.y += -r.y * us;
     }
-    b[col * b_stride + i] = make_double2(0.0, 0.0);
+    double2 in = make_double2(0.0, 0.0);
+    if (cu != nullptr) {
+        const double2 ie = inv_eps[col * S + surf[i]];
+        in = make_double2(cu[i] * ie.x, cu[i] * ie.y);
+    }
+    b[col * b_stride + i] = in;
     b[col * b_stride + N + i] = acc;
+}
+
+// charge_u[i] = sum over the charges of panel i's surface (off[s] .. off[s + 1]) of
+// q_k / (4 pi |c_i - r_k|), in order
+__global__ void k_charge_u(const double* __restrict__ cen, const int32_t* __restrict__ surf,
+                           int N, const double* __restrict__ pos, const double* __restrict__ q,
+                           const int32_t* __restrict__ off, double* __restrict__ cu) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = surf[i];
+    double acc = 0.0;
+    for (int k = off[s]; k < off[s + 1]; ++k) {
+        const double dx = cen[3 * i] - pos[3 * k], dy = cen[3 * i + 1] - pos[3 * k + 1],
+                     dz = cen[3 * i + 2] - pos[3 * k + 2];
+        acc += q[k] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    cu[i] = acc * INV_4PI;
 }
 
 // RHS geometry columns: V column 3s + d holds -n_d on surface s, zero elsewhere.
@@ -180,7 +205,50 @@ void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hi
     }
     d.reserve(h.size());
     LSPR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    if (g.charge_u.p != nullptr) {  // 1 / eps_s for the charges' right-hand side
+        std::vector<double2> ie(static_cast<size_t>(B) * g.S);
+        for (size_t k = 0; k < ie.size(); ++k) {
+            const double sr = eps.es_re[k], si = eps.es_im[k], dd = sr * sr + si * si;
+            ie[k] = make_double2(sr / dd, -si / dd);
+        }
+        g.ws_inv_eps.reserve(ie.size());
+        LSPR_HIP(hipMemcpyAsync(g.ws_inv_eps.p, ie.data(), ie.size() * sizeof(double2),
+                                hipMemcpyHostToDevice, s));
+        LSPR_HIP(hipStreamSynchronize(s));  // ie is local
+    }
     LSPR_HIP(hipStreamSynchronize(s));  // h is local
+}
+
+void set_charges(Geometry& g, int n_q, const double* pos, const double* q, const int32_t* sid,
+                 hipStream_t s) {
+    g.charge_u.release();
+    if (n_q == 0) return;
+    std::vector<int32_t> order(n_q), off(g.S + 1, 0);
+    for (int k = 0; k < n_q; ++k) {
+        LSPR_REQUIRE(sid[k] >= 0 && sid[k] < g.S, LSPR_E_INVALID, "charge surface out of range");
+        LSPR_REQUIRE(std::isfinite(pos[3 * k]) && std::isfinite(pos[3 * k + 1]) &&
+                         std::isfinite(pos[3 * k + 2]) && std::isfinite(q[k]),
+                     LSPR_E_INVALID, "charges must be finite");
+        ++off[sid[k] + 1];
+    }
+    for (int t = 0; t < g.S; ++t) off[t + 1] += off[t];
+    std::vector<double> p_s(3 * static_cast<size_t>(n_q)), q_s(n_q);
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int k = 0; k < n_q; ++k) {  // grouped by surface, input order kept within a surface
+        const int at = fill[sid[k]]++;
+        for (int d = 0; d < 3; ++d) p_s[3 * at + d] = pos[3 * k + d];
+        q_s[at] = q[k];
+    }
+    DevBuf<double> pd(p_s.size()), qd(q_s.size());
+    DevBuf<int32_t> od(off.size());
+    copy_sync(pd.p, p_s.data(), p_s.size() * 8, hipMemcpyHostToDevice, s);
+    copy_sync(qd.p, q_s.data(), q_s.size() * 8, hipMemcpyHostToDevice, s);
+    copy_sync(od.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s);
+    g.charge_u.alloc(g.N);
+    hipLaunchKernelGGL(k_charge_u, dim3((g.N + TPB - 1) / TPB), dim3(TPB), 0, s, g.cen.p,
+                       g.surf.p, g.N, pd.p, qd.p, od.p, g.charge_u.p);
+    LSPR_HIP(hipGetLastError());
+    LSPR_HIP(hipStreamSynchronize(s));
 }
 
 // y[col] = A(eps[col]) x[col] for the nslot columns listed in d_cols (or 0..nslot-1).
@@ -216,8 +284,13 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
 void system_rhs(Geometry& g, int ncolumn, const double2* ratio_d, const double* e_field,
                 double2* b, int64_t b_stride, hipStream_t s) {
     const int64_t t = static_cast<int64_t>(g.N) * ncolumn;
+    const bool q = g.charge_u.p != nullptr;
+    LSPR_REQUIRE(!q || g.ws_inv_eps.n >= static_cast<size_t>(ncolumn) * g.S, LSPR_E_INVALID,
+                 "permittivities of the batch not uploaded");
     hipLaunchKernelGGL(k_rhs, dim3((t + TPB - 1) / TPB), dim3(TPB), 0, s, g.rhs_u.p, g.S, g.N,
-                       ncolumn, ratio_d, e_field[0], e_field[1], e_field[2], b, b_stride);
+                       ncolumn, ratio_d, e_field[0], e_field[1], e_field[2],
+                       q ? g.charge_u.p : nullptr, q ? g.ws_inv_eps.p : nullptr, g.surf.p, b,
+                       b_stride);
     LSPR_HIP(hipGetLastError());
 }
 

@@ -21,7 +21,12 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
                   int64_t x_stride, double2* y, int64_t y_stride, const int32_t* d_cols,
                   hipStream_t s, bool precond = false);
 
-// b[col] for columns 0..ncolumn-1 (sorted order, stride b_stride).
+// Point charges (host arrays: positions [n_q][3], values, surfaces); n_q = 0 removes them.
+void set_charges(Geometry& g, int n_q, const double* pos, const double* q, const int32_t* sid,
+                 hipStream_t s);
+
+// b[col] for columns 0..ncolumn-1 (sorted order, stride b_stride); with charges, the
+// permittivities of the batch must have been uploaded (upload_ratios) first.
 void system_rhs(Geometry& g, int ncolumn, const double2* ratio_d, const double* e_field,
                 double2* b, int64_t b_stride, hipStream_t s);
 

@@ -65,6 +65,7 @@ def _load():
         "lspr_geometry_create": (C.c_int, [P(lspr_surface), i32, P(lspr_op_params), vp, P(vp)]),
         "lspr_geometry_destroy": (C.c_int, [vp]),
         "lspr_geometry_info": (C.c_int, [vp, P(lspr_geometry_stats)]),
+        "lspr_geometry_set_charges": (C.c_int, [vp, i32, P(dbl), P(dbl), P(i32), vp]),
         "lspr_solve": (C.c_int, [vp, i32, P(dbl), P(lspr_c64), P(lspr_c64), P(dbl),
                                  P(lspr_gmres_params), vp, vp, vp, P(lspr_c64), P(lspr_c64),
                                  P(dbl), P(dbl), P(i32), P(dbl)]),
@@ -214,6 +215,18 @@ class Geometry:
             self.close()
         except Exception:
             pass
+
+    def set_charges(self, positions, charges, surfaces, stream=None):
+        """Point charges inside the surfaces (lspr_geometry_set_charges): positions [n, 3],
+        charges [n] (divided by the vacuum permittivity), surfaces [n]; empty removes them."""
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
+        q = np.ascontiguousarray(np.asarray(charges, dtype=np.float64).ravel())
+        sid = np.ascontiguousarray(np.asarray(surfaces, dtype=np.int32).ravel())
+        assert len(pos) == len(q) == len(sid)
+        _check(_lib.lspr_geometry_set_charges(
+            self.handle, len(q), _dptr(pos), _dptr(q),
+            sid.ctypes.data_as(C.POINTER(C.c_int32)), _stream_ptr(stream)),
+            "lspr_geometry_set_charges")
 
     def info(self) -> dict:
         st = lspr_geometry_stats()

@@ -338,3 +338,43 @@ def test_autotune_meets_the_bound_and_picks_the_fastest(lib):
     geo.close()
     ref = A @ x[0]
     assert np.linalg.norm(y[0] - ref) / np.linalg.norm(ref) < 3 * bound
+
+
+@pytest.mark.parametrize("method,precision,tol", [("dense", "fp64", 1e-6),
+                                                  ("treecode", "fp32_lead64", 1e-4)])
+def test_point_charges_in_an_analyte_match_oracle(lib, method, precision, tol):
+    """Three seeded charges inside the analyte (Eq. integral_eq_lspr_system, last row): the
+    right-hand side, C_ext and the dipoles equal the oracle's; removing the charges restores
+    the charge-free solution."""
+    surfs = sensor_and_blob(8, 6)
+    v, t, sid = merge_surfaces(surfs)
+    blob = surfs[1][0]
+    rng = np.random.default_rng(9)
+    pos = blob.mean(0)[None, :] + 0.3 * rng.standard_normal((3, 3))
+    q = np.array([18.0951, -2 * 18.0951, 0.5 * 18.0951])  # +1, -2, +0.5 e
+    charges = (pos, q, np.array([1, 1, 1]))
+    lam = np.array([378.0, 386.0])
+    em = np.full(2, EPS_WATER + 0j)
+    es = np.stack([eps_silver_drude(lam), np.full(2, 2.5 + 0.1j)], 1)
+    ref = oracle.solve(v, t, sid, lam, em, es, [0, 0, 1.0], k_far=4, k_fine=19, charges=charges)
+    geo = lib.Geometry(surfs, method=method, precision=precision, p=8, theta=0.5)
+    geo.set_charges(*charges)
+    if method == "dense":  # the right-hand side itself
+        g = oracle.panel_geometry(v, t)
+        V, K = oracle.dense_operators(v, t, 4, 19, 9, 0.5)
+        _, b_ref = oracle.assemble_system(V, K, sid, g["normal"], em[0], es[0], [0, 0, 1.0],
+                                          g["centroid"], charges)
+        b = geo.rhs(em[:1], es[:1]).cpu().numpy()[0]
+        assert np.abs(b - b_ref).max() < 1e-10 * np.abs(b_ref).max()
+    fp32 = precision != "fp64"
+    kw = dict(tol=1e-6 if fp32 else 1e-10, restart=100, max_iter=1000)
+    out = geo.solve(lam, em, es, [0, 0, 1.0], **kw)
+    assert out["converged"]
+    for key in ("cext_sensor", "cext_total"):
+        assert np.abs(out[key] / ref[key] - 1).max() < tol, key
+    assert np.abs(out["p_total"] - ref["p_total"]).max() < 10 * tol * np.abs(ref["p_total"]).max()
+    geo.set_charges(np.zeros((0, 3)), [], [])
+    plain = geo.solve(lam, em, es, [0, 0, 1.0], **kw)
+    ref0 = oracle.solve(v, t, sid, lam, em, es, [0, 0, 1.0], k_far=4, k_fine=19)
+    assert np.abs(plain["cext_total"] / ref0["cext_total"] - 1).max() < tol
+    geo.close()
