@@ -42,47 +42,57 @@ __device__ __forceinline__ void unknowns(const double2* xc, int N, int i, double
 
 // x (complex, [col][2N] sorted order) -> packed real columns dens [N][2 pad]:
 // K columns 2s, 2s+1 = Re, Im phi; V columns pad + 2s, pad + 2s + 1 = Re, Im sigma.
+// Block = pp consecutive panels, all columns: (slot, panel) pairs with the panel fastest read
+// the vectors along the panels; the rows are assembled in LDS (row stride 2 pad + 1 elements,
+// so that consecutive panels fall in different banks) and written whole.
 template <class T>
-__global__ void k_pack(const double2* __restrict__ x, int64_t x_stride,
-                       const int32_t* __restrict__ cols, int nslot, int N,
-                       const double2* __restrict__ ratio, int S,
-                       const int32_t* __restrict__ surf, const double* __restrict__ vself,
-                       int pad, T* __restrict__ dens) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= static_cast<int64_t>(N) * pad) return;
-    const int i = static_cast<int>(t / pad), c = static_cast<int>(t % pad);
-    const int slot = c >> 1;
-    T* row = dens + static_cast<size_t>(i) * 2 * pad;
-    if (slot >= nslot) {
-        row[c] = T(0);
-        row[pad + c] = T(0);
-        return;
+__global__ void __launch_bounds__(TPB) k_pack(const double2* __restrict__ x, int64_t x_stride,
+                                              const int32_t* __restrict__ cols, int nslot, int N,
+                                              const double2* __restrict__ ratio, int S,
+                                              const int32_t* __restrict__ surf,
+                                              const double* __restrict__ vself, int pad, int pp,
+                                              T* __restrict__ dens) {
+    extern __shared__ double pack_sh[];
+    T* tile = reinterpret_cast<T*>(pack_sh);
+    const int ncols = 2 * pad, ld = ncols + 1;
+    const int i0 = blockIdx.x * pp, np = min(pp, N - i0);
+    for (int u = threadIdx.x; u < (pad / 2) * pp; u += TPB) {
+        const int p = u % pp, slot = u / pp, i = i0 + p;
+        T a = T(0), b = T(0), c = T(0), d = T(0);
+        if (p < np && slot < nslot) {
+            const int col = cols ? cols[slot] : slot;
+            const double2 r = ratio[col * S + surf[i]];
+            double2 phi, psi;
+            unknowns(x + col * x_stride, N, i, r, vself, phi, psi);
+            const double2 sig = cmul(r, psi);
+            a = static_cast<T>(phi.x);
+            b = static_cast<T>(phi.y);
+            c = static_cast<T>(sig.x);
+            d = static_cast<T>(sig.y);
+        }
+        T* row = tile + p * ld;
+        row[2 * slot] = a;
+        row[2 * slot + 1] = b;
+        row[pad + 2 * slot] = c;
+        row[pad + 2 * slot + 1] = d;
     }
-    const int col = cols ? cols[slot] : slot;
-    const double2 r = ratio[col * S + surf[i]];
-    double2 phi, psi;
-    unknowns(x + col * x_stride, N, i, r, vself, phi, psi);
-    const double2 sig = cmul(r, psi);
-    row[c] = static_cast<T>((c & 1) ? phi.y : phi.x);
-    row[pad + c] = static_cast<T>((c & 1) ? sig.y : sig.x);
+    __syncthreads();
+    T* dst = dens + static_cast<size_t>(i0) * ncols;
+    for (int e = threadIdx.x; e < np * ncols; e += TPB) dst[e] = tile[(e / ncols) * ld + e % ncols];
 }
 
-// Rows of Eq. matrix_multi from the raw sums (no 1/4pi yet).
-__global__ void k_combine(const double2* __restrict__ x, int64_t x_stride,
-                          double2* __restrict__ y, int64_t y_stride,
-                          const int32_t* __restrict__ cols, int nslot, int N,
-                          const double2* __restrict__ ratio, int S,
-                          const int32_t* __restrict__ surf, const double* __restrict__ vself,
-                          int pad, const double* __restrict__ out_self,
-                          const double* __restrict__ out_all) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= static_cast<int64_t>(N) * nslot) return;
-    const int slot = static_cast<int>(t / N), i = static_cast<int>(t % N);
+// One output pair (interior, exterior row) of column `slot` at panel i, from its rows of raw
+// sums (rs: own surface, ra: all surfaces).
+__device__ __forceinline__ void combine_one(const double2* __restrict__ x, int64_t x_stride,
+                                            double2* __restrict__ y, int64_t y_stride,
+                                            const int32_t* __restrict__ cols, int slot, int N,
+                                            int i, const double2* __restrict__ ratio, int S,
+                                            const int32_t* __restrict__ surf,
+                                            const double* __restrict__ vself, int pad,
+                                            const double* rs, const double* ra) {
     const int col = cols ? cols[slot] : slot;
     double2 phi, psi;
     unknowns(x + col * x_stride, N, i, ratio[col * S + surf[i]], vself, phi, psi);
-    const double* ra = out_all + static_cast<size_t>(i) * 2 * pad;
-    const double* rs = (out_self ? out_self : out_all) + static_cast<size_t>(i) * 2 * pad;
     const double2 k_all = make_double2(ra[2 * slot] * INV_4PI, ra[2 * slot + 1] * INV_4PI);
     const double2 v_all = make_double2(ra[pad + 2 * slot] * INV_4PI, ra[pad + 2 * slot + 1] * INV_4PI);
     const double2 k_own = make_double2(rs[2 * slot] * INV_4PI, rs[2 * slot + 1] * INV_4PI);
@@ -94,6 +104,35 @@ __global__ void k_combine(const double2* __restrict__ x, int64_t x_stride,
     double2* yc = y + col * y_stride;
     yc[i] = make_double2(0.5 * phi.x + k_own.x - vpsi.x, 0.5 * phi.y + k_own.y - vpsi.y);
     yc[N + i] = make_double2(0.5 * phi.x - k_all.x + v_all.x, 0.5 * phi.y - k_all.y + v_all.y);
+}
+
+// Rows of Eq. matrix_multi from the raw sums (no 1/4pi yet).  Block = pp consecutive panels:
+// their rows of raw sums are read whole into LDS (row stride 2 pad + 1), then (slot, panel)
+// pairs with the panel fastest read x and write y along the panels.
+__global__ void __launch_bounds__(TPB) k_combine(const double2* __restrict__ x, int64_t x_stride,
+                                                 double2* __restrict__ y, int64_t y_stride,
+                                                 const int32_t* __restrict__ cols, int nslot,
+                                                 int N, const double2* __restrict__ ratio, int S,
+                                                 const int32_t* __restrict__ surf,
+                                                 const double* __restrict__ vself, int pad,
+                                                 int pp, const double* __restrict__ out_self,
+                                                 const double* __restrict__ out_all) {
+    extern __shared__ double comb_sh[];
+    const int ncols = 2 * pad, ld = ncols + 1;
+    const int i0 = blockIdx.x * pp, np = min(pp, N - i0);
+    double* ta = comb_sh;
+    double* ts = out_self ? comb_sh + pp * ld : comb_sh;
+    for (int e = threadIdx.x; e < np * ncols; e += TPB) {
+        const int p = e / ncols, c = e % ncols;
+        ta[p * ld + c] = out_all[static_cast<size_t>(i0) * ncols + e];
+        if (out_self) ts[p * ld + c] = out_self[static_cast<size_t>(i0) * ncols + e];
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < nslot * pp; u += TPB) {
+        const int p = u % pp, slot = u / pp, i = i0 + p;
+        if (p < np) combine_one(x, x_stride, y, y_stride, cols, slot, N, i, ratio, S, surf,
+                                vself, pad, ts + p * ld, ta + p * ld);
+    }
 }
 
 // b = [cu / eps_s; sum_s (1 - r_s) sum_d E_d u[s][d] / 4pi] per column (cu: the point charges'
@@ -223,7 +262,7 @@ void set_charges(Geometry& g, int n_q, const double* pos, const double* q, const
                  hipStream_t s) {
     g.charge_u.release();
     if (n_q == 0) return;
-    std::vector<int32_t> order(n_q), off(g.S + 1, 0);
+    std::vector<int32_t> off(g.S + 1, 0);
     for (int k = 0; k < n_q; ++k) {
         LSPR_REQUIRE(sid[k] >= 0 && sid[k] < g.S, LSPR_E_INVALID, "charge surface out of range");
         LSPR_REQUIRE(std::isfinite(pos[3 * k]) && std::isfinite(pos[3 * k + 1]) &&
@@ -264,20 +303,30 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
     g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
     double* oa = reinterpret_cast<double*>(g.ws_out.p);
     double* os = g.S > 1 ? oa + nd : nullptr;
-    const int64_t tp = static_cast<int64_t>(g.N) * c.pad;
+    // panels per block of the packing and combining kernels: their LDS rows within 48 KB
+    auto panels_per_block = [&](size_t row_bytes) {
+        int pp = 32;
+        while (pp > 1 && static_cast<size_t>(pp) * row_bytes > 48 * 1024) pp /= 2;
+        return pp;
+    };
+    const size_t ld = static_cast<size_t>(2 * c.pad + 1);
+    const int ppk = panels_per_block(ld * esz);
+    const int nbk = (g.N + ppk - 1) / ppk;
     if (c.prec == LSPR_FP32)
-        hipLaunchKernelGGL(k_pack<float>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
-                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad,
+        hipLaunchKernelGGL(k_pack<float>, dim3(nbk), dim3(TPB), ppk * ld * esz, s, x, x_stride,
+                           d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, ppk,
                            reinterpret_cast<float*>(g.ws_dens.p));
     else
-        hipLaunchKernelGGL(k_pack<double>, dim3((tp + TPB - 1) / TPB), dim3(TPB), 0, s, x,
-                           x_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad,
+        hipLaunchKernelGGL(k_pack<double>, dim3(nbk), dim3(TPB), ppk * ld * esz, s, x, x_stride,
+                           d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, ppk,
                            reinterpret_cast<double*>(g.ws_dens.p));
     LSPR_HIP(hipGetLastError());
     apply_raw(g, c, g.ws_dens.p, os, oa, s);
-    const int64_t tc = static_cast<int64_t>(g.N) * nslot;
-    hipLaunchKernelGGL(k_combine, dim3((tc + TPB - 1) / TPB), dim3(TPB), 0, s, x, x_stride, y,
-                       y_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, os, oa);
+    const size_t crow = ld * sizeof(double) * (os ? 2 : 1);
+    const int ppc = panels_per_block(crow);
+    hipLaunchKernelGGL(k_combine, dim3((g.N + ppc - 1) / ppc), dim3(TPB), ppc * crow, s, x,
+                       x_stride, y, y_stride, d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs,
+                       c.pad, ppc, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
