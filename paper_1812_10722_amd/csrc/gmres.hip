@@ -41,6 +41,7 @@ namespace lspr {
 namespace {
 
 constexpr int GT = 256;
+constexpr int FT = 256, FR = 8;  // finishing kernel: threads, threads per partial-sum reduction
 constexpr int GE = 16;
 constexpr int GSLICE = GT * GE;
 constexpr double INV_4PI = 0.07957747154594767;
@@ -212,7 +213,7 @@ __device__ void rotate_column(double2* h, int c, const double2* cs, const double
 // mode 1, step j (nq = j + 1): finalise column j only.
 // Finalising column c: h_{i,c} = hp_i + nu s_i (i <= c), h_{c+1,c} = nu r; stored raw and
 // rotated, with the rotated right-hand side and the final residual estimate.
-__global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ part, int nparts,
+__global__ void __launch_bounds__(FT) k_dcgs_finish(const double2* __restrict__ part, int nparts,
                                                     const int32_t* __restrict__ cols, int mode,
                                                     int j, ArnoldiState A) {
     extern __shared__ double2 sh[];  // rd [kmax], g [m1 + 1], tmp [m1 + 1], cs [m], sn [m], hp [m1 + 1]
@@ -229,22 +230,32 @@ __global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ 
     const int c = mode == 0 ? j - 1 : j;  // the column to finalise (none when c < 0)
     __shared__ double r_sh;
     __shared__ int fin_sh;
-    // partial sums, in part order
-    for (int k = tid; k < nk; k += 64) {
-        const double2* p = part + (static_cast<int64_t>(slot) * A.kmax + k) * nparts;
+    // partial sums: FR consecutive threads per sum, each adding every FR-th partial, then
+    // combined across the FR threads in a fixed order (so that the loads are in flight together)
+    for (int k0 = 0; k0 < nk; k0 += FT / FR) {
+        const int k = k0 + tid / FR, sub = tid % FR;
         double2 acc = make_double2(0.0, 0.0);
-        for (int b = 0; b < nparts; ++b) {
-            acc.x += p[b].x;
-            acc.y += p[b].y;
+        if (k < nk) {
+            const double2* p = part + (static_cast<int64_t>(slot) * A.kmax + k) * nparts;
+#pragma unroll 8
+            for (int b = sub; b < nparts; b += FR) {
+                acc.x += p[b].x;
+                acc.y += p[b].y;
+            }
         }
-        rd[k] = acc;
+#pragma unroll
+        for (int off = FR / 2; off > 0; off >>= 1) {
+            acc.x += __shfl_xor(acc.x, off, 64);
+            acc.y += __shfl_xor(acc.y, off, 64);
+        }
+        if (k < nk && sub == 0) rd[k] = acc;
     }
     const int nrot = mode == 0 ? j : j + 1;  // rotations a step may read (0..c, then c)
-    for (int i = tid; i < nrot && i < m; i += 64) {
+    for (int i = tid; i < nrot && i < m; i += FT) {
         csl[i] = A.cs[col * m + i];
         snl[i] = A.sn[col * m + i];
     }
-    for (int i = tid; i <= j + 1 && i <= m1; i += 64) hpl[i] = A.hp[static_cast<int64_t>(col) * (m1 + 1) + i];
+    for (int i = tid; i <= j + 1 && i <= m1; i += FT) hpl[i] = A.hp[static_cast<int64_t>(col) * (m1 + 1) + i];
     __syncthreads();
     const double2* s = rd;                // s_i = q_i^H p, i < nq
     const double2* z = rd + nq + 1;       // z_i = q_i^H w, i < nq (mode 0)
@@ -282,7 +293,7 @@ __global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ 
     if (fin_sh) {  // column c, raw (in g) and rotated (in tmp)
         double2* hr = A.Hr + (static_cast<int64_t>(col) * m + c) * m1;
         double2* H = A.H + (static_cast<int64_t>(col) * m + c) * m1;
-        for (int i = tid; i <= c + 1; i += 64) {
+        for (int i = tid; i <= c + 1; i += FT) {
             hr[i] = g[i];
             H[i] = tmp[i];
         }
@@ -292,7 +303,7 @@ __global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ 
     const double r = r_sh;
     // g = Hr[0..j][0..j-1] s (column k of Hr has entries 0..k+1)
     const double2* hr = A.Hr + static_cast<int64_t>(col) * m * m1;
-    for (int i = tid; i <= j; i += 64) {
+    for (int i = tid; i <= j; i += FT) {
         double2 acc = make_double2(0.0, 0.0);
         for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) {
             const double2 p = cmul(hr[k * m1 + i], s[k]);
@@ -345,13 +356,13 @@ __global__ void __launch_bounds__(64) k_dcgs_finish(const double2* __restrict__ 
     const bool ok = r > 0.0;
     const double2 t = t_sh;
     double2* hp = A.hp + static_cast<int64_t>(col) * (m1 + 1);
-    for (int i = tid; i < j; i += 64) {
+    for (int i = tid; i < j; i += FT) {
         const double2 st = cmul(s[i], t);
         coef[i] = ok ? s[i] : make_double2(0.0, 0.0);
         coef[m1 + i] = ok ? make_double2(z[i].x - st.x, z[i].y - st.y) : make_double2(0.0, 0.0);
     }
     if (ok)
-        for (int i = tid; i <= j + 1; i += 64) hp[i] = hpl[i];
+        for (int i = tid; i <= j + 1; i += FT) hp[i] = hpl[i];
 }
 
 // Second pass of step j: q_j = (p - Q s) / r into slot j and the next provisional vector
@@ -756,7 +767,7 @@ SolveResult gmres_solve(Geometry& g, int prec, int B, const double2* ratio_d,
         else
             hipLaunchKernelGGL(k_dcgs_red<0>, dim3(nblk, ns), dim3(GT), 0, s, V.p, m1, nvec, nq,
                                w.p, cols_d.p, part.p, kmax, nparts);
-        hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(64),
+        hipLaunchKernelGGL(k_dcgs_finish, dim3(ns), dim3(FT),
                            (kmax + 2 * (m1 + 1) + 2 * m + (m1 + 1)) * sizeof(double2), s, part.p,
                            nparts, cols_d.p, mode, j, AS);
         LSPR_HIP(hipGetLastError());
