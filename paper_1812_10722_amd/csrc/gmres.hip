@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
     for (int e = 0; e < GE; ++e) {
         const double2 a = Vc[nq * nvec + nn[e]];
         pl[e] = in[e] ? a : make_double2(0.0, 0.0);
-        if (WITH_W) {
+        if constexpr (WITH_W) {
             const double2 c = wc[nn[e]];
             wl[e] = in[e] ? c : make_double2(0.0, 0.0);
         } else {
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
                 const double2 a = cconjmul(q[e], pl[e]);
                 v[kk][0] += a.x;
                 v[kk][1] += a.y;
-                if (WITH_W) {
+                if constexpr (WITH_W) {
                     const double2 c = cconjmul(q[e], wl[e]);
                     v[kk][2] += c.x;
                     v[kk][3] += c.y;
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
                 const int k = k0 + kk;
                 if (k < nq) {
                     out[static_cast<int64_t>(k) * nparts] = make_double2(v[kk][0], v[kk][1]);
-                    if (WITH_W)
+                    if constexpr (WITH_W)
                         out[static_cast<int64_t>(nq + 1 + k) * nparts] = make_double2(v[kk][2], v[kk][3]);
                 }
             }
@@ -155,14 +155,14 @@ __global__ void __launch_bounds__(GT) k_dcgs_red(const double2* __restrict__ V, 
         ga += wl[e].x * wl[e].x + wl[e].y * wl[e].y;
     }
     al = wave_sum(al);
-    if (WITH_W) {
+    if constexpr (WITH_W) {
         br = wave_sum(br);
         bi = wave_sum(bi);
         ga = wave_sum(ga);
     }
     if (lane == 0) {
         out[static_cast<int64_t>(nq) * nparts] = make_double2(al, 0.0);
-        if (WITH_W) {
+        if constexpr (WITH_W) {
             out[static_cast<int64_t>(2 * nq + 1) * nparts] = make_double2(br, bi);
             out[static_cast<int64_t>(2 * nq + 2) * nparts] = make_double2(ga, 0.0);
         }
