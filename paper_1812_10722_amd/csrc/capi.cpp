@@ -248,15 +248,10 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     lspr::build_tree(g);
     lspr::build_lists(g);
     // boxes whose moments are needed
-    std::vector<int32_t> mb(static_cast<size_t>(g.n_m2p));
-    if (g.n_m2p > 0)
-        lspr::copy_sync(mb.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost, g.stream);
-    std::set<int32_t> uniq(mb.begin(), mb.end());
+    std::set<int32_t> uniq(g.m2p_box_h.begin(), g.m2p_box_h.end());
     g.mom_boxes.assign(uniq.begin(), uniq.end());
     if (!g.mom_boxes.empty()) {
-        std::vector<lspr::Box> bh(g.n_boxes);
-        lspr::copy_sync(bh.data(), g.boxes.p, bh.size() * sizeof(lspr::Box),
-                           hipMemcpyDeviceToHost, g.stream);
+        const std::vector<lspr::Range>& bh = g.box_rng_h;
         g.mom_panels = 0;
         for (int32_t b : g.mom_boxes) g.mom_panels += bh[b].end - bh[b].start;
         // P2M work items: segments of at most 128 panels per expanded box
@@ -280,16 +275,16 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
         g.n_slots = slots;
         g.n_red = static_cast<int>(reds.size());
         g.p2m_seg.alloc(segs.size());
-        lspr::copy_sync(g.p2m_seg.p, segs.data(), segs.size() * sizeof(lspr::P2MSeg),
-                           hipMemcpyHostToDevice, g.stream);
+        g.mom_boxes_d.alloc(g.mom_boxes.size());
+        lspr::Uploads up(g.stream);
+        up.add(g.p2m_seg.p, segs.data(), segs.size());
+        up.add(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size());
         if (!reds.empty()) {
             g.p2m_red.alloc(reds.size());
-            lspr::copy_sync(g.p2m_red.p, reds.data(), reds.size() * sizeof(lspr::P2MRed),
-                               hipMemcpyHostToDevice, g.stream);
+            up.add(g.p2m_red.p, reds.data(), reds.size());
         }
-        g.mom_boxes_d.alloc(g.mom_boxes.size());
-        lspr::copy_sync(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size() * 4,
-                           hipMemcpyHostToDevice, g.stream);
+        up.flush();
+        g.p2m_seg_h = std::move(segs);
     }
     lspr::build_near_table(g);
     if (g.tile_budget_bytes <= 0.0) {
@@ -299,6 +294,15 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     }
     if (g.allow_mfma) lspr::build_tiles(g);
     lspr::precompute_rhs(g);
+    // the host copies were only needed while building
+    g.box_rng_h = {};
+    g.p2p_rng_h = {};
+    g.m2p_off_h = {};
+    g.p2p_off_h = {};
+    g.m2p_self_h = {};
+    g.p2p_self_h = {};
+    g.m2p_box_h = {};
+    g.p2m_seg_h = {};
 }
 
 bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,

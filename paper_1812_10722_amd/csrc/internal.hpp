@@ -186,6 +186,92 @@ inline void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind ki
     LSPR_HIP(hipStreamSynchronize(s));
 }
 
+// Batched host-to-device uploads of set-up code.  add() copies host data into one host buffer
+// (so temporaries may be passed); flush() moves the buffer to the device in one transfer and
+// queues a device-to-device copy to each destination on `s`, so the host waits once rather
+// than once per destination.  The device staging block is kept until the next flush or the
+// object's end, both of which first wait for `s`.
+class Uploads {
+  public:
+    explicit Uploads(hipStream_t s) : s_(s) {}
+    ~Uploads() {
+        if (stage_.p) (void)hipStreamSynchronize(s_);
+    }
+    Uploads(const Uploads&) = delete;
+    Uploads& operator=(const Uploads&) = delete;
+    template <class T>
+    void add(T* dst, const T* src, size_t count) {
+        const size_t bytes = count * sizeof(T);
+        if (bytes == 0) return;
+        const size_t at = (host_.size() + 255) & ~static_cast<size_t>(255);
+        host_.resize(at + bytes);
+        std::memcpy(host_.data() + at, src, bytes);
+        items_.push_back({dst, at, bytes});
+    }
+    void flush() {
+        if (items_.empty()) return;
+        if (stage_.p) {
+            LSPR_HIP(hipStreamSynchronize(s_));
+            stage_.release();
+        }
+        stage_.alloc(host_.size());
+        copy_sync(stage_.p, host_.data(), host_.size(), hipMemcpyHostToDevice, s_);
+        for (const Item& it : items_)
+            LSPR_HIP(hipMemcpyAsync(it.dst, stage_.p + it.at, it.bytes, hipMemcpyDeviceToDevice,
+                                    s_));
+        items_.clear();
+        host_.clear();
+    }
+
+  private:
+    struct Item {
+        void* dst;
+        size_t at, bytes;
+    };
+    hipStream_t s_;
+    std::vector<uint8_t> host_;
+    std::vector<Item> items_;
+    DevBuf<uint8_t> stage_;
+};
+
+// Batched device-to-host downloads: add() records a destination; fetch() gathers the sources
+// into one device block (device-to-device copies queued on `s`), reads it back in one transfer
+// and fills every destination.  The sources must be ready in the stream order of `s`.
+class Downloads {
+  public:
+    explicit Downloads(hipStream_t s) : s_(s) {}
+    template <class T>
+    void add(T* dst, const T* src, size_t count) {
+        const size_t bytes = count * sizeof(T);
+        if (bytes == 0) return;
+        const size_t at = (total_ + 255) & ~static_cast<size_t>(255);
+        items_.push_back({dst, src, at, bytes});
+        total_ = at + bytes;
+    }
+    void fetch() {
+        if (items_.empty()) return;
+        DevBuf<uint8_t> stage(total_);
+        for (const Item& it : items_)
+            LSPR_HIP(hipMemcpyAsync(stage.p + it.at, it.src, it.bytes, hipMemcpyDeviceToDevice,
+                                    s_));
+        std::vector<uint8_t> host(total_);
+        copy_sync(host.data(), stage.p, total_, hipMemcpyDeviceToHost, s_);
+        for (const Item& it : items_) std::memcpy(it.dst, host.data() + it.at, it.bytes);
+        items_.clear();
+        total_ = 0;
+    }
+
+  private:
+    struct Item {
+        void* dst;
+        const void* src;
+        size_t at, bytes;
+    };
+    hipStream_t s_;
+    std::vector<Item> items_;
+    size_t total_ = 0;
+};
+
 // Octree box, one per node of every surface's tree.  Boxes of one surface are stored level by
 // level; the children of a box are contiguous.
 struct Box {
@@ -298,6 +384,11 @@ struct Geometry {
     DevBuf<Range> p2p_rng;     // [n_p2p]
     DevBuf<int32_t> p2p_self;  // [n_chunks]
     int64_t n_m2p = 0, n_p2p = 0, p2p_pairs = 0, m2p_pairs = 0;
+    // host copies the set-up steps hand on to each other (released once the geometry is
+    // built): panel range of each box, list offsets, own-surface counts and expansion boxes
+    std::vector<Range> box_rng_h, p2p_rng_h;
+    std::vector<int32_t> m2p_off_h, p2p_off_h, m2p_self_h, p2p_self_h, m2p_box_h;
+    std::vector<P2MSeg> p2m_seg_h;
     // near-singular corrections (CSR over targets, sorted order) and singular self terms
     DevBuf<int64_t> near_off64; // [N + 1]
     DevBuf<int32_t> near_col;  // [n_near]

@@ -1406,8 +1406,9 @@ bool launch_p2m_tiles(Geometry& g, const Cols& c, const T* dens, T* mom, hipStre
 template <int P>
 void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
     constexpr int RT = p2m_row_tiles<P>();
-    std::vector<P2MSeg> segs(g.n_seg);
-    copy_sync(segs.data(), g.p2m_seg.p, segs.size() * sizeof(P2MSeg), hipMemcpyDeviceToHost, s);
+    const std::vector<P2MSeg>& segs = g.p2m_seg_h;
+    LSPR_REQUIRE(static_cast<int>(segs.size()) == g.n_seg, LSPR_E_INVALID,
+                 "moment segments missing on the host");
     std::vector<int64_t> off(g.n_seg);
     int64_t tot = 0;
     for (int k = 0; k < g.n_seg; ++k) {
@@ -1569,16 +1570,15 @@ bool fold_near(Geometry& g, T* A, float* A32, const int32_t* dt_off, const int32
 void build_tiles(Geometry& g) {
     hipStream_t s = g.stream;
     const int nc = g.n_chunks;
-    std::vector<int32_t> mo(nc + 1), po(nc + 1), ms(nc), ps(nc);
-    copy_sync(mo.data(), g.m2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost, s);
-    copy_sync(po.data(), g.p2p_off.p, (nc + 1) * 4, hipMemcpyDeviceToHost, s);
-    copy_sync(ms.data(), g.m2p_self.p, nc * 4, hipMemcpyDeviceToHost, s);
-    copy_sync(ps.data(), g.p2p_self.p, nc * 4, hipMemcpyDeviceToHost, s);
-    std::vector<int32_t> mbox(std::max<int64_t>(g.n_m2p, 1));
-    std::vector<Range> rng(std::max<int64_t>(g.n_p2p, 1));
-    if (g.n_m2p) copy_sync(mbox.data(), g.m2p_box.p, g.n_m2p * 4, hipMemcpyDeviceToHost, s);
-    if (g.n_p2p)
-        copy_sync(rng.data(), g.p2p_rng.p, g.n_p2p * sizeof(Range), hipMemcpyDeviceToHost, s);
+    // the lists as the list builder left them on the host
+    const std::vector<int32_t>&mo = g.m2p_off_h, &po = g.p2p_off_h, &ms = g.m2p_self_h,
+                                &ps = g.p2p_self_h, &mbox = g.m2p_box_h;
+    const std::vector<Range>& rng = g.p2p_rng_h;
+    LSPR_REQUIRE(static_cast<int>(mo.size()) == nc + 1 && static_cast<int>(po.size()) == nc + 1 &&
+                     static_cast<int>(ms.size()) == nc && static_cast<int>(ps.size()) == nc &&
+                     static_cast<int64_t>(mbox.size()) == g.n_m2p &&
+                     static_cast<int64_t>(rng.size()) == g.n_p2p,
+                 LSPR_E_INVALID, "interaction lists missing on the host");
     const int nsm = (g.n_terms + 3) / 4;  // K-steps of an expansion tile
     auto make_tile = [](int kind, int nstep, int64_t aoff, int r0, int rows) {
         LSPR_REQUIRE(aoff % 256 == 0 && aoff / 256 < INT32_MAX, LSPR_E_INVALID,
@@ -1676,16 +1676,17 @@ void build_tiles(Geometry& g) {
     g.tile_off.alloc(nc + 1);
     g.tile_self.alloc(nc);
     g.chunk_order.alloc(order.size());
-    copy_sync(g.chunk_order.p, order.data(), order.size() * 4, hipMemcpyHostToDevice, s);
-    copy_sync(g.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
-    copy_sync(g.tile_off.p, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s);
-    copy_sync(g.tile_self.p, tself.data(), tself.size() * 4, hipMemcpyHostToDevice, s);
+    Uploads up(s);  // every table below in one transfer
+    up.add(g.chunk_order.p, order.data(), order.size());
+    up.add(g.tiles.p, tiles.data(), tiles.size());
+    up.add(g.tile_off.p, toff.data(), toff.size());
+    up.add(g.tile_self.p, tself.data(), tself.size());
     const int n_m2p = static_cast<int>(g.n_m2p), n_p2p = static_cast<int>(p2p_tile.size());
     DevBuf<int32_t> mt(n_m2p), mc(n_m2p), pt(n_p2p), pc(n_p2p);
-    copy_sync(mt.p, m2p_tile.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
-    copy_sync(mc.p, m2p_chunk.data(), n_m2p * 4, hipMemcpyHostToDevice, s);
-    copy_sync(pt.p, p2p_tile.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
-    copy_sync(pc.p, p2p_chunk.data(), n_p2p * 4, hipMemcpyHostToDevice, s);
+    up.add(mt.p, m2p_tile.data(), n_m2p);
+    up.add(mc.p, m2p_chunk.data(), n_m2p);
+    up.add(pt.p, p2p_tile.data(), n_p2p);
+    up.add(pc.p, p2p_chunk.data(), n_p2p);
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     std::vector<int32_t> dto(nc + 1, 0), dtr, dti;
     for (int c = 0; c < nc; ++c) {
@@ -1701,11 +1702,10 @@ void build_tiles(Geometry& g) {
     }
     dto[nc] = static_cast<int32_t>(dti.size());
     DevBuf<int32_t> dto_d(nc + 1), dtr_d(std::max<size_t>(dtr.size(), 1)), dti_d(std::max<size_t>(dti.size(), 1));
-    copy_sync(dto_d.p, dto.data(), dto.size() * 4, hipMemcpyHostToDevice, s);
-    if (!dti.empty()) {
-        copy_sync(dtr_d.p, dtr.data(), dtr.size() * 4, hipMemcpyHostToDevice, s);
-        copy_sync(dti_d.p, dti.data(), dti.size() * 4, hipMemcpyHostToDevice, s);
-    }
+    up.add(dto_d.p, dto.data(), dto.size());
+    up.add(dtr_d.p, dtr.data(), dtr.size());
+    up.add(dti_d.p, dti.data(), dti.size());
+    up.flush();
     // with both stores, one FP64 pass fills both (the FP32 tiles are the FP64 values rounded)
     if (keep32) g.tileA.alloc(std::max<int64_t>(aoff, 1));
     if (keep64) {

@@ -446,14 +446,6 @@ __global__ void k_vself(const double* __restrict__ tri, const double* __restrict
     vself[i] = total;
 }
 
-// Copies a host vector to a new device buffer; waits for the copy, so temporaries may be passed.
-DevBuf<double> upload(const std::vector<double>& h, hipStream_t s) {
-    DevBuf<double> d(h.size());
-    LSPR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    LSPR_HIP(hipStreamSynchronize(s));
-    return d;
-}
-
 std::vector<double> rule_rows(int n) {
     std::vector<double> bary, w;
     LSPR_REQUIRE(triangle_rule(n, bary, w), LSPR_E_INVALID, "unsupported triangle rule");
@@ -474,7 +466,7 @@ void build_tree(Geometry& g) {
     std::vector<Box> bx;
     g.surf_root.assign(g.S, 0);
     g.max_depth = 0;
-    DevBuf<int32_t> se_d, lv_d, out_d;
+    DevBuf<int32_t> in_d, out_d;
     for (int sf = 0; sf < g.S; ++sf) {
         Box root{};
         root.start = g.surf_start[sf];
@@ -492,19 +484,18 @@ void build_tree(Geometry& g) {
                 if (bx[b].end - bx[b].start > g.ncrit) split.push_back(b);
             if (split.empty()) break;
             const int nb = static_cast<int>(split.size());
-            std::vector<int32_t> se(2 * nb), lv(nb), out(9 * nb);
+            // one upload: (start, end) pairs, then levels
+            std::vector<int32_t> in(3 * nb), out(9 * nb);
             for (int k = 0; k < nb; ++k) {
-                se[2 * k] = bx[split[k]].start;
-                se[2 * k + 1] = bx[split[k]].end;
-                lv[k] = bx[split[k]].level;
+                in[2 * k] = bx[split[k]].start;
+                in[2 * k + 1] = bx[split[k]].end;
+                in[2 * nb + k] = bx[split[k]].level;
             }
-            se_d.reserve(se.size());
-            lv_d.reserve(lv.size());
+            in_d.reserve(in.size());
             out_d.reserve(out.size());
-            LSPR_HIP(hipMemcpyAsync(se_d.p, se.data(), se.size() * 4, hipMemcpyHostToDevice, s));
-            LSPR_HIP(hipMemcpyAsync(lv_d.p, lv.data(), lv.size() * 4, hipMemcpyHostToDevice, s));
+            LSPR_HIP(hipMemcpyAsync(in_d.p, in.data(), in.size() * 4, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_split, dim3((9 * nb + TPB - 1) / TPB), dim3(TPB), 0, s,
-                               g.morton.p, se_d.p, lv_d.p, nb, out_d.p);
+                               g.morton.p, in_d.p, in_d.p + 2 * nb, nb, out_d.p);
             LSPR_HIP(hipGetLastError());
             LSPR_HIP(hipMemcpyAsync(out.data(), out_d.p, out.size() * 4, hipMemcpyDeviceToHost, s));
             LSPR_HIP(hipStreamSynchronize(s));
@@ -536,12 +527,8 @@ void build_tree(Geometry& g) {
     g.n_boxes = static_cast<int>(bx.size());
     g.n_leaves = 0;
     for (const Box& b : bx) g.n_leaves += b.nchild == 0;
-    g.boxes.alloc(bx.size());
-    LSPR_HIP(hipMemcpyAsync(g.boxes.p, bx.data(), bx.size() * sizeof(Box), hipMemcpyHostToDevice, s));
-    g.far_rule = upload(rule_rows(g.K), s);
-    hipLaunchKernelGGL(k_box_stats, dim3(g.n_boxes), dim3(TPB), 0, s, g.boxes.p, g.tri.p,
-                       g.area.p, g.far_rule.p, g.K);
-    LSPR_HIP(hipGetLastError());
+    g.box_rng_h.resize(bx.size());
+    for (size_t b = 0; b < bx.size(); ++b) g.box_rng_h[b] = Range{bx[b].start, bx[b].end};
     // target chunks: consecutive panels of one surface
     std::vector<Chunk> ch;
     for (int sf = 0; sf < g.S; ++sf)
@@ -553,8 +540,18 @@ void build_tree(Geometry& g) {
             ch.push_back(c);
         }
     g.n_chunks = static_cast<int>(ch.size());
+    g.boxes.alloc(bx.size());
     g.chunks.alloc(ch.size());
-    LSPR_HIP(hipMemcpyAsync(g.chunks.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, s));
+    const std::vector<double> rule = rule_rows(g.K);
+    g.far_rule.alloc(rule.size());
+    Uploads up(s);
+    up.add(g.boxes.p, bx.data(), bx.size());
+    up.add(g.chunks.p, ch.data(), ch.size());
+    up.add(g.far_rule.p, rule.data(), rule.size());
+    up.flush();
+    hipLaunchKernelGGL(k_box_stats, dim3(g.n_boxes), dim3(TPB), 0, s, g.boxes.p, g.tri.p,
+                       g.area.p, g.far_rule.p, g.K);
+    LSPR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_stats, dim3(g.n_chunks), dim3(TPB), 0, s, g.chunks.p, g.cen.p);
     LSPR_HIP(hipGetLastError());
     LSPR_HIP(hipStreamSynchronize(s));
@@ -582,10 +579,15 @@ void build_lists(Geometry& g) {
     LSPR_HIP(hipGetLastError());
     std::vector<int32_t> mh(nc), ph(nc);
     std::vector<int64_t> prh(2 * nc);
-    LSPR_HIP(hipMemcpyAsync(mh.data(), mc.p, nc * 4, hipMemcpyDeviceToHost, s));
-    LSPR_HIP(hipMemcpyAsync(ph.data(), pc.p, nc * 4, hipMemcpyDeviceToHost, s));
-    LSPR_HIP(hipMemcpyAsync(prh.data(), pairs.p, 2 * nc * 8, hipMemcpyDeviceToHost, s));
-    LSPR_HIP(hipStreamSynchronize(s));
+    g.m2p_self_h.resize(nc);
+    g.p2p_self_h.resize(nc);
+    Downloads down(s);
+    down.add(mh.data(), mc.p, nc);
+    down.add(ph.data(), pc.p, nc);
+    down.add(prh.data(), pairs.p, 2 * nc);
+    down.add(g.m2p_self_h.data(), g.m2p_self.p, nc);
+    down.add(g.p2p_self_h.data(), g.p2p_self.p, nc);
+    down.fetch();
     std::vector<int64_t> mo(nc + 1, 0), po(nc + 1, 0);
     g.p2p_pairs = 0;
     g.m2p_pairs = 0;
@@ -599,31 +601,50 @@ void build_lists(Geometry& g) {
     g.n_p2p = po[nc];
     LSPR_REQUIRE(g.n_m2p < (1ll << 31) && g.n_p2p < (1ll << 31), LSPR_E_INVALID,
                  "interaction lists too long");
+    g.m2p_off_h.resize(nc + 1);
+    g.p2p_off_h.resize(nc + 1);
+    for (int c = 0; c <= nc; ++c) {
+        g.m2p_off_h[c] = static_cast<int32_t>(mo[c]);
+        g.p2p_off_h[c] = static_cast<int32_t>(po[c]);
+    }
     DevBuf<int64_t> mo_d(nc + 1), po_d(nc + 1);
-    LSPR_HIP(hipMemcpyAsync(mo_d.p, mo.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s));
-    LSPR_HIP(hipMemcpyAsync(po_d.p, po.data(), (nc + 1) * 8, hipMemcpyHostToDevice, s));
+    g.m2p_off.alloc(nc + 1);
+    g.p2p_off.alloc(nc + 1);
+    Uploads up(s);
+    up.add(mo_d.p, mo.data(), nc + 1);
+    up.add(po_d.p, po.data(), nc + 1);
+    up.add(g.m2p_off.p, g.m2p_off_h.data(), nc + 1);
+    up.add(g.p2p_off.p, g.p2p_off_h.data(), nc + 1);
+    up.flush();
     g.m2p_box.alloc(std::max<int64_t>(g.n_m2p, 1));
     g.p2p_rng.alloc(std::max<int64_t>(g.n_p2p, 1));
     hipLaunchKernelGGL(k_lists_fill, grid, blk, 0, s, g.boxes.p, g.chunks.p, nc, lp, place.p,
                        mo_d.p, po_d.p, g.m2p_box.p, g.p2p_rng.p);
     LSPR_HIP(hipGetLastError());
-    std::vector<int32_t> mo32(nc + 1), po32(nc + 1);
-    for (int c = 0; c <= nc; ++c) {
-        mo32[c] = static_cast<int32_t>(mo[c]);
-        po32[c] = static_cast<int32_t>(po[c]);
-    }
-    g.m2p_off.alloc(nc + 1);
-    g.p2p_off.alloc(nc + 1);
-    LSPR_HIP(hipMemcpyAsync(g.m2p_off.p, mo32.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
-    LSPR_HIP(hipMemcpyAsync(g.p2p_off.p, po32.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
-    LSPR_HIP(hipStreamSynchronize(s));
+    // the expansion boxes and direct ranges, for the tile and moment set-up
+    g.m2p_box_h.resize(g.n_m2p);
+    g.p2p_rng_h.resize(g.n_p2p);
+    Downloads lists(s);
+    lists.add(g.m2p_box_h.data(), g.m2p_box.p, g.m2p_box_h.size());
+    lists.add(g.p2p_rng_h.data(), g.p2p_rng.p, g.p2p_rng_h.size());
+    lists.fetch();
 }
 
 void build_near_table(Geometry& g) {
     hipStream_t s = g.stream;
     const int N = g.N;
+    // one upload: surface roots, the fine rule and the Gauss-Legendre nodes of V_ii
+    const std::vector<double> fine_h = rule_rows(g.Kf);
+    std::vector<double> t, w;
+    gauss_legendre(g.Nk, t, w);
     DevBuf<int32_t> roots(g.S);
-    LSPR_HIP(hipMemcpyAsync(roots.p, g.surf_root.data(), g.S * 4, hipMemcpyHostToDevice, s));
+    DevBuf<double> fine(fine_h.size()), t_d(t.size()), w_d(w.size());
+    Uploads up(s);
+    up.add(roots.p, g.surf_root.data(), g.S);
+    up.add(fine.p, fine_h.data(), fine_h.size());
+    up.add(t_d.p, t.data(), t.size());
+    up.add(w_d.p, w.data(), w.size());
+    up.flush();
     NearParams np{1.0 / g.threshold, g.S, roots.p};
     DevBuf<int64_t> cnt(N + 1);
     const dim3 grid((N + TPB - 1) / TPB), blk(TPB);
@@ -646,16 +667,12 @@ void build_near_table(Geometry& g) {
     DevBuf<int32_t> row_of(std::max<int64_t>(nnz, 1));
     hipLaunchKernelGGL(k_row_of, grid, blk, 0, s, g.near_off64.p, N, row_of.p);
     LSPR_HIP(hipGetLastError());
-    DevBuf<double> fine = upload(rule_rows(g.Kf), s);
     if (nnz > 0) {
         hipLaunchKernelGGL(k_near_values, dim3((nnz + TPB - 1) / TPB), dim3(TPB), 0, s, row_of.p,
                            g.near_col.p, nnz, g.tri.p, g.cen.p, g.nrm.p, g.area.p, g.far_rule.p,
                            g.K, fine.p, g.Kf, g.near_dv.p, g.near_dk.p);
         LSPR_HIP(hipGetLastError());
     }
-    std::vector<double> t, w;
-    gauss_legendre(g.Nk, t, w);
-    DevBuf<double> t_d = upload(t, s), w_d = upload(w, s);
     g.vself.alloc(N);
     hipLaunchKernelGGL(k_vself, grid, blk, 0, s, g.tri.p, g.cen.p, g.nrm.p, N, t_d.p, w_d.p,
                        g.Nk, g.vself.p);
