@@ -5,6 +5,7 @@
 #include <map>
 #include <cmath>
 #include <complex>
+#include <future>
 #include <set>
 #include <utility>
 
@@ -116,6 +117,45 @@ bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s) {
     }
     cache.push_back({pool, p, bytes, ev});
     return true;
+}
+
+namespace {
+std::mutex pinned_mu;
+std::vector<lspr::PinnedBuf> pinned_free;  // staging buffers not in use
+constexpr size_t PINNED_KEEP = 8;           // free buffers kept (larger ones first)
+}  // namespace
+
+PinnedBuf pinned_take(size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(pinned_mu);
+        int best = -1;
+        for (size_t i = 0; i < pinned_free.size(); ++i)
+            if (pinned_free[i].cap >= bytes &&
+                (best < 0 || pinned_free[i].cap < pinned_free[best].cap))
+                best = static_cast<int>(i);
+        if (best >= 0) {
+            const PinnedBuf b = pinned_free[best];
+            pinned_free.erase(pinned_free.begin() + best);
+            return b;
+        }
+    }
+    PinnedBuf b;
+    b.cap = ((bytes > 0 ? bytes : 1) + (1u << 20) - 1) & ~static_cast<size_t>((1u << 20) - 1);
+    LSPR_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.p), b.cap, hipHostMallocPortable));
+    return b;
+}
+
+void pinned_put(PinnedBuf b) {
+    if (b.p == nullptr) return;
+    std::lock_guard<std::mutex> lk(pinned_mu);
+    pinned_free.push_back(b);
+    if (pinned_free.size() > PINNED_KEEP) {  // drop the smallest
+        size_t k = 0;
+        for (size_t i = 1; i < pinned_free.size(); ++i)
+            if (pinned_free[i].cap < pinned_free[k].cap) k = i;
+        (void)hipHostFree(pinned_free[k].p);
+        pinned_free.erase(pinned_free.begin() + k);
+    }
 }
 
 bool big_block_flush(hipMemPool_t pool) {
@@ -247,6 +287,10 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);
     lspr::build_lists(g);
+    // the host part of the tiles runs beside the moment set-up and the near-singular table
+    std::future<lspr::TilePlan> plan;
+    if (g.allow_mfma)
+        plan = std::async(std::launch::async, [&g] { return lspr::plan_tiles(g); });
     // boxes whose moments are needed
     std::set<int32_t> uniq(g.m2p_box_h.begin(), g.m2p_box_h.end());
     g.mom_boxes.assign(uniq.begin(), uniq.end());
@@ -292,7 +336,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
         LSPR_HIP(hipMemGetInfo(&free_b, &total_b));
         g.tile_budget_bytes = 0.4 * static_cast<double>(free_b);
     }
-    if (g.allow_mfma) lspr::build_tiles(g);
+    if (g.allow_mfma) lspr::build_tiles(g, plan.get());
     lspr::precompute_rhs(g);
     // the host copies were only needed while building
     g.box_rng_h = {};

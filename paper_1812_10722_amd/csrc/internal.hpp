@@ -186,16 +186,28 @@ inline void copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind ki
     LSPR_HIP(hipStreamSynchronize(s));
 }
 
-// Batched host-to-device uploads of set-up code.  add() copies host data into one host buffer
-// (so temporaries may be passed); flush() moves the buffer to the device in one transfer and
-// queues a device-to-device copy to each destination on `s`, so the host waits once rather
-// than once per destination.  The device staging block is kept until the next flush or the
-// object's end, both of which first wait for `s`.
+// Pinned (page-locked) host staging buffers, shared by all threads and reused: a transfer from
+// or to pinned memory is one DMA, where pageable memory goes through the runtime's own staging
+// at a few GB/s.  A buffer is put back only once no transfer uses it.
+struct PinnedBuf {
+    uint8_t* p = nullptr;
+    size_t cap = 0;
+};
+// A free buffer of at least `bytes` (a new one, a multiple of 1 MiB, if none is free).
+PinnedBuf pinned_take(size_t bytes);
+void pinned_put(PinnedBuf b);
+
+// Batched host-to-device uploads of set-up code.  add() copies host data into one pinned
+// buffer (so temporaries may be passed); flush() moves the buffer to the device in one
+// transfer and queues a device-to-device copy to each destination on `s`, so the host waits
+// once rather than once per destination.  The device staging block is kept until the next
+// flush or the object's end, both of which first wait for `s`.
 class Uploads {
   public:
     explicit Uploads(hipStream_t s) : s_(s) {}
     ~Uploads() {
         if (stage_.p) (void)hipStreamSynchronize(s_);
+        if (buf_.p) pinned_put(buf_);
     }
     Uploads(const Uploads&) = delete;
     Uploads& operator=(const Uploads&) = delete;
@@ -203,10 +215,11 @@ class Uploads {
     void add(T* dst, const T* src, size_t count) {
         const size_t bytes = count * sizeof(T);
         if (bytes == 0) return;
-        const size_t at = (host_.size() + 255) & ~static_cast<size_t>(255);
-        host_.resize(at + bytes);
-        std::memcpy(host_.data() + at, src, bytes);
+        const size_t at = (used_ + 255) & ~static_cast<size_t>(255);
+        reserve(at + bytes);
+        std::memcpy(buf_.p + at, src, bytes);
         items_.push_back({dst, at, bytes});
+        used_ = at + bytes;
     }
     void flush() {
         if (items_.empty()) return;
@@ -214,13 +227,13 @@ class Uploads {
             LSPR_HIP(hipStreamSynchronize(s_));
             stage_.release();
         }
-        stage_.alloc(host_.size());
-        copy_sync(stage_.p, host_.data(), host_.size(), hipMemcpyHostToDevice, s_);
+        stage_.alloc(used_);
+        copy_sync(stage_.p, buf_.p, used_, hipMemcpyHostToDevice, s_);  // buf_ free again
         for (const Item& it : items_)
             LSPR_HIP(hipMemcpyAsync(it.dst, stage_.p + it.at, it.bytes, hipMemcpyDeviceToDevice,
                                     s_));
         items_.clear();
-        host_.clear();
+        used_ = 0;
     }
 
   private:
@@ -228,15 +241,24 @@ class Uploads {
         void* dst;
         size_t at, bytes;
     };
+    void reserve(size_t n) {
+        if (n <= buf_.cap) return;
+        const PinnedBuf nb = pinned_take(n > 2 * buf_.cap ? n : 2 * buf_.cap);
+        if (used_) std::memcpy(nb.p, buf_.p, used_);
+        if (buf_.p) pinned_put(buf_);
+        buf_ = nb;
+    }
     hipStream_t s_;
-    std::vector<uint8_t> host_;
+    PinnedBuf buf_;
+    size_t used_ = 0;
     std::vector<Item> items_;
     DevBuf<uint8_t> stage_;
 };
 
 // Batched device-to-host downloads: add() records a destination; fetch() gathers the sources
 // into one device block (device-to-device copies queued on `s`), reads it back in one transfer
-// and fills every destination.  The sources must be ready in the stream order of `s`.
+// into a pinned buffer and fills every destination.  The sources must be ready in the stream
+// order of `s`.
 class Downloads {
   public:
     explicit Downloads(hipStream_t s) : s_(s) {}
@@ -254,9 +276,16 @@ class Downloads {
         for (const Item& it : items_)
             LSPR_HIP(hipMemcpyAsync(stage.p + it.at, it.src, it.bytes, hipMemcpyDeviceToDevice,
                                     s_));
-        std::vector<uint8_t> host(total_);
-        copy_sync(host.data(), stage.p, total_, hipMemcpyDeviceToHost, s_);
-        for (const Item& it : items_) std::memcpy(it.dst, host.data() + it.at, it.bytes);
+        const PinnedBuf host = pinned_take(total_);
+        try {
+            copy_sync(host.p, stage.p, total_, hipMemcpyDeviceToHost, s_);
+        } catch (...) {
+            (void)hipStreamSynchronize(s_);  // no transfer into the buffer once it is put back
+            pinned_put(host);
+            throw;
+        }
+        for (const Item& it : items_) std::memcpy(it.dst, host.p + it.at, it.bytes);
+        pinned_put(host);
         items_.clear();
         total_ = 0;
     }
@@ -449,7 +478,21 @@ void build_near_table(Geometry& g);
 void apply_raw(Geometry& g, const Cols& c, const void* dens, double* out_self, double* out_all,
                hipStream_t s);
 void precompute_rhs(Geometry& g);
+// Host part of the matrix-core tiles: descriptors, the tiles of each chunk, workgroup order and
+// the direct tiles sorted for the near-field fold.  Reads only host copies of the lists (and
+// sizes), so it may run on another host thread while the device builds the near-singular table.
+struct TilePlan {
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> toff, tself;            // per chunk: first tile, own-surface tiles
+    std::vector<int32_t> m2p_tile, m2p_chunk;    // per expansion entry: its tile and chunk
+    std::vector<int32_t> p2p_tile, p2p_chunk;    // per direct tile: its tile and chunk
+    std::vector<int32_t> order;                  // workgroup -> chunk
+    std::vector<int32_t> dto, dtr, dti;          // per chunk: direct tiles by first panel
+    int64_t aoff = 0;                            // elements of one tile store
+    int64_t tile_steps = 0, max_chunk_steps = 0;
+};
+TilePlan plan_tiles(const Geometry& g);
 // Geometry-only left factors of the matrix-core far-field product, in each needed precision.
-void build_tiles(Geometry& g);
+void build_tiles(Geometry& g, const TilePlan& plan);
 
 }  // namespace lspr

@@ -1567,8 +1567,8 @@ bool fold_near(Geometry& g, T* A, float* A32, const int32_t* dt_off, const int32
     return false;
 }
 
-void build_tiles(Geometry& g) {
-    hipStream_t s = g.stream;
+TilePlan plan_tiles(const Geometry& g) {
+    TilePlan P;
     const int nc = g.n_chunks;
     // the lists as the list builder left them on the host
     const std::vector<int32_t>&mo = g.m2p_off_h, &po = g.p2p_off_h, &ms = g.m2p_self_h,
@@ -1591,11 +1591,14 @@ void build_tiles(Geometry& g) {
         T.b_rows = rows;
         return T;
     };
-    std::vector<TileDesc> tiles;
-    std::vector<int32_t> toff(nc + 1, 0), tself(nc, 0);
-    std::vector<int32_t> m2p_tile(std::max<int64_t>(g.n_m2p, 1)), m2p_chunk(std::max<int64_t>(g.n_m2p, 1));
-    std::vector<int32_t> p2p_tile, p2p_chunk;
-    int64_t aoff = 0;
+    std::vector<TileDesc>& tiles = P.tiles;
+    std::vector<int32_t>&toff = P.toff, &tself = P.tself, &m2p_tile = P.m2p_tile,
+                         &m2p_chunk = P.m2p_chunk, &p2p_tile = P.p2p_tile, &p2p_chunk = P.p2p_chunk;
+    toff.assign(nc + 1, 0);
+    tself.assign(nc, 0);
+    m2p_tile.assign(g.n_m2p, 0);
+    m2p_chunk.assign(g.n_m2p, 0);
+    int64_t& aoff = P.aoff;
     for (int c = 0; c < nc; ++c) {
         toff[c] = static_cast<int32_t>(tiles.size());
         for (int phase = 0; phase < 2; ++phase) {
@@ -1619,13 +1622,13 @@ void build_tiles(Geometry& g) {
         }
     }
     toff[nc] = static_cast<int32_t>(tiles.size());
-    g.tile_steps = 0;
-    g.max_chunk_steps = 0;
+    P.tile_steps = 0;
+    P.max_chunk_steps = 0;
     std::vector<int64_t> csteps(nc, 0);
     for (int c = 0; c < nc; ++c) {
         for (int t = toff[c]; t < toff[c + 1]; ++t) csteps[c] += tiles[t].nstep;
-        g.tile_steps += csteps[c];
-        g.max_chunk_steps = std::max(g.max_chunk_steps, csteps[c]);
+        P.tile_steps += csteps[c];
+        P.max_chunk_steps = std::max(P.max_chunk_steps, csteps[c]);
     }
     // Workgroup order: run x = b % 8 of consecutive chunks (the workgroups of one XCD), the runs
     // cut at equal shares of the estimated work (K-steps plus 4 per tile for its fixed costs),
@@ -1656,9 +1659,36 @@ void build_tiles(Geometry& g) {
                          [&](int32_t a, int32_t b) { return ccost[a] > ccost[b]; });
         per_xcd = std::max(per_xcd, run.size());
     }
-    std::vector<int32_t> order(std::max<size_t>(per_xcd, 1) * 8, -1);
+    std::vector<int32_t>& order = P.order;
+    order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
+    // each chunk's direct tiles sorted by first source panel, for the near-field fold
+    P.dto.assign(nc + 1, 0);
+    for (int c = 0; c < nc; ++c) {
+        P.dto[c] = static_cast<int32_t>(P.dti.size());
+        std::vector<std::pair<int32_t, int32_t>> d;
+        for (int t = toff[c]; t < toff[c + 1]; ++t)
+            if (tiles[t].kind == 1) d.emplace_back(tiles[t].b_row0, t);
+        std::sort(d.begin(), d.end());
+        for (auto& e : d) {
+            P.dtr.push_back(e.first);
+            P.dti.push_back(e.second);
+        }
+    }
+    P.dto[nc] = static_cast<int32_t>(P.dti.size());
+    return P;
+}
+
+void build_tiles(Geometry& g, const TilePlan& P) {
+    hipStream_t s = g.stream;
+    const int nc = g.n_chunks;
+    LSPR_REQUIRE(static_cast<int>(P.toff.size()) == nc + 1, LSPR_E_INVALID,
+                 "tile plan does not match the geometry");
+    g.tile_steps = P.tile_steps;
+    g.max_chunk_steps = P.max_chunk_steps;
+    const std::vector<int32_t>& order = P.order;
+    const int64_t aoff = P.aoff;
     g.n_order = static_cast<int>(order.size());
     // Tile stores within the budget: FP32 first (the GMRES products of the FP32 and refinement
     // modes), then FP64 with what is left.  A precision without tiles keeps the on-the-fly
@@ -1671,40 +1701,26 @@ void build_tiles(Geometry& g) {
         g.n_tiles = 0;
         return;
     }
-    g.n_tiles = static_cast<int64_t>(tiles.size());
+    g.n_tiles = static_cast<int64_t>(P.tiles.size());
     g.tiles.alloc(std::max<int64_t>(g.n_tiles, 1));
     g.tile_off.alloc(nc + 1);
     g.tile_self.alloc(nc);
     g.chunk_order.alloc(order.size());
     Uploads up(s);  // every table below in one transfer
     up.add(g.chunk_order.p, order.data(), order.size());
-    up.add(g.tiles.p, tiles.data(), tiles.size());
-    up.add(g.tile_off.p, toff.data(), toff.size());
-    up.add(g.tile_self.p, tself.data(), tself.size());
-    const int n_m2p = static_cast<int>(g.n_m2p), n_p2p = static_cast<int>(p2p_tile.size());
+    up.add(g.tiles.p, P.tiles.data(), P.tiles.size());
+    up.add(g.tile_off.p, P.toff.data(), P.toff.size());
+    up.add(g.tile_self.p, P.tself.data(), P.tself.size());
+    const int n_m2p = static_cast<int>(g.n_m2p), n_p2p = static_cast<int>(P.p2p_tile.size());
     DevBuf<int32_t> mt(n_m2p), mc(n_m2p), pt(n_p2p), pc(n_p2p);
-    up.add(mt.p, m2p_tile.data(), n_m2p);
-    up.add(mc.p, m2p_chunk.data(), n_m2p);
-    up.add(pt.p, p2p_tile.data(), n_p2p);
-    up.add(pc.p, p2p_chunk.data(), n_p2p);
-    // each chunk's direct tiles sorted by first source panel, for the near-field fold
-    std::vector<int32_t> dto(nc + 1, 0), dtr, dti;
-    for (int c = 0; c < nc; ++c) {
-        dto[c] = static_cast<int32_t>(dti.size());
-        std::vector<std::pair<int32_t, int32_t>> d;
-        for (int t = toff[c]; t < toff[c + 1]; ++t)
-            if (tiles[t].kind == 1) d.emplace_back(tiles[t].b_row0, t);
-        std::sort(d.begin(), d.end());
-        for (auto& e : d) {
-            dtr.push_back(e.first);
-            dti.push_back(e.second);
-        }
-    }
-    dto[nc] = static_cast<int32_t>(dti.size());
-    DevBuf<int32_t> dto_d(nc + 1), dtr_d(std::max<size_t>(dtr.size(), 1)), dti_d(std::max<size_t>(dti.size(), 1));
-    up.add(dto_d.p, dto.data(), dto.size());
-    up.add(dtr_d.p, dtr.data(), dtr.size());
-    up.add(dti_d.p, dti.data(), dti.size());
+    up.add(mt.p, P.m2p_tile.data(), n_m2p);
+    up.add(mc.p, P.m2p_chunk.data(), n_m2p);
+    up.add(pt.p, P.p2p_tile.data(), n_p2p);
+    up.add(pc.p, P.p2p_chunk.data(), n_p2p);
+    DevBuf<int32_t> dto_d(nc + 1), dtr_d(std::max<size_t>(P.dtr.size(), 1)), dti_d(std::max<size_t>(P.dti.size(), 1));
+    up.add(dto_d.p, P.dto.data(), P.dto.size());
+    up.add(dtr_d.p, P.dtr.data(), P.dtr.size());
+    up.add(dti_d.p, P.dti.data(), P.dti.size());
     up.flush();
     // with both stores, one FP64 pass fills both (the FP32 tiles are the FP64 values rounded)
     if (keep32) g.tileA.alloc(std::max<int64_t>(aoff, 1));
