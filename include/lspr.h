@@ -290,6 +290,17 @@ int lspr_server_submit(lspr_server* sv, const lspr_surface* surfaces, int32_t n_
                        const lspr_c64* eps_medium, const lspr_c64* eps_surface,
                        const double* e_field, const lspr_gmres_params* gm, uint64_t* ticket);
 
+/* As lspr_server_submit, with point charges inside the surfaces (Eq. integral_eq_lspr_system,
+ * last row; arguments and units as lspr_geometry_set_charges, HOST arrays copied before
+ * return): the request's geometry takes them before its solve.  n_q = 0 is a plain request.
+ * LSPR_E_INVALID at once for a surface index out of range or non-finite values. */
+int lspr_server_submit_charges(lspr_server* sv, const lspr_surface* surfaces, int32_t n_surf,
+                               const lspr_op_params* op, int32_t n_lambda,
+                               const double* lambda_nm, const lspr_c64* eps_medium,
+                               const lspr_c64* eps_surface, const double* e_field,
+                               const lspr_gmres_params* gm, int32_t n_q, const double* pos,
+                               const double* q, const int32_t* surface, uint64_t* ticket);
+
 /* Result of a request.  wait = 0 returns LSPR_E_BUSY while the request is queued or running;
  * wait != 0 blocks until it is done.  On LSPR_OK the results are copied (host arrays of
  * n_lambda entries, [n_lambda][3] for the dipoles; any may be NULL), *info is filled and the
@@ -353,8 +364,8 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
  * permittivity, in units of the incident potential times length: one elementary charge is
  * 18.0951 V nm), surface [n_q] (index of the enclosing surface).  The geometry keeps
  * sum_k q_k / (4 pi |c_i - r_k|) per panel (FP64, direct sum) for every later lspr_solve and
- * lspr_rhs; n_q = 0 removes the charges.  The request server does not take charges.
- * LSPR_E_INVALID for a surface index out of range or non-finite values. */
+ * lspr_rhs; n_q = 0 removes the charges.  lspr_server_submit_charges passes charges to the
+ * request server.  LSPR_E_INVALID for a surface index out of range or non-finite values. */
 int lspr_geometry_set_charges(lspr_geometry* g, int32_t n_q, const double* pos, const double* q,
                               const int32_t* surface, void* stream);
 

@@ -8,6 +8,7 @@
 // run concurrently on the device.  After set-up the reservation shrinks to what the request
 // actually holds, so that queued requests are admitted early.
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -18,6 +19,7 @@
 #include <unordered_map>
 
 #include "driver.hpp"
+#include "system.hpp"
 
 namespace {
 
@@ -33,6 +35,8 @@ struct Request {
     std::vector<double> lambda;
     std::vector<lspr_c64> em, es;
     double e[3] = {0, 0, 0};
+    std::vector<double> qpos, qval;  // point charges (may be empty): [n][3], [n]
+    std::vector<int32_t> qsurf;      // [n] enclosing surface
     int64_t n_panels = 0;
     int S = 0, B = 0;
     int64_t est = 0, reserved = 0;
@@ -101,6 +105,9 @@ void lspr_server::run(Request& r, hipStream_t s) {
             }
             lspr::create_geometry(g, dev.data(), r.S, r.op, s);
         }
+        if (!r.qval.empty())
+            lspr::set_charges(g, static_cast<int>(r.qval.size()), r.qpos.data(), r.qval.data(),
+                              r.qsurf.data(), s);
         // the set-up is done: keep only what the solve still needs reserved
         {
             const int64_t need =
@@ -247,10 +254,27 @@ int lspr_server_submit(lspr_server* sv, const lspr_surface* surfaces, int32_t n_
                        const lspr_op_params* op, int32_t n_lambda, const double* lambda_nm,
                        const lspr_c64* eps_medium, const lspr_c64* eps_surface,
                        const double* e_field, const lspr_gmres_params* gm, uint64_t* ticket) {
+    return lspr_server_submit_charges(sv, surfaces, n_surf, op, n_lambda, lambda_nm, eps_medium,
+                                      eps_surface, e_field, gm, 0, nullptr, nullptr, nullptr,
+                                      ticket);
+}
+
+int lspr_server_submit_charges(lspr_server* sv, const lspr_surface* surfaces, int32_t n_surf,
+                               const lspr_op_params* op, int32_t n_lambda,
+                               const double* lambda_nm, const lspr_c64* eps_medium,
+                               const lspr_c64* eps_surface, const double* e_field,
+                               const lspr_gmres_params* gm, int32_t n_q, const double* pos,
+                               const double* q, const int32_t* surface, uint64_t* ticket) {
     return guarded([&] {
         LSPR_REQUIRE(sv && surfaces && op && lambda_nm && eps_medium && eps_surface && e_field &&
-                         gm && ticket && n_surf >= 1 && n_surf <= 4096 && n_lambda >= 1,
+                         gm && ticket && n_surf >= 1 && n_surf <= 4096 && n_lambda >= 1 &&
+                         n_q >= 0 && (n_q == 0 || (pos && q && surface)),
                      LSPR_E_INVALID, "bad arguments");
+        for (int k = 0; k < n_q; ++k)  // checked here so that a bad charge fails the submit
+            LSPR_REQUIRE(surface[k] >= 0 && surface[k] < n_surf && std::isfinite(q[k]) &&
+                             std::isfinite(pos[3 * k]) && std::isfinite(pos[3 * k + 1]) &&
+                             std::isfinite(pos[3 * k + 2]),
+                         LSPR_E_INVALID, "charges must be finite and inside a listed surface");
         lspr::validate_op(surfaces, n_surf, op);
         LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1 &&
                      gm->inner_tol >= 0.0 && gm->inner_tol < 1.0,
@@ -269,8 +293,14 @@ int lspr_server_submit(lspr_server* sv, const lspr_surface* surfaces, int32_t n_
         r->em.assign(eps_medium, eps_medium + n_lambda);
         r->es.assign(eps_surface, eps_surface + static_cast<size_t>(n_lambda) * n_surf);
         for (int d = 0; d < 3; ++d) r->e[d] = e_field[d];
+        r->qpos.assign(pos, pos + 3 * static_cast<size_t>(n_q));
+        r->qval.assign(q, q + n_q);
+        r->qsurf.assign(surface, surface + n_q);
         r->B = std::min<int>(n_lambda, lspr::MAX_BATCH);
         r->est = lspr::request_footprint(r->n_panels, n_surf, n_lambda, *op, *gm);
+        if (n_q > 0)  // per-panel charge potential, 1 / eps_s per batch column, charge copies
+            r->est += 8 * r->n_panels + 16 * static_cast<int64_t>(r->B) * n_surf + 32ll * n_q +
+                      8 * (n_surf + 1);
         std::lock_guard<std::mutex> lk(sv->mu);
         LSPR_REQUIRE(!sv->stop, LSPR_E_INVALID, "server is shutting down");
         LSPR_REQUIRE(r->est <= sv->budget, LSPR_E_NOMEM,

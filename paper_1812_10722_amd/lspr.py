@@ -347,6 +347,10 @@ _sig("lspr_server_create", C.c_int, [_P(lspr_server_params), _P(C.c_void_p)])
 _sig("lspr_server_submit", C.c_int, [C.c_void_p, _P(lspr_surface), C.c_int32, _P(lspr_op_params),
                                      C.c_int32, _P(C.c_double), _P(lspr_c64), _P(lspr_c64),
                                      _P(C.c_double), _P(lspr_gmres_params), _P(C.c_uint64)])
+_sig("lspr_server_submit_charges", C.c_int,
+     [C.c_void_p, _P(lspr_surface), C.c_int32, _P(lspr_op_params), C.c_int32, _P(C.c_double),
+      _P(lspr_c64), _P(lspr_c64), _P(C.c_double), _P(lspr_gmres_params), C.c_int32,
+      _P(C.c_double), _P(C.c_double), _P(C.c_int32), _P(C.c_uint64)])
 _sig("lspr_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, _P(lspr_request_info),
                                    _P(C.c_double), _P(C.c_double), _P(lspr_c64), _P(lspr_c64),
                                    _P(C.c_int32), _P(C.c_double)])
@@ -417,7 +421,9 @@ class Server:
         self._nl = {}
 
     def submit(self, surfaces, lambdas, eps_medium, eps_surface, e_field=(0.0, 0.0, 1.0),
-               op=None, gmres=None) -> int:
+               op=None, gmres=None, charges=None) -> int:
+        """Queues one request; charges = (positions [n, 3], charges [n], surfaces [n]) or None
+        (lspr_server_submit_charges / lspr_server_submit)."""
         lam = np.ascontiguousarray(lambdas, dtype=np.float64).reshape(-1)
         nl = len(lam)
         ns = len(surfaces)
@@ -434,9 +440,20 @@ class Server:
         op = op if op is not None else op_params()
         gm = gmres if gmres is not None else gmres_params()
         tk = C.c_uint64()
-        _check(_lib.lspr_server_submit(self.handle, arr, ns, C.byref(op), nl, _dptr(lam), em_p,
-                                       es_p, _dptr(ef), C.byref(gm), C.byref(tk)),
-               "lspr_server_submit")
+        if charges is None:
+            _check(_lib.lspr_server_submit(self.handle, arr, ns, C.byref(op), nl, _dptr(lam),
+                                           em_p, es_p, _dptr(ef), C.byref(gm), C.byref(tk)),
+                   "lspr_server_submit")
+        else:
+            pos = np.ascontiguousarray(np.asarray(charges[0], dtype=np.float64).reshape(-1, 3))
+            q = np.ascontiguousarray(np.asarray(charges[1], dtype=np.float64).ravel())
+            sid = np.ascontiguousarray(np.asarray(charges[2], dtype=np.int32).ravel())
+            assert len(pos) == len(q) == len(sid)
+            _check(_lib.lspr_server_submit_charges(
+                self.handle, arr, ns, C.byref(op), nl, _dptr(lam), em_p, es_p, _dptr(ef),
+                C.byref(gm), len(q), _dptr(pos), _dptr(q),
+                sid.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(tk)),
+                "lspr_server_submit_charges")
         self._nl[tk.value] = nl
         return tk.value
 

@@ -5,7 +5,7 @@ What is checked: a request's results are the same alone and in a mix of concurre
 far inside the 1e-4 FP32 tolerance), the mix really overlaps on the device, the admission
 estimate bounds every request's measured peak of device memory, the budget is never
 over-reserved, failures stay with their own request, and a small multi-surface request matches
-the oracle.
+the oracle, with and without point charges in an analyte.
 """
 import numpy as np
 import pytest
@@ -192,6 +192,40 @@ def test_small_multi_surface_request_matches_oracle(lib):
     for key in ("cext_sensor", "cext_total"):
         rel = np.abs(r[key] - ref[key]) / np.abs(ref[key])
         assert rel.max() < 1e-4, (key, rel.max())
+
+
+def test_request_with_charges_matches_oracle(lib):
+    """Point charges inside one analyte of a served request (Eq. integral_eq_lspr_system, last
+    row) against the dense FP64 oracle with the same charges (FP32 bar 1e-4); the charges move
+    C_ext by far more than that, and a charge outside the listed surfaces fails the submit."""
+    rng = np.random.default_rng(23)
+    s = octasphere(8, 8.0)
+    bv, bt = perturbed_ellipsoid(5, (1.5, 4.0, 1.5), rng)
+    blob = place_at_gap(bv, [0, 0, 1.0], 8.0, 1.0)
+    surfs = [s, (blob, bt)]
+    pos = blob.mean(0)[None, :] + 0.3 * rng.standard_normal((2, 3))
+    charges = (pos, np.array([2 * 18.0951, -18.0951]), np.array([1, 1]))  # +2 e, -1 e
+    lam = wavelength_grid(378.0, 392.0, 4)
+    em = np.full(4, EPS_WATER + 0j)
+    es = np.stack([eps_silver_drude(lam), np.full(4, 2.5 + 0.1j)], 1)
+    sv = lib.Server(max_slots=2)
+    try:
+        with pytest.raises(lib.LsprError):
+            sv.submit(surfs, lam, em, es, op=_op(lib), charges=(pos, [1.0, 1.0], [1, 2]))
+        # FP32 products: tol 1e-6 (1e-7 is near what they can resolve), as the geometry test
+        r = sv.poll(sv.submit(surfs, lam, em, es, op=_op(lib),
+                              gmres=lib.gmres_params(tol=1e-6, restart=100, max_iter=1000),
+                              charges=charges), wait=True)
+    finally:
+        sv.close()
+    assert r["status"] == 0, r["error"]
+    v, t, sid = merge_surfaces(surfs)
+    ref = oracle.solve(v, t, sid, lam, em, es, [0, 0, 1.0], k_far=4, k_fine=19, charges=charges)
+    ref0 = oracle.solve(v, t, sid, lam, em, es, [0, 0, 1.0], k_far=4, k_fine=19)
+    for key in ("cext_sensor", "cext_total"):
+        rel = np.abs(r[key] - ref[key]) / np.abs(ref[key])
+        assert rel.max() < 1e-4, (key, rel.max())
+    assert (np.abs(ref0["cext_total"] / ref["cext_total"] - 1)).max() > 1e-3
 
 
 def test_burst_of_large_requests_all_succeed(lib):
