@@ -29,21 +29,55 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("treecode matvec Gpair/s; wavelength-solves/s at 1e-4 rel err vs FP64; p50/p99")
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X datasheet, dense FP32 matrix cores (measured sustained: 155)
+PEAK_FP64_MFMA_TFLOPS = 78.6    # MI355X datasheet, dense FP64 matrix cores
 PEAK_HBM_GBS = 8000.0
+WIDTH_BINS = ((1, 8), (9, 16), (17, 32), (33, 64))  # wavelengths per far-field launch
+
+
+def precomputed_flops(info, op):
+    """Geometry-only work the matrix-core path does once per geometry instead of per launch:
+    far-rule kernel values (15 flops per node, 9 per pair) and Taylor coefficients (about 10
+    flops per term)."""
+    return (float(info["p2p_pairs"]) * (15.0 * op["k_far"] + 9.0)
+            + float(info["m2p_pairs"]) * 10.0 * info["n_terms"])
+
+
+def width_rows(lspr, name, peak_tflops, timed):
+    """Roofline position of the far-field launches by width.  Arithmetic intensity = executed
+    flops / algorithmic bytes (the tile store read once, densities, moments, sums); below the
+    ridge (peak flop/s over 8 TB/s) a launch is bound by HBM and its fraction is GB/s over
+    8 TB/s, above it by the matrix cores and its fraction is TFLOP/s over the peak."""
+    rows = []
+    ridge = peak_tflops * 1e12 / (PEAK_HBM_GBS * 1e9)
+    for lo, hi in WIDTH_BINS:
+        q = timed[(name, lo, hi)]
+        if q["launches"] == 0 or q["total_ms"] <= 0:
+            continue
+        t = q["total_ms"] * 1e-3
+        tf, gbs = q["flops"] / t / 1e12, q["bytes"] / t / 1e9
+        hbm = q["flops"] / max(q["bytes"], 1.0) < ridge
+        rows.append({"wavelengths": f"{lo}-{hi}", "launches": q["launches"],
+                     "avg_launch_ms": q["total_ms"] / q["launches"],
+                     "tflops": tf, "gbs": gbs, "flop_per_byte": q["flops"] / max(q["bytes"], 1.0),
+                     "bound": "hbm" if hbm else "mfma",
+                     "frac": gbs / PEAK_HBM_GBS if hbm else tf / peak_tflops})
+    return rows
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_rows=768, seed=0):
+def cpu_baseline(w, n_rows=768, seed=0, iters_full=None):
     """The oracle (numpy FP64 dense BEM, unchanged) timed on a bounded sample of this workload.
 
     Sample: `n_rows` random target rows of the dense single/double-layer matrices at full size
-    (all 4N far-rule nodes, near-singular and singular terms), one dense complex product of those
-    rows of the system matrix, and the oracle's own GMRES iteration count on the same sphere
-    coarsened to 512 panels at the central wavelength.  Extrapolated per wavelength-solve:
-    (row assembly x N / n_rows) / n_lambda + (iterations + 1) x (row product x 2N / n_rows).
+    (all 4N far-rule nodes, near-singular and singular terms) and one dense complex product of
+    those rows of the system matrix.  Extrapolated per wavelength-solve:
+    (row assembly x N / n_rows) / n_lambda + (iterations + 1) x (row product x 2N / n_rows),
+    with the iteration count of this system itself (`iters_full`: the mean of the GPU's FP64
+    solves of the same workload at the same tolerance, one wavelength per solve); without it,
+    the oracle's own GMRES count on the same sphere coarsened to 512 panels.
     """
     import oracle
     from threadpoolctl import threadpool_info
@@ -65,15 +99,24 @@ def cpu_baseline(w, n_rows=768, seed=0):
     for _ in range(3):
         A_rows @ x
     t_mv = (time.perf_counter() - t0) / 3
-    vs, ts = octasphere(8, 10.0)
-    mid = len(w.lambdas) // 2
-    t0 = time.perf_counter()
-    r = oracle.solve(vs, ts, np.zeros(len(ts), int), w.lambdas[mid:mid + 1],
-                     w.eps_medium[mid:mid + 1], w.eps_surface[mid:mid + 1], w.e_field,
-                     op["k_far"], op["k_fine"], op["n_k"], op["threshold"], method="gmres",
-                     tol=w.gmres["tol"], restart=w.gmres["restart"], max_iter=w.gmres["max_iter"])
-    t_small = time.perf_counter() - t0
-    iters = int(r["iters"][0])
+    if iters_full is not None:
+        iters = float(iters_full)
+        how = (f"the {N}-panel system's own GMRES iteration count ({iters:.1f}, mean of the "
+               f"GPU's FP64 treecode solves of this workload at tol {w.gmres['tol']:g}, one "
+               f"wavelength per solve)")
+    else:
+        vs, ts = octasphere(8, 10.0)
+        mid = len(w.lambdas) // 2
+        t0 = time.perf_counter()
+        r = oracle.solve(vs, ts, np.zeros(len(ts), int), w.lambdas[mid:mid + 1],
+                         w.eps_medium[mid:mid + 1], w.eps_surface[mid:mid + 1], w.e_field,
+                         op["k_far"], op["k_fine"], op["n_k"], op["threshold"], method="gmres",
+                         tol=w.gmres["tol"], restart=w.gmres["restart"],
+                         max_iter=w.gmres["max_iter"])
+        iters = float(r["iters"][0])
+        how = (f"the oracle's unpreconditioned GMRES iteration count ({iters:.0f}) on the "
+               f"512-panel sphere at {w.lambdas[mid]:.1f} nm "
+               f"({time.perf_counter() - t0:.1f} s)")
     per_solve = (t_rows * N / n_rows) / len(w.lambdas) + (iters + 1) * t_mv * (2 * N / n_rows)
     blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     return {
@@ -81,23 +124,43 @@ def cpu_baseline(w, n_rows=768, seed=0):
         "kind": "oracle",
         "sample": (f"{n_rows} of {N} target rows of the dense V,K matrices ({t_rows:.1f} s) and "
                    f"one product of those system rows ({t_mv * 1e3:.1f} ms), extrapolated to one "
-                   f"wavelength-solve with the oracle's unpreconditioned GMRES iteration count "
-                   f"({iters}) on the 512-panel sphere at {w.lambdas[mid]:.1f} nm "
-                   f"({t_small:.1f} s); row assembly single-threaded numpy, products use "
-                   f"{blas_threads} BLAS threads"),
+                   f"wavelength-solve with {how}; row assembly single-threaded numpy, products "
+                   f"use {blas_threads} BLAS threads"),
         "seconds_per_solve": per_solve,
     }
 
 
-def serving_leg(lspr, n_requests, seed=5, max_slots=4, load=0.8):
+def _build_request(args):
+    from lspr_inputs import serving_request
+    return serving_request(*args)
+
+
+def serving_requests(n_requests, seed=5, workers=12):
+    """The first n_requests of the seeded Poisson stream (arrival offsets, workloads); meshes are
+    built in a process pool (each request has its own generator, so the stream is unchanged)."""
+    from lspr_inputs import serving_stream_params
+    params = list(serving_stream_params(seed=seed, n_requests=n_requests))
+    arrivals = np.array([p[0] for p in params])
+    jobs = [(seed,) + tuple(p[1:]) for p in params]
+    if n_requests <= 16 or workers <= 1:
+        reqs = [_build_request(j) for j in jobs]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            reqs = pool.map(_build_request, jobs, chunksize=1)
+    return arrivals, reqs
+
+
+def serving_leg(lspr, n_requests, seed=5, max_slots=4, load=0.8, n_burst=None):
     """Request-serving leg: the first n_requests of the seeded Poisson stream (spheres of
     2048-131072 panels with 0-4 analytes at 0.5-3 nm, 1-64 wavelengths each) through the
-    request server.  A burst (all submitted at once) gives the saturated throughput; then the
-    same requests arrive with the stream's own exponential gaps rescaled to `load` times that
-    rate, and the latency (completion - arrival) of each is recorded."""
-    from lspr_inputs import serving_stream
-    reqs = [w for _, w in serving_stream(seed=seed, n_requests=n_requests)]
-    gaps = np.diff([t for t, _ in serving_stream(seed=seed, n_requests=n_requests)], prepend=0.0)
+    request server.  A burst of the first n_burst requests (all submitted at once; default all
+    of them) gives the saturated throughput; then all n_requests arrive with the stream's own
+    exponential gaps rescaled to `load` times that rate, and the latency (completion - arrival)
+    of each is recorded: p50 and p99 are over those n_requests samples."""
+    arrivals, reqs = serving_requests(n_requests, seed)
+    n_burst = len(reqs) if n_burst is None else min(n_burst, len(reqs))
+    gaps = np.diff(arrivals, prepend=0.0)
     sv = lspr.Server(max_slots=max_slots)
 
     def submit(w):
@@ -106,10 +169,12 @@ def serving_leg(lspr, n_requests, seed=5, max_slots=4, load=0.8):
 
     try:
         t0 = time.perf_counter()
-        burst = [sv.poll(t, wait=True) for t in [submit(w) for w in reqs]]
+        burst = [sv.poll(t, wait=True) for t in [submit(w) for w in reqs[:n_burst]]]
         burst_s = time.perf_counter() - t0
         burst_stats = sv.stats()
-        rate = load * len(reqs) / burst_s
+        rate = load * n_burst / burst_s
+        log(f"[bench] serving burst: {n_burst} requests in {burst_s:.1f} s; pacing "
+            f"{len(reqs)} requests at {rate:.3f} req/s")
         arrive = np.cumsum(gaps) - gaps[0]
         arrive *= (1.0 / rate) / max(np.mean(gaps), 1e-12)
         start = time.perf_counter()
@@ -118,29 +183,62 @@ def serving_leg(lspr, n_requests, seed=5, max_slots=4, load=0.8):
             while time.perf_counter() - start < arrive[k]:
                 time.sleep(0.0005)
             tickets.append(submit(w))
+            if (k + 1) % 25 == 0:
+                log(f"[bench] serving: {k + 1}/{len(reqs)} submitted")
         paced = [sv.poll(t, wait=True) for t in tickets]
+        paced_s = time.perf_counter() - start
         paced_stats = sv.stats()
     finally:
         sv.close()
     lat = np.array([r["latency_s"] for r in paced])
-    ok = [r["status"] == lspr.LSPR_OK for r in burst]
-    n_ok_lambda = int(sum(r["n_lambda"] for r, good in zip(burst, ok) if good))
+    ok_b = [r["status"] == lspr.LSPR_OK for r in burst]
+    ok_p = [r["status"] == lspr.LSPR_OK for r in paced]
+    n_ok_lambda = int(sum(r["n_lambda"] for r, good in zip(burst, ok_b) if good))
     return {
-        "requests": len(reqs), "max_slots": max_slots,
-        "panels": {"min": int(min(r["n_panels"] for r in burst)),
-                   "max": int(max(r["n_panels"] for r in burst))},
-        "wavelengths": int(sum(r["n_lambda"] for r in burst)),
-        "converged": int(sum(ok)),
-        "burst_s": burst_s, "burst_requests_per_s": len(reqs) / burst_s,
+        "requests": len(reqs), "burst_requests": n_burst, "max_slots": max_slots,
+        "panels": {"min": int(min(r["n_panels"] for r in paced)),
+                   "max": int(max(r["n_panels"] for r in paced))},
+        "wavelengths": int(sum(r["n_lambda"] for r in paced)),
+        "converged": int(sum(ok_p)),
+        "burst_s": burst_s, "burst_requests_per_s": n_burst / burst_s,
         "burst_wavelength_solves_per_s": n_ok_lambda / burst_s,
-        "max_concurrent": int(burst_stats["max_active"]),
+        "max_concurrent": int(max(burst_stats["max_active"], paced_stats["max_active"])),
         "paced_rate_requests_per_s": rate,
+        "paced_s": paced_s,
+        "paced_wavelength_solves_per_s": int(sum(r["n_lambda"] for r, g in zip(paced, ok_p)
+                                                 if g)) / paced_s,
+        "latency_samples": int(len(lat)),
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
         "latency_max_s": float(lat.max()),
         "estimate_violations": int(paced_stats["estimate_violations"]),
         "precision": reqs[0].op["precision"],
     }
+
+
+def serving_main(args):
+    """--serving-only: the request stream alone (metric: served wavelength-solves/s at the paced
+    rate, with p50/p99 latency over every paced request)."""
+    import torch
+    from paper_1812_10722_amd import lspr
+    torch.cuda.set_device(0)
+    n = 200 if args.serving_requests is None else args.serving_requests
+    n_burst = 32 if args.serving_burst is None else args.serving_burst
+    log(f"[bench] serving stream: {n} requests, burst of {n_burst} ...")
+    srv = serving_leg(lspr, n, n_burst=n_burst)
+    line = {"metric": "served wavelength-solves/s at 0.8 of the saturated request rate; p50/p99 "
+                      "request latency", "value": srv["paced_wavelength_solves_per_s"],
+            "unit": "wavelength-solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "fp32+fp64", "data": "synthetic (seeded Poisson request stream)",
+            "config": {"workload": f"serving_stream_seed5_first{n}", "requests": n,
+                       "max_slots": srv["max_slots"], "parallelism": "single GPU"},
+            "latency_p50_s": srv["latency_p50_s"], "latency_p99_s": srv["latency_p99_s"],
+            "serving": srv}
+    log(f"[bench] serving: burst {srv['burst_requests_per_s']:.3f} req/s; {n} paced at "
+        f"{srv['paced_rate_requests_per_s']:.3f} req/s: p50 {srv['latency_p50_s']:.2f} s, p99 "
+        f"{srv['latency_p99_s']:.2f} s")
+    print(json.dumps(line), flush=True)
 
 
 def traffic_entry(kernel_file, name):
@@ -230,8 +328,16 @@ def main():
                          "fp32_lead64 (default: the library's)")
     ap.add_argument("--tol", type=float, default=None, help="override the GMRES tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=16,
-                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serving-requests", type=int, default=None,
+                    help="requests of the serving leg (default 16, or 200 with --serving-only; "
+                         "0 skips it)")
+    ap.add_argument("--serving-burst", type=int, default=None,
+                    help="requests of the burst that measures the saturated rate (default: all "
+                         "of them, or 32 with --serving-only)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving stream: a burst prefix measures the saturated rate, "
+                         "then the requests arrive paced at 0.8 of it; one JSON line with p50/p99 "
+                         "latency over all of them")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference solve and the one-at-a-time FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -248,10 +354,12 @@ def main():
                        workload(args.workload).name)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the build targets a "
-              "single MI355X; a multi-GPU split by wavelength is described in DESIGN.md but not "
-              "built.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the library targets "
+              "a single MI355X; a split of the wavelengths over several GPUs is designed but "
+              "not built.", file=sys.stderr)
         sys.exit(2)
+    if args.serving_only:
+        return serving_main(args)
 
     import torch
     from lspr_inputs import workload
@@ -308,6 +416,8 @@ def main():
     total = time.perf_counter() - t_start
     lspr.lspr_profile_enable(False)
     far_timed = lspr.lspr_profile_query("far")
+    width_timed = {(name, lo, hi): lspr.lspr_profile_query_width(name, lo, hi)
+                   for name in ("far", "far64") for lo, hi in WIDTH_BINS}
     lspr.lspr_profile_reset()
     lspr.lspr_profile_enable(1)
     step(op, lam, em, es, gm)
@@ -337,19 +447,21 @@ def main():
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
+        it64 = []
         for k in sel:
-            g64.solve(lam[k:k + 1], em[k:k + 1], es[k:k + 1], ef, **gm)
+            it64.append(int(g64.solve(lam[k:k + 1], em[k:k + 1], es[k:k + 1], ef,
+                                      **gm)["iters"][0]))
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
         g64.close()
         fp64_b1 = {"form": "treecode FP64 kernels, one wavelength per solve",
-                   "wavelengths": int(len(sel)),
+                   "wavelengths": int(len(sel)), "iters": it64,
                    "solves_per_s_incl_setup": len(sel) / (t_setup + t_solve),
                    "solves_per_s_steady": len(sel) / t_solve}
         log(f"[bench] FP64 one-at-a-time: {fp64_b1['solves_per_s_steady']:.2f} solves/s")
 
-    ok = accuracy["within_1e-4"] if accuracy else len(lam)
-    value = ok * args.steps / total
+    # wavelengths within 1e-4 of the FP64 reference; without the reference nothing is credited
+    value = accuracy["within_1e-4"] * args.steps / total if accuracy else None
     far = far_timed
     achieved = far["flops"] / (far["total_ms"] * 1e-3) / 1e12 if far["total_ms"] > 0 else 0.0
     trec = traffic_entry(os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"), "far")
@@ -360,7 +472,13 @@ def main():
                 "traffic": (trec["bytes_per_launch"] if trec else None),
                 "launches": far["launches"],
                 "avg_launch_ms": far["total_ms"] / max(far["launches"], 1),
-                "algorithmic_flops_per_launch": far["flops"] / max(far["launches"], 1)}
+                # executed: 4 flops per used real column and direct pair, 4 (P+1)^2 per column
+                # and expansion pair (the tile contraction); the kernel values and Taylor
+                # coefficients are precomputed once per geometry (precomputed_flops)
+                "flops_per_launch": far["flops"] / max(far["launches"], 1),
+                "precomputed_flops": precomputed_flops(info, op),
+                "by_width": width_rows(lspr, "far", PEAK_FP32_MFMA_TFLOPS, width_timed),
+                "fp64_by_width": width_rows(lspr, "far64", PEAK_FP64_MFMA_TFLOPS, width_timed)}
     times_s = np.array(times)
     line = {
         "metric": METRIC, "value": value, "unit": "wavelength-solves/s", "n_gpus": 1,
@@ -373,9 +491,15 @@ def main():
                    "k_far": op["k_far"], "k_fine": op["k_fine"], "n_k": op["n_k"],
                    "threshold": op["threshold"], "kernels": op["precision"], "gmres": "fp64",
                    "gmres_tol": gm["tol"], "parallelism": "single GPU"},
-        # (direct target-node pairs + expansion target-box pairs) x wavelengths per second of
-        # the far-field kernel
+        # (direct target-NODE pairs + expansion target-box pairs) x wavelengths per second of
+        # the FP32 far-field launches; the panel form counts direct target-PANEL pairs (the
+        # entries of the operator matrices the launch applies, K = 4 times fewer)
         "matvec_gpair_per_s": far["items"] / (far["total_ms"] * 1e-3) / 1e9
+        if far["total_ms"] > 0 else None,
+        "matvec_gpair_definition": "(target-node + target-box) pairs x wavelengths / s",
+        "matvec_panel_gpair_per_s": (far["items"] / (far["total_ms"] * 1e-3) / 1e9
+                                     * (info["p2p_pairs"] + info["m2p_pairs"])
+                                     / (info["p2p_pairs"] * op["k_far"] + info["m2p_pairs"]))
         if far["total_ms"] > 0 else None,
         "matvec_launches_per_step": n_matvec,
         "step_latency_p50_s": float(np.percentile(times_s, 50)),
@@ -400,9 +524,10 @@ def main():
         "lists": {k: int(info[k]) for k in ("n_boxes", "n_m2p", "n_p2p_ranges", "p2p_pairs",
                                             "m2p_pairs", "n_near", "n_terms", "ncrit")},
     }
-    if args.serving_requests > 0:
-        log(f"[bench] serving leg: {args.serving_requests} requests ...")
-        srv = serving_leg(lspr, args.serving_requests)
+    n_srv = 16 if args.serving_requests is None else args.serving_requests
+    if n_srv > 0:
+        log(f"[bench] serving leg: {n_srv} requests ...")
+        srv = serving_leg(lspr, n_srv, n_burst=args.serving_burst)
         line["serving"] = srv
         line["latency_p50_s"] = srv["latency_p50_s"]
         line["latency_p99_s"] = srv["latency_p99_s"]
@@ -411,7 +536,8 @@ def main():
             f"{srv['paced_rate_requests_per_s']:.2f} req/s")
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline on a bounded sample ...")
-        line["cpu_baseline"] = cpu_baseline(w)
+        line["cpu_baseline"] = cpu_baseline(
+            w, iters_full=float(np.mean(fp64_b1["iters"])) if fp64_b1 else None)
     print(json.dumps(line), flush=True)
 
 

@@ -69,7 +69,8 @@ typedef struct {
 /* Discretisation and treecode parameters (section "Integral evaluation", Tables 1, 2, 4, 5;
  * section "Acceleration strategies").
  *   k_far     points of the far-panel rule: 1, 3, 4 or 7 (the paper uses 4)
- *   k_fine    points of the near-singular rule: 19 or 25 (the paper lists 19, 25, 37)
+ *   k_fine    points of the near-singular rule: 19, 25 or 37 (Dunavant's degree-9, 10 and 13
+ *             rules; the paper uses 19 and, for its grid-convergence study, 37)
  *   n_k       Gauss nodes per edge of the semi-analytic singular rule, 1..64 (paper: 9)
  *   threshold a source panel j is near-singular for collocation point x_i when
  *             |x_i - c_j| <= L_j / threshold, L = sqrt(2 Area) (paper: 0.5, i.e. 2L)
@@ -117,13 +118,16 @@ typedef struct {
 
 /* GMRES parameters (the paper gives only tolerances, Tables 2 and 5).
  *   tol       stop a wavelength when ||b - A x||_2 <= tol ||b||_2 (complex 2-norm over all
- *             2N unknowns)
+ *             2N unknowns).  LSPR_FP32 and LSPR_FP32_LEAD64 form that residual with FP32
+ *             products and reject tol < 1e-6 (LSPR_E_INVALID): use LSPR_FP32_REFINE64 or
+ *             LSPR_FP64 for tighter tolerances
  *   restart   Krylov dimension before restart, 1..512
  *   max_iter  total iteration cap per wavelength
  *   precond   0 = none, 1 = right block-Jacobi with the 2x2 self-panel blocks (does not
  *             change the solution, only the iteration count)
  *   inner_tol LSPR_FP32_REFINE64: relative tolerance of each inner FP32 solve (0 selects
- *             1e-4); max_iter then caps the inner iterations summed over the outer steps.
+ *             1e-4, values below 1e-6 are rejected); max_iter then caps the inner iterations
+ *             summed over the outer steps.
  *             LSPR_FP32_LEAD64: relative residual level below which a wavelength's products
  *             switch from FP64 to FP32 (0 selects 0.3).  Ignored otherwise. */
 typedef struct {
@@ -225,15 +229,26 @@ int lspr_gauss_legendre(int32_t n, double* t, double* w);
  * the interaction lists (direct pairs, expansion pairs) and the columns actually used, bytes of
  * the arrays the kernel must read and write once.  Names: "far" (expansions plus direct sums),
  * "p2m", "near" (near-singular corrections), "matvec" (one whole block product), "arnoldi"
- * (orthogonalisation of one GMRES step).  For "far", `items` counts interactions times
- * wavelengths: (direct target-node pairs + expansion target-box pairs) per launch times the
- * complex columns of that launch.  lspr_profile_query waits for the recorded events and returns
- * totals since the last reset; unknown names give zero launches.  on: 0 off, 1 all launches,
- * 2 far-field launches only ("far", "far64"; the fewest events in the timed stream). */
+ * (orthogonalisation of one GMRES step).  "far" (FP32 products) and "far64" (FP64) count, on
+ * the matrix-core path, the work the launch executes: 4 flops per used real column of each
+ * operator and direct (target, panel) pair, 4 (P+1)^2 per column and expansion (target, box)
+ * pair; bytes are the tile store (read once), the densities, moments and sums.  The kernel
+ * values and Taylor coefficients are computed once per geometry, not per launch, and are not
+ * counted (the vector-ALU kernel, which computes them on the fly, counts them too).  For "far",
+ * `items` counts interactions times wavelengths: (direct target-node pairs + expansion
+ * target-box pairs) per launch times the complex columns of that launch.  lspr_profile_query
+ * waits for the recorded events and returns totals since the last reset; unknown names give
+ * zero launches.  lspr_profile_query_width does the same for the launches of width_min ..
+ * width_max wavelengths (complex columns; scopes without a width count as 0).  on: 0 off,
+ * 1 all launches, 2 far-field launches only ("far", "far64"; the fewest events in the timed
+ * stream). */
 int lspr_profile_enable(int32_t on);
 int lspr_profile_reset(void);
 int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
                        double* bytes, double* items);
+int lspr_profile_query_width(const char* name, int32_t width_min, int32_t width_max,
+                             double* total_ms, int64_t* launches, double* flops, double* bytes,
+                             double* items);
 
 /* ------------------------------------------------------------------ request server
  * Continuous batching of independent solve requests (mixed meshes, wavelength sets and

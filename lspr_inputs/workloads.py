@@ -41,10 +41,12 @@ def _sphere_case(nu, radius, lambdas, eps_p=None):
 
 
 def sphere_512():
-    """Isolated silver sphere R = 10 nm, 512 panels, 380 nm, eps_p = -3.38+0.20i, dense FP64."""
+    """Isolated silver sphere R = 10 nm, 512 panels, 380 nm, eps_p = -3.38+0.20i, dense FP64,
+    with the integration settings of the paper's grid-convergence study (Table quadparams1:
+    K = 4, K_fine = 37, N_k = 9)."""
     surfs, lam, em, es = _sphere_case(8, 10.0, [380.0], eps_p=-3.38 + 0.20j)
     return Workload("sphere_R10_N512_lambda380_dense_fp64", surfs, lam, em, es,
-                    op=dict(k_far=4, k_fine=25, n_k=9, threshold=0.5, method="dense",
+                    op=dict(k_far=4, k_fine=37, n_k=9, threshold=0.5, method="dense",
                             precision="fp64"),
                     gmres=dict(tol=1e-8, restart=100, max_iter=1000))
 
@@ -127,13 +129,10 @@ def large_sensor(seed=4, nu_sphere=128, nu_blob=75, n_blobs=8, n_lambda=16):
                     gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3), seed=seed)
 
 
-def serving_stream(seed=5, n_requests=2000, rate_per_s=1.0, nu_range=(16, 128),
-                   blob_nu_range=(25, 75), max_blobs=4, max_lambda=64):
-    """Seeded Poisson request stream: (arrival_s, Workload) pairs, generated lazily.
-
-    Requests solve with FP32 products and FP64 residuals (iterative refinement): analytes at
-    sub-nanometre gaps make the systems ill-conditioned near resonance, where GMRES on FP32
-    products alone needs several times more iterations."""
+def serving_stream_params(seed=5, n_requests=2000, rate_per_s=1.0, nu_range=(16, 128),
+                          blob_nu_range=(25, 75), max_blobs=4, max_lambda=64):
+    """The draws of the seeded Poisson request stream, without meshes (cheap):
+    (arrival_s, k, nu, n_blobs, nu_blob, wavelengths) per request."""
     rng = np.random.default_rng(seed)
     t = 0.0
     for k in range(n_requests):
@@ -143,16 +142,33 @@ def serving_stream(seed=5, n_requests=2000, rate_per_s=1.0, nu_range=(16, 128),
         nub = int(rng.integers(blob_nu_range[0], blob_nu_range[1] + 1))
         nl = int(rng.integers(1, max_lambda + 1))
         lam = np.sort(rng.uniform(350.0, 420.0, nl))
-        sub = np.random.default_rng([seed, k])
-        surfs = [octasphere(nu, 10.0)] + (_place_blobs(sub, nb, nub, 10.0, (0.5, 3.0))
-                                          if nb else [])
-        em = np.full(nl, EPS_WATER + 0j)
-        es = np.concatenate([eps_silver_drude(lam)[:, None], np.full((nl, nb), 2.5 + 0j)], 1)
-        yield t, Workload(f"req{k}", surfs, lam, em, es,
-                          op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                                  p=8, theta=0.5, ncrit=0, precision="fp32_refine64"),
-                          gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3),
-                          seed=seed)
+        yield t, k, nu, nb, nub, lam
+
+
+def serving_request(seed, k, nu, nb, nub, lam):
+    """Request k of the stream from its draws (the blobs come from a generator of its own, so
+    requests can be built in any order or in parallel)."""
+    nl = len(lam)
+    sub = np.random.default_rng([seed, k])
+    surfs = [octasphere(nu, 10.0)] + (_place_blobs(sub, nb, nub, 10.0, (0.5, 3.0))
+                                      if nb else [])
+    em = np.full(nl, EPS_WATER + 0j)
+    es = np.concatenate([eps_silver_drude(lam)[:, None], np.full((nl, nb), 2.5 + 0j)], 1)
+    return Workload(f"req{k}", surfs, lam, em, es,
+                    op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
+                            p=8, theta=0.5, ncrit=0, precision="fp32_refine64"),
+                    gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3),
+                    seed=seed)
+
+
+def serving_stream(seed=5, n_requests=2000, **kw):
+    """Seeded Poisson request stream: (arrival_s, Workload) pairs, generated lazily.
+
+    Requests solve with FP32 products and FP64 residuals (iterative refinement): analytes at
+    sub-nanometre gaps make the systems ill-conditioned near resonance, where GMRES on FP32
+    products alone needs several times more iterations."""
+    for t, k, nu, nb, nub, lam in serving_stream_params(seed, n_requests, **kw):
+        yield t, serving_request(seed, k, nu, nb, nub, lam)
 
 
 WORKLOADS = {

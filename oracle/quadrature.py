@@ -3,9 +3,9 @@
 The paper gives the point counts of its triangle rules but not the points (section "Integral
 evaluation"; Tables 1 and 4): K = 1, 3 or 4 for far panels and K_fine = 19, 25 or 37 for
 near-singular ones.  These counts are those of Dunavant's symmetric rules (1982), so the
-oracle reads them as Dunavant's rules of degree 1, 2, 3 (far) and 9, 10 (fine), plus the
-7-point degree-5 rule of Radon.  The 37-point rule is not carried: the strict setting uses the
-25-point rule instead (a documented reading).
+oracle reads them as Dunavant's rules of degree 1, 2, 3 (far) and 9, 10, 13 (fine), plus the
+7-point degree-5 rule of Radon.  The 37-point rule is the fine rule of the paper's strict
+setting (grid-convergence study, Table quadparams1).
 
 A rule is returned as barycentric points b [n, 3] and weights w [n] summing to 1, so that
 integral over a triangle of f ~= Area * sum_g w_g f(sum_k b_gk v_k).
@@ -36,9 +36,19 @@ _ORBITS = {
          ("s3", 0.072757916845420, 0.141707219414880, 0.307939838764121),
          ("s3", 0.028327242531057, 0.025003534762686, 0.246672560639903),
          ("s3", 0.009421666963733, 0.009540815400299, 0.066803251012200)],
+    37: [("c", 0.052520923400802),
+         ("s2", 0.011280145209330, 0.009903630120591),
+         ("s2", 0.031423518362454, 0.062566729780852),
+         ("s2", 0.047072502504194, 0.170957326397447),
+         ("s2", 0.047363586536355, 0.541200855914337),
+         ("s2", 0.031167529045794, 0.771151009607340),
+         ("s2", 0.007975771465074, 0.950377217273082),
+         ("s3", 0.036848402728732, 0.094853828379579, 0.268794997058761),
+         ("s3", 0.017401463303822, 0.018100773278807, 0.291730066734288),
+         ("s3", 0.015521786839045, 0.022233076674090, 0.126357385491669)],
 }
 
-RULE_DEGREE = {1: 1, 3: 2, 4: 3, 7: 5, 19: 9, 25: 10}
+RULE_DEGREE = {1: 1, 3: 2, 4: 3, 7: 5, 19: 9, 25: 10, 37: 13}
 
 
 def triangle_rule(n_points: int):

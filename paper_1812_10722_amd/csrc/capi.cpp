@@ -245,7 +245,7 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     LSPR_REQUIRE(lspr::triangle_rule(op->k_far, b, w) && op->k_far <= 8, LSPR_E_INVALID,
              "k_far must be 1, 3, 4 or 7");
     LSPR_REQUIRE(lspr::triangle_rule(op->k_fine, b, w), LSPR_E_INVALID,
-             "k_fine must be one of 1, 3, 4, 7, 19, 25");
+             "k_fine must be one of 1, 3, 4, 7, 19, 25, 37");
     LSPR_REQUIRE(op->n_k >= 1 && op->n_k <= 64, LSPR_E_INVALID, "n_k must be in 1..64");
     LSPR_REQUIRE(op->threshold > 0.0, LSPR_E_INVALID, "threshold must be positive");
     LSPR_REQUIRE(op->method == LSPR_DENSE || op->method == LSPR_TREECODE, LSPR_E_INVALID,
@@ -261,6 +261,20 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     }
     LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
              "ncrit and m2p_min_panels must be >= 0");
+}
+
+void validate_gmres(const lspr_gmres_params& gm, int precision) {
+    LSPR_REQUIRE(gm.tol > 0.0 && gm.restart >= 1 && gm.restart <= 512 && gm.max_iter >= 1 &&
+                     gm.inner_tol >= 0.0 && gm.inner_tol < 1.0 &&
+                     (gm.precond == 0 || gm.precond == 1),
+                 LSPR_E_INVALID, "bad GMRES parameters");
+    if (precision == LSPR_FP32 || precision == LSPR_FP32_LEAD64)
+        LSPR_REQUIRE(gm.tol >= FP32_MIN_TOL, LSPR_E_INVALID,
+                     "tol below 1e-6 cannot be certified with FP32 products; use "
+                     "LSPR_FP32_REFINE64 (FP64 residuals) or LSPR_FP64");
+    if (precision == LSPR_FP32_REFINE64)
+        LSPR_REQUIRE(gm.inner_tol == 0.0 || gm.inner_tol >= FP32_MIN_TOL, LSPR_E_INVALID,
+                     "inner_tol below 1e-6 cannot be reached by the FP32 inner solves");
 }
 
 void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
@@ -357,9 +371,7 @@ bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
     const lspr_gmres_params* gm = &gmr;
     LSPR_REQUIRE(lambda_nm && eps_medium && eps_surface && e_field && gm && n_lambda >= 1,
                  LSPR_E_INVALID, "bad arguments");
-    LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1 &&
-                     gm->inner_tol >= 0.0 && gm->inner_tol < 1.0,
-                 LSPR_E_INVALID, "bad GMRES parameters");
+    validate_gmres(*gm, g.precision);
     const double e2 = e_field[0] * e_field[0] + e_field[1] * e_field[1] + e_field[2] * e_field[2];
     LSPR_REQUIRE(e2 > 0.0, LSPR_E_INVALID, "zero incident field");
     for (int k = 0; k < n_lambda; ++k)

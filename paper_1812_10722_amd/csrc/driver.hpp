@@ -31,6 +31,13 @@ constexpr int MAX_BATCH = 64;  // wavelengths per block matrix-vector product
 
 // Checks the operator parameters and the surface array shapes (throws Error).
 void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params* op);
+// Smallest relative residual a solve whose final residual is formed with FP32 products can
+// certify (the FP32 rounding of one product is about 1e-7 of its norm, and GMRES stalls a few
+// times above it near resonance): tol of LSPR_FP32 and LSPR_FP32_LEAD64, inner_tol of
+// LSPR_FP32_REFINE64.
+constexpr double FP32_MIN_TOL = 1e-6;
+// Checks GMRES parameters against the product precision of the solve (throws Error).
+void validate_gmres(const lspr_gmres_params& gm, int precision);
 // Host check of closed, consistently oriented, edge-manifold surfaces (throws Error, E_MESH).
 void validate_mesh_host(const lspr_surface* surfaces, int n_surf);
 

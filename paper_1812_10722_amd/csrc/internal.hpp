@@ -391,6 +391,7 @@ struct Geometry {
     // matrix-core tiles (FP32 geometries)
     int64_t n_tiles = 0;
     int64_t tile_steps = 0, max_chunk_steps = 0;  // K-steps in all, and of the busiest chunk
+    int64_t tile_elems = 0;  // elements of one tile store (the left factors of one precision)
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
     DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)

@@ -1484,14 +1484,21 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
         }
     }
     {
-        // direct pairs: per node 15 flops (difference, r^2, rsqrt, two weighted sums), 9 per
-        // pair (centroid difference, plane height, product), then 2 flops per used column of
-        // each operator; expansion pairs: about 10 flops per coefficient of the recurrence and
-        // 2 per coefficient and used column of each operator
-        const double f = double(g.p2p_pairs) * (15.0 * g.K + 9.0 + 4.0 * nc) +
-                         double(g.m2p_pairs) * (10.0 * g.n_terms + 4.0 * nc * g.n_terms);
-        prof::Scope sc(fp64 ? "far64" : "far", s, f, dens_bytes + mom_bytes + out_bytes,
-                       (double(g.p2p_pairs) * g.K + double(g.m2p_pairs)) * (nc / 2));
+        // executed work: 2 flops per used column of each operator and pair (direct: kernel
+        // value times density; expansion: per Taylor term, coefficient times moment).  The
+        // vector-ALU kernel also forms the kernel values (per node 15 flops: difference, r^2,
+        // rsqrt, two weighted sums; 9 per pair: centroid difference, plane height, product) and
+        // the coefficients (about 10 flops per term of the recurrence); on matrix cores those
+        // are geometry-only factors computed once at set-up, and the launch reads them instead
+        // (the tile store, once).
+        const bool pre = c.mfma && tiles_of<T>(g) != nullptr;
+        const double f = double(g.p2p_pairs) * (4.0 * nc + (pre ? 0.0 : 15.0 * g.K + 9.0)) +
+                         double(g.m2p_pairs) * g.n_terms * (4.0 * nc + (pre ? 0.0 : 10.0));
+        const double tile_bytes = pre ? double(g.tile_elems) * esz : 0.0;
+        prof::Scope sc(fp64 ? "far64" : "far", s, f,
+                       tile_bytes + dens_bytes + mom_bytes + out_bytes,
+                       (double(g.p2p_pairs) * g.K + double(g.m2p_pairs)) * (nc / 2),
+                       c.ncol / 2);
         if (c.mfma) {
             LSPR_REQUIRE(tiles_of<T>(g) != nullptr || (g.n_m2p == 0 && g.n_p2p == 0),
                          LSPR_E_INVALID, "matrix-core tiles were not built");
@@ -1687,6 +1694,7 @@ void build_tiles(Geometry& g, const TilePlan& P) {
                  "tile plan does not match the geometry");
     g.tile_steps = P.tile_steps;
     g.max_chunk_steps = P.max_chunk_steps;
+    g.tile_elems = P.aoff;
     const std::vector<int32_t>& order = P.order;
     const int64_t aoff = P.aoff;
     g.n_order = static_cast<int>(order.size());

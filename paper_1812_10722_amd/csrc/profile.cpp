@@ -2,6 +2,7 @@
 // the algorithmic flops and bytes of that launch.  Events are kept until the next reset.
 #include "profile.hpp"
 
+#include <climits>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -16,6 +17,7 @@ struct Rec {
     hipEvent_t a = nullptr, b = nullptr;
     int dev = 0;
     double flops = 0, bytes = 0, items = 0;
+    int width = 0;
     bool done = false;
 };
 
@@ -66,7 +68,7 @@ int start(const char* name, hipStream_t s) {
     return static_cast<int>(recs.size()) - 1;
 }
 
-void stop(int token, hipStream_t s, double flops, double bytes, double items) {
+void stop(int token, hipStream_t s, double flops, double bytes, double items, int width) {
     std::lock_guard<std::mutex> lk(mu);
     if (token < 0 || token >= static_cast<int>(recs.size())) return;
     Rec& r = recs[token];
@@ -74,6 +76,7 @@ void stop(int token, hipStream_t s, double flops, double bytes, double items) {
     r.flops = flops;
     r.bytes = bytes;
     r.items = items;
+    r.width = width;
     r.done = true;
 }
 
@@ -97,12 +100,18 @@ int lspr_profile_reset(void) {
 
 int lspr_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
                        double* bytes, double* items) {
+    return lspr_profile_query_width(name, 0, INT32_MAX, total_ms, launches, flops, bytes, items);
+}
+
+int lspr_profile_query_width(const char* name, int32_t width_min, int32_t width_max,
+                             double* total_ms, int64_t* launches, double* flops, double* bytes,
+                             double* items) {
     if (!name || !total_ms || !launches || !flops || !bytes || !items) return LSPR_E_INVALID;
     std::lock_guard<std::mutex> lk(lspr::prof::mu);
     double ms = 0, f = 0, by = 0, it = 0;
     int64_t n = 0;
     for (auto& r : lspr::prof::recs) {
-        if (!r.done || r.name != name) continue;
+        if (!r.done || r.name != name || r.width < width_min || r.width > width_max) continue;
         if (hipEventSynchronize(r.b) != hipSuccess) return LSPR_E_DEVICE;
         float t = 0.f;
         if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return LSPR_E_DEVICE;

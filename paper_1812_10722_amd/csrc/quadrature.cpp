@@ -3,7 +3,7 @@
 // The paper lists only the point counts of its triangle rules (section "Integral evaluation",
 // Tables 1 and 4): 1, 3 or 4 points for far panels and 19, 25 or 37 for near-singular ones.
 // These are the counts of Dunavant's symmetric rules (degrees 1, 2, 3, 9, 10, 13); the library
-// carries the published degree-1, 2, 3, 9 and 10 rules and Radon's 7-point degree-5 rule.
+// carries the published degree-1, 2, 3, 9, 10 and 13 rules and Radon's 7-point degree-5 rule.
 // Each rule is stored as symmetric orbits of barycentric coordinates.
 #include <cmath>
 
@@ -35,6 +35,18 @@ const Orbit kRule25[] = {
     {6, 0.072757916845420, 0.141707219414880, 0.307939838764121},
     {6, 0.028327242531057, 0.025003534762686, 0.246672560639903},
     {6, 0.009421666963733, 0.009540815400299, 0.066803251012200}};
+// degree 13: the strict near-singular rule of the paper's grid-convergence study
+const Orbit kRule37[] = {
+    {1, 0.052520923400802, 0, 0},
+    {3, 0.011280145209330, 0.009903630120591, 0.495048184939705},
+    {3, 0.031423518362454, 0.062566729780852, 0.468716635109574},
+    {3, 0.047072502504194, 0.170957326397447, 0.414521336801277},
+    {3, 0.047363586536355, 0.541200855914337, 0.229399572042831},
+    {3, 0.031167529045794, 0.771151009607340, 0.114424495196330},
+    {3, 0.007975771465074, 0.950377217273082, 0.024811391363459},
+    {6, 0.036848402728732, 0.094853828379579, 0.268794997058761},
+    {6, 0.017401463303822, 0.018100773278807, 0.291730066734288},
+    {6, 0.015521786839045, 0.022233076674090, 0.126357385491669}};
 
 void expand(const Orbit* o, int n_orbits, std::vector<double>& bary, std::vector<double>& w) {
     bary.clear();
@@ -83,6 +95,7 @@ bool triangle_rule(int n, std::vector<double>& bary, std::vector<double>& w) {
         }
         case 19: expand(kRule19, 6, bary, w); return true;
         case 25: expand(kRule25, 6, bary, w); return true;
+        case 37: expand(kRule37, 10, bary, w); return true;
         default: return false;
     }
 }

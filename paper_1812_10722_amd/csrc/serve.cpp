@@ -276,9 +276,7 @@ int lspr_server_submit_charges(lspr_server* sv, const lspr_surface* surfaces, in
                              std::isfinite(pos[3 * k + 2]),
                          LSPR_E_INVALID, "charges must be finite and inside a listed surface");
         lspr::validate_op(surfaces, n_surf, op);
-        LSPR_REQUIRE(gm->tol > 0.0 && gm->restart >= 1 && gm->restart <= 512 && gm->max_iter >= 1 &&
-                     gm->inner_tol >= 0.0 && gm->inner_tol < 1.0,
-                     LSPR_E_INVALID, "bad GMRES parameters");
+        lspr::validate_gmres(*gm, op->precision);
         auto r = std::make_shared<Request>();
         r->S = n_surf;
         for (int k = 0; k < n_surf; ++k) {

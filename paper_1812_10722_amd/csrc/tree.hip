@@ -151,6 +151,7 @@ struct ListParams {
     int min_panels;
     int S;
     const int32_t* roots;  // [S]
+    int32_t* overflow;     // set when a walk would outgrow its stack (checked by the host)
 };
 
 // Interaction lists of one chunk against every surface's tree, own surface first.  A box is
@@ -240,7 +241,12 @@ __device__ void walk_sub(const Box* __restrict__ boxes, const Chunk& T, int q,
             L.pp += static_cast<int64_t>(nt) * (B.end - B.start);
             L.flags |= 2 | 4;
         } else {
-            if (top + B.nchild > STACK) continue;  // cannot happen for depth <= 16; stay safe
+            // at most 7 pending siblings per level below MAX_LEVEL, so the stack cannot fill;
+            // if it ever did, the lists would be incomplete: report it instead of dropping pairs
+            if (top + B.nchild > STACK) {
+                atomicOr(lp.overflow, 1);
+                return;
+            }
             for (int k = B.nchild - 1; k >= 0; --k) stack[top++] = B.child + k;
         }
     }
@@ -330,6 +336,7 @@ struct NearParams {
     double inv_thr;
     int S;
     const int32_t* roots;
+    int32_t* overflow;  // set when a walk would outgrow its stack (checked by the host)
 };
 
 // Near-singular source panels of every target panel, all surfaces, ascending index order.
@@ -363,7 +370,11 @@ __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__
                     }
                 }
             } else {
-                if (top + B.nchild > STACK) continue;
+                if (top + B.nchild > STACK) {  // cannot happen below MAX_LEVEL; reported
+                    atomicOr(np.overflow, 1);
+                    if (!fill) cnt[i] = 0;
+                    return;
+                }
                 for (int q = B.nchild - 1; q >= 0; --q) stack[top++] = B.child + q;
             }
         }
@@ -560,10 +571,13 @@ void build_tree(Geometry& g) {
 void build_lists(Geometry& g) {
     hipStream_t s = g.stream;
     const int nc = g.n_chunks;
-    DevBuf<int32_t> roots(g.S);
-    LSPR_HIP(hipMemcpyAsync(roots.p, g.surf_root.data(), g.S * 4, hipMemcpyHostToDevice, s));
+    // surface roots, then the overflow flag (zero)
+    std::vector<int32_t> roots_h(g.surf_root.begin(), g.surf_root.end());
+    roots_h.push_back(0);
+    DevBuf<int32_t> roots(g.S + 1);
+    LSPR_HIP(hipMemcpyAsync(roots.p, roots_h.data(), (g.S + 1) * 4, hipMemcpyHostToDevice, s));
     ListParams lp{g.method == LSPR_DENSE ? 0.0 : g.theta, 1.0 / g.threshold, g.m2p_min_panels,
-                  g.S, roots.p};
+                  g.S, roots.p, roots.p + g.S};
     DevBuf<int32_t> mc(nc), pc(nc);
     g.m2p_self.alloc(nc);
     g.p2p_self.alloc(nc);
@@ -579,6 +593,7 @@ void build_lists(Geometry& g) {
     LSPR_HIP(hipGetLastError());
     std::vector<int32_t> mh(nc), ph(nc);
     std::vector<int64_t> prh(2 * nc);
+    int32_t overflow = 0;
     g.m2p_self_h.resize(nc);
     g.p2p_self_h.resize(nc);
     Downloads down(s);
@@ -587,7 +602,9 @@ void build_lists(Geometry& g) {
     down.add(prh.data(), pairs.p, 2 * nc);
     down.add(g.m2p_self_h.data(), g.m2p_self.p, nc);
     down.add(g.p2p_self_h.data(), g.p2p_self.p, nc);
+    down.add(&overflow, lp.overflow, 1);
     down.fetch();
+    LSPR_REQUIRE(overflow == 0, LSPR_E_DEVICE, "interaction-list walk outgrew its stack");
     std::vector<int64_t> mo(nc + 1, 0), po(nc + 1, 0);
     g.p2p_pairs = 0;
     g.m2p_pairs = 0;
@@ -637,15 +654,17 @@ void build_near_table(Geometry& g) {
     const std::vector<double> fine_h = rule_rows(g.Kf);
     std::vector<double> t, w;
     gauss_legendre(g.Nk, t, w);
-    DevBuf<int32_t> roots(g.S);
+    std::vector<int32_t> roots_h(g.surf_root.begin(), g.surf_root.end());
+    roots_h.push_back(0);  // overflow flag
+    DevBuf<int32_t> roots(g.S + 1);
     DevBuf<double> fine(fine_h.size()), t_d(t.size()), w_d(w.size());
     Uploads up(s);
-    up.add(roots.p, g.surf_root.data(), g.S);
+    up.add(roots.p, roots_h.data(), g.S + 1);
     up.add(fine.p, fine_h.data(), fine_h.size());
     up.add(t_d.p, t.data(), t.size());
     up.add(w_d.p, w.data(), w.size());
     up.flush();
-    NearParams np{1.0 / g.threshold, g.S, roots.p};
+    NearParams np{1.0 / g.threshold, g.S, roots.p, roots.p + g.S};
     DevBuf<int64_t> cnt(N + 1);
     const dim3 grid((N + TPB - 1) / TPB), blk(TPB);
     hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, false,
@@ -653,8 +672,11 @@ void build_near_table(Geometry& g) {
     LSPR_HIP(hipGetLastError());
     scan_exclusive(cnt.p, cnt.p, N, s);
     int64_t nnz = 0;
+    int32_t overflow = 0;
     LSPR_HIP(hipMemcpyAsync(&nnz, cnt.p + N, 8, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipMemcpyAsync(&overflow, np.overflow, 4, hipMemcpyDeviceToHost, s));
     LSPR_HIP(hipStreamSynchronize(s));
+    LSPR_REQUIRE(overflow == 0, LSPR_E_DEVICE, "near-singular walk outgrew its stack");
     LSPR_REQUIRE(nnz < (1ll << 31), LSPR_E_INVALID, "near-singular table too large");
     g.n_near = nnz;
     g.near_col.alloc(std::max<int64_t>(nnz, 1));

@@ -296,6 +296,11 @@ _lib.lspr_profile_enable.argtypes = [C.c_int32]
 _lib.lspr_profile_reset.restype = C.c_int
 _lib.lspr_profile_reset.argtypes = []
 _lib.lspr_profile_query.restype = C.c_int
+_lib.lspr_profile_query_width.restype = C.c_int
+_lib.lspr_profile_query_width.argtypes = [C.c_char_p, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
 _lib.lspr_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
@@ -315,6 +320,17 @@ def lspr_profile_query(name: str) -> dict:
     n = C.c_int64()
     _check(_lib.lspr_profile_query(name.encode(), C.byref(ms), C.byref(n), C.byref(fl),
                                    C.byref(by), C.byref(it)), "lspr_profile_query")
+    return {"total_ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value,
+            "items": it.value}
+
+
+def lspr_profile_query_width(name: str, width_min: int, width_max: int) -> dict:
+    """As lspr_profile_query, for the launches of width_min..width_max wavelengths."""
+    ms, fl, by, it = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    n = C.c_int64()
+    _check(_lib.lspr_profile_query_width(name.encode(), int(width_min), int(width_max),
+                                         C.byref(ms), C.byref(n), C.byref(fl), C.byref(by),
+                                         C.byref(it)), "lspr_profile_query_width")
     return {"total_ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value,
             "items": it.value}
 

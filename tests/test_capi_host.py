@@ -36,9 +36,10 @@ def test_binding_wraps_every_declared_symbol():
         assert hasattr(lspr._lib, n)
 
 
-@pytest.mark.parametrize("n,deg", [(1, 1), (3, 2), (4, 3), (7, 5), (19, 9), (25, 10)])
+@pytest.mark.parametrize("n,deg", [(1, 1), (3, 2), (4, 3), (7, 5), (19, 9), (25, 10), (37, 13)])
 def test_library_triangle_rules_are_exact(n, deg):
-    """The library's own tables (independent of the oracle's) integrate monomials exactly."""
+    """The library's own tables (independent of the oracle's) integrate monomials exactly to
+    their degree, and no further (closed form a! b! / (a + b + 2)! on the unit triangle)."""
     from paper_1812_10722_amd.lspr import lspr_triangle_rule
     bary, w = lspr_triangle_rule(n)
     assert abs(w.sum() - 1) < 1e-14 and np.allclose(bary.sum(1), 1)
@@ -48,6 +49,10 @@ def test_library_triangle_rules_are_exact(n, deg):
             b = d - a
             exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
             assert abs(0.5 * np.sum(w * x ** a * y ** b) / exact - 1) < 1e-13
+    d = deg + 1
+    miss = max(abs(0.5 * np.sum(w * x ** a * y ** (d - a)) * math.factorial(d + 2)
+                   / (math.factorial(a) * math.factorial(d - a)) - 1) for a in range(d + 1))
+    assert miss > 1e-8  # the stated degree is the true one
 
 
 def test_library_gauss_legendre():

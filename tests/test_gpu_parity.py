@@ -41,18 +41,20 @@ def sensor_and_blob(nu_s=6, nu_b=5, seed=1):
 
 
 # ----------------------------------------------------------------------------- operator parity
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
-def test_apply_dense_matches_oracle_matrix(lib, precision, tol):
+@pytest.mark.parametrize("precision,tol,k_fine", [("fp64", 1e-12, 19), ("fp32", 2e-6, 19),
+                                                  ("fp64", 1e-12, 37)])
+def test_apply_dense_matches_oracle_matrix(lib, precision, tol, k_fine):
     """y = A x with every far pair summed directly equals the oracle's dense matrix product
-    (FP64: rounding only; FP32: single-precision sums with compensated accumulation)."""
+    (FP64: rounding only; FP32: single-precision sums with compensated accumulation), with the
+    relaxed (19-point) and the strict (37-point, Table quadparams1) near-singular rule."""
     surfs = sensor_and_blob()
-    v, t, sid, V, K, g = _dense_system(surfs, None, None)
+    v, t, sid, V, K, g = _dense_system(surfs, None, None, k_fine=k_fine)
     rng = np.random.default_rng(7)
     ncol = 3
     eps_m = np.array([1.7733, 1.80 + 0.01j, 1.0])
     eps_s = np.array([[-3.38 + 0.2j, 2.5], [-2.0 + 0.5j, 2.7 + 0.3j], [4.0, 1.5]])
     x = _rand_x(rng, ncol, len(t))
-    geo = lib.Geometry(surfs, method="dense", precision=precision, k_far=4, k_fine=19)
+    geo = lib.Geometry(surfs, method="dense", precision=precision, k_far=4, k_fine=k_fine)
     y = geo.apply(torch.as_tensor(x).cuda(), eps_m, eps_s).cpu().numpy()
     for c in range(ncol):
         A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m[c], eps_s[c], [0, 0, 1.0])
@@ -131,12 +133,14 @@ def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol, 
 # ----------------------------------------------------------------------------- full solves
 def test_sphere_512_dense_fp64_matches_oracle(lib):
     """The 512-panel silver sphere (lambda = 380 nm) solved by the GPU dense FP64 path equals the
-    oracle's LU solution to the GMRES tolerance."""
+    oracle's LU solution to the GMRES tolerance, at the integration settings of the paper's
+    grid-convergence study (Table quadparams1: K = 4, K_fine = 37, N_k = 9)."""
     w = workload("sphere_512")
+    assert (w.op["k_far"], w.op["k_fine"], w.op["n_k"]) == (4, 37, 9)
     v, t = w.surfaces[0]
     ref = oracle.solve(v, t, np.zeros(len(t), int), w.lambdas, w.eps_medium, w.eps_surface,
-                       w.e_field, k_far=4, k_fine=25, n_k=9, threshold=0.5)
-    geo = lib.Geometry(w.surfaces, method="dense", precision="fp64", k_far=4, k_fine=25, n_k=9)
+                       w.e_field, k_far=4, k_fine=37, n_k=9, threshold=0.5)
+    geo = lib.Geometry(w.surfaces, op=lib.op_params(**w.op))
     out = geo.solve(w.lambdas, w.eps_medium, w.eps_surface, w.e_field, tol=1e-10, restart=100,
                     max_iter=1000, precond=1, want_fields=True)
     assert out["converged"] and out["rel_resid"][0] < 1e-10
@@ -263,6 +267,13 @@ def test_bad_inputs_are_rejected(lib):
     geo = lib.Geometry([(v, t)], method="dense", precision="fp64")
     with pytest.raises(lib.LsprError):
         geo.solve([380.0], [1.7733], [[0.0]])  # eps_surface = 0
+    # FP32 products cannot certify a residual below 1e-6: such a request is refused up front
+    for prec in ("fp32", "fp32_lead64"):
+        g32 = lib.Geometry([(v, t)], method="dense", precision=prec)
+        with pytest.raises(lib.LsprError) as e:
+            g32.solve([380.0], [1.7733], [[-3.38 + 0.2j]], tol=1e-7)
+        assert e.value.code == lib.LSPR_E_INVALID
+        assert g32.solve([380.0], [1.7733], [[-3.38 + 0.2j]], tol=1e-6)["converged"]
 
 
 def test_refinement_reaches_fp64_solution(lib):

@@ -54,6 +54,77 @@ def test_peak_and_shift_match_oracle(lib):
     assert peaks["with"] > peaks["alone"]  # analytes of higher index red-shift the peak
 
 
+def _placed(axis, gap=1.0, nu_s=8, nu_b=5, radius=8.0, seed=2):
+    """Sensor and two analytes at +-axis (the second turned 180 degrees about an axis normal to
+    the placement axis, so the pair is mirror-like)."""
+    rng = np.random.default_rng(seed)
+    bv, bt = perturbed_ellipsoid(nu_b, (1.5, 4.0, 1.5), rng)
+    d = {"x": np.array([1.0, 0, 0]), "y": np.array([0, 1.0, 0]), "z": np.array([0, 0, 1.0])}[axis]
+    flip = np.diag([-1.0, -1.0, 1.0]) if axis == "x" else np.diag([1.0, -1.0, -1.0])
+    return [octasphere(nu_s, radius), (place_at_gap(bv, d, radius, gap), bt),
+            (place_at_gap(bv @ flip, -d, radius, gap), bt)]
+
+
+PLACEMENTS = [("x", (0.0, 0.0, 1.0)), ("y", (0.0, 0.0, 1.0)), ("z", (1.0, 0.0, 0.0)),
+              ("z", (0.0, 1.0, 0.0))]
+F3_LAMBDA = wavelength_grid(377.0, 389.0, 7)
+
+
+@pytest.fixture(scope="module")
+def placement_refs():
+    """Oracle (dense FP64, LU) spectra of the sensor alone and with the analytes, per field
+    direction and placement."""
+    out = {}
+    for axis, e in PLACEMENTS:
+        surfs = _placed(axis)
+        for label, ss in (("alone", surfs[:1]), ("with", surfs)):
+            if (label, axis, e) in out or (label == "alone" and ("alone", e) in out):
+                continue
+            em, es = _spectrum(ss, F3_LAMBDA)
+            v, t, sid = merge_surfaces(ss)
+            r = oracle.solve(v, t, sid, F3_LAMBDA, em, es, list(e), k_far=4, k_fine=19)
+            out[("alone", e) if label == "alone" else ("with", axis, e)] = r
+    return out
+
+
+@pytest.mark.parametrize("axis,e_field", PLACEMENTS)
+@pytest.mark.parametrize("method,precision,bar,peak_bar", [("dense", "fp64", 1e-6, 1e-4),
+                                                           ("treecode", "fp32_lead64", 1e-4, 5e-3)])
+def test_placement_and_polarisation_match_oracle(lib, placement_refs, axis, e_field, method,
+                                                 precision, bar, peak_bar):
+    """Section "Results", sensing experiments: analytes on +-x or +-y with the field along z,
+    and on +-z with the field along x or y.  The library's study driver (resonance shift of the
+    sensor's spectrum, alone and with the analytes) against the oracle on the same mesh:
+    C_ext (sensor and total) within the path's bar at every wavelength, the dipole moments
+    within 10x that bar of their largest component, and the peak shift within peak_bar nm
+    (the parabola vertex moves by about 6 x the relative C_ext error on this 2 nm grid)."""
+    from paper_1812_10722_amd import studies
+    surfs = _placed(axis)
+    em, es = _spectrum(surfs, F3_LAMBDA)
+    kw = dict(method=method, precision=precision, p=8, theta=0.5, k_fine=19)
+    gm = lib.gmres_params(tol=1e-10 if precision == "fp64" else 1e-6, restart=100, max_iter=2000)
+    geo = lib.Geometry(surfs, **kw)
+    try:
+        got = geo.solve(F3_LAMBDA, em, es, list(e_field), gmres=gm)
+    finally:
+        geo.close()
+    ref = placement_refs[("with", axis, tuple(e_field))]
+    assert got["converged"]
+    for key in ("cext_sensor", "cext_total"):
+        rel = np.abs(got[key] / ref[key] - 1)
+        assert rel.max() < bar, (key, rel.max())
+    for key in ("p_sensor", "p_total"):
+        err = np.abs(got[key] - ref[key]).max() / np.abs(ref[key]).max()
+        assert err < 10 * bar, (key, err)
+    sh = studies.resonance_shift(surfs[0], surfs[1:], F3_LAMBDA, em, es[:, 0], 2.5,
+                                 e_field=list(e_field), gmres=gm, **kw)
+    ref_alone = placement_refs[("alone", tuple(e_field))]
+    shift_ref = (lib.lspr_resonance_peak(F3_LAMBDA, ref["cext_sensor"])[0]
+                 - lib.lspr_resonance_peak(F3_LAMBDA, ref_alone["cext_sensor"])[0])
+    assert sh["converged"]
+    assert abs(sh["shift"] - shift_ref) < peak_bar, (sh["shift"], shift_ref)
+
+
 def test_shift_decreases_with_analyte_distance(lib):
     """Treecode FP32 path, sphere of 8192 panels and two analytes of 800 panels at 0.5, 1, 2 nm:
     the red shift of the resonance is positive and falls with distance."""

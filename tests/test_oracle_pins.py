@@ -158,6 +158,41 @@ def test_double_layer_is_minus_solid_angle_over_4pi():
         assert abs(K[li].sum() + 0.5) < 5e-3
 
 
+@pytest.mark.parametrize("k_fine,bound", [(19, 5e-3), (37, 2e-4)])
+def test_near_singular_length_is_the_source_panels(k_fine, bound):
+    """Section "Integral evaluation": a panel is integrated with the fine rule when the
+    collocation point lies within 2 L of it, L the representative length of the *integrated*
+    (source) triangle.  On a mesh with a sharp jump in panel size (a finely meshed sphere
+    0.5 nm from a coarse one) the fine-surface targets see large coarse panels well inside
+    2 L_source but outside 2 L_target.  Against the exact Van Oosterom-Strackee solid angle,
+    K_ij = -Omega_ij / 4 pi, every such pair meets the bound only if the fine rule was used;
+    the far rule misses it by an order of magnitude (so measuring the distance in the
+    target's L would fail this test)."""
+    coarse = octasphere(4, 5.0)
+    fine = octasphere(16, 1.5, center=(0.0, 0.0, 5.0 + 0.5 + 1.5))
+    v, t, sid = merge_surfaces([coarse, fine])
+    g = oracle.panel_geometry(v, t)
+    fi = np.flatnonzero(sid == 1)
+    rows = fi[np.argsort(g["centroid"][fi, 2])[:12]]  # fine panels facing the coarse sphere
+    _, K = oracle.operator_rows(v, t, rows, k_far=4, k_fine=k_fine, n_k=9, threshold=0.5)
+    _, K_far = oracle.operator_rows(v, t, rows, k_far=4, k_fine=k_fine, n_k=9, threshold=1e12)
+    ci = np.flatnonzero(sid == 0)
+    assert g["L"][ci].min() > 5 * g["L"][fi].max()  # the size jump the test relies on
+    worst = worst_far = 0.0
+    pairs = 0
+    for li, i in enumerate(rows):
+        d = np.linalg.norm(g["centroid"][ci] - g["centroid"][i], axis=1)
+        sel = ci[(d <= 2 * g["L"][ci]) & (d > 2 * g["L"][i])]
+        pairs += len(sel)
+        exact = np.array([-solid_angle(v[t[j]], g["centroid"][i]) / (4 * np.pi) for j in sel])
+        scale = np.abs(exact).max()
+        worst = max(worst, np.abs(K[li, sel] - exact).max() / scale)
+        worst_far = max(worst_far, np.abs(K_far[li, sel] - exact).max() / scale)
+    assert pairs >= 100
+    assert worst < bound, worst
+    assert worst_far > 10 * bound, worst_far
+
+
 @pytest.fixture(scope="module")
 def graded_ops():
     out = {}
