@@ -328,6 +328,8 @@ def main():
                          "fp32_lead64 (default: the library's)")
     ap.add_argument("--tol", type=float, default=None, help="override the GMRES tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run a workload's fixed treecode settings instead of the autotuner's")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests of the serving leg (default 16, or 200 with --serving-only; "
                          "0 skips it)")
@@ -378,6 +380,30 @@ def main():
     lam, em, es, ef = w.lambdas, w.eps_medium, w.eps_surface, w.e_field
     dev = [(torch.as_tensor(v).cuda(), torch.as_tensor(t).cuda()) for v, t in w.surfaces]
     stream = torch.cuda.current_stream()
+    tuned = None
+    if w.tune and not args.no_autotune:
+        # untimed: the library's autotuner picks P, theta, N_crit and the kernel schedule under
+        # the workload's bound, at the middle wavelength's permittivities
+        mid = len(lam) // 2
+        t0 = time.perf_counter()
+        top, entries, ok = lspr.lspr_autotune(dev, w.tune["n_cols"], em[mid], es[mid],
+                                              max_rel_err=w.tune["max_rel_err"],
+                                              op=lspr.op_params(**op))
+        tuned = {"seconds": time.perf_counter() - t0, "met_bound": bool(ok),
+                 "max_rel_err": w.tune["max_rel_err"], "n_cols": w.tune["n_cols"],
+                 "p": top.p, "theta": top.theta, "ncrit": top.ncrit,
+                 "m2p_min_panels": top.m2p_min_panels, "flags": top.flags,
+                 "candidates": len(entries),
+                 "chosen": next((e for e in entries if e["p"] == top.p and e["ncrit"] == top.ncrit
+                                 and abs(e["theta"] - top.theta) < 1e-12
+                                 and e["m2p_min_panels"] == top.m2p_min_panels
+                                 and e["flags"] == top.flags), None)}
+        op.update(p=top.p, theta=top.theta, ncrit=top.ncrit, m2p_min_panels=top.m2p_min_panels,
+                  split_operators=not (top.flags & lspr.LSPR_NO_SPLIT_OPERATORS),
+                  stream_narrow=bool(top.flags & lspr.LSPR_STREAM_NARROW))
+        log(f"[bench] autotune: P={top.p} theta={top.theta} ncrit={top.ncrit} "
+            f"m2p_min_panels={top.m2p_min_panels} flags={top.flags} ({tuned['seconds']:.1f} s, "
+            f"{len(entries)} candidates)")
 
     def step(op_kw, lam_, em_, es_, gm_kw):
         g = lspr.Geometry(dev, validate=False, **op_kw)
@@ -523,6 +549,7 @@ def main():
                        for n in ("arnoldi", "near") if prof[n]["total_ms"] > 0},
         "lists": {k: int(info[k]) for k in ("n_boxes", "n_m2p", "n_p2p_ranges", "p2p_pairs",
                                             "m2p_pairs", "n_near", "n_terms", "ncrit")},
+        "autotune": tuned,
     }
     n_srv = 16 if args.serving_requests is None else args.serving_requests
     if n_srv > 0:

@@ -53,7 +53,7 @@ enum lspr_status {
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
 enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2, LSPR_FP32_LEAD64 = 3 };
-enum lspr_flags { LSPR_NO_MATRIX_CORES = 1, LSPR_NO_SPLIT_OPERATORS = 2 };
+enum lspr_flags { LSPR_NO_MATRIX_CORES = 1, LSPR_NO_SPLIT_OPERATORS = 2, LSPR_STREAM_NARROW = 4 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
  * counter-clockwise seen from outside (outward right-hand normal, as the paper's dipole
@@ -75,7 +75,9 @@ typedef struct {
  *   threshold a source panel j is near-singular for collocation point x_i when
  *             |x_i - c_j| <= L_j / threshold, L = sqrt(2 Area) (paper: 0.5, i.e. 2L)
  *   method    LSPR_DENSE (every far pair summed directly) or LSPR_TREECODE
- *   p         Taylor expansion order of the treecode: 2, 4, 6, 8 or 10 (paper: 6 or 15)
+ *   p         Taylor expansion order of the treecode: 2, 4, 6, 8, 10, 12 or 15 (paper: 6,
+ *             and 15 for its grid-convergence study); orders above 10 run only on matrix cores
+ *             (their tiles must fit the tile budget, else LSPR_E_NOMEM)
  *   theta     multipole acceptance parameter, 0 < theta < 1 (paper: 0.5)
  *   ncrit     maximum panels per octree leaf; 0 selects the library default
  *   precision LSPR_FP64 or LSPR_FP32 for the far-field sums (P2P, P2M, M2P).  Singular and
@@ -97,11 +99,14 @@ typedef struct {
  *             precomputes the geometry-only factors of every expansion and direct tile in the
  *             precision(s) it computes in (about 1.7 GB at 32768 panels, P = 8, in FP32; twice
  *             that in FP64) and runs all products on matrix cores.  Tiles are kept while they
- *             fit in 40 % of the free device memory (FP32 first, then FP64); a precision whose
+ *             fit in 55 % of the free device memory (FP32 first, then FP64); a precision whose
  *             tiles do not fit uses the vector-ALU kernel, which computes the same sums on the
  *             fly.
  *             bit 1: FP32 matrix-core products keep both operators in one workgroup instead of
- *             one workgroup per operator (same sums; a tuning alternative). */
+ *             one workgroup per operator (same sums; a tuning alternative).
+ *             bit 2: products of up to 16 wavelengths stream every wave's operands from
+ *             memory instead of staging each left factor in LDS for the workgroup (identical
+ *             sums; a tuning alternative, faster for FP64 products of up to 8 wavelengths). */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;
@@ -338,33 +343,39 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
                            const lspr_op_params* op, const lspr_gmres_params* gm,
                            int64_t* bytes);
 
-/* Autotuner for the treecode parameters of a mesh (the paper picks P and theta by hand per
- * experiment, section "Acceleration strategies", Tables treeparams1/2): expansion order
- * P in {4, 6, 8, 10}, acceptance parameter theta in {0.4, 0.5, 0.6, 0.7} and leaf size N_crit
- * in {8, 16, 32}.  The truncation error of a candidate is measured apart from rounding: the
+/* Autotuner for the treecode parameters and kernel schedule of a mesh (the paper picks P and
+ * theta by hand per experiment, section "Acceleration strategies", Tables treeparams1/2).
+ * Stage 1: expansion order P in {4, 6, 8, 10, 12, 15}, acceptance parameter theta in {0.4,
+ * 0.5, 0.6, 0.7} and leaf size N_crit in {8, 16, 32} (above 100000 panels theta in {0.5, 0.6}
+ * and N_crit = 16).  The truncation error of a candidate is measured apart from rounding: the
  * relative 2-norm difference between its FP64 product of the system matrix (first
- * wavelength's permittivities, a fixed pseudo-random complex vector) and a reference product
- * (the dense FP64 product for N <= 40000 panels, otherwise the treecode at P = 10, theta =
- * 0.3).  For each (theta, N_crit) the smallest P that meets max_rel_err is timed: n_cols
- * columns in the product precision of op (FP32 unless op->precision is LSPR_FP64), fastest of
- * three after one warm-up, HIP events on `stream`.  The fastest candidate that meets the bound
- * is written to op->p, op->theta, op->ncrit (op->method becomes LSPR_TREECODE; the other
- * fields are kept and used for every candidate).
+ * wavelength's permittivities, a fixed pseudo-random complex vector) and the dense FP64
+ * product (every far pair summed directly).  For each (theta, N_crit) the smallest P that meets
+ * max_rel_err is timed: n_cols columns in the product precision of op (FP32 unless
+ * op->precision is LSPR_FP64), fastest of three after one warm-up, HIP events on `stream`.
+ * Stage 2, on the fastest of those: the kernel schedule, timed the same way: m2p_min_panels at
+ * half and twice its default ((P+1)^2; the error is checked again), both operators in one
+ * workgroup (LSPR_NO_SPLIT_OPERATORS, FP32 products), and for n_cols <= 16 the streamed
+ * narrow kernel (LSPR_STREAM_NARROW).  The fastest candidate that meets the bound is written
+ * to op->p, op->theta, op->ncrit, op->m2p_min_panels and op->flags (op->method becomes
+ * LSPR_TREECODE; the other fields are kept and used for every candidate).
  *   surfaces     device pointers, as lspr_geometry_create
  *   n_cols       columns of the timed product, 1..64
  *   eps_medium   host [1]; eps_surface host [n_surf]
  *   entries      host [max_entries] or null: every candidate tried, in order (ms_per_product
  *                -1 when it was not timed); *n_entries receives their number (it may exceed
  *                max_entries, the rest is not stored)
- * Device memory: the reference (dense FP64 tiles: 16 N^2 bytes) and one candidate geometry at
- * a time.  LSPR_E_NOCONV when no candidate meets the bound (op then holds the most accurate
- * one); LSPR_E_INVALID for bad arguments. */
+ * Device memory: the reference geometry (dense FP64 tiles, 16 N^2 bytes, when they fit) and one
+ * candidate geometry at a time.  LSPR_E_NOCONV when no candidate meets the bound (op then holds
+ * the most accurate one); LSPR_E_INVALID for bad arguments. */
 typedef struct {
     int32_t p;
     int32_t ncrit;
     double theta;
     double rel_err;         /* FP64 product against the reference */
     double ms_per_product;  /* n_cols columns in the timed precision, or -1 */
+    int32_t m2p_min_panels; /* 0: the default */
+    int32_t flags;          /* lspr_flags of the candidate */
 } lspr_tune_entry;
 
 int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,

@@ -27,6 +27,9 @@ class Workload:
     op: dict = field(default_factory=dict)      # quadrature / treecode / precision parameters
     gmres: dict = field(default_factory=dict)   # tol, restart, max_iter
     seed: int | None = None
+    # treecode parameters and kernel schedule chosen by the library's autotuner before the
+    # solve, under this bound on the FP64 product error at this batch width (None: op as given)
+    tune: dict | None = None
 
     @property
     def n_panels(self) -> int:
@@ -70,7 +73,8 @@ def sphere_32k_sweep(n_lambda=64, nu=64, p=8, theta=0.5, tol=1e-5):
 
 
 def sensor_two_analytes(seed=3, nu_sphere=71, nu_blob=61, gap=1.0, n_lambda=32, axis="z"):
-    """Sphere R = 8 nm plus two perturbed 14x4x4 nm ellipsoids at +/- axis, 1 nm gap, eps 2.5."""
+    """Sphere R = 8 nm plus two perturbed 14x4x4 nm ellipsoids at +/- axis, 1 nm gap, eps 2.5;
+    FP32 products inside FP64-residual refinement, treecode settings from the autotuner."""
     rng = np.random.default_rng(seed)
     sphere = octasphere(nu_sphere, 8.0)
     bv, bt = perturbed_ellipsoid(nu_blob, (2.0, 7.0, 2.0), rng)  # long axis along y
@@ -86,8 +90,9 @@ def sensor_two_analytes(seed=3, nu_sphere=71, nu_blob=61, gap=1.0, n_lambda=32, 
     return Workload(f"sensor_R8_N{len(sphere[1])}+2x{len(bt)}_gap{gap}_{axis}_sweep{n_lambda}",
                     [sphere, (b1, bt), (b2, bt)], lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
-                            p=8, theta=0.5, ncrit=0, precision="fp32"),
-                    gmres=dict(tol=1e-6, restart=60, max_iter=600), seed=seed)
+                            p=8, theta=0.5, ncrit=0, precision="fp32_refine64"),
+                    gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3), seed=seed,
+                    tune=dict(max_rel_err=1e-6, n_cols=n_lambda))
 
 
 def _place_blobs(rng, n_blobs, nu_blob, radius, gap_range, semi=(2.0, 7.0, 2.0),
@@ -126,7 +131,8 @@ def large_sensor(seed=4, nu_sphere=128, nu_blob=75, n_blobs=8, n_lambda=16):
     return Workload(f"large_sensor_R10_N{n}_{n_blobs}blobs_sweep{n_lambda}", surfs, lam, em, es,
                     op=dict(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode",
                             p=8, theta=0.5, ncrit=0, precision="fp32_refine64"),
-                    gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3), seed=seed)
+                    gmres=dict(tol=1e-6, restart=60, max_iter=1200, inner_tol=1e-3), seed=seed,
+                    tune=dict(max_rel_err=1e-6, n_cols=n_lambda))
 
 
 def serving_stream_params(seed=5, n_requests=2000, rate_per_s=1.0, nu_range=(16, 128),

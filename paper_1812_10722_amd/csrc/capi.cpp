@@ -14,10 +14,6 @@
 #include "profile.hpp"
 #include "system.hpp"
 
-struct lspr_geometry {
-    lspr::Geometry g;
-};
-
 namespace {
 
 using lspr::guarded;
@@ -122,11 +118,15 @@ bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s) {
 namespace {
 std::mutex pinned_mu;
 std::vector<lspr::PinnedBuf> pinned_free;  // staging buffers not in use
-constexpr size_t PINNED_KEEP = 8;           // free buffers kept (larger ones first)
+// Free buffers are kept up to this many bytes in all (the largest first); freeing pinned memory
+// can wait for the whole device, so a buffer is freed only when the pool is over its cap, and
+// outside the lock.
+constexpr size_t PINNED_KEEP_BYTES = 1ull << 30;
 }  // namespace
 
 PinnedBuf pinned_take(size_t bytes) {
     {
+        // the smallest free buffer that holds the request
         std::lock_guard<std::mutex> lk(pinned_mu);
         int best = -1;
         for (size_t i = 0; i < pinned_free.size(); ++i)
@@ -147,15 +147,22 @@ PinnedBuf pinned_take(size_t bytes) {
 
 void pinned_put(PinnedBuf b) {
     if (b.p == nullptr) return;
-    std::lock_guard<std::mutex> lk(pinned_mu);
-    pinned_free.push_back(b);
-    if (pinned_free.size() > PINNED_KEEP) {  // drop the smallest
-        size_t k = 0;
-        for (size_t i = 1; i < pinned_free.size(); ++i)
-            if (pinned_free[i].cap < pinned_free[k].cap) k = i;
-        (void)hipHostFree(pinned_free[k].p);
-        pinned_free.erase(pinned_free.begin() + k);
+    std::vector<PinnedBuf> drop;
+    {
+        std::lock_guard<std::mutex> lk(pinned_mu);
+        pinned_free.push_back(b);
+        size_t total = 0;
+        for (const PinnedBuf& f : pinned_free) total += f.cap;
+        while (total > PINNED_KEEP_BYTES && pinned_free.size() > 1) {  // drop the smallest
+            size_t k = 0;
+            for (size_t i = 1; i < pinned_free.size(); ++i)
+                if (pinned_free[i].cap < pinned_free[k].cap) k = i;
+            total -= pinned_free[k].cap;
+            drop.push_back(pinned_free[k]);
+            pinned_free.erase(pinned_free.begin() + k);
+        }
     }
+    for (const PinnedBuf& f : drop) (void)hipHostFree(f.p);
 }
 
 bool big_block_flush(hipMemPool_t pool) {
@@ -254,8 +261,11 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
                      op->precision == LSPR_FP32_REFINE64 || op->precision == LSPR_FP32_LEAD64,
                  LSPR_E_INVALID, "unknown precision");
     if (op->method == LSPR_TREECODE) {
-        LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10,
-             LSPR_E_INVALID, "p must be 2, 4, 6, 8 or 10");
+        LSPR_REQUIRE(op->p == 2 || op->p == 4 || op->p == 6 || op->p == 8 || op->p == 10 ||
+                         op->p == 12 || op->p == 15,
+                     LSPR_E_INVALID, "p must be 2, 4, 6, 8, 10, 12 or 15");
+        LSPR_REQUIRE(op->p <= 10 || (op->flags & LSPR_NO_MATRIX_CORES) == 0, LSPR_E_INVALID,
+                     "expansion orders above 10 run only on matrix cores");
         LSPR_REQUIRE(op->theta > 0.0 && op->theta < 1.0, LSPR_E_INVALID,
              "theta must be in (0, 1)");
     }
@@ -297,17 +307,39 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
     g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
     if (op->flags & LSPR_NO_SPLIT_OPERATORS) g.far_op_min_pad = 0;
+    g.stream_narrow = (op->flags & LSPR_STREAM_NARROW) != 0;
     lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);
     lspr::build_lists(g);
-    // the host part of the tiles runs beside the moment set-up and the near-singular table
-    std::future<lspr::TilePlan> plan;
-    if (g.allow_mfma)
-        plan = std::async(std::launch::async, [&g] { return lspr::plan_tiles(g); });
-    // boxes whose moments are needed
+    // boxes whose moments are needed, and the row block of each in the moment array
     std::set<int32_t> uniq(g.m2p_box_h.begin(), g.m2p_box_h.end());
     g.mom_boxes.assign(uniq.begin(), uniq.end());
+    g.mom_slot_h.assign(g.n_boxes, -1);
+    for (size_t k = 0; k < g.mom_boxes.size(); ++k)
+        g.mom_slot_h[g.mom_boxes[k]] = static_cast<int32_t>(k);
+    if (g.tile_budget_bytes <= 0.0) {
+        size_t free_b = 0, total_b = 0;
+        LSPR_HIP(hipMemGetInfo(&free_b, &total_b));
+        // both stores of the 491k-panel sensor (42 + 85 GB) fit on one MI355X beside its
+        // Krylov state (15 GB at 16 wavelengths)
+        g.tile_budget_bytes = 0.55 * static_cast<double>(free_b);
+    }
+    // no tile plan when not even one store of a needed precision fits (e.g. every pair of a
+    // large mesh summed directly): the products then run on the vector ALUs
+    bool tiles = g.allow_mfma;
+    if (tiles) {
+        const double elems = static_cast<double>(lspr::estimate_tile_elems(g));
+        tiles = (g.need32 && 4.0 * elems <= g.tile_budget_bytes) ||
+                (g.need64 && 8.0 * elems <= g.tile_budget_bytes);
+        LSPR_REQUIRE(tiles || g.P <= 10, LSPR_E_NOMEM,
+                     "expansion orders above 10 run only from matrix-core tiles, and they do not "
+                     "fit the tile budget");
+    }
+    // the host part of the tiles runs beside the moment set-up and the near-singular table
+    std::future<lspr::TilePlan> plan;
+    if (tiles)
+        plan = std::async(std::launch::async, [&g] { return lspr::plan_tiles(g); });
     if (!g.mom_boxes.empty()) {
         const std::vector<lspr::Range>& bh = g.box_rng_h;
         g.mom_panels = 0;
@@ -321,11 +353,12 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
             const int n = bh[b].end - bh[b].start;
             const int ns = (n + SEG - 1) / SEG;
             const int slot0 = ns > 1 ? slots : -1;
+            const int ms = g.mom_slot_h[b];
             for (int k = 0; k < ns; ++k)
                 segs.push_back({b, bh[b].start + k * SEG, std::min(bh[b].end, bh[b].start + (k + 1) * SEG),
-                                ns > 1 ? slots + k : -1});
+                                ns > 1 ? slots + k : -1, ms});
             if (ns > 1) {
-                reds.push_back({b, slot0, slot0 + ns, 0});
+                reds.push_back({b, slot0, slot0 + ns, ms});
                 slots += ns;
             }
         }
@@ -333,10 +366,10 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
         g.n_slots = slots;
         g.n_red = static_cast<int>(reds.size());
         g.p2m_seg.alloc(segs.size());
-        g.mom_boxes_d.alloc(g.mom_boxes.size());
+        g.mom_slot.alloc(g.n_boxes);
         lspr::Uploads up(g.stream);
         up.add(g.p2m_seg.p, segs.data(), segs.size());
-        up.add(g.mom_boxes_d.p, g.mom_boxes.data(), g.mom_boxes.size());
+        up.add(g.mom_slot.p, g.mom_slot_h.data(), g.mom_slot_h.size());
         if (!reds.empty()) {
             g.p2m_red.alloc(reds.size());
             up.add(g.p2m_red.p, reds.data(), reds.size());
@@ -345,12 +378,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
         g.p2m_seg_h = std::move(segs);
     }
     lspr::build_near_table(g);
-    if (g.tile_budget_bytes <= 0.0) {
-        size_t free_b = 0, total_b = 0;
-        LSPR_HIP(hipMemGetInfo(&free_b, &total_b));
-        g.tile_budget_bytes = 0.4 * static_cast<double>(free_b);
-    }
-    if (g.allow_mfma) lspr::build_tiles(g, plan.get());
+    if (tiles) lspr::build_tiles(g, plan.get());
     lspr::precompute_rhs(g);
     // the host copies were only needed while building
     g.box_rng_h = {};
@@ -361,6 +389,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.p2p_self_h = {};
     g.m2p_box_h = {};
     g.p2m_seg_h = {};
+    g.mom_slot_h = {};
 }
 
 bool solve_geometry(Geometry& g, int n_lambda, const double* lambda_nm,
@@ -448,9 +477,12 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
     return b;
 }
 
-int64_t tile_cap_bytes(int64_t N, int precision) {
+int64_t tile_cap_bytes(int64_t N, const lspr_op_params& op) {
+    const int precision = op.precision;
     const int64_t per_elem = (precision != LSPR_FP64 ? 4 : 0) + (precision != LSPR_FP32 ? 8 : 0);
-    return N * 24 * 1024 * per_elem;  // 24 K elements per panel (measured: 13-18 K)
+    // 24 K elements per panel at P <= 8 (measured: 13-18 K), more with more Taylor terms
+    const int64_t terms = static_cast<int64_t>(op.p + 1) * (op.p + 1);
+    return N * 24 * 1024 * std::max<int64_t>(terms, 81) / 81 * per_elem;
 }
 
 int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& op,
@@ -462,7 +494,7 @@ int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& 
     int64_t b = N * (1024 + 24 * S + (4 + 4 * op.k_far) * esz + 96 * 20) + (64 << 20);
     b += N * 32 * (esz + 16);
     if ((op.flags & LSPR_NO_MATRIX_CORES) == 0)
-        b += tile_cap_bytes(N, op.precision);
+        b += tile_cap_bytes(N, op);
     return b + solve_bytes(N, S, B, op, gm);
 }
 
@@ -471,7 +503,7 @@ int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& 
 size_t lspr::Geometry::device_bytes() const {
     return tri.bytes() + cen.bytes() + nrm.bytes() + area.bytes() + surf.bytes() + perm.bytes() +
            iperm.bytes() + morton.bytes() + boxes.bytes() + far_rule.bytes() +
-           mom_boxes_d.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
+           mom_slot.bytes() + chunks.bytes() + m2p_off.bytes() + m2p_box.bytes() +
            m2p_self.bytes() + p2p_off.bytes() + p2p_rng.bytes() + p2p_self.bytes() +
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + charge_u.bytes() + ws_inv_eps.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
@@ -713,15 +745,11 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
         };
         std::vector<double2> yh(nvec), rh(nvec);
         {
+            // reference: every far pair summed directly in FP64 (on matrix cores when its tiles
+            // fit, otherwise by the vector-ALU kernel)
             lspr_op_params r = *op;
             r.precision = LSPR_FP64;
-            if (N <= 40000) {
-                r.method = LSPR_DENSE;
-            } else {
-                r.method = LSPR_TREECODE;
-                r.p = 10;
-                r.theta = 0.3;
-            }
+            r.method = LSPR_DENSE;
             lspr::Geometry gr;
             lspr::create_geometry(gr, surfaces, n_surf, r, s);
             product(gr, LSPR_FP64, yref.p);
@@ -732,75 +760,126 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
         rn = std::sqrt(rn);
         LSPR_REQUIRE(rn > 0.0, LSPR_E_INVALID, "zero reference product");
         const int tprec = op->precision == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32;
-        const int orders[] = {4, 6, 8, 10};
-        const double thetas[] = {0.4, 0.5, 0.6, 0.7};
-        const int leaves[] = {8, 16, 32};
         hipEvent_t e0 = nullptr, e_1 = nullptr;
         LSPR_HIP(hipEventCreate(&e0));
         LSPR_HIP(hipEventCreate(&e_1));
+        struct Events {
+            hipEvent_t a, b;
+            ~Events() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } events{e0, e_1};
         int count = 0;
-        lspr_tune_entry best{0, 0, 0.0, 0.0, -1.0}, closest{0, 0, 0.0, 1e300, -1.0};
-        try {
-            for (double th : thetas)
-                for (int nc : leaves)
-                    for (int P : orders) {
-                        lspr_op_params c = *op;
-                        c.method = LSPR_TREECODE;
-                        c.p = P;
-                        c.theta = th;
-                        c.ncrit = nc;
-                        // both tile stores: FP64 for the error, the timed precision for speed
-                        c.precision = tprec == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32_LEAD64;
-                        lspr::Geometry g;
-                        lspr::create_geometry(g, surfaces, n_surf, c, s);
-                        product(g, LSPR_FP64, y.p);
-                        LSPR_HIP(hipMemcpy(yh.data(), y.p, nvec * sizeof(double2),
-                                           hipMemcpyDeviceToHost));
-                        double dn = 0.0;
-                        for (int64_t i = 0; i < nvec; ++i) {
-                            const double dx = yh[i].x - rh[i].x, dy = yh[i].y - rh[i].y;
-                            dn += dx * dx + dy * dy;
-                        }
-                        lspr_tune_entry t{P, nc, th, std::sqrt(dn) / rn, -1.0};
-                        if (t.rel_err <= max_rel_err) {
-                            lspr::DevBuf<double2> ratio, ys(n_cols * nvec), xs(nvec);
-                            lspr::upload_ratios(g, eb, n_cols, ratio, s);
-                            lspr::to_sorted(g, 1, x.p, xs.p, s);
-                            float ms_min = 1e30f;
-                            for (int rep = 0; rep < 4; ++rep) {
-                                LSPR_HIP(hipEventRecord(e0, s));
-                                // every column multiplies the same vector (stride 0)
-                                lspr::system_apply(g, tprec, n_cols, ratio.p, xs.p, 0, ys.p,
-                                                   nvec, nullptr, s);
-                                LSPR_HIP(hipEventRecord(e_1, s));
-                                LSPR_HIP(hipEventSynchronize(e_1));
-                                float ms = 0.0f;
-                                LSPR_HIP(hipEventElapsedTime(&ms, e0, e_1));
-                                if (rep > 0) ms_min = std::min(ms_min, ms);
-                            }
-                            t.ms_per_product = ms_min;
-                            if (best.ms_per_product < 0.0 || t.ms_per_product < best.ms_per_product)
-                                best = t;
-                        }
-                        if (t.rel_err < closest.rel_err) closest = t;
-                        if (count < max_entries) entries[count] = t;
-                        ++count;
-                        LSPR_HIP(hipStreamSynchronize(s));
-                        if (t.rel_err <= max_rel_err) break;  // a higher order only costs more
-                    }
-        } catch (...) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e_1);
-            throw;
+        auto record = [&](const lspr_tune_entry& t) {
+            if (count < max_entries) entries[count] = t;
+            ++count;
+        };
+        // FP64 error of a candidate against the reference, and (if within the bound) its
+        // fastest product of n_cols columns in the timed precision, of three after a warm-up
+        auto measure = [&](const lspr_op_params& c, bool timed) {
+            lspr_tune_entry t{c.p, c.ncrit, c.theta, 0.0, -1.0, c.m2p_min_panels, c.flags};
+            lspr_op_params cc = c;
+            cc.method = LSPR_TREECODE;
+            // both tile stores: FP64 for the error, the timed precision for speed
+            cc.precision = tprec == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32_LEAD64;
+            lspr::Geometry g;
+            lspr::create_geometry(g, surfaces, n_surf, cc, s);
+            product(g, LSPR_FP64, y.p);
+            LSPR_HIP(hipMemcpy(yh.data(), y.p, nvec * sizeof(double2), hipMemcpyDeviceToHost));
+            double dn = 0.0;
+            for (int64_t i = 0; i < nvec; ++i) {
+                const double dx = yh[i].x - rh[i].x, dy = yh[i].y - rh[i].y;
+                dn += dx * dx + dy * dy;
+            }
+            t.rel_err = std::sqrt(dn) / rn;
+            if (timed && t.rel_err <= max_rel_err) {
+                lspr::DevBuf<double2> ratio, ys(n_cols * nvec), xs(nvec);
+                lspr::upload_ratios(g, eb, n_cols, ratio, s);
+                lspr::to_sorted(g, 1, x.p, xs.p, s);
+                float ms_min = 1e30f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    LSPR_HIP(hipEventRecord(e0, s));
+                    // every column multiplies the same vector (stride 0)
+                    lspr::system_apply(g, tprec, n_cols, ratio.p, xs.p, 0, ys.p, nvec, nullptr,
+                                       s);
+                    LSPR_HIP(hipEventRecord(e_1, s));
+                    LSPR_HIP(hipEventSynchronize(e_1));
+                    float ms = 0.0f;
+                    LSPR_HIP(hipEventElapsedTime(&ms, e0, e_1));
+                    if (rep > 0) ms_min = std::min(ms_min, ms);
+                }
+                t.ms_per_product = ms_min;
+            }
+            LSPR_HIP(hipStreamSynchronize(s));
+            return t;
+        };
+        // stage 1: expansion order, acceptance parameter and leaf size (large meshes search a
+        // narrower grid: each candidate is a full set-up)
+        const bool big = N > 100000;
+        const std::vector<double> thetas = big ? std::vector<double>{0.5, 0.6}
+                                               : std::vector<double>{0.4, 0.5, 0.6, 0.7};
+        const std::vector<int> leaves = big ? std::vector<int>{16} : std::vector<int>{8, 16, 32};
+        const int orders[] = {4, 6, 8, 10, 12, 15};
+        lspr_tune_entry best{0, 0, 0.0, 0.0, -1.0, 0, 0}, closest{0, 0, 0.0, 1e300, -1.0, 0, 0};
+        for (double th : thetas)
+            for (int nc : leaves)
+                for (int P : orders) {
+                    lspr_op_params c = *op;
+                    c.p = P;
+                    c.theta = th;
+                    c.ncrit = nc;
+                    c.m2p_min_panels = 0;
+                    const lspr_tune_entry t = measure(c, true);
+                    if (t.ms_per_product >= 0.0 &&
+                        (best.ms_per_product < 0.0 || t.ms_per_product < best.ms_per_product))
+                        best = t;
+                    if (t.rel_err < closest.rel_err) closest = t;
+                    record(t);
+                    if (t.rel_err <= max_rel_err) break;  // a higher order only costs more
+                }
+        // stage 2: the kernel schedule of the best expansion: the cost threshold for expanding a
+        // box (half and twice the default of one panel per Taylor term; it moves work between
+        // expansions and direct sums, so the bound is checked again), one workgroup per operator
+        // or both operators in one (FP32), and for narrow products operands streamed or staged
+        if (best.ms_per_product >= 0.0) {
+            const int terms = (best.p + 1) * (best.p + 1);
+            lspr_op_params b = *op;
+            b.p = best.p;
+            b.theta = best.theta;
+            b.ncrit = best.ncrit;
+            b.m2p_min_panels = 0;
+            b.flags = op->flags & LSPR_NO_MATRIX_CORES;
+            std::vector<lspr_op_params> sched;
+            for (int mp : {terms / 2, 2 * terms}) {
+                lspr_op_params c = b;
+                c.m2p_min_panels = mp;
+                sched.push_back(c);
+            }
+            if (tprec == LSPR_FP32) {
+                lspr_op_params c = b;
+                c.flags |= LSPR_NO_SPLIT_OPERATORS;
+                sched.push_back(c);
+            }
+            if (n_cols <= 16) {
+                lspr_op_params c = b;
+                c.flags |= LSPR_STREAM_NARROW;
+                sched.push_back(c);
+            }
+            for (const lspr_op_params& c : sched) {
+                const lspr_tune_entry t = measure(c, true);
+                record(t);
+                if (t.ms_per_product >= 0.0 && t.ms_per_product < best.ms_per_product) best = t;
+            }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e_1);
         *n_entries = count;
         const lspr_tune_entry& pick = best.ms_per_product >= 0.0 ? best : closest;
         op->method = LSPR_TREECODE;
         op->p = pick.p;
         op->theta = pick.theta;
         op->ncrit = pick.ncrit;
+        op->m2p_min_panels = pick.m2p_min_panels;
+        op->flags = pick.flags;
         if (best.ms_per_product < 0.0) {
             lspr::last_error() = "no candidate meets the error bound";
             return static_cast<int>(LSPR_E_NOCONV);

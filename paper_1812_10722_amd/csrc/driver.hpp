@@ -4,6 +4,11 @@
 
 #include "internal.hpp"
 
+// The opaque handle of the C ABI.
+struct lspr_geometry {
+    lspr::Geometry g;
+};
+
 namespace lspr {
 
 // Detail text of the calling thread's last error (lspr_last_error).
@@ -59,7 +64,7 @@ int64_t solve_bytes(int64_t N, int S, int B, const lspr_op_params& op,
                     const lspr_gmres_params& gm);
 // Upper bound of the matrix-core tile store kept for a geometry of N panels in the given
 // precision mode (larger stores fall back to the on-the-fly kernel).
-int64_t tile_cap_bytes(int64_t N, int precision);
+int64_t tile_cap_bytes(int64_t N, const lspr_op_params& op);
 // Upper bound of the device bytes one request holds at its peak (set-up, tiles, solve).
 int64_t request_footprint(int64_t N, int S, int n_lambda, const lspr_op_params& op,
                           const lspr_gmres_params& gm);

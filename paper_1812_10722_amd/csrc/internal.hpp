@@ -322,14 +322,15 @@ struct Chunk {
     int32_t surf, pad;
 };
 
-// A P2M work item: panels [start, end) of expanded box `box`; slot < 0 writes the box's
+// A P2M work item: panels [start, end) of expanded box `box`, whose moments are row block
+// `mslot` of the moment array (expanded boxes only, in box order); slot < 0 writes the box's
 // moments directly, otherwise partial moments go to scratch slot `slot`.
 struct P2MSeg {
-    int32_t box, start, end, slot;
+    int32_t box, start, end, slot, mslot;
 };
 // Boxes assembled from several segments: moments = sum of scratch slots [slot0, slot1).
 struct P2MRed {
-    int32_t box, slot0, slot1, pad;
+    int32_t box, slot0, slot1, mslot;
 };
 
 // One left factor of the matrix-core far-field product, stored in MFMA operand order.
@@ -385,7 +386,8 @@ struct Geometry {
     int n_boxes = 0, n_leaves = 0;
     DevBuf<Box> boxes;
     DevBuf<double> far_rule;   // [K][4] barycentric coordinates and weight of the far rule
-    std::vector<int32_t> mom_boxes;  // boxes that appear in some expansion list
+    std::vector<int32_t> mom_boxes;  // boxes that appear in some expansion list (ascending)
+    std::vector<int32_t> mom_slot_h; // [n_boxes] index of each box in mom_boxes, -1 if absent
     int64_t mom_panels = 0;          // panels summed over those boxes
     int n_seg = 0, n_slots = 0, n_red = 0;
     // matrix-core tiles (FP32 geometries)
@@ -403,7 +405,7 @@ struct Geometry {
     DevBuf<double> p2mA64;       // FP64 ones, same element offsets
     DevBuf<int64_t> p2m_aoff;    // [n_seg] offset of each segment's block in p2mA / p2mA64
     DevBuf<P2MRed> p2m_red;
-    DevBuf<int32_t> mom_boxes_d;
+    DevBuf<int32_t> mom_slot;    // [n_boxes] moment row block of each box (-1: not expanded)
     int n_chunks = 0;
     DevBuf<Chunk> chunks;
     std::vector<int> chunk_h_surf;
@@ -439,7 +441,9 @@ struct Geometry {
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
     int far_op_min_pad = 16;  // products with at least this many columns per operator run
                               // one operator per workgroup (0: never)
-    double tile_budget_bytes = 0.0;  // largest tile store kept (0: 40 % of free device memory)
+    bool stream_narrow = false;  // products of up to 16 wavelengths stream their operands
+                                 // (k_far_stream) instead of staging them in LDS
+    double tile_budget_bytes = 0.0;  // largest tile store kept (0: 55 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the
     // matrix-core products then need no separate near-field pass)
     bool near_in_tiles32 = false, near_in_tiles64 = false;
@@ -493,6 +497,8 @@ struct TilePlan {
     int64_t tile_steps = 0, max_chunk_steps = 0;
 };
 TilePlan plan_tiles(const Geometry& g);
+// Elements of one tile store, from the host lists (the size plan_tiles will find).
+int64_t estimate_tile_elems(const Geometry& g);
 // Geometry-only left factors of the matrix-core far-field product, in each needed precision.
 void build_tiles(Geometry& g, const TilePlan& plan);
 

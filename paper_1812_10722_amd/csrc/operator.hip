@@ -138,7 +138,7 @@ k_p2m(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs,
         acc[ex.fdx[f]] += T(ex.fcx[f]) * acc[ex.fsrc[f]];
         acc[ex.fdy[f]] += T(ex.fcy[f]) * acc[ex.fsrc[f]];
     }
-    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * E::NR * ncols
+    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.mslot) * E::NR * ncols
                          : part + static_cast<size_t>(sg.slot) * E::NR * ncols;
 #pragma unroll
     for (int q = 0; q < E::NR; ++q) out[static_cast<size_t>(q) * ncols + col] = acc[ex.rfull[q]];
@@ -156,7 +156,7 @@ __global__ void k_p2m_reduce(const P2MRed* __restrict__ red, int n_red, int nr, 
     const P2MRed R = red[r];
     T s = T(0);
     for (int k = R.slot0; k < R.slot1; ++k) s += part[static_cast<int64_t>(k) * per + e];
-    mom[static_cast<int64_t>(R.box) * per + e] = s;
+    mom[static_cast<int64_t>(R.mslot) * per + e] = s;
 }
 
 // ------------------------------------------------------------------------------- far field
@@ -171,8 +171,8 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
       const int32_t* __restrict__ m2p_self, const int32_t* __restrict__ p2p_off,
       const Range* __restrict__ p2p_rng, const int32_t* __restrict__ p2p_self,
       const double* __restrict__ cen, const T* __restrict__ src, int K,
-      const T* __restrict__ dens, const T* __restrict__ mom, int pad,
-      double* __restrict__ out_self, double* __restrict__ out_all) {
+      const T* __restrict__ dens, const T* __restrict__ mom, const int32_t* __restrict__ mom_slot,
+      int pad, double* __restrict__ out_self, double* __restrict__ out_all) {
     using E = Expansion<P>;
     constexpr int NR = E::NR;
     constexpr int PT = tile_panels<T>();
@@ -217,7 +217,7 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
                 for (int q = 0; q < NR; ++q) coef[q][lane] = valid ? F[q] : T(0);
             }
             __syncthreads();
-            const T* M = mom + static_cast<size_t>(bi) * NR * ncols;
+            const T* M = mom + static_cast<size_t>(mom_slot[bi]) * NR * ncols;
             T pk[CPT], pv[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) pk[c] = pv[c] = T(0);
@@ -320,6 +320,18 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // cores before the tile joins the FP64 running sum (longer tiles measured no faster and add
 // FP32 rounding that GMRES feels near resonance).
 constexpr int DSTEPS = 8;
+
+// Expansion tiles of high orders are cut along the Taylor terms into slices of equal K-steps
+// (at most 21, the P = 8 tile), each a tile of its own with its slice of moment rows; orders up
+// to 10 keep one tile per expansion.  The kernels then never stage or hold more than one slice.
+constexpr int expansion_slices(int n_terms) {
+    const int steps = (n_terms + 3) / 4;
+    return steps <= 31 ? 1 : (steps + 20) / 21;
+}
+constexpr int expansion_slice_steps(int n_terms) {
+    const int steps = (n_terms + 3) / 4, n = expansion_slices(n_terms);
+    return (steps + n - 1) / n;
+}
 
 template <class T>
 struct alignas(4 * sizeof(T)) Quad {
@@ -875,6 +887,162 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     write_sums(out_all);
 }
 
+// Narrow products (one or two column groups of 16 per operator, up to 16 wavelengths) without
+// LDS staging.  At these widths a left-factor value feeds the matrix cores of one wave only
+// (the S = 4 / G waves of a column group split each tile's K-steps, wave k taking steps k,
+// k + S, ...), so each wave streams its own operands straight from HBM into registers: per
+// K-step one 16-byte (FP64: 32-byte) A operand per lane, contiguous across the wave, and one B
+// value.  Two sets of operand registers alternate between tiles, and each register is reloaded
+// with the operand two tiles ahead right after the current step has used it, so a wave keeps
+// two tiles of loads in flight while it computes, and the loop holds no barrier.
+// Raw buffer loads with per-tile records read zero past a tile's factor and rows.  The step
+// partition, the FP32 partial per tile, its FP64 running sum and the wave-order addition at
+// the end are those of k_far_tiles_op's narrow form, so both give identical sums.
+template <class T, int NSM, int S>
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && S == 4) ? 4 : 2)
+k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
+             const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
+             const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
+             const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
+             double* __restrict__ out_self, double* __restrict__ out_all) {
+    static_assert(S == 2 || S == 4, "narrow products only");
+    constexpr uint32_t ES = sizeof(T);
+    constexpr int G = 4 / S;                   // column groups per workgroup
+    constexpr int NA = NSM > DSTEPS ? NSM : DSTEPS;
+    constexpr int NBS = (NA + S - 1) / S;      // operand registers per wave
+    using Acc = typename Mma<T>::acc;
+    __shared__ double red[G][16][64];          // wave-order addition of the partial sums
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int ncols = 2 * pad;
+    const int b = blockIdx.x;
+    const int opr = (b >> 3) & 1;              // 0: K columns, 1: V columns
+    const int kpart = wave % S;                // this wave's share of the K-steps
+    const int wg = wave / S;                   // column group of this wave
+    const int chunk = chunk_order[(b >> 4) * 8 + (b & 7)];
+    if (chunk < 0) return;
+    const Chunk C = chunks[chunk];
+    const int ntg = C.end - C.start;
+    const bool mma = wg < nwc;
+    const int col = opr * pad + 16 * wg + c16;
+    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * ES;
+    const uint32_t bstep = 4u * ES * static_cast<uint32_t>(ncols);
+    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
+    const int t_mid = t_beg + tile_self[chunk];
+    Acc acc[4];
+    double run[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        acc[a] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[a][q] = 0.0;
+    }
+    auto own = [&](int mt, int q) -> double {
+        if constexpr (sizeof(T) == 4) return run[mt][q];
+        else return acc[mt][q];
+    };
+    auto write_sums = [&](double* out) {
+        double sum[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[mt][q] = own(mt, q);
+        for (int k = 1; k < S; ++k) {
+            if (kpart == k)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) red[wg][4 * mt + q][lane] = own(mt, q);
+            __syncthreads();
+            if (kpart == 0)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sum[mt][q] += red[wg][4 * mt + q][lane];
+            __syncthreads();
+        }
+        if (!mma || kpart != 0) return;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + out_row<T>(grp, q);
+                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = sum[mt][q];
+            }
+    };
+    // operand sources of tile e (empty records past the chunk's last tile)
+    auto a_rsrc = [&](int e) {
+        if (e >= t_end) return buffer_rsrc(tileA, 0u);
+        const TileDesc D = tiles[e];
+        const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
+        return buffer_rsrc(tileA + off, static_cast<uint32_t>(D.nstep) * 256u * ES);
+    };
+    auto b_rsrc = [&](int e) {
+        if (e >= t_end) return buffer_rsrc(dens, 0u);
+        const TileDesc D = tiles[e];
+        const T* src = D.kind == 0 ? mom : dens;
+        return buffer_rsrc(src + static_cast<size_t>(D.b_row0) * ncols,
+                           static_cast<uint32_t>(D.b_rows) * static_cast<uint32_t>(ncols) * ES);
+    };
+    // this lane's A operand of K-step st: 4 consecutive elements (the four target tiles)
+    auto load_a = [&](__amdgpu_buffer_rsrc_t ra, int st) {
+        Quad<T> q;
+        if constexpr (sizeof(T) == 4) {
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 1024, 0);
+            q.x = __uint_as_float(v[0]);
+            q.y = __uint_as_float(v[1]);
+            q.z = __uint_as_float(v[2]);
+            q.w = __uint_as_float(v[3]);
+        } else {
+            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048, 0);
+            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048, 0);
+            q.x = __builtin_bit_cast(double, make_uint2(lo[0], lo[1]));
+            q.y = __builtin_bit_cast(double, make_uint2(lo[2], lo[3]));
+            q.z = __builtin_bit_cast(double, make_uint2(hi[0], hi[1]));
+            q.w = __builtin_bit_cast(double, make_uint2(hi[2], hi[3]));
+        }
+        return q;
+    };
+    Quad<T> a[NBS];
+    T bv[NBS];
+    {
+        const __amdgpu_buffer_rsrc_t ra = a_rsrc(t_beg), rb = b_rsrc(t_beg);
+#pragma unroll
+        for (int i = 0; i < NBS; ++i) {
+            a[i] = load_a(ra, kpart + S * i);
+            bv[i] = load_elem<T>(rb, boff, (kpart + S * i) * bstep);
+        }
+    }
+    auto tile = [&](int e) {
+        const int ns = tiles[e].nstep;
+        const __amdgpu_buffer_rsrc_t ran = a_rsrc(e + 1), rbn = b_rsrc(e + 1);
+#pragma unroll
+        for (int i = 0; i < NBS; ++i) {
+            const int st = kpart + S * i;
+            if (st < ns && mma) {
+                acc[0] = Mma<T>::op(a[i].x, bv[i], acc[0]);
+                acc[1] = Mma<T>::op(a[i].y, bv[i], acc[1]);
+                acc[2] = Mma<T>::op(a[i].z, bv[i], acc[2]);
+                acc[3] = Mma<T>::op(a[i].w, bv[i], acc[3]);
+            }
+            a[i] = load_a(ran, st);
+            bv[i] = load_elem<T>(rbn, boff, st * bstep);
+        }
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
+                acc[q] = Acc{0, 0, 0, 0};
+            }
+        }
+    };
+    for (int e = t_beg; e < t_mid; ++e) tile(e);
+    if (out_self != nullptr) write_sums(out_self);
+    for (int e = t_mid; e < t_end; ++e) tile(e);
+    write_sums(out_all);
+}
+
 // ------------------------------------------------------------------------------- P2M, MFMA
 // The folded moments of an expanded box are linear in the densities of its panels with
 // geometry-only weights: M[term][col] = sum_j A[term][j] dens[j][col], A[term][j] the folded
@@ -908,7 +1076,7 @@ k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
-    constexpr int PB = 8, TPP = 16;
+    constexpr int PB = P <= 10 ? 8 : 4, TPP = 128 / PB;  // LDS under 64 KB up to P = 15
     __shared__ double poly[PB][2][NF];  // V then K polynomial of each panel of the batch
     const P2MSeg sg = segs[blockIdx.x];
     const Box B = boxes[sg.box];
@@ -1029,7 +1197,7 @@ k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
 #pragma unroll
         for (int t = 0; t < RT; ++t) acc[t] = Mma<T>::op(a[t * 64], bb, acc[t]);
     }
-    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.box) * NR * ncols
+    T* out = sg.slot < 0 ? mom + static_cast<size_t>(sg.mslot) * NR * ncols
                          : part + static_cast<size_t>(sg.slot) * NR * ncols;
 #pragma unroll
     for (int t = 0; t < RT; ++t)
@@ -1071,11 +1239,15 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
         for (int q = 0; q < NR; ++q) F[q] = T(0);
     }
     const int mt = t >> 4, r16 = t & 15;
-    constexpr int NRP = (NR + 3) / 4 * 4;  // equals 4 * TD.nstep
+    // slice k holds terms [4 SST k, 4 SST (k + 1)) as SST K-steps, its tile right after slice
+    // k - 1's in the store (zero past the last term)
+    constexpr int SST = expansion_slice_steps(NR), PER = 4 * SST;
+    constexpr int TOT = expansion_slices(NR) * PER;
 #pragma unroll
-    for (int q = 0; q < NRP; ++q) {
-        const int st = q >> 2, g = q & 3;
-        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
+    for (int q = 0; q < TOT; ++q) {
+        const int k = q / PER, st = (q % PER) >> 2, g = q & 3;
+        const size_t idx = static_cast<size_t>(k) * SST * 256 +
+                           (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
         const T v = q < NR ? F[q] : T(0);
         A[idx] = v;
         if (tileA32 != nullptr) tileA32[TD.a_off() + idx] = static_cast<float>(v);
@@ -1233,8 +1405,8 @@ void launch_far_p(Geometry& g, int pad, const T* dens, const T* mom, double* os,
     const int threads = NT * (pad / CPT);
     hipLaunchKernelGGL((k_far<T, P, CPT>), dim3(g.n_chunks), dim3(threads), 0, s, g.chunks.p,
                        g.boxes.p, g.m2p_off.p, g.m2p_box.p, g.m2p_self.p, g.p2p_off.p,
-                       g.p2p_rng.p, g.p2p_self.p, g.cen.p, src_of<T>(g), g.K, dens, mom, pad, os,
-                       oa);
+                       g.p2p_rng.p, g.p2p_self.p, g.cen.p, src_of<T>(g), g.K, dens, mom,
+                       g.mom_slot.p, pad, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
@@ -1299,21 +1471,39 @@ void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const 
     LSPR_HIP(hipGetLastError());
 }
 
-// one column group per operator: four waves share it; two: two waves each; more: one each
+template <class T, int NSM, int S>
+void launch_far_stream(Geometry& g, int pad, const T* dens, const T* mom, double* os,
+                       double* oa, hipStream_t s) {
+    const int nblk = g.n_order * 2;
+    hipLaunchKernelGGL((k_far_stream<T, NSM, S>), dim3(nblk), dim3(256), 0, s, g.chunks.p,
+                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g),
+                       dens, mom, pad, pad / 16, os, oa);
+    LSPR_HIP(hipGetLastError());
+}
+
+// one column group per operator: four waves share it; two: two waves each; more: one each.
+// Narrow products stage their left factors in LDS, or stream their operands (k_far_stream)
+// when the geometry asks for it.
 template <class T, int NSM>
 void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                          double* os, double* oa, hipStream_t s) {
     const int groups = pad / 16;
-    if (groups == 1) launch_far_tiles_op_s<T, NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
-    else if (groups == 2) launch_far_tiles_op_s<T, NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
-    else launch_far_tiles_op_s<T, NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
+    if (groups == 1) {
+        if (g.stream_narrow) launch_far_stream<T, NSM, 4>(g, pad, dens, mom, os, oa, s);
+        else launch_far_tiles_op_s<T, NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
+    } else if (groups == 2) {
+        if (g.stream_narrow) launch_far_stream<T, NSM, 2>(g, pad, dens, mom, os, oa, s);
+        else launch_far_tiles_op_s<T, NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
+    } else {
+        launch_far_tiles_op_s<T, NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
+    }
 }
 
 template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
     if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
-        const int nsm = (g.n_terms + 3) / 4;
+        const int nsm = expansion_slice_steps(g.n_terms);
         const int abuf = std::max(nsm, DSTEPS) * 256;  // largest part a workgroup stages
 #define LSPR_FAR_OP(NSM_)                                                                    \
     case NSM_:                                                                               \
@@ -1323,6 +1513,8 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
             LSPR_FAR_OP(3)
             LSPR_FAR_OP(7)
             LSPR_FAR_OP(13)
+            LSPR_FAR_OP(15)
+            LSPR_FAR_OP(16)
             LSPR_FAR_OP(21)
             LSPR_FAR_OP(31)
             default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
@@ -1334,7 +1526,7 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
     // over two workgroups); FP64 left factors fill a CU's LDS, so one 8-wave workgroup per CU
     constexpr int NTHR = sizeof(T) == 4 ? 256 : 512;
     const int halves = nwc > NTHR / 64 ? 2 : 1;
-    const int nsm = (g.n_terms + 3) / 4;
+    const int nsm = expansion_slice_steps(g.n_terms);
     const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);  // elements of the largest left factor
     const int per16 = 16 / static_cast<int>(sizeof(T));
     const int pf = (abuf / per16 + NTHR - 1) / NTHR;  // 16-byte chunks per thread
@@ -1350,10 +1542,12 @@ void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double*
         else                                                                                    \
             launch_far_tiles_pf<T, 8, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
         break;
-    switch (nsm) {  // (P + 1)^2 / 4 rounded up for P = 2, 4, 6, 8, 10
+    switch (nsm) {  // K-steps of an expansion slice for P = 2, 4, 6, 12, 15, 8, 10
         LSPR_FAR_TILES(3)
         LSPR_FAR_TILES(7)
         LSPR_FAR_TILES(13)
+        LSPR_FAR_TILES(15)
+        LSPR_FAR_TILES(16)
         LSPR_FAR_TILES(21)
         LSPR_FAR_TILES(31)
         default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
@@ -1398,7 +1592,9 @@ bool launch_p2m_tiles(Geometry& g, const Cols& c, const T* dens, T* mom, hipStre
         case 6: launch_p2m_mfma<T, 6>(g, c.pad, dens, mom, s); break;
         case 8: launch_p2m_mfma<T, 8>(g, c.pad, dens, mom, s); break;
         case 10: launch_p2m_mfma<T, 10>(g, c.pad, dens, mom, s); break;
-        default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        case 12: launch_p2m_mfma<T, 12>(g, c.pad, dens, mom, s); break;
+        case 15: launch_p2m_mfma<T, 15>(g, c.pad, dens, mom, s); break;
+        default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8, 10, 12 or 15");
     }
     return true;
 }
@@ -1446,7 +1642,7 @@ void launch_far_cpt(Geometry& g, int pad, const T* dens, const T* mom, double* o
         case 6: launch_far_p<T, 6, CPT>(g, pad, dens, mom, os, oa, s); break;
         case 8: launch_far_p<T, 8, CPT>(g, pad, dens, mom, os, oa, s); break;
         case 10: launch_far_p<T, 10, CPT>(g, pad, dens, mom, os, oa, s); break;
-        default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+        default: throw Error(LSPR_E_INVALID, "expansion orders above 10 run only from matrix-core tiles");
     }
 }
 
@@ -1464,7 +1660,7 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
     const bool fp64 = sizeof(T) == 8;
     T* mom = nullptr;
     if (!g.mom_boxes.empty()) {
-        const size_t need = static_cast<size_t>(g.n_boxes) * g.n_terms * 2 * c.pad * sizeof(T);
+        const size_t need = g.mom_boxes.size() * g.n_terms * 2 * c.pad * sizeof(T);
         g.ws_mom.reserve(need);
         mom = reinterpret_cast<T*>(g.ws_mom.p);
         // per panel of an expanded box: node polynomials (V and K) and the contraction with
@@ -1479,7 +1675,7 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
                 case 6: launch_p2m_p<T, 6>(g, c.pad, dens, mom, s); break;
                 case 8: launch_p2m_p<T, 8>(g, c.pad, dens, mom, s); break;
                 case 10: launch_p2m_p<T, 10>(g, c.pad, dens, mom, s); break;
-                default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+                default: throw Error(LSPR_E_INVALID, "expansion orders above 10 run only from matrix-core tiles");
             }
         }
     }
@@ -1542,7 +1738,9 @@ void build_tiles_t(Geometry& g, T* A, float* A32, const int32_t* mt, const int32
             case 6: launch_build_m2p<T, 6>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
             case 8: launch_build_m2p<T, 8>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
             case 10: launch_build_m2p<T, 10>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
-            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+            case 12: launch_build_m2p<T, 12>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            case 15: launch_build_m2p<T, 15>(g, A, A32, g.tiles.p, mt, mc, n_m2p, s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8, 10, 12 or 15");
         }
     }
     if (n_p2p > 0) {
@@ -1574,6 +1772,17 @@ bool fold_near(Geometry& g, T* A, float* A32, const int32_t* dt_off, const int32
     return false;
 }
 
+int64_t estimate_tile_elems(const Geometry& g) {
+    const int nc = g.n_chunks;
+    const int64_t exp_elems = static_cast<int64_t>(expansion_slices(g.n_terms)) *
+                              expansion_slice_steps(g.n_terms) * 256;
+    int64_t e = static_cast<int64_t>(g.m2p_off_h.size() == static_cast<size_t>(nc) + 1
+                                         ? g.m2p_off_h[nc] : 0) * exp_elems;
+    for (const Range& r : g.p2p_rng_h)
+        e += static_cast<int64_t>((r.end - r.start + 4 * DSTEPS - 1) / (4 * DSTEPS)) * 2 * DSTEPS * 256;
+    return e;
+}
+
 TilePlan plan_tiles(const Geometry& g) {
     TilePlan P;
     const int nc = g.n_chunks;
@@ -1584,9 +1793,11 @@ TilePlan plan_tiles(const Geometry& g) {
     LSPR_REQUIRE(static_cast<int>(mo.size()) == nc + 1 && static_cast<int>(po.size()) == nc + 1 &&
                      static_cast<int>(ms.size()) == nc && static_cast<int>(ps.size()) == nc &&
                      static_cast<int64_t>(mbox.size()) == g.n_m2p &&
-                     static_cast<int64_t>(rng.size()) == g.n_p2p,
+                     static_cast<int64_t>(rng.size()) == g.n_p2p &&
+                     static_cast<int>(g.mom_slot_h.size()) == g.n_boxes,
                  LSPR_E_INVALID, "interaction lists missing on the host");
-    const int nsm = (g.n_terms + 3) / 4;  // K-steps of an expansion tile
+    const int nsl = expansion_slices(g.n_terms);      // tiles per expansion
+    const int nsm = expansion_slice_steps(g.n_terms);  // K-steps of each
     auto make_tile = [](int kind, int nstep, int64_t aoff, int r0, int rows) {
         LSPR_REQUIRE(aoff % 256 == 0 && aoff / 256 < INT32_MAX, LSPR_E_INVALID,
                      "tile store offset out of range");
@@ -1612,10 +1823,15 @@ TilePlan plan_tiles(const Geometry& g) {
             const int ma = phase == 0 ? mo[c] : mo[c] + ms[c], mb = phase == 0 ? mo[c] + ms[c] : mo[c + 1];
             const int pa = phase == 0 ? po[c] : po[c] + ps[c], pb = phase == 0 ? po[c] + ps[c] : po[c + 1];
             for (int e = ma; e < mb; ++e) {
-                m2p_tile[e] = static_cast<int32_t>(tiles.size());
+                m2p_tile[e] = static_cast<int32_t>(tiles.size());  // its first slice
                 m2p_chunk[e] = c;
-                tiles.push_back(make_tile(0, nsm, aoff, mbox[e] * g.n_terms, g.n_terms));
-                aoff += static_cast<int64_t>(nsm) * 256;
+                for (int k = 0; k < nsl; ++k) {
+                    const int t0 = 4 * nsm * k;
+                    tiles.push_back(make_tile(0, nsm, aoff,
+                                              g.mom_slot_h[mbox[e]] * g.n_terms + t0,
+                                              std::min(4 * nsm, g.n_terms - t0)));
+                    aoff += static_cast<int64_t>(nsm) * 256;
+                }
             }
             for (int e = pa; e < pb; ++e)
                 for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 4 * DSTEPS) {
@@ -1705,6 +1921,9 @@ void build_tiles(Geometry& g, const TilePlan& P) {
     const bool keep32 = g.need32 && static_cast<double>(aoff) * 4.0 <= left;
     if (keep32) left -= static_cast<double>(aoff) * 4.0;
     const bool keep64 = g.need64 && static_cast<double>(aoff) * 8.0 <= left;
+    LSPR_REQUIRE(g.P <= 10 || ((!g.need32 || keep32) && (!g.need64 || keep64)), LSPR_E_NOMEM,
+                 "expansion orders above 10 run only from matrix-core tiles, and they do not "
+                 "fit the tile budget");
     if (!keep32 && !keep64) {
         g.n_tiles = 0;
         return;
@@ -1752,7 +1971,9 @@ void build_tiles(Geometry& g, const TilePlan& P) {
             case 6: build_p2m_tiles_p<6>(g, s); break;
             case 8: build_p2m_tiles_p<8>(g, s); break;
             case 10: build_p2m_tiles_p<10>(g, s); break;
-            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8 or 10");
+            case 12: build_p2m_tiles_p<12>(g, s); break;
+            case 15: build_p2m_tiles_p<15>(g, s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8, 10, 12 or 15");
         }
     }
 }

@@ -90,7 +90,7 @@ void lspr_server::run(Request& r, hipStream_t s) {
         lspr::validate_mesh_host(host.data(), r.S);
         lspr::Geometry g;
         g.tile_budget_bytes =
-            static_cast<double>(lspr::tile_cap_bytes(r.n_panels, r.op.precision));
+            static_cast<double>(lspr::tile_cap_bytes(r.n_panels, r.op));
         {
             std::vector<lspr::DevBuf<double>> vd(r.S);
             std::vector<lspr::DevBuf<int32_t>> td(r.S);

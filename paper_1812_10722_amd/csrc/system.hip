@@ -229,7 +229,7 @@ void precompute_rhs(Geometry& g) {
     LSPR_HIP(hipStreamSynchronize(s));
 }
 
-void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s) {
+std::vector<double2> ratio_values(const Geometry& g, const EpsSet& eps, int B) {
     std::vector<double2> h(static_cast<size_t>(B) * g.S);
     for (int b = 0; b < B; ++b) {
         const double mr = eps.em_re[b], mi = eps.em_im[b];
@@ -242,6 +242,11 @@ void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hi
             h[b * g.S + k] = make_double2((sr * mr + si * mi) / den, (si * mr - sr * mi) / den);
         }
     }
+    return h;
+}
+
+void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s) {
+    const std::vector<double2> h = ratio_values(g, eps, B);
     d.reserve(h.size());
     LSPR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     if (g.charge_u.p != nullptr) {  // 1 / eps_s for the charges' right-hand side
@@ -301,6 +306,7 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
     prof::Scope sc("matvec", s, 0.0, 0.0);
     g.ws_dens.reserve(nd * esz);
     g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
+    uint8_t* dens = g.ws_dens.p;
     double* oa = reinterpret_cast<double*>(g.ws_out.p);
     double* os = g.S > 1 ? oa + nd : nullptr;
     // panels per block of the packing and combining kernels: their LDS rows within 48 KB
@@ -315,13 +321,13 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
     if (c.prec == LSPR_FP32)
         hipLaunchKernelGGL(k_pack<float>, dim3(nbk), dim3(TPB), ppk * ld * esz, s, x, x_stride,
                            d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, ppk,
-                           reinterpret_cast<float*>(g.ws_dens.p));
+                           reinterpret_cast<float*>(dens));
     else
         hipLaunchKernelGGL(k_pack<double>, dim3(nbk), dim3(TPB), ppk * ld * esz, s, x, x_stride,
                            d_cols, nslot, g.N, ratio_d, g.S, g.surf.p, vs, c.pad, ppk,
-                           reinterpret_cast<double*>(g.ws_dens.p));
+                           reinterpret_cast<double*>(dens));
     LSPR_HIP(hipGetLastError());
-    apply_raw(g, c, g.ws_dens.p, os, oa, s);
+    apply_raw(g, c, dens, os, oa, s);
     const size_t crow = ld * sizeof(double) * (os ? 2 : 1);
     const int ppc = panels_per_block(crow);
     hipLaunchKernelGGL(k_combine, dim3((g.N + ppc - 1) / ppc), dim3(TPB), ppc * crow, s, x,

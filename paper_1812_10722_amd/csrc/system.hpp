@@ -10,8 +10,11 @@ struct EpsSet {
     std::vector<double> es_re, es_im;  // [B][S]
 };
 
-// ratio[b][s] = eps_surface[b][s] / eps_medium[b] on the device (grow-only buffer).
+// ratio[b][s] = eps_surface[b][s] / eps_medium[b] on the host ([B][S]), and on the device
+// (grow-only buffer; with point charges also 1 / eps_s for the right-hand side).
+std::vector<double2> ratio_values(const Geometry& g, const EpsSet& eps, int B);
 void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s);
+
 
 // y[col] = A(col) x[col] for nslot columns; col = d_cols[slot] (or slot when d_cols is null),
 // with far-field products in precision prec (LSPR_FP32 or LSPR_FP64); with precond,

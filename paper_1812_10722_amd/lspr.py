@@ -155,16 +155,18 @@ def _stream_ptr(stream):
 
 LSPR_NO_MATRIX_CORES = 1
 LSPR_NO_SPLIT_OPERATORS = 2
+LSPR_STREAM_NARROW = 4
 
 
 def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, theta=0.5,
               ncrit=0, precision="fp32", m2p_min_panels=0, matrix_cores=True,
-              split_operators=True):
+              split_operators=True, stream_narrow=False):
     return lspr_op_params(k_far, k_fine, n_k, threshold,
                           LSPR_TREECODE if method == "treecode" else LSPR_DENSE, p, theta, ncrit,
                           _PRECISION[precision], m2p_min_panels,
                           (0 if matrix_cores else LSPR_NO_MATRIX_CORES) |
-                          (0 if split_operators else LSPR_NO_SPLIT_OPERATORS))
+                          (0 if split_operators else LSPR_NO_SPLIT_OPERATORS) |
+                          (LSPR_STREAM_NARROW if stream_narrow else 0))
 
 
 def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1, inner_tol=0.0):
@@ -378,7 +380,8 @@ _sig("lspr_request_footprint", C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P(lsp
 
 class lspr_tune_entry(C.Structure):
     _fields_ = [("p", C.c_int32), ("ncrit", C.c_int32), ("theta", C.c_double),
-                ("rel_err", C.c_double), ("ms_per_product", C.c_double)]
+                ("rel_err", C.c_double), ("ms_per_product", C.c_double),
+                ("m2p_min_panels", C.c_int32), ("flags", C.c_int32)]
 
 
 _sig("lspr_autotune", C.c_int, [_P(lspr_surface), C.c_int32, C.c_int32, _P(lspr_c64),
@@ -407,7 +410,7 @@ def lspr_autotune(surfaces, n_cols, eps_medium, eps_surface, max_rel_err=1e-5, o
     em = (lspr_c64 * 1)(lspr_c64(complex(eps_medium).real, complex(eps_medium).imag))
     es_list = [complex(e) for e in np.ravel(eps_surface)]
     es = (lspr_c64 * len(es_list))(*[lspr_c64(e.real, e.imag) for e in es_list])
-    cap = 64
+    cap = 256
     ent = (lspr_tune_entry * cap)()
     n = C.c_int32()
     code = _lib.lspr_autotune(arr, len(dev), int(n_cols), em, es, float(max_rel_err),

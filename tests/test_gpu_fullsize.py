@@ -76,7 +76,7 @@ def test_sweep_workload_sampled_rows_dense_fp64(lib):
 
 def test_sensor_two_analytes_sampled_rows(lib):
     """Sphere (40328 panels) and two 29768-panel analytes at 1 nm, 32 wavelengths, FP32."""
-    _sampled_row_parity(lib, workload("sensor_two_analytes"), 40, 32, 1e-4)
+    _sampled_row_parity(lib, workload("sensor_two_analytes"), 40, 32, 1e-4, precision="fp32")
 
 
 def test_large_sensor_sampled_rows(lib):

@@ -101,6 +101,35 @@ def test_treecode_error_falls_with_order(lib, precision):
     assert errs[2] < 2e-4 and errs[-1] < max(1e-5, floor), errs  # P = 6 and P = 10
 
 
+def test_high_orders_continue_the_convergence(lib):
+    """Orders 12 and 15 (the paper's grid-convergence setting, Table treeparams1) run from
+    expansion tiles cut into slices of Taylor terms: the FP64 product keeps converging to the
+    dense product past P = 10, at the rate theta^(P+1) (theta = 0.5)."""
+    v, t = graded_octasphere(16, 10.0)
+    V, K = oracle.dense_operators(v, t, 4, 19, 9, 0.5)
+    g = oracle.panel_geometry(v, t)
+    A, _ = oracle.assemble_system(V, K, np.zeros(len(t), int), g["normal"], 1.7733,
+                                  [-3.38 + 0.2j], [0, 0, 1.0])
+    rng = np.random.default_rng(5)
+    x = _rand_x(rng, 3, len(t))
+    errs = []
+    for p in (8, 10, 12, 15):
+        geo = lib.Geometry([(v, t)], method="treecode", precision="fp64", p=p, theta=0.5,
+                           ncrit=8, m2p_min_panels=1)
+        assert geo.info()["n_m2p"] > 0
+        y = geo.apply(torch.as_tensor(x).cuda(), [1.7733] * 3, [[-3.38 + 0.2j]] * 3).cpu().numpy()
+        errs.append(max(np.linalg.norm(y[c] - A @ x[c]) / np.linalg.norm(A @ x[c])
+                        for c in range(3)))
+        # the FP32 tiles of the same orders (sliced too) agree with the FP64 product
+        g32 = lib.Geometry([(v, t)], method="treecode", precision="fp32", p=p, theta=0.5,
+                           ncrit=8, m2p_min_panels=1)
+        y32 = g32.apply(torch.as_tensor(x).cuda(), [1.7733] * 3,
+                        [[-3.38 + 0.2j]] * 3).cpu().numpy()
+        assert np.abs(y32 - y).max() / np.abs(y).max() < 3e-6, p
+    assert errs[0] > errs[1] > errs[2] > errs[3], errs
+    assert errs[3] < 1e-7, errs
+
+
 @pytest.mark.parametrize("method,ncol,precision", [("treecode", 20, "fp32"), ("dense", 9, "fp32"),
                                                    ("treecode", 64, "fp32"),
                                                    ("treecode", 20, "fp64"), ("treecode", 64, "fp64"),
@@ -128,6 +157,34 @@ def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol, 
         scale = np.abs(ref).max()
         assert np.abs(y_mc[c] - y_vc[c]).max() / scale < same
         assert np.abs(y_mc[c] - ref).max() / scale < (same if method == "dense" else 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_streamed_narrow_products_equal_staged(lib, precision):
+    """Products of 1 to 16 wavelengths stream each wave's operands from memory (no LDS): the
+    same step partition and summation order as the LDS-staged form, so the results are equal
+    bit for bit; both match the oracle's dense product to the treecode's truncation error."""
+    surfs = sensor_and_blob(10, 7)
+    v, t, sid, V, K, g = _dense_system(surfs, None, None)
+    kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
+    streamed = lib.Geometry(surfs, stream_narrow=True, **kw)
+    staged = lib.Geometry(surfs, **kw)
+    rng = np.random.default_rng(17)
+    for nl in (1, 5, 8, 9, 12, 16):
+        eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
+        eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(nl), np.full(nl, 2.5 + 0.1j)], 1)
+        xt = torch.as_tensor(_rand_x(rng, nl, len(t))).cuda()
+        a = streamed.apply(xt, eps_m, eps_s).cpu().numpy()
+        b = staged.apply(xt, eps_m, eps_s).cpu().numpy()
+        assert np.array_equal(a, b), (nl, np.abs(a - b).max())
+        for c in (0, nl - 1):
+            A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m[c], eps_s[c], [0, 0, 1.0])
+            ref = A @ _to_np(xt[c])
+            assert np.abs(a[c] - ref).max() / np.abs(ref).max() < 1e-4
+
+
+def _to_np(t):
+    return t.cpu().numpy()
 
 
 # ----------------------------------------------------------------------------- full solves
@@ -187,13 +244,15 @@ def test_short_restart_cycles(lib, sphere_512_ref, restart):
     assert rel < 1e-7, rel
 
 
-@pytest.mark.parametrize("method,precision,tol", [("dense", "fp64", 1e-6), ("dense", "fp32", 1e-4),
-                                                  ("treecode", "fp64", 1e-4),
-                                                  ("treecode", "fp32", 1e-4),
-                                                  ("dense", "fp32_refine64", 1e-6),
-                                                  ("treecode", "fp32_refine64", 1e-4),
-                                                  ("treecode", "fp32_lead64", 1e-4)])
-def test_spectrum_matches_oracle(lib, method, precision, tol):
+@pytest.mark.parametrize("method,precision,tol,p", [("dense", "fp64", 1e-6, 8),
+                                                    ("dense", "fp32", 1e-4, 8),
+                                                    ("treecode", "fp64", 1e-4, 8),
+                                                    ("treecode", "fp64", 1e-6, 15),
+                                                    ("treecode", "fp32", 1e-4, 8),
+                                                    ("dense", "fp32_refine64", 1e-6, 8),
+                                                    ("treecode", "fp32_refine64", 1e-4, 8),
+                                                    ("treecode", "fp32_lead64", 1e-4, 8)])
+def test_spectrum_matches_oracle(lib, method, precision, tol, p):
     """A spectrum across the Drude resonance (8 wavelengths, 2048-panel sphere, E along x):
     every wavelength's C_ext within the path's bar of the oracle's LU value."""
     v, t = octasphere(16, 10.0)
@@ -202,7 +261,7 @@ def test_spectrum_matches_oracle(lib, method, precision, tol):
     es = eps_silver_drude(lam)[:, None]
     e = [1.0, 0.0, 0.0]
     ref = oracle.solve(v, t, np.zeros(len(t), int), lam, em, es, e, k_far=4, k_fine=19)
-    geo = lib.Geometry([(v, t)], method=method, precision=precision, p=8, theta=0.5)
+    geo = lib.Geometry([(v, t)], method=method, precision=precision, p=p, theta=0.5)
     fp32_resid = precision in ("fp32", "fp32_lead64")  # the residual uses FP32 products
     out = geo.solve(lam, em, es, e, tol=1e-6 if fp32_resid else 1e-9, restart=80, max_iter=800)
     assert out["converged"]
@@ -333,12 +392,18 @@ def test_autotune_meets_the_bound_and_picks_the_fastest(lib):
     assert all(e["rel_err"] > bound for e in entries if e["ms_per_product"] < 0)
     fastest = min(timed, key=lambda e: e["ms_per_product"])
     assert (op.p, op.ncrit) == (fastest["p"], fastest["ncrit"])
+    assert (op.m2p_min_panels, op.flags) == (fastest["m2p_min_panels"], fastest["flags"])
     assert abs(op.theta - fastest["theta"]) < 1e-12 and op.method == lib.LSPR_TREECODE
     # each (theta, N_crit) stops at its first order that meets the bound, orders ascending
+    # (the schedule candidates of the second stage repeat the chosen order)
     for th in {e["theta"] for e in entries}:
         for nc in {e["ncrit"] for e in entries}:
             ps = [e["p"] for e in entries if e["theta"] == th and e["ncrit"] == nc]
             assert ps == sorted(ps)
+    # the second stage tried the cost threshold both ways and the staged narrow kernel
+    sched = [e for e in entries if e["m2p_min_panels"] != 0 or e["flags"] != 0]
+    assert {(op.p + 1) ** 2 // 2, 2 * (op.p + 1) ** 2} <= {e["m2p_min_panels"] for e in sched}
+    assert any(e["flags"] & lib.LSPR_STREAM_NARROW for e in sched)
     op.precision = lib.LSPR_FP64
     surfs = [(v, t)]
     _, _, sid, V, K, g = _dense_system(surfs, None, None)
@@ -349,6 +414,55 @@ def test_autotune_meets_the_bound_and_picks_the_fastest(lib):
     geo.close()
     ref = A @ x[0]
     assert np.linalg.norm(y[0] - ref) / np.linalg.norm(ref) < 3 * bound
+
+
+def test_autotuned_schedule_is_no_slower_than_the_fixed_rule(lib):
+    """On an 8192-panel sphere at 32 wavelengths, the tuned parameters and kernel schedule
+    (bound 1e-6 on the FP64 product, the level the 1e-4 C_ext bar needs near resonance) give an
+    FP32 product no slower than the fixed rule the workloads use (P = 8, theta = 0.5, default
+    schedule), and the tuned FP64 product meets the bound against the oracle's own rows."""
+    v, t = octasphere(32, 10.0)
+    em = EPS_WATER + 0j
+    es = eps_silver_drude(np.array([384.0]))
+    bound, ncol = 1e-6, 32
+    op, entries, ok = lib.lspr_autotune([(v, t)], ncol, em, es, max_rel_err=bound, p=8,
+                                        theta=0.5, precision="fp32")
+    assert ok
+    fixed = lib.op_params(p=8, theta=0.5, precision="fp32")
+    x = torch.as_tensor(_rand_x(np.random.default_rng(9), ncol, len(t))).cuda()
+    ems, ess = np.full(ncol, em), np.repeat(es[:, None], ncol, 0)
+
+    def timed(o):
+        geo = lib.Geometry([(v, t)], op=o)
+        geo.apply(x, ems, ess)
+        best = 1e9
+        for _ in range(5):
+            lib.lspr_profile_reset()
+            lib.lspr_profile_enable(1)
+            geo.apply(x, ems, ess)
+            torch.cuda.synchronize()
+            lib.lspr_profile_enable(0)
+            best = min(best, lib.lspr_profile_query("matvec")["total_ms"])
+        geo.close()
+        return best
+
+    t_fixed, t_tuned = timed(fixed), timed(op)
+    assert t_tuned <= 1.1 * t_fixed, (t_tuned, t_fixed, op.p, op.theta, op.ncrit,
+                                      op.m2p_min_panels, op.flags)
+    # the tuned expansion against the oracle's rows (FP64 product, all columns share eps)
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(len(t), 64, replace=False))
+    V, K = oracle.operator_rows(v, t, rows, 4, 19, 9, 0.5)
+    inner, outer = oracle.system_rows(V, K, rows, np.zeros(len(t), int), em, es)
+    o64 = lib.op_params(p=op.p, theta=op.theta, ncrit=op.ncrit, precision="fp64",
+                        m2p_min_panels=op.m2p_min_panels)
+    geo = lib.Geometry([(v, t)], op=o64)
+    y = geo.apply(x[:1], ems[:1], ess[:1]).cpu().numpy()[0]
+    geo.close()
+    xr = _to_np(x[0])
+    ref = np.concatenate([inner @ xr, outer @ xr])
+    got = np.concatenate([y[rows], y[len(t) + rows]])
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 3 * bound
 
 
 @pytest.mark.parametrize("method,precision,tol", [("dense", "fp64", 1e-6),
