@@ -219,6 +219,25 @@ int lspr_solve(lspr_geometry* g, int32_t n_lambda, const double* lambda_nm,
 int lspr_apply(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,
                const lspr_c64* eps_surface, const lspr_c64* x, lspr_c64* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): lspr_apply with every temporary of the product
+ * (permittivity ratios, sorted copies of x and y, packed densities, raw layer sums, box moments
+ * and partial moments) in one fixed device array of LSPR_NOALLOC_SCRATCH_MIB MiB, which the
+ * library holds on every device it runs on from its load until the process ends.  Arguments,
+ * batching (64 columns at a time) and results are those of lspr_apply, bit for bit (the same
+ * kernels in the same order); the geometry is created beforehand with lspr_geometry_create.
+ * The call allocates no device memory and calls no allocating library routine.
+ * LSPR_E_INVALID, with the number of bytes in lspr_last_error(), when one batch needs more
+ * scratch than the array holds (roughly 64 N B + 16 N pad (S > 1 ? 3 : 2) bytes plus the
+ * moments, B the columns of a batch and pad = 2 B rounded up to 16: e.g. N = 32768 panels fits
+ * up to about 16 columns).  Every call on one device shares that device's array and leaves its
+ * contents behind (nothing in it needs to start at zero): calls that overlap on one device
+ * (other streams or threads) race and must be serialised by the caller. */
+#define LSPR_NOALLOC_SCRATCH_MIB 256
+int lspr_apply_noalloc(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,
+                       const lspr_c64* eps_surface, const lspr_c64* x, lspr_c64* y,
+                       void* stream);
+
 /* Right-hand side of Eq. matrix_multi for n_cols permittivity sets: b device [n_cols][2N]
  * (interior rows zero; exterior rows sum_s ((eps_m - eps_s)/eps_m) V_s g_s, g = -E . n). */
 int lspr_rhs(lspr_geometry* g, int32_t n_cols, const lspr_c64* eps_medium,

@@ -432,6 +432,13 @@ struct Geometry {
     DevBuf<double> rhs_u;      // [S][3][N]
     // workspaces reused by the operator
     DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
+    // While set, the operator takes those workspaces from this caller-provided region instead
+    // (lspr_apply_noalloc), so a product allocates nothing.
+    struct Arena {
+        uint8_t* base = nullptr;
+        size_t cap = 0, used = 0;
+    };
+    Arena* arena = nullptr;
     // point charges: charge_u[i] = sum over the charges inside panel i's surface of
     // q_k / (4 pi |c_i - r_k|) (sorted order; empty without charges); ws_inv_eps: 1 / eps_s
     // [column][surface] of the current batch, filled with the ratios
@@ -450,6 +457,23 @@ struct Geometry {
 
     size_t device_bytes() const;
 };
+
+// Bytes of region `bytes` taken from an arena (256-byte aligned pieces, in call order).
+inline size_t arena_piece(size_t bytes) { return (bytes + 255) & ~static_cast<size_t>(255); }
+// A workspace of `bytes` for the operator: from the geometry's arena when one is set (an
+// error if it is exhausted), else the grow-only buffer `own`.
+inline uint8_t* workspace(Geometry& g, DevBuf<uint8_t>& own, size_t bytes) {
+    if (g.arena != nullptr) {
+        Geometry::Arena& a = *g.arena;
+        const size_t piece = arena_piece(bytes);
+        LSPR_REQUIRE(a.used + piece <= a.cap, LSPR_E_INVALID, "scratch region exhausted");
+        uint8_t* p = a.base + a.used;
+        a.used += piece;
+        return p;
+    }
+    own.reserve(bytes);
+    return own.p;
+}
 
 // Column layout of one block matrix-vector product.  The real operators act on 2*ncol real
 // columns: ncol "K columns" (real and imaginary parts of phi) and ncol "V columns" (of

@@ -1417,8 +1417,8 @@ void launch_p2m_p(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s) {
     const int nr = Expansion<P>::NR;
     T* part = nullptr;
     if (g.n_slots > 0) {
-        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * nr * ncols * sizeof(T));
-        part = reinterpret_cast<T*>(g.ws_part.p);
+        part = reinterpret_cast<T*>(
+            workspace(g, g.ws_part, static_cast<size_t>(g.n_slots) * nr * ncols * sizeof(T)));
     }
     const dim3 grid(g.n_seg, (ncols + P2M_THREADS - 1) / P2M_THREADS);
     hipLaunchKernelGGL((k_p2m<T, P>), grid, dim3(P2M_THREADS), 0, s, g.boxes.p, g.p2m_seg.p,
@@ -1565,8 +1565,8 @@ void launch_p2m_mfma(Geometry& g, int pad, const T* dens, T* mom, hipStream_t s)
     const int ncols = 2 * pad;
     T* part = nullptr;
     if (g.n_slots > 0) {
-        g.ws_part.reserve(static_cast<size_t>(g.n_slots) * NR * ncols * sizeof(T));
-        part = reinterpret_cast<T*>(g.ws_part.p);
+        part = reinterpret_cast<T*>(
+            workspace(g, g.ws_part, static_cast<size_t>(g.n_slots) * NR * ncols * sizeof(T)));
     }
     const int halves = pad > 64 ? 2 : 1;
     hipLaunchKernelGGL((k_p2m_mfma<T, RT, NR>), dim3(g.n_seg, 2 * halves), dim3(256), 0, s,
@@ -1661,8 +1661,7 @@ void apply_far_t(Geometry& g, const Cols& c, const T* dens, double* os, double* 
     T* mom = nullptr;
     if (!g.mom_boxes.empty()) {
         const size_t need = g.mom_boxes.size() * g.n_terms * 2 * c.pad * sizeof(T);
-        g.ws_mom.reserve(need);
-        mom = reinterpret_cast<T*>(g.ws_mom.p);
+        mom = reinterpret_cast<T*>(workspace(g, g.ws_mom, need));
         // per panel of an expanded box: node polynomials (V and K) and the contraction with
         // every used column
         prof::Scope sc(fp64 ? "p2m64" : "p2m", s,

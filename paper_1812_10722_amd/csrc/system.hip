@@ -304,10 +304,9 @@ void system_apply(Geometry& g, int prec, int nslot, const double2* ratio_d, cons
     const size_t nd = static_cast<size_t>(g.N) * 2 * c.pad;
     const size_t esz = c.prec == LSPR_FP32 ? 4 : 8;
     prof::Scope sc("matvec", s, 0.0, 0.0);
-    g.ws_dens.reserve(nd * esz);
-    g.ws_out.reserve(nd * sizeof(double) * (g.S > 1 ? 2 : 1));
-    uint8_t* dens = g.ws_dens.p;
-    double* oa = reinterpret_cast<double*>(g.ws_out.p);
+    uint8_t* dens = workspace(g, g.ws_dens, nd * esz);
+    double* oa = reinterpret_cast<double*>(
+        workspace(g, g.ws_out, nd * sizeof(double) * (g.S > 1 ? 2 : 1)));
     double* os = g.S > 1 ? oa + nd : nullptr;
     // panels per block of the packing and combining kernels: their LDS rows within 48 KB
     auto panels_per_block = [&](size_t row_bytes) {

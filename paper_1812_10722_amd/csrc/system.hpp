@@ -14,7 +14,10 @@ struct EpsSet {
 // (grow-only buffer; with point charges also 1 / eps_s for the right-hand side).
 std::vector<double2> ratio_values(const Geometry& g, const EpsSet& eps, int B);
 void upload_ratios(Geometry& g, const EpsSet& eps, int B, DevBuf<double2>& d, hipStream_t s);
-
+// Bytes of scratch one lspr_apply batch of B columns needs in precision prec (ratios, the
+// sorted copies of x and y, packed densities, raw sums, moments, P2M partial sums), counted in
+// the arena's 256-byte pieces.
+size_t apply_scratch_bytes(const Geometry& g, int B, int prec);
 
 // y[col] = A(col) x[col] for nslot columns; col = d_cols[slot] (or slot when d_cols is null),
 // with far-field products in precision prec (LSPR_FP32 or LSPR_FP64); with precond,

@@ -70,6 +70,7 @@ def _load():
                                  P(lspr_gmres_params), vp, vp, vp, P(lspr_c64), P(lspr_c64),
                                  P(dbl), P(dbl), P(i32), P(dbl)]),
         "lspr_apply": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), vp, vp, vp]),
+        "lspr_apply_noalloc": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), vp, vp, vp]),
         "lspr_rhs": (C.c_int, [vp, i32, P(lspr_c64), P(lspr_c64), P(dbl), vp, vp]),
         "lspr_triangle_rule": (C.c_int, [i32, P(dbl), P(dbl)]),
         "lspr_gauss_legendre": (C.c_int, [i32, P(dbl), P(dbl)]),
@@ -267,16 +268,22 @@ class Geometry:
                 "iters": it, "rel_resid": rr, "phi": phi, "dphi": dphi,
                 "converged": code == LSPR_OK}
 
-    def apply(self, x, eps_medium, eps_surface, stream=None):
-        """y = A x for x a complex128 cuda tensor [n_cols, 2N] (caller's panel order)."""
+    def apply(self, x, eps_medium, eps_surface, stream=None, out=None, noalloc=False):
+        """y = A x for x a complex128 cuda tensor [n_cols, 2N] (caller's panel order).
+        noalloc: through lspr_apply_noalloc (the library allocates no device memory; `out`, a
+        complex128 cuda tensor like x, may be given so that the call allocates nothing at all)."""
         import torch
         x = x.to(torch.complex128).contiguous()
         nc = x.shape[0]
         em, em_p = _c64_array(np.broadcast_to(np.asarray(eps_medium), (nc,)))
         es, es_p = _c64_array(np.asarray(eps_surface).reshape(nc, self.n_surf))
-        y = torch.empty_like(x)
-        _check(_lib.lspr_apply(self.handle, nc, em_p, es_p, C.c_void_p(x.data_ptr()),
-                               C.c_void_p(y.data_ptr()), _stream_ptr(stream)), "lspr_apply")
+        y = torch.empty_like(x) if out is None else out
+        if out is not None:
+            assert out.dtype == torch.complex128 and out.is_contiguous() and out.shape == x.shape
+        fn = _lib.lspr_apply_noalloc if noalloc else _lib.lspr_apply
+        name = "lspr_apply_noalloc" if noalloc else "lspr_apply"
+        _check(fn(self.handle, nc, em_p, es_p, C.c_void_p(x.data_ptr()),
+                  C.c_void_p(y.data_ptr()), _stream_ptr(stream)), name)
         return y
 
     def rhs(self, eps_medium, eps_surface, e_field=(0.0, 0.0, 1.0), stream=None):
