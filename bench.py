@@ -330,6 +330,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run a workload's fixed treecode settings instead of the autotuner's")
+    ap.add_argument("--op", action="append", default=[], metavar="KEY=VALUE",
+                    help="override an operator parameter of the workload (p, theta, ncrit, "
+                         "m2p_min_panels, split_operators, stream_narrow, pair_operators, ...); "
+                         "implies --no-autotune")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests of the serving leg (default 16, or 200 with --serving-only; "
                          "0 skips it)")
@@ -373,6 +377,11 @@ def main():
     gm = dict(w.gmres)
     if args.precision:
         op["precision"] = args.precision
+    for kv in args.op:
+        k, v = kv.split("=", 1)
+        op[k] = (v.lower() == "true") if v.lower() in ("true", "false") else \
+            (int(v) if v.lstrip("-").isdigit() else (float(v) if k == "theta" else v))
+        args.no_autotune = True
     if args.inner_tol is not None:
         gm["inner_tol"] = args.inner_tol
     if args.tol is not None:
@@ -400,7 +409,8 @@ def main():
                                  and e["flags"] == top.flags), None)}
         op.update(p=top.p, theta=top.theta, ncrit=top.ncrit, m2p_min_panels=top.m2p_min_panels,
                   split_operators=not (top.flags & lspr.LSPR_NO_SPLIT_OPERATORS),
-                  stream_narrow=bool(top.flags & lspr.LSPR_STREAM_NARROW))
+                  stream_narrow=bool(top.flags & lspr.LSPR_STREAM_NARROW),
+                  pair_operators=bool(top.flags & lspr.LSPR_PAIR_OPERATORS))
         log(f"[bench] autotune: P={top.p} theta={top.theta} ncrit={top.ncrit} "
             f"m2p_min_panels={top.m2p_min_panels} flags={top.flags} ({tuned['seconds']:.1f} s, "
             f"{len(entries)} candidates)")

@@ -53,7 +53,12 @@ enum lspr_status {
 
 enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
 enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2, LSPR_FP32_LEAD64 = 3 };
-enum lspr_flags { LSPR_NO_MATRIX_CORES = 1, LSPR_NO_SPLIT_OPERATORS = 2, LSPR_STREAM_NARROW = 4 };
+enum lspr_flags {
+    LSPR_NO_MATRIX_CORES = 1,
+    LSPR_NO_SPLIT_OPERATORS = 2,
+    LSPR_STREAM_NARROW = 4,
+    LSPR_PAIR_OPERATORS = 8
+};
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
  * counter-clockwise seen from outside (outward right-hand normal, as the paper's dipole
@@ -106,7 +111,10 @@ typedef struct {
  *             one workgroup per operator (same sums; a tuning alternative).
  *             bit 2: products of up to 16 wavelengths stream every wave's operands from
  *             memory instead of staging each left factor in LDS for the workgroup (identical
- *             sums; a tuning alternative, faster for FP64 products of up to 8 wavelengths). */
+ *             sums; a tuning alternative, faster for FP64 products of up to 8 wavelengths).
+ *             bit 3: products of more than 16 wavelengths run eight-wave workgroups that stage
+ *             each left factor once for both operators (identical sums; a tuning
+ *             alternative). */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;
@@ -374,16 +382,18 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
  * op->precision is LSPR_FP64), fastest of three after one warm-up, HIP events on `stream`.
  * Stage 2, on the fastest of those: the kernel schedule, timed the same way: m2p_min_panels at
  * half and twice its default ((P+1)^2; the error is checked again), both operators in one
- * workgroup (LSPR_NO_SPLIT_OPERATORS, FP32 products), and for n_cols <= 16 the streamed
- * narrow kernel (LSPR_STREAM_NARROW).  The fastest candidate that meets the bound is written
+ * workgroup (LSPR_NO_SPLIT_OPERATORS, FP32 products), for n_cols <= 16 the streamed narrow
+ * kernel (LSPR_STREAM_NARROW), for n_cols > 16 the paired-operator workgroups
+ * (LSPR_PAIR_OPERATORS).  The fastest candidate that meets the bound is written
  * to op->p, op->theta, op->ncrit, op->m2p_min_panels and op->flags (op->method becomes
  * LSPR_TREECODE; the other fields are kept and used for every candidate).
  *   surfaces     device pointers, as lspr_geometry_create
  *   n_cols       columns of the timed product, 1..64
  *   eps_medium   host [1]; eps_surface host [n_surf]
  *   entries      host [max_entries] or null: every candidate tried, in order (ms_per_product
- *                -1 when it was not timed); *n_entries receives their number (it may exceed
- *                max_entries, the rest is not stored)
+ *                -1 when it was not timed; rel_err infinite for a candidate whose set-up did
+ *                not fit the device, which also ends that (theta, N_crit)'s orders); *n_entries
+ *                receives their number (it may exceed max_entries, the rest is not stored)
  * Device memory: the reference geometry (dense FP64 tiles, 16 N^2 bytes, when they fit) and one
  * candidate geometry at a time.  LSPR_E_NOCONV when no candidate meets the bound (op then holds
  * the most accurate one); LSPR_E_INVALID for bad arguments. */

@@ -61,7 +61,7 @@ hipMemPool_t library_pool() {
     props.location.id = dev;
     hipMemPool_t pool = nullptr;
     LSPR_HIP(hipMemPoolCreate(&pool, &props));
-    uint64_t keep = 16ull << 30;
+    uint64_t keep = 64ull << 30;
     LSPR_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
     pools[dev] = pool;
     return pool;
@@ -76,7 +76,7 @@ struct CachedBlock {
 };
 std::mutex cache_mu;
 std::vector<CachedBlock> cache;  // every device's pools; blocks are few and large
-constexpr size_t CACHE_CAP = 16ull << 30;
+constexpr size_t CACHE_CAP = 64ull << 30;
 size_t cached_bytes(hipMemPool_t pool) {
     size_t t = 0;
     for (const CachedBlock& b : cache) t += b.pool == pool ? b.bytes : 0;
@@ -308,6 +308,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
     if (op->flags & LSPR_NO_SPLIT_OPERATORS) g.far_op_min_pad = 0;
     g.stream_narrow = (op->flags & LSPR_STREAM_NARROW) != 0;
+    g.pair_ops = (op->flags & LSPR_PAIR_OPERATORS) != 0;
     lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);
@@ -784,7 +785,16 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
             // both tile stores: FP64 for the error, the timed precision for speed
             cc.precision = tprec == LSPR_FP64 ? LSPR_FP64 : LSPR_FP32_LEAD64;
             lspr::Geometry g;
-            lspr::create_geometry(g, surfaces, n_surf, cc, s);
+            try {
+                lspr::create_geometry(g, surfaces, n_surf, cc, s);
+            } catch (const lspr::Error& err) {
+                // a candidate whose set-up does not fit the device is skipped (rel_err infinite)
+                if (err.code != LSPR_E_NOMEM) throw;
+                (void)hipGetLastError();
+                LSPR_HIP(hipStreamSynchronize(s));
+                t.rel_err = HUGE_VAL;
+                return t;
+            }
             product(g, LSPR_FP64, y.p);
             LSPR_HIP(hipMemcpy(yh.data(), y.p, nvec * sizeof(double2), hipMemcpyDeviceToHost));
             double dn = 0.0;
@@ -836,7 +846,8 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
                         best = t;
                     if (t.rel_err < closest.rel_err) closest = t;
                     record(t);
-                    if (t.rel_err <= max_rel_err) break;  // a higher order only costs more
+                    // a higher order only costs more (and one that did not fit, more memory)
+                    if (t.rel_err <= max_rel_err || t.rel_err == HUGE_VAL) break;
                 }
         // stage 2: the kernel schedule of the best expansion: the cost threshold for expanding a
         // box (half and twice the default of one panel per Taylor term; it moves work between
@@ -859,6 +870,11 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
             if (tprec == LSPR_FP32) {
                 lspr_op_params c = b;
                 c.flags |= LSPR_NO_SPLIT_OPERATORS;
+                sched.push_back(c);
+            }
+            if (n_cols > 16) {
+                lspr_op_params c = b;
+                c.flags |= LSPR_PAIR_OPERATORS;
                 sched.push_back(c);
             }
             if (n_cols <= 16) {

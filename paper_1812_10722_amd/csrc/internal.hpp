@@ -50,13 +50,14 @@ struct AllocCtx {
 };
 AllocCtx& alloc_ctx();
 
-// The library's memory pool on the current device (created on first use; keeps up to 16 GiB of
+// The library's memory pool on the current device (created on first use; keeps up to 64 GiB of
 // freed memory for reuse instead of returning it at every synchronisation).
 hipMemPool_t library_pool();
 
 // Cache of large released blocks of the library pool.  Returning a pool allocation of several
 // GB costs the host about 1.3 ms per GB, and obtaining it again a few tenths of a ms, so blocks
-// of at least BIG_BLOCK bytes are kept (up to 16 GiB per pool) and handed to the next request
+// of at least BIG_BLOCK bytes are kept (up to 64 GiB per pool: the tile stores of a 100k-panel
+// geometry in both precisions) and handed to the next request
 // of a size they cover.  A kept block is reusable once an event recorded on its last stream
 // has completed; the taker's stream waits for that event.
 constexpr size_t BIG_BLOCK = 32ull << 20;
@@ -450,6 +451,8 @@ struct Geometry {
                               // one operator per workgroup (0: never)
     bool stream_narrow = false;  // products of up to 16 wavelengths stream their operands
                                  // (k_far_stream) instead of staging them in LDS
+    bool pair_ops = false;  // products of more than 16 wavelengths stage each left factor once
+                            // for both operators (eight-wave workgroups)
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 55 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the
     // matrix-core products then need no separate near-field pass)

@@ -649,14 +649,20 @@ __device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) 
 // Narrow products (one or two column groups per operator) split the K-steps instead: S = 4 / G
 // waves share each of the G column groups, wave k taking steps k, k + S, ...; at the end their
 // FP64 sums are added in wave order through LDS.  S = 1 is the wide kernel.
-template <class T, int NSM, int S>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4))
+// OPS = 2 (wide products only): eight waves per workgroup, waves 0-3 on the K columns and 4-7 on
+// the V columns of one column half, so each left factor is staged once for both operators (a
+// direct tile's two factors side by side) and a chunk's tiles are read by `halves` workgroups
+// instead of 2 * halves; each wave's arithmetic is that of OPS = 1.
+template <class T, int NSM, int S, int OPS = 1>
+__global__ void __launch_bounds__(256 * OPS, OPS == 2 ? (sizeof(T) == 8 ? 1 : 2)
+                                                      : (sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4)))
 k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
                const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
                const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
                int halves, double* __restrict__ out_self, double* __restrict__ out_all) {
-    constexpr int NTHR = 256;
+    static_assert(OPS == 1 || (OPS == 2 && S == 1), "both operators per workgroup: wide only");
+    constexpr int NTHR = 256 * OPS;
     constexpr uint32_t ES = sizeof(T);       // bytes per element
     constexpr int EPU = 16 / sizeof(T);      // elements per 16-byte unit
     using Acc = typename Mma<T>::acc;
@@ -664,14 +670,16 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, grp = lane >> 4;
     const int ncols = 2 * pad;
-    // 2 * halves workgroups per chunk, at b, b + 8, ...: operator j & 1, column half j >> 1
+    // OPS = 1: 2 * halves workgroups per chunk, at b, b + 8, ...: operator j & 1, column half
+    // j >> 1.  OPS = 2: halves workgroups per chunk, column half j, operator wave / 4.
     const int b = blockIdx.x;
-    const int per = 2 * halves;
+    const int per = OPS == 2 ? halves : 2 * halves;
     const int j = (b >> 3) % per;
-    const int opr = j & 1;                  // 0: K columns, 1: V columns
-    constexpr int G = 4 / S;                // column groups per workgroup
-    const int kpart = wave % S;             // this wave's share of the K-steps
-    const int wg = wave / S + G * (j >> 1); // column group of this wave
+    const int opr = OPS == 2 ? wave >> 2 : j & 1;  // 0: K columns, 1: V columns
+    const int hj = OPS == 2 ? j : j >> 1;          // column half
+    constexpr int G = 4 / S;                // column groups per workgroup and operator
+    const int kpart = (wave & 3) % S;       // this wave's share of the K-steps
+    const int wg = (wave & 3) / S + G * hj; // column group of this wave
     const int chunk = chunk_order[(b >> 3) / per * 8 + (b & 7)];
     if (chunk < 0) return;
     const Chunk C = chunks[chunk];
@@ -767,11 +775,14 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         return D;
     };
     // the part of a left factor this workgroup uses: all of an expansion tile, the factor of its
-    // own operator of a direct tile (its first element, count)
+    // own operator of a direct tile, or with OPS = 2 both (its first element, count)
     auto own_off = [&](const TileDesc& D) {
-        return D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
+        return D.a_off() +
+               (OPS == 1 && D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
     };
-    auto own_elems = [](const TileDesc& D) { return 256 * D.nstep; };
+    auto own_elems = [](const TileDesc& D) {
+        return 256 * D.nstep * (OPS == 2 && D.kind == 1 ? 2 : 1);
+    };
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
     T bc[NBS];
@@ -785,8 +796,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     }
     __syncthreads();
     // a left factor is NA elements per thread: NA / EPU 16-byte units at unit index
-    // tid + 256 r, then NA % EPU elements at element index 256 EPU (NA / EPU) + tid + 256 r
-    constexpr int NA = NSM > DSTEPS ? NSM : DSTEPS;
+    // tid + NTHR r, then NA % EPU elements at element index NTHR EPU (NA / EPU) + tid + NTHR r
+    constexpr int NA = OPS == 1 ? (NSM > DSTEPS ? NSM : DSTEPS)
+                                : ((NSM + 1) / 2 > DSTEPS ? (NSM + 1) / 2 : DSTEPS);
     constexpr int QA = NA / EPU, RA = NA % EPU;
     // one tile: prefetches for the next, products of this one (all waves of the workgroup run
     // it together: it ends with a barrier)
@@ -810,11 +822,12 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             }
 #pragma unroll
             for (int r = 0; r < RA; ++r)
-                pr[r] = load_elem<T>(ra, tid * ES, (QA * EPU * 256 + r * NTHR) * ES);
+                pr[r] = load_elem<T>(ra, tid * ES, (QA * EPU * NTHR + r * NTHR) * ES);
         }
         const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
         if (mma) {
-            const float4* ab = abuf16;
+            // with OPS = 2 the V waves read a direct tile's second factor
+            const float4* ab = abuf16 + (OPS == 2 && Te.kind == 1 ? opr * Te.nstep * 256 / EPU : 0);
 #define LSPR_OP_TILE(NS)                                                             \
     if constexpr (S == 1) {                                                                \
         uint32_t so = 0;                                                                   \
@@ -868,7 +881,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             T* dst1 = reinterpret_cast<T*>(dst);
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
-                const int k = QA * EPU * 256 + tid + r * NTHR;  // element index
+                const int k = QA * EPU * NTHR + tid + r * NTHR;  // element index
                 if (k < EPU * n16n) {
                     if constexpr (sizeof(T) == 4) dst1[k] = pr[r];
                     else dst1[lds_unit<T>(k / EPU) * EPU + k % EPU] = pr[r];
@@ -1454,20 +1467,22 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
-template <class T, int NSM, int S>
+template <class T, int NSM, int S, int OPS = 1>
 void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                            double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
-    const int nblk = g.n_order * 2 * halves;
-    // the left factor, then (S > 1) one slot of FP64 sums per column group for the final additions
-    const size_t lds = static_cast<size_t>(abuf) * sizeof(T) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
+    const int nblk = g.n_order * (OPS == 2 ? 1 : 2) * halves;
+    // the left factor (OPS = 2: a direct tile's two), then (S > 1) one slot of FP64 sums per
+    // column group for the final additions
+    const size_t ab = OPS == 2 ? std::max<size_t>(abuf, 2 * DSTEPS * 256) : abuf;
+    const size_t lds = ab * sizeof(T) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
     if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles_op<T, NSM, S>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles_op<T, NSM, S, OPS>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(lds));
-    hipLaunchKernelGGL((k_far_tiles_op<T, NSM, S>), dim3(nblk), dim3(256), lds, s, g.chunks.p,
-                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g),
-                       dens, mom, pad, pad / 16, halves, os, oa);
+    hipLaunchKernelGGL((k_far_tiles_op<T, NSM, S, OPS>), dim3(nblk), dim3(256 * OPS), lds, s,
+                       g.chunks.p, g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p,
+                       tiles_of<T>(g), dens, mom, pad, pad / 16, halves, os, oa);
     LSPR_HIP(hipGetLastError());
 }
 
@@ -1494,6 +1509,8 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
     } else if (groups == 2) {
         if (g.stream_narrow) launch_far_stream<T, NSM, 2>(g, pad, dens, mom, os, oa, s);
         else launch_far_tiles_op_s<T, NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
+    } else if (g.pair_ops) {
+        launch_far_tiles_op_s<T, NSM, 1, 2>(g, pad, abuf, dens, mom, os, oa, s);
     } else {
         launch_far_tiles_op_s<T, NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
     }

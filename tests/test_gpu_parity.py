@@ -187,6 +187,26 @@ def _to_np(t):
     return t.cpu().numpy()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_paired_operator_workgroups_equal_split(lib, precision):
+    """Wide products in eight-wave workgroups that stage each left factor once for both
+    operators: each wave's arithmetic is that of the one-operator workgroups, so the results are
+    equal bit for bit (20 to 64 wavelengths: one or two column halves)."""
+    surfs = sensor_and_blob(10, 7)
+    kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
+    paired = lib.Geometry(surfs, pair_operators=True, **kw)
+    split = lib.Geometry(surfs, **kw)
+    rng = np.random.default_rng(23)
+    n = paired.n_panels
+    for nl in (17, 20, 40, 64):
+        eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
+        eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(nl), np.full(nl, 2.5 + 0.1j)], 1)
+        xt = torch.as_tensor(_rand_x(rng, nl, n)).cuda()
+        a = paired.apply(xt, eps_m, eps_s).cpu().numpy()
+        b = split.apply(xt, eps_m, eps_s).cpu().numpy()
+        assert np.array_equal(a, b), (nl, np.abs(a - b).max())
+
+
 # ----------------------------------------------------------------------------- full solves
 def test_sphere_512_dense_fp64_matches_oracle(lib):
     """The 512-panel silver sphere (lambda = 380 nm) solved by the GPU dense FP64 path equals the
