@@ -57,7 +57,8 @@ enum lspr_flags {
     LSPR_NO_MATRIX_CORES = 1,
     LSPR_NO_SPLIT_OPERATORS = 2,
     LSPR_STREAM_NARROW = 4,
-    LSPR_PAIR_OPERATORS = 8
+    LSPR_PAIR_OPERATORS = 8,
+    LSPR_PAIR_NARROW = 16
 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
@@ -114,7 +115,8 @@ typedef struct {
  *             sums; a tuning alternative, faster for FP64 products of up to 8 wavelengths).
  *             bit 3: products of more than 16 wavelengths run eight-wave workgroups that stage
  *             each left factor once for both operators (identical sums; a tuning
- *             alternative). */
+ *             alternative).
+ *             bit 4: the same for products of up to 16 wavelengths. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;

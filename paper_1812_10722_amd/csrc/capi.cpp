@@ -165,6 +165,20 @@ void pinned_put(PinnedBuf b) {
     for (const PinnedBuf& f : drop) (void)hipHostFree(f.p);
 }
 
+size_t reusable_bytes(hipMemPool_t pool) {
+    if (pool == nullptr) return 0;
+    size_t cached = 0;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        cached = cached_bytes(pool);
+    }
+    uint64_t reserved = 0, used = 0;
+    if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &reserved) != hipSuccess ||
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemCurrent, &used) != hipSuccess)
+        return cached;
+    return cached + (reserved > used ? static_cast<size_t>(reserved - used) : 0);
+}
+
 bool big_block_flush(hipMemPool_t pool) {
     std::lock_guard<std::mutex> lk(cache_mu);
     bool any = false;
@@ -309,6 +323,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     if (op->flags & LSPR_NO_SPLIT_OPERATORS) g.far_op_min_pad = 0;
     g.stream_narrow = (op->flags & LSPR_STREAM_NARROW) != 0;
     g.pair_ops = (op->flags & LSPR_PAIR_OPERATORS) != 0;
+    g.pair_narrow = (op->flags & LSPR_PAIR_NARROW) != 0;
     lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);
@@ -322,9 +337,12 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     if (g.tile_budget_bytes <= 0.0) {
         size_t free_b = 0, total_b = 0;
         LSPR_HIP(hipMemGetInfo(&free_b, &total_b));
-        // both stores of the 491k-panel sensor (42 + 85 GB) fit on one MI355X beside its
-        // Krylov state (15 GB at 16 wavelengths)
-        g.tile_budget_bytes = 0.55 * static_cast<double>(free_b);
+        // free memory plus what the library's pool holds for reuse (cached blocks and reserved
+        // memory not in use: an allocation that does not fit returns them first).  Both stores
+        // of the 491k-panel sensor (48 + 96 GB at P = 10) fit on one MI355X beside its Krylov
+        // state (15 GB at 16 wavelengths).
+        const size_t avail = free_b + lspr::reusable_bytes(lspr::alloc_ctx().pool);
+        g.tile_budget_bytes = 0.55 * static_cast<double>(std::min(avail, total_b));
     }
     // no tile plan when not even one store of a needed precision fits (e.g. every pair of a
     // large mesh summed directly): the products then run on the vector ALUs

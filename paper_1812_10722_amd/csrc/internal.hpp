@@ -68,6 +68,8 @@ void* big_block_take(hipMemPool_t pool, size_t bytes, hipStream_t s, size_t* got
 bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s);
 // Frees every cached block of `pool` (after their last uses); true if there was any.
 bool big_block_flush(hipMemPool_t pool);
+// Bytes `pool` holds for reuse: cached blocks and reserved memory not in use (0 for no pool).
+size_t reusable_bytes(hipMemPool_t pool);
 
 // Installs the library pool and `stream` for allocations, and `stream` for frees, for the
 // lifetime of the object, unless the thread already has a pool (the request server's).
@@ -453,6 +455,7 @@ struct Geometry {
                                  // (k_far_stream) instead of staging them in LDS
     bool pair_ops = false;  // products of more than 16 wavelengths stage each left factor once
                             // for both operators (eight-wave workgroups)
+    bool pair_narrow = false;  // the same for products of up to 16 wavelengths
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 55 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the
     // matrix-core products then need no separate near-field pass)

@@ -649,10 +649,10 @@ __device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) 
 // Narrow products (one or two column groups per operator) split the K-steps instead: S = 4 / G
 // waves share each of the G column groups, wave k taking steps k, k + S, ...; at the end their
 // FP64 sums are added in wave order through LDS.  S = 1 is the wide kernel.
-// OPS = 2 (wide products only): eight waves per workgroup, waves 0-3 on the K columns and 4-7 on
-// the V columns of one column half, so each left factor is staged once for both operators (a
-// direct tile's two factors side by side) and a chunk's tiles are read by `halves` workgroups
-// instead of 2 * halves; each wave's arithmetic is that of OPS = 1.
+// OPS = 2: eight waves per workgroup, waves 0-3 on the K columns and 4-7 on the V columns (of
+// one column half), so each left factor is staged once for both operators (a direct tile's two
+// factors side by side) and a chunk's tiles are read by `halves` workgroups instead of
+// 2 * halves; each wave's arithmetic is that of OPS = 1.
 template <class T, int NSM, int S, int OPS = 1>
 __global__ void __launch_bounds__(256 * OPS, OPS == 2 ? (sizeof(T) == 8 ? 1 : 2)
                                                       : (sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4)))
@@ -661,7 +661,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
                const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
                int halves, double* __restrict__ out_self, double* __restrict__ out_all) {
-    static_assert(OPS == 1 || (OPS == 2 && S == 1), "both operators per workgroup: wide only");
+    static_assert(OPS == 1 || OPS == 2, "one or both operators per workgroup");
     constexpr int NTHR = 256 * OPS;
     constexpr uint32_t ES = sizeof(T);       // bytes per element
     constexpr int EPU = 16 / sizeof(T);      // elements per 16-byte unit
@@ -714,10 +714,12 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 #pragma unroll
             for (int q = 0; q < 4; ++q) sum[mt][q] = own(mt, q);
         if constexpr (S > 1) {
-            // one 8 KB slot per column group, passed from wave to wave
-            constexpr int NAB = NSM > DSTEPS ? NSM : DSTEPS;  // 16-byte units per lane / EPU
-            double* red = reinterpret_cast<double*>(abuf16 + NAB * 64 * 4 / EPU) +
-                          (wave / S) * 16 * 64;
+            // one 8 KB slot per column group (and operator), passed from wave to wave; the slots
+            // follow the left-factor buffer
+            constexpr int AEL = OPS == 2 ? (NSM > 2 * DSTEPS ? NSM : 2 * DSTEPS) * 256
+                                         : (NSM > DSTEPS ? NSM : DSTEPS) * 256;
+            double* red = reinterpret_cast<double*>(abuf16 + AEL / EPU) +
+                          ((wave & 3) / S + (OPS == 2 ? opr * G : 0)) * 16 * 64;
             for (int k = 1; k < S; ++k) {
                 if (kpart == k)
 #pragma unroll
@@ -1475,7 +1477,7 @@ void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const 
     // the left factor (OPS = 2: a direct tile's two), then (S > 1) one slot of FP64 sums per
     // column group for the final additions
     const size_t ab = OPS == 2 ? std::max<size_t>(abuf, 2 * DSTEPS * 256) : abuf;
-    const size_t lds = ab * sizeof(T) + (S > 1 ? (4 / S) * 16 * 64 * 8 : 0);
+    const size_t lds = ab * sizeof(T) + (S > 1 ? OPS * (4 / S) * 16 * 64 * 8 : 0);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles_op<T, NSM, S, OPS>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1505,9 +1507,11 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
     const int groups = pad / 16;
     if (groups == 1) {
         if (g.stream_narrow) launch_far_stream<T, NSM, 4>(g, pad, dens, mom, os, oa, s);
+        else if (g.pair_narrow) launch_far_tiles_op_s<T, NSM, 4, 2>(g, pad, abuf, dens, mom, os, oa, s);
         else launch_far_tiles_op_s<T, NSM, 4>(g, pad, abuf, dens, mom, os, oa, s);
     } else if (groups == 2) {
         if (g.stream_narrow) launch_far_stream<T, NSM, 2>(g, pad, dens, mom, os, oa, s);
+        else if (g.pair_narrow) launch_far_tiles_op_s<T, NSM, 2, 2>(g, pad, abuf, dens, mom, os, oa, s);
         else launch_far_tiles_op_s<T, NSM, 2>(g, pad, abuf, dens, mom, os, oa, s);
     } else if (g.pair_ops) {
         launch_far_tiles_op_s<T, NSM, 1, 2>(g, pad, abuf, dens, mom, os, oa, s);

@@ -189,16 +189,17 @@ def _to_np(t):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_paired_operator_workgroups_equal_split(lib, precision):
-    """Wide products in eight-wave workgroups that stage each left factor once for both
-    operators: each wave's arithmetic is that of the one-operator workgroups, so the results are
-    equal bit for bit (20 to 64 wavelengths: one or two column halves)."""
+    """Products in eight-wave workgroups that stage each left factor once for both operators:
+    each wave's arithmetic is that of the one-operator workgroups, so the results are equal bit
+    for bit (1 to 16 wavelengths: the K-steps split over 4 or 2 waves per column group; 17 to 64:
+    one or two column halves)."""
     surfs = sensor_and_blob(10, 7)
     kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
-    paired = lib.Geometry(surfs, pair_operators=True, **kw)
+    paired = lib.Geometry(surfs, pair_operators=True, pair_narrow=True, **kw)
     split = lib.Geometry(surfs, **kw)
     rng = np.random.default_rng(23)
     n = paired.n_panels
-    for nl in (17, 20, 40, 64):
+    for nl in (1, 5, 8, 9, 16, 17, 20, 40, 64):
         eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
         eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(nl), np.full(nl, 2.5 + 0.1j)], 1)
         xt = torch.as_tensor(_rand_x(rng, nl, n)).cuda()
