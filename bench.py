@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("treecode matvec Gpair/s; wavelength-solves/s at 1e-4 rel err vs FP64; p50/p99")
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X datasheet, dense FP32 matrix cores (measured sustained: 155)
 PEAK_FP64_MFMA_TFLOPS = 78.6    # MI355X datasheet, dense FP64 matrix cores
+PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X datasheet, FP32 vector (packed); 78.6 unpacked
 PEAK_HBM_GBS = 8000.0
 WIDTH_BINS = ((1, 8), (9, 16), (17, 32), (33, 64))  # wavelengths per far-field launch
 
@@ -500,11 +501,18 @@ def main():
     value = accuracy["within_1e-4"] * args.steps / total if accuracy else None
     far = far_timed
     achieved = far["flops"] / (far["total_ms"] * 1e-3) / 1e12 if far["total_ms"] > 0 else 0.0
-    trec = traffic_entry(os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"), "far")
+    mfma = op.get("matrix_cores", True) and info["n_tiles"] > 0
+    # without tiles the far field is FP32 vector arithmetic: 256 CUs x 64 lanes x 2 flops (FMA)
+    # x 2 (packed FP32) x 2.4 GHz
+    peak = PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS
+    trec = traffic_entry(os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"),
+                         "far") if mfma else None
     roofline = {"kernel": "k_far_tiles_op (FP32 matrix-core far field: expansion and direct "
-                          "far-rule tiles)", "bound": "mfma",
-                "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                          "far-rule tiles)" if mfma else
+                          "k_far (FP32 vector-ALU far field, no tiles kept)",
+                "bound": "mfma" if mfma else "alu",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak,
                 "traffic": (trec["bytes_per_launch"] if trec else None),
                 "launches": far["launches"],
                 "avg_launch_ms": far["total_ms"] / max(far["launches"], 1),
