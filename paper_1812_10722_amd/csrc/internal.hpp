@@ -339,7 +339,9 @@ struct P2MRed {
 // One left factor of the matrix-core far-field product, stored in MFMA operand order.
 // kind 0: expansion (Taylor coefficients; B rows = moments rows b_row0 .. b_row0 + b_rows);
 // kind 1: direct tile (double-layer then single-layer kernel values; B rows = density rows of
-// panels b_row0 .. b_row0 + b_rows).  nstep K-steps of 4 rows; the left factor starts at
+// panels b_row0 .. b_row0 + b_rows); kind 2 (the products' list only): two consecutive direct
+// tiles of one source range, the first full, stored one after the other (B rows = the 32 + up
+// to 32 panels of both).  nstep K-steps of 4 rows; the left factor starts at
 // element 256 a_blk of the tile store (every tile is a multiple of 256 elements).  16 bytes, so
 // a kernel fetches a descriptor with one 128-bit load.
 struct TileDesc {
@@ -349,6 +351,19 @@ struct TileDesc {
     __host__ __device__ int64_t a_off() const { return static_cast<int64_t>(a_blk) * 256; }
 };
 static_assert(sizeof(TileDesc) == 16, "tile descriptors are fetched as one 128-bit load");
+
+// A work item of the one-operator matrix-core far-field kernel: tiles [t0, t1) of a chunk.
+// slot < 0: the whole chunk, whose sums the kernel writes itself; slot >= 0: a piece of a
+// chunk cut into several (never across its own-surface/other-surface boundary), whose FP64
+// partial sums go to scratch block `slot` for k_far_reduce.
+struct FarItem {
+    int32_t chunk, t0, t1, slot;
+};
+// A chunk cut into pieces: its partial sums are scratch blocks [slot0, slot1), the first
+// `nself` of them over own-surface tiles; they are added in block order.
+struct FarRed {
+    int32_t chunk, slot0, slot1, nself;
+};
 
 // One entry of a chunk's direct-sum list: source panels [start, end) of one surface.
 struct Range {
@@ -399,8 +414,29 @@ struct Geometry {
     int64_t tile_elems = 0;  // elements of one tile store (the left factors of one precision)
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
+    // the tiles as the FP64 products visit them: the same left factors, with consecutive
+    // direct tiles of a source range paired (kind 2) when the kernels' operand registers hold
+    // two; own-surface tiles of each chunk in this list
+    DevBuf<TileDesc> ktiles;
+    DevBuf<int32_t> ktile_self;
     DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)
     int n_order = 0;              // entries of chunk_order (a multiple of 8)
+    // Work items of the one-operator far-field kernel, one set per launch class (0: up to 16
+    // wavelengths, 1: more): chunks heavier than a share of the mean are cut into pieces of
+    // about that cost, so that no workgroup holds the launch's tail alone.
+    struct FarPlan {
+        DevBuf<FarItem> items;
+        DevBuf<int32_t> order;  // workgroup -> item (-1: none); a multiple of 8 entries
+        DevBuf<FarRed> red;     // chunks cut into pieces
+        int n_order = 0, n_red = 0, n_slots = 0;
+        size_t bytes() const { return items.bytes() + order.bytes() + red.bytes(); }
+    };
+    FarPlan far_plan[2][2];  // [tile list: 0 tiles, 1 ktiles][launch class]
+    // largest piece, as a fraction of the mean chunk cost, per launch class (0: no pieces):
+    // measured on the 32768-panel sphere (busiest chunk 1.95 x the mean), 0.35 for up to 16
+    // wavelengths (every workgroup resident at once: the busiest chunk set the launch time)
+    // and 0.5 above
+    double far_split[2] = {0.35, 0.5};
     DevBuf<float> tileA;      // FP32 left factors (need32)
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
@@ -434,7 +470,7 @@ struct Geometry {
     // geometry part of the right-hand side: u[s][d][i] = sum_{j in s} V_ij (-n_j,d)
     DevBuf<double> rhs_u;      // [S][3][N]
     // workspaces reused by the operator
-    DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part;
+    DevBuf<uint8_t> ws_dens, ws_mom, ws_out, ws_part, ws_fpart;
     // While set, the operator takes those workspaces from this caller-provided region instead
     // (lspr_apply_noalloc), so a product allocates nothing.
     struct Arena {
@@ -519,14 +555,27 @@ void precompute_rhs(Geometry& g);
 struct TilePlan {
     std::vector<TileDesc> tiles;
     std::vector<int32_t> toff, tself;            // per chunk: first tile, own-surface tiles
+    std::vector<TileDesc> ktiles;                // the products' list (direct tiles paired)
+    std::vector<int32_t> ktoff, ktself;
     std::vector<int32_t> m2p_tile, m2p_chunk;    // per expansion entry: its tile and chunk
     std::vector<int32_t> p2p_tile, p2p_chunk;    // per direct tile: its tile and chunk
     std::vector<int32_t> order;                  // workgroup -> chunk
+    struct Items {                               // one launch class's work items
+        std::vector<FarItem> items;
+        std::vector<int32_t> order;
+        std::vector<FarRed> red;
+        int n_slots = 0;
+    } far[2][2];                                 // [list: tiles, ktiles][launch class]
     std::vector<int32_t> dto, dtr, dti;          // per chunk: direct tiles by first panel
     int64_t aoff = 0;                            // elements of one tile store
     int64_t tile_steps = 0, max_chunk_steps = 0;
 };
 TilePlan plan_tiles(const Geometry& g);
+TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
+                           const std::vector<int32_t>& self, const std::vector<uint8_t>& keep,
+                           double split);
+// Scratch bytes the far-field pieces of a product of pad columns per operator write.
+size_t far_part_bytes(const Geometry& g, int pad, bool fp64);
 // Elements of one tile store, from the host lists (the size plan_tiles will find).
 int64_t estimate_tile_elems(const Geometry& g);
 // Geometry-only left factors of the matrix-core far-field product, in each needed precision.

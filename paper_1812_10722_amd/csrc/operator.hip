@@ -656,11 +656,12 @@ __device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) 
 template <class T, int NSM, int S, int OPS = 1>
 __global__ void __launch_bounds__(256 * OPS, OPS == 2 ? (sizeof(T) == 8 ? 1 : 2)
                                                       : (sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4)))
-k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
-               const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
-               const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
-               const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
-               int halves, double* __restrict__ out_self, double* __restrict__ out_all) {
+k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
+               const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
+               const TileDesc* __restrict__ tiles,
+               const T* __restrict__ tileA, const T* __restrict__ dens, const T* __restrict__ mom,
+               int pad, int nwc, int halves, double* __restrict__ out_self,
+               double* __restrict__ out_all, double* __restrict__ part) {
     static_assert(OPS == 1 || OPS == 2, "one or both operators per workgroup");
     constexpr int NTHR = 256 * OPS;
     constexpr uint32_t ES = sizeof(T);       // bytes per element
@@ -680,8 +681,10 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     constexpr int G = 4 / S;                // column groups per workgroup and operator
     const int kpart = (wave & 3) % S;       // this wave's share of the K-steps
     const int wg = (wave & 3) / S + G * hj; // column group of this wave
-    const int chunk = chunk_order[(b >> 3) / per * 8 + (b & 7)];
-    if (chunk < 0) return;
+    const int item = item_order[(b >> 3) / per * 8 + (b & 7)];
+    if (item < 0) return;
+    const FarItem I = items[item];
+    const int chunk = I.chunk;
     const Chunk C = chunks[chunk];
     const int ntg = C.end - C.start;
     const bool mma = wg < nwc;
@@ -703,10 +706,17 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         if constexpr (sizeof(T) == 4) return run[mt][q];
         else return acc[mt][q];
     };
-    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
-    const int t_mid = t_beg + tile_self[chunk];
+    // a whole chunk writes its own-surface sums after its own-surface tiles and its sums over
+    // all surfaces at the end; a piece writes its partial sums to its scratch block (rows from 0)
+    const bool whole = I.slot < 0;
+    const int t_beg = I.t0, t_end = I.t1;
+    const int t_mid = whole ? t_beg + tile_self[chunk] : t_beg;
+    double* const o_self = whole ? out_self : nullptr;
+    double* const o_all = whole ? out_all + static_cast<size_t>(C.start) * ncols
+                                : part + static_cast<size_t>(I.slot) * NT * ncols;
     // Writes the sums (with S > 1 the first wave of each column group adds the others' sums, in
-    // wave order, from LDS after the left-factor buffer; all waves call it).
+    // wave order, from LDS after the left-factor buffer; all waves call it); out: the chunk's
+    // first row.
     auto write_sums = [&](double* out) {
         double sum[4][4];
 #pragma unroll
@@ -741,7 +751,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = 16 * mt + out_row<T>(grp, q);
-                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = sum[mt][q];
+                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = sum[mt][q];
             }
     };
     // B operands: NB values per lane whatever the tile's kind (steps past a tile's rows read
@@ -777,21 +787,42 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         return D;
     };
     // the part of a left factor this workgroup uses: all of an expansion tile, the factor of its
-    // own operator of a direct tile, or with OPS = 2 both (its first element, count)
+    // own operator of a direct tile (of each tile of a pair: two pieces of 8 K-steps, the second
+    // one direct tile further on), or with OPS = 2 both factors (its first element, count)
     auto own_off = [&](const TileDesc& D) {
         return D.a_off() +
-               (OPS == 1 && D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
+               (OPS == 1 && D.kind != 0 ? static_cast<int64_t>(opr) * DSTEPS * 256 : 0);
     };
+    // With pairs (PAIRS: the operand registers hold 2 DSTEPS steps) every direct tile runs as
+    // a pair: an unpaired one stages zeros for the second piece (the loads past its record
+    // read zero), whose products then add nothing.
+    constexpr bool PAIRS = sizeof(T) == 8 && OPS == 1 && (NSM > DSTEPS ? NSM : DSTEPS) >= 2 * DSTEPS;
     auto own_elems = [](const TileDesc& D) {
-        return 256 * D.nstep * (OPS == 2 && D.kind == 1 ? 2 : 1);
+        return PAIRS && D.kind != 0 ? 2 * DSTEPS * 256
+                                    : 256 * D.nstep * (OPS == 2 && D.kind == 1 ? 2 : 1);
     };
+    // bytes of the record over a tile's own part: a pair's two pieces and the other
+    // operator's factor of the first tile in between; one piece of an unpaired direct tile
+    auto own_bytes = [&](const TileDesc& D) {
+        return (D.kind == 2 ? 3u * DSTEPS * 256u
+                            : static_cast<uint32_t>(PAIRS && D.kind == 1 ? DSTEPS * 256
+                                                                          : own_elems(D))) * ES;
+    };
+    // prefetch rounds r >= RSEG load a pair's second piece: their offsets skip the other
+    // operator's factor of the first tile (DSTEPS * 256 elements)
+    constexpr int RSEG = DSTEPS * 256 / (EPU * NTHR);
+    static_assert(OPS == 2 || DSTEPS * 256 % (EPU * NTHR) == 0, "pair pieces split by rounds");
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
     T bc[NBS];
     if (t_beg < t_end) {
         const int n16 = own_elems(Te) / EPU;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
-        for (int k = tid; k < n16; k += NTHR) abuf16[lds_unit<T>(k)] = src[k];
+        const int seg = DSTEPS * 256 / EPU;  // a pair's second piece, or zeros
+        for (int k = tid; k < n16; k += NTHR)
+            abuf16[lds_unit<T>(k)] = k < seg || !PAIRS || Te.kind == 0 ? src[k]
+                                     : Te.kind == 2 ? src[k + seg]
+                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
         for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
@@ -815,10 +846,13 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         const bool more = e + 1 < t_end;
         const int n16n = more ? own_elems(Tn) / EPU : 0;
         {
-            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(tileA + own_off(Tn), n16n * 16u);
+            const uint32_t gap = more && Tn.kind == 2 ? DSTEPS * 256u * ES : 0u;
+            const __amdgpu_buffer_rsrc_t ra =
+                buffer_rsrc(tileA + own_off(Tn), more ? own_bytes(Tn) : 0u);
 #pragma unroll
             for (int r = 0; r < QA; ++r) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, r * NTHR * 16, 0);
+                const uint32_t so = r * NTHR * 16 + (r >= RSEG ? gap : 0u);
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, so, 0);
                 pf[r] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
                                     __uint_as_float(v[2]), __uint_as_float(v[3]));
             }
@@ -830,7 +864,19 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
         if (mma) {
             // with OPS = 2 the V waves read a direct tile's second factor
             const float4* ab = abuf16 + (OPS == 2 && Te.kind == 1 ? opr * Te.nstep * 256 / EPU : 0);
-#define LSPR_OP_TILE(NS)                                                             \
+            // FP32: a tile's partial joins the FP64 running sums (after each tile of a pair)
+            auto flush = [&]() {
+                if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
+                        acc[a] = Acc{0, 0, 0, 0};
+                    }
+                }
+            };
+// NS K-steps; FL >= 0: the partial is flushed after step FL (the first tile of a pair)
+#define LSPR_OP_TILE(NS, FL)                                                               \
     if constexpr (S == 1) {                                                                \
         uint32_t so = 0;                                                                   \
         _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
@@ -841,6 +887,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
             acc[3] = Mma<T>::op(a.w, bc[st], acc[3]);                                      \
             bc[st] = load_b_at(rbn, so);                                                   \
             so = next_step(so, bstep);                                                     \
+            if ((FL) >= 0 && st == (FL)) flush();                                          \
         }                                                                                  \
         _Pragma("unroll") for (int st = (NS); st < NB; ++st) {                             \
             bc[st] = load_b_at(rbn, so);                                                   \
@@ -857,20 +904,18 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
                 acc[3] = Mma<T>::op(a.w, bc[i], acc[3]);                                   \
             }                                                                              \
             bc[i] = load_b(rbn, st);                                                       \
+            if ((FL) >= 0 && i == ((FL) + 1) / S - 1) flush();                             \
         }                                                                                  \
     }
-            if (Te.kind == 0) LSPR_OP_TILE(NSM)
-            else LSPR_OP_TILE(DSTEPS)
-#undef LSPR_OP_TILE
-            // FP32: the tile's partial joins an FP64 running sum
-            if constexpr (sizeof(T) == 4) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) run[a][q] += static_cast<double>(acc[a][q]);
-                    acc[a] = Acc{0, 0, 0, 0};
-                }
+            if (Te.kind == 0) {
+                LSPR_OP_TILE(NSM, -1)
+            } else if constexpr (PAIRS) {
+                LSPR_OP_TILE(2 * DSTEPS, DSTEPS - 1)
+            } else {
+                LSPR_OP_TILE(DSTEPS, -1)
             }
+#undef LSPR_OP_TILE
+            flush();
         }
         __syncthreads();  // every wave is done with this tile's left factor
         {
@@ -897,9 +942,32 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
     // own-surface tiles first: their sums are the own-surface result (written between the two
     // loops, so that no output address is kept in registers across the tile loop)
     for (int e = t_beg; e < t_mid; ++e) tile(e);
-    if (out_self != nullptr) write_sums(out_self);
+    if (o_self != nullptr) write_sums(o_self + static_cast<size_t>(C.start) * ncols);
     for (int e = t_mid; e < t_end; ++e) tile(e);
-    write_sums(out_all);
+    write_sums(o_all);
+}
+
+// Sums of the chunks cut into pieces: for each target row and column, the pieces' FP64 partial
+// sums added in piece order (own-surface pieces first; their sum is the own-surface result).
+__global__ void __launch_bounds__(256)
+k_far_reduce(const Chunk* __restrict__ chunks, const FarRed* __restrict__ red, int n_red,
+             int ncols, const double* __restrict__ part, double* __restrict__ out_self,
+             double* __restrict__ out_all) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int per = NT * ncols;
+    if (i >= static_cast<int64_t>(n_red) * per) return;
+    const FarRed R = red[i / per];
+    const int rc = static_cast<int>(i % per), t = rc / ncols;
+    const Chunk C = chunks[R.chunk];
+    if (t >= C.end - C.start) return;
+    const size_t o = static_cast<size_t>(C.start) * ncols + rc;
+    double s = 0.0;
+    for (int k = R.slot0; k < R.slot1; ++k) {
+        if (k == R.slot0 + R.nself && out_self != nullptr) out_self[o] = s;
+        s += part[static_cast<size_t>(k) * per + rc];
+    }
+    if (R.nself == R.slot1 - R.slot0 && out_self != nullptr) out_self[o] = s;
+    out_all[o] = s;
 }
 
 // Narrow products (one or two column groups of 16 per operator, up to 16 wavelengths) without
@@ -907,19 +975,20 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chu
 // (the S = 4 / G waves of a column group split each tile's K-steps, wave k taking steps k,
 // k + S, ...), so each wave streams its own operands straight from HBM into registers: per
 // K-step one 16-byte (FP64: 32-byte) A operand per lane, contiguous across the wave, and one B
-// value.  Two sets of operand registers alternate between tiles, and each register is reloaded
-// with the operand two tiles ahead right after the current step has used it, so a wave keeps
-// two tiles of loads in flight while it computes, and the loop holds no barrier.
+// value.  Each operand register is reloaded with the next tile's operand right after the
+// current step has used it, so a wave keeps a tile of its own loads in flight while it
+// computes, and the loop holds no barrier.
 // Raw buffer loads with per-tile records read zero past a tile's factor and rows.  The step
 // partition, the FP32 partial per tile, its FP64 running sum and the wave-order addition at
 // the end are those of k_far_tiles_op's narrow form, so both give identical sums.
 template <class T, int NSM, int S>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 && S == 4) ? 4 : 2)
-k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order,
-             const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_self,
+k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
+             const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
              const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
              const T* __restrict__ dens, const T* __restrict__ mom, int pad, int nwc,
-             double* __restrict__ out_self, double* __restrict__ out_all) {
+             double* __restrict__ out_self, double* __restrict__ out_all,
+             double* __restrict__ part) {
     static_assert(S == 2 || S == 4, "narrow products only");
     constexpr uint32_t ES = sizeof(T);
     constexpr int G = 4 / S;                   // column groups per workgroup
@@ -934,16 +1003,23 @@ k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk
     const int opr = (b >> 3) & 1;              // 0: K columns, 1: V columns
     const int kpart = wave % S;                // this wave's share of the K-steps
     const int wg = wave / S;                   // column group of this wave
-    const int chunk = chunk_order[(b >> 4) * 8 + (b & 7)];
-    if (chunk < 0) return;
+    const int item = item_order[(b >> 4) * 8 + (b & 7)];
+    if (item < 0) return;
+    const FarItem I = items[item];
+    const int chunk = I.chunk;
     const Chunk C = chunks[chunk];
     const int ntg = C.end - C.start;
     const bool mma = wg < nwc;
     const int col = opr * pad + 16 * wg + c16;
     const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * ES;
     const uint32_t bstep = 4u * ES * static_cast<uint32_t>(ncols);
-    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
-    const int t_mid = t_beg + tile_self[chunk];
+    // a whole chunk, or a piece that writes its partial sums to its scratch block
+    const bool whole = I.slot < 0;
+    const int t_beg = I.t0, t_end = I.t1;
+    const int t_mid = whole ? t_beg + tile_self[chunk] : t_beg;
+    double* const o_self = whole ? out_self : nullptr;
+    double* const o_all = whole ? out_all + static_cast<size_t>(C.start) * ncols
+                                : part + static_cast<size_t>(I.slot) * NT * ncols;
     Acc acc[4];
     double run[4][4];
 #pragma unroll
@@ -982,15 +1058,22 @@ k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = 16 * mt + out_row<T>(grp, q);
-                if (t < ntg) out[static_cast<size_t>(C.start + t) * ncols + col] = sum[mt][q];
+                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = sum[mt][q];
             }
     };
     // operand sources of tile e (empty records past the chunk's last tile)
+    // (a pair's two pieces of this operator's factor are one direct tile apart: the record
+    // spans the other operator's factor of the first tile in between)
     auto a_rsrc = [&](int e) {
         if (e >= t_end) return buffer_rsrc(tileA, 0u);
         const TileDesc D = tiles[e];
-        const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
-        return buffer_rsrc(tileA + off, static_cast<uint32_t>(D.nstep) * 256u * ES);
+        const int64_t off = D.a_off() + (D.kind != 0 ? static_cast<int64_t>(opr) * DSTEPS * 256 : 0);
+        const uint32_t steps = D.kind == 2 ? 3 * DSTEPS : static_cast<uint32_t>(D.nstep);
+        return buffer_rsrc(tileA + off, steps * 256u * ES);
+    };
+    // byte offset of a pair's second piece from its first (0 for other tiles)
+    auto a_gap = [&](int e) {
+        return e < t_end && tiles[e].kind == 2 ? DSTEPS * 256u * ES : 0u;
     };
     auto b_rsrc = [&](int e) {
         if (e >= t_end) return buffer_rsrc(dens, 0u);
@@ -1000,17 +1083,17 @@ k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk
                            static_cast<uint32_t>(D.b_rows) * static_cast<uint32_t>(ncols) * ES);
     };
     // this lane's A operand of K-step st: 4 consecutive elements (the four target tiles)
-    auto load_a = [&](__amdgpu_buffer_rsrc_t ra, int st) {
+    auto load_a = [&](__amdgpu_buffer_rsrc_t ra, int st, uint32_t gap) {
         Quad<T> q;
         if constexpr (sizeof(T) == 4) {
-            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 1024, 0);
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 1024 + gap, 0);
             q.x = __uint_as_float(v[0]);
             q.y = __uint_as_float(v[1]);
             q.z = __uint_as_float(v[2]);
             q.w = __uint_as_float(v[3]);
         } else {
-            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048, 0);
-            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048, 0);
+            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048 + gap, 0);
+            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048 + gap, 0);
             q.x = __builtin_bit_cast(double, make_uint2(lo[0], lo[1]));
             q.y = __builtin_bit_cast(double, make_uint2(lo[2], lo[3]));
             q.z = __builtin_bit_cast(double, make_uint2(hi[0], hi[1]));
@@ -1020,29 +1103,19 @@ k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk
     };
     Quad<T> a[NBS];
     T bv[NBS];
+    // steps kpart + S i of a pair with i >= 8 / S are its second tile's
+    constexpr int ISEG = DSTEPS / S;
     {
         const __amdgpu_buffer_rsrc_t ra = a_rsrc(t_beg), rb = b_rsrc(t_beg);
+        const uint32_t gap = a_gap(t_beg);
 #pragma unroll
         for (int i = 0; i < NBS; ++i) {
-            a[i] = load_a(ra, kpart + S * i);
+            a[i] = load_a(ra, kpart + S * i, i >= ISEG ? gap : 0u);
             bv[i] = load_elem<T>(rb, boff, (kpart + S * i) * bstep);
         }
     }
-    auto tile = [&](int e) {
-        const int ns = tiles[e].nstep;
-        const __amdgpu_buffer_rsrc_t ran = a_rsrc(e + 1), rbn = b_rsrc(e + 1);
-#pragma unroll
-        for (int i = 0; i < NBS; ++i) {
-            const int st = kpart + S * i;
-            if (st < ns && mma) {
-                acc[0] = Mma<T>::op(a[i].x, bv[i], acc[0]);
-                acc[1] = Mma<T>::op(a[i].y, bv[i], acc[1]);
-                acc[2] = Mma<T>::op(a[i].z, bv[i], acc[2]);
-                acc[3] = Mma<T>::op(a[i].w, bv[i], acc[3]);
-            }
-            a[i] = load_a(ran, st);
-            bv[i] = load_elem<T>(rbn, boff, st * bstep);
-        }
+    // FP32: a tile's partial joins the FP64 running sums (after each tile of a pair)
+    auto flush = [&]() {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1052,10 +1125,31 @@ k_far_stream(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk
             }
         }
     };
+    auto tile = [&](int e) {
+        const TileDesc D = tiles[e];
+        const int ns = D.nstep;
+        const bool pair = D.kind == 2;
+        const __amdgpu_buffer_rsrc_t ran = a_rsrc(e + 1), rbn = b_rsrc(e + 1);
+        const uint32_t gapn = a_gap(e + 1);
+#pragma unroll
+        for (int i = 0; i < NBS; ++i) {
+            const int st = kpart + S * i;
+            if (st < ns && mma) {
+                acc[0] = Mma<T>::op(a[i].x, bv[i], acc[0]);
+                acc[1] = Mma<T>::op(a[i].y, bv[i], acc[1]);
+                acc[2] = Mma<T>::op(a[i].z, bv[i], acc[2]);
+                acc[3] = Mma<T>::op(a[i].w, bv[i], acc[3]);
+            }
+            a[i] = load_a(ran, st, i >= ISEG ? gapn : 0u);
+            bv[i] = load_elem<T>(rbn, boff, st * bstep);
+            if (i == ISEG - 1 && pair) flush();
+        }
+        flush();
+    };
     for (int e = t_beg; e < t_mid; ++e) tile(e);
-    if (out_self != nullptr) write_sums(out_self);
+    if (o_self != nullptr) write_sums(o_self + static_cast<size_t>(C.start) * ncols);
     for (int e = t_mid; e < t_end; ++e) tile(e);
-    write_sums(out_all);
+    write_sums(o_all);
 }
 
 // ------------------------------------------------------------------------------- P2M, MFMA
@@ -1469,11 +1563,42 @@ void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, co
     LSPR_HIP(hipGetLastError());
 }
 
+// Work items of a launch of pad columns per operator: pieces of chunks for products of up to
+// 16 wavelengths (plan 0), the other plan above.
+inline const Geometry::FarPlan& far_plan_for(const Geometry& g, int pad, bool paired) {
+    return g.far_plan[paired ? 1 : 0][pad > 32 ? 1 : 0];
+}
+
+}  // namespace
+
+// Scratch bytes of the pieces' partial sums of a launch of pad columns per operator.
+size_t far_part_bytes(const Geometry& g, int pad, bool fp64) {
+    return static_cast<size_t>(far_plan_for(g, pad, fp64).n_slots) * NT * 2 * pad * sizeof(double);
+}
+
+namespace {
+
+// Sums of the chunks a launch cut into pieces (after the far-field kernel, same stream).
+void launch_far_reduce(Geometry& g, const Geometry::FarPlan& fp, int pad, const double* part,
+                       double* os, double* oa, hipStream_t s) {
+    if (fp.n_red == 0) return;
+    const int64_t tot = static_cast<int64_t>(fp.n_red) * NT * 2 * pad;
+    hipLaunchKernelGGL(k_far_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, g.chunks.p,
+                       fp.red.p, fp.n_red, 2 * pad, part, os, oa);
+    LSPR_HIP(hipGetLastError());
+}
+
 template <class T, int NSM, int S, int OPS = 1>
 void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                            double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
-    const int nblk = g.n_order * (OPS == 2 ? 1 : 2) * halves;
+    // FP64 products visit the list with paired direct tiles
+    constexpr bool paired = sizeof(T) == 8;
+    const Geometry::FarPlan& fp = far_plan_for(g, pad, paired);
+    double* part = nullptr;
+    if (fp.n_slots > 0)
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad, paired)));
+    const int nblk = fp.n_order * (OPS == 2 ? 1 : 2) * halves;
     // the left factor (OPS = 2: a direct tile's two), then (S > 1) one slot of FP64 sums per
     // column group for the final additions
     const size_t ab = OPS == 2 ? std::max<size_t>(abuf, 2 * DSTEPS * 256) : abuf;
@@ -1483,19 +1608,29 @@ void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const 
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(lds));
     hipLaunchKernelGGL((k_far_tiles_op<T, NSM, S, OPS>), dim3(nblk), dim3(256 * OPS), lds, s,
-                       g.chunks.p, g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p,
-                       tiles_of<T>(g), dens, mom, pad, pad / 16, halves, os, oa);
+                       g.chunks.p, fp.items.p, fp.order.p,
+                       paired ? g.ktile_self.p : g.tile_self.p, paired ? g.ktiles.p : g.tiles.p,
+                       tiles_of<T>(g), dens, mom, pad, pad / 16, halves, os, oa, part);
     LSPR_HIP(hipGetLastError());
+    launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
 
 template <class T, int NSM, int S>
 void launch_far_stream(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                        double* oa, hipStream_t s) {
-    const int nblk = g.n_order * 2;
+    // FP64 products visit the list with paired direct tiles
+    constexpr bool paired = sizeof(T) == 8;
+    const Geometry::FarPlan& fp = far_plan_for(g, pad, paired);
+    double* part = nullptr;
+    if (fp.n_slots > 0)
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad, paired)));
+    const int nblk = fp.n_order * 2;
     hipLaunchKernelGGL((k_far_stream<T, NSM, S>), dim3(nblk), dim3(256), 0, s, g.chunks.p,
-                       g.chunk_order.p, g.tile_off.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g),
-                       dens, mom, pad, pad / 16, os, oa);
+                       fp.items.p, fp.order.p, paired ? g.ktile_self.p : g.tile_self.p,
+                       paired ? g.ktiles.p : g.tiles.p, tiles_of<T>(g), dens, mom, pad, pad / 16,
+                       os, oa, part);
     LSPR_HIP(hipGetLastError());
+    launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
 
 // one column group per operator: four waves share it; two: two waves each; more: one each.
@@ -1803,6 +1938,85 @@ int64_t estimate_tile_elems(const Geometry& g) {
     return e;
 }
 
+// Work items of the far-field kernels over one tile list (per chunk: first tile `off`, own-
+// surface tiles `self`): a chunk whose cost (K-steps + 4 per tile) exceeds `split` x the mean
+// is cut at its own-surface boundary and into pieces of about equal cost (split 0: whole
+// chunks), never between tiles t and t + 1 where keep[t] is set; then XCD runs of
+// consecutive chunks' items, cut at equal shares of the cost, with the heaviest items first
+// within each run (workgroup b takes an item of run b % 8).
+TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
+                           const std::vector<int32_t>& self, const std::vector<uint8_t>& keep,
+                           double split) {
+    TilePlan::Items W;
+    const int nc = static_cast<int>(self.size());
+    auto tcost = [&](int t) { return static_cast<double>(tl[t].nstep) + 4.0; };
+    std::vector<double> ccost(nc, 0.0);
+    double total = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        for (int t = off[c]; t < off[c + 1]; ++t) ccost[c] += tcost(t);
+        total += ccost[c];
+    }
+    const double cap = nc > 0 ? split * total / nc : 0.0;
+    std::vector<double> icost;
+    auto add = [&](int c, int t0, int t1, int slot) {
+        double cs = 0.0;
+        for (int t = t0; t < t1; ++t) cs += tcost(t);
+        W.items.push_back({c, t0, t1, slot});
+        icost.push_back(cs);
+    };
+    for (int c = 0; c < nc; ++c) {
+        const int a = off[c], m = off[c] + self[c], e = off[c + 1];
+        if (cap <= 0.0 || ccost[c] <= cap) {
+            add(c, a, e, -1);
+            continue;
+        }
+        FarRed R{c, W.n_slots, 0, 0};
+        for (int half = 0; half < 2; ++half) {
+            const int x = half == 0 ? a : m, y = half == 0 ? m : e;
+            if (x < y) {
+                double cs = 0.0;
+                for (int t = x; t < y; ++t) cs += tcost(t);
+                const int n = std::max(1, static_cast<int>(std::ceil(cs / cap)));
+                double acc = 0.0;
+                int start = x, k = 0;
+                for (int t = x; t < y; ++t) {
+                    acc += tcost(t);
+                    if (k < n - 1 && t + 1 < y && !keep[t] && acc >= (k + 1) * cs / n) {
+                        add(c, start, t + 1, W.n_slots++);
+                        start = t + 1;
+                        ++k;
+                    }
+                }
+                add(c, start, y, W.n_slots++);
+            }
+            if (half == 0) R.nself = W.n_slots - R.slot0;
+        }
+        R.slot1 = W.n_slots;
+        W.red.push_back(R);
+    }
+    const int ni = static_cast<int>(W.items.size());
+    std::vector<std::vector<int32_t>> runs(8);
+    double acc = 0.0;
+    int x = 0;
+    for (int i = 0; i < ni; ++i) {
+        while (x < 7 && !runs[x].empty() &&
+               (acc + 0.5 * icost[i] > (x + 1) * total / 8.0 || ni - i <= 7 - x))
+            ++x;
+        runs[x].push_back(i);
+        acc += icost[i];
+    }
+    size_t per = 0;
+    for (auto& run : runs) {
+        std::stable_sort(run.begin(), run.end(),
+                         [&](int32_t u, int32_t v) { return icost[u] > icost[v]; });
+        per = std::max(per, run.size());
+    }
+    W.order.assign(std::max<size_t>(per, 1) * 8, -1);
+    for (int xx = 0; xx < 8; ++xx)
+        for (size_t i = 0; i < runs[xx].size(); ++i) W.order[i * 8 + xx] = runs[xx][i];
+    return W;
+}
+
 TilePlan plan_tiles(const Geometry& g) {
     TilePlan P;
     const int nc = g.n_chunks;
@@ -1906,6 +2120,64 @@ TilePlan plan_tiles(const Geometry& g) {
     order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
+    // The FP64 products' tile list: consecutive direct tiles of one source range (the first
+    // full) become one 16-step tile when the kernels hold 16 steps of operands (expansion
+    // slices of at least 16 steps) and no paired-operator schedule is asked for; the left
+    // factors stay where they are.
+    // Where pairs could form is fixed by the lists alone, so that every schedule cuts chunks
+    // into the same pieces (identical sums): no piece ends inside a pairable couple.
+    const bool pairs = nsm >= 2 * DSTEPS && !g.pair_ops && !g.pair_narrow;
+    std::vector<uint8_t> pstart(tiles.size(), 0);
+    for (int c = 0; c < nc; ++c) {
+        const int m = toff[c] + tself[c];
+        for (int t = toff[c]; t + 1 < toff[c + 1]; ++t) {
+            const TileDesc &A = tiles[t], &B = tiles[t + 1];
+            if (A.kind == 1 && A.b_rows == 4 * DSTEPS && t + 1 != m && B.kind == 1 &&
+                B.b_row0 == A.b_row0 + 4 * DSTEPS && B.a_off() == A.a_off() + 2 * DSTEPS * 256) {
+                pstart[t] = 1;
+                ++t;
+            }
+        }
+    }
+    std::vector<TileDesc>& kt = P.ktiles;
+    std::vector<int32_t> kidx(tiles.size() + 1, 0);  // list position -> ktiles position
+    P.ktoff.assign(nc + 1, 0);
+    P.ktself.assign(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+        P.ktoff[c] = static_cast<int32_t>(kt.size());
+        const int m = toff[c] + tself[c];
+        for (int t = toff[c]; t < toff[c + 1]; ++t) {
+            if (t == m) P.ktself[c] = static_cast<int32_t>(kt.size()) - P.ktoff[c];
+            const TileDesc& A = tiles[t];
+            kidx[t] = static_cast<int32_t>(kt.size());
+            if (pairs && pstart[t]) {
+                kidx[t + 1] = kidx[t];
+                TileDesc D = A;
+                D.kind = 2;
+                D.nstep = static_cast<int16_t>(2 * DSTEPS);
+                D.b_rows = A.b_rows + tiles[t + 1].b_rows;
+                kt.push_back(D);
+                ++t;
+            } else {
+                kt.push_back(A);
+            }
+        }
+        if (toff[c] + tself[c] == toff[c + 1])
+            P.ktself[c] = static_cast<int32_t>(kt.size()) - P.ktoff[c];
+    }
+    P.ktoff[nc] = static_cast<int32_t>(kt.size());
+    kidx[tiles.size()] = static_cast<int32_t>(kt.size());
+    // Work items per launch class, planned on the list and carried over to ktiles (the same
+    // pieces, workgroup order and scratch blocks).
+    for (int cls = 0; cls < 2; ++cls) {
+        P.far[0][cls] = plan_items(tiles, toff, tself, pstart, g.far_split[cls]);
+        P.far[1][cls] = P.far[0][cls];
+        for (FarItem& I : P.far[1][cls].items) {
+            const int a = I.t0, b = I.t1;
+            I.t0 = kidx[a];
+            I.t1 = a < b ? kidx[b - 1] + 1 : I.t0;
+        }
+    }
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
     for (int c = 0; c < nc; ++c) {
@@ -1958,6 +2230,25 @@ void build_tiles(Geometry& g, const TilePlan& P) {
     up.add(g.tiles.p, P.tiles.data(), P.tiles.size());
     up.add(g.tile_off.p, P.toff.data(), P.toff.size());
     up.add(g.tile_self.p, P.tself.data(), P.tself.size());
+    g.ktiles.alloc(std::max<size_t>(P.ktiles.size(), 1));
+    g.ktile_self.alloc(nc);
+    up.add(g.ktiles.p, P.ktiles.data(), P.ktiles.size());
+    up.add(g.ktile_self.p, P.ktself.data(), P.ktself.size());
+    for (int li = 0; li < 4; ++li) {
+        Geometry::FarPlan& fp = g.far_plan[li >> 1][li & 1];
+        const TilePlan::Items& W = P.far[li >> 1][li & 1];
+        fp.items.alloc(W.items.size());
+        fp.order.alloc(W.order.size());
+        up.add(fp.items.p, W.items.data(), W.items.size());
+        up.add(fp.order.p, W.order.data(), W.order.size());
+        fp.n_order = static_cast<int>(W.order.size());
+        fp.n_red = static_cast<int>(W.red.size());
+        fp.n_slots = W.n_slots;
+        if (!W.red.empty()) {
+            fp.red.alloc(W.red.size());
+            up.add(fp.red.p, W.red.data(), W.red.size());
+        }
+    }
     const int n_m2p = static_cast<int>(g.n_m2p), n_p2p = static_cast<int>(P.p2p_tile.size());
     DevBuf<int32_t> mt(n_m2p), mc(n_m2p), pt(n_p2p), pc(n_p2p);
     up.add(mt.p, P.m2p_tile.data(), n_m2p);
