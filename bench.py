@@ -333,7 +333,7 @@ def main():
                     help="run a workload's fixed treecode settings instead of the autotuner's")
     ap.add_argument("--op", action="append", default=[], metavar="KEY=VALUE",
                     help="override an operator parameter of the workload (p, theta, ncrit, "
-                         "m2p_min_panels, split_operators, stream_narrow, pair_operators, ...); "
+                         "m2p_min_panels, stream_narrow, pair_operators, pair_narrow, ...); "
                          "implies --no-autotune")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests of the serving leg (default 16, or 200 with --serving-only; "
@@ -409,7 +409,6 @@ def main():
                                  and e["m2p_min_panels"] == top.m2p_min_panels
                                  and e["flags"] == top.flags), None)}
         op.update(p=top.p, theta=top.theta, ncrit=top.ncrit, m2p_min_panels=top.m2p_min_panels,
-                  split_operators=not (top.flags & lspr.LSPR_NO_SPLIT_OPERATORS),
                   stream_narrow=bool(top.flags & lspr.LSPR_STREAM_NARROW),
                   pair_operators=bool(top.flags & lspr.LSPR_PAIR_OPERATORS))
         log(f"[bench] autotune: P={top.p} theta={top.theta} ncrit={top.ncrit} "

@@ -55,7 +55,8 @@ enum lspr_method { LSPR_DENSE = 0, LSPR_TREECODE = 1 };
 enum lspr_precision { LSPR_FP64 = 0, LSPR_FP32 = 1, LSPR_FP32_REFINE64 = 2, LSPR_FP32_LEAD64 = 3 };
 enum lspr_flags {
     LSPR_NO_MATRIX_CORES = 1,
-    LSPR_NO_SPLIT_OPERATORS = 2,
+    /* bit 1 (value 2) is retired: it selected a schedule with both operators per four-wave
+     * workgroup; a geometry created with it is refused as an unknown flag */
     LSPR_STREAM_NARROW = 4,
     LSPR_PAIR_OPERATORS = 8,
     LSPR_PAIR_NARROW = 16
@@ -108,8 +109,7 @@ typedef struct {
  *             fit in 55 % of the free device memory (FP32 first, then FP64); a precision whose
  *             tiles do not fit uses the vector-ALU kernel, which computes the same sums on the
  *             fly.
- *             bit 1: FP32 matrix-core products keep both operators in one workgroup instead of
- *             one workgroup per operator (same sums; a tuning alternative).
+ *             bit 1: retired (refused).
  *             bit 2: products of up to 16 wavelengths stream every wave's operands from
  *             memory instead of staging each left factor in LDS for the workgroup (identical
  *             sums; a tuning alternative, faster for FP64 products of up to 8 wavelengths).
@@ -383,9 +383,8 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
  * max_rel_err is timed: n_cols columns in the product precision of op (FP32 unless
  * op->precision is LSPR_FP64), fastest of three after one warm-up, HIP events on `stream`.
  * Stage 2, on the fastest of those: the kernel schedule, timed the same way: m2p_min_panels at
- * half and twice its default ((P+1)^2; the error is checked again), both operators in one
- * workgroup (LSPR_NO_SPLIT_OPERATORS, FP32 products), for n_cols <= 16 the streamed narrow
- * kernel (LSPR_STREAM_NARROW), for n_cols > 16 the paired-operator workgroups
+ * half and twice its default ((P+1)^2; the error is checked again), for n_cols <= 16 the
+ * streamed narrow kernel (LSPR_STREAM_NARROW), for n_cols > 16 the paired-operator workgroups
  * (LSPR_PAIR_OPERATORS).  The fastest candidate that meets the bound is written
  * to op->p, op->theta, op->ncrit, op->m2p_min_panels and op->flags (op->method becomes
  * LSPR_TREECODE; the other fields are kept and used for every candidate).

@@ -285,6 +285,9 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     }
     LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
              "ncrit and m2p_min_panels must be >= 0");
+    LSPR_REQUIRE((op->flags & ~(LSPR_NO_MATRIX_CORES | LSPR_STREAM_NARROW | LSPR_PAIR_OPERATORS |
+                                LSPR_PAIR_NARROW)) == 0,
+                 LSPR_E_INVALID, "unknown flags");
 }
 
 void validate_gmres(const lspr_gmres_params& gm, int precision) {
@@ -320,7 +323,6 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.n_terms = lspr::expansion_terms(g.P);
     g.m2p_min_panels = op->m2p_min_panels > 0 ? op->m2p_min_panels : g.n_terms;
     g.allow_mfma = (op->flags & LSPR_NO_MATRIX_CORES) == 0;
-    if (op->flags & LSPR_NO_SPLIT_OPERATORS) g.far_op_min_pad = 0;
     g.stream_narrow = (op->flags & LSPR_STREAM_NARROW) != 0;
     g.pair_ops = (op->flags & LSPR_PAIR_OPERATORS) != 0;
     g.pair_narrow = (op->flags & LSPR_PAIR_NARROW) != 0;
@@ -527,9 +529,7 @@ size_t lspr::Geometry::device_bytes() const {
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + charge_u.bytes() + ws_inv_eps.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
            ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2mA64.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
-           far_plan[0][0].bytes() + far_plan[0][1].bytes() + far_plan[1][0].bytes() +
-           far_plan[1][1].bytes() + ws_fpart.bytes() + ktiles.bytes() +
-           ktile_self.bytes() +
+           far_plan[0].bytes() + far_plan[1].bytes() + ws_fpart.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 
@@ -872,8 +872,8 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
                 }
         // stage 2: the kernel schedule of the best expansion: the cost threshold for expanding a
         // box (half and twice the default of one panel per Taylor term; it moves work between
-        // expansions and direct sums, so the bound is checked again), one workgroup per operator
-        // or both operators in one (FP32), and for narrow products operands streamed or staged
+        // expansions and direct sums, so the bound is checked again), both operators staged once
+        // in eight-wave workgroups, and for narrow products operands streamed or staged
         if (best.ms_per_product >= 0.0) {
             const int terms = (best.p + 1) * (best.p + 1);
             lspr_op_params b = *op;
@@ -886,11 +886,6 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
             for (int mp : {terms / 2, 2 * terms}) {
                 lspr_op_params c = b;
                 c.m2p_min_panels = mp;
-                sched.push_back(c);
-            }
-            if (tprec == LSPR_FP32) {
-                lspr_op_params c = b;
-                c.flags |= LSPR_NO_SPLIT_OPERATORS;
                 sched.push_back(c);
             }
             if (n_cols > 16) {

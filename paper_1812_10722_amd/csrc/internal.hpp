@@ -339,9 +339,7 @@ struct P2MRed {
 // One left factor of the matrix-core far-field product, stored in MFMA operand order.
 // kind 0: expansion (Taylor coefficients; B rows = moments rows b_row0 .. b_row0 + b_rows);
 // kind 1: direct tile (double-layer then single-layer kernel values; B rows = density rows of
-// panels b_row0 .. b_row0 + b_rows); kind 2 (the products' list only): two consecutive direct
-// tiles of one source range, the first full, stored one after the other (B rows = the 32 + up
-// to 32 panels of both).  nstep K-steps of 4 rows; the left factor starts at
+// panels b_row0 .. b_row0 + b_rows).  nstep K-steps of 4 rows; the left factor starts at
 // element 256 a_blk of the tile store (every tile is a multiple of 256 elements).  16 bytes, so
 // a kernel fetches a descriptor with one 128-bit load.
 struct TileDesc {
@@ -414,11 +412,6 @@ struct Geometry {
     int64_t tile_elems = 0;  // elements of one tile store (the left factors of one precision)
     DevBuf<TileDesc> tiles;
     DevBuf<int32_t> tile_off, tile_self;
-    // the tiles as the FP64 products visit them: the same left factors, with consecutive
-    // direct tiles of a source range paired (kind 2) when the kernels' operand registers hold
-    // two; own-surface tiles of each chunk in this list
-    DevBuf<TileDesc> ktiles;
-    DevBuf<int32_t> ktile_self;
     DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)
     int n_order = 0;              // entries of chunk_order (a multiple of 8)
     // Work items of the one-operator far-field kernel, one set per launch class (0: up to 16
@@ -431,7 +424,7 @@ struct Geometry {
         int n_order = 0, n_red = 0, n_slots = 0;
         size_t bytes() const { return items.bytes() + order.bytes() + red.bytes(); }
     };
-    FarPlan far_plan[2][2];  // [tile list: 0 tiles, 1 ktiles][launch class]
+    FarPlan far_plan[2];
     // largest piece, as a fraction of the mean chunk cost, per launch class (0: no pieces):
     // measured on the 32768-panel sphere (busiest chunk 1.95 x the mean), 0.35 for up to 16
     // wavelengths (every workgroup resident at once: the busiest chunk set the launch time)
@@ -485,8 +478,6 @@ struct Geometry {
     DevBuf<double2> ws_inv_eps;
     hipStream_t stream = nullptr;
     bool allow_mfma = true;  // products use matrix cores (precomputed tiles)
-    int far_op_min_pad = 16;  // products with at least this many columns per operator run
-                              // one operator per workgroup (0: never)
     bool stream_narrow = false;  // products of up to 16 wavelengths stream their operands
                                  // (k_far_stream) instead of staging them in LDS
     bool pair_ops = false;  // products of more than 16 wavelengths stage each left factor once
@@ -555,8 +546,6 @@ void precompute_rhs(Geometry& g);
 struct TilePlan {
     std::vector<TileDesc> tiles;
     std::vector<int32_t> toff, tself;            // per chunk: first tile, own-surface tiles
-    std::vector<TileDesc> ktiles;                // the products' list (direct tiles paired)
-    std::vector<int32_t> ktoff, ktself;
     std::vector<int32_t> m2p_tile, m2p_chunk;    // per expansion entry: its tile and chunk
     std::vector<int32_t> p2p_tile, p2p_chunk;    // per direct tile: its tile and chunk
     std::vector<int32_t> order;                  // workgroup -> chunk
@@ -565,17 +554,16 @@ struct TilePlan {
         std::vector<int32_t> order;
         std::vector<FarRed> red;
         int n_slots = 0;
-    } far[2][2];                                 // [list: tiles, ktiles][launch class]
+    } far[2];                                    // per launch class
     std::vector<int32_t> dto, dtr, dti;          // per chunk: direct tiles by first panel
     int64_t aoff = 0;                            // elements of one tile store
     int64_t tile_steps = 0, max_chunk_steps = 0;
 };
 TilePlan plan_tiles(const Geometry& g);
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, const std::vector<uint8_t>& keep,
-                           double split);
+                           const std::vector<int32_t>& self, double split);
 // Scratch bytes the far-field pieces of a product of pad columns per operator write.
-size_t far_part_bytes(const Geometry& g, int pad, bool fp64);
+size_t far_part_bytes(const Geometry& g, int pad);
 // Elements of one tile store, from the host lists (the size plan_tiles will find).
 int64_t estimate_tile_elems(const Geometry& g);
 // Geometry-only left factors of the matrix-core far-field product, in each needed precision.

@@ -56,8 +56,8 @@ size_t apply_scratch_bytes(const Geometry& g, int B, int prec) {
         if (g.n_slots > 0)
             b += arena_piece(static_cast<size_t>(g.n_slots) * g.n_terms * 2 * c.pad * esz);
     }
-    if (c.mfma && far_part_bytes(g, c.pad, c.prec == LSPR_FP64) > 0)    // far-field pieces
-        b += arena_piece(far_part_bytes(g, c.pad, c.prec == LSPR_FP64));
+    if (c.mfma && far_part_bytes(g, c.pad) > 0)                          // far-field pieces
+        b += arena_piece(far_part_bytes(g, c.pad));
     return b;
 }
 

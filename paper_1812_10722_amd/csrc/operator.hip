@@ -303,7 +303,7 @@ k_far(const Chunk* __restrict__ chunks, const Box* __restrict__ boxes,
 // ------------------------------------------------------------------------------- far field, MFMA
 // Far-field sums on matrix cores, FP32 or FP64.  For a chunk of 64 targets every interaction is
 // a small dense product: an expansion is (64 x terms) . (terms x columns) of Taylor
-// coefficients and box moments, a direct tile is (64 x 32 panels) . (32 panels x columns) of
+// coefficients and box moments, a direct tile is (64 x panels) . (panels x columns) of
 // far-rule kernel values and densities.  The left factors depend on geometry only; build_tiles
 // stores them once per geometry, in the operand order of v_mfma_{f32,f64}_16x16x4 (lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; see out_row for the result rows): for
@@ -316,9 +316,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// K-steps of a direct tile: 4 * DSTEPS source panels per tile, summed in FP32 by the matrix
-// cores before the tile joins the FP64 running sum (longer tiles measured no faster and add
-// FP32 rounding that GMRES feels near resonance).
+// Direct tiles: a chunk's direct-sum range is cut into pieces of up to 4 direct_steps()
+// source panels, one tile each (K-steps = panels / 4 rounded up).  That is the length of an
+// expansion slice (at least DSTEPS), so every tile covers the prefetch of the next one for as
+// long and the kernels run one loop of that many steps for both kinds; each tile's partial is
+// summed in FP32 by the matrix cores before it joins the FP64 running sum.
 constexpr int DSTEPS = 8;
 
 // Expansion tiles of high orders are cut along the Taylor terms into slices of equal K-steps
@@ -331,6 +333,9 @@ constexpr int expansion_slices(int n_terms) {
 constexpr int expansion_slice_steps(int n_terms) {
     const int steps = (n_terms + 3) / 4, n = expansion_slices(n_terms);
     return (steps + n - 1) / n;
+}
+constexpr int direct_steps(int n_terms) {
+    return expansion_slice_steps(n_terms) > DSTEPS ? expansion_slice_steps(n_terms) : DSTEPS;
 }
 
 template <class T>
@@ -355,231 +360,11 @@ struct Mma<double> {
     }
 };
 
-// Workgroup = one chunk; waves [0, nwc) each own 16 K columns and the same 16 V columns
-// (4 target tiles x 2 column tiles of 16 x 16); extra waves only help to stage the left
-// factors.  The left factor of tile e + 1 is fetched into registers while tile e is multiplied
-// out of LDS, then stored to the other LDS buffer (double buffering).
-// Consecutive chunks are spatially close and share moments and densities, so workgroups are
-// mapped to chunks XCD by XCD: the hardware deals workgroups round-robin over the 8 XCDs, and
-// workgroup b handles a chunk of run b % 8 of ceil(n / 8) consecutive chunks, which gives every
-// XCD's L2 one contiguous run.  Within a run, workgroups take the chunks in decreasing order of
-// work (chunk_order, built with the tiles), so the longest chunks start first and the short
-// ones fill in behind them.
-// One tile: NST K-steps of 4 rows.  FP32: the B operands of the whole tile are requested
-// before the first matrix-core instruction so that their latency overlaps the products.
-// FP64 operands take twice the registers: the tile goes in groups of 2 K-steps.
-#define LSPR_MMA_STEP(AK, AV, BK, BV)                         \
-    acc[0][0] = Mma<T>::op((AK).x, (BK), acc[0][0]);          \
-    acc[1][0] = Mma<T>::op((AK).y, (BK), acc[1][0]);          \
-    acc[2][0] = Mma<T>::op((AK).z, (BK), acc[2][0]);          \
-    acc[3][0] = Mma<T>::op((AK).w, (BK), acc[3][0]);          \
-    acc[0][1] = Mma<T>::op((AV).x, (BV), acc[0][1]);          \
-    acc[1][1] = Mma<T>::op((AV).y, (BV), acc[1][1]);          \
-    acc[2][1] = Mma<T>::op((AV).z, (BV), acc[2][1]);          \
-    acc[3][1] = Mma<T>::op((AV).w, (BV), acc[3][1]);
-
-template <class T, int NST>
-__device__ __forceinline__ void tile_product(const Quad<T>* __restrict__ ak4,
-                                             const Quad<T>* __restrict__ av4,
-                                             const T* __restrict__ B, int rows, int ncols,
-                                             int colk, int colv, int lane, int grp,
-                                             typename Mma<T>::acc (&acc)[4][2]) {
-    if constexpr (sizeof(T) == 4) {
-        T bk[NST], bv[NST];
-#pragma unroll
-        for (int st = 0; st < NST; ++st) {
-            const int row = 4 * st + grp;
-            const bool ok = row < rows;
-            const T* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
-            bk[st] = ok ? br[colk] : T(0);
-            bv[st] = ok ? br[colv] : T(0);
-        }
-#pragma unroll
-        for (int st = 0; st < NST; ++st) {
-            const Quad<T> ak = ak4[st * 64 + lane];
-            const Quad<T> av = av4[st * 64 + lane];
-            LSPR_MMA_STEP(ak, av, bk[st], bv[st])
-        }
-    } else {
-        constexpr int G = 2;
-#pragma unroll 1
-        for (int g0 = 0; g0 < NST; g0 += G) {
-            T bk[G], bv[G];
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const int row = 4 * (g0 + k) + grp;
-                const bool ok = g0 + k < NST && row < rows;
-                const T* br = B + static_cast<size_t>(ok ? row : 0) * ncols;
-                bk[k] = ok ? br[colk] : T(0);
-                bv[k] = ok ? br[colv] : T(0);
-            }
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                if (g0 + k < NST) {
-                    const Quad<T> ak = ak4[(g0 + k) * 64 + lane];
-                    const Quad<T> av = av4[(g0 + k) * 64 + lane];
-                    LSPR_MMA_STEP(ak, av, bk[k], bv[k])
-                }
-            }
-        }
-    }
-}
-#undef LSPR_MMA_STEP
-
 // Row within a 16 x 16 result tile of accumulator element q of lane group grp = lane / 16:
 // v_mfma_f32_16x16x4f32 holds rows 4 grp + q, v_mfma_f64_16x16x4f64 rows grp + 4 q.
 template <class T>
 __device__ __forceinline__ int out_row(int grp, int q) {
     return sizeof(T) == 4 ? 4 * grp + q : grp + 4 * q;
-}
-
-// Elements of a tile's left factor: expansion tiles nstep * 256, direct tiles two factors
-// (double layer, then single layer) of nstep * 256.
-__device__ __forceinline__ int tile_elems(const TileDesc& T) {
-    return (T.kind == 0 ? 256 : 512) * T.nstep;
-}
-
-template <class T, int PF, int NSM, int NTHR>
-__global__ void __launch_bounds__(NTHR, 2)
-k_far_tiles(const Chunk* __restrict__ chunks, const int32_t* __restrict__ chunk_order, int halves,
-            const int32_t* __restrict__ tile_off,
-            const int32_t* __restrict__ tile_self, const TileDesc* __restrict__ tiles,
-            const T* __restrict__ tileA, const T* __restrict__ dens, const T* __restrict__ mom,
-            int pad, int nwc, int abuf_elems, double* __restrict__ out_self,
-            double* __restrict__ out_all) {
-    using Acc = typename Mma<T>::acc;
-    constexpr int PER16 = 16 / sizeof(T);  // elements per 16-byte staging chunk
-    extern __shared__ float4 abuf16[];    // [2][abuf_elems / PER16]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int nthr = NTHR;
-    const int c16 = lane & 15, grp = lane >> 4;
-    const int ncols = 2 * pad;
-    // halves == 2: the chunk's column groups are split over two workgroups (b and b + 8,
-    // which land on the same XCD), so that two independent workgroups share each CU
-    const int b = blockIdx.x;
-    const int half = halves == 2 ? (b >> 3) & 1 : 0;
-    const int chunk = chunk_order[halves == 2 ? ((b >> 4) << 3) + (b & 7) : b];
-    if (chunk < 0) return;
-    const Chunk C = chunks[chunk];
-    const int ntg = C.end - C.start;
-    const int wg = wave + half * (NTHR / 64);  // column group of this wave
-    const bool mma = wg < nwc;
-    const int colk = 16 * wg + c16;        // K column of this lane
-    const int colv = pad + 16 * wg + c16;  // V column of this lane
-    Acc acc[4][2];
-    double run[4][2][4];  // FP32 only: FP64 running sums of the tiles' partials
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            acc[a][b] = Acc{0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) run[a][b][q] = 0.0;
-        }
-    const int t_beg = tile_off[chunk], t_end = tile_off[chunk + 1];
-    const int t_mid = t_beg + tile_self[chunk];
-    const int buf16 = abuf_elems / PER16;
-    auto result = [&](int mt, int b, int q) -> double {
-        if constexpr (sizeof(T) == 4) return run[mt][b][q];
-        else return acc[mt][b][q];
-    };
-    // stage the first left factor
-    if (t_beg < t_end) {
-        const TileDesc Tf = tiles[t_beg];
-        const int n16 = tile_elems(Tf) / PER16;
-        const float4* src = reinterpret_cast<const float4*>(tileA + Tf.a_off());
-        for (int k = tid; k < n16; k += nthr) abuf16[k] = src[k];
-    }
-    __syncthreads();
-    // the next tile's descriptor is read one tile ahead, so that the B operands of a tile
-    // can be requested as soon as the tile starts
-    TileDesc Tnext = tiles[t_beg < t_end ? t_beg : 0];
-    for (int e = t_beg; e < t_end; ++e) {
-        const int cur = (e - t_beg) & 1;
-        const TileDesc Te = Tnext;
-        if (e + 1 < t_end) Tnext = tiles[e + 1];
-        // fetch the next left factor into registers
-        float4 pf[PF];
-        int n16n = 0;
-        const float4* srcn = reinterpret_cast<const float4*>(tileA);
-        if (e + 1 < t_end) {
-            n16n = tile_elems(Tnext) / PER16;
-            srcn = reinterpret_cast<const float4*>(tileA + Tnext.a_off());
-        }
-#pragma unroll
-        for (int r = 0; r < PF; ++r) {
-            const int k = tid + r * nthr;
-            pf[r] = k < n16n ? srcn[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        if (mma) {
-            const Quad<T>* ak4 = reinterpret_cast<const Quad<T>*>(abuf16 + cur * buf16);
-            if (Te.kind == 0)
-                tile_product<T, NSM>(ak4, ak4, mom + static_cast<size_t>(Te.b_row0) * ncols,
-                                     Te.b_rows, ncols, colk, colv, lane, grp, acc);
-            else
-                tile_product<T, DSTEPS>(ak4, ak4 + 64 * DSTEPS, dens + static_cast<size_t>(Te.b_row0) * ncols,
-                                   Te.b_rows, ncols, colk, colv, lane, grp, acc);
-            if constexpr (sizeof(T) == 4) {
-                // the tile's FP32 partial joins an FP64 running sum
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) run[a][b][q] += static_cast<double>(acc[a][b][q]);
-                        acc[a][b] = Acc{0, 0, 0, 0};
-                    }
-            }
-        }
-        {
-            float4* dst = abuf16 + (cur ^ 1) * buf16;
-#pragma unroll
-            for (int r = 0; r < PF; ++r) {
-                const int k = tid + r * nthr;
-                if (k < n16n) dst[k] = pf[r];
-            }
-        }
-        // own-surface sums are complete after the last own-surface tile
-        if (e + 1 == t_mid && out_self != nullptr && mma) {
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int t = 16 * mt + out_row<T>(grp, q);
-                    if (t < ntg) {
-                        double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
-                        rowp[colk] = result(mt, 0, q);
-                        rowp[colv] = result(mt, 1, q);
-                    }
-                }
-        }
-        __syncthreads();
-    }
-    if (!mma) return;
-    if (t_mid == t_beg && out_self != nullptr) {  // no own-surface tiles
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = 16 * mt + out_row<T>(grp, q);
-                if (t < ntg) {
-                    double* rowp = out_self + static_cast<size_t>(C.start + t) * ncols;
-                    rowp[colk] = 0.0;
-                    rowp[colv] = 0.0;
-                }
-            }
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int t = 16 * mt + out_row<T>(grp, q);
-            if (t < ntg) {
-                double* rowp = out_all + static_cast<size_t>(C.start + t) * ncols;
-                rowp[colk] = result(mt, 0, q);
-                rowp[colv] = result(mt, 1, q);
-            }
-        }
 }
 
 // Scalar offset of the next K-step's B operand.  The empty asm makes each step's offset opaque,
@@ -654,8 +439,10 @@ __device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) 
 // factors side by side) and a chunk's tiles are read by `halves` workgroups instead of
 // 2 * halves; each wave's arithmetic is that of OPS = 1.
 template <class T, int NSM, int S, int OPS = 1>
-__global__ void __launch_bounds__(256 * OPS, OPS == 2 ? (sizeof(T) == 8 ? 1 : 2)
-                                                      : (sizeof(T) == 8 ? 2 : ((S == 2 || NSM > 21) ? 3 : 4)))
+__global__ void __launch_bounds__(256 * OPS,
+                                  OPS == 2 ? (sizeof(T) == 8 ? 1 : 2)
+                                           : (sizeof(T) == 8 || (S > 1 && NSM > 21) ? 2
+                                                                                    : (S > 1 || NSM > 21 ? 3 : 4)))
 k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
                const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
                const TileDesc* __restrict__ tiles,
@@ -726,8 +513,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
         if constexpr (S > 1) {
             // one 8 KB slot per column group (and operator), passed from wave to wave; the slots
             // follow the left-factor buffer
-            constexpr int AEL = OPS == 2 ? (NSM > 2 * DSTEPS ? NSM : 2 * DSTEPS) * 256
-                                         : (NSM > DSTEPS ? NSM : DSTEPS) * 256;
+            constexpr int AEL = OPS * (NSM > DSTEPS ? NSM : DSTEPS) * 256;
             double* red = reinterpret_cast<double*>(abuf16 + AEL / EPU) +
                           ((wave & 3) / S + (OPS == 2 ? opr * G : 0)) * 16 * 64;
             for (int k = 1; k < S; ++k) {
@@ -787,42 +573,25 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
         return D;
     };
     // the part of a left factor this workgroup uses: all of an expansion tile, the factor of its
-    // own operator of a direct tile (of each tile of a pair: two pieces of 8 K-steps, the second
-    // one direct tile further on), or with OPS = 2 both factors (its first element, count)
+    // own operator of a direct tile, or with OPS = 2 both (its first element, count).  Every
+    // tile is staged as NB K-steps (OPS = 2: 2 NB): the loads past its own elements read zero,
+    // so the steps a tile does not have add nothing and the loop needs no branch.
     auto own_off = [&](const TileDesc& D) {
         return D.a_off() +
-               (OPS == 1 && D.kind != 0 ? static_cast<int64_t>(opr) * DSTEPS * 256 : 0);
+               (OPS == 1 && D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
     };
-    // With pairs (PAIRS: the operand registers hold 2 DSTEPS steps) every direct tile runs as
-    // a pair: an unpaired one stages zeros for the second piece (the loads past its record
-    // read zero), whose products then add nothing.
-    constexpr bool PAIRS = sizeof(T) == 8 && OPS == 1 && (NSM > DSTEPS ? NSM : DSTEPS) >= 2 * DSTEPS;
     auto own_elems = [](const TileDesc& D) {
-        return PAIRS && D.kind != 0 ? 2 * DSTEPS * 256
-                                    : 256 * D.nstep * (OPS == 2 && D.kind == 1 ? 2 : 1);
+        return 256 * D.nstep * (OPS == 2 && D.kind == 1 ? 2 : 1);
     };
-    // bytes of the record over a tile's own part: a pair's two pieces and the other
-    // operator's factor of the first tile in between; one piece of an unpaired direct tile
-    auto own_bytes = [&](const TileDesc& D) {
-        return (D.kind == 2 ? 3u * DSTEPS * 256u
-                            : static_cast<uint32_t>(PAIRS && D.kind == 1 ? DSTEPS * 256
-                                                                          : own_elems(D))) * ES;
-    };
-    // prefetch rounds r >= RSEG load a pair's second piece: their offsets skip the other
-    // operator's factor of the first tile (DSTEPS * 256 elements)
-    constexpr int RSEG = DSTEPS * 256 / (EPU * NTHR);
-    static_assert(OPS == 2 || DSTEPS * 256 % (EPU * NTHR) == 0, "pair pieces split by rounds");
+    constexpr int STAGE16 = OPS * NB * 256 / EPU;  // 16-byte units staged per tile
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
     T bc[NBS];
     if (t_beg < t_end) {
         const int n16 = own_elems(Te) / EPU;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
-        const int seg = DSTEPS * 256 / EPU;  // a pair's second piece, or zeros
-        for (int k = tid; k < n16; k += NTHR)
-            abuf16[lds_unit<T>(k)] = k < seg || !PAIRS || Te.kind == 0 ? src[k]
-                                     : Te.kind == 2 ? src[k + seg]
-                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int k = tid; k < STAGE16; k += NTHR)
+            abuf16[lds_unit<T>(k)] = k < n16 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
         for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
@@ -830,8 +599,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
     __syncthreads();
     // a left factor is NA elements per thread: NA / EPU 16-byte units at unit index
     // tid + NTHR r, then NA % EPU elements at element index NTHR EPU (NA / EPU) + tid + NTHR r
-    constexpr int NA = OPS == 1 ? (NSM > DSTEPS ? NSM : DSTEPS)
-                                : ((NSM + 1) / 2 > DSTEPS ? (NSM + 1) / 2 : DSTEPS);
+    constexpr int NA = NB;
     constexpr int QA = NA / EPU, RA = NA % EPU;
     // one tile: prefetches for the next, products of this one (all waves of the workgroup run
     // it together: it ends with a barrier)
@@ -844,15 +612,13 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
         float4 pf[QA];
         T pr[RA > 0 ? RA : 1];
         const bool more = e + 1 < t_end;
-        const int n16n = more ? own_elems(Tn) / EPU : 0;
+        const int n16n = more ? STAGE16 : 0;  // past the tile's own elements: zeros
         {
-            const uint32_t gap = more && Tn.kind == 2 ? DSTEPS * 256u * ES : 0u;
             const __amdgpu_buffer_rsrc_t ra =
-                buffer_rsrc(tileA + own_off(Tn), more ? own_bytes(Tn) : 0u);
+                buffer_rsrc(tileA + own_off(Tn), more ? own_elems(Tn) / EPU * 16u : 0u);
 #pragma unroll
             for (int r = 0; r < QA; ++r) {
-                const uint32_t so = r * NTHR * 16 + (r >= RSEG ? gap : 0u);
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, so, 0);
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ra, tid * 16, r * NTHR * 16, 0);
                 pf[r] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
                                     __uint_as_float(v[2]), __uint_as_float(v[3]));
             }
@@ -864,7 +630,6 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
         if (mma) {
             // with OPS = 2 the V waves read a direct tile's second factor
             const float4* ab = abuf16 + (OPS == 2 && Te.kind == 1 ? opr * Te.nstep * 256 / EPU : 0);
-            // FP32: a tile's partial joins the FP64 running sums (after each tile of a pair)
             auto flush = [&]() {
                 if constexpr (sizeof(T) == 4) {
 #pragma unroll
@@ -875,47 +640,43 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
                     }
                 }
             };
-// NS K-steps; FL >= 0: the partial is flushed after step FL (the first tile of a pair)
-#define LSPR_OP_TILE(NS, FL)                                                               \
-    if constexpr (S == 1) {                                                                \
-        uint32_t so = 0;                                                                   \
-        _Pragma("unroll") for (int st = 0; st < (NS); ++st) {                              \
-            const Quad<T> a = lds_quad<T>(ab, st, lane);                                   \
-            acc[0] = Mma<T>::op(a.x, bc[st], acc[0]);                                      \
-            acc[1] = Mma<T>::op(a.y, bc[st], acc[1]);                                      \
-            acc[2] = Mma<T>::op(a.z, bc[st], acc[2]);                                      \
-            acc[3] = Mma<T>::op(a.w, bc[st], acc[3]);                                      \
-            bc[st] = load_b_at(rbn, so);                                                   \
-            so = next_step(so, bstep);                                                     \
-            if ((FL) >= 0 && st == (FL)) flush();                                          \
-        }                                                                                  \
-        _Pragma("unroll") for (int st = (NS); st < NB; ++st) {                             \
-            bc[st] = load_b_at(rbn, so);                                                   \
-            so = next_step(so, bstep);                                                     \
-        }                                                                                  \
-    } else {                                                                               \
-        _Pragma("unroll") for (int i = 0; i < NBS; ++i) {                                  \
-            const int st = kpart + S * i;                                                  \
-            if (st < (NS)) {                                                               \
-                const Quad<T> a = lds_quad<T>(ab, st, lane);                               \
-                acc[0] = Mma<T>::op(a.x, bc[i], acc[0]);                                   \
-                acc[1] = Mma<T>::op(a.y, bc[i], acc[1]);                                   \
-                acc[2] = Mma<T>::op(a.z, bc[i], acc[2]);                                   \
-                acc[3] = Mma<T>::op(a.w, bc[i], acc[3]);                                   \
-            }                                                                              \
-            bc[i] = load_b(rbn, st);                                                       \
-            if ((FL) >= 0 && i == ((FL) + 1) / S - 1) flush();                             \
-        }                                                                                  \
-    }
-            if (Te.kind == 0) {
-                LSPR_OP_TILE(NSM, -1)
-            } else if constexpr (PAIRS) {
-                LSPR_OP_TILE(2 * DSTEPS, DSTEPS - 1)
+            // one loop for every tile: NB steps of LDS reads, products and B prefetches; FP32:
+            // each wave's partial of every DSTEPS K-steps of the tile joins the FP64 running
+            // sums, so no FP32 partial sums more than 4 DSTEPS panels or terms
+            if constexpr (S == 1) {
+                // the tile's own steps on the matrix cores (a uniform branch per step), the next
+                // tile's operands requested for every step
+                const int ns = Te.nstep;
+                uint32_t so = 0;
+#pragma unroll
+                for (int st = 0; st < NB; ++st) {
+                    const Quad<T> a = lds_quad<T>(ab, st, lane);
+                    if (st < ns) {
+                        acc[0] = Mma<T>::op(a.x, bc[st], acc[0]);
+                        acc[1] = Mma<T>::op(a.y, bc[st], acc[1]);
+                        acc[2] = Mma<T>::op(a.z, bc[st], acc[2]);
+                        acc[3] = Mma<T>::op(a.w, bc[st], acc[3]);
+                    }
+                    bc[st] = load_b_at(rbn, so);
+                    so = next_step(so, bstep);
+                }
+                flush();
             } else {
-                LSPR_OP_TILE(DSTEPS, -1)
+#pragma unroll
+                for (int i = 0; i < NBS; ++i) {
+                    const int st = kpart + S * i;
+                    if (st < NB) {
+                        const Quad<T> a = lds_quad<T>(ab, st, lane);
+                        acc[0] = Mma<T>::op(a.x, bc[i], acc[0]);
+                        acc[1] = Mma<T>::op(a.y, bc[i], acc[1]);
+                        acc[2] = Mma<T>::op(a.z, bc[i], acc[2]);
+                        acc[3] = Mma<T>::op(a.w, bc[i], acc[3]);
+                    }
+                    bc[i] = load_b(rbn, st);
+                    // this wave's steps of K-steps [8 m, 8 m + 8) are i in [8 m / S, 8 (m + 1) / S)
+                    if ((i + 1) % (DSTEPS / S) == 0 || i + 1 == NBS) flush();
+                }
             }
-#undef LSPR_OP_TILE
-            flush();
         }
         __syncthreads();  // every wave is done with this tile's left factor
         {
@@ -982,7 +743,7 @@ k_far_reduce(const Chunk* __restrict__ chunks, const FarRed* __restrict__ red, i
 // partition, the FP32 partial per tile, its FP64 running sum and the wave-order addition at
 // the end are those of k_far_tiles_op's narrow form, so both give identical sums.
 template <class T, int NSM, int S>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4 && S == 4) ? 4 : 2)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 && NSM <= 21 ? 3 : 2)
 k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
              const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
              const TileDesc* __restrict__ tiles, const T* __restrict__ tileA,
@@ -1062,18 +823,11 @@ k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items
             }
     };
     // operand sources of tile e (empty records past the chunk's last tile)
-    // (a pair's two pieces of this operator's factor are one direct tile apart: the record
-    // spans the other operator's factor of the first tile in between)
     auto a_rsrc = [&](int e) {
         if (e >= t_end) return buffer_rsrc(tileA, 0u);
         const TileDesc D = tiles[e];
-        const int64_t off = D.a_off() + (D.kind != 0 ? static_cast<int64_t>(opr) * DSTEPS * 256 : 0);
-        const uint32_t steps = D.kind == 2 ? 3 * DSTEPS : static_cast<uint32_t>(D.nstep);
-        return buffer_rsrc(tileA + off, steps * 256u * ES);
-    };
-    // byte offset of a pair's second piece from its first (0 for other tiles)
-    auto a_gap = [&](int e) {
-        return e < t_end && tiles[e].kind == 2 ? DSTEPS * 256u * ES : 0u;
+        const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
+        return buffer_rsrc(tileA + off, static_cast<uint32_t>(D.nstep) * 256u * ES);
     };
     auto b_rsrc = [&](int e) {
         if (e >= t_end) return buffer_rsrc(dens, 0u);
@@ -1083,17 +837,17 @@ k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items
                            static_cast<uint32_t>(D.b_rows) * static_cast<uint32_t>(ncols) * ES);
     };
     // this lane's A operand of K-step st: 4 consecutive elements (the four target tiles)
-    auto load_a = [&](__amdgpu_buffer_rsrc_t ra, int st, uint32_t gap) {
+    auto load_a = [&](__amdgpu_buffer_rsrc_t ra, int st) {
         Quad<T> q;
         if constexpr (sizeof(T) == 4) {
-            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 1024 + gap, 0);
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 1024, 0);
             q.x = __uint_as_float(v[0]);
             q.y = __uint_as_float(v[1]);
             q.z = __uint_as_float(v[2]);
             q.w = __uint_as_float(v[3]);
         } else {
-            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048 + gap, 0);
-            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048 + gap, 0);
+            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048, 0);
+            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048, 0);
             q.x = __builtin_bit_cast(double, make_uint2(lo[0], lo[1]));
             q.y = __builtin_bit_cast(double, make_uint2(lo[2], lo[3]));
             q.z = __builtin_bit_cast(double, make_uint2(hi[0], hi[1]));
@@ -1103,48 +857,40 @@ k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items
     };
     Quad<T> a[NBS];
     T bv[NBS];
-    // steps kpart + S i of a pair with i >= 8 / S are its second tile's
-    constexpr int ISEG = DSTEPS / S;
     {
         const __amdgpu_buffer_rsrc_t ra = a_rsrc(t_beg), rb = b_rsrc(t_beg);
-        const uint32_t gap = a_gap(t_beg);
 #pragma unroll
         for (int i = 0; i < NBS; ++i) {
-            a[i] = load_a(ra, kpart + S * i, i >= ISEG ? gap : 0u);
+            a[i] = load_a(ra, kpart + S * i);
             bv[i] = load_elem<T>(rb, boff, (kpart + S * i) * bstep);
         }
     }
-    // FP32: a tile's partial joins the FP64 running sums (after each tile of a pair)
-    auto flush = [&]() {
-        if constexpr (sizeof(T) == 4) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
-                acc[q] = Acc{0, 0, 0, 0};
-            }
-        }
-    };
     auto tile = [&](int e) {
-        const TileDesc D = tiles[e];
-        const int ns = D.nstep;
-        const bool pair = D.kind == 2;
         const __amdgpu_buffer_rsrc_t ran = a_rsrc(e + 1), rbn = b_rsrc(e + 1);
-        const uint32_t gapn = a_gap(e + 1);
 #pragma unroll
         for (int i = 0; i < NBS; ++i) {
             const int st = kpart + S * i;
-            if (st < ns && mma) {
+            if (st < NA && mma) {  // past a tile's own steps the operands read zero
                 acc[0] = Mma<T>::op(a[i].x, bv[i], acc[0]);
                 acc[1] = Mma<T>::op(a[i].y, bv[i], acc[1]);
                 acc[2] = Mma<T>::op(a[i].z, bv[i], acc[2]);
                 acc[3] = Mma<T>::op(a[i].w, bv[i], acc[3]);
             }
-            a[i] = load_a(ran, st, i >= ISEG ? gapn : 0u);
+            a[i] = load_a(ran, st);
             bv[i] = load_elem<T>(rbn, boff, st * bstep);
-            if (i == ISEG - 1 && pair) flush();
+            // FP32: this wave's partial of every DSTEPS K-steps of the tile joins the FP64
+            // running sums (the staged kernel's schedule)
+            if constexpr (sizeof(T) == 4) {
+                if ((i + 1) % (DSTEPS / S) == 0 || i + 1 == NBS) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
+                        acc[q] = Acc{0, 0, 0, 0};
+                    }
+                }
+            }
         }
-        flush();
     };
     for (int e = t_beg; e < t_mid; ++e) tile(e);
     if (o_self != nullptr) write_sums(o_self + static_cast<size_t>(C.start) * ncols);
@@ -1317,7 +1063,7 @@ k_p2m_mfma(const P2MSeg* __restrict__ segs, const int64_t* __restrict__ aoff,
         }
 }
 
-// ---- geometry-only tiles for k_far_tiles (built once per geometry)
+// ---- geometry-only tiles of the far-field products (built once per geometry)
 // Expansion tile of list entry e: Taylor coefficients of the chunk's 64 targets for its box.
 // tileA32 (FP64 builds, may be null): the same values rounded to FP32, at the same offsets.
 template <class T, int P>
@@ -1367,7 +1113,8 @@ __device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
 
 // Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
-// up to 4 * DSTEPS consecutive source panels (zero for the target's own panel and past the range).
+// up to 4 direct_steps() consecutive source panels (zero for the target's own panel and past the
+// range).
 template <class T>
 __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
                                   const int32_t* __restrict__ p2p_tile,
@@ -1548,32 +1295,17 @@ const float* tiles_of<float>(const Geometry& g) { return g.tileA.p; }
 template <>
 const double* tiles_of<double>(const Geometry& g) { return g.tileA64.p; }
 
-template <class T, int PF, int NSM, int NTHR>
-void launch_far_tiles_pf(Geometry& g, int pad, int halves, int nwc, int abuf, const T* dens,
-                         const T* mom, double* os, double* oa, hipStream_t s) {
-    const int nblk = g.n_order * halves;
-    const size_t lds = 2 * static_cast<size_t>(abuf) * sizeof(T);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles<T, PF, NSM, NTHR>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  static_cast<int>(lds));
-    hipLaunchKernelGGL((k_far_tiles<T, PF, NSM, NTHR>), dim3(nblk), dim3(NTHR), lds, s,
-                       g.chunks.p, g.chunk_order.p, halves, g.tile_off.p, g.tile_self.p,
-                       g.tiles.p, tiles_of<T>(g), dens, mom, pad, nwc, abuf, os, oa);
-    LSPR_HIP(hipGetLastError());
-}
-
 // Work items of a launch of pad columns per operator: pieces of chunks for products of up to
 // 16 wavelengths (plan 0), the other plan above.
-inline const Geometry::FarPlan& far_plan_for(const Geometry& g, int pad, bool paired) {
-    return g.far_plan[paired ? 1 : 0][pad > 32 ? 1 : 0];
+inline const Geometry::FarPlan& far_plan_for(const Geometry& g, int pad) {
+    return g.far_plan[pad > 32 ? 1 : 0];
 }
 
 }  // namespace
 
 // Scratch bytes of the pieces' partial sums of a launch of pad columns per operator.
-size_t far_part_bytes(const Geometry& g, int pad, bool fp64) {
-    return static_cast<size_t>(far_plan_for(g, pad, fp64).n_slots) * NT * 2 * pad * sizeof(double);
+size_t far_part_bytes(const Geometry& g, int pad) {
+    return static_cast<size_t>(far_plan_for(g, pad).n_slots) * NT * 2 * pad * sizeof(double);
 }
 
 namespace {
@@ -1592,24 +1324,21 @@ template <class T, int NSM, int S, int OPS = 1>
 void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                            double* os, double* oa, hipStream_t s) {
     const int halves = pad > 64 ? 2 : 1;
-    // FP64 products visit the list with paired direct tiles
-    constexpr bool paired = sizeof(T) == 8;
-    const Geometry::FarPlan& fp = far_plan_for(g, pad, paired);
+    const Geometry::FarPlan& fp = far_plan_for(g, pad);
     double* part = nullptr;
     if (fp.n_slots > 0)
-        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad, paired)));
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad)));
     const int nblk = fp.n_order * (OPS == 2 ? 1 : 2) * halves;
     // the left factor (OPS = 2: a direct tile's two), then (S > 1) one slot of FP64 sums per
     // column group for the final additions
-    const size_t ab = OPS == 2 ? std::max<size_t>(abuf, 2 * DSTEPS * 256) : abuf;
+    const size_t ab = OPS == 2 ? 2 * static_cast<size_t>(abuf) : abuf;
     const size_t lds = ab * sizeof(T) + (S > 1 ? OPS * (4 / S) * 16 * 64 * 8 : 0);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_far_tiles_op<T, NSM, S, OPS>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(lds));
     hipLaunchKernelGGL((k_far_tiles_op<T, NSM, S, OPS>), dim3(nblk), dim3(256 * OPS), lds, s,
-                       g.chunks.p, fp.items.p, fp.order.p,
-                       paired ? g.ktile_self.p : g.tile_self.p, paired ? g.ktiles.p : g.tiles.p,
+                       g.chunks.p, fp.items.p, fp.order.p, g.tile_self.p, g.tiles.p,
                        tiles_of<T>(g), dens, mom, pad, pad / 16, halves, os, oa, part);
     LSPR_HIP(hipGetLastError());
     launch_far_reduce(g, fp, pad, part, os, oa, s);
@@ -1618,17 +1347,14 @@ void launch_far_tiles_op_s(Geometry& g, int pad, int abuf, const T* dens, const 
 template <class T, int NSM, int S>
 void launch_far_stream(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                        double* oa, hipStream_t s) {
-    // FP64 products visit the list with paired direct tiles
-    constexpr bool paired = sizeof(T) == 8;
-    const Geometry::FarPlan& fp = far_plan_for(g, pad, paired);
+    const Geometry::FarPlan& fp = far_plan_for(g, pad);
     double* part = nullptr;
     if (fp.n_slots > 0)
-        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad, paired)));
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad)));
     const int nblk = fp.n_order * 2;
     hipLaunchKernelGGL((k_far_stream<T, NSM, S>), dim3(nblk), dim3(256), 0, s, g.chunks.p,
-                       fp.items.p, fp.order.p, paired ? g.ktile_self.p : g.tile_self.p,
-                       paired ? g.ktiles.p : g.tiles.p, tiles_of<T>(g), dens, mom, pad, pad / 16,
-                       os, oa, part);
+                       fp.items.p, fp.order.p, g.tile_self.p, g.tiles.p, tiles_of<T>(g), dens,
+                       mom, pad, pad / 16, os, oa, part);
     LSPR_HIP(hipGetLastError());
     launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
@@ -1658,57 +1384,23 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
 template <class T>
 void launch_far_tiles(Geometry& g, int pad, const T* dens, const T* mom, double* os,
                       double* oa, hipStream_t s) {
-    if (g.far_op_min_pad > 0 && pad >= g.far_op_min_pad) {  // one operator per workgroup
-        const int nsm = expansion_slice_steps(g.n_terms);
-        const int abuf = std::max(nsm, DSTEPS) * 256;  // largest part a workgroup stages
+    const int nsm = expansion_slice_steps(g.n_terms);
+    const int abuf = direct_steps(g.n_terms) * 256;  // largest part a workgroup stages
 #define LSPR_FAR_OP(NSM_)                                                                    \
     case NSM_:                                                                               \
         launch_far_tiles_op<T, NSM_>(g, pad, abuf, dens, mom, os, oa, s);                    \
         return;
-        switch (nsm) {
-            LSPR_FAR_OP(3)
-            LSPR_FAR_OP(7)
-            LSPR_FAR_OP(13)
-            LSPR_FAR_OP(15)
-            LSPR_FAR_OP(16)
-            LSPR_FAR_OP(21)
-            LSPR_FAR_OP(31)
-            default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
-        }
-#undef LSPR_FAR_OP
-    }
-    const int nwc = pad / 16;  // column groups (16 K and 16 V columns each)
-    // FP32: 4-wave workgroups, two per CU (a chunk with more than 4 column groups is split
-    // over two workgroups); FP64 left factors fill a CU's LDS, so one 8-wave workgroup per CU
-    constexpr int NTHR = sizeof(T) == 4 ? 256 : 512;
-    const int halves = nwc > NTHR / 64 ? 2 : 1;
-    const int nsm = expansion_slice_steps(g.n_terms);
-    const int abuf = std::max(nsm * 256, 2 * DSTEPS * 256);  // elements of the largest left factor
-    const int per16 = 16 / static_cast<int>(sizeof(T));
-    const int pf = (abuf / per16 + NTHR - 1) / NTHR;  // 16-byte chunks per thread
-    LSPR_REQUIRE(pf <= 8, LSPR_E_INVALID, "expansion tile too large for the matrix-core kernel");
-#define LSPR_FAR_TILES(NSM_)                                                                    \
-    case NSM_:                                                                                  \
-        if (pf <= 2)                                                                            \
-            launch_far_tiles_pf<T, 2, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
-        else if (pf <= 4)                                                                       \
-            launch_far_tiles_pf<T, 4, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
-        else if (pf <= 6)                                                                       \
-            launch_far_tiles_pf<T, 6, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
-        else                                                                                    \
-            launch_far_tiles_pf<T, 8, NSM_, NTHR>(g, pad, halves, nwc, abuf, dens, mom, os, oa, s); \
-        break;
     switch (nsm) {  // K-steps of an expansion slice for P = 2, 4, 6, 12, 15, 8, 10
-        LSPR_FAR_TILES(3)
-        LSPR_FAR_TILES(7)
-        LSPR_FAR_TILES(13)
-        LSPR_FAR_TILES(15)
-        LSPR_FAR_TILES(16)
-        LSPR_FAR_TILES(21)
-        LSPR_FAR_TILES(31)
+        LSPR_FAR_OP(3)
+        LSPR_FAR_OP(7)
+        LSPR_FAR_OP(13)
+        LSPR_FAR_OP(15)
+        LSPR_FAR_OP(16)
+        LSPR_FAR_OP(21)
+        LSPR_FAR_OP(31)
         default: throw Error(LSPR_E_INVALID, "unsupported expansion order");
     }
-#undef LSPR_FAR_TILES
+#undef LSPR_FAR_OP
 }
 
 inline const float* p2m_tiles_of(const Geometry& g, const float*) { return g.p2mA.p; }
@@ -1933,20 +1625,21 @@ int64_t estimate_tile_elems(const Geometry& g) {
                               expansion_slice_steps(g.n_terms) * 256;
     int64_t e = static_cast<int64_t>(g.m2p_off_h.size() == static_cast<size_t>(nc) + 1
                                          ? g.m2p_off_h[nc] : 0) * exp_elems;
-    for (const Range& r : g.p2p_rng_h)
-        e += static_cast<int64_t>((r.end - r.start + 4 * DSTEPS - 1) / (4 * DSTEPS)) * 2 * DSTEPS * 256;
+    const int dmax = direct_steps(g.n_terms);
+    for (const Range& r : g.p2p_rng_h) {
+        const int n = r.end - r.start, full = n / (4 * dmax), rest = n % (4 * dmax);
+        e += (static_cast<int64_t>(full) * dmax + (rest + 3) / 4) * 2 * 256;
+    }
     return e;
 }
 
 // Work items of the far-field kernels over one tile list (per chunk: first tile `off`, own-
 // surface tiles `self`): a chunk whose cost (K-steps + 4 per tile) exceeds `split` x the mean
 // is cut at its own-surface boundary and into pieces of about equal cost (split 0: whole
-// chunks), never between tiles t and t + 1 where keep[t] is set; then XCD runs of
-// consecutive chunks' items, cut at equal shares of the cost, with the heaviest items first
-// within each run (workgroup b takes an item of run b % 8).
+// chunks); then XCD runs of consecutive chunks' items, cut at equal shares of the cost, with
+// the heaviest items first within each run (workgroup b takes an item of run b % 8).
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, const std::vector<uint8_t>& keep,
-                           double split) {
+                           const std::vector<int32_t>& self, double split) {
     TilePlan::Items W;
     const int nc = static_cast<int>(self.size());
     auto tcost = [&](int t) { return static_cast<double>(tl[t].nstep) + 4.0; };
@@ -1981,7 +1674,7 @@ TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<in
                 int start = x, k = 0;
                 for (int t = x; t < y; ++t) {
                     acc += tcost(t);
-                    if (k < n - 1 && t + 1 < y && !keep[t] && acc >= (k + 1) * cs / n) {
+                    if (k < n - 1 && t + 1 < y && acc >= (k + 1) * cs / n) {
                         add(c, start, t + 1, W.n_slots++);
                         start = t + 1;
                         ++k;
@@ -2032,6 +1725,7 @@ TilePlan plan_tiles(const Geometry& g) {
                  LSPR_E_INVALID, "interaction lists missing on the host");
     const int nsl = expansion_slices(g.n_terms);      // tiles per expansion
     const int nsm = expansion_slice_steps(g.n_terms);  // K-steps of each
+    const int dmax = direct_steps(g.n_terms);         // most K-steps of a direct tile
     auto make_tile = [](int kind, int nstep, int64_t aoff, int r0, int rows) {
         LSPR_REQUIRE(aoff % 256 == 0 && aoff / 256 < INT32_MAX, LSPR_E_INVALID,
                      "tile store offset out of range");
@@ -2068,12 +1762,12 @@ TilePlan plan_tiles(const Geometry& g) {
                 }
             }
             for (int e = pa; e < pb; ++e)
-                for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 4 * DSTEPS) {
+                for (int p0 = rng[e].start; p0 < rng[e].end; p0 += 4 * dmax) {
+                    const int rows = std::min(4 * dmax, rng[e].end - p0), ns = (rows + 3) / 4;
                     p2p_tile.push_back(static_cast<int32_t>(tiles.size()));
                     p2p_chunk.push_back(c);
-                    tiles.push_back(
-                        make_tile(1, DSTEPS, aoff, p0, std::min(4 * DSTEPS, rng[e].end - p0)));
-                    aoff += 2 * DSTEPS * 256;
+                    tiles.push_back(make_tile(1, ns, aoff, p0, rows));
+                    aoff += 2 * static_cast<int64_t>(ns) * 256;
                 }
             if (phase == 0) tself[c] = static_cast<int32_t>(tiles.size()) - toff[c];
         }
@@ -2120,64 +1814,8 @@ TilePlan plan_tiles(const Geometry& g) {
     order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
-    // The FP64 products' tile list: consecutive direct tiles of one source range (the first
-    // full) become one 16-step tile when the kernels hold 16 steps of operands (expansion
-    // slices of at least 16 steps) and no paired-operator schedule is asked for; the left
-    // factors stay where they are.
-    // Where pairs could form is fixed by the lists alone, so that every schedule cuts chunks
-    // into the same pieces (identical sums): no piece ends inside a pairable couple.
-    const bool pairs = nsm >= 2 * DSTEPS && !g.pair_ops && !g.pair_narrow;
-    std::vector<uint8_t> pstart(tiles.size(), 0);
-    for (int c = 0; c < nc; ++c) {
-        const int m = toff[c] + tself[c];
-        for (int t = toff[c]; t + 1 < toff[c + 1]; ++t) {
-            const TileDesc &A = tiles[t], &B = tiles[t + 1];
-            if (A.kind == 1 && A.b_rows == 4 * DSTEPS && t + 1 != m && B.kind == 1 &&
-                B.b_row0 == A.b_row0 + 4 * DSTEPS && B.a_off() == A.a_off() + 2 * DSTEPS * 256) {
-                pstart[t] = 1;
-                ++t;
-            }
-        }
-    }
-    std::vector<TileDesc>& kt = P.ktiles;
-    std::vector<int32_t> kidx(tiles.size() + 1, 0);  // list position -> ktiles position
-    P.ktoff.assign(nc + 1, 0);
-    P.ktself.assign(nc, 0);
-    for (int c = 0; c < nc; ++c) {
-        P.ktoff[c] = static_cast<int32_t>(kt.size());
-        const int m = toff[c] + tself[c];
-        for (int t = toff[c]; t < toff[c + 1]; ++t) {
-            if (t == m) P.ktself[c] = static_cast<int32_t>(kt.size()) - P.ktoff[c];
-            const TileDesc& A = tiles[t];
-            kidx[t] = static_cast<int32_t>(kt.size());
-            if (pairs && pstart[t]) {
-                kidx[t + 1] = kidx[t];
-                TileDesc D = A;
-                D.kind = 2;
-                D.nstep = static_cast<int16_t>(2 * DSTEPS);
-                D.b_rows = A.b_rows + tiles[t + 1].b_rows;
-                kt.push_back(D);
-                ++t;
-            } else {
-                kt.push_back(A);
-            }
-        }
-        if (toff[c] + tself[c] == toff[c + 1])
-            P.ktself[c] = static_cast<int32_t>(kt.size()) - P.ktoff[c];
-    }
-    P.ktoff[nc] = static_cast<int32_t>(kt.size());
-    kidx[tiles.size()] = static_cast<int32_t>(kt.size());
-    // Work items per launch class, planned on the list and carried over to ktiles (the same
-    // pieces, workgroup order and scratch blocks).
-    for (int cls = 0; cls < 2; ++cls) {
-        P.far[0][cls] = plan_items(tiles, toff, tself, pstart, g.far_split[cls]);
-        P.far[1][cls] = P.far[0][cls];
-        for (FarItem& I : P.far[1][cls].items) {
-            const int a = I.t0, b = I.t1;
-            I.t0 = kidx[a];
-            I.t1 = a < b ? kidx[b - 1] + 1 : I.t0;
-        }
-    }
+    // Work items per launch class.
+    for (int cls = 0; cls < 2; ++cls) P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls]);
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
     for (int c = 0; c < nc; ++c) {
@@ -2230,13 +1868,9 @@ void build_tiles(Geometry& g, const TilePlan& P) {
     up.add(g.tiles.p, P.tiles.data(), P.tiles.size());
     up.add(g.tile_off.p, P.toff.data(), P.toff.size());
     up.add(g.tile_self.p, P.tself.data(), P.tself.size());
-    g.ktiles.alloc(std::max<size_t>(P.ktiles.size(), 1));
-    g.ktile_self.alloc(nc);
-    up.add(g.ktiles.p, P.ktiles.data(), P.ktiles.size());
-    up.add(g.ktile_self.p, P.ktself.data(), P.ktself.size());
-    for (int li = 0; li < 4; ++li) {
-        Geometry::FarPlan& fp = g.far_plan[li >> 1][li & 1];
-        const TilePlan::Items& W = P.far[li >> 1][li & 1];
+    for (int cls = 0; cls < 2; ++cls) {
+        Geometry::FarPlan& fp = g.far_plan[cls];
+        const TilePlan::Items& W = P.far[cls];
         fp.items.alloc(W.items.size());
         fp.order.alloc(W.order.size());
         up.add(fp.items.p, W.items.data(), W.items.size());
