@@ -529,7 +529,7 @@ size_t lspr::Geometry::device_bytes() const {
            near_off64.bytes() + near_col.bytes() + near_dv.bytes() + near_dk.bytes() +
            vself.bytes() + rhs_u.bytes() + charge_u.bytes() + ws_inv_eps.bytes() + ws_dens.bytes() + ws_mom.bytes() + ws_out.bytes() +
            ws_part.bytes() + p2m_seg.bytes() + p2m_red.bytes() + p2mA.bytes() + p2mA64.bytes() + p2m_aoff.bytes() + tiles.bytes() + tile_off.bytes() + chunk_order.bytes() +
-           far_plan[0].bytes() + far_plan[1].bytes() + ws_fpart.bytes() +
+           far_plan[0].bytes() + far_plan[1].bytes() + far_plan[2].bytes() + ws_fpart.bytes() +
            tile_self.bytes() + tileA.bytes() + tileA64.bytes() + src32.bytes() + src64.bytes();
 }
 

@@ -415,8 +415,8 @@ struct Geometry {
     DevBuf<int32_t> chunk_order;  // workgroup -> chunk of the matrix-core kernel (-1: none)
     int n_order = 0;              // entries of chunk_order (a multiple of 8)
     // Work items of the one-operator far-field kernel, one set per launch class (0: up to 16
-    // wavelengths, 1: more): chunks heavier than a share of the mean are cut into pieces of
-    // about that cost, so that no workgroup holds the launch's tail alone.
+    // wavelengths, 1: 17 to 32, 2: more): chunks heavier than a share of the mean are cut into
+    // pieces of about that cost, so that no workgroup holds the launch's tail alone.
     struct FarPlan {
         DevBuf<FarItem> items;
         DevBuf<int32_t> order;  // workgroup -> item (-1: none); a multiple of 8 entries
@@ -424,12 +424,14 @@ struct Geometry {
         int n_order = 0, n_red = 0, n_slots = 0;
         size_t bytes() const { return items.bytes() + order.bytes() + red.bytes(); }
     };
-    FarPlan far_plan[2];
+    FarPlan far_plan[3];
     // largest piece, as a fraction of the mean chunk cost, per launch class (0: no pieces):
-    // measured on the 32768-panel sphere (busiest chunk 1.95 x the mean), 0.35 for up to 16
-    // wavelengths (every workgroup resident at once: the busiest chunk set the launch time)
-    // and 0.5 above
-    double far_split[2] = {0.35, 0.5};
+    // measured on the 32768-panel sphere (busiest chunk 1.95 x the mean; in a launch of up to
+    // 16 wavelengths every workgroup is resident at once, so that chunk set the launch time);
+    // the times are flat around these values (above 32 wavelengths, cutting only chunks
+    // heavier than the mean saves most of the pieces' additions but slows the FP64 product by
+    // 5 % and leaves the FP32 one unchanged)
+    double far_split[3] = {0.25, 0.35, 0.35};
     DevBuf<float> tileA;      // FP32 left factors (need32)
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
@@ -554,7 +556,7 @@ struct TilePlan {
         std::vector<int32_t> order;
         std::vector<FarRed> red;
         int n_slots = 0;
-    } far[2];                                    // per launch class
+    } far[3];                                    // per launch class
     std::vector<int32_t> dto, dtr, dti;          // per chunk: direct tiles by first panel
     int64_t aoff = 0;                            // elements of one tile store
     int64_t tile_steps = 0, max_chunk_steps = 0;

@@ -338,6 +338,19 @@ constexpr int direct_steps(int n_terms) {
     return expansion_slice_steps(n_terms) > DSTEPS ? expansion_slice_steps(n_terms) : DSTEPS;
 }
 
+// Element of a tile's left factor (within one factor) holding K-step st, lane l (row 16 g + r
+// of the step's 16 x 4 operand: l = 16 g + r) and target tile mt.  FP32: the four target tiles
+// of a lane and step are adjacent (16 bytes, one 128-bit read).  FP64: the 32 bytes are split
+// into two planes of 64 lanes per step (target tiles 0-1, then 2-3), so that both 128-bit reads
+// of a step, and the copies that stage it, are contiguous across the lanes.
+template <class T>
+__host__ __device__ __forceinline__ size_t tile_index(int st, int l, int mt) {
+    if constexpr (sizeof(T) == 4)
+        return (static_cast<size_t>(st) * 64 + l) * 4 + mt;
+    else
+        return (static_cast<size_t>(2 * st + (mt >> 1)) * 64 + l) * 2 + (mt & 1);
+}
+
 template <class T>
 struct alignas(4 * sizeof(T)) Quad {
     T x, y, z, w;
@@ -395,15 +408,9 @@ __device__ __forceinline__ double load_elem<double>(__amdgpu_buffer_rsrc_t rb, u
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, voff, soff, 0));
 }
 
-// Left factors in LDS.  A K-step's operand of one lane is the four target tiles' values (16
-// bytes in FP32, 32 in FP64).  FP32 keeps the order of HBM (one conflict-free 128-bit read per
-// lane and step); FP64 stores the two halves of each lane's 32 bytes in separate planes of 64
-// lanes, so that both 128-bit reads of a step are contiguous across the lanes.
-template <class T>
-__device__ __forceinline__ int lds_unit(int u) {  // LDS position of 16-byte unit u of a factor
-    if constexpr (sizeof(T) == 4) return u;
-    else return (u & ~127) | ((u & 1) << 6) | ((u >> 1) & 63);
-}
+// Left factors in LDS, in the store's order (tile_index): a K-step's operand of one lane is
+// one 128-bit read in FP32 and one from each of the step's two planes in FP64, both
+// conflict-free.
 template <class T>
 __device__ __forceinline__ Quad<T> lds_quad(const float4* ab, int st, int lane) {
     if constexpr (sizeof(T) == 4) {
@@ -591,7 +598,7 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
         const int n16 = own_elems(Te) / EPU;
         const float4* src = reinterpret_cast<const float4*>(tileA + own_off(Te));
         for (int k = tid; k < STAGE16; k += NTHR)
-            abuf16[lds_unit<T>(k)] = k < n16 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            abuf16[k] = k < n16 ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
         const __amdgpu_buffer_rsrc_t rb = b_rsrc(Te, static_cast<uint32_t>(Te.b_rows));
 #pragma unroll
         for (int i = 0; i < NBS; ++i) bc[i] = load_b(rb, kpart + S * i);
@@ -684,16 +691,13 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
 #pragma unroll
             for (int r = 0; r < QA; ++r) {
                 const int k = tid + r * NTHR;
-                if (k < n16n) dst[lds_unit<T>(k)] = pf[r];
+                if (k < n16n) dst[k] = pf[r];
             }
             T* dst1 = reinterpret_cast<T*>(dst);
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
                 const int k = QA * EPU * NTHR + tid + r * NTHR;  // element index
-                if (k < EPU * n16n) {
-                    if constexpr (sizeof(T) == 4) dst1[k] = pr[r];
-                    else dst1[lds_unit<T>(k / EPU) * EPU + k % EPU] = pr[r];
-                }
+                if (k < EPU * n16n) dst1[k] = pr[r];
             }
         }
         Te = Tn;
@@ -846,8 +850,8 @@ k_far_stream(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items
             q.z = __uint_as_float(v[2]);
             q.w = __uint_as_float(v[3]);
         } else {
-            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32, st * 2048, 0);
-            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 32 + 16, st * 2048, 0);
+            const v4u lo = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 2048, 0);
+            const v4u hi = __builtin_amdgcn_raw_buffer_load_b128(ra, lane * 16, st * 2048 + 1024, 0);
             q.x = __builtin_bit_cast(double, make_uint2(lo[0], lo[1]));
             q.y = __builtin_bit_cast(double, make_uint2(lo[2], lo[3]));
             q.z = __builtin_bit_cast(double, make_uint2(hi[0], hi[1]));
@@ -1101,11 +1105,11 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
 #pragma unroll
     for (int q = 0; q < TOT; ++q) {
         const int k = q / PER, st = (q % PER) >> 2, g = q & 3;
-        const size_t idx = static_cast<size_t>(k) * SST * 256 +
-                           (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
+        const size_t base = static_cast<size_t>(k) * SST * 256;
         const T v = q < NR ? F[q] : T(0);
-        A[idx] = v;
-        if (tileA32 != nullptr) tileA32[TD.a_off() + idx] = static_cast<float>(v);
+        A[base + tile_index<T>(st, 16 * g + r16, mt)] = v;
+        if (tileA32 != nullptr)
+            tileA32[TD.a_off() + base + tile_index<float>(st, 16 * g + r16, mt)] = static_cast<float>(v);
     }
 }
 
@@ -1153,12 +1157,13 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
             kk = sh * sk;
         }
         const int st = p >> 2, g = p & 3, mt = t >> 4, r16 = t & 15;
-        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * g + r16) * 4 + mt;
+        const size_t idx = tile_index<T>(st, 16 * g + r16, mt);
         AK[idx] = kk;
         AV[idx] = kv;
         if (BK != nullptr) {
-            BK[idx] = static_cast<float>(kk);
-            BK[static_cast<size_t>(TD.nstep) * 256 + idx] = static_cast<float>(kv);
+            const size_t i32 = tile_index<float>(st, 16 * g + r16, mt);
+            BK[i32] = static_cast<float>(kk);
+            BK[static_cast<size_t>(TD.nstep) * 256 + i32] = static_cast<float>(kv);
         }
     }
 }
@@ -1205,13 +1210,14 @@ __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
         T* AK = tileA + TD.a_off();
         T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
         const int st = p >> 2, gq = p & 3, mt = t >> 4, r16 = t & 15;
-        const size_t idx = (static_cast<size_t>(st) * 64 + 16 * gq + r16) * 4 + mt;
+        const size_t idx = tile_index<T>(st, 16 * gq + r16, mt);
         AK[idx] = static_cast<T>(static_cast<double>(AK[idx]) + add_k);
         AV[idx] = static_cast<T>(static_cast<double>(AV[idx]) + add_v);
         if (tileA32 != nullptr) {  // FP32 copy of FP64 tiles: the folded values, rounded
             float* BK = tileA32 + TD.a_off();
-            BK[idx] = static_cast<float>(AK[idx]);
-            BK[static_cast<size_t>(TD.nstep) * 256 + idx] = static_cast<float>(AV[idx]);
+            const size_t i32 = tile_index<float>(st, 16 * gq + r16, mt);
+            BK[i32] = static_cast<float>(AK[idx]);
+            BK[static_cast<size_t>(TD.nstep) * 256 + i32] = static_cast<float>(AV[idx]);
         }
         return true;
     };
@@ -1295,10 +1301,10 @@ const float* tiles_of<float>(const Geometry& g) { return g.tileA.p; }
 template <>
 const double* tiles_of<double>(const Geometry& g) { return g.tileA64.p; }
 
-// Work items of a launch of pad columns per operator: pieces of chunks for products of up to
-// 16 wavelengths (plan 0), the other plan above.
+// Work items of a launch of pad columns per operator: plan 0 up to 16 wavelengths, 1 up to 32,
+// 2 above.
 inline const Geometry::FarPlan& far_plan_for(const Geometry& g, int pad) {
-    return g.far_plan[pad > 32 ? 1 : 0];
+    return g.far_plan[pad > 64 ? 2 : (pad > 32 ? 1 : 0)];
 }
 
 }  // namespace
@@ -1815,7 +1821,7 @@ TilePlan plan_tiles(const Geometry& g) {
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
     // Work items per launch class.
-    for (int cls = 0; cls < 2; ++cls) P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls]);
+    for (int cls = 0; cls < 3; ++cls) P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls]);
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
     for (int c = 0; c < nc; ++c) {
@@ -1868,7 +1874,7 @@ void build_tiles(Geometry& g, const TilePlan& P) {
     up.add(g.tiles.p, P.tiles.data(), P.tiles.size());
     up.add(g.tile_off.p, P.toff.data(), P.toff.size());
     up.add(g.tile_self.p, P.tself.data(), P.tself.size());
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < 3; ++cls) {
         Geometry::FarPlan& fp = g.far_plan[cls];
         const TilePlan::Items& W = P.far[cls];
         fp.items.alloc(W.items.size());
