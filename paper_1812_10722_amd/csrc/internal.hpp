@@ -425,13 +425,16 @@ struct Geometry {
         size_t bytes() const { return items.bytes() + order.bytes() + red.bytes(); }
     };
     FarPlan far_plan[3];
-    // largest piece, as a fraction of the mean chunk cost, per launch class (0: no pieces):
-    // measured on the 32768-panel sphere (busiest chunk 1.95 x the mean; in a launch of up to
-    // 16 wavelengths every workgroup is resident at once, so that chunk set the launch time);
-    // the times are flat around these values (above 32 wavelengths, cutting only chunks
-    // heavier than the mean saves most of the pieces' additions but slows the FP64 product by
-    // 5 % and leaves the FP32 one unchanged)
-    double far_split[3] = {0.25, 0.35, 0.35};
+    // largest piece, as a fraction of the mean chunk cost, per launch class (0: no pieces), and
+    // the share of each XCD run's cost, at its end, cut into pieces of a quarter of that size.
+    // Measured on the 32768-panel sphere (busiest chunk 1.95 x the mean): a per-workgroup clock
+    // trace showed the launches' slots full until the last items started and a tail of about
+    // one item's length; cutting only the chunks above the mean and the last fifth of each
+    // run's work finer is 4-8 % faster than pieces of 0.25-0.35 x the mean everywhere, with
+    // fewer partial sums to add (times flat within 3 % for splits of 1-2, tails of 0.2-0.3 and
+    // tail pieces of 0.15-0.25 x the mean)
+    double far_split[3] = {1.0, 1.0, 1.0};
+    double far_tail[3] = {0.2, 0.2, 0.2};
     DevBuf<float> tileA;      // FP32 left factors (need32)
     DevBuf<double> tileA64;   // FP64 left factors (need64), same element offsets
     DevBuf<P2MSeg> p2m_seg;
@@ -563,7 +566,7 @@ struct TilePlan {
 };
 TilePlan plan_tiles(const Geometry& g);
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split);
+                           const std::vector<int32_t>& self, double split, double tail);
 // Scratch bytes the far-field pieces of a product of pad columns per operator write.
 size_t far_part_bytes(const Geometry& g, int pad);
 // Elements of one tile store, from the host lists (the size plan_tiles will find).

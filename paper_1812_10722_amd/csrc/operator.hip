@@ -473,8 +473,9 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
     const int opr = OPS == 2 ? wave >> 2 : j & 1;  // 0: K columns, 1: V columns
     const int hj = OPS == 2 ? j : j >> 1;          // column half
     constexpr int G = 4 / S;                // column groups per workgroup and operator
-    const int kpart = (wave & 3) % S;       // this wave's share of the K-steps
-    const int wg = (wave & 3) / S + G * hj; // column group of this wave
+    // wave-uniform values in scalar registers, so that the branches on them are scalar
+    const int kpart = __builtin_amdgcn_readfirstlane((wave & 3) % S);  // share of the K-steps
+    const int wg = __builtin_amdgcn_readfirstlane((wave & 3) / S + G * hj);  // column group
     const int item = item_order[(b >> 3) / per * 8 + (b & 7)];
     if (item < 0) return;
     const FarItem I = items[item];
@@ -634,7 +635,12 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
                 pr[r] = load_elem<T>(ra, tid * ES, (QA * EPU * NTHR + r * NTHR) * ES);
         }
         const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
-        if (mma) {
+        // Every wave, with columns or not, issues the same vector loads in the same order, and
+        // only the matrix-core blocks are conditional (scalar branches): the wait counts the
+        // compiler places before the staging stores then cover the left-factor loads alone, not
+        // the B operands just requested for the next tile (on a path that skipped those loads
+        // the counts would be too small for the path that made them).
+        {
             // with OPS = 2 the V waves read a direct tile's second factor
             const float4* ab = abuf16 + (OPS == 2 && Te.kind == 1 ? opr * Te.nstep * 256 / EPU : 0);
             auto flush = [&]() {
@@ -649,15 +655,18 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
             };
             // one loop for every tile: NB steps of LDS reads, products and B prefetches; FP32:
             // each wave's partial of every DSTEPS K-steps of the tile joins the FP64 running
-            // sums, so no FP32 partial sums more than 4 DSTEPS panels or terms
+            // sums, so no FP32 partial sums more than 4 DSTEPS panels or terms.  Each step's
+            // left operand is read from LDS one step ahead.
             if constexpr (S == 1) {
                 // the tile's own steps on the matrix cores (a uniform branch per step), the next
                 // tile's operands requested for every step
-                const int ns = Te.nstep;
+                const int ns = mma ? Te.nstep : 0;
                 uint32_t so = 0;
+                Quad<T> a = lds_quad<T>(ab, 0, lane);
 #pragma unroll
                 for (int st = 0; st < NB; ++st) {
-                    const Quad<T> a = lds_quad<T>(ab, st, lane);
+                    Quad<T> an = a;
+                    if (st + 1 < NB) an = lds_quad<T>(ab, st + 1, lane);
                     if (st < ns) {
                         acc[0] = Mma<T>::op(a.x, bc[st], acc[0]);
                         acc[1] = Mma<T>::op(a.y, bc[st], acc[1]);
@@ -666,20 +675,25 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
                     }
                     bc[st] = load_b_at(rbn, so);
                     so = next_step(so, bstep);
+                    a = an;
                 }
                 flush();
             } else {
+                const int ns = mma ? NB : 0;
+                Quad<T> a = lds_quad<T>(ab, kpart < NB ? kpart : NB - 1, lane);
 #pragma unroll
                 for (int i = 0; i < NBS; ++i) {
                     const int st = kpart + S * i;
-                    if (st < NB) {
-                        const Quad<T> a = lds_quad<T>(ab, st, lane);
+                    Quad<T> an = a;
+                    if (i + 1 < NBS) an = lds_quad<T>(ab, st + S < NB ? st + S : NB - 1, lane);
+                    if (st < ns) {
                         acc[0] = Mma<T>::op(a.x, bc[i], acc[0]);
                         acc[1] = Mma<T>::op(a.y, bc[i], acc[1]);
                         acc[2] = Mma<T>::op(a.z, bc[i], acc[2]);
                         acc[3] = Mma<T>::op(a.w, bc[i], acc[3]);
                     }
                     bc[i] = load_b(rbn, st);
+                    a = an;
                     // this wave's steps of K-steps [8 m, 8 m + 8) are i in [8 m / S, 8 (m + 1) / S)
                     if ((i + 1) % (DSTEPS / S) == 0 || i + 1 == NBS) flush();
                 }
@@ -1640,79 +1654,133 @@ int64_t estimate_tile_elems(const Geometry& g) {
 }
 
 // Work items of the far-field kernels over one tile list (per chunk: first tile `off`, own-
-// surface tiles `self`): a chunk whose cost (K-steps + 4 per tile) exceeds `split` x the mean
-// is cut at its own-surface boundary and into pieces of about equal cost (split 0: whole
-// chunks); then XCD runs of consecutive chunks' items, cut at equal shares of the cost, with
-// the heaviest items first within each run (workgroup b takes an item of run b % 8).
+// surface tiles `self`; a tile costs its K-steps + 4).  A chunk whose cost exceeds `split` x the
+// mean is cut at its own-surface boundary and into pieces of about equal cost (split 0: whole
+// chunks).  The items, in chunk order, are dealt to 8 XCD runs of consecutive items at equal
+// shares of the cost, the heaviest first within each run (workgroup b takes an item of run
+// b % 8).  A run ends when its last items end, and items that start late leave the other
+// slots of the XCD idle until they finish; so the items making up the last `tail` share of
+// each run's cost are cut again, into pieces of at most a quarter of the first limit, which the
+// ordering puts at the end of the run.  A chunk of several items has consecutive partial-sum
+// slots in tile order (own-surface pieces first), added in that order by k_far_reduce.
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split) {
+                           const std::vector<int32_t>& self, double split, double tail) {
     TilePlan::Items W;
     const int nc = static_cast<int>(self.size());
     auto tcost = [&](int t) { return static_cast<double>(tl[t].nstep) + 4.0; };
-    std::vector<double> ccost(nc, 0.0);
-    double total = 0.0;
-    for (int c = 0; c < nc; ++c) {
-        for (int t = off[c]; t < off[c + 1]; ++t) ccost[c] += tcost(t);
-        total += ccost[c];
-    }
-    const double cap = nc > 0 ? split * total / nc : 0.0;
-    std::vector<double> icost;
-    auto add = [&](int c, int t0, int t1, int slot) {
+    auto rcost = [&](int t0, int t1) {
         double cs = 0.0;
         for (int t = t0; t < t1; ++t) cs += tcost(t);
-        W.items.push_back({c, t0, t1, slot});
-        icost.push_back(cs);
+        return cs;
     };
-    for (int c = 0; c < nc; ++c) {
-        const int a = off[c], m = off[c] + self[c], e = off[c + 1];
-        if (cap <= 0.0 || ccost[c] <= cap) {
-            add(c, a, e, -1);
-            continue;
-        }
-        FarRed R{c, W.n_slots, 0, 0};
-        for (int half = 0; half < 2; ++half) {
-            const int x = half == 0 ? a : m, y = half == 0 ? m : e;
-            if (x < y) {
-                double cs = 0.0;
-                for (int t = x; t < y; ++t) cs += tcost(t);
-                const int n = std::max(1, static_cast<int>(std::ceil(cs / cap)));
-                double acc = 0.0;
-                int start = x, k = 0;
-                for (int t = x; t < y; ++t) {
-                    acc += tcost(t);
-                    if (k < n - 1 && t + 1 < y && acc >= (k + 1) * cs / n) {
-                        add(c, start, t + 1, W.n_slots++);
-                        start = t + 1;
-                        ++k;
-                    }
-                }
-                add(c, start, y, W.n_slots++);
+    double total = 0.0;
+    for (int c = 0; c < nc; ++c) total += rcost(off[c], off[c + 1]);
+    const double cap = nc > 0 ? split * total / nc : 0.0;
+    struct Piece {
+        int32_t c, t0, t1, run;
+        double cost;
+    };
+    // [x, y) of chunk c into about equal pieces of at most `lim` (appended in tile order)
+    auto cut = [&](int c, int x, int y, int run, double lim, std::vector<Piece>& out) {
+        const double cs = rcost(x, y);
+        const int n = lim > 0.0 ? std::max(1, static_cast<int>(std::ceil(cs / lim))) : 1;
+        double acc = 0.0, done = 0.0;
+        int start = x, k = 0;
+        for (int t = x; t < y; ++t) {
+            acc += tcost(t);
+            if (k < n - 1 && t + 1 < y && acc >= (k + 1) * cs / n) {
+                out.push_back({c, start, t + 1, run, acc - done});
+                done = acc;
+                start = t + 1;
+                ++k;
             }
-            if (half == 0) R.nself = W.n_slots - R.slot0;
         }
-        R.slot1 = W.n_slots;
-        W.red.push_back(R);
+        out.push_back({c, start, y, run, acc - done});
+    };
+    // the cut of a chunk's tiles [x, y) at its own-surface boundary and then by `lim`
+    auto cut_chunk = [&](int c, int x, int y, int run, double lim, std::vector<Piece>& out) {
+        const int m = off[c] + self[c];
+        if (lim <= 0.0 || rcost(x, y) <= lim) {
+            out.push_back({c, x, y, run, rcost(x, y)});
+            return;
+        }
+        if (x < m) cut(c, x, std::min(m, y), run, lim, out);
+        if (std::max(x, m) < y) cut(c, std::max(x, m), y, run, lim, out);
+    };
+    std::vector<Piece> pcs;
+    for (int c = 0; c < nc; ++c) cut_chunk(c, off[c], off[c + 1], 0, cap, pcs);
+    // XCD runs of consecutive items at equal shares of the cost
+    {
+        const int ni = static_cast<int>(pcs.size());
+        double acc = 0.0;
+        int x = 0, in_run = 0;
+        for (int i = 0; i < ni; ++i) {
+            while (x < 7 && in_run > 0 &&
+                   (acc + 0.5 * pcs[i].cost > (x + 1) * total / 8.0 || ni - i <= 7 - x)) {
+                ++x;
+                in_run = 0;
+            }
+            pcs[i].run = x;
+            ++in_run;
+            acc += pcs[i].cost;
+        }
     }
-    const int ni = static_cast<int>(W.items.size());
-    std::vector<std::vector<int32_t>> runs(8);
-    double acc = 0.0;
-    int x = 0;
-    for (int i = 0; i < ni; ++i) {
-        while (x < 7 && !runs[x].empty() &&
-               (acc + 0.5 * icost[i] > (x + 1) * total / 8.0 || ni - i <= 7 - x))
-            ++x;
-        runs[x].push_back(i);
-        acc += icost[i];
+    auto by_cost = [&](const std::vector<Piece>& v, int run) {
+        std::vector<int32_t> ix;
+        for (int i = 0; i < static_cast<int>(v.size()); ++i)
+            if (v[i].run == run) ix.push_back(i);
+        std::stable_sort(ix.begin(), ix.end(),
+                         [&](int32_t u, int32_t w) { return v[u].cost > v[w].cost; });
+        return ix;
+    };
+    // the tail of each run cut finer
+    if (tail > 0.0 && cap > 0.0) {
+        std::vector<char> fine(pcs.size(), 0);
+        for (int r = 0; r < 8; ++r) {
+            const std::vector<int32_t> ix = by_cost(pcs, r);
+            double rc = 0.0, acc = 0.0;
+            for (int32_t i : ix) rc += pcs[i].cost;
+            for (int k = static_cast<int>(ix.size()) - 1; k >= 0 && acc < tail * rc; --k) {
+                fine[ix[k]] = 1;
+                acc += pcs[ix[k]].cost;
+            }
+        }
+        std::vector<Piece> ref;
+        for (size_t i = 0; i < pcs.size(); ++i) {
+            if (fine[i])
+                cut_chunk(pcs[i].c, pcs[i].t0, pcs[i].t1, pcs[i].run, 0.25 * cap, ref);
+            else
+                ref.push_back(pcs[i]);
+        }
+        pcs.swap(ref);
+    }
+    // slots: the items of a chunk are consecutive in `pcs`, in tile order
+    for (size_t i = 0; i < pcs.size();) {
+        size_t j = i + 1;
+        while (j < pcs.size() && pcs[j].c == pcs[i].c) ++j;
+        const int c = pcs[i].c, m = off[c] + self[c];
+        if (j - i == 1) {
+            W.items.push_back({c, pcs[i].t0, pcs[i].t1, -1});
+        } else {
+            FarRed R{c, W.n_slots, 0, 0};
+            for (size_t k = i; k < j; ++k) {
+                W.items.push_back({c, pcs[k].t0, pcs[k].t1, W.n_slots++});
+                if (pcs[k].t1 <= m) ++R.nself;
+            }
+            R.slot1 = W.n_slots;
+            W.red.push_back(R);
+        }
+        i = j;
     }
     size_t per = 0;
-    for (auto& run : runs) {
-        std::stable_sort(run.begin(), run.end(),
-                         [&](int32_t u, int32_t v) { return icost[u] > icost[v]; });
-        per = std::max(per, run.size());
+    std::vector<std::vector<int32_t>> runs(8);
+    for (int r = 0; r < 8; ++r) {
+        runs[r] = by_cost(pcs, r);
+        per = std::max(per, runs[r].size());
     }
     W.order.assign(std::max<size_t>(per, 1) * 8, -1);
-    for (int xx = 0; xx < 8; ++xx)
-        for (size_t i = 0; i < runs[xx].size(); ++i) W.order[i * 8 + xx] = runs[xx][i];
+    for (int r = 0; r < 8; ++r)
+        for (size_t i = 0; i < runs[r].size(); ++i) W.order[i * 8 + r] = runs[r][i];
     return W;
 }
 
@@ -1821,7 +1889,8 @@ TilePlan plan_tiles(const Geometry& g) {
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
     // Work items per launch class.
-    for (int cls = 0; cls < 3; ++cls) P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls]);
+    for (int cls = 0; cls < 3; ++cls)
+        P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls], g.far_tail[cls]);
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
     for (int c = 0; c < nc; ++c) {
