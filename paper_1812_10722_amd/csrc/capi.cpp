@@ -6,7 +6,6 @@
 #include <cmath>
 #include <complex>
 #include <future>
-#include <set>
 #include <utility>
 
 #include "driver.hpp"
@@ -331,11 +330,15 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     lspr::build_tree(g);
     lspr::build_lists(g);
     // boxes whose moments are needed, and the row block of each in the moment array
-    std::set<int32_t> uniq(g.m2p_box_h.begin(), g.m2p_box_h.end());
-    g.mom_boxes.assign(uniq.begin(), uniq.end());
+    // (in box order: a flag per box, then the flagged boxes numbered)
     g.mom_slot_h.assign(g.n_boxes, -1);
-    for (size_t k = 0; k < g.mom_boxes.size(); ++k)
-        g.mom_slot_h[g.mom_boxes[k]] = static_cast<int32_t>(k);
+    for (int32_t b : g.m2p_box_h) g.mom_slot_h[b] = 0;
+    g.mom_boxes.clear();
+    for (int32_t b = 0; b < g.n_boxes; ++b)
+        if (g.mom_slot_h[b] == 0) {
+            g.mom_slot_h[b] = static_cast<int32_t>(g.mom_boxes.size());
+            g.mom_boxes.push_back(b);
+        }
     if (g.tile_budget_bytes <= 0.0) {
         size_t free_b = 0, total_b = 0;
         LSPR_HIP(hipMemGetInfo(&free_b, &total_b));

@@ -1818,6 +1818,13 @@ TilePlan plan_tiles(const Geometry& g) {
     tself.assign(nc, 0);
     m2p_tile.assign(g.n_m2p, 0);
     m2p_chunk.assign(g.n_m2p, 0);
+    {
+        int64_t nd = 0;  // direct tiles
+        for (const Range& r : rng) nd += (r.end - r.start + 4 * dmax - 1) / (4 * dmax);
+        tiles.reserve(static_cast<size_t>(g.n_m2p * nsl + nd));
+        p2p_tile.reserve(static_cast<size_t>(nd));
+        p2p_chunk.reserve(static_cast<size_t>(nd));
+    }
     int64_t& aoff = P.aoff;
     for (int c = 0; c < nc; ++c) {
         toff[c] = static_cast<int32_t>(tiles.size());
@@ -1888,14 +1895,22 @@ TilePlan plan_tiles(const Geometry& g) {
     order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
-    // Work items per launch class.
-    for (int cls = 0; cls < 3; ++cls)
-        P.far[cls] = plan_items(tiles, toff, tself, g.far_split[cls], g.far_tail[cls]);
+    // Work items per launch class (planned once for classes of equal parameters).
+    for (int cls = 0; cls < 3; ++cls) {
+        int same = -1;
+        for (int k = 0; k < cls && same < 0; ++k)
+            if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls]) same = k;
+        P.far[cls] = same >= 0 ? P.far[same]
+                               : plan_items(tiles, toff, tself, g.far_split[cls], g.far_tail[cls]);
+    }
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
+    P.dtr.reserve(p2p_tile.size());
+    P.dti.reserve(p2p_tile.size());
+    std::vector<std::pair<int32_t, int32_t>> d;
     for (int c = 0; c < nc; ++c) {
         P.dto[c] = static_cast<int32_t>(P.dti.size());
-        std::vector<std::pair<int32_t, int32_t>> d;
+        d.clear();
         for (int t = toff[c]; t < toff[c + 1]; ++t)
             if (tiles[t].kind == 1) d.emplace_back(tiles[t].b_row0, t);
         std::sort(d.begin(), d.end());
