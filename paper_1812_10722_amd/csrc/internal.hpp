@@ -488,6 +488,7 @@ struct Geometry {
     bool pair_ops = false;  // products of more than 16 wavelengths stage each left factor once
                             // for both operators (eight-wave workgroups)
     bool pair_narrow = false;  // the same for products of up to 16 wavelengths
+    bool four_wave_wide = false;  // FP32 products above 32 wavelengths in four-wave workgroups
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 55 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the
     // matrix-core products then need no separate near-field pass)
@@ -566,7 +567,8 @@ struct TilePlan {
 };
 TilePlan plan_tiles(const Geometry& g);
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split, double tail);
+                           const std::vector<int32_t>& self, double split, double tail,
+                           bool cut_self);
 // Scratch bytes the far-field pieces of a product of pad columns per operator write.
 size_t far_part_bytes(const Geometry& g, int pad);
 // Elements of one tile store, from the host lists (the size plan_tiles will find).

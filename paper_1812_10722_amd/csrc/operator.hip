@@ -14,6 +14,7 @@
 // Sums are raw: no 1/(4 pi) factor.
 #include <algorithm>
 #include <functional>
+#include <type_traits>
 #include <cmath>
 
 #include "expansion.hpp"
@@ -726,6 +727,185 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
     write_sums(o_all);
 }
 
+// Wide FP32 products (more than 64 columns per operator) with the left factors read straight
+// into LDS.  One operator's columns per eight-wave workgroup (eight column groups of 16, both
+// column halves), so the tiles of a work item are read by two workgroups (the two operators)
+// instead of four.  Three LDS buffers: at the start of tile e every wave requests its share of
+// the left factor of tile e + 2 (whole K-steps of 1 KB, by buffer loads that write LDS; zeros
+// past the tile's elements) into the buffer tile e - 1 used; at the end each wave waits for its
+// own requests of tile e + 1, with everything it has requested since still outstanding, and
+// one barrier ends the tile.  Per wave the arithmetic is that of k_far_tiles_op<float, NSM, 1>
+// (the same B operands, K-step order, FP32 partial per tile and FP64 running sums), so both
+// give the same sums.  Two workgroups (16 waves) per CU, each with 3 x 21 KB of LDS at P = 8.
+// Requires work items that do not span a chunk's own-surface boundary (plan_items, cut_self).
+template <int NSM>
+__global__ void __launch_bounds__(512, 2)
+k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
+           const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
+           const TileDesc* __restrict__ tiles, const float* __restrict__ tileA,
+           const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
+           double* __restrict__ out_self, double* __restrict__ out_all,
+           double* __restrict__ part) {
+    constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
+    constexpr int NREQ = (NB + 7) / 8;  // K-steps each wave requests per tile
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    __shared__ float4 lb0[NB * 64];
+    __shared__ float4 lb1[NB * 64];
+    __shared__ float4 lb2[NB * 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wg = __builtin_amdgcn_readfirstlane(tid >> 6);  // column group of this wave
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int ncols = 2 * pad;
+    // two workgroups per work item, at b and b + 8: operator (b >> 3) & 1
+    const int b = blockIdx.x;
+    const int opr = (b >> 3) & 1;
+    const int item = item_order[(b >> 4) * 8 + (b & 7)];
+    if (item < 0) return;
+    const FarItem I = items[item];
+    const int chunk = I.chunk;
+    const Chunk C = chunks[chunk];
+    const int ntg = C.end - C.start;
+    const bool mma = wg < nwc;
+    const int col = opr * pad + 16 * wg + c16;
+    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * 4u;
+    const uint32_t bstep = 16u * static_cast<uint32_t>(ncols);
+    v4f acc[4];
+    double run[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        acc[a] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[a][q] = 0.0;
+    }
+    const bool whole = I.slot < 0;
+    const int t_beg = I.t0, t_end = I.t1;
+    const int t_mid = whole ? t_beg + tile_self[chunk] : t_beg;
+    double* const o_self = whole ? out_self : nullptr;
+    double* const o_all = whole ? out_all + static_cast<size_t>(C.start) * ncols
+                                : part + static_cast<size_t>(I.slot) * NT * ncols;
+    auto write_sums = [&](double* out) {
+        if (!mma) return;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + out_row<float>(grp, q);
+                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = run[mt][q];
+            }
+    };
+    auto b_rsrc = [&](const TileDesc& D, uint32_t rows) {
+        const float* bsrc = D.kind == 0 ? mom : dens;
+        return buffer_rsrc(bsrc + static_cast<size_t>(D.b_row0) * ncols,
+                           rows * static_cast<uint32_t>(ncols) * 4u);
+    };
+    auto to_desc = [](const v4u& w) {
+        const uint32_t w0 = __builtin_amdgcn_readfirstlane(w[0]);
+        TileDesc D;
+        D.kind = static_cast<int16_t>(w0 & 0xffffu);
+        D.nstep = static_cast<int16_t>(w0 >> 16);
+        D.a_blk = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[1]));
+        D.b_row0 = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[2]));
+        D.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
+        return D;
+    };
+    // this wave's requests for the left factor of tile D (its own operator's factor of a
+    // direct tile): K-steps wg, wg + 8, ... (the last step of the tile may be requested by more
+    // than one wave, with the same data), none of the tile's data when `more` is false
+    auto request = [&](const TileDesc& D, bool more, float4* L) {
+        const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
+        const __amdgpu_buffer_rsrc_t ra =
+            buffer_rsrc(tileA + off, more ? static_cast<uint32_t>(D.nstep) * 1024u : 0u);
+#pragma unroll
+        for (int k = 0; k < NREQ; ++k) {
+            const int st = wg + 8 * k < NB ? wg + 8 * k : NB - 1;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(L + st * 64), 16, lane * 16,
+                                                     st * 1024, 0, 0);
+        }
+    };
+    // The work items of these launches never span the own-surface boundary (the plan cuts
+    // every chunk there): a whole chunk's own-surface sums are its sums over all its tiles, or
+    // zero when it has no own-surface tiles.
+    if (o_self != nullptr && t_mid == t_beg) write_sums(o_self + static_cast<size_t>(C.start) * ncols);
+    const __amdgpu_buffer_rsrc_t rt =
+        buffer_rsrc(tiles + t_beg, static_cast<uint32_t>(t_end - t_beg) * 16u);
+    TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
+    TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
+    TileDesc Tnn = tiles[t_beg + 2 < t_end ? t_beg + 2 : 0];
+    float bc[NB];
+    {
+        request(Te, t_beg < t_end, lb0);
+        request(Tn, t_beg + 1 < t_end, lb1);
+        const __amdgpu_buffer_rsrc_t rb =
+            b_rsrc(Te, t_beg < t_end ? static_cast<uint32_t>(Te.b_rows) : 0u);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) bc[i] = load_elem<float>(rb, boff, i * bstep);
+    }
+    __syncthreads();  // waits for every load: the first two left factors are complete
+    // one tile: reads buffer P, requests the left factor of tile e + 2 into buffer P + 2
+    auto tile = [&](int e, auto par) {
+        constexpr int P = decltype(par)::value;
+        float4* const Lc = P == 0 ? lb0 : (P == 1 ? lb1 : lb2);
+        float4* const Lr = P == 0 ? lb2 : (P == 1 ? lb0 : lb1);
+        const v4u dn = __builtin_amdgcn_raw_buffer_load_b128(
+            rt, 0, static_cast<uint32_t>(e + 3 - t_beg) * 16u, 0);
+        const bool more = e + 1 < t_end;
+        request(Tnn, e + 2 < t_end, Lr);
+        const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
+        const int ns = mma ? Te.nstep : 0;
+        uint32_t so = 0;
+        Quad<float> a = lds_quad<float>(Lc, 0, lane);
+#pragma unroll
+        for (int st = 0; st < NB; ++st) {
+            Quad<float> an = a;
+            if (st + 1 < NB) an = lds_quad<float>(Lc, st + 1, lane);
+            if (st < ns) {
+                acc[0] = Mma<float>::op(a.x, bc[st], acc[0]);
+                acc[1] = Mma<float>::op(a.y, bc[st], acc[1]);
+                acc[2] = Mma<float>::op(a.z, bc[st], acc[2]);
+                acc[3] = Mma<float>::op(a.w, bc[st], acc[3]);
+            }
+            bc[st] = load_elem<float>(rbn, boff, so);
+            so = next_step(so, bstep);
+            a = an;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
+            acc[q] = v4f{0, 0, 0, 0};
+        }
+        // this wave's requests of tile e + 1 (made at the start of tile e - 1, or before the
+        // first tile) are complete when no more than the loads issued after them are
+        // outstanding: the NB B operands of tile e - 1, this tile's descriptor, requests and NB
+        // B operands (vmcnt field split over bits 3:0 and 15:14; expcnt and lgkmcnt not waited
+        // for); the barrier then makes every wave's part visible and frees Lc for the next
+        // tile's request
+        constexpr int VM = 2 * NB + 1 + NREQ;
+        static_assert(VM < 64, "vmcnt range");
+        __builtin_amdgcn_s_waitcnt((VM & 15) | (7 << 4) | (15 << 8) | ((VM >> 4) << 14));
+        // (the empty statements keep the compiler from moving memory accesses across the
+        // barrier, which itself orders none)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        Te = Tn;
+        Tn = Tnn;
+        Tnn = to_desc(dn);
+    };
+    // the buffer a tile reads cycles with its position in the item: three copies of the tile in
+    // sequence, so that no branch selects among them
+    for (int e = t_beg; e < t_end;) {
+        tile(e++, std::integral_constant<int, 0>{});
+        if (e >= t_end) break;
+        tile(e++, std::integral_constant<int, 1>{});
+        if (e >= t_end) break;
+        tile(e++, std::integral_constant<int, 2>{});
+    }
+    if (o_self != nullptr && t_mid == t_end && t_mid > t_beg)
+        write_sums(o_self + static_cast<size_t>(C.start) * ncols);
+    write_sums(o_all);
+}
+
 // Sums of the chunks cut into pieces: for each target row and column, the pieces' FP64 partial
 // sums added in piece order (own-surface pieces first; their sum is the own-surface result).
 __global__ void __launch_bounds__(256)
@@ -1379,6 +1559,21 @@ void launch_far_stream(Geometry& g, int pad, const T* dens, const T* mom, double
     launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
 
+template <int NSM>
+void launch_far_wide(Geometry& g, int pad, const float* dens, const float* mom, double* os,
+                     double* oa, hipStream_t s) {
+    const Geometry::FarPlan& fp = far_plan_for(g, pad);
+    double* part = nullptr;
+    if (fp.n_slots > 0)
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad)));
+    const int nblk = fp.n_order * 2;
+    hipLaunchKernelGGL((k_far_wide<NSM>), dim3(nblk), dim3(512), 0, s, g.chunks.p, fp.items.p,
+                       fp.order.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens, mom, pad, pad / 16,
+                       os, oa, part);
+    LSPR_HIP(hipGetLastError());
+    launch_far_reduce(g, fp, pad, part, os, oa, s);
+}
+
 // one column group per operator: four waves share it; two: two waves each; more: one each.
 // Narrow products stage their left factors in LDS, or stream their operands (k_far_stream)
 // when the geometry asks for it.
@@ -1397,6 +1592,14 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
     } else if (g.pair_ops) {
         launch_far_tiles_op_s<T, NSM, 1, 2>(g, pad, abuf, dens, mom, os, oa, s);
     } else {
+        if constexpr (std::is_same<T, float>::value && NSM <= 21) {
+            // FP32 above 64 columns per operator: both column halves in one workgroup (up to
+            // P = 8: at longer slices its registers exceed four waves per SIMD)
+            if (groups > 4 && !g.four_wave_wide) {
+                launch_far_wide<NSM>(g, pad, dens, mom, os, oa, s);
+                return;
+            }
+        }
         launch_far_tiles_op_s<T, NSM, 1>(g, pad, abuf, dens, mom, os, oa, s);
     }
 }
@@ -1661,10 +1864,13 @@ int64_t estimate_tile_elems(const Geometry& g) {
 // b % 8).  A run ends when its last items end, and items that start late leave the other
 // slots of the XCD idle until they finish; so the items making up the last `tail` share of
 // each run's cost are cut again, into pieces of at most a quarter of the first limit, which the
-// ordering puts at the end of the run.  A chunk of several items has consecutive partial-sum
-// slots in tile order (own-surface pieces first), added in that order by k_far_reduce.
+// ordering puts at the end of the run.  With `cut_self` every chunk that has tiles on both
+// sides of its own-surface boundary is cut there too, so no item spans it.  A chunk of several
+// items has consecutive partial-sum slots in tile order (own-surface pieces first), added in
+// that order by k_far_reduce.
 TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split, double tail) {
+                           const std::vector<int32_t>& self, double split, double tail,
+                           bool cut_self) {
     TilePlan::Items W;
     const int nc = static_cast<int>(self.size());
     auto tcost = [&](int t) { return static_cast<double>(tl[t].nstep) + 4.0; };
@@ -1700,7 +1906,7 @@ TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<in
     // the cut of a chunk's tiles [x, y) at its own-surface boundary and then by `lim`
     auto cut_chunk = [&](int c, int x, int y, int run, double lim, std::vector<Piece>& out) {
         const int m = off[c] + self[c];
-        if (lim <= 0.0 || rcost(x, y) <= lim) {
+        if ((lim <= 0.0 || rcost(x, y) <= lim) && !(cut_self && x < m && m < y)) {
             out.push_back({c, x, y, run, rcost(x, y)});
             return;
         }
@@ -1895,13 +2101,17 @@ TilePlan plan_tiles(const Geometry& g) {
     order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
-    // Work items per launch class (planned once for classes of equal parameters).
+    // Work items per launch class (planned once for classes of equal parameters); above 64
+    // columns per operator no item spans a chunk's own-surface boundary (k_far_wide needs it).
     for (int cls = 0; cls < 3; ++cls) {
         int same = -1;
         for (int k = 0; k < cls && same < 0; ++k)
-            if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls]) same = k;
+            if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls] &&
+                (k == 2) == (cls == 2))
+                same = k;
         P.far[cls] = same >= 0 ? P.far[same]
-                               : plan_items(tiles, toff, tself, g.far_split[cls], g.far_tail[cls]);
+                               : plan_items(tiles, toff, tself, g.far_split[cls],
+                                            g.far_tail[cls], cls == 2);
     }
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);

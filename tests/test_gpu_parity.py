@@ -208,6 +208,26 @@ def test_paired_operator_workgroups_equal_split(lib, precision):
         assert np.array_equal(a, b), (nl, np.abs(a - b).max())
 
 
+def test_wide_kernel_equals_four_wave_kernel(lib):
+    """FP32 products of more than 32 wavelengths in eight-wave workgroups that read each left
+    factor straight into two LDS buffers, against the four-wave workgroups of one column half
+    each (LSPR_FOUR_WAVE_WIDE): per wave the same operands, K-step order and sums, so the
+    results are equal bit for bit, for full and partly used column groups."""
+    surfs = sensor_and_blob(10, 7)
+    kw = dict(method="treecode", precision="fp32", p=8, theta=0.5)
+    four = lib.Geometry(surfs, four_wave_wide=True, **kw)
+    eight = lib.Geometry(surfs, **kw)
+    rng = np.random.default_rng(29)
+    n = four.n_panels
+    for nl in (17, 33, 40, 41, 48, 57, 64):
+        eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
+        eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(nl), np.full(nl, 2.5 + 0.1j)], 1)
+        xt = torch.as_tensor(_rand_x(rng, nl, n)).cuda()
+        a = four.apply(xt, eps_m, eps_s).cpu().numpy()
+        b = eight.apply(xt, eps_m, eps_s).cpu().numpy()
+        assert np.array_equal(a, b), (nl, np.abs(a - b).max())
+
+
 # ----------------------------------------------------------------------------- full solves
 def test_sphere_512_dense_fp64_matches_oracle(lib):
     """The 512-panel silver sphere (lambda = 380 nm) solved by the GPU dense FP64 path equals the
