@@ -283,7 +283,8 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
     write_scale = known_kib / only(write, "FillFunctor")
     per, total_b, total_n = {}, 0.0, 0
     for k in sorted(fetch):
-        if "k_far_tiles_op<float" not in k:  # the FP32 instances: the kernel the roofline times
+        # the FP32 instances (wide launches run k_far_wide): the kernel the roofline times
+        if "k_far_tiles_op<float" not in k and "k_far_wide<" not in k:
             continue
         f, wr = fetch[k], write.get(k, [])
         if len(f) != len(wr):
@@ -298,7 +299,7 @@ def record_traffic(fetch_csv, write_csv, kernel_file, name, workload):
         total_n += len(b)
     if not total_n:
         raise SystemExit("no far-field dispatches in the counter files")
-    rec = {"kernel": "k_far_tiles_op", "workload": workload,
+    rec = {"kernel": "k_far_wide + k_far_tiles_op<float>", "workload": workload,
            "source_sha256": hashlib.sha256(open(kernel_file, "rb").read()).hexdigest(),
            "fetch_scale": fetch_scale, "write_scale": write_scale,
            "bytes_per_launch": total_b / total_n, "per_instance": per}
@@ -506,8 +507,8 @@ def main():
     peak = PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS
     trec = traffic_entry(os.path.join(ROOT, "paper_1812_10722_amd", "csrc", "operator.hip"),
                          "far") if mfma else None
-    roofline = {"kernel": "k_far_tiles_op (FP32 matrix-core far field: expansion and direct "
-                          "far-rule tiles)" if mfma else
+    roofline = {"kernel": "k_far_wide (above 32 wavelengths) and k_far_tiles_op (FP32 "
+                          "matrix-core far field: expansion and direct far-rule tiles)" if mfma else
                           "k_far (FP32 vector-ALU far field, no tiles kept)",
                 "bound": "mfma" if mfma else "alu",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
