@@ -60,7 +60,7 @@ enum lspr_flags {
     LSPR_STREAM_NARROW = 4,
     LSPR_PAIR_OPERATORS = 8,
     LSPR_PAIR_NARROW = 16,
-    LSPR_FOUR_WAVE_WIDE = 32
+    LSPR_FOUR_WAVE = 32
 };
 
 /* One closed surface.  vert: [n_vert][3] FP64, tri: [n_tri][3] int32 vertex indices ordered
@@ -118,10 +118,12 @@ typedef struct {
  *             each left factor once for both operators (identical sums; a tuning
  *             alternative).
  *             bit 4: the same for products of up to 16 wavelengths.
- *             bit 5: FP32 products of more than 32 wavelengths run four-wave workgroups, one
- *             column half each, that stage the left factors through registers, instead of
- *             eight-wave workgroups with both halves that read them straight into two LDS
- *             buffers (identical sums; a tuning alternative). */
+ *             bit 5: FP32 products run four-wave workgroups that stage the left factors
+ *             through registers (more than 32 wavelengths: one column half each) instead of
+ *             eight-wave workgroups that read them straight into three LDS buffers (more than
+ *             32 wavelengths: both column halves, identical sums; up to 16 wavelengths at
+ *             P = 8 or 15: 4 or 8 waves per column group instead of 2 or 4, so the FP32
+ *             partial sums are split differently).  A tuning alternative. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;
@@ -390,8 +392,8 @@ int lspr_request_footprint(int64_t n_panels, int32_t n_surf, int32_t n_lambda,
  * Stage 2, on the fastest of those: the kernel schedule, timed the same way: m2p_min_panels at
  * half and twice its default ((P+1)^2; the error is checked again), for n_cols <= 16 the
  * streamed narrow kernel (LSPR_STREAM_NARROW), for n_cols > 16 the paired-operator workgroups
- * (LSPR_PAIR_OPERATORS), for n_cols > 32 in FP32 the four-wave workgroups of one column half
- * (LSPR_FOUR_WAVE_WIDE).  The fastest candidate that meets the bound is written
+ * (LSPR_PAIR_OPERATORS), in FP32 the four-wave workgroups (LSPR_FOUR_WAVE).  The fastest
+ * candidate that meets the bound is written
  * to op->p, op->theta, op->ncrit, op->m2p_min_panels and op->flags (op->method becomes
  * LSPR_TREECODE; the other fields are kept and used for every candidate).
  *   surfaces     device pointers, as lspr_geometry_create

@@ -285,7 +285,7 @@ void validate_op(const lspr_surface* surfaces, int n_surf, const lspr_op_params*
     LSPR_REQUIRE(op->ncrit >= 0 && op->m2p_min_panels >= 0, LSPR_E_INVALID,
              "ncrit and m2p_min_panels must be >= 0");
     LSPR_REQUIRE((op->flags & ~(LSPR_NO_MATRIX_CORES | LSPR_STREAM_NARROW | LSPR_PAIR_OPERATORS |
-                                LSPR_PAIR_NARROW | LSPR_FOUR_WAVE_WIDE)) == 0,
+                                LSPR_PAIR_NARROW | LSPR_FOUR_WAVE)) == 0,
                  LSPR_E_INVALID, "unknown flags");
 }
 
@@ -325,7 +325,7 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
     g.stream_narrow = (op->flags & LSPR_STREAM_NARROW) != 0;
     g.pair_ops = (op->flags & LSPR_PAIR_OPERATORS) != 0;
     g.pair_narrow = (op->flags & LSPR_PAIR_NARROW) != 0;
-    g.four_wave_wide = (op->flags & LSPR_FOUR_WAVE_WIDE) != 0;
+    g.four_wave = (op->flags & LSPR_FOUR_WAVE) != 0;
     lspr::prof::Scope setup_scope("setup", g.stream, 0.0, 0.0);
     lspr::build_geometry(g, surfaces, n_surf);
     lspr::build_tree(g);
@@ -878,7 +878,7 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
         // box (half and twice the default of one panel per Taylor term; it moves work between
         // expansions and direct sums, so the bound is checked again), both operators staged once
         // in eight-wave workgroups, for narrow products operands streamed or staged, and for
-        // wide FP32 products the four-wave workgroups of one column half
+        // FP32 products the four-wave workgroups that stage the left factors through registers
         if (best.ms_per_product >= 0.0) {
             const int terms = (best.p + 1) * (best.p + 1);
             lspr_op_params b = *op;
@@ -903,9 +903,9 @@ int lspr_autotune(const lspr_surface* surfaces, int32_t n_surf, int32_t n_cols,
                 c.flags |= LSPR_STREAM_NARROW;
                 sched.push_back(c);
             }
-            if (n_cols > 32 && b.precision != LSPR_FP64) {
+            if (b.precision != LSPR_FP64) {
                 lspr_op_params c = b;
-                c.flags |= LSPR_FOUR_WAVE_WIDE;
+                c.flags |= LSPR_FOUR_WAVE;
                 sched.push_back(c);
             }
             for (const lspr_op_params& c : sched) {

@@ -727,18 +727,22 @@ k_far_tiles_op(const Chunk* __restrict__ chunks, const FarItem* __restrict__ ite
     write_sums(o_all);
 }
 
-// Wide FP32 products (more than 64 columns per operator) with the left factors read straight
-// into LDS.  One operator's columns per eight-wave workgroup (eight column groups of 16, both
-// column halves), so the tiles of a work item are read by two workgroups (the two operators)
-// instead of four.  Three LDS buffers: at the start of tile e every wave requests its share of
-// the left factor of tile e + 2 (whole K-steps of 1 KB, by buffer loads that write LDS; zeros
-// past the tile's elements) into the buffer tile e - 1 used; at the end each wave waits for its
-// own requests of tile e + 1, with everything it has requested since still outstanding, and
-// one barrier ends the tile.  Per wave the arithmetic is that of k_far_tiles_op<float, NSM, 1>
-// (the same B operands, K-step order, FP32 partial per tile and FP64 running sums), so both
-// give the same sums.  Two workgroups (16 waves) per CU, each with 3 x 21 KB of LDS at P = 8.
+// FP32 products with the left factors read straight into LDS, one operator's columns per
+// eight-wave workgroup: 8 / S column groups of 16, S waves each.  S = 1 (more than 64 columns
+// per operator): eight column groups, both column halves, so the tiles of a work item are read
+// by two workgroups (the two operators) instead of four.  S = 4, 8 (up to 32, 16 columns): S
+// waves share a column group and split its K-steps, wave k taking steps k, k + S, ..., with its
+// FP32 partial of each tile (at most 6 K-steps: 24 panels or terms) added to its FP64 sums, and
+// the S waves' FP64 sums added in wave order through LDS at the end.
+// Three LDS buffers: at the start of tile e every wave requests its share of the left factor of
+// tile e + 2 (whole K-steps of 1 KB, by buffer loads that write LDS; zeros past the tile's
+// elements) into the buffer tile e - 1 used; at the end each wave waits for its own requests of
+// tile e + 1, with everything it has requested since still outstanding, and one barrier ends
+// the tile.  For S = 1 the arithmetic per wave is that of k_far_tiles_op<float, NSM, 1> (the
+// same B operands, K-step order, FP32 partial per tile and FP64 running sums), so both give the
+// same sums.  Two workgroups (16 waves) per CU, each with 3 x 21 KB of LDS at P = 8.
 // Requires work items that do not span a chunk's own-surface boundary (plan_items, cut_self).
-template <int NSM>
+template <int NSM, int S>
 __global__ void __launch_bounds__(512, 2)
 k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
            const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
@@ -746,14 +750,18 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
            const float* __restrict__ dens, const float* __restrict__ mom, int pad, int nwc,
            double* __restrict__ out_self, double* __restrict__ out_all,
            double* __restrict__ part) {
+    static_assert(S == 1 || S == 4 || S == 8, "waves per column group");
     constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
-    constexpr int NREQ = (NB + 7) / 8;  // K-steps each wave requests per tile
+    constexpr int NBS = (NB + S - 1) / S;  // K-steps (B operands) per wave and tile
+    constexpr int G = 8 / S;               // column groups per workgroup
+    constexpr int NREQ = (NB + 7) / 8;     // K-steps each wave requests per tile
     typedef __attribute__((address_space(3))) void* lds_ptr;
     __shared__ float4 lb0[NB * 64];
     __shared__ float4 lb1[NB * 64];
     __shared__ float4 lb2[NB * 64];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wg = __builtin_amdgcn_readfirstlane(tid >> 6);  // column group of this wave
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wg = wave / S, kpart = wave % S;  // column group, share of the K-steps
     const int c16 = lane & 15, grp = lane >> 4;
     const int ncols = 2 * pad;
     // two workgroups per work item, at b and b + 8: operator (b >> 3) & 1
@@ -783,14 +791,43 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
     double* const o_self = whole ? out_self : nullptr;
     double* const o_all = whole ? out_all + static_cast<size_t>(C.start) * ncols
                                 : part + static_cast<size_t>(I.slot) * NT * ncols;
+    // (S > 1: all waves call it; the first wave of each column group adds the others' sums in
+    // wave order, through one 8 KB slot per group in the LDS buffers, after every request into
+    // them has landed)
     auto write_sums = [&](double* out) {
-        if (!mma) return;
+        double sum[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[mt][q] = run[mt][q];
+        if constexpr (S > 1) {
+            constexpr int SPB = NB * 64 * 16 / (16 * 64 * 8);  // 8 KB slots per buffer
+            static_assert(G <= 3 * SPB, "reduction slots");
+            float4* const base = wg < SPB ? lb0 : (wg < 2 * SPB ? lb1 : lb2);
+            double* red = reinterpret_cast<double*>(base) + (wg % SPB) * 16 * 64;
+            __syncthreads();
+            for (int k = 1; k < S; ++k) {
+                if (kpart == k)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) red[(4 * mt + q) * 64 + lane] = run[mt][q];
+                __syncthreads();
+                if (kpart == 0)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) sum[mt][q] += red[(4 * mt + q) * 64 + lane];
+                __syncthreads();
+            }
+        }
+        if (!mma || kpart != 0) return;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = 16 * mt + out_row<float>(grp, q);
-                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = run[mt][q];
+                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = sum[mt][q];
             }
     };
     auto b_rsrc = [&](const TileDesc& D, uint32_t rows) {
@@ -809,15 +846,15 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
         return D;
     };
     // this wave's requests for the left factor of tile D (its own operator's factor of a
-    // direct tile): K-steps wg, wg + 8, ... (the last step of the tile may be requested by more
-    // than one wave, with the same data), none of the tile's data when `more` is false
+    // direct tile): K-steps wave, wave + 8, ... (the last step of the tile may be requested by
+    // more than one wave, with the same data), none of the tile's data when `more` is false
     auto request = [&](const TileDesc& D, bool more, float4* L) {
         const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0);
         const __amdgpu_buffer_rsrc_t ra =
             buffer_rsrc(tileA + off, more ? static_cast<uint32_t>(D.nstep) * 1024u : 0u);
 #pragma unroll
         for (int k = 0; k < NREQ; ++k) {
-            const int st = wg + 8 * k < NB ? wg + 8 * k : NB - 1;
+            const int st = wave + 8 * k < NB ? wave + 8 * k : NB - 1;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(L + st * 64), 16, lane * 16,
                                                      st * 1024, 0, 0);
         }
@@ -831,14 +868,14 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
     TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
     TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
     TileDesc Tnn = tiles[t_beg + 2 < t_end ? t_beg + 2 : 0];
-    float bc[NB];
+    float bc[NBS];
     {
         request(Te, t_beg < t_end, lb0);
         request(Tn, t_beg + 1 < t_end, lb1);
         const __amdgpu_buffer_rsrc_t rb =
             b_rsrc(Te, t_beg < t_end ? static_cast<uint32_t>(Te.b_rows) : 0u);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) bc[i] = load_elem<float>(rb, boff, i * bstep);
+        for (int i = 0; i < NBS; ++i) bc[i] = load_elem<float>(rb, boff, (kpart + S * i) * bstep);
     }
     __syncthreads();  // waits for every load: the first two left factors are complete
     // one tile: reads buffer P, requests the left factor of tile e + 2 into buffer P + 2
@@ -852,35 +889,59 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
         request(Tnn, e + 2 < t_end, Lr);
         const __amdgpu_buffer_rsrc_t rbn = b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u);
         const int ns = mma ? Te.nstep : 0;
-        uint32_t so = 0;
-        Quad<float> a = lds_quad<float>(Lc, 0, lane);
+        auto flush = [&]() {
 #pragma unroll
-        for (int st = 0; st < NB; ++st) {
-            Quad<float> an = a;
-            if (st + 1 < NB) an = lds_quad<float>(Lc, st + 1, lane);
-            if (st < ns) {
-                acc[0] = Mma<float>::op(a.x, bc[st], acc[0]);
-                acc[1] = Mma<float>::op(a.y, bc[st], acc[1]);
-                acc[2] = Mma<float>::op(a.z, bc[st], acc[2]);
-                acc[3] = Mma<float>::op(a.w, bc[st], acc[3]);
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
+                acc[q] = v4f{0, 0, 0, 0};
             }
-            bc[st] = load_elem<float>(rbn, boff, so);
-            so = next_step(so, bstep);
-            a = an;
-        }
+        };
+        if constexpr (S == 1) {
+            uint32_t so = 0;
+            Quad<float> a = lds_quad<float>(Lc, 0, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+            for (int st = 0; st < NB; ++st) {
+                Quad<float> an = a;
+                if (st + 1 < NB) an = lds_quad<float>(Lc, st + 1, lane);
+                if (st < ns) {
+                    acc[0] = Mma<float>::op(a.x, bc[st], acc[0]);
+                    acc[1] = Mma<float>::op(a.y, bc[st], acc[1]);
+                    acc[2] = Mma<float>::op(a.z, bc[st], acc[2]);
+                    acc[3] = Mma<float>::op(a.w, bc[st], acc[3]);
+                }
+                bc[st] = load_elem<float>(rbn, boff, so);
+                so = next_step(so, bstep);
+                a = an;
+            }
+            flush();
+        } else {
+            Quad<float> a = lds_quad<float>(Lc, kpart < NB ? kpart : NB - 1, lane);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) run[q][r] += static_cast<double>(acc[q][r]);
-            acc[q] = v4f{0, 0, 0, 0};
+            for (int i = 0; i < NBS; ++i) {
+                const int st = kpart + S * i;
+                Quad<float> an = a;
+                if (i + 1 < NBS) an = lds_quad<float>(Lc, st + S < NB ? st + S : NB - 1, lane);
+                if (st < ns) {
+                    acc[0] = Mma<float>::op(a.x, bc[i], acc[0]);
+                    acc[1] = Mma<float>::op(a.y, bc[i], acc[1]);
+                    acc[2] = Mma<float>::op(a.z, bc[i], acc[2]);
+                    acc[3] = Mma<float>::op(a.w, bc[i], acc[3]);
+                }
+                bc[i] = load_elem<float>(rbn, boff, st * bstep);
+                a = an;
+                // (at S >= 4 a wave holds at most 6 K-steps of a tile: its FP32 partial of the
+                // tile spans at most 24 panels or terms)
+                if (i + 1 == NBS) flush();
+            }
         }
         // this wave's requests of tile e + 1 (made at the start of tile e - 1, or before the
         // first tile) are complete when no more than the loads issued after them are
-        // outstanding: the NB B operands of tile e - 1, this tile's descriptor, requests and NB
-        // B operands (vmcnt field split over bits 3:0 and 15:14; expcnt and lgkmcnt not waited
-        // for); the barrier then makes every wave's part visible and frees Lc for the next
-        // tile's request
-        constexpr int VM = 2 * NB + 1 + NREQ;
+        // outstanding: the NBS B operands of tile e - 1, this tile's descriptor, requests and
+        // NBS B operands (vmcnt field split over bits 3:0 and 15:14; expcnt and lgkmcnt not
+        // waited for); the barrier then makes every wave's part visible and frees Lc for the
+        // next tile's request
+        constexpr int VM = 2 * NBS + 1 + NREQ;
         static_assert(VM < 64, "vmcnt range");
         __builtin_amdgcn_s_waitcnt((VM & 15) | (7 << 4) | (15 << 8) | ((VM >> 4) << 14));
         // (the empty statements keep the compiler from moving memory accesses across the
@@ -1559,7 +1620,7 @@ void launch_far_stream(Geometry& g, int pad, const T* dens, const T* mom, double
     launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
 
-template <int NSM>
+template <int NSM, int S>
 void launch_far_wide(Geometry& g, int pad, const float* dens, const float* mom, double* os,
                      double* oa, hipStream_t s) {
     const Geometry::FarPlan& fp = far_plan_for(g, pad);
@@ -1567,7 +1628,7 @@ void launch_far_wide(Geometry& g, int pad, const float* dens, const float* mom, 
     if (fp.n_slots > 0)
         part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad)));
     const int nblk = fp.n_order * 2;
-    hipLaunchKernelGGL((k_far_wide<NSM>), dim3(nblk), dim3(512), 0, s, g.chunks.p, fp.items.p,
+    hipLaunchKernelGGL((k_far_wide<NSM, S>), dim3(nblk), dim3(512), 0, s, g.chunks.p, fp.items.p,
                        fp.order.p, g.tile_self.p, g.tiles.p, g.tileA.p, dens, mom, pad, pad / 16,
                        os, oa, part);
     LSPR_HIP(hipGetLastError());
@@ -1581,6 +1642,16 @@ template <class T, int NSM>
 void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T* mom,
                          double* os, double* oa, hipStream_t s) {
     const int groups = pad / 16;
+    // FP32 products of up to 32 columns per operator at P = 8 or 15: eight-wave workgroups that
+    // read the left factors straight into LDS, with 4 or 8 waves per column group (two waves
+    // per group, for three or four groups, need more than four waves' registers per SIMD)
+    if constexpr (std::is_same<T, float>::value && (NSM == 21 || NSM == 16)) {
+        if (!g.four_wave && !g.stream_narrow && !g.pair_narrow && groups <= 2) {
+            if (groups == 1) launch_far_wide<NSM, 8>(g, pad, dens, mom, os, oa, s);
+            else launch_far_wide<NSM, 4>(g, pad, dens, mom, os, oa, s);
+            return;
+        }
+    }
     if (groups == 1) {
         if (g.stream_narrow) launch_far_stream<T, NSM, 4>(g, pad, dens, mom, os, oa, s);
         else if (g.pair_narrow) launch_far_tiles_op_s<T, NSM, 4, 2>(g, pad, abuf, dens, mom, os, oa, s);
@@ -1595,8 +1666,8 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
         if constexpr (std::is_same<T, float>::value && NSM <= 21) {
             // FP32 above 64 columns per operator: both column halves in one workgroup (up to
             // P = 8: at longer slices its registers exceed four waves per SIMD)
-            if (groups > 4 && !g.four_wave_wide) {
-                launch_far_wide<NSM>(g, pad, dens, mom, os, oa, s);
+            if (groups > 4 && !g.four_wave) {
+                launch_far_wide<NSM, 1>(g, pad, dens, mom, os, oa, s);
                 return;
             }
         }
@@ -2101,17 +2172,15 @@ TilePlan plan_tiles(const Geometry& g) {
     order.assign(std::max<size_t>(per_xcd, 1) * 8, -1);
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < runs[x].size(); ++i) order[i * 8 + x] = runs[x][i];
-    // Work items per launch class (planned once for classes of equal parameters); above 64
-    // columns per operator no item spans a chunk's own-surface boundary (k_far_wide needs it).
+    // Work items per launch class (planned once for classes of equal parameters); no item spans
+    // a chunk's own-surface boundary (k_far_wide needs it).
     for (int cls = 0; cls < 3; ++cls) {
         int same = -1;
         for (int k = 0; k < cls && same < 0; ++k)
-            if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls] &&
-                (k == 2) == (cls == 2))
-                same = k;
+            if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls]) same = k;
         P.far[cls] = same >= 0 ? P.far[same]
                                : plan_items(tiles, toff, tself, g.far_split[cls],
-                                            g.far_tail[cls], cls == 2);
+                                            g.far_tail[cls], true);
     }
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);

@@ -158,13 +158,13 @@ LSPR_NO_MATRIX_CORES = 1
 LSPR_STREAM_NARROW = 4
 LSPR_PAIR_OPERATORS = 8
 LSPR_PAIR_NARROW = 16
-LSPR_FOUR_WAVE_WIDE = 32
+LSPR_FOUR_WAVE = 32
 
 
 def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, theta=0.5,
               ncrit=0, precision="fp32", m2p_min_panels=0, matrix_cores=True,
               stream_narrow=False, pair_operators=False, pair_narrow=False,
-              four_wave_wide=False):
+              four_wave=False):
     return lspr_op_params(k_far, k_fine, n_k, threshold,
                           LSPR_TREECODE if method == "treecode" else LSPR_DENSE, p, theta, ncrit,
                           _PRECISION[precision], m2p_min_panels,
@@ -172,7 +172,7 @@ def op_params(k_far=4, k_fine=19, n_k=9, threshold=0.5, method="treecode", p=6, 
                           (LSPR_STREAM_NARROW if stream_narrow else 0) |
                           (LSPR_PAIR_OPERATORS if pair_operators else 0) |
                           (LSPR_PAIR_NARROW if pair_narrow else 0) |
-                          (LSPR_FOUR_WAVE_WIDE if four_wave_wide else 0))
+                          (LSPR_FOUR_WAVE if four_wave else 0))
 
 
 def gmres_params(tol=1e-6, restart=60, max_iter=600, precond=1, inner_tol=0.0):

@@ -162,13 +162,14 @@ def test_matrix_core_kernel_matches_vector_kernel_and_oracle(lib, method, ncol, 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_streamed_narrow_products_equal_staged(lib, precision):
     """Products of 1 to 16 wavelengths stream each wave's operands from memory (no LDS): the
-    same step partition and summation order as the LDS-staged form, so the results are equal
-    bit for bit; both match the oracle's dense product to the treecode's truncation error."""
+    same step partition and summation order as the four-wave form that stages each left factor
+    in LDS through registers, so the results are equal bit for bit; both match the oracle's
+    dense product to the treecode's truncation error."""
     surfs = sensor_and_blob(10, 7)
     v, t, sid, V, K, g = _dense_system(surfs, None, None)
     kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
     streamed = lib.Geometry(surfs, stream_narrow=True, **kw)
-    staged = lib.Geometry(surfs, **kw)
+    staged = lib.Geometry(surfs, four_wave=True, **kw)
     rng = np.random.default_rng(17)
     for nl in (1, 5, 8, 9, 12, 16):
         eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
@@ -190,13 +191,13 @@ def _to_np(t):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_paired_operator_workgroups_equal_split(lib, precision):
     """Products in eight-wave workgroups that stage each left factor once for both operators:
-    each wave's arithmetic is that of the one-operator workgroups, so the results are equal bit
-    for bit (1 to 16 wavelengths: the K-steps split over 4 or 2 waves per column group; 17 to 64:
-    one or two column halves)."""
+    each wave's arithmetic is that of the one-operator four-wave workgroups, so the results are
+    equal bit for bit (1 to 16 wavelengths: the K-steps split over 4 or 2 waves per column
+    group; 17 to 64: one or two column halves)."""
     surfs = sensor_and_blob(10, 7)
     kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
     paired = lib.Geometry(surfs, pair_operators=True, pair_narrow=True, **kw)
-    split = lib.Geometry(surfs, **kw)
+    split = lib.Geometry(surfs, four_wave=True, **kw)
     rng = np.random.default_rng(23)
     n = paired.n_panels
     for nl in (1, 5, 8, 9, 16, 17, 20, 40, 64):
@@ -208,24 +209,31 @@ def test_paired_operator_workgroups_equal_split(lib, precision):
         assert np.array_equal(a, b), (nl, np.abs(a - b).max())
 
 
-def test_wide_kernel_equals_four_wave_kernel(lib):
-    """FP32 products of more than 32 wavelengths in eight-wave workgroups that read each left
-    factor straight into two LDS buffers, against the four-wave workgroups of one column half
-    each (LSPR_FOUR_WAVE_WIDE): per wave the same operands, K-step order and sums, so the
-    results are equal bit for bit, for full and partly used column groups."""
+def test_lds_destination_kernels_against_four_wave_kernels(lib):
+    """FP32 products in eight-wave workgroups that read each left factor straight into three
+    LDS buffers, against the four-wave workgroups that stage it through registers
+    (LSPR_FOUR_WAVE).  Above 32 wavelengths each wave's operands, K-step order and sums are the
+    same (both column halves in one workgroup instead of one each), so the results are equal bit
+    for bit, and at 17-32 both take the four-wave kernel; up to 16 wavelengths the K-steps of a
+    column group are split over twice as many waves, so the FP32 partial sums differ in
+    rounding only: within a few FP32 units of the largest entry."""
     surfs = sensor_and_blob(10, 7)
     kw = dict(method="treecode", precision="fp32", p=8, theta=0.5)
-    four = lib.Geometry(surfs, four_wave_wide=True, **kw)
+    four = lib.Geometry(surfs, four_wave=True, **kw)
     eight = lib.Geometry(surfs, **kw)
     rng = np.random.default_rng(29)
     n = four.n_panels
-    for nl in (17, 33, 40, 41, 48, 57, 64):
+    for nl in (1, 5, 8, 9, 12, 16, 17, 24, 32, 33, 40, 41, 48, 57, 64):
         eps_m = np.full(nl, 1.7733) + 0.01j * rng.standard_normal(nl)
         eps_s = np.stack([-3.0 + 0.3j + rng.standard_normal(nl), np.full(nl, 2.5 + 0.1j)], 1)
         xt = torch.as_tensor(_rand_x(rng, nl, n)).cuda()
         a = four.apply(xt, eps_m, eps_s).cpu().numpy()
         b = eight.apply(xt, eps_m, eps_s).cpu().numpy()
-        assert np.array_equal(a, b), (nl, np.abs(a - b).max())
+        if nl > 16:
+            assert np.array_equal(a, b), (nl, np.abs(a - b).max())
+        else:
+            err = np.abs(a - b).max() / np.abs(a).max()
+            assert err < 2e-6, (nl, err)
 
 
 # ----------------------------------------------------------------------------- full solves
