@@ -118,12 +118,12 @@ typedef struct {
  *             each left factor once for both operators (identical sums; a tuning
  *             alternative).
  *             bit 4: the same for products of up to 16 wavelengths.
- *             bit 5: FP32 products run four-wave workgroups that stage the left factors
- *             through registers (more than 32 wavelengths: one column half each) instead of
- *             eight-wave workgroups that read them straight into three LDS buffers (more than
- *             32 wavelengths: both column halves, identical sums; up to 16 wavelengths at
- *             P = 8 or 15: 4 or 8 waves per column group instead of 2 or 4, so the FP32
- *             partial sums are split differently).  A tuning alternative. */
+ *             bit 5: products run four-wave workgroups that stage the left factors through
+ *             registers (more than 32 wavelengths: one column half each) instead of
+ *             eight-wave workgroups that read them straight into LDS buffers (more than 32
+ *             wavelengths, FP32 and FP64: both column halves, identical sums; FP32 up to 16
+ *             wavelengths at P = 8 or 15: 4 or 8 waves per column group instead of 2 or 4, so
+ *             the FP32 partial sums are split differently).  A tuning alternative. */
 typedef struct {
     int32_t k_far;
     int32_t k_fine;

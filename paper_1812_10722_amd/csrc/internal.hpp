@@ -488,7 +488,7 @@ struct Geometry {
     bool pair_ops = false;  // products of more than 16 wavelengths stage each left factor once
                             // for both operators (eight-wave workgroups)
     bool pair_narrow = false;  // the same for products of up to 16 wavelengths
-    bool four_wave = false;  // FP32 products in four-wave workgroups (register staging)
+    bool four_wave = false;  // products in four-wave workgroups (register staging)
     double tile_budget_bytes = 0.0;  // largest tile store kept (0: 55 % of free device memory)
     // near-singular corrections and V_ii folded into the direct tiles of that precision (the
     // matrix-core products then need no separate near-field pass)

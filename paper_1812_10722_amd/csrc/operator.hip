@@ -967,6 +967,174 @@ k_far_wide(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
     write_sums(o_all);
 }
 
+// Wide FP64 products (more than 64 columns per operator): the same eight-wave workgroups as
+// k_far_wide<NSM, 1> (one operator's eight column groups, two workgroups per work item), on
+// v_mfma_f64_16x16x4f64.  An FP64 left factor takes 2 KB per K-step, too large for three buffers
+// of whole tiles, so every tile runs as two halves of ceil(n / 2) and n - ceil(n / 2) of its n
+// K-steps (at most 11 each), in two LDS buffers of 22 KB: at the start of each half every wave
+// requests its share of the next half (whole K-steps, two 1 KB buffer loads with LDS
+// destination each; zeros past the half's steps) into the other buffer, and at its end waits
+// for those requests, with the NH B operands it has requested since still outstanding, before
+// one barrier.  A half is 11 K-steps of 64-cycle products per wave, longer than a request's
+// latency.  Per wave the products are those of k_far_tiles_op<double, NSM, 1> in the same order
+// (the accumulators are the FP64 sums), so both give the same sums.  Requires work items that
+// do not span a chunk's own-surface boundary (plan_items, cut_self).
+template <int NSM>
+__global__ void __launch_bounds__(512, 2)
+k_far_wide64(const Chunk* __restrict__ chunks, const FarItem* __restrict__ items,
+             const int32_t* __restrict__ item_order, const int32_t* __restrict__ tile_self,
+             const TileDesc* __restrict__ tiles, const double* __restrict__ tileA,
+             const double* __restrict__ dens, const double* __restrict__ mom, int pad, int nwc,
+             double* __restrict__ out_self, double* __restrict__ out_all,
+             double* __restrict__ part) {
+    constexpr int NB = NSM > DSTEPS ? NSM : DSTEPS;
+    constexpr int NH = (NB + 1) / 2;    // most K-steps of a half tile
+    constexpr int NREQ = (NH + 7) / 8;  // K-steps each wave requests per half
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    __shared__ float4 lb0[NH * 128];
+    __shared__ float4 lb1[NH * 128];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wg = __builtin_amdgcn_readfirstlane(tid >> 6);  // column group of this wave
+    const int c16 = lane & 15, grp = lane >> 4;
+    const int ncols = 2 * pad;
+    // two workgroups per work item, at b and b + 8: operator (b >> 3) & 1
+    const int b = blockIdx.x;
+    const int opr = (b >> 3) & 1;
+    const int item = item_order[(b >> 4) * 8 + (b & 7)];
+    if (item < 0) return;
+    const FarItem I = items[item];
+    const int chunk = I.chunk;
+    const Chunk C = chunks[chunk];
+    const int ntg = C.end - C.start;
+    const bool mma = wg < nwc;
+    const int col = opr * pad + 16 * wg + c16;
+    const uint32_t boff = static_cast<uint32_t>(grp * ncols + (mma ? col : 0)) * 8u;
+    const uint32_t bstep = 32u * static_cast<uint32_t>(ncols);
+    v4d acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a] = v4d{0, 0, 0, 0};
+    const bool whole = I.slot < 0;
+    const int t_beg = I.t0, t_end = I.t1;
+    const int t_mid = whole ? t_beg + tile_self[chunk] : t_beg;
+    double* const o_self = whole ? out_self : nullptr;
+    double* const o_all = whole ? out_all + static_cast<size_t>(C.start) * ncols
+                                : part + static_cast<size_t>(I.slot) * NT * ncols;
+    auto write_sums = [&](double* out) {
+        if (!mma) return;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * mt + out_row<double>(grp, q);
+                if (t < ntg) out[static_cast<size_t>(t) * ncols + col] = acc[mt][q];
+            }
+    };
+    auto b_rsrc = [&](const TileDesc& D, uint32_t rows) {
+        const double* bsrc = D.kind == 0 ? mom : dens;
+        return buffer_rsrc(bsrc + static_cast<size_t>(D.b_row0) * ncols,
+                           rows * static_cast<uint32_t>(ncols) * 8u);
+    };
+    auto to_desc = [](const v4u& w) {
+        const uint32_t w0 = __builtin_amdgcn_readfirstlane(w[0]);
+        TileDesc D;
+        D.kind = static_cast<int16_t>(w0 & 0xffffu);
+        D.nstep = static_cast<int16_t>(w0 >> 16);
+        D.a_blk = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[1]));
+        D.b_row0 = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[2]));
+        D.b_rows = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(w[3]));
+        return D;
+    };
+    // this wave's requests for K-steps [s0, s0 + n) of tile D's left factor (its own operator's
+    // factor of a direct tile) into L: local steps wave, wave + 8, ... (the last slot may be
+    // requested by more than one wave, with the same data), zeros past n
+    auto request = [&](const TileDesc& D, int s0, int n, float4* L) {
+        const int64_t off = D.a_off() + (D.kind == 1 ? static_cast<int64_t>(opr) * D.nstep * 256 : 0) +
+                            static_cast<int64_t>(s0) * 256;
+        const __amdgpu_buffer_rsrc_t ra =
+            buffer_rsrc(tileA + off, n > 0 ? static_cast<uint32_t>(n) * 2048u : 0u);
+#pragma unroll
+        for (int k = 0; k < NREQ; ++k) {
+            const int st = wg + 8 * k < NH ? wg + 8 * k : NH - 1;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(L + st * 128), 16, lane * 16,
+                                                     st * 2048, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(L + st * 128 + 64), 16,
+                                                     lane * 16, st * 2048 + 1024, 0, 0);
+        }
+    };
+    // The work items of these launches never span the own-surface boundary (the plan cuts
+    // every chunk there): a whole chunk's own-surface sums are its sums over all its tiles, or
+    // zero when it has no own-surface tiles.
+    if (o_self != nullptr && t_mid == t_beg) write_sums(o_self + static_cast<size_t>(C.start) * ncols);
+    const __amdgpu_buffer_rsrc_t rt =
+        buffer_rsrc(tiles + t_beg, static_cast<uint32_t>(t_end - t_beg) * 16u);
+    TileDesc Te = tiles[t_beg < t_end ? t_beg : 0];
+    TileDesc Tn = tiles[t_beg + 1 < t_end ? t_beg + 1 : 0];
+    double bc[NH];
+    {
+        const int h = t_beg < t_end ? (Te.nstep + 1) / 2 : 0;
+        request(Te, 0, h, lb0);
+        const __amdgpu_buffer_rsrc_t rb =
+            b_rsrc(Te, t_beg < t_end ? static_cast<uint32_t>(Te.b_rows) : 0u);
+#pragma unroll
+        for (int i = 0; i < NH; ++i) bc[i] = load_elem<double>(rb, boff, i * bstep);
+    }
+    __syncthreads();  // waits for every load: the first half tile is complete
+    // the products of one half: n K-steps from Lc with the operands in bc, each operand register
+    // then refilled with the next half's operand (step st of rbn at offset b0 + st * bstep)
+    auto products = [&](const float4* Lc, int n, __amdgpu_buffer_rsrc_t rbn, uint32_t b0) {
+        const int ns = mma ? n : 0;
+        Quad<double> a = lds_quad<double>(Lc, 0, lane);
+        uint32_t so = b0;
+#pragma unroll
+        for (int st = 0; st < NH; ++st) {
+            Quad<double> an = a;
+            if (st + 1 < NH) an = lds_quad<double>(Lc, st + 1, lane);
+            if (st < ns) {
+                acc[0] = Mma<double>::op(a.x, bc[st], acc[0]);
+                acc[1] = Mma<double>::op(a.y, bc[st], acc[1]);
+                acc[2] = Mma<double>::op(a.z, bc[st], acc[2]);
+                acc[3] = Mma<double>::op(a.w, bc[st], acc[3]);
+            }
+            bc[st] = load_elem<double>(rbn, boff, so);
+            so = next_step(so, bstep);
+            a = an;
+        }
+    };
+    // this wave's requests of the next half were made before the NH B-operand loads that
+    // followed them (vmcnt field split over bits 3:0 and 15:14; expcnt and lgkmcnt not waited
+    // for); the barrier then makes every wave's part visible and frees the buffer just read
+    auto end_half = [&]() {
+        constexpr int VM = NH;
+        static_assert(VM < 64, "vmcnt range");
+        __builtin_amdgcn_s_waitcnt((VM & 15) | (7 << 4) | (15 << 8) | ((VM >> 4) << 14));
+        // (the empty statements keep the compiler from moving memory accesses across the
+        // barrier, which itself orders none)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    for (int e = t_beg; e < t_end; ++e) {
+        const v4u dn = __builtin_amdgcn_raw_buffer_load_b128(
+            rt, 0, static_cast<uint32_t>(e + 2 - t_beg) * 16u, 0);
+        const int n = Te.nstep, h = (n + 1) / 2;
+        // first half: reads lb0, requests the second half of this tile into lb1
+        request(Te, h, n - h, lb1);
+        products(lb0, h, b_rsrc(Te, static_cast<uint32_t>(Te.b_rows)), static_cast<uint32_t>(h) * bstep);
+        end_half();
+        // second half: reads lb1, requests the first half of the next tile into lb0
+        const bool more = e + 1 < t_end;
+        const int hn = more ? (Tn.nstep + 1) / 2 : 0;
+        request(Tn, 0, hn, lb0);
+        products(lb1, n - h, b_rsrc(Tn, more ? static_cast<uint32_t>(Tn.b_rows) : 0u), 0u);
+        end_half();
+        Te = Tn;
+        Tn = to_desc(dn);
+    }
+    if (o_self != nullptr && t_mid == t_end && t_mid > t_beg)
+        write_sums(o_self + static_cast<size_t>(C.start) * ncols);
+    write_sums(o_all);
+}
+
 // Sums of the chunks cut into pieces: for each target row and column, the pieces' FP64 partial
 // sums added in piece order (own-surface pieces first; their sum is the own-surface result).
 __global__ void __launch_bounds__(256)
@@ -1635,6 +1803,21 @@ void launch_far_wide(Geometry& g, int pad, const float* dens, const float* mom, 
     launch_far_reduce(g, fp, pad, part, os, oa, s);
 }
 
+template <int NSM>
+void launch_far_wide64(Geometry& g, int pad, const double* dens, const double* mom, double* os,
+                       double* oa, hipStream_t s) {
+    const Geometry::FarPlan& fp = far_plan_for(g, pad);
+    double* part = nullptr;
+    if (fp.n_slots > 0)
+        part = reinterpret_cast<double*>(workspace(g, g.ws_fpart, far_part_bytes(g, pad)));
+    const int nblk = fp.n_order * 2;
+    hipLaunchKernelGGL((k_far_wide64<NSM>), dim3(nblk), dim3(512), 0, s, g.chunks.p, fp.items.p,
+                       fp.order.p, g.tile_self.p, g.tiles.p, g.tileA64.p, dens, mom, pad,
+                       pad / 16, os, oa, part);
+    LSPR_HIP(hipGetLastError());
+    launch_far_reduce(g, fp, pad, part, os, oa, s);
+}
+
 // one column group per operator: four waves share it; two: two waves each; more: one each.
 // Narrow products stage their left factors in LDS, or stream their operands (k_far_stream)
 // when the geometry asks for it.
@@ -1668,6 +1851,13 @@ void launch_far_tiles_op(Geometry& g, int pad, int abuf, const T* dens, const T*
             // P = 8: at longer slices its registers exceed four waves per SIMD)
             if (groups > 4 && !g.four_wave) {
                 launch_far_wide<NSM, 1>(g, pad, dens, mom, os, oa, s);
+                return;
+            }
+        }
+        if constexpr (std::is_same<T, double>::value && NSM <= 21) {
+            // FP64 above 64 columns per operator: the same, in half tiles
+            if (groups > 4 && !g.four_wave) {
+                launch_far_wide64<NSM>(g, pad, dens, mom, os, oa, s);
                 return;
             }
         }

@@ -209,16 +209,18 @@ def test_paired_operator_workgroups_equal_split(lib, precision):
         assert np.array_equal(a, b), (nl, np.abs(a - b).max())
 
 
-def test_lds_destination_kernels_against_four_wave_kernels(lib):
-    """FP32 products in eight-wave workgroups that read each left factor straight into three
-    LDS buffers, against the four-wave workgroups that stage it through registers
-    (LSPR_FOUR_WAVE).  Above 32 wavelengths each wave's operands, K-step order and sums are the
-    same (both column halves in one workgroup instead of one each), so the results are equal bit
-    for bit, and at 17-32 both take the four-wave kernel; up to 16 wavelengths the K-steps of a
-    column group are split over twice as many waves, so the FP32 partial sums differ in
-    rounding only: within a few FP32 units of the largest entry."""
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_lds_destination_kernels_against_four_wave_kernels(lib, precision):
+    """Products in eight-wave workgroups that read each left factor straight into LDS buffers,
+    against the four-wave workgroups that stage it through registers (LSPR_FOUR_WAVE).  Above
+    32 wavelengths each wave's operands, K-step order and sums are the same (both column halves
+    in one workgroup instead of one each; FP64 in half tiles), so the results are equal bit for
+    bit, and at 17-32 both take the four-wave kernel; FP32 products of up to 16 wavelengths split
+    the K-steps of a column group over twice as many waves, so their FP32 partial sums differ in
+    rounding only: within a few FP32 units of the largest entry (FP64 ones take the four-wave
+    kernel)."""
     surfs = sensor_and_blob(10, 7)
-    kw = dict(method="treecode", precision="fp32", p=8, theta=0.5)
+    kw = dict(method="treecode", precision=precision, p=8, theta=0.5)
     four = lib.Geometry(surfs, four_wave=True, **kw)
     eight = lib.Geometry(surfs, **kw)
     rng = np.random.default_rng(29)
@@ -229,7 +231,7 @@ def test_lds_destination_kernels_against_four_wave_kernels(lib):
         xt = torch.as_tensor(_rand_x(rng, nl, n)).cuda()
         a = four.apply(xt, eps_m, eps_s).cpu().numpy()
         b = eight.apply(xt, eps_m, eps_s).cpu().numpy()
-        if nl > 16:
+        if nl > 16 or precision == "fp64":
             assert np.array_equal(a, b), (nl, np.abs(a - b).max())
         else:
             err = np.abs(a - b).max() / np.abs(a).max()
