@@ -32,7 +32,16 @@ template <class T> constexpr int tile_panels() { return sizeof(T) == 8 ? 16 : 32
 
 template <class T> __device__ __forceinline__ T rsqrt_t(T x);
 template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return rsqrtf(x); }
-template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+// FP64: the hardware estimate (about 23 correct bits) refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2, each of which about doubles the correct bits (to within 1-2 ulp),
+// instead of a square root followed by a division
+template <> __device__ __forceinline__ double rsqrt_t<double>(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
 // Knuth's TwoSum: hi + lo += part exactly up to the final rounding.
 template <class T>
@@ -1536,8 +1545,6 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
     }
 }
 
-__device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
-__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
 
 // Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
 // up to 4 direct_steps() consecutive source panels (zero for the target's own panel and past the
@@ -1572,7 +1579,7 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
                 const T ey_ = dy - r[5 + 4 * gq];
                 const T ez_ = dz - r[6 + 4 * gq];
                 const T w = r[7 + 4 * gq];
-                const T ri = inv_sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                const T ri = rsqrt_t<T>(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
                 sv += w * ri;
                 sk += w * ri * ri * ri;
             }
