@@ -23,29 +23,6 @@ constexpr int TPB = 256;
 constexpr int MAX_LEVEL = 16;   // 16 Morton bits per axis
 constexpr int STACK = 160;
 
-// For each box to split (start, end, level) the lower bounds of its 8 octants; out[9*b + 8] =
-// end.  The octant bits follow the box's common prefix, so they are sorted inside the box.
-__global__ void k_split(const uint64_t* __restrict__ keys, const int32_t* __restrict__ se,
-                        const int32_t* __restrict__ level, int nb, int32_t* __restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * 9) return;
-    const int b = t / 9, o = t % 9;
-    const int start = se[2 * b], end = se[2 * b + 1];
-    if (o == 8) {
-        out[t] = end;
-        return;
-    }
-    const int shift = 45 - 3 * level[b];
-    int lo = start, hi = end;  // first index with octant >= o
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int oct = static_cast<int>((keys[mid] >> shift) & 7);
-        if (oct < o) lo = mid + 1;
-        else hi = mid;
-    }
-    out[t] = lo;
-}
-
 __device__ inline void node_pos(const double* v, const double* rule, int g, double* y) {
     const double b0 = rule[4 * g], b1 = rule[4 * g + 1], b2 = rule[4 * g + 2];
     for (int d = 0; d < 3; ++d) y[d] = b0 * v[d] + b1 * v[3 + d] + b2 * v[6 + d];
@@ -477,7 +454,30 @@ void build_tree(Geometry& g) {
     std::vector<Box> bx;
     g.surf_root.assign(g.S, 0);
     g.max_depth = 0;
-    DevBuf<int32_t> in_d, out_d;
+    // The sorted keys are read back once and the octant bounds of the boxes found on the host:
+    // a few binary searches per box, instead of a device pass and a round trip per level.
+    std::vector<uint64_t> keys(g.N);
+    {
+        Downloads dl(s);
+        dl.add(keys.data(), g.morton.p, keys.size());
+        dl.fetch();
+    }
+    // lower bounds of box b's 8 octants, then its end: the octant bits follow the box's common
+    // prefix, so they are sorted inside the box
+    auto split_box = [&](const Box& b, int32_t* out) {
+        const int shift = 45 - 3 * b.level;
+        for (int o = 0; o < 8; ++o) {
+            int lo = b.start, hi = b.end;  // first index with octant >= o
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int oct = static_cast<int>((keys[mid] >> shift) & 7);
+                if (oct < o) lo = mid + 1;
+                else hi = mid;
+            }
+            out[o] = lo;
+        }
+        out[8] = b.end;
+    };
     for (int sf = 0; sf < g.S; ++sf) {
         Box root{};
         root.start = g.surf_start[sf];
@@ -495,21 +495,8 @@ void build_tree(Geometry& g) {
                 if (bx[b].end - bx[b].start > g.ncrit) split.push_back(b);
             if (split.empty()) break;
             const int nb = static_cast<int>(split.size());
-            // one upload: (start, end) pairs, then levels
-            std::vector<int32_t> in(3 * nb), out(9 * nb);
-            for (int k = 0; k < nb; ++k) {
-                in[2 * k] = bx[split[k]].start;
-                in[2 * k + 1] = bx[split[k]].end;
-                in[2 * nb + k] = bx[split[k]].level;
-            }
-            in_d.reserve(in.size());
-            out_d.reserve(out.size());
-            LSPR_HIP(hipMemcpyAsync(in_d.p, in.data(), in.size() * 4, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_split, dim3((9 * nb + TPB - 1) / TPB), dim3(TPB), 0, s,
-                               g.morton.p, in_d.p, in_d.p + 2 * nb, nb, out_d.p);
-            LSPR_HIP(hipGetLastError());
-            LSPR_HIP(hipMemcpyAsync(out.data(), out_d.p, out.size() * 4, hipMemcpyDeviceToHost, s));
-            LSPR_HIP(hipStreamSynchronize(s));
+            std::vector<int32_t> out(9 * nb);
+            for (int k = 0; k < nb; ++k) split_box(bx[split[k]], out.data() + 9 * k);
             std::vector<int> next;
             for (int k = 0; k < nb; ++k) {
                 const int b = split[k];
