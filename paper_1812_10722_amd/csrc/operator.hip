@@ -1367,8 +1367,10 @@ k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs
     using E = Expansion<P>;
     constexpr E ex{};
     constexpr int NF = E::NF, NR = E::NR, RT = p2m_row_tiles<P>();
-    constexpr int PB = P <= 10 ? 8 : 4, TPP = 128 / PB;  // LDS under 64 KB up to P = 15
+    constexpr int PB = P <= 10 ? 8 : 4, TPP = 128 / PB;  // LDS at most 65 KB up to P = 15
     __shared__ double poly[PB][2][NF];  // V then K polynomial of each panel of the batch
+    // powers d^0..d^P of each node's offset from the box centre, per axis (at most 8 nodes)
+    __shared__ double pw[PB][8][3][P + 1];
     const P2MSeg sg = segs[blockIdx.x];
     const Box B = boxes[sg.box];
     const int lp = threadIdx.x / TPP, lt = threadIdx.x % TPP;
@@ -1380,27 +1382,38 @@ k_build_p2m_tiles(const Box* __restrict__ boxes, const P2MSeg* __restrict__ segs
     for (int base = sg.start; base < sg.end; base += PB) {
         const int j = base + lp;
         const bool live = j < sg.end;
+        const S* r = src + static_cast<size_t>(live ? j : sg.start) * rs;
         if (live) {
-            const S* r = src + static_cast<size_t>(j) * rs;
-            const double cx = cen[3 * j] - B.cx, cy = cen[3 * j + 1] - B.cy,
-                         cz = cen[3 * j + 2] - B.cz;
+            // powers of each node's offset by successive products from 1, once per node and axis
+            const double cc[3] = {cen[3 * j] - B.cx, cen[3 * j + 1] - B.cy, cen[3 * j + 2] - B.cz};
+            for (int u = lt; u < 3 * K; u += TPP) {
+                const int gq = u / 3, ax = u % 3;
+                const double d = cc[ax] + r[4 + 4 * gq + ax];
+                double* pp = pw[lp][gq][ax];
+                double X = 1.0;
+                pp[0] = X;
+                for (int q = 1; q <= P; ++q) {
+                    X *= d;
+                    pp[q] = X;
+                }
+            }
+        }
+        __syncthreads();
+        if (live) {
             for (int t = lt; t < NF; t += TPP) {
                 const int kx = ex.fx[t], ky = ex.fy[t], kz = ex.fz[t];
                 double v = 0.0, k = 0.0;
                 for (int gq = 0; gq < K; ++gq) {
-                    const double d0 = cx + r[4 + 4 * gq], d1 = cy + r[5 + 4 * gq],
-                                 d2 = cz + r[6 + 4 * gq];
+                    const double* px = pw[lp][gq][0];
+                    const double* py = pw[lp][gq][1];
+                    const double* pz = pw[lp][gq][2];
                     const double w = r[7 + 4 * gq];
-                    // powers d^k and d^(k - 1), by successive products from 1
-                    double X = 1.0, Y = 1.0, Z = 1.0, Xm = 1.0, Ym = 1.0, Zm = 1.0;
-                    for (int q = 0; q < kx; ++q) { Xm = X; X *= d0; }
-                    for (int q = 0; q < ky; ++q) { Ym = Y; Y *= d1; }
-                    for (int q = 0; q < kz; ++q) { Zm = Z; Z *= d2; }
+                    const double X = px[kx], Y = py[ky], Z = pz[kz];
                     v += w * X * Y * Z;
                     double gs = 0.0;
-                    if (kx > 0) gs += r[0] * kx * Xm * Y * Z;
-                    if (ky > 0) gs += r[1] * ky * X * Ym * Z;
-                    if (kz > 0) gs += r[2] * kz * X * Y * Zm;
+                    if (kx > 0) gs += r[0] * kx * px[kx - 1] * Y * Z;
+                    if (ky > 0) gs += r[1] * ky * X * py[ky - 1] * Z;
+                    if (kz > 0) gs += r[2] * kz * X * Y * pz[kz - 1];
                     k += w * gs;
                 }
                 pv[t] = v;
