@@ -9,32 +9,55 @@ namespace {
 constexpr int SCAN_THREADS = 1024;
 
 // Single-workgroup exclusive scan of n int64 counts (setup-time sizes, up to a few million).
-// out[i] = sum_{k < i} in[k]; out[n] = total.  in and out may alias.
+// out[i] = sum_{k < i} in[k]; out[n] = total.  in and out may alias: each thread reads its
+// SCAN_ITEMS consecutive elements of a chunk into registers and writes only those.  Per chunk,
+// the thread sums are scanned in LDS, one wave's 64 by one thread, then the 16 wave sums by
+// thread 0, which carries the running total from chunk to chunk (four barriers per chunk).
+constexpr int SCAN_ITEMS = 8;
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_excl(const int64_t* in, int64_t* out,
                                                              int64_t n) {
-    __shared__ int64_t part[SCAN_THREADS];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n; base += SCAN_THREADS) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < n ? in[i] : 0;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < SCAN_THREADS; off <<= 1) {  // Hillis-Steele inclusive scan
-            const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
+    constexpr int NW = SCAN_THREADS / 64, CH = SCAN_THREADS * SCAN_ITEMS;
+    __shared__ int64_t tsum[SCAN_THREADS];
+    __shared__ int64_t wsum[NW];
+    int64_t carry = 0;  // thread 0 only
+    const int tid = threadIdx.x;
+    for (int64_t base = 0; base < n; base += CH) {
+        const int64_t first = base + static_cast<int64_t>(tid) * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS], sum = 0;
+#pragma unroll
+        for (int e = 0; e < SCAN_ITEMS; ++e) {
+            v[e] = first + e < n ? in[first + e] : 0;
+            sum += v[e];
         }
-        const int64_t incl = part[threadIdx.x];
-        const int64_t c = carry;
-        if (i < n) out[i] = c + incl - v;
+        tsum[tid] = sum;
         __syncthreads();
-        if (threadIdx.x == SCAN_THREADS - 1) carry = c + incl;
+        if (tid < NW) {
+            int64_t a = 0;
+            for (int l = 0; l < 64; ++l) {
+                const int64_t t = tsum[64 * tid + l];
+                tsum[64 * tid + l] = a;
+                a += t;
+            }
+            wsum[tid] = a;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 0; w < NW; ++w) {
+                const int64_t t = wsum[w];
+                wsum[w] = carry;
+                carry += t;
+            }
+        }
+        __syncthreads();
+        int64_t pre = wsum[tid >> 6] + tsum[tid];
+#pragma unroll
+        for (int e = 0; e < SCAN_ITEMS; ++e) {
+            if (first + e < n) out[first + e] = pre;
+            pre += v[e];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (tid == 0) out[n] = carry;
 }
 
 constexpr int RS_THREADS = 256;               // 4 wavefronts

@@ -314,13 +314,16 @@ struct NearParams {
     int S;
     const int32_t* roots;
     int32_t* overflow;  // set when a walk would outgrow its stack (checked by the host)
+    int32_t* maxcnt;    // largest count of a target (counting walk)
 };
 
 // Near-singular source panels of every target panel, all surfaces, ascending index order.
+// Counting walk (fill false): cnt[i], and (slot not null) the first `cap` panels of target i in
+// slot[i cap ..]; filling walk: col[off[i] ..].
 __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__ cen,
                        const double* __restrict__ area, int N, NearParams np, bool fill,
                        int64_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                       int32_t* __restrict__ col) {
+                       int32_t* __restrict__ col, int32_t* __restrict__ slot, int cap) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = cen[3 * i], y = cen[3 * i + 1], z = cen[3 * i + 2];
@@ -343,6 +346,7 @@ __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__
                     const double dj = sqrt(ex * ex + ey * ey + ez * ez);
                     if (dj <= sqrt(2.0 * area[j]) * np.inv_thr) {
                         if (fill) col[k + n] = j;
+                        else if (slot != nullptr && n < cap) slot[static_cast<size_t>(i) * cap + n] = j;
                         ++n;
                     }
                 }
@@ -356,7 +360,19 @@ __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__
             }
         }
     }
-    if (!fill) cnt[i] = n;
+    if (!fill) {
+        cnt[i] = n;
+        atomicMax(np.maxcnt, n);
+    }
+}
+
+// The counting walk's slots moved into the table: one wave per target, lane e copies entry e.
+__global__ void __launch_bounds__(64) k_near_compact(const int32_t* __restrict__ slot, int cap,
+                                                     const int64_t* __restrict__ off,
+                                                     int32_t* __restrict__ col) {
+    const int i = blockIdx.x, e = threadIdx.x;
+    const int64_t o = off[i], n = off[i + 1] - o;
+    for (int q = e; q < n; q += 64) col[o + q] = slot[static_cast<size_t>(i) * cap + q];
 }
 
 // Rule sums of one panel at point x (no 1/4pi): V = sum w/r, K = sum w n.(x - y)/r^3.
@@ -643,34 +659,44 @@ void build_near_table(Geometry& g) {
     gauss_legendre(g.Nk, t, w);
     std::vector<int32_t> roots_h(g.surf_root.begin(), g.surf_root.end());
     roots_h.push_back(0);  // overflow flag
-    DevBuf<int32_t> roots(g.S + 1);
+    roots_h.push_back(0);  // largest count
+    DevBuf<int32_t> roots(g.S + 2);
     DevBuf<double> fine(fine_h.size()), t_d(t.size()), w_d(w.size());
     Uploads up(s);
-    up.add(roots.p, roots_h.data(), g.S + 1);
+    up.add(roots.p, roots_h.data(), g.S + 2);
     up.add(fine.p, fine_h.data(), fine_h.size());
     up.add(t_d.p, t.data(), t.size());
     up.add(w_d.p, w.data(), w.size());
     up.flush();
-    NearParams np{1.0 / g.threshold, g.S, roots.p, roots.p + g.S};
+    NearParams np{1.0 / g.threshold, g.S, roots.p, roots.p + g.S, roots.p + g.S + 1};
     DevBuf<int64_t> cnt(N + 1);
     const dim3 grid((N + TPB - 1) / TPB), blk(TPB);
+    // The counting walk keeps the first NEAR_CAP panels of each target; when no target has
+    // more, they are moved into the table and the filling walk is not needed.
+    constexpr int NEAR_CAP = 64;
+    DevBuf<int32_t> slot;
+    if (static_cast<size_t>(N) * NEAR_CAP * 4 <= (size_t(512) << 20)) slot.alloc(static_cast<size_t>(N) * NEAR_CAP);
     hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, false,
-                       cnt.p, nullptr, nullptr);
+                       cnt.p, nullptr, nullptr, slot.p, NEAR_CAP);
     LSPR_HIP(hipGetLastError());
     scan_exclusive(cnt.p, cnt.p, N, s);
     int64_t nnz = 0;
-    int32_t overflow = 0;
+    int32_t flags[2] = {0, 0};  // overflow, largest count
     LSPR_HIP(hipMemcpyAsync(&nnz, cnt.p + N, 8, hipMemcpyDeviceToHost, s));
-    LSPR_HIP(hipMemcpyAsync(&overflow, np.overflow, 4, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipMemcpyAsync(flags, np.overflow, 8, hipMemcpyDeviceToHost, s));
     LSPR_HIP(hipStreamSynchronize(s));
-    LSPR_REQUIRE(overflow == 0, LSPR_E_DEVICE, "near-singular walk outgrew its stack");
+    LSPR_REQUIRE(flags[0] == 0, LSPR_E_DEVICE, "near-singular walk outgrew its stack");
     LSPR_REQUIRE(nnz < (1ll << 31), LSPR_E_INVALID, "near-singular table too large");
     g.n_near = nnz;
     g.near_col.alloc(std::max<int64_t>(nnz, 1));
     g.near_dv.alloc(std::max<int64_t>(nnz, 1));
     g.near_dk.alloc(std::max<int64_t>(nnz, 1));
-    hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, true,
-                       nullptr, cnt.p, g.near_col.p);
+    if (slot.p != nullptr && flags[1] <= NEAR_CAP)
+        hipLaunchKernelGGL(k_near_compact, dim3(N), dim3(64), 0, s, slot.p, NEAR_CAP, cnt.p,
+                           g.near_col.p);
+    else
+        hipLaunchKernelGGL(k_near, grid, blk, 0, s, g.boxes.p, g.cen.p, g.area.p, N, np, true,
+                           nullptr, cnt.p, g.near_col.p, nullptr, 0);
     LSPR_HIP(hipGetLastError());
     g.near_off64 = std::move(cnt);
     DevBuf<int32_t> row_of(std::max<int64_t>(nnz, 1));
