@@ -362,9 +362,13 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
                      "fit the tile budget");
     }
     // the host part of the tiles runs beside the moment set-up and the near-singular table
-    std::future<lspr::TilePlan> plan;
-    if (tiles)
-        plan = std::async(std::launch::async, [&g] { return lspr::plan_tiles(g); });
+    std::unique_ptr<lspr::TilePlan> plan_buf;
+    std::future<void> plan;
+    if (tiles) {
+        plan_buf = lspr::take_plan();
+        plan = std::async(std::launch::async,
+                          [&g, p = plan_buf.get()] { lspr::plan_tiles(g, *p); });
+    }
     if (!g.mom_boxes.empty()) {
         const std::vector<lspr::Range>& bh = g.box_rng_h;
         g.mom_panels = 0;
@@ -403,7 +407,11 @@ void create_geometry(Geometry& g, const lspr_surface* surfaces, int n_surf,
         g.p2m_seg_h = std::move(segs);
     }
     lspr::build_near_table(g);
-    if (tiles) lspr::build_tiles(g, plan.get());
+    if (tiles) {
+        plan.get();
+        lspr::build_tiles(g, *plan_buf);
+        lspr::put_plan(std::move(plan_buf));
+    }
     lspr::precompute_rhs(g);
     // the host copies were only needed while building
     g.box_rng_h = {};

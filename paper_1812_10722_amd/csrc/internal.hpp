@@ -565,10 +565,15 @@ struct TilePlan {
     int64_t aoff = 0;                            // elements of one tile store
     int64_t tile_steps = 0, max_chunk_steps = 0;
 };
-TilePlan plan_tiles(const Geometry& g);
-TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split, double tail,
-                           bool cut_self);
+// Fills P (its vectors keep their capacity).
+void plan_tiles(const Geometry& g, TilePlan& P);
+void plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
+                const std::vector<int32_t>& self, double split, double tail, bool cut_self,
+                TilePlan::Items& W);
+// Tile plans kept for reuse: a plan refilled in place keeps its host memory mapped from one
+// geometry to the next, instead of fresh pages being faulted in on every set-up.
+std::unique_ptr<TilePlan> take_plan();
+void put_plan(std::unique_ptr<TilePlan> p);
 // Scratch bytes the far-field pieces of a product of pad columns per operator write.
 size_t far_part_bytes(const Geometry& g, int pad);
 // Elements of one tile store, from the host lists (the size plan_tiles will find).

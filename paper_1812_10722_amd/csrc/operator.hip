@@ -14,6 +14,7 @@
 // Sums are raw: no 1/(4 pi) factor.
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 
@@ -2149,10 +2150,12 @@ int64_t estimate_tile_elems(const Geometry& g) {
 // sides of its own-surface boundary is cut there too, so no item spans it.  A chunk of several
 // items has consecutive partial-sum slots in tile order (own-surface pieces first), added in
 // that order by k_far_reduce.
-TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
-                           const std::vector<int32_t>& self, double split, double tail,
-                           bool cut_self) {
-    TilePlan::Items W;
+void plan_items(const std::vector<TileDesc>& tl, const std::vector<int32_t>& off,
+                const std::vector<int32_t>& self, double split, double tail, bool cut_self,
+                TilePlan::Items& W) {
+    W.items.clear();
+    W.red.clear();
+    W.n_slots = 0;
     const int nc = static_cast<int>(self.size());
     auto tcost = [&](int t) { return static_cast<double>(tl[t].nstep) + 4.0; };
     auto rcost = [&](int t0, int t1) {
@@ -2268,11 +2271,28 @@ TilePlan::Items plan_items(const std::vector<TileDesc>& tl, const std::vector<in
     W.order.assign(std::max<size_t>(per, 1) * 8, -1);
     for (int r = 0; r < 8; ++r)
         for (size_t i = 0; i < runs[r].size(); ++i) W.order[i * 8 + r] = runs[r][i];
-    return W;
 }
 
-TilePlan plan_tiles(const Geometry& g) {
-    TilePlan P;
+namespace {
+std::mutex plan_mu;
+std::vector<std::unique_ptr<TilePlan>> plan_cache;  // at most 4 kept
+}  // namespace
+
+std::unique_ptr<TilePlan> take_plan() {
+    std::lock_guard<std::mutex> lk(plan_mu);
+    if (plan_cache.empty()) return std::make_unique<TilePlan>();
+    std::unique_ptr<TilePlan> p = std::move(plan_cache.back());
+    plan_cache.pop_back();
+    return p;
+}
+
+void put_plan(std::unique_ptr<TilePlan> p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(plan_mu);
+    if (plan_cache.size() < 4) plan_cache.push_back(std::move(p));
+}
+
+void plan_tiles(const Geometry& g, TilePlan& P) {
     const int nc = g.n_chunks;
     // the lists as the list builder left them on the host
     const std::vector<int32_t>&mo = g.m2p_off_h, &po = g.p2p_off_h, &ms = g.m2p_self_h,
@@ -2305,6 +2325,10 @@ TilePlan plan_tiles(const Geometry& g) {
     tself.assign(nc, 0);
     m2p_tile.assign(g.n_m2p, 0);
     m2p_chunk.assign(g.n_m2p, 0);
+    tiles.clear();
+    p2p_tile.clear();
+    p2p_chunk.clear();
+    P.aoff = 0;
     {
         int64_t nd = 0;  // direct tiles
         for (const Range& r : rng) nd += (r.end - r.start + 4 * dmax - 1) / (4 * dmax);
@@ -2388,12 +2412,15 @@ TilePlan plan_tiles(const Geometry& g) {
         int same = -1;
         for (int k = 0; k < cls && same < 0; ++k)
             if (g.far_split[k] == g.far_split[cls] && g.far_tail[k] == g.far_tail[cls]) same = k;
-        P.far[cls] = same >= 0 ? P.far[same]
-                               : plan_items(tiles, toff, tself, g.far_split[cls],
-                                            g.far_tail[cls], true);
+        if (same >= 0)
+            P.far[cls] = P.far[same];
+        else
+            plan_items(tiles, toff, tself, g.far_split[cls], g.far_tail[cls], true, P.far[cls]);
     }
     // each chunk's direct tiles sorted by first source panel, for the near-field fold
     P.dto.assign(nc + 1, 0);
+    P.dtr.clear();
+    P.dti.clear();
     P.dtr.reserve(p2p_tile.size());
     P.dti.reserve(p2p_tile.size());
     std::vector<std::pair<int32_t, int32_t>> d;
@@ -2409,7 +2436,6 @@ TilePlan plan_tiles(const Geometry& g) {
         }
     }
     P.dto[nc] = static_cast<int32_t>(P.dti.size());
-    return P;
 }
 
 void build_tiles(Geometry& g, const TilePlan& P) {

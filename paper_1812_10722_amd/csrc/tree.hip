@@ -470,14 +470,24 @@ void build_tree(Geometry& g) {
     std::vector<Box> bx;
     g.surf_root.assign(g.S, 0);
     g.max_depth = 0;
-    // The sorted keys are read back once and the octant bounds of the boxes found on the host:
-    // a few binary searches per box, instead of a device pass and a round trip per level.
-    std::vector<uint64_t> keys(g.N);
-    {
-        Downloads dl(s);
-        dl.add(keys.data(), g.morton.p, keys.size());
-        dl.fetch();
+    // The sorted keys are read back once, into a reused pinned buffer, and the octant bounds of
+    // the boxes found on the host: a few binary searches per box, instead of a device pass and a
+    // round trip per level.
+    struct PinnedKeys {
+        PinnedBuf b;
+        ~PinnedKeys() {
+            if (b.p) pinned_put(b);
+        }
+    } pk;
+    pk.b = pinned_take(static_cast<size_t>(g.N) * sizeof(uint64_t));
+    try {
+        copy_sync(pk.b.p, g.morton.p, static_cast<size_t>(g.N) * sizeof(uint64_t),
+                  hipMemcpyDeviceToHost, s);
+    } catch (...) {
+        (void)hipStreamSynchronize(s);  // no transfer into the buffer once it is put back
+        throw;
     }
+    const uint64_t* keys = reinterpret_cast<const uint64_t*>(pk.b.p);
     // lower bounds of box b's 8 octants, then its end: the octant bits follow the box's common
     // prefix, so they are sorted inside the box
     auto split_box = [&](const Box& b, int32_t* out) {
