@@ -1562,13 +1562,18 @@ __global__ void k_build_m2p_tiles(const Chunk* __restrict__ chunks, const Box* _
 
 // Direct tile: far-rule single- and double-layer kernel values of the chunk's 64 targets for
 // up to 4 direct_steps() consecutive source panels (zero for the target's own panel and past the
-// range).
+// range).  The tile's source records and centroids are staged in LDS by one contiguous copy;
+// each thread keeps its target's centroid (thread t of every wave: target t).
+constexpr int P2P_MAXP = 4 * 31;    // panels of a direct tile: direct_steps() <= 31
+constexpr int P2P_MAXR = 4 + 4 * 8;  // record length for up to 8 far-rule nodes
 template <class T>
-__global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
-                                  const int32_t* __restrict__ p2p_tile,
-                                  const int32_t* __restrict__ p2p_chunk, int n,
-                                  const double* __restrict__ cen, const T* __restrict__ src,
-                                  int K, T* __restrict__ tileA, float* __restrict__ tileA32) {
+__global__ void __launch_bounds__(256)
+k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__ tiles,
+                  const int32_t* __restrict__ p2p_tile, const int32_t* __restrict__ p2p_chunk,
+                  int n, const double* __restrict__ cen, const T* __restrict__ src, int K,
+                  T* __restrict__ tileA, float* __restrict__ tileA32) {
+    __shared__ T rec[P2P_MAXP * P2P_MAXR];
+    __shared__ double cj[P2P_MAXP * 3];
     const int e = blockIdx.x;
     if (e >= n) return;
     const TileDesc TD = tiles[p2p_tile[e]];
@@ -1576,16 +1581,24 @@ __global__ void k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDe
     T* AK = tileA + TD.a_off();
     T* AV = AK + static_cast<size_t>(TD.nstep) * 256;
     float* BK = tileA32 != nullptr ? tileA32 + TD.a_off() : nullptr;
-    const int rs = 4 + 4 * K;
+    const int rs = 4 + 4 * K, np = TD.b_rows;
+    const T* rsrc = src + static_cast<size_t>(TD.b_row0) * rs;
+    for (int u = threadIdx.x; u < np * rs; u += blockDim.x) rec[u] = rsrc[u];
+    for (int u = threadIdx.x; u < np * 3; u += blockDim.x) cj[u] = cen[3 * static_cast<size_t>(TD.b_row0) + u];
+    const int t = threadIdx.x & 63, i = C.start + t;  // every pr below has pr & 63 == t
+    const bool tin = i < C.end;
+    const double xi = tin ? cen[3 * i] : 0.0, yi = tin ? cen[3 * i + 1] : 0.0,
+                 zi = tin ? cen[3 * i + 2] : 0.0;
+    __syncthreads();
     for (int pr = threadIdx.x; pr < 64 * 4 * TD.nstep; pr += blockDim.x) {
-        const int t = pr & 63, p = pr >> 6;  // target, panel within the tile
-        const int i = C.start + t, j = TD.b_row0 + p;
+        const int p = pr >> 6;  // panel within the tile
+        const int j = TD.b_row0 + p;
         T kv = 0, kk = 0;
-        if (i < C.end && p < TD.b_rows && j != i) {
-            const T* r = src + static_cast<size_t>(j) * rs;
-            const T dx = static_cast<T>(cen[3 * i] - cen[3 * j]);
-            const T dy = static_cast<T>(cen[3 * i + 1] - cen[3 * j + 1]);
-            const T dz = static_cast<T>(cen[3 * i + 2] - cen[3 * j + 2]);
+        if (tin && p < np && j != i) {
+            const T* r = rec + p * rs;
+            const T dx = static_cast<T>(xi - cj[3 * p]);
+            const T dy = static_cast<T>(yi - cj[3 * p + 1]);
+            const T dz = static_cast<T>(zi - cj[3 * p + 2]);
             const T sh = r[0] * dx + r[1] * dy + r[2] * dz;
             T sv = 0, sk = 0;
             for (int gq = 0; gq < K; ++gq) {
@@ -2096,6 +2109,8 @@ void build_tiles_t(Geometry& g, T* A, float* A32, const int32_t* mt, const int32
         }
     }
     if (n_p2p > 0) {
+        LSPR_REQUIRE(4 * direct_steps(g.n_terms) <= P2P_MAXP && 4 + 4 * g.K <= P2P_MAXR,
+                     LSPR_E_INVALID, "direct tile larger than the tile builder's staging");
         hipLaunchKernelGGL(k_build_p2p_tiles<T>, dim3(n_p2p), dim3(256), 0, s, g.chunks.p,
                            g.tiles.p, pt, pc, n_p2p, g.cen.p, src_of<T>(g), g.K, A, A32);
         LSPR_HIP(hipGetLastError());
