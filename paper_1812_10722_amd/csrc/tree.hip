@@ -467,7 +467,9 @@ std::vector<double> rule_rows(int n) {
 
 void build_tree(Geometry& g) {
     hipStream_t s = g.stream;
-    std::vector<Box> bx;
+    // kept per thread between geometries: its capacity (and host pages) are reused
+    static thread_local std::vector<Box> bx;
+    bx.clear();
     g.surf_root.assign(g.S, 0);
     g.max_depth = 0;
     // The sorted keys are read back once, into a reused pinned buffer, and the octant bounds of
@@ -488,20 +490,23 @@ void build_tree(Geometry& g) {
         throw;
     }
     const uint64_t* keys = reinterpret_cast<const uint64_t*>(pk.b.p);
-    // lower bounds of box b's 8 octants, then its end: the octant bits follow the box's common
-    // prefix, so they are sorted inside the box
+    // lower bounds of box b's 8 octants (first index with octant >= o), then its end: the octant
+    // bits follow the box's common prefix, so they are sorted inside the box.  The 8 searches run
+    // in lockstep without branches: the remaining length halves whatever the keys, so their loads
+    // overlap instead of forming one chain.
     auto split_box = [&](const Box& b, int32_t* out) {
         const int shift = 45 - 3 * b.level;
-        for (int o = 0; o < 8; ++o) {
-            int lo = b.start, hi = b.end;  // first index with octant >= o
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                const int oct = static_cast<int>((keys[mid] >> shift) & 7);
-                if (oct < o) lo = mid + 1;
-                else hi = mid;
-            }
-            out[o] = lo;
+        auto oct = [&](int k) { return static_cast<int>((keys[k] >> shift) & 7); };
+        int base[8];
+        for (int o = 0; o < 8; ++o) base[o] = b.start;
+        int n = b.end - b.start;
+        while (n > 1) {  // the bound of o is in [base[o], base[o] + n]
+            const int half = n >> 1;
+            for (int o = 0; o < 8; ++o) base[o] = oct(base[o] + half) < o ? base[o] + half : base[o];
+            n -= half;
         }
+        for (int o = 0; o < 8; ++o)
+            out[o] = n == 0 ? b.start : base[o] + (oct(base[o]) < o ? 1 : 0);
         out[8] = b.end;
     };
     for (int sf = 0; sf < g.S; ++sf) {
