@@ -44,16 +44,24 @@ __device__ inline double block_reduce(double v, double* sh, Op op) {
 struct MinOp { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
 struct MaxOp { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
 
-// One block per box: centre of the nodes' bounding box, node radius, vertex radius, max L.
-__global__ void __launch_bounds__(TPB) k_box_stats(Box* __restrict__ boxes,
-                                                   const double* __restrict__ tri,
-                                                   const double* __restrict__ area,
-                                                   const double* __restrict__ rule, int K) {
-    __shared__ double sh[TPB];
-    Box& b = boxes[blockIdx.x];
+// Boxes of more panels than this get blocks of 1024 threads (a launch of their own).
+constexpr int BIG_BOX = 2048;
+
+// One block of NT threads per box: centre of the nodes' bounding box, node radius, vertex radius,
+// max L.  With `list` the blocks take the listed boxes; without it, every box of at most
+// BIG_BOX panels (the others are in the list).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_box_stats(Box* __restrict__ boxes,
+                                                  const int32_t* __restrict__ list,
+                                                  const double* __restrict__ tri,
+                                                  const double* __restrict__ area,
+                                                  const double* __restrict__ rule, int K) {
+    __shared__ double sh[NT];
+    Box& b = boxes[list != nullptr ? list[blockIdx.x] : blockIdx.x];
     const int start = b.start, end = b.end;
+    if (list == nullptr && end - start > BIG_BOX) return;  // whole block: the box is listed
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int p = start + threadIdx.x; p < end; p += TPB) {
+    for (int p = start + threadIdx.x; p < end; p += NT) {
         const double* v = tri + 9 * static_cast<size_t>(p);
         for (int gq = 0; gq < K; ++gq) {
             double y[3];
@@ -68,7 +76,7 @@ __global__ void __launch_bounds__(TPB) k_box_stats(Box* __restrict__ boxes,
     for (int d = 0; d < 3; ++d)
         c[d] = 0.5 * (block_reduce(lo[d], sh, MinOp()) + block_reduce(hi[d], sh, MaxOp()));
     double rb = 0.0, rv = 0.0, lm = 0.0;
-    for (int p = start + threadIdx.x; p < end; p += TPB) {
+    for (int p = start + threadIdx.x; p < end; p += NT) {
         const double* v = tri + 9 * static_cast<size_t>(p);
         for (int gq = 0; gq < K; ++gq) {
             double y[3];
@@ -573,13 +581,24 @@ void build_tree(Geometry& g) {
     g.chunks.alloc(ch.size());
     const std::vector<double> rule = rule_rows(g.K);
     g.far_rule.alloc(rule.size());
+    std::vector<int32_t> big;  // boxes for the 1024-thread blocks
+    for (size_t b = 0; b < bx.size(); ++b)
+        if (bx[b].end - bx[b].start > BIG_BOX) big.push_back(static_cast<int32_t>(b));
+    DevBuf<int32_t> big_d(std::max<size_t>(big.size(), 1));
     Uploads up(s);
     up.add(g.boxes.p, bx.data(), bx.size());
     up.add(g.chunks.p, ch.data(), ch.size());
     up.add(g.far_rule.p, rule.data(), rule.size());
+    up.add(big_d.p, big.data(), big.size());
     up.flush();
-    hipLaunchKernelGGL(k_box_stats, dim3(g.n_boxes), dim3(TPB), 0, s, g.boxes.p, g.tri.p,
-                       g.area.p, g.far_rule.p, g.K);
+    if (!big.empty()) {
+        hipLaunchKernelGGL(k_box_stats<1024>, dim3(big.size()), dim3(1024), 0, s, g.boxes.p,
+                           big_d.p, g.tri.p, g.area.p, g.far_rule.p, g.K);
+        LSPR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_box_stats<TPB>, dim3(g.n_boxes), dim3(TPB), 0, s, g.boxes.p,
+                       static_cast<const int32_t*>(nullptr), g.tri.p, g.area.p, g.far_rule.p,
+                       g.K);
     LSPR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_chunk_stats, dim3(g.n_chunks), dim3(TPB), 0, s, g.chunks.p, g.cen.p);
     LSPR_HIP(hipGetLastError());
