@@ -22,9 +22,9 @@ def lib():
     return lspr
 
 
-def _dense_system(surfaces, eps_m, eps_s, k_far=4, k_fine=19, n_k=9):
+def _dense_system(surfaces, eps_m, eps_s, k_far=4, k_fine=19, n_k=9, threshold=0.5):
     v, t, sid = merge_surfaces(surfaces)
-    V, K = oracle.dense_operators(v, t, k_far, k_fine, n_k, 0.5)
+    V, K = oracle.dense_operators(v, t, k_far, k_fine, n_k, threshold)
     g = oracle.panel_geometry(v, t)
     return v, t, sid, V, K, g
 
@@ -61,6 +61,32 @@ def test_apply_dense_matches_oracle_matrix(lib, precision, tol, k_fine):
         ref = A @ x[c]
         err = np.abs(y[c] - ref).max() / np.abs(ref).max()
         assert err < tol, (precision, c, err)
+
+
+def test_apply_dense_with_many_near_panels_matches_oracle_matrix(lib):
+    """At a small near-singular threshold some targets are near to more than 64 panels, so the
+    library builds its near-singular table with a counting and a filling tree walk instead of
+    one walk (the case is checked on the oracle's own mask); the dense FP64 product still equals
+    the oracle's matrix to rounding."""
+    surfs = sensor_and_blob()
+    thr = 0.2
+    v, t, sid, V, K, g = _dense_system(surfs, None, None, threshold=thr)
+    n = len(t)
+    mask = oracle.near_singular_mask(g["centroid"], np.arange(n), g["centroid"], g["L"], thr)
+    assert mask.sum(axis=1).max() > 64, mask.sum(axis=1).max()
+    rng = np.random.default_rng(11)
+    eps_m = np.array([1.7733, 1.0])
+    eps_s = np.array([[-3.38 + 0.2j, 2.5], [4.0, 1.5]])
+    x = _rand_x(rng, 2, n)
+    geo = lib.Geometry(surfs, method="dense", precision="fp64", k_far=4, k_fine=19,
+                       threshold=thr)
+    assert geo.info()["n_near"] == int(mask.sum())
+    y = geo.apply(torch.as_tensor(x).cuda(), eps_m, eps_s).cpu().numpy()
+    for c in range(2):
+        A, _ = oracle.assemble_system(V, K, sid, g["normal"], eps_m[c], eps_s[c], [0, 0, 1.0])
+        ref = A @ x[c]
+        err = np.abs(y[c] - ref).max() / np.abs(ref).max()
+        assert err < 1e-12, (c, err)
 
 
 def test_rhs_matches_oracle(lib):
