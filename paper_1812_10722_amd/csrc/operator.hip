@@ -1629,9 +1629,10 @@ k_build_p2p_tiles(const Chunk* __restrict__ chunks, const TileDesc* __restrict__
 // value of a near pair (i, j) plus its fine-minus-far correction is its fine-rule value
 // (section "Integral evaluation"), and V_ii joins the otherwise empty self pair.  Every near
 // pair lies in a direct tile of its target's chunk (a box is never expanded for targets that
-// could be near-singular to it), so the tiles then carry the whole operator.  Thread = target;
-// each thread writes its own tile row, so no two threads touch one entry; pairs without a tile
-// are counted (the caller then rebuilds the tiles without folding).
+// could be near-singular to it), so the tiles then carry the whole operator.  Thread = one
+// near-singular entry (e < nnz) or one self pair (e = nnz + i): every thread adds to its own
+// tile entry once, so no two threads touch one entry; pairs without a tile are counted (the
+// caller then rebuilds the tiles without folding).
 template <class T>
 __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
                             const int32_t* __restrict__ dt_off, const int32_t* __restrict__ dt_row0,
@@ -1639,10 +1640,31 @@ __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
                             const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
                             const int32_t* __restrict__ col, const double* __restrict__ dv,
                             const double* __restrict__ dk, const double* __restrict__ vself,
-                            int N, T* __restrict__ tileA, float* __restrict__ tileA32,
-                            int32_t* __restrict__ missing) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+                            int N, int64_t nnz, T* __restrict__ tileA,
+                            float* __restrict__ tileA32, int32_t* __restrict__ missing) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz + N) return;
+    int i, j;
+    double add_k, add_v;
+    if (e < nnz) {
+        // the row of entry e: the last target whose first entry is at or before e (an empty
+        // row shares its offset with the next one)
+        int a = 0, b = N - 1;
+        while (a < b) {
+            const int mid = (a + b + 1) / 2;
+            if (off[mid] <= e) a = mid;
+            else b = mid - 1;
+        }
+        i = a;
+        j = col[e];
+        add_k = dk[e];
+        add_v = dv[e];
+    } else {
+        i = static_cast<int>(e - nnz);
+        j = i;
+        add_k = 0.0;
+        add_v = vself[i];
+    }
     int lo = 0, hi = n_chunks - 1;  // the chunk holding target i (chunks are in target order)
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
@@ -1678,10 +1700,7 @@ __global__ void k_fold_near(const Chunk* __restrict__ chunks, int n_chunks,
         }
         return true;
     };
-    int miss = 0;
-    for (int64_t e = off[i]; e < off[i + 1]; ++e) miss += !place(col[e], dk[e], dv[e]);
-    miss += !place(i, 0.0, vself[i]);
-    if (miss) atomicAdd(missing, miss);
+    if (!place(j, add_k, add_v)) atomicAdd(missing, 1);
 }
 
 // ------------------------------------------------------------------------------- near field
@@ -2128,9 +2147,11 @@ bool fold_near(Geometry& g, T* A, float* A32, const int32_t* dt_off, const int32
     if (g.N == 0 || g.n_chunks == 0) return false;
     DevBuf<int32_t> miss(1);
     LSPR_HIP(hipMemsetAsync(miss.p, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_fold_near<T>, dim3((g.N + 255) / 256), dim3(256), 0, s, g.chunks.p,
-                       g.n_chunks, dt_off, dt_row0, dt_tile, g.tiles.p, g.near_off64.p,
-                       g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p, g.N, A, A32, miss.p);
+    const int64_t n_fold = g.n_near + g.N;  // near-singular entries, then the self pairs
+    hipLaunchKernelGGL(k_fold_near<T>, dim3(static_cast<unsigned>((n_fold + 255) / 256)), dim3(256),
+                       0, s, g.chunks.p, g.n_chunks, dt_off, dt_row0, dt_tile, g.tiles.p,
+                       g.near_off64.p, g.near_col.p, g.near_dv.p, g.near_dk.p, g.vself.p, g.N,
+                       static_cast<int64_t>(g.n_near), A, A32, miss.p);
     LSPR_HIP(hipGetLastError());
     int32_t h = 0;
     copy_sync(&h, miss.p, sizeof(int32_t), hipMemcpyDeviceToHost, s);
