@@ -314,6 +314,7 @@ struct Box {
     int32_t start, end; // panel range [start, end) in sorted order
     int32_t child, nchild;
     int32_t level, surf;
+    int32_t next;       // the box after this one's subtree in depth-first order (-1: none)
 };
 
 // Group of consecutive targets (panel centroids of one surface, sorted order) that share

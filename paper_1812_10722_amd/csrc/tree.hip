@@ -21,7 +21,6 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int MAX_LEVEL = 16;   // 16 Morton bits per axis
-constexpr int STACK = 160;
 
 __device__ inline void node_pos(const double* v, const double* rule, int g, double* y) {
     const double b0 = rule[4 * g], b1 = rule[4 * g + 1], b2 = rule[4 * g + 2];
@@ -136,7 +135,6 @@ struct ListParams {
     int min_panels;
     int S;
     const int32_t* roots;  // [S]
-    int32_t* overflow;     // set when a walk would outgrow its stack (checked by the host)
 };
 
 // Interaction lists of one chunk against every surface's tree, own surface first.  A box is
@@ -198,17 +196,18 @@ __device__ void walk_sub(const Box* __restrict__ boxes, const Chunk& T, int q,
                          const ListParams& lp, SubList& L, const SubPlace& pl,
                          int32_t* __restrict__ m2p_box, Range* __restrict__ p2p_rng) {
     const int nt = T.end - T.start;
-    int stack[STACK];
-    int top = 0;
-    stack[top++] = q;
+    // depth-first over q's subtree without a stack: into the first child, or past the subtree
+    const int stop = boxes[q].next;
+    int bi = q;
     int last_end = -1, li = -1;  // li: local index of the last direct range
     auto slot = [&](int i) { return pl.p2p + i - pl.skip; };
-    while (top > 0) {
-        const int bi = stack[--top];
-        const Box B = boxes[bi];
+    while (bi != stop) {
+        const int cur = bi;
+        const Box B = boxes[cur];
         const int act = list_action(T, B, lp);
+        bi = B.next;
         if (act == LIST_M2P) {
-            if (FILL) m2p_box[pl.m2p + L.nm] = bi;
+            if (FILL) m2p_box[pl.m2p + L.nm] = cur;
             ++L.nm;
             L.mp += nt;
             L.flags = (L.flags & ~2) | 4;
@@ -225,14 +224,8 @@ __device__ void walk_sub(const Box* __restrict__ boxes, const Chunk& T, int q,
             last_end = B.end;
             L.pp += static_cast<int64_t>(nt) * (B.end - B.start);
             L.flags |= 2 | 4;
-        } else {
-            // at most 7 pending siblings per level below MAX_LEVEL, so the stack cannot fill;
-            // if it ever did, the lists would be incomplete: report it instead of dropping pairs
-            if (top + B.nchild > STACK) {
-                atomicOr(lp.overflow, 1);
-                return;
-            }
-            for (int k = B.nchild - 1; k >= 0; --k) stack[top++] = B.child + k;
+        } else if (B.nchild > 0) {
+            bi = B.child;
         }
     }
     if (FILL && pl.end >= 0 && (L.flags & 2) && !(pl.skip && li == 0)) p2p_rng[slot(li)].end = pl.end;
@@ -321,7 +314,6 @@ struct NearParams {
     double inv_thr;
     int S;
     const int32_t* roots;
-    int32_t* overflow;  // set when a walk would outgrow its stack (checked by the host)
     int32_t* maxcnt;    // largest count of a target (counting walk)
 };
 
@@ -335,19 +327,21 @@ __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = cen[3 * i], y = cen[3 * i + 1], z = cen[3 * i + 2];
-    int stack[STACK];
     int64_t k = fill ? off[i] : 0;
     int n = 0;
     for (int s = 0; s < np.S; ++s) {
-        int top = 0;
-        stack[top++] = np.roots[s];
-        while (top > 0) {
-            const int bi = stack[--top];
+        // depth-first without a stack: into the first child, or past the box's subtree
+        int bi = np.roots[s];
+        while (bi >= 0) {
             const Box B = boxes[bi];
             const double dx = x - B.cx, dy = y - B.cy, dz = z - B.cz;
             const double d = sqrt(dx * dx + dy * dy + dz * dz);
-            if (d - B.rv > B.lmax * np.inv_thr * (1.0 + 1e-9) + 1e-12) continue;
-            if (B.nchild == 0) {
+            const bool far = d - B.rv > B.lmax * np.inv_thr * (1.0 + 1e-9) + 1e-12;
+            if (!far && B.nchild > 0) {
+                bi = B.child;
+                continue;
+            }
+            if (!far) {
                 for (int j = B.start; j < B.end; ++j) {
                     if (j == i) continue;
                     const double ex = x - cen[3 * j], ey = y - cen[3 * j + 1], ez = z - cen[3 * j + 2];
@@ -358,14 +352,8 @@ __global__ void k_near(const Box* __restrict__ boxes, const double* __restrict__
                         ++n;
                     }
                 }
-            } else {
-                if (top + B.nchild > STACK) {  // cannot happen below MAX_LEVEL; reported
-                    atomicOr(np.overflow, 1);
-                    if (!fill) cnt[i] = 0;
-                    return;
-                }
-                for (int q = B.nchild - 1; q >= 0; --q) stack[top++] = B.child + q;
             }
+            bi = B.next;
         }
     }
     if (!fill) {
@@ -561,6 +549,12 @@ void build_tree(Geometry& g) {
             frontier.swap(next);
         }
     }
+    // depth-first successors: a child is followed by its next sibling, the last child by its
+    // parent's successor (boxes are numbered level by level, so a parent's is set first)
+    for (Box& b : bx) b.next = -1;
+    for (size_t b = 0; b < bx.size(); ++b)
+        for (int k = 0; k < bx[b].nchild; ++k)
+            bx[bx[b].child + k].next = k + 1 < bx[b].nchild ? bx[b].child + k + 1 : bx[b].next;
     g.n_boxes = static_cast<int>(bx.size());
     g.n_leaves = 0;
     for (const Box& b : bx) g.n_leaves += b.nchild == 0;
@@ -608,13 +602,11 @@ void build_tree(Geometry& g) {
 void build_lists(Geometry& g) {
     hipStream_t s = g.stream;
     const int nc = g.n_chunks;
-    // surface roots, then the overflow flag (zero)
-    std::vector<int32_t> roots_h(g.surf_root.begin(), g.surf_root.end());
-    roots_h.push_back(0);
-    DevBuf<int32_t> roots(g.S + 1);
-    LSPR_HIP(hipMemcpyAsync(roots.p, roots_h.data(), (g.S + 1) * 4, hipMemcpyHostToDevice, s));
+    // surface roots
+    DevBuf<int32_t> roots(g.S);
+    LSPR_HIP(hipMemcpyAsync(roots.p, g.surf_root.data(), g.S * 4, hipMemcpyHostToDevice, s));
     ListParams lp{g.method == LSPR_DENSE ? 0.0 : g.theta, 1.0 / g.threshold, g.m2p_min_panels,
-                  g.S, roots.p, roots.p + g.S};
+                  g.S, roots.p};
     DevBuf<int32_t> mc(nc), pc(nc);
     g.m2p_self.alloc(nc);
     g.p2p_self.alloc(nc);
@@ -630,7 +622,6 @@ void build_lists(Geometry& g) {
     LSPR_HIP(hipGetLastError());
     std::vector<int32_t> mh(nc), ph(nc);
     std::vector<int64_t> prh(2 * nc);
-    int32_t overflow = 0;
     g.m2p_self_h.resize(nc);
     g.p2p_self_h.resize(nc);
     Downloads down(s);
@@ -639,9 +630,7 @@ void build_lists(Geometry& g) {
     down.add(prh.data(), pairs.p, 2 * nc);
     down.add(g.m2p_self_h.data(), g.m2p_self.p, nc);
     down.add(g.p2p_self_h.data(), g.p2p_self.p, nc);
-    down.add(&overflow, lp.overflow, 1);
     down.fetch();
-    LSPR_REQUIRE(overflow == 0, LSPR_E_DEVICE, "interaction-list walk outgrew its stack");
     std::vector<int64_t> mo(nc + 1, 0), po(nc + 1, 0);
     g.p2p_pairs = 0;
     g.m2p_pairs = 0;
@@ -692,17 +681,16 @@ void build_near_table(Geometry& g) {
     std::vector<double> t, w;
     gauss_legendre(g.Nk, t, w);
     std::vector<int32_t> roots_h(g.surf_root.begin(), g.surf_root.end());
-    roots_h.push_back(0);  // overflow flag
     roots_h.push_back(0);  // largest count
-    DevBuf<int32_t> roots(g.S + 2);
+    DevBuf<int32_t> roots(g.S + 1);
     DevBuf<double> fine(fine_h.size()), t_d(t.size()), w_d(w.size());
     Uploads up(s);
-    up.add(roots.p, roots_h.data(), g.S + 2);
+    up.add(roots.p, roots_h.data(), g.S + 1);
     up.add(fine.p, fine_h.data(), fine_h.size());
     up.add(t_d.p, t.data(), t.size());
     up.add(w_d.p, w.data(), w.size());
     up.flush();
-    NearParams np{1.0 / g.threshold, g.S, roots.p, roots.p + g.S, roots.p + g.S + 1};
+    NearParams np{1.0 / g.threshold, g.S, roots.p, roots.p + g.S};
     DevBuf<int64_t> cnt(N + 1);
     const dim3 grid((N + TPB - 1) / TPB), blk(TPB);
     // The counting walk keeps the first NEAR_CAP panels of each target; when no target has
@@ -715,17 +703,16 @@ void build_near_table(Geometry& g) {
     LSPR_HIP(hipGetLastError());
     scan_exclusive(cnt.p, cnt.p, N, s);
     int64_t nnz = 0;
-    int32_t flags[2] = {0, 0};  // overflow, largest count
+    int32_t maxcnt = 0;  // largest count of a target
     LSPR_HIP(hipMemcpyAsync(&nnz, cnt.p + N, 8, hipMemcpyDeviceToHost, s));
-    LSPR_HIP(hipMemcpyAsync(flags, np.overflow, 8, hipMemcpyDeviceToHost, s));
+    LSPR_HIP(hipMemcpyAsync(&maxcnt, np.maxcnt, 4, hipMemcpyDeviceToHost, s));
     LSPR_HIP(hipStreamSynchronize(s));
-    LSPR_REQUIRE(flags[0] == 0, LSPR_E_DEVICE, "near-singular walk outgrew its stack");
     LSPR_REQUIRE(nnz < (1ll << 31), LSPR_E_INVALID, "near-singular table too large");
     g.n_near = nnz;
     g.near_col.alloc(std::max<int64_t>(nnz, 1));
     g.near_dv.alloc(std::max<int64_t>(nnz, 1));
     g.near_dk.alloc(std::max<int64_t>(nnz, 1));
-    if (slot.p != nullptr && flags[1] <= NEAR_CAP)
+    if (slot.p != nullptr && maxcnt <= NEAR_CAP)
         hipLaunchKernelGGL(k_near_compact, dim3(N), dim3(64), 0, s, slot.p, NEAR_CAP, cnt.p,
                            g.near_col.p);
     else
