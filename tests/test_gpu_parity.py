@@ -89,6 +89,25 @@ def test_apply_dense_with_many_near_panels_matches_oracle_matrix(lib):
         assert err < 1e-12, (c, err)
 
 
+def test_geometry_after_a_larger_one_gives_the_same_product(lib):
+    """Set-up reuses host tile plans and buffers between geometries: a small treecode geometry
+    built again after a larger one gives the same FP32 product, bit for bit, as when it was built
+    first."""
+    small = sensor_and_blob()
+    rng = np.random.default_rng(5)
+    eps_m = np.array([1.7733, 1.80 + 0.01j])
+    eps_s = np.array([[-3.38 + 0.2j, 2.5], [-2.0 + 0.5j, 2.7 + 0.3j]])
+    n = sum(len(t) for _, t in small)
+    x = torch.as_tensor(_rand_x(rng, 2, n)).cuda()
+    kw = dict(method="treecode", precision="fp32", p=8, theta=0.5, k_far=4, k_fine=19)
+    y1 = lib.Geometry(small, **kw).apply(x, eps_m, eps_s).cpu().numpy()
+    big = [octasphere(16, 10.0)]
+    xb = torch.as_tensor(_rand_x(rng, 2, len(big[0][1]))).cuda()
+    lib.Geometry(big, **kw).apply(xb, eps_m, eps_s[:, :1]).cpu().numpy()
+    y2 = lib.Geometry(small, **kw).apply(x, eps_m, eps_s).cpu().numpy()
+    assert np.array_equal(y1, y2), np.abs(y1 - y2).max()
+
+
 def test_rhs_matches_oracle(lib):
     surfs = sensor_and_blob()
     v, t, sid, V, K, g = _dense_system(surfs, None, None)
