@@ -75,7 +75,10 @@ struct CachedBlock {
 };
 std::mutex cache_mu;
 std::vector<CachedBlock> cache;  // every device's pools; blocks are few and large
-constexpr size_t CACHE_CAP = 64ull << 30;
+// Cached blocks are kept up to this many bytes per pool; a block that does not fit evicts smaller
+// ones (a large block is the one that costs most to map again: the 96 GB FP64 tile store of a
+// 491k-panel mesh), and an allocation that does not fit flushes the cache.
+constexpr size_t CACHE_CAP = 128ull << 30;
 size_t cached_bytes(hipMemPool_t pool) {
     size_t t = 0;
     for (const CachedBlock& b : cache) t += b.pool == pool ? b.bytes : 0;
@@ -103,7 +106,27 @@ void* big_block_take(hipMemPool_t pool, size_t bytes, hipStream_t s, size_t* got
 
 bool big_block_put(hipMemPool_t pool, void* p, size_t bytes, hipStream_t s) {
     std::lock_guard<std::mutex> lk(cache_mu);
-    if (cached_bytes(pool) + bytes > CACHE_CAP) return false;
+    size_t have = cached_bytes(pool);
+    if (have + bytes > CACHE_CAP) {
+        // room from smaller blocks of the pool, smallest first, if they free enough
+        size_t smaller = 0;
+        for (const CachedBlock& b : cache)
+            if (b.pool == pool && b.bytes < bytes) smaller += b.bytes;
+        if (have - smaller + bytes > CACHE_CAP) return false;
+        while (have + bytes > CACHE_CAP) {
+            int k = -1;
+            for (size_t i = 0; i < cache.size(); ++i)
+                if (cache[i].pool == pool && cache[i].bytes < bytes &&
+                    (k < 0 || cache[i].bytes < cache[k].bytes))
+                    k = static_cast<int>(i);
+            const CachedBlock d = cache[k];
+            cache.erase(cache.begin() + k);
+            (void)hipEventSynchronize(d.ready);  // its last use has finished
+            (void)hipEventDestroy(d.ready);
+            (void)hipFreeAsync(d.p, s);  // back to the pool, which keeps it for reuse
+            have -= d.bytes;
+        }
+    }
     hipEvent_t ev = nullptr;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
     if (hipEventRecord(ev, s) != hipSuccess) {

@@ -56,8 +56,9 @@ hipMemPool_t library_pool();
 
 // Cache of large released blocks of the library pool.  Returning a pool allocation of several
 // GB costs the host about 1.3 ms per GB, and obtaining it again a few tenths of a ms, so blocks
-// of at least BIG_BLOCK bytes are kept (up to 64 GiB per pool: the tile stores of a 100k-panel
-// geometry in both precisions) and handed to the next request
+// of at least BIG_BLOCK bytes are kept (up to 128 GiB per pool, larger blocks first: both tile
+// stores of a 100k-panel geometry, or the FP64 store of a 491k-panel one) and handed to the next
+// request
 // of a size they cover.  A kept block is reusable once an event recorded on its last stream
 // has completed; the taker's stream waits for that event.
 constexpr size_t BIG_BLOCK = 32ull << 20;
