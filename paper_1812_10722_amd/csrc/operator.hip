@@ -1984,8 +1984,10 @@ bool launch_p2m_tiles(Geometry& g, const Cols& c, const T* dens, T* mom, hipStre
     return true;
 }
 
+// Allocations and the offset table in the order of s; the fills and the builder on s2, after
+// that point of s (the caller waits for s2).
 template <int P>
-void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
+void build_p2m_tiles_p(Geometry& g, hipStream_t s, hipStream_t s2) {
     constexpr int RT = p2m_row_tiles<P>();
     const std::vector<P2MSeg>& segs = g.p2m_seg_h;
     LSPR_REQUIRE(static_cast<int>(segs.size()) == g.n_seg, LSPR_E_INVALID,
@@ -1998,24 +2000,25 @@ void build_p2m_tiles_p(Geometry& g, hipStream_t s) {
     }
     g.p2m_aoff.alloc(g.n_seg);
     copy_sync(g.p2m_aoff.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
-    if (g.tileA.p != nullptr) {
-        g.p2mA.alloc(std::max<int64_t>(tot, 1));
-        LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s));
-    }
-    if (g.tileA64.p != nullptr) {
-        g.p2mA64.alloc(std::max<int64_t>(tot, 1));
-        LSPR_HIP(hipMemsetAsync(g.p2mA64.p, 0, g.p2mA64.bytes(), s));
-    }
+    if (g.tileA.p != nullptr) g.p2mA.alloc(std::max<int64_t>(tot, 1));
+    if (g.tileA64.p != nullptr) g.p2mA64.alloc(std::max<int64_t>(tot, 1));
+    hipEvent_t ev = nullptr;
+    LSPR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    const hipError_t e1 = hipEventRecord(ev, s);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s2, ev, 0) : e1;
+    (void)hipEventDestroy(ev);
+    LSPR_HIP(e2);
+    if (g.p2mA.p != nullptr) LSPR_HIP(hipMemsetAsync(g.p2mA.p, 0, g.p2mA.bytes(), s2));
+    if (g.p2mA64.p != nullptr) LSPR_HIP(hipMemsetAsync(g.p2mA64.p, 0, g.p2mA64.bytes(), s2));
     if (g.src64.p != nullptr)
-        hipLaunchKernelGGL((k_build_p2m_tiles<double, P>), dim3(g.n_seg), dim3(128), 0, s,
+        hipLaunchKernelGGL((k_build_p2m_tiles<double, P>), dim3(g.n_seg), dim3(128), 0, s2,
                            g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src64.p, g.K,
                            g.p2mA.p, g.p2mA64.p);
     else
-        hipLaunchKernelGGL((k_build_p2m_tiles<float, P>), dim3(g.n_seg), dim3(128), 0, s,
+        hipLaunchKernelGGL((k_build_p2m_tiles<float, P>), dim3(g.n_seg), dim3(128), 0, s2,
                            g.boxes.p, g.p2m_seg.p, g.p2m_aoff.p, g.cen.p, g.src32.p, g.K,
                            g.p2mA.p, g.p2mA64.p);
     LSPR_HIP(hipGetLastError());
-    LSPR_HIP(hipStreamSynchronize(s));
 }
 
 template <class T, int CPT>
@@ -2535,10 +2538,34 @@ void build_tiles(Geometry& g, const TilePlan& P) {
     up.add(dtr_d.p, P.dtr.data(), P.dtr.size());
     up.add(dti_d.p, P.dti.data(), P.dti.size());
     up.flush();
-    // with both stores, one FP64 pass fills both (the FP32 tiles are the FP64 values rounded)
     if (keep32) g.tileA.alloc(std::max<int64_t>(aoff, 1));
+    if (keep64) g.tileA64.alloc(std::max<int64_t>(aoff, 1));
+    // the moments' tiles, for each precision with tiles, on a second stream beside the expansion
+    // and direct tiles (a latency-bound builder next to two bandwidth-bound ones)
+    struct AuxStream {
+        hipStream_t s = nullptr;
+        ~AuxStream() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+        }
+    } aux;
+    if (g.n_seg > 0) {
+        LSPR_HIP(hipStreamCreateWithFlags(&aux.s, hipStreamNonBlocking));
+        switch (g.P) {
+            case 2: build_p2m_tiles_p<2>(g, s, aux.s); break;
+            case 4: build_p2m_tiles_p<4>(g, s, aux.s); break;
+            case 6: build_p2m_tiles_p<6>(g, s, aux.s); break;
+            case 8: build_p2m_tiles_p<8>(g, s, aux.s); break;
+            case 10: build_p2m_tiles_p<10>(g, s, aux.s); break;
+            case 12: build_p2m_tiles_p<12>(g, s, aux.s); break;
+            case 15: build_p2m_tiles_p<15>(g, s, aux.s); break;
+            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8, 10, 12 or 15");
+        }
+    }
+    // with both stores, one FP64 pass fills both (the FP32 tiles are the FP64 values rounded)
     if (keep64) {
-        g.tileA64.alloc(std::max<int64_t>(aoff, 1));
         float* a32 = keep32 ? g.tileA.p : nullptr;
         auto build = [&] { build_tiles_t<double>(g, g.tileA64.p, a32, mt.p, mc.p, n_m2p, pt.p, pc.p, n_p2p, s); };
         build();
@@ -2550,18 +2577,7 @@ void build_tiles(Geometry& g, const TilePlan& P) {
         g.near_in_tiles32 = fold_near(g, g.tileA.p, nullptr, dto_d.p, dtr_d.p, dti_d.p, s, build);
     }
     LSPR_HIP(hipStreamSynchronize(s));
-    if (g.n_seg > 0) {  // moments on matrix cores as well, for each precision with tiles
-        switch (g.P) {
-            case 2: build_p2m_tiles_p<2>(g, s); break;
-            case 4: build_p2m_tiles_p<4>(g, s); break;
-            case 6: build_p2m_tiles_p<6>(g, s); break;
-            case 8: build_p2m_tiles_p<8>(g, s); break;
-            case 10: build_p2m_tiles_p<10>(g, s); break;
-            case 12: build_p2m_tiles_p<12>(g, s); break;
-            case 15: build_p2m_tiles_p<15>(g, s); break;
-            default: throw Error(LSPR_E_INVALID, "expansion order must be 2, 4, 6, 8, 10, 12 or 15");
-        }
-    }
+    if (aux.s) LSPR_HIP(hipStreamSynchronize(aux.s));
 }
 
 Cols make_cols(const Geometry& g, int ncol, int prec) {
